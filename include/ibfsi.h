@@ -1,0 +1,178 @@
+/* ibfsi: strongly coupled immersed-boundary flow step on MI355X (gfx950).
+ *
+ * One solver instance advances the 2-D incompressible flow around rigid,
+ * torsionally hinged and deformable bodies with the block-LU factored, strongly
+ * coupled immersed-boundary method of Nair & Goza ("A strongly coupled immersed
+ * boundary method for fluid-structure interaction that mimics the efficiency of
+ * stationary body methods"):
+ *
+ *   predictor   s* = (C^T A C)^{-1} r^f                     (Sec. 2.3, eq. (16))
+ *   FSI loop    Schur system for the body stresses f,       (eqs. (17)-(19); with the
+ *               structural Newton update, until              sub-domain operator:
+ *               max |delta theta|, |delta chi| <= tol        eqs. (37)-(39), Alg. 2)
+ *   corrector   s_{n+1} = s* - (C^T A C)^{-1} C^T E^T f      (eq. (20) / (40))
+ *
+ * on a staggered streamfunction-vorticity grid (Sec. 2.2) with nested levels that
+ * double in extent about a common centre (far field, Sec. 5).  Moving bodies use the
+ * precomputed, drop-tolerance filtered sub-domain operator B' (Sec. 3, Algorithm 1).
+ *
+ * Conventions
+ *   - All host buffers are owned by the caller; the library copies what it needs.
+ *   - Device state is owned by the solver and allocated through the optional
+ *     allocator callbacks (e.g. PyTorch's caching allocator), else hipMalloc.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = default stream);
+ *     ib_step returns once the work is enqueued unless a host decision is needed
+ *     (FSI convergence test), ib_sync waits for it.
+ *   - A solver handle is not thread-safe; distinct handles are independent.
+ *   - Grid arrays are row-major with the y index outer: value (i, j) of an
+ *     (n-1) x (n-1) interior array is at [(j-1) * (n-1) + (i-1)].
+ *   - Stresses of a body of m points are 2m values: the m x-components, then the m
+ *     y-components (Sec. 4.2).  f is the stress the fluid exerts on the body (force
+ *     per unit length), so the body's force is sum(f) * ds.
+ *   - Every function returns IB_OK (0) or a negative ib_status; no exception
+ *     crosses the ABI.  After a failed ib_step the handle stays readable but further
+ *     steps return IB_ERR_STATE.
+ */
+#ifndef IBFSI_H
+#define IBFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ib_status;
+#define IB_OK 0
+#define IB_ERR_ARG (-1)               /* invalid argument (null pointer, bad size, unsupported n) */
+#define IB_ERR_STATE (-2)             /* wrong call order, or stepping after a failure */
+#define IB_ERR_OOM (-3)               /* device allocation failed */
+#define IB_ERR_HIP (-4)               /* HIP runtime error */
+#define IB_ERR_NOT_CONVERGED (-5)     /* FSI iteration hit newton_max_iter */
+#define IB_ERR_OUT_OF_SUBDOMAIN (-6)  /* a body point left the sub-domain rectangle */
+#define IB_ERR_NEAR_BOUNDARY (-7)     /* delta support reaches the finest level's edge */
+#define IB_ERR_NONFINITE (-8)         /* NaN or Inf in the state */
+#define IB_ERR_CAPACITY (-9)          /* caller's output buffer is too small */
+
+/* precision */
+#define IB_FP64 0        /* everything in double precision */
+#define IB_FP32_FLOW 1   /* stencils, sine transforms, spreading in float; Schur, LU and
+                            structure in double */
+
+/* Schur operator */
+#define IB_SCHUR_AUTO 0       /* sub-domain if a sub-domain is set, else exact */
+#define IB_SCHUR_EXACT 1      /* E C (C^T A C)^{-1} C^T E^T with the true E (eq. (17));
+                                 precomputed once when every body is rigid */
+#define IB_SCHUR_SUBDOMAIN 2  /* P B' P^T (eqs. (23), (37)) */
+
+typedef struct ib_solver ib_solver;
+
+typedef struct {
+  int32_t n;          /* cells per side of every level; one of 16, 32, 48, 64, 96, 128,
+                         192, 256, 384, 512, 768, 1024 */
+  int32_t levels;     /* nested levels (>= 1); level 0 is the finest */
+  double h;           /* finest grid spacing */
+  double cx, cy;      /* common centre of all levels */
+  double re;          /* Reynolds number */
+  double dt;          /* time step */
+  double u_inf[2];    /* free stream */
+  int32_t precision;  /* IB_FP64 or IB_FP32_FLOW */
+  int32_t schur_mode; /* IB_SCHUR_* */
+  double newton_tol;  /* FSI tolerance on max |delta theta|, |delta chi| (1e-7, Sec. 5) */
+  int32_t newton_max_iter;   /* give up after this many FSI iterations (e.g. 20) */
+  int32_t newton_fixed_iter; /* > 0: run exactly this many FSI iterations, no test */
+  double drop_tol;    /* B' drop tolerance epsilon (0.007, Sec. 3.2.2) */
+} ib_config;
+
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx); /* returns device memory or NULL */
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} ib_allocator;
+
+typedef struct {
+  int64_t step;              /* completed steps */
+  int32_t newton_iters;      /* FSI iterations of the last step */
+  int32_t newton_iters_max;  /* largest count so far */
+  double newton_delta;       /* last max |delta| */
+  int64_t subdomain_points;  /* 2 n_sd (rows of B'), 0 when not used */
+  int64_t subdomain_nnz;     /* stored entries of B' */
+  double prepare_seconds;    /* wall time of the offline stage */
+} ib_stats;
+
+/* Create a solver.  `alloc` may be NULL (hipMalloc); `hip_stream` is a hipStream_t
+ * or NULL.  Errors: IB_ERR_ARG for unsupported sizes (n not in the list, n % 4 != 0,
+ * levels < 1, non-positive h/dt/re). */
+ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_stream,
+                    ib_solver** out);
+
+/* Stationary or prescribed-velocity rigid body: m points xy[2m] (x0, y0, x1, y1, ...),
+ * arc length per point ds, optional velocity u_b[2m] (NULL = at rest).  Eq. (5). */
+ib_status ib_add_rigid(ib_solver* s, int32_t m, const double* xy, double ds,
+                       const double* u_b, int32_t* body_id);
+
+/* Torsionally hinged flat plate of m points at hinge + j ds (cos, sin)(theta0 + theta),
+ * j = 0 .. m-1, ds = length / (m - 1); moment of inertia, spring stiffness and
+ * damping about the hinge; initial deflection theta and rate phi.  Eqs. (3), (6),
+ * (A.2)-(A.4). */
+ib_status ib_add_torsional(ib_solver* s, int32_t m, double hinge_x, double hinge_y,
+                           double length, double theta0, double inertia, double stiffness,
+                           double damping, double theta, double phi, int32_t* body_id);
+
+/* Deformable beam clamped at its first node: stress-free straight reference xy_ref[2m],
+ * mass per unit length, bending (ei) and stretching (ea) stiffness, initial node
+ * positions xy0[2m] and rotations rot0[m] (relative to the reference), at rest.
+ * Eqs. (4), (7), (A.5).  Finite elements: corotational Euler-Bernoulli beam. */
+ib_status ib_add_deformable(ib_solver* s, int32_t m, const double* xy_ref, double mass,
+                            double ei, double ea, const double* xy0, const double* rot0,
+                            int32_t* body_id);
+
+/* Sub-domain rectangle (Sec. 3.1.1); it is snapped outwards to finest-level vertices. */
+ib_status ib_set_subdomain(ib_solver* s, double x0, double x1, double y0, double y1);
+
+/* Initial vorticity of one level: omega[(n-1)^2] at interior vertices (host). */
+ib_status ib_set_vorticity(ib_solver* s, int32_t level, const double* omega);
+
+/* Offline stage: initial streamfunction from the vorticity, then the stationary
+ * Schur inverse (exact mode, rigid bodies only) or B' (Algorithm 1). */
+ib_status ib_prepare(ib_solver* s);
+
+/* Online stage: advance nsteps time steps (Algorithm 2). */
+ib_status ib_step(ib_solver* s, int32_t nsteps);
+
+ib_status ib_sync(ib_solver* s);
+
+/* Stresses of a body after the last step: 2m doubles (x block then y block). */
+ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap);
+
+/* Structure state: torsional -> (theta, phi, phidot); deformable -> 3m doubles
+ * (x, y, rotation per node); rigid -> its 2m point coordinates. */
+ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap);
+
+/* Vorticity omega = C^T C s / h^2 of a level at interior vertices, (n-1)^2 doubles. */
+ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap);
+
+/* Streamfunction of a level including its ring, (n+1)^2 doubles. */
+ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap);
+
+ib_status ib_get_stats(ib_solver* s, ib_stats* out);
+
+ib_status ib_destroy(ib_solver* s);
+
+const char* ib_status_str(ib_status st);
+
+/* ---- operator-level entry points (device pointers, enqueued on hip_stream) ---- */
+
+/* out = [L (I + alpha L)]^{-1} in, L = C^T C with zero boundary values (the solve of
+ * eqs. (16) and (20) without its dt factor; Sec. 3.2.1).  in/out: (n-1) x (n-1) arrays
+ * of float (precision = IB_FP32_FLOW) or double (IB_FP64) with row pitch `pitch`
+ * elements; in == out is allowed. */
+ib_status ib_op_solve(int32_t n, int32_t precision, double alpha, const void* in, void* out,
+                      int32_t pitch, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBFSI_H */

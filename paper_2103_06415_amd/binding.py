@@ -1,0 +1,246 @@
+"""ctypes binding of libibfsi.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts Python/NumPy
+arguments to the C-ABI declared in ``include/ibfsi.h`` and raises on error codes.
+PyTorch supplies device memory (through the allocator callbacks) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libibfsi.so")
+
+IB_FP64 = 0
+IB_FP32_FLOW = 1
+IB_SCHUR_AUTO = 0
+IB_SCHUR_EXACT = 1
+IB_SCHUR_SUBDOMAIN = 2
+
+STATUS = {
+    0: "IB_OK", -1: "IB_ERR_ARG", -2: "IB_ERR_STATE", -3: "IB_ERR_OOM", -4: "IB_ERR_HIP",
+    -5: "IB_ERR_NOT_CONVERGED", -6: "IB_ERR_OUT_OF_SUBDOMAIN", -7: "IB_ERR_NEAR_BOUNDARY",
+    -8: "IB_ERR_NONFINITE", -9: "IB_ERR_CAPACITY",
+}
+
+
+class IbError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class IbConfig(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32), ("levels", c_int32), ("h", c_double), ("cx", c_double), ("cy", c_double),
+        ("re", c_double), ("dt", c_double), ("u_inf", c_double * 2), ("precision", c_int32),
+        ("schur_mode", c_int32), ("newton_tol", c_double), ("newton_max_iter", c_int32),
+        ("newton_fixed_iter", c_int32), ("drop_tol", c_double),
+    ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class IbAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", c_void_p)]
+
+
+class IbStats(ctypes.Structure):
+    _fields_ = [
+        ("step", c_int64), ("newton_iters", c_int32), ("newton_iters_max", c_int32),
+        ("newton_delta", c_double), ("subdomain_points", c_int64), ("subdomain_nnz", c_int64),
+        ("prepare_seconds", c_double),
+    ]
+
+
+_SIGS = {
+    "ib_create": (c_int32, [POINTER(IbConfig), POINTER(IbAllocator), c_void_p, POINTER(c_void_p)]),
+    "ib_add_rigid": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, POINTER(c_double),
+                               POINTER(c_int32)]),
+    "ib_add_torsional": (c_int32, [c_void_p, c_int32] + [c_double] * 9 + [POINTER(c_int32)]),
+    "ib_add_deformable": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, c_double,
+                                    c_double, POINTER(c_double), POINTER(c_double),
+                                    POINTER(c_int32)]),
+    "ib_set_subdomain": (c_int32, [c_void_p, c_double, c_double, c_double, c_double]),
+    "ib_set_vorticity": (c_int32, [c_void_p, c_int32, POINTER(c_double)]),
+    "ib_prepare": (c_int32, [c_void_p]),
+    "ib_step": (c_int32, [c_void_p, c_int32]),
+    "ib_sync": (c_int32, [c_void_p]),
+    "ib_read_stresses": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
+    "ib_read_deflection": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
+    "ib_read_vorticity": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
+    "ib_read_streamfunction": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
+    "ib_get_stats": (c_int32, [c_void_p, POINTER(IbStats)]),
+    "ib_destroy": (c_int32, [c_void_p]),
+    "ib_status_str": (ctypes.c_char_p, [c_int32]),
+    "ib_op_solve": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_void_p, c_int32, c_void_p]),
+}
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library; raises if it is missing (no fallback exists)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"libibfsi.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise IbError(code, what)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator, on the solver's stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.stream = stream
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = IbAllocator(self._alloc, self._free, None)
+
+
+def op_solve(n, precision, alpha, in_ptr, out_ptr, pitch, stream=0):
+    """[L (I + alpha L)]^{-1} on device arrays (see ib_op_solve)."""
+    lib = load()
+    _check(lib.ib_op_solve(n, precision, alpha, c_void_p(in_ptr), c_void_p(out_ptr), pitch,
+                           c_void_p(stream)), "ib_op_solve")
+
+
+class Solver:
+    """One solver instance built from a ``workloads.Problem``."""
+
+    def __init__(self, problem, precision=IB_FP64, schur=IB_SCHUR_AUTO, newton_tol=1e-7,
+                 newton_max=20, fixed_iters=0, drop_tol=0.007, torch_alloc=True, stream=None):
+        import torch
+        import workloads as W
+        self.lib = load()
+        self.problem = problem
+        fl = problem.flow
+        cfg = IbConfig()
+        cfg.n, cfg.levels, cfg.h = fl.n, fl.levels, fl.h
+        cfg.cx, cfg.cy, cfg.re, cfg.dt = fl.cx, fl.cy, fl.re, fl.dt
+        cfg.u_inf[0], cfg.u_inf[1] = fl.u_inf
+        cfg.precision, cfg.schur_mode = precision, schur
+        cfg.newton_tol, cfg.newton_max_iter = newton_tol, newton_max
+        cfg.newton_fixed_iter, cfg.drop_tol = fixed_iters, drop_tol
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._alloc = TorchAllocator(torch.cuda.current_device(), self.stream) if torch_alloc else None
+        self.handle = c_void_p()
+        _check(self.lib.ib_create(byref(cfg), byref(self._alloc.struct) if self._alloc else None,
+                                  c_void_p(self.stream.cuda_stream), byref(self.handle)), "ib_create")
+        self.npts = []
+        for b in problem.bodies:
+            bid = c_int32()
+            if isinstance(b, W.Rigid):
+                xy = _f64(b.xy)
+                ub = None if b.u_b is None else _f64(b.u_b)
+                _check(self.lib.ib_add_rigid(self.handle, xy.shape[0], _dptr(xy), b.ds,
+                                             None if ub is None else _dptr(ub), byref(bid)),
+                       "ib_add_rigid")
+                self.npts.append(xy.shape[0])
+            elif isinstance(b, W.Torsional):
+                _check(self.lib.ib_add_torsional(self.handle, b.n, b.hinge[0], b.hinge[1], b.length,
+                                                 b.theta0, b.inertia, b.stiffness, b.damping,
+                                                 b.theta, b.phi, byref(bid)), "ib_add_torsional")
+                self.npts.append(b.n)
+            else:
+                xr, x0, r0 = _f64(b.xy_ref), _f64(b.xy0), _f64(b.rot0)
+                _check(self.lib.ib_add_deformable(self.handle, xr.shape[0], _dptr(xr), b.mass, b.ei,
+                                                  b.ea, _dptr(x0), _dptr(r0), byref(bid)),
+                       "ib_add_deformable")
+                self.npts.append(xr.shape[0])
+        if problem.subdomain is not None:
+            _check(self.lib.ib_set_subdomain(self.handle, *problem.subdomain), "ib_set_subdomain")
+        if problem.vorticity0 is not None:
+            for g, w in enumerate(problem.vorticity0):
+                if w is not None:
+                    w = _f64(w)
+                    _check(self.lib.ib_set_vorticity(self.handle, g, _dptr(w)), "ib_set_vorticity")
+
+    def prepare(self):
+        _check(self.lib.ib_prepare(self.handle), "ib_prepare")
+
+    def step(self, n=1):
+        _check(self.lib.ib_step(self.handle, n), "ib_step")
+
+    def sync(self):
+        _check(self.lib.ib_sync(self.handle), "ib_sync")
+
+    def stresses(self, body):
+        out = np.zeros(2 * self.npts[body])
+        _check(self.lib.ib_read_stresses(self.handle, body, _dptr(out), out.size), "ib_read_stresses")
+        return out
+
+    def deflection(self, body):
+        import workloads as W
+        b = self.problem.bodies[body]
+        size = 3 if isinstance(b, W.Torsional) else (3 if isinstance(b, W.Deformable) else 2) * self.npts[body]
+        out = np.zeros(size)
+        _check(self.lib.ib_read_deflection(self.handle, body, _dptr(out), out.size), "ib_read_deflection")
+        return out
+
+    def vorticity(self, level=0):
+        n = self.problem.flow.n
+        out = np.zeros((n - 1) * (n - 1))
+        _check(self.lib.ib_read_vorticity(self.handle, level, _dptr(out), out.size), "ib_read_vorticity")
+        return out.reshape(n - 1, n - 1)
+
+    def streamfunction(self, level=0):
+        n = self.problem.flow.n
+        out = np.zeros((n + 1) * (n + 1))
+        _check(self.lib.ib_read_streamfunction(self.handle, level, _dptr(out), out.size),
+               "ib_read_streamfunction")
+        return out.reshape(n + 1, n + 1)
+
+    def stats(self):
+        st = IbStats()
+        _check(self.lib.ib_get_stats(self.handle, byref(st)), "ib_get_stats")
+        return {k: getattr(st, k) for k, _ in IbStats._fields_}
+
+    def close(self):
+        if self.handle:
+            self.lib.ib_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,934 @@
+// Kernels of the FSI loop and of the offline stage.
+//
+// Body operator (Sec. 3.1): every stress row a (one component of one body point) is
+// a window of 4 x 4 faces with weights.  Exact mode uses the true interpolation E
+// (eq. (24), 3-point kernel of Roma et al.); sub-domain mode uses P E0 (eqs. (22),
+// (26)-(29)): the hat interpolation over the 4 surrounding sub-domain vertices of
+// their E0 rows, or weight 1 on an appended exact point.
+//
+// FSI iteration (eqs. (17)-(19) / (37)-(39)): body operator and u* = (1/h) E (C s* +
+// q_inf), flow block of the Schur matrix (stationary inverse, or P B' P^T from the
+// CSR of B'), structural blocks and right-hand side, LU solve for f, structure
+// update and the convergence measure.  The host reads the measure and decides.
+#include <math.h>
+
+#include "ib_body.hpp"
+#include "ib_internal.hpp"
+#include "ib_fft.hpp"
+
+namespace ib {
+
+__device__ __forceinline__ double roma3(double r) {
+  const double a = fabs(r);
+  if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+  if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(fmax(0.0, 1.0 - 3.0 * (1.0 - a) * (1.0 - a)))) / 6.0;
+  return 0.0;
+}
+
+// True-E window of a point for one component (0: x-faces, 1: y-faces).
+__device__ void exact_window(double px, double py, int comp, double x0, double y0, double h,
+                             int* base, double* w) {
+  for (int e = 0; e < 16; ++e) w[e] = 0.0;
+  int ic, jc;
+  if (comp == 0) {
+    ic = (int)rint((px - x0) / h);
+    jc = (int)rint((py - y0) / h - 0.5);
+  } else {
+    ic = (int)rint((px - x0) / h - 0.5);
+    jc = (int)rint((py - y0) / h);
+  }
+  base[0] = ic - 1;
+  base[1] = jc - 1;
+  for (int dj = 0; dj < 3; ++dj) {
+    const int j = jc - 1 + dj;
+    const double fy = comp == 0 ? y0 + h * (j + 0.5) : y0 + h * j;
+    const double wy = roma3((fy - py) / h);
+    for (int di = 0; di < 3; ++di) {
+      const int i = ic - 1 + di;
+      const double fx = comp == 0 ? x0 + h * i : x0 + h * (i + 0.5);
+      w[dj * 4 + di] = wy * roma3((fx - px) / h);
+    }
+  }
+}
+
+// E0 row of sub-domain grid vertex (p, q) added with weight c into the window at base.
+__device__ void add_e0_vertex(int p, int q, int comp, double c, double x0, double y0, double h,
+                              const int* base, double* w) {
+  const double px = x0 + p * h, py = y0 + q * h;
+  for (int dj = 0; dj < 4; ++dj) {
+    const int j = base[1] + dj;
+    const double fy = comp == 0 ? y0 + h * (j + 0.5) : y0 + h * j;
+    const double wy = roma3((fy - py) / h);
+    if (wy == 0.0) continue;
+    for (int di = 0; di < 4; ++di) {
+      const int i = base[0] + di;
+      const double fx = comp == 0 ? x0 + h * i : x0 + h * (i + 0.5);
+      w[dj * 4 + di] += c * (wy * roma3((fx - px) / h));
+    }
+  }
+}
+
+// The faces touched with nonzero weight must have both end vertices interior.
+__device__ bool window_ok(const int* base, const double* w, int comp, int n) {
+  for (int dj = 0; dj < 4; ++dj)
+    for (int di = 0; di < 4; ++di) {
+      if (w[dj * 4 + di] == 0.0) continue;
+      const int i = base[0] + di, j = base[1] + dj;
+      if (comp == 0) {
+        if (i < 1 || i > n - 1 || j < 1 || j > n - 2) return false;
+      } else {
+        if (i < 1 || i > n - 2 || j < 1 || j > n - 1) return false;
+      }
+    }
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ double face_flux(const T* s, int ps, int comp, int i, int j, double ux,
+                                            double uy) {
+  if (comp == 0) return ((double)s[(size_t)(j + 1) * ps + i] - (double)s[(size_t)j * ps + i]) + ux;
+  return -((double)s[(size_t)j * ps + i + 1] - (double)s[(size_t)j * ps + i]) + uy;
+}
+
+__device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, double* px,
+                               double* py) {
+  if (b.kind == BODY_RIGID) {
+    *px = a.rigid_xy[2 * (b.pt0 + local)];
+    *py = a.rigid_xy[2 * (b.pt0 + local) + 1];
+  } else if (b.kind == BODY_TORSIONAL) {
+    const double* ts = a.tors + b.tors * TS_COUNT;
+    const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
+    const double ang = b.theta0 + th;
+    const double r = local * b.ds;
+    *px = b.hx + r * cos(ang);
+    *py = b.hy + r * sin(ang);
+  } else {
+    const double* c = a.iter == 0 ? a.chi : a.chi_new;
+    *px = c[b.dof0 + 3 * local];
+    *py = c[b.dof0 + 3 * local + 1];
+  }
+}
+
+// Body operator rows and u* for every point; one thread per point.
+template <typename T>
+__global__ void k_body_ops(FsiArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.npts) return;
+  int bi = 0;
+  while (bi + 1 < a.nbodies && a.bodies[bi + 1].pt0 <= p) ++bi;
+  const BodyDev& b = a.bodies[bi];
+  const int local = p - b.pt0;
+  double px, py;
+  point_position(a, b, local, &px, &py);
+  a.pos[2 * p] = px;
+  a.pos[2 * p + 1] = py;
+  const T* s = static_cast<const T*>(a.sstar);
+  for (int comp = 0; comp < 2; ++comp) {
+    const int row = 2 * b.pt0 + comp * b.npts + local;
+    int base[2];
+    double w[16];
+    int* pidx = a.p_idx + 4 * row;
+    double* pw = a.p_w + 4 * row;
+    if (!a.use_sd) {
+      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w);
+    } else if (b.kind == BODY_RIGID) {
+      const int app = a.sd_ngrid + b.app0 + local;
+      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w);
+      for (int e = 0; e < 4; ++e) {
+        pidx[e] = comp * a.sd_total + app;
+        pw[e] = e == 0 ? 1.0 : 0.0;
+      }
+    } else {
+      const double xs0 = a.x0 + a.sd_i0 * a.h, ys0 = a.y0 + a.sd_j0 * a.h;
+      const double rx = (px - xs0) / a.h, ry = (py - ys0) / a.h;
+      const double tol = 1e-9;
+      if (!(rx >= -tol && ry >= -tol && rx <= a.sd_npx - 1 + tol && ry <= a.sd_npy - 1 + tol)) {
+        atomicMax(&a.flags[0], 1);  // out of sub-domain (or non-finite position)
+        for (int e = 0; e < 16; ++e) w[e] = 0.0;
+        base[0] = base[1] = 2;
+        for (int e = 0; e < 4; ++e) {
+          pidx[e] = 0;
+          pw[e] = 0.0;
+        }
+      } else {
+        int ix = (int)floor(rx), iy = (int)floor(ry);
+        ix = ix < 0 ? 0 : (ix > a.sd_npx - 2 ? a.sd_npx - 2 : ix);
+        iy = iy < 0 ? 0 : (iy > a.sd_npy - 2 ? a.sd_npy - 2 : iy);
+        const double fx = rx - ix, fy = ry - iy;
+        const int gp = a.sd_i0 + ix, gq = a.sd_j0 + iy;
+        base[0] = gp - 1;
+        base[1] = gq - 1;
+        for (int e = 0; e < 16; ++e) w[e] = 0.0;
+        const double hw[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};
+        const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
+        for (int e = 0; e < 4; ++e) {
+          pidx[e] = comp * a.sd_total + (iy + dy[e]) * a.sd_npx + (ix + dx[e]);
+          pw[e] = hw[e];
+          add_e0_vertex(gp + dx[e], gq + dy[e], comp, hw[e], a.x0, a.y0, a.h, base, w);
+        }
+      }
+    }
+    if (!window_ok(base, w, comp, a.n)) {
+      atomicMax(&a.flags[0], 2);  // near the boundary: keep every later access in bounds
+      for (int e = 0; e < 16; ++e) w[e] = 0.0;
+      base[0] = base[1] = 2;
+    }
+    a.st_base[3 * row] = base[0];
+    a.st_base[3 * row + 1] = base[1];
+    a.st_base[3 * row + 2] = comp;
+    double acc = 0.0;
+    for (int dj = 0; dj < 4; ++dj)
+      for (int di = 0; di < 4; ++di) {
+        const double ww = w[dj * 4 + di];
+        a.st_w[16 * row + dj * 4 + di] = ww;
+        if (ww != 0.0)
+          acc += ww * face_flux(s, a.ps, comp, base[0] + di, base[1] + dj, a.ux, a.uy);
+      }
+    a.ustar[row] = acc / a.h;
+  }
+}
+
+// Entry (c, d) of B' by binary search in CSR row c.
+__device__ __forceinline__ double bp_lookup(const FsiArgs& a, int c, int d) {
+  int64_t lo = a.bp_ptr[c], hi = a.bp_ptr[c + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int v = a.bp_col[mid];
+    if (v == d) return a.bp_val[mid];
+    if (v < d) lo = mid + 1;
+    else hi = mid;
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ double row_ds(const FsiArgs& a, int row) {
+  const int p = row >> 1;  // rows of a body are 2 pt0 .. 2 pt0 + 2m - 1
+  int bi = 0;
+  while (bi + 1 < a.nbodies && 2 * a.bodies[bi + 1].pt0 <= row) ++bi;
+  (void)p;
+  return a.bodies[bi].ds;
+}
+
+// Flow block of the Schur matrix in sub-domain mode: (dt/h^2) (P B' P^T)_ab ds_b.
+__global__ void k_schur_sd(FsiArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nf * a.nf) return;
+  const int r = e / a.nf, c = e % a.nf;
+  double acc = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const double wu = a.p_w[4 * r + u];
+    if (wu == 0.0) continue;
+    const int cu = a.p_idx[4 * r + u];
+    double inner = 0.0;
+    for (int v = 0; v < 4; ++v) {
+      const double wv = a.p_w[4 * c + v];
+      if (wv == 0.0) continue;
+      inner += wv * bp_lookup(a, cu, a.p_idx[4 * c + v]);
+    }
+    acc += wu * inner;
+  }
+  a.M[(size_t)r * a.pm + c] = (a.dt / (a.h * a.h)) * acc * row_ds(a, c);
+}
+
+// -------------------------------------------------------- corotational beam
+// Element internal force fe[6] and tangent ke[36] (Crisfield's 2-D corotational
+// Euler-Bernoulli element; rotations relative to the straight reference).
+__device__ void beam_element(const double* x, double l0, double beta0, double ea, double ei,
+                             double* fe, double* ke) {
+  const double dx = x[3] - x[0], dy = x[4] - x[1];
+  const double len = sqrt(dx * dx + dy * dy);
+  const double c = dx / len, s = dy / len;
+  double al = atan2(dy, dx) - beta0;
+  al = al - 2.0 * M_PI * floor((al + M_PI) / (2.0 * M_PI));
+  double t1 = x[2] - al, t2 = x[5] - al;
+  t1 = t1 - 2.0 * M_PI * floor((t1 + M_PI) / (2.0 * M_PI));
+  t2 = t2 - 2.0 * M_PI * floor((t2 + M_PI) / (2.0 * M_PI));
+  const double nax = ea * (len - l0) / l0;
+  const double m1 = 2.0 * ei / l0 * (2.0 * t1 + t2);
+  const double m2 = 2.0 * ei / l0 * (t1 + 2.0 * t2);
+  const double r[6] = {-c, -s, 0.0, c, s, 0.0};
+  const double z[6] = {s, -c, 0.0, -s, c, 0.0};
+  double bm[3][6];
+  for (int k = 0; k < 6; ++k) {
+    bm[0][k] = r[k];
+    bm[1][k] = (k == 2 ? 1.0 : 0.0) - z[k] / len;
+    bm[2][k] = (k == 5 ? 1.0 : 0.0) - z[k] / len;
+  }
+  const double d[3][3] = {{ea / l0, 0.0, 0.0},
+                          {0.0, 4.0 * ei / l0, 2.0 * ei / l0},
+                          {0.0, 2.0 * ei / l0, 4.0 * ei / l0}};
+  const double fl[3] = {nax, m1, m2};
+  for (int k = 0; k < 6; ++k) fe[k] = bm[0][k] * fl[0] + bm[1][k] * fl[1] + bm[2][k] * fl[2];
+  for (int p = 0; p < 6; ++p)
+    for (int q = 0; q < 6; ++q) {
+      double v = 0.0;
+      for (int u = 0; u < 3; ++u) {
+        double t = 0.0;
+        for (int w = 0; w < 3; ++w) t += d[u][w] * bm[w][q];
+        v += bm[u][p] * t;
+      }
+      v += (nax / len) * z[p] * z[q] + ((m1 + m2) / (len * len)) * (r[p] * z[q] + z[p] * r[q]);
+      ke[p * 6 + q] = v;
+    }
+}
+
+// Band LU (half-bandwidth 5, no pivoting: J_d is dominated by its mass term) of an
+// nd system stored as band[u * 11 + (v - u + 5)]; one thread.
+__device__ void band_factor(double* band, int nd) {
+  for (int k = 0; k < nd; ++k) {
+    const double piv = band[k * 11 + 5];
+    const int hi = k + 5 > nd - 1 ? nd - 1 : k + 5;
+    for (int i = k + 1; i <= hi; ++i) {
+      const double l = band[i * 11 + (k - i + 5)] / piv;
+      band[i * 11 + (k - i + 5)] = l;
+      for (int j = k + 1; j <= hi; ++j) band[i * 11 + (j - i + 5)] -= l * band[k * 11 + (j - k + 5)];
+    }
+  }
+}
+
+// Forward and back substitution with a sliding register window; x is read through
+// `in(u)` and the result written to out[u * stride].
+template <typename F>
+__device__ void band_solve(const double* lu, int nd, F in, double* out, size_t stride) {
+  double w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0;  // x[u-1] .. x[u-5]
+  for (int u = 0; u < nd; ++u) {
+    const double* row = lu + u * 11;
+    double v = in(u);
+    if (u >= 1) v -= row[4] * w0;
+    if (u >= 2) v -= row[3] * w1;
+    if (u >= 3) v -= row[2] * w2;
+    if (u >= 4) v -= row[1] * w3;
+    if (u >= 5) v -= row[0] * w4;
+    out[(size_t)u * stride] = v;
+    w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
+  }
+  w0 = w1 = w2 = w3 = w4 = 0;  // x[u+1] .. x[u+5]
+  for (int u = nd - 1; u >= 0; --u) {
+    const double* row = lu + u * 11;
+    double v = out[(size_t)u * stride];
+    if (u + 1 < nd) v -= row[6] * w0;
+    if (u + 2 < nd) v -= row[7] * w1;
+    if (u + 3 < nd) v -= row[8] * w2;
+    if (u + 4 < nd) v -= row[9] * w3;
+    if (u + 5 < nd) v -= row[10] * w4;
+    v /= row[5];
+    out[(size_t)u * stride] = v;
+    w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
+  }
+}
+
+constexpr int MAX_BEAM_DOF = 600;  // free DOFs of one deformable body (<= 201 nodes)
+
+constexpr int STRUCT_NT = 256;
+
+// Structural blocks of the Schur matrix and right-hand side (one workgroup).
+//   rigid       rhs -= u_b
+//   torsional   M += (2 ds/dt) S^T S / J,  rhs -= S ((2/dt) r_phi / J - r_theta)
+//   deformable  M += (2 ds/dt) T J_d^{-1} T^T,
+//               rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
+__global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_M) {
+  const int tid = threadIdx.x;
+  (void)flow_in_M;  // the flow block is either already in M or not used (stationary inverse)
+  for (int r = tid; r < a.nf; r += STRUCT_NT) a.rhs[r] = a.ustar[r];
+  __syncthreads();
+  const double dt = a.dt;
+  for (int bi = 0; bi < a.nbodies; ++bi) {
+    const BodyDev& b = a.bodies[bi];
+    const int m = b.npts, r0 = 2 * b.pt0;
+    if (b.kind == BODY_RIGID) {
+      if (b.has_ub)
+        for (int e = tid; e < 2 * m; e += STRUCT_NT) {
+          const int pt = b.pt0 + (e % m);
+          a.rhs[r0 + e] -= a.rigid_ub[2 * pt + e / m];
+        }
+    } else if (b.kind == BODY_TORSIONAL) {
+      const double* ts = a.tors + b.tors * TS_COUNT;
+      const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
+      const double ang = b.theta0 + th;
+      const double sn = sin(ang), cs = cos(ang);
+      const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
+      const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
+                          b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
+      const double rth = ts[TS_PHI] + 2.0 * ts[TS_THETA] / dt;
+      const double coef = (2.0 * b.ds / dt) / jt;
+      const double rc = (2.0 / dt) * rphi / jt - rth;
+      for (int e = tid; e < 4 * m * m; e += STRUCT_NT) {
+        const int u = e / (2 * m), v = e % (2 * m);
+        const double su = (u < m ? -sn : cs) * (u % m) * b.ds;
+        const double sv = (v < m ? -sn : cs) * (v % m) * b.ds;
+        a.M[(size_t)(r0 + u) * a.pm + r0 + v] += coef * su * sv;
+      }
+      for (int e = tid; e < 2 * m; e += STRUCT_NT) {
+        const double su = (e < m ? -sn : cs) * (e % m) * b.ds;
+        a.rhs[r0 + e] -= su * rc;
+      }
+    } else {
+      // deformable: assemble J_d in band form over the free DOFs in LDS
+      __shared__ double band[MAX_BEAM_DOF * 11];
+      __shared__ double rint[MAX_BEAM_DOF + 3];
+      const int nd = 3 * m - 3;
+      const double* chi = a.iter == 0 ? a.chi : a.chi_new;
+      const double* xn = a.chi + b.dof0;
+      const double* zn = a.zeta + b.dof0;
+      const double* an = a.zetadot + b.dof0;
+      const double* ms = a.dmass + b.dof0;
+      const double* ck = chi + b.dof0;
+      for (int e = tid; e < nd * 11; e += STRUCT_NT) band[e] = 0.0;
+      for (int e = tid; e < 3 * m; e += STRUCT_NT) rint[e] = 0.0;
+      __syncthreads();
+      for (int parity = 0; parity < 2; ++parity) {
+        for (int el = 2 * tid + parity; el < m - 1; el += 2 * STRUCT_NT) {
+          double fe[6], ke[36];
+          beam_element(ck + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el], b.ea, b.ei, fe, ke);
+          for (int p = 0; p < 6; ++p) {
+            const int gp = 3 * el + p;
+            rint[gp] += fe[p];
+            if (gp < 3) continue;
+            for (int q = 0; q < 6; ++q) {
+              const int gq = 3 * el + q;
+              if (gq < 3) continue;
+              band[(gp - 3) * 11 + (gq - gp + 5)] += ke[p * 6 + q];
+            }
+          }
+        }
+        __syncthreads();
+      }
+      double* res = a.dres + b.dof0;
+      for (int u = tid; u < nd; u += STRUCT_NT) {
+        const int g = u + 3;
+        band[u * 11 + 5] += 4.0 * ms[g] / (dt * dt);
+        const double rz = ms[g] * (4.0 * xn[g] / (dt * dt) + 4.0 * zn[g] / dt + an[g]);
+        res[g] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint[g];
+      }
+      __syncthreads();
+      if (tid == 0) band_factor(band, nd);
+      __syncthreads();
+      double* lu = a.band + (size_t)b.band0 * 11;
+      for (int e = tid; e < nd * 11; e += STRUCT_NT) lu[e] = band[e];
+      // columns of J_d^{-1} T^T (2m, node 0's are zero) and J_d^{-1} res
+      const int ncol = 2 * m + 1;
+      double* y = a.ywork + b.yoff;  // [nd][2m+1]
+      for (int col = tid; col < ncol; col += STRUCT_NT) {
+        if (col < 2 * m) {
+          const int node = col % m, cmp = col / m;
+          const int hot = node > 0 ? 3 * node + cmp - 3 : -1;
+          band_solve(band, nd, [&](int u) { return u == hot ? 1.0 : 0.0; }, y + col, ncol);
+        } else {
+          band_solve(band, nd, [&](int u) { return res[u + 3]; }, y + col, ncol);
+        }
+      }
+      __syncthreads();
+      const double coef = 2.0 * b.ds / dt;
+      for (int e = tid; e < 4 * m * m; e += STRUCT_NT) {
+        const int u = e / (2 * m), v = e % (2 * m);
+        const int node = u % m, cmp = u / m;
+        if (node == 0) continue;
+        const int du = 3 * node + cmp - 3;
+        a.M[(size_t)(r0 + u) * a.pm + r0 + v] += coef * y[(size_t)du * ncol + v];
+      }
+      for (int u = tid; u < 2 * m; u += STRUCT_NT) {
+        const int node = u % m, cmp = u / m;
+        if (node == 0) continue;
+        const int g = 3 * node + cmp;
+        const double pred = ck[g] + y[(size_t)(g - 3) * ncol + 2 * m];
+        const double rchi = zn[g] + 2.0 * xn[g] / dt;
+        a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int LU_NT = 1024;
+
+// Solve M X = B in place (partial pivoting, one workgroup).  M: n x n (pitch pm),
+// B: n x nrhs (pitch pb).  M is overwritten.
+__global__ __launch_bounds__(LU_NT) void k_lu_solve(double* M, int pm, double* B, int pb, int n,
+                                                    int nrhs, int* flags) {
+  __shared__ double sv[LU_NT / 64];
+  __shared__ int si[LU_NT / 64];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += LU_NT) {
+      const double v = fabs(M[(size_t)i * pm + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(best, off);
+      const int oi = __shfl_down(bi, off);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      sv[wv] = best;
+      si[wv] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b2 = sv[0];
+      int i2 = si[0];
+      for (int w = 1; w < LU_NT / 64; ++w)
+        if (sv[w] > b2 || (sv[w] == b2 && si[w] < i2)) {
+          b2 = sv[w];
+          i2 = si[w];
+        }
+      piv_s = i2;
+      if (!(b2 > 0.0)) flags[0] = flags[0] > 3 ? flags[0] : 3;  // singular / non-finite
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != k) {
+      for (int j = k + tid; j < n; j += LU_NT) {
+        const double t = M[(size_t)k * pm + j];
+        M[(size_t)k * pm + j] = M[(size_t)p * pm + j];
+        M[(size_t)p * pm + j] = t;
+      }
+      for (int j = tid; j < nrhs; j += LU_NT) {
+        const double t = B[(size_t)k * pb + j];
+        B[(size_t)k * pb + j] = B[(size_t)p * pb + j];
+        B[(size_t)p * pb + j] = t;
+      }
+    }
+    __syncthreads();
+    const double pivot = M[(size_t)k * pm + k];
+    const int rows = n - k - 1;
+    const int wcols = (n - k - 1) + nrhs;
+    for (int e = tid; e < rows * wcols; e += LU_NT) {
+      const int i = k + 1 + e / wcols, c = e % wcols;
+      const double l = M[(size_t)i * pm + k] / pivot;
+      if (c < n - k - 1) {
+        const int j = k + 1 + c;
+        M[(size_t)i * pm + j] -= l * M[(size_t)k * pm + j];
+      } else {
+        const int j = c - (n - k - 1);
+        B[(size_t)i * pb + j] -= l * B[(size_t)k * pb + j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double d = M[(size_t)k * pm + k];
+    for (int j = tid; j < nrhs; j += LU_NT) B[(size_t)k * pb + j] /= d;
+    __syncthreads();
+    for (int e = tid; e < k * nrhs; e += LU_NT) {
+      const int i = e / nrhs, j = e % nrhs;
+      B[(size_t)i * pb + j] -= M[(size_t)i * pm + k] * B[(size_t)k * pb + j];
+    }
+    __syncthreads();
+  }
+}
+
+// f = Minv rhs (stationary bodies).
+__global__ void k_matvec(const double* A, int pa, const double* x, double* y, int n) {
+  const int r = blockIdx.x;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) acc += A[(size_t)r * pa + c] * x[c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[r] = red[0];
+}
+
+// Structure update from the new stresses and the convergence measure (one workgroup).
+__global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
+  __shared__ double dmax[STRUCT_NT];
+  const int tid = threadIdx.x;
+  double my = 0.0;
+  for (int bi = 0; bi < a.nbodies; ++bi) {
+    const BodyDev& b = a.bodies[bi];
+    const int m = b.npts, r0 = 2 * b.pt0;
+    if (b.kind == BODY_TORSIONAL) {
+      if (tid == 0) {
+        double* ts = a.tors + b.tors * TS_COUNT;
+        const double dt = a.dt;
+        const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
+        const double ang = b.theta0 + th;
+        const double sn = sin(ang), cs = cos(ang);
+        const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
+        const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
+                            b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
+        double sf = 0.0;
+        for (int u = 0; u < 2 * m; ++u) sf += (u < m ? -sn : cs) * (u % m) * b.ds * a.f[r0 + u];
+        const double thn = (rphi + b.ds * sf) / jt;
+        my = fmax(my, fabs(thn - th));
+        ts[TS_NEW] = thn;
+      }
+    } else if (b.kind == BODY_DEFORMABLE) {
+      __shared__ double band[MAX_BEAM_DOF * 11];
+      const int nd = 3 * m - 3;
+      const double* lu = a.band + (size_t)b.band0 * 11;
+      for (int e = tid; e < nd * 11; e += STRUCT_NT) band[e] = lu[e];
+      __syncthreads();
+      if (tid == 0) {
+        const double* res = a.dres + b.dof0;
+        double* xw = a.ywork + b.yoff;  // column 0 of J_d^{-1} T^T reused as scratch
+        band_solve(band, nd, [&](int u) {
+          const int node = (u + 3) / 3, cmp = (u + 3) % 3;
+          double v = res[u + 3];
+          if (cmp < 2) v += b.ds * a.f[r0 + cmp * m + node];
+          return v;
+        }, xw, 2 * m + 1);
+        const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
+        double* cn = a.chi_new + b.dof0;
+        // ck may alias cn: each DOF is read before it is written
+        for (int u = 0; u < nd; ++u) {
+          const double dx = xw[(size_t)u * (2 * m + 1)];
+          my = fmax(my, fabs(dx));
+          cn[u + 3] = ck[u + 3] + dx;
+        }
+        cn[0] = ck[0];
+        cn[1] = ck[1];
+        cn[2] = ck[2];
+      }
+    }
+    __syncthreads();
+  }
+  dmax[tid] = my;
+  __syncthreads();
+  for (int s = STRUCT_NT / 2; s > 0; s >>= 1) {
+    if (tid < s) dmax[tid] = fmax(dmax[tid], dmax[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) a.delta[0] = dmax[0];
+}
+
+// Newmark completion of the step with the accepted iterate.
+__global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) {
+  const int tid = threadIdx.x;
+  const double dt = a.dt;
+  for (int bi = 0; bi < a.nbodies; ++bi) {
+    const BodyDev& b = a.bodies[bi];
+    if (b.kind == BODY_TORSIONAL) {
+      if (tid == 0) {
+        double* ts = a.tors + b.tors * TS_COUNT;
+        const double thn = ts[TS_NEW];
+        const double rth = ts[TS_PHI] + 2.0 * ts[TS_THETA] / dt;
+        const double phin = 2.0 * thn / dt - rth;
+        const double phidn = 4.0 * (thn - ts[TS_THETA]) / (dt * dt) - 4.0 * ts[TS_PHI] / dt - ts[TS_PHIDOT];
+        ts[TS_THETA] = thn;
+        ts[TS_PHI] = phin;
+        ts[TS_PHIDOT] = phidn;
+      }
+    } else if (b.kind == BODY_DEFORMABLE) {
+      for (int u = tid; u < 3 * b.npts; u += STRUCT_NT) {
+        const int g = b.dof0 + u;
+        if (u < 3) {
+          a.zeta[g] = 0.0;
+          a.zetadot[g] = 0.0;
+          continue;
+        }
+        const double xnew = a.chi_new[g];
+        const double rchi = a.zeta[g] + 2.0 * a.chi[g] / dt;
+        const double zn = 2.0 * xnew / dt - rchi;
+        const double an = 4.0 * (xnew - a.chi[g]) / (dt * dt) - 4.0 * a.zeta[g] / dt - a.zetadot[g];
+        a.chi[g] = xnew;
+        a.zeta[g] = zn;
+        a.zetadot[g] = an;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Corrector source C^T E^T lambda at interior vertices of rows [jlo, jhi]; entries
+// outside columns [ilo, ihi] are zero.  lambda_a = (ds_a / h) f_a.  Deterministic:
+// every vertex sums the rows in a fixed order.
+template <typename T>
+__global__ void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi, T* out, int po) {
+  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = jlo + blockIdx.y;
+  if (i > a.n - 1 || j > jhi) return;
+  double src = 0.0;
+  if (i >= ilo && i <= ihi) {
+    for (int r = 0; r < a.nf; ++r) {
+      const int i0 = a.st_base[3 * r], j0 = a.st_base[3 * r + 1], comp = a.st_base[3 * r + 2];
+      const int di = i - i0, dj = j - j0;
+      if (di < -1 || di > 4 || dj < -1 || dj > 4) continue;
+      const double* w = a.st_w + 16 * r;
+      double c = 0.0;
+      if (comp == 0) {
+        // x-faces [j][i] (-) and [j-1][i] (+)
+        if (di >= 0 && di < 4 && dj >= 0 && dj < 4) c -= w[dj * 4 + di];
+        if (di >= 0 && di < 4 && dj - 1 >= 0 && dj - 1 < 4) c += w[(dj - 1) * 4 + di];
+      } else {
+        // y-faces [j][i] (+) and [j][i-1] (-)
+        if (di >= 0 && di < 4 && dj >= 0 && dj < 4) c += w[dj * 4 + di];
+        if (di - 1 >= 0 && di - 1 < 4 && dj >= 0 && dj < 4) c -= w[dj * 4 + di - 1];
+      }
+      if (c != 0.0) src += c * (row_ds(a, r) / a.h) * a.f[r];
+    }
+  }
+  out[(size_t)(j - 1) * po + (i - 1)] = (T)src;
+}
+
+// ------------------------------------------------------------ offline stage
+
+__device__ void off_window(const OffRows& o, int row, int* base, int* comp, double* w) {
+  if (o.kind == 0) {
+    base[0] = o.st_base[3 * row];
+    base[1] = o.st_base[3 * row + 1];
+    *comp = o.st_base[3 * row + 2];
+    for (int e = 0; e < 16; ++e) w[e] = o.st_w[16 * row + e];
+    return;
+  }
+  *comp = row >= o.sd_total ? 1 : 0;
+  const int pt = row - (*comp) * o.sd_total;
+  if (pt < o.sd_ngrid) {
+    const int p = o.sd_i0 + pt % o.sd_npx, q = o.sd_j0 + pt / o.sd_npx;
+    base[0] = p - 1;
+    base[1] = q - 1;
+    for (int e = 0; e < 16; ++e) w[e] = 0.0;
+    add_e0_vertex(p, q, *comp, 1.0, o.x0, o.y0, o.h, base, w);
+  } else {
+    const int ap = pt - o.sd_ngrid;
+    exact_window(o.app_xy[2 * ap], o.app_xy[2 * ap + 1], *comp, o.x0, o.y0, o.h, base, w);
+  }
+}
+
+// Row-transformed point sources: slot b holds C^T E^T e_{col0 + b} after the row DST,
+// as 6 consecutive rows starting at rows_first[b] (1-based).
+template <typename T>
+__global__ void k_point_source_rowdst(OffRows o, int col0, int ncols, const c2<T>* __restrict__ tw,
+                                      T* out, int po, size_t bso, int* rows_first) {
+  const int b = blockIdx.y;
+  if (col0 + b >= ncols) return;
+  int base[2], comp;
+  double w[16];
+  off_window(o, col0 + b, base, &comp, w);
+  // vertex source on a 6 x 6 patch of vertices starting at (base[0], base[1])
+  double v[6][6];
+  for (int q = 0; q < 6; ++q)
+    for (int p = 0; p < 6; ++p) v[q][p] = 0.0;
+  for (int dj = 0; dj < 4; ++dj)
+    for (int di = 0; di < 4; ++di) {
+      const double ww = w[dj * 4 + di];
+      if (ww == 0.0) continue;
+      if (comp == 0) {  // x-face [j][i]: vertex (i, j) -w, vertex (i, j+1) +w
+        v[dj][di] -= ww;
+        v[dj + 1][di] += ww;
+      } else {          // y-face [j][i]: vertex (i, j) +w, vertex (i+1, j) -w
+        v[dj][di] += ww;
+        v[dj][di + 1] -= ww;
+      }
+    }
+  const int n = o.n;
+  if (threadIdx.x == 0 && blockIdx.x == 0) rows_first[b] = base[1];
+  T* ob = out + (size_t)b * bso;
+  // row DST: X_k = sum_i v_i sin(pi i k / n); sin(pi m / n) = -Im tw[m mod 2n]
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 6 * (n - 1); e += gridDim.x * blockDim.x) {
+    const int rq = e / (n - 1), k = 1 + e % (n - 1);
+    const int j = base[1] + rq;
+    double acc = 0.0;
+    if (j >= 1 && j <= n - 1) {
+      for (int p = 0; p < 6; ++p) {
+        const int i = base[0] + p;
+        if (v[rq][p] == 0.0 || i < 1 || i > n - 1) continue;
+        acc += v[rq][p] * (-(double)tw[(i * k) % (2 * n)].y);
+      }
+    }
+    ob[(size_t)rq * po + (k - 1)] = (T)acc;
+  }
+}
+
+// Sample E C s of every target row for each slot: vals[b * ntarget + t].
+template <typename T>
+__global__ void k_sample(OffRows o, int ntarget, const T* sl, int ps, size_t bss, double* vals,
+                         int nslots) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (t >= ntarget || b >= nslots) return;
+  int base[2], comp;
+  double w[16];
+  off_window(o, t, base, &comp, w);
+  const T* s = sl + (size_t)b * bss;
+  double acc = 0.0;
+  for (int dj = 0; dj < 4; ++dj)
+    for (int di = 0; di < 4; ++di) {
+      const double ww = w[dj * 4 + di];
+      if (ww != 0.0) acc += ww * face_flux(s, ps, comp, base[0] + di, base[1] + dj, 0.0, 0.0);
+    }
+  vals[(size_t)b * ntarget + t] = acc;
+}
+
+// Drop filter of column col0 + b (eq. (34), kept iff |b_tc| > eps |b_cc|) and
+// compaction in target order: cols/vals at b * ntarget, count in counts[b].
+constexpr int CMP_NT = 1024;
+__global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, int ntarget, int col0,
+                                                           int ncols, double eps, int* out_col,
+                                                           double* out_val, int* counts) {
+  const int b = blockIdx.x;
+  if (col0 + b >= ncols) return;
+  __shared__ int scan[CMP_NT];
+  __shared__ int base_s;
+  const double* v = vals + (size_t)b * ntarget;
+  const double thr = eps * fabs(v[col0 + b]);
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  for (int t0 = 0; t0 < ntarget; t0 += CMP_NT) {
+    const int t = t0 + threadIdx.x;
+    const int keep = (t < ntarget && fabs(v[t]) > thr) ? 1 : 0;
+    scan[threadIdx.x] = keep;
+    __syncthreads();
+    for (int off = 1; off < CMP_NT; off <<= 1) {
+      const int add = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (keep) {
+      const int pos = base_s + scan[threadIdx.x] - 1;
+      out_col[(size_t)b * ntarget + pos] = t;
+      out_val[(size_t)b * ntarget + pos] = v[t];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base_s += scan[CMP_NT - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[b] = base_s;
+}
+
+// ----------------------------------------------------------------- launchers
+
+template <typename T>
+hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_body_ops<T>), dim3((a.npts + 63) / 64), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
+  const int tot = a.nf * a.nf;
+  hipLaunchKernelGGL(k_schur_sd, dim3((tot + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st) {
+  hipLaunchKernelGGL(k_structure, dim3(1), dim3(STRUCT_NT), 0, st, a, flow_in_M);
+  return hipGetLastError();
+}
+hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(LU_NT), 0, st, M, pm, B, pb, n, nrhs, flags);
+  return hipGetLastError();
+}
+hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_matvec, dim3(n), dim3(256), 0, st, A, pa, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_update(const FsiArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3(1), dim3(STRUCT_NT), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_finish(const FsiArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(STRUCT_NT), 0, st, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,
+                         hipStream_t st) {
+  dim3 g((a.n - 1 + 127) / 128, jhi - jlo + 1);
+  hipLaunchKernelGGL((k_spread<T>), g, dim3(128), 0, st, a, jlo, jhi, ilo, ihi, out, po);
+  return hipGetLastError();
+}
+hipError_t launch_point_source_rowdst(const OffRows& o, int col0, int ncols, int nslots,
+                                      const void* tw, double* out, int po, size_t bso,
+                                      int* rows_first, hipStream_t st) {
+  hipLaunchKernelGGL((k_point_source_rowdst<double>), dim3(4, nslots), dim3(256), 0, st, o, col0,
+                     ncols, static_cast<const c2<double>*>(tw), out, po, bso, rows_first);
+  return hipGetLastError();
+}
+hipError_t launch_sample(const OffRows& o, int ntarget, const double* sl, int ps, size_t bss,
+                         double* vals, int nslots, hipStream_t st) {
+  hipLaunchKernelGGL((k_sample<double>), dim3((ntarget + 255) / 256, nslots), dim3(256), 0, st, o,
+                     ntarget, sl, ps, bss, vals, nslots);
+  return hipGetLastError();
+}
+hipError_t launch_filter_compact(const double* vals, int ntarget, int col0, int ncols, int nslots,
+                                 double eps, int* out_col, double* out_val, int* counts,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_filter_compact, dim3(nslots), dim3(CMP_NT), 0, st, vals, ntarget, col0,
+                     ncols, eps, out_col, out_val, counts);
+  return hipGetLastError();
+}
+
+// Concatenate the compacted entries of every slot (in slot order).
+__global__ void k_gather_batch(const int* cols, const double* vals, int ntarget, const int* counts,
+                               int* out_col, double* out_val) {
+  const int b = blockIdx.x;
+  int off = 0;
+  for (int q = 0; q < b; ++q) off += counts[q];
+  const int c = counts[b];
+  for (int e = threadIdx.x; e < c; e += blockDim.x) {
+    out_col[off + e] = cols[(size_t)b * ntarget + e];
+    out_val[off + e] = vals[(size_t)b * ntarget + e];
+  }
+}
+
+// M[:, c] *= s * colscale[c]
+__global__ void k_scale_cols(double* M, int pm, int n, const double* colscale, double s) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int r = e / n, c = e % n;
+  M[(size_t)r * pm + c] *= s * colscale[c];
+}
+
+// Initial acceleration of the deformable bodies at rest: zetadot = -R(chi) / m.
+__global__ __launch_bounds__(STRUCT_NT) void k_beam_init(FsiArgs a) {
+  const int tid = threadIdx.x;
+  for (int bi = 0; bi < a.nbodies; ++bi) {
+    const BodyDev& b = a.bodies[bi];
+    if (b.kind != BODY_DEFORMABLE) continue;
+    const int m = b.npts;
+    __shared__ double rint[MAX_BEAM_DOF + 3];
+    for (int e = tid; e < 3 * m; e += STRUCT_NT) rint[e] = 0.0;
+    __syncthreads();
+    for (int parity = 0; parity < 2; ++parity) {
+      for (int el = 2 * tid + parity; el < m - 1; el += 2 * STRUCT_NT) {
+        double fe[6], ke[36];
+        beam_element(a.chi + b.dof0 + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el],
+                     b.ea, b.ei, fe, ke);
+        for (int p = 0; p < 6; ++p) rint[3 * el + p] += fe[p];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < 3 * m; e += STRUCT_NT) {
+      const int g = b.dof0 + e;
+      a.zeta[g] = 0.0;
+      a.zetadot[g] = e < 3 ? 0.0 : -rint[e] / a.dmass[g];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_gather_batch(const int* cols, const double* vals, int ntarget, const int* counts,
+                               int nslots, int* out_col, double* out_val, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_batch, dim3(nslots), dim3(256), 0, st, cols, vals, ntarget, counts,
+                     out_col, out_val);
+  return hipGetLastError();
+}
+hipError_t launch_scale_cols(double* M, int pm, int n, const double* colscale, double s,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_cols, dim3((n * n + 255) / 256), dim3(256), 0, st, M, pm, n, colscale, s);
+  return hipGetLastError();
+}
+hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_beam_init, dim3(1), dim3(STRUCT_NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_body_ops<float>(const FsiArgs&, hipStream_t);
+template hipError_t launch_body_ops<double>(const FsiArgs&, hipStream_t);
+template hipError_t launch_spread<float>(const FsiArgs&, int, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_spread<double>(const FsiArgs&, int, int, int, int, double*, int, hipStream_t);
+
+}  // namespace ib

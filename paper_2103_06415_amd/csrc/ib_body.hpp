@@ -1,0 +1,114 @@
+// Device-side body description and the FSI-loop kernels' interface.
+#pragma once
+
+#include "ib_common.hpp"
+
+namespace ib {
+
+enum { BODY_RIGID = 0, BODY_TORSIONAL = 1, BODY_DEFORMABLE = 2 };
+
+// Per-body data in device memory (double precision throughout).
+struct BodyDev {
+  int kind;
+  int npts;   // m
+  int pt0;    // first point in the solver-wide point list; its rows start at 2 * pt0
+  int app0;   // sub-domain mode: first appended sub-domain point of a rigid body
+  int tors;   // index into the torsional state array
+  int dof0;   // deformable: offset of node 0's DOFs in the DOF arrays (3 per node)
+  int band0;  // deformable: offset of its band matrix / workspace
+  int has_ub; // rigid: prescribed velocity present
+  int64_t yoff; // deformable: offset of its J_d^{-1} T^T workspace
+  double ds;
+  double hx, hy, theta0, inertia, stiffness, damping;  // torsional
+  double mass, ei, ea;                                 // deformable
+};
+
+// Torsional state slots.
+enum { TS_THETA = 0, TS_PHI, TS_PHIDOT, TS_NEW, TS_G, TS_COUNT };
+
+// Everything the FSI kernels need.  Pointers are device pointers.
+struct FsiArgs {
+  const BodyDev* bodies;
+  int nbodies, npts, nf, ntors, ndef;
+  int iter;            // FSI iteration (0 = start from the old structure state)
+  // level 0 geometry
+  int n, ps;
+  double h, x0, y0, ux, uy, dt;
+  const void* sstar;   // predictor streamfunction, float or double per fp64
+  int fp64;
+  // sub-domain
+  int use_sd, sd_i0, sd_j0, sd_npx, sd_npy, sd_ngrid, sd_total;
+  const double* app_xy;     // appended exact points (2 per point)
+  const int64_t* bp_ptr;    // B' CSR (rows = 2 sd_total)
+  const int32_t* bp_col;
+  const double* bp_val;
+  // rigid geometry and prescribed velocities (2 per point, per body at pt0)
+  const double* rigid_xy;
+  const double* rigid_ub;
+  // per-row operator: window base (i0, j0) and 4 x 4 weights; P (4 entries)
+  int* st_base;
+  double* st_w;
+  int* p_idx;
+  double* p_w;
+  double* pos;         // current point positions (2 per point)
+  // FSI vectors and matrix
+  double* ustar;       // (1/h) E (C s* + q_inf)
+  double* rhs;
+  double* f;
+  double* M;
+  int pm;
+  const double* Minv;  // stationary inverse (exact, rigid only) or null
+  // structure
+  double* tors;        // [ntors][TS_COUNT]
+  double* chi;         // deformable DOFs at time n
+  double* zeta;
+  double* zetadot;
+  double* chi_new;     // latest iterate
+  const double* dmass; // lumped mass per DOF
+  const double* l0;    // per element (indexed like DOFs / 3)
+  const double* beta0;
+  double* band;        // band LU factors, 11 per DOF
+  double* dres;        // residual per DOF
+  double* ywork;       // J_d^{-1} T^T, per deformable body: (3m) x (2m)
+  int* flags;          // [0] error code, [1] reserved
+  double* delta;       // [0] max |delta| of the last update
+};
+
+// Rows of the offline stage: body rows (from the operator arrays) or sub-domain points.
+struct OffRows {
+  int kind;  // 0: body rows from st arrays, 1: sub-domain points
+  const int* st_base;
+  const double* st_w;
+  int sd_i0, sd_j0, sd_npx, sd_ngrid, sd_total;
+  const double* app_xy;
+  int n;
+  double h, x0, y0;
+};
+
+template <typename T>
+hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st);
+hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st);
+hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st);
+hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,
+                           hipStream_t st);
+hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st);
+hipError_t launch_update(const FsiArgs& a, hipStream_t st);
+hipError_t launch_finish(const FsiArgs& a, hipStream_t st);
+template <typename T>
+hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,
+                         hipStream_t st);
+hipError_t launch_point_source_rowdst(const OffRows& o, int col0, int ncols, int nslots,
+                                      const void* tw, double* out, int po, size_t bso,
+                                      int* rows_first, hipStream_t st);
+hipError_t launch_sample(const OffRows& o, int ntarget, const double* sl, int ps, size_t bss,
+                         double* vals, int nslots, hipStream_t st);
+hipError_t launch_filter_compact(const double* vals, int ntarget, int col0, int ncols, int nslots,
+                                 double eps, int* out_col, double* out_val, int* counts,
+                                 hipStream_t st);
+hipError_t launch_gather_batch(const int* cols, const double* vals, int ntarget, const int* counts,
+                               int nslots, int* out_col, double* out_val, hipStream_t st);
+hipError_t launch_scale_cols(double* M, int pm, int n, const double* colscale, double s,
+                             hipStream_t st);
+hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
+
+}  // namespace ib

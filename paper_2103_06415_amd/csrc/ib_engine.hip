@@ -1,0 +1,1155 @@
+// Host engine and C-ABI of the immersed-boundary solver (see include/ibfsi.h).
+//
+// A step (Sec. 2.3 and 3.3; Algorithm 2) is enqueued on the solver's stream as:
+//   for every level, coarse to fine:
+//     ring of the level from the coarser level's new streamfunction
+//     explicit right-hand side + row DST       (k_rhs_rowdst)
+//     column DST, spectral solve, inverse      (k_col_solve)
+//     inverse row DST -> new streamfunction   (k_row_idst)   [level 0: only the rows
+//                                                             the bodies need -> s*]
+//   level 0 with bodies: FSI iterations (body operator, Schur matrix, LU, structure
+//   update; the host reads the convergence measure), then the corrector source, its
+//   row DST, the column solve accumulated into level 0's spectral rows, and the final
+//   inverse row DST.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ib_body.hpp"
+#include "ib_internal.hpp"
+#include "ibfsi.h"
+
+using namespace ib;
+
+namespace {
+
+struct HostBody {
+  int kind = BODY_RIGID;
+  int m = 0;
+  double ds = 0;
+  std::vector<double> xy, ub;                       // rigid
+  double hx = 0, hy = 0, length = 0, theta0 = 0, inertia = 0, stiffness = 0, damping = 0;
+  double theta = 0, phi = 0;                        // torsional
+  std::vector<double> xy_ref, xy0, rot0;            // deformable
+  double mass = 0, ei = 0, ea = 0;
+};
+
+struct LevelState {
+  double h = 0, alpha = 0;
+  void* s = nullptr;
+  void* hist = nullptr;
+  void* sring = nullptr;
+  void* gring[2] = {nullptr, nullptr};
+  int gcur = 0;
+};
+
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct ib_solver {
+  ib_config cfg{};
+  ib_allocator alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+  int n = 0, pitch = 0;
+  bool fp64 = true;
+  size_t es = 8;
+  std::vector<LevelState> lv;
+  void* work = nullptr;
+  void* work2 = nullptr;
+  void* sstar = nullptr;
+  void* tw = nullptr;
+  void* lam = nullptr;
+  void* tw64 = nullptr;
+  void* lam64 = nullptr;
+  std::vector<std::vector<double>> omega0;
+  std::vector<HostBody> bodies;
+  bool has_sd = false;
+  double sd[4] = {0, 0, 0, 0};
+  bool prepared = false, failed = false, first = true;
+  int64_t step = 0;
+  int iters_last = 0, iters_max = 0;
+  double delta_last = 0;
+  double prepare_seconds = 0;
+  std::vector<std::pair<void*, size_t>> allocs;
+  std::string last_error;
+
+  // ---- bodies on the device
+  int npts = 0, nf = 0, ntors = 0, ndef = 0, ndof = 0, nel_total = 0;
+  bool use_sd = false, stationary = false;
+  int sd_i0 = 0, sd_i1 = 0, sd_j0 = 0, sd_j1 = 0, sd_npx = 0, sd_npy = 0, sd_ngrid = 0,
+      sd_total = 0;
+  int64_t bp_nnz = 0;
+  int blo = 1, bhi = 1, bilo = 1, bihi = 1;  // rows / columns the bodies can touch
+  FsiArgs fa{};
+  double* f = nullptr;
+  double* rhs = nullptr;
+  double* Minv = nullptr;
+  int* flags = nullptr;
+  double* delta = nullptr;
+  int* hflags = nullptr;  // pinned mirrors
+  double* hdelta = nullptr;
+  std::vector<double> ds_rows;
+};
+
+namespace {
+
+ib_status hip_fail(ib_solver* s, hipError_t e, const char* what) {
+  if (s) s->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return IB_ERR_HIP;
+}
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(s, e_, #expr); \
+  } while (0)
+
+void* dalloc(ib_solver* s, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  if (s->has_alloc) {
+    p = s->alloc.alloc(bytes, s->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) s->allocs.push_back({p, bytes});
+  return p;
+}
+
+void dfree(ib_solver* s, void* p) {
+  if (!p) return;
+  for (size_t k = 0; k < s->allocs.size(); ++k)
+    if (s->allocs[k].first == p) {
+      s->allocs.erase(s->allocs.begin() + k);
+      break;
+    }
+  if (s->has_alloc) s->alloc.free(p, s->alloc.ctx);
+  else (void)hipFree(p);
+}
+
+// Twiddles exp(-i pi m / n), m < 2n, and 1-D eigenvalues 4 sin^2(pi k / 2n), k < n.
+template <typename T>
+ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
+  std::vector<T> t(4 * n), l(n);
+  for (int m = 0; m < 2 * n; ++m) {
+    const long double a = 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+    t[2 * m] = (T)std::cos((double)a);
+    t[2 * m + 1] = (T)-std::sin((double)a);
+  }
+  for (int k = 1; k < n; ++k) {
+    const double v = std::sin(M_PI * k / (2.0 * n));
+    l[k - 1] = (T)(4.0 * v * v);
+  }
+  *tw = dalloc(s, t.size() * sizeof(T));
+  *lam = dalloc(s, l.size() * sizeof(T));
+  if (!*tw || !*lam) return IB_ERR_OOM;
+  HIPCHK(hipMemcpy(*tw, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(*lam, l.data(), l.size() * sizeof(T), hipMemcpyHostToDevice));
+  return IB_OK;
+}
+
+// ------------------------------------------------------------- flow helpers
+
+template <typename T>
+ib_status solve_into(ib_solver* s, void* work, double alpha, double scale, int r0, int r1,
+                     const void* tw, const void* lam) {
+  ColArgs<T> c{};
+  c.in = static_cast<T*>(work);
+  c.out = static_cast<T*>(work);
+  c.pi = c.po = s->pitch;
+  c.r0 = r0;
+  c.r1 = r1;
+  c.alpha = (T)alpha;
+  c.scale = (T)scale;
+  c.w0 = 1;
+  c.w1 = s->n - 1;
+  HIPCHK(launch_col_solve<T>(c, s->n, 1, tw, lam, s->stream));
+  return IB_OK;
+}
+
+// Initial streamfunction of every level from its vorticity, coarse to fine.
+template <typename T>
+ib_status init_streamfunction(ib_solver* s) {
+  const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
+  std::vector<T> host((size_t)(n - 1) * P, T(0));
+  for (int g = G - 1; g >= 0; --g) {
+    LevelState& L = s->lv[g];
+    if (g < G - 1) {
+      HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
+                            static_cast<T*>(L.gring[L.gcur]), s->stream));
+    }
+    std::fill(host.begin(), host.end(), T(0));
+    if (g < (int)s->omega0.size() && !s->omega0[g].empty()) {
+      const double h2 = L.h * L.h;
+      for (int j = 0; j < n - 1; ++j)
+        for (int i = 0; i < n - 1; ++i)
+          host[(size_t)j * P + i] = (T)(h2 * s->omega0[g][(size_t)j * (n - 1) + i]);
+    }
+    HIPCHK(hipMemcpyAsync(s->work, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice,
+                          s->stream));
+    if (g < G - 1)
+      HIPCHK(launch_add_ring_lift<T>(static_cast<T*>(s->work), P, static_cast<T*>(L.sring), n,
+                                     s->stream));
+    RowArgs<T> r{};
+    r.in = static_cast<T*>(s->work);
+    r.out = static_cast<T*>(s->work);
+    r.pi = r.po = P;
+    r.r0 = 1;
+    r.r1 = n - 1;
+    HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
+    ib_status st = solve_into<T>(s, s->work, 0.0, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam);
+    if (st) return st;
+    RowArgs<T> q = r;
+    q.out = static_cast<T*>(L.s);
+    HIPCHK(launch_row_idst<T>(q, n, 1, s->tw, g < G - 1 ? static_cast<T*>(L.sring) : nullptr, 1,
+                              s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));  // host buffer is reused
+  }
+  return IB_OK;
+}
+
+// ---------------------------------------------------------------- offline
+
+// Batched columns of E C K C^T E^T (K = [L (I + alpha L)]^{-1}) for the rows of
+// `src` sampled at the rows of `dst`: vals[b * ntarget + t] for b < nslots.
+struct Offline {
+  int nslots = 0;
+  double* srcrows = nullptr;  // [nslots][6][pitch]
+  int* rfirst = nullptr;
+  double* X = nullptr;        // [nslots][(n-1) pitch]
+  double* S = nullptr;        // [nslots][(n+1) pitch]
+  double* vals = nullptr;     // [nslots][ntarget]
+};
+
+ib_status offline_columns(ib_solver* s, Offline& w, const OffRows& src, int col0, int ncols,
+                          const OffRows& dst, int ntarget, int tlo, int thi) {
+  const int n = s->n, P = s->pitch;
+  const int ns = std::min(w.nslots, ncols - col0);
+  const double alpha = s->lv[0].alpha;
+  HIPCHK(launch_point_source_rowdst(src, col0, ncols, ns, s->tw64, w.srcrows, P, (size_t)6 * P,
+                                    w.rfirst, s->stream));
+  ColArgs<double> c{};
+  c.in = w.srcrows;
+  c.out = w.X;
+  c.pi = c.po = P;
+  c.r0 = 1;
+  c.r1 = n - 1;
+  c.alpha = alpha;
+  c.scale = 4.0 / ((double)n * n);
+  c.bsi = (size_t)6 * P;
+  c.bso = (size_t)(n - 1) * P;
+  c.rfirst = w.rfirst;
+  c.rcount = 6;
+  c.w0 = tlo;
+  c.w1 = thi;
+  HIPCHK(launch_col_solve<double>(c, n, ns, s->tw64, s->lam64, s->stream));
+  RowArgs<double> r{};
+  r.in = w.X;
+  r.out = w.S;
+  r.pi = r.po = P;
+  r.r0 = tlo;
+  r.r1 = thi;
+  r.bsi = (size_t)(n - 1) * P;
+  r.bso = (size_t)(n + 1) * P;
+  HIPCHK(launch_row_idst<double>(r, n, ns, s->tw64, nullptr, 0, s->stream));
+  HIPCHK(launch_sample(dst, ntarget, w.S, P, (size_t)(n + 1) * P, w.vals, ns, s->stream));
+  return IB_OK;
+}
+
+ib_status offline_alloc(ib_solver* s, Offline& w, int nslots, int ntarget) {
+  const int n = s->n, P = s->pitch;
+  w.nslots = nslots;
+  w.srcrows = static_cast<double*>(dalloc(s, (size_t)nslots * 6 * P * 8));
+  w.rfirst = static_cast<int*>(dalloc(s, (size_t)nslots * 4));
+  w.X = static_cast<double*>(dalloc(s, (size_t)nslots * (n - 1) * P * 8));
+  w.S = static_cast<double*>(dalloc(s, (size_t)nslots * (n + 1) * P * 8));
+  w.vals = static_cast<double*>(dalloc(s, (size_t)nslots * ntarget * 8));
+  if (!w.srcrows || !w.rfirst || !w.X || !w.S || !w.vals) return IB_ERR_OOM;
+  HIPCHK(hipMemsetAsync(w.S, 0, (size_t)nslots * (n + 1) * P * 8, s->stream));
+  return IB_OK;
+}
+
+void offline_free(ib_solver* s, Offline& w) {
+  dfree(s, w.srcrows);
+  dfree(s, w.rfirst);
+  dfree(s, w.X);
+  dfree(s, w.S);
+  dfree(s, w.vals);
+  w = Offline{};
+}
+
+int offline_slots(ib_solver* s, int ntarget) {
+  // keep the batch buffers near 1 GiB
+  const size_t per = (size_t)(2 * s->n + 6) * s->pitch * 8 + (size_t)ntarget * 8;
+  size_t k = ((size_t)1 << 30) / per;
+  if (k > 256) k = 256;
+  if (k < 1) k = 1;
+  return (int)k;
+}
+
+template <typename T>
+ib_status run_body_ops(ib_solver* s) {
+  HIPCHK(launch_body_ops<T>(s->fa, s->stream));
+  return IB_OK;
+}
+
+ib_status map_flags(ib_solver* s, int code) {
+  if (code == 1) {
+    s->last_error = "a body point left the sub-domain";
+    return IB_ERR_OUT_OF_SUBDOMAIN;
+  }
+  if (code == 2) {
+    s->last_error = "delta support reaches the level-0 boundary";
+    return IB_ERR_NEAR_BOUNDARY;
+  }
+  if (code == 3) {
+    s->last_error = "singular or non-finite Schur matrix";
+    return IB_ERR_NONFINITE;
+  }
+  return IB_OK;
+}
+
+// Device body data, the stationary Schur inverse or B' (Algorithm 1).
+template <typename T>
+ib_status prepare_bodies(ib_solver* s) {
+  const int n = s->n;
+  LevelState& L0 = s->lv[0];
+  const double h = L0.h;
+  const double x0 = s->cfg.cx - 0.5 * n * h, y0 = s->cfg.cy - 0.5 * n * h;
+  // ---- host-side layout
+  std::vector<BodyDev> bd;
+  std::vector<double> rigid_xy, rigid_ub, tors, chi, dmass, l0v, beta0v, appxy;
+  int pt = 0, app = 0, ntors = 0, dof = 0, band0 = 0;
+  int64_t yoff = 0;
+  bool any_moving = false;
+  s->ds_rows.clear();
+  for (auto& hb : s->bodies) {
+    BodyDev b{};
+    b.kind = hb.kind;
+    b.npts = hb.m;
+    b.pt0 = pt;
+    b.ds = hb.ds;
+    for (int k = 0; k < 2 * hb.m; ++k) s->ds_rows.push_back(hb.ds);
+    // rigid geometry array is indexed by global point
+    rigid_xy.resize(2 * (pt + hb.m), 0.0);
+    rigid_ub.resize(2 * (pt + hb.m), 0.0);
+    if (hb.kind == BODY_RIGID) {
+      for (int k = 0; k < 2 * hb.m; ++k) rigid_xy[2 * pt + k] = hb.xy[k];
+      if (!hb.ub.empty()) {
+        b.has_ub = 1;
+        for (int k = 0; k < 2 * hb.m; ++k) rigid_ub[2 * pt + k] = hb.ub[k];
+      }
+      b.app0 = app;
+      for (int k = 0; k < 2 * hb.m; ++k) appxy.push_back(hb.xy[k]);
+      app += hb.m;
+    } else if (hb.kind == BODY_TORSIONAL) {
+      any_moving = true;
+      b.tors = ntors++;
+      b.hx = hb.hx;
+      b.hy = hb.hy;
+      b.theta0 = hb.theta0;
+      b.inertia = hb.inertia;
+      b.stiffness = hb.stiffness;
+      b.damping = hb.damping;
+      const double g = 0.0;
+      const double phidot = (g - hb.damping * hb.phi - hb.stiffness * hb.theta) / hb.inertia;
+      const double st[TS_COUNT] = {hb.theta, hb.phi, phidot, hb.theta, g};
+      tors.insert(tors.end(), st, st + TS_COUNT);
+    } else {
+      any_moving = true;
+      b.dof0 = dof;
+      b.band0 = band0;
+      b.yoff = yoff;
+      yoff += (int64_t)3 * hb.m * (2 * hb.m + 1);
+      b.mass = hb.mass;
+      b.ei = hb.ei;
+      b.ea = hb.ea;
+      const int m = hb.m;
+      chi.resize(dof + 3 * m, 0.0);
+      dmass.resize(dof + 3 * m, 0.0);
+      l0v.resize(dof / 3 + m, 0.0);
+      beta0v.resize(dof / 3 + m, 0.0);
+      for (int k = 0; k < m; ++k) {
+        chi[dof + 3 * k] = hb.xy0[2 * k];
+        chi[dof + 3 * k + 1] = hb.xy0[2 * k + 1];
+        chi[dof + 3 * k + 2] = hb.rot0[k];
+      }
+      for (int e = 0; e < m - 1; ++e) {
+        const double dx = hb.xy_ref[2 * e + 2] - hb.xy_ref[2 * e];
+        const double dy = hb.xy_ref[2 * e + 3] - hb.xy_ref[2 * e + 1];
+        const double le = std::sqrt(dx * dx + dy * dy);
+        l0v[dof / 3 + e] = le;
+        beta0v[dof / 3 + e] = std::atan2(dy, dx);
+        const double me = hb.mass * le;
+        for (int node = e; node <= e + 1; ++node) {
+          dmass[dof + 3 * node] += 0.5 * me;
+          dmass[dof + 3 * node + 1] += 0.5 * me;
+          dmass[dof + 3 * node + 2] += me * le * le / 105.0;
+        }
+      }
+      dof += 3 * m;
+      band0 += 3 * m;
+    }
+    bd.push_back(b);
+    pt += hb.m;
+  }
+  s->npts = pt;
+  s->nf = 2 * pt;
+  s->ntors = ntors;
+  s->ndof = dof;
+  // ---- mode
+  int mode = s->cfg.schur_mode;
+  if (mode == IB_SCHUR_AUTO) mode = s->has_sd ? IB_SCHUR_SUBDOMAIN : IB_SCHUR_EXACT;
+  s->use_sd = mode == IB_SCHUR_SUBDOMAIN;
+  if (s->use_sd && !s->has_sd) {
+    s->last_error = "sub-domain mode needs ib_set_subdomain";
+    return IB_ERR_STATE;
+  }
+  s->stationary = !s->use_sd && !any_moving;
+  if (!s->use_sd && any_moving) {
+    s->last_error = "moving bodies need the sub-domain operator (set a sub-domain)";
+    return IB_ERR_ARG;
+  }
+  for (auto& hb : s->bodies)
+    if (hb.kind == BODY_DEFORMABLE && 3 * hb.m - 3 > 600) {
+      s->last_error = "deformable body with more than 201 nodes";
+      return IB_ERR_ARG;
+    }
+  // ---- sub-domain geometry (snapped outwards to vertices)
+  if (s->use_sd) {
+    const double tol = 1e-9;
+    s->sd_i0 = (int)std::floor((s->sd[0] - x0) / h + tol);
+    s->sd_i1 = (int)std::ceil((s->sd[1] - x0) / h - tol);
+    s->sd_j0 = (int)std::floor((s->sd[2] - y0) / h + tol);
+    s->sd_j1 = (int)std::ceil((s->sd[3] - y0) / h - tol);
+    if (s->sd_i0 < 2 || s->sd_j0 < 2 || s->sd_i1 > n - 2 || s->sd_j1 > n - 2) {
+      s->last_error = "sub-domain reaches the level-0 boundary";
+      return IB_ERR_NEAR_BOUNDARY;
+    }
+    s->sd_npx = s->sd_i1 - s->sd_i0 + 1;
+    s->sd_npy = s->sd_j1 - s->sd_j0 + 1;
+    s->sd_ngrid = s->sd_npx * s->sd_npy;
+    s->sd_total = s->sd_ngrid + app;
+  }
+  // rows and columns the body operators and the spread can touch
+  {
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    auto acc = [&](double x, double y) {
+      xmin = std::min(xmin, x); xmax = std::max(xmax, x);
+      ymin = std::min(ymin, y); ymax = std::max(ymax, y);
+    };
+    for (int k = 0; k < (int)rigid_xy.size() / 2; ++k)
+      if (rigid_xy[2 * k] != 0.0 || rigid_xy[2 * k + 1] != 0.0) acc(rigid_xy[2 * k], rigid_xy[2 * k + 1]);
+    for (auto& hb : s->bodies) if (hb.kind == BODY_RIGID) for (int k = 0; k < hb.m; ++k) acc(hb.xy[2 * k], hb.xy[2 * k + 1]);
+    if (s->use_sd) {
+      acc(x0 + s->sd_i0 * h, y0 + s->sd_j0 * h);
+      acc(x0 + s->sd_i1 * h, y0 + s->sd_j1 * h);
+    }
+    if (xmin > xmax) { xmin = xmax = s->cfg.cx; ymin = ymax = s->cfg.cy; }
+    s->bilo = std::max(1, (int)std::floor((xmin - x0) / h) - 4);
+    s->bihi = std::min(n - 1, (int)std::ceil((xmax - x0) / h) + 4);
+    s->blo = std::max(1, (int)std::floor((ymin - y0) / h) - 4);
+    s->bhi = std::min(n - 1, (int)std::ceil((ymax - y0) / h) + 4);
+  }
+  // ---- device arrays
+  auto up = [&](const std::vector<double>& v) -> double* {
+    double* p = static_cast<double*>(dalloc(s, std::max<size_t>(1, v.size()) * 8));
+    if (p && !v.empty()) (void)hipMemcpy(p, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    return p;
+  };
+  FsiArgs& a = s->fa;
+  a = FsiArgs{};
+  BodyDev* dbodies = static_cast<BodyDev*>(dalloc(s, bd.size() * sizeof(BodyDev)));
+  HIPCHK(hipMemcpy(dbodies, bd.data(), bd.size() * sizeof(BodyDev), hipMemcpyHostToDevice));
+  a.bodies = dbodies;
+  a.nbodies = (int)bd.size();
+  a.npts = s->npts;
+  a.nf = s->nf;
+  a.ntors = ntors;
+  a.n = n;
+  a.ps = s->pitch;
+  a.h = h;
+  a.x0 = x0;
+  a.y0 = y0;
+  a.ux = s->cfg.u_inf[0] * h;
+  a.uy = s->cfg.u_inf[1] * h;
+  a.dt = s->cfg.dt;
+  a.sstar = s->sstar;
+  a.fp64 = s->fp64;
+  a.use_sd = s->use_sd;
+  a.sd_i0 = s->sd_i0;
+  a.sd_j0 = s->sd_j0;
+  a.sd_npx = s->sd_npx;
+  a.sd_npy = s->sd_npy;
+  a.sd_ngrid = s->sd_ngrid;
+  a.sd_total = s->sd_total;
+  a.app_xy = up(appxy);
+  a.rigid_xy = up(rigid_xy);
+  a.rigid_ub = up(rigid_ub);
+  const int nf = s->nf;
+  a.st_base = static_cast<int*>(dalloc(s, (size_t)nf * 3 * 4));
+  a.st_w = static_cast<double*>(dalloc(s, (size_t)nf * 16 * 8));
+  a.p_idx = static_cast<int*>(dalloc(s, (size_t)nf * 4 * 4));
+  a.p_w = static_cast<double*>(dalloc(s, (size_t)nf * 4 * 8));
+  a.pos = static_cast<double*>(dalloc(s, (size_t)s->npts * 2 * 8));
+  a.ustar = static_cast<double*>(dalloc(s, (size_t)nf * 8));
+  s->f = static_cast<double*>(dalloc(s, (size_t)nf * 8));
+  s->rhs = static_cast<double*>(dalloc(s, (size_t)nf * 8));
+  a.f = s->f;
+  a.rhs = s->stationary ? s->rhs : s->f;
+  a.pm = round_up(nf, 8);
+  a.M = static_cast<double*>(dalloc(s, (size_t)nf * a.pm * 8 + 8));
+  a.tors = up(tors);
+  a.chi = up(chi);
+  a.zeta = up(std::vector<double>(chi.size(), 0.0));
+  a.zetadot = up(std::vector<double>(chi.size(), 0.0));
+  a.chi_new = up(chi);
+  a.dmass = up(dmass);
+  a.l0 = up(l0v);
+  a.beta0 = up(beta0v);
+  a.band = static_cast<double*>(dalloc(s, std::max<size_t>(1, (size_t)band0 * 11) * 8));
+  a.dres = up(std::vector<double>(chi.size(), 0.0));
+  size_t yw = 0;
+  for (auto& hb : s->bodies) if (hb.kind == BODY_DEFORMABLE) yw += (size_t)3 * hb.m * (2 * hb.m + 1);
+  a.ywork = static_cast<double*>(dalloc(s, std::max<size_t>(1, yw) * 8));
+  s->flags = static_cast<int*>(dalloc(s, 16));
+  s->delta = static_cast<double*>(dalloc(s, 16));
+  a.flags = s->flags;
+  a.delta = s->delta;
+  if (!a.st_base || !a.st_w || !a.M || !s->f || !s->flags) return IB_ERR_OOM;
+  HIPCHK(hipMemset(s->flags, 0, 16));
+  if (!s->hflags) {
+    HIPCHK(hipHostMalloc((void**)&s->hflags, 16, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&s->hdelta, 16, hipHostMallocDefault));
+  }
+  if (dof > 0) HIPCHK(launch_beam_init(a, s->stream));
+  // operator at the initial configuration
+  a.iter = 0;
+  ib_status st = run_body_ops<T>(s);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
+  if ((st = map_flags(s, s->hflags[0]))) return st;
+  double* dsr = up(s->ds_rows);
+  // ---- offline operator
+  OffRows geo{};
+  geo.n = n;
+  geo.h = h;
+  geo.x0 = x0;
+  geo.y0 = y0;
+  if (s->stationary) {
+    OffRows rows = geo;
+    rows.kind = 0;
+    rows.st_base = a.st_base;
+    rows.st_w = a.st_w;
+    Offline w;
+    const int slots = std::min(offline_slots(s, nf), nf);
+    if ((st = offline_alloc(s, w, slots, nf))) return st;
+    double* G = a.M;  // G then M in place
+    const int tlo = std::max(1, s->blo), thi = std::min(n - 1, s->bhi);
+    std::vector<double> hv((size_t)slots * nf);
+    std::vector<double> gm((size_t)nf * a.pm, 0.0);
+    for (int c0 = 0; c0 < nf; c0 += slots) {
+      if ((st = offline_columns(s, w, rows, c0, nf, rows, nf, tlo, thi))) return st;
+      const int ns = std::min(slots, nf - c0);
+      HIPCHK(hipMemcpyAsync(hv.data(), w.vals, (size_t)ns * nf * 8, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+      for (int b = 0; b < ns; ++b)
+        for (int t = 0; t < nf; ++t) gm[(size_t)t * a.pm + c0 + b] = hv[(size_t)b * nf + t];
+    }
+    offline_free(s, w);
+    HIPCHK(hipMemcpy(G, gm.data(), gm.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(launch_scale_cols(G, a.pm, nf, dsr, s->cfg.dt / (h * h), s->stream));
+    // inverse: solve M X = I
+    s->Minv = static_cast<double*>(dalloc(s, (size_t)nf * a.pm * 8 + 8));
+    std::vector<double> eye((size_t)nf * a.pm, 0.0);
+    for (int k = 0; k < nf; ++k) eye[(size_t)k * a.pm + k] = 1.0;
+    HIPCHK(hipMemcpy(s->Minv, eye.data(), eye.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(launch_lu_solve(G, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
+    if ((st = map_flags(s, s->hflags[0]))) return st;
+    a.Minv = s->Minv;
+  } else if (s->use_sd) {
+    OffRows rows = geo;
+    rows.kind = 1;
+    rows.sd_i0 = s->sd_i0;
+    rows.sd_j0 = s->sd_j0;
+    rows.sd_npx = s->sd_npx;
+    rows.sd_ngrid = s->sd_ngrid;
+    rows.sd_total = s->sd_total;
+    rows.app_xy = a.app_xy;
+    const int nsd = 2 * s->sd_total;
+    // target rows: the sub-domain vertices' windows and the appended points' windows
+    int tlo = s->sd_j0 - 2, thi = s->sd_j1 + 3;
+    for (size_t k = 0; k < appxy.size() / 2; ++k) {
+      const int jj = (int)std::floor((appxy[2 * k + 1] - y0) / h);
+      tlo = std::min(tlo, jj - 3);
+      thi = std::max(thi, jj + 4);
+    }
+    tlo = std::max(1, tlo);
+    thi = std::min(n - 1, thi);
+    Offline w;
+    const int slots = std::min(offline_slots(s, nsd), nsd);
+    if ((st = offline_alloc(s, w, slots, nsd))) return st;
+    int* ccol = static_cast<int*>(dalloc(s, (size_t)slots * nsd * 4));
+    double* cval = static_cast<double*>(dalloc(s, (size_t)slots * nsd * 8));
+    int* counts = static_cast<int*>(dalloc(s, (size_t)slots * 4));
+    int* gcol = static_cast<int*>(dalloc(s, (size_t)slots * nsd * 4));
+    double* gval = static_cast<double*>(dalloc(s, (size_t)slots * nsd * 8));
+    if (!ccol || !cval || !counts || !gcol || !gval) return IB_ERR_OOM;
+    std::vector<int64_t> rowptr(1, 0);
+    std::vector<int32_t> hcol;
+    std::vector<double> hval;
+    std::vector<int> hcounts(slots);
+    for (int c0 = 0; c0 < nsd; c0 += slots) {
+      if ((st = offline_columns(s, w, rows, c0, nsd, rows, nsd, tlo, thi))) return st;
+      const int ns = std::min(slots, nsd - c0);
+      HIPCHK(launch_filter_compact(w.vals, nsd, c0, nsd, ns, s->cfg.drop_tol, ccol, cval, counts,
+                                   s->stream));
+      HIPCHK(launch_gather_batch(ccol, cval, nsd, counts, ns, gcol, gval, s->stream));
+      HIPCHK(hipMemcpyAsync(hcounts.data(), counts, (size_t)ns * 4, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+      int64_t tot = 0;
+      for (int b = 0; b < ns; ++b) tot += hcounts[b];
+      const size_t old = hcol.size();
+      hcol.resize(old + tot);
+      hval.resize(old + tot);
+      HIPCHK(hipMemcpy(hcol.data() + old, gcol, (size_t)tot * 4, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(hval.data() + old, gval, (size_t)tot * 8, hipMemcpyDeviceToHost));
+      for (int b = 0; b < ns; ++b) rowptr.push_back(rowptr.back() + hcounts[b]);
+    }
+    dfree(s, ccol);
+    dfree(s, cval);
+    dfree(s, counts);
+    dfree(s, gcol);
+    dfree(s, gval);
+    offline_free(s, w);
+    s->bp_nnz = (int64_t)hcol.size();
+    int64_t* dptr = static_cast<int64_t*>(dalloc(s, rowptr.size() * 8));
+    int32_t* dcol = static_cast<int32_t*>(dalloc(s, std::max<size_t>(1, hcol.size()) * 4));
+    double* dval = static_cast<double*>(dalloc(s, std::max<size_t>(1, hval.size()) * 8));
+    if (!dptr || !dcol || !dval) return IB_ERR_OOM;
+    HIPCHK(hipMemcpy(dptr, rowptr.data(), rowptr.size() * 8, hipMemcpyHostToDevice));
+    if (!hcol.empty()) {
+      HIPCHK(hipMemcpy(dcol, hcol.data(), hcol.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dval, hval.data(), hval.size() * 8, hipMemcpyHostToDevice));
+    }
+    a.bp_ptr = dptr;
+    a.bp_col = dcol;
+    a.bp_val = dval;
+  }
+  return IB_OK;
+}
+
+template <typename T>
+ib_status do_prepare(ib_solver* s) {
+  auto t0 = std::chrono::steady_clock::now();
+  ib_status st = init_streamfunction<T>(s);
+  if (st) return st;
+  if (!s->bodies.empty()) {
+    st = prepare_bodies<T>(s);
+    if (st) return st;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->prepare_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return IB_OK;
+}
+
+// --------------------------------------------------------------------- step
+
+template <typename T>
+ib_status fsi_and_correct(ib_solver* s) {
+  const int n = s->n, P = s->pitch;
+  LevelState& L0 = s->lv[0];
+  FsiArgs& a = s->fa;
+  HIPCHK(hipMemsetAsync(s->flags, 0, 8, s->stream));
+  int it = 0;
+  const int fixed = s->cfg.newton_fixed_iter;
+  const int kmax = s->cfg.newton_max_iter > 0 ? s->cfg.newton_max_iter : 20;
+  for (;;) {
+    a.iter = it;
+    HIPCHK(launch_body_ops<T>(a, s->stream));
+    if (s->stationary) {
+      HIPCHK(launch_structure(a, 0, s->stream));
+      HIPCHK(launch_matvec(s->Minv, a.pm, s->rhs, s->f, s->nf, s->stream));
+      s->iters_last = 1;
+      s->delta_last = 0.0;
+      break;
+    }
+    HIPCHK(launch_schur_sd(a, s->stream));
+    HIPCHK(launch_structure(a, 1, s->stream));
+    HIPCHK(launch_lu_solve(a.M, a.pm, s->f, 1, s->nf, 1, s->flags, s->stream));
+    HIPCHK(launch_update(a, s->stream));
+    bool done = false;
+    if (fixed > 0) {
+      done = it + 1 >= fixed;
+      if (done) {
+        HIPCHK(hipMemcpyAsync(s->hflags, s->flags, 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(s->hdelta, s->delta, 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+      }
+    } else {
+      HIPCHK(hipMemcpyAsync(s->hflags, s->flags, 8, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipMemcpyAsync(s->hdelta, s->delta, 8, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+      ib_status st = map_flags(s, s->hflags[0]);
+      if (st) return st;
+      if (!std::isfinite(s->hdelta[0])) {
+        s->last_error = "non-finite structure update";
+        return IB_ERR_NONFINITE;
+      }
+      done = s->hdelta[0] <= s->cfg.newton_tol;
+      if (!done && it + 1 >= kmax) {
+        s->iters_last = it + 1;
+        s->delta_last = s->hdelta[0];
+        s->last_error = "FSI iteration did not converge";
+        return IB_ERR_NOT_CONVERGED;
+      }
+    }
+    if (done) {
+      ib_status st = map_flags(s, s->hflags[0]);
+      if (st) return st;
+      s->iters_last = it + 1;
+      s->delta_last = s->hdelta[0];
+      HIPCHK(launch_finish(a, s->stream));
+      break;
+    }
+    ++it;
+  }
+  s->iters_max = std::max(s->iters_max, s->iters_last);
+  // corrector: s_{n+1} = s* - dt K C^T E^T (ds/h) f on level 0
+  HIPCHK(launch_spread<T>(a, s->blo, s->bhi, s->bilo, s->bihi, static_cast<T*>(s->work2), P,
+                          s->stream));
+  RowArgs<T> r{};
+  r.in = static_cast<T*>(s->work2);
+  r.out = static_cast<T*>(s->work2);
+  r.pi = r.po = P;
+  r.r0 = s->blo;
+  r.r1 = s->bhi;
+  HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
+  ColArgs<T> c{};
+  c.in = static_cast<T*>(s->work2);
+  c.out = static_cast<T*>(s->work);
+  c.pi = c.po = P;
+  c.r0 = s->blo;
+  c.r1 = s->bhi;
+  c.alpha = (T)L0.alpha;
+  c.scale = (T)(-s->cfg.dt * 4.0 / ((double)n * n));
+  c.accumulate = 1;
+  c.w0 = 1;
+  c.w1 = n - 1;
+  HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
+  return IB_OK;
+}
+
+template <typename T>
+ib_status do_step(ib_solver* s) {
+  const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
+  const bool bodies = !s->bodies.empty();
+  for (int g = G - 1; g >= 0; --g) {
+    LevelState& L = s->lv[g];
+    const bool has_ring = g < G - 1;
+    const int nxt = 1 - L.gcur;
+    if (has_ring)
+      HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
+                            static_cast<T*>(L.gring[nxt]), s->stream));
+    RhsArgs<T> a{};
+    a.s = static_cast<T*>(L.s);
+    a.sf = g > 0 ? static_cast<T*>(s->lv[g - 1].s) : nullptr;
+    a.gring = static_cast<T*>(L.gring[L.gcur]);
+    a.sring_new = has_ring ? static_cast<T*>(L.sring) : nullptr;
+    a.gring_new = has_ring ? static_cast<T*>(L.gring[nxt]) : nullptr;
+    a.hist_in = s->first ? nullptr : static_cast<T*>(L.hist);
+    a.hist_out = static_cast<T*>(L.hist);
+    a.out = static_cast<T*>(s->work);
+    a.n = n;
+    a.ps = a.psf = a.ph = a.po = P;
+    a.alpha = (T)L.alpha;
+    a.dt = (T)s->cfg.dt;
+    a.ux = (T)(s->cfg.u_inf[0] * L.h);
+    a.uy = (T)(s->cfg.u_inf[1] * L.h);
+    a.cn = (T)(-1.0 / (2.0 * L.h * L.h));
+    HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
+    ib_status st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam);
+    if (st) return st;
+    RowArgs<T> r{};
+    r.in = static_cast<T*>(s->work);
+    r.pi = r.po = P;
+    const T* ring = has_ring ? static_cast<T*>(L.sring) : nullptr;
+    if (g == 0 && bodies) {
+      // s* on the rows the body operators can reach
+      r.out = static_cast<T*>(s->sstar);
+      r.r0 = std::max(1, s->blo - 3);
+      r.r1 = std::min(n - 1, s->bhi + 3);
+      HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 0, s->stream));
+      st = fsi_and_correct<T>(s);
+      if (st) return st;
+    }
+    r.out = static_cast<T*>(L.s);
+    r.r0 = 1;
+    r.r1 = n - 1;
+    HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
+    if (has_ring) L.gcur = nxt;
+  }
+  s->first = false;
+  s->step++;
+  return IB_OK;
+}
+
+ib_status check(ib_solver* s) {
+  if (!s) return IB_ERR_ARG;
+  return IB_OK;
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+
+extern "C" {
+
+const char* ib_status_str(ib_status st) {
+  switch (st) {
+    case IB_OK: return "ok";
+    case IB_ERR_ARG: return "invalid argument";
+    case IB_ERR_STATE: return "invalid call order or failed solver";
+    case IB_ERR_OOM: return "out of device memory";
+    case IB_ERR_HIP: return "HIP runtime error";
+    case IB_ERR_NOT_CONVERGED: return "FSI iteration did not converge";
+    case IB_ERR_OUT_OF_SUBDOMAIN: return "body left the sub-domain";
+    case IB_ERR_NEAR_BOUNDARY: return "delta support reaches the finest level's boundary";
+    case IB_ERR_NONFINITE: return "non-finite value";
+    case IB_ERR_CAPACITY: return "output buffer too small";
+    default: return "unknown status";
+  }
+}
+
+ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_stream,
+                    ib_solver** out) {
+  if (!cfg || !out) return IB_ERR_ARG;
+  *out = nullptr;
+  if (!supported_n(cfg->n) || cfg->n % 4 != 0 || cfg->levels < 1 || cfg->levels > 12 ||
+      !(cfg->h > 0) || !(cfg->dt > 0) || !(cfg->re > 0) ||
+      (cfg->precision != IB_FP64 && cfg->precision != IB_FP32_FLOW) || cfg->schur_mode < 0 ||
+      cfg->schur_mode > 2)
+    return IB_ERR_ARG;
+  ib_solver* s = new ib_solver();
+  s->cfg = *cfg;
+  if (s->cfg.newton_tol <= 0) s->cfg.newton_tol = 1e-7;
+  if (s->cfg.newton_max_iter <= 0) s->cfg.newton_max_iter = 20;
+  if (s->cfg.drop_tol < 0) s->cfg.drop_tol = 0.007;
+  if (alloc && alloc->alloc && alloc->free) {
+    s->alloc = *alloc;
+    s->has_alloc = true;
+  }
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->n = cfg->n;
+  s->fp64 = cfg->precision == IB_FP64;
+  s->es = s->fp64 ? 8 : 4;
+  s->pitch = round_up(s->n + 1, 64);
+  const size_t full = (size_t)(s->n + 1) * s->pitch * s->es;
+  const size_t inner = (size_t)(s->n - 1) * s->pitch * s->es;
+  const size_t ring = (size_t)4 * (s->n + 1) * s->es;
+  ib_status st = IB_OK;
+  for (int g = 0; g < cfg->levels; ++g) {
+    LevelState L;
+    L.h = cfg->h * std::ldexp(1.0, g);
+    L.alpha = cfg->dt / (2.0 * cfg->re * L.h * L.h);
+    L.s = dalloc(s, full);
+    L.hist = dalloc(s, inner);
+    L.sring = dalloc(s, ring);
+    L.gring[0] = dalloc(s, ring);
+    L.gring[1] = dalloc(s, ring);
+    if (!L.s || !L.hist || !L.sring || !L.gring[0] || !L.gring[1]) st = IB_ERR_OOM;
+    s->lv.push_back(L);
+  }
+  s->work = dalloc(s, inner);
+  s->work2 = dalloc(s, inner);
+  s->sstar = dalloc(s, full);
+  if (!s->work || !s->work2 || !s->sstar) st = IB_ERR_OOM;
+  if (st == IB_OK) {
+    st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
+                 : make_tables<float>(s, s->n, &s->tw, &s->lam);
+  }
+  if (st == IB_OK) st = make_tables<double>(s, s->n, &s->tw64, &s->lam64);
+  if (st == IB_OK) {
+    for (auto& L : s->lv) {
+      if (hipMemset(L.s, 0, full) != hipSuccess || hipMemset(L.hist, 0, inner) != hipSuccess ||
+          hipMemset(L.sring, 0, ring) != hipSuccess || hipMemset(L.gring[0], 0, ring) != hipSuccess ||
+          hipMemset(L.gring[1], 0, ring) != hipSuccess)
+        st = IB_ERR_HIP;
+    }
+    if (hipMemset(s->work2, 0, inner) != hipSuccess || hipMemset(s->sstar, 0, full) != hipSuccess)
+      st = IB_ERR_HIP;
+  }
+  if (st != IB_OK) {
+    ib_destroy(s);
+    return st;
+  }
+  *out = s;
+  return IB_OK;
+}
+
+ib_status ib_add_rigid(ib_solver* s, int32_t m, const double* xy, double ds, const double* u_b,
+                       int32_t* body_id) {
+  if (check(s) || m < 1 || !xy || !(ds > 0)) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  HostBody b;
+  b.kind = BODY_RIGID;
+  b.m = m;
+  b.ds = ds;
+  b.xy.assign(xy, xy + 2 * m);
+  if (u_b) b.ub.assign(u_b, u_b + 2 * m);
+  s->bodies.push_back(b);
+  if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
+  return IB_OK;
+}
+
+ib_status ib_add_torsional(ib_solver* s, int32_t m, double hinge_x, double hinge_y, double length,
+                           double theta0, double inertia, double stiffness, double damping,
+                           double theta, double phi, int32_t* body_id) {
+  if (check(s) || m < 2 || !(length > 0) || !(inertia > 0)) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  HostBody b;
+  b.kind = BODY_TORSIONAL;
+  b.m = m;
+  b.ds = length / (m - 1);
+  b.hx = hinge_x;
+  b.hy = hinge_y;
+  b.length = length;
+  b.theta0 = theta0;
+  b.inertia = inertia;
+  b.stiffness = stiffness;
+  b.damping = damping;
+  b.theta = theta;
+  b.phi = phi;
+  s->bodies.push_back(b);
+  if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
+  return IB_OK;
+}
+
+ib_status ib_add_deformable(ib_solver* s, int32_t m, const double* xy_ref, double mass, double ei,
+                            double ea, const double* xy0, const double* rot0, int32_t* body_id) {
+  if (check(s) || m < 2 || m > 201 || !xy_ref || !xy0 || !rot0 || !(mass > 0) || !(ei > 0) ||
+      !(ea > 0))
+    return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  HostBody b;
+  b.kind = BODY_DEFORMABLE;
+  b.m = m;
+  b.xy_ref.assign(xy_ref, xy_ref + 2 * m);
+  b.xy0.assign(xy0, xy0 + 2 * m);
+  b.rot0.assign(rot0, rot0 + m);
+  double len = 0;
+  for (int k = 0; k + 1 < m; ++k)
+    len += std::hypot(xy_ref[2 * k + 2] - xy_ref[2 * k], xy_ref[2 * k + 3] - xy_ref[2 * k + 1]);
+  b.ds = len / (m - 1);
+  b.mass = mass;
+  b.ei = ei;
+  b.ea = ea;
+  s->bodies.push_back(b);
+  if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
+  return IB_OK;
+}
+
+ib_status ib_set_subdomain(ib_solver* s, double x0, double x1, double y0, double y1) {
+  if (check(s) || !(x1 > x0) || !(y1 > y0)) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  s->has_sd = true;
+  s->sd[0] = x0;
+  s->sd[1] = x1;
+  s->sd[2] = y0;
+  s->sd[3] = y1;
+  return IB_OK;
+}
+
+ib_status ib_set_vorticity(ib_solver* s, int32_t level, const double* omega) {
+  if (check(s) || level < 0 || level >= (int)s->lv.size() || !omega) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  if ((int)s->omega0.size() <= level) s->omega0.resize(level + 1);
+  s->omega0[level].assign(omega, omega + (size_t)(s->n - 1) * (s->n - 1));
+  return IB_OK;
+}
+
+ib_status ib_prepare(ib_solver* s) {
+  if (check(s)) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  ib_status st = s->fp64 ? do_prepare<double>(s) : do_prepare<float>(s);
+  if (st) {
+    s->failed = true;
+    return st;
+  }
+  s->prepared = true;
+  return IB_OK;
+}
+
+ib_status ib_step(ib_solver* s, int32_t nsteps) {
+  if (check(s) || nsteps < 0) return IB_ERR_ARG;
+  if (!s->prepared || s->failed) return IB_ERR_STATE;
+  for (int k = 0; k < nsteps; ++k) {
+    ib_status st = s->fp64 ? do_step<double>(s) : do_step<float>(s);
+    if (st) {
+      s->failed = true;
+      return st;
+    }
+  }
+  return IB_OK;
+}
+
+ib_status ib_sync(ib_solver* s) {
+  if (check(s)) return IB_ERR_ARG;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  return e == hipSuccess ? IB_OK : hip_fail(s, e, "hipStreamSynchronize");
+}
+
+ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap) {
+  if (check(s) || !f || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
+  if (!s->prepared || !s->f) return IB_ERR_STATE;
+  int pt0 = 0;
+  for (int k = 0; k < body_id; ++k) pt0 += s->bodies[k].m;
+  const int m = s->bodies[body_id].m;
+  if (cap < 2 * m) return IB_ERR_CAPACITY;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(f, s->f + 2 * pt0, (size_t)2 * m * 8, hipMemcpyDeviceToHost));
+  return IB_OK;
+}
+
+ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap) {
+  if (check(s) || !out || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
+  if (!s->prepared) return IB_ERR_STATE;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const HostBody& hb = s->bodies[body_id];
+  int tors = 0, dof = 0;
+  for (int k = 0; k < body_id; ++k) {
+    if (s->bodies[k].kind == BODY_TORSIONAL) ++tors;
+    if (s->bodies[k].kind == BODY_DEFORMABLE) dof += 3 * s->bodies[k].m;
+  }
+  if (hb.kind == BODY_TORSIONAL) {
+    if (cap < 3) return IB_ERR_CAPACITY;
+    HIPCHK(hipMemcpy(out, s->fa.tors + tors * TS_COUNT, 3 * 8, hipMemcpyDeviceToHost));
+  } else if (hb.kind == BODY_DEFORMABLE) {
+    if (cap < 3 * hb.m) return IB_ERR_CAPACITY;
+    HIPCHK(hipMemcpy(out, s->fa.chi + dof, (size_t)3 * hb.m * 8, hipMemcpyDeviceToHost));
+  } else {
+    if (cap < 2 * hb.m) return IB_ERR_CAPACITY;
+    std::memcpy(out, hb.xy.data(), (size_t)2 * hb.m * 8);
+  }
+  return IB_OK;
+}
+
+ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap) {
+  if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
+  const int n = s->n;
+  if (cap < (int64_t)(n + 1) * (n + 1)) return IB_ERR_CAPACITY;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  std::vector<char> buf((size_t)(n + 1) * s->pitch * s->es);
+  HIPCHK(hipMemcpy(buf.data(), s->lv[level].s, buf.size(), hipMemcpyDeviceToHost));
+  for (int j = 0; j <= n; ++j)
+    for (int i = 0; i <= n; ++i) {
+      const size_t k = (size_t)j * s->pitch + i;
+      out[(size_t)j * (n + 1) + i] =
+          s->fp64 ? reinterpret_cast<double*>(buf.data())[k] : reinterpret_cast<float*>(buf.data())[k];
+    }
+  return IB_OK;
+}
+
+ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap) {
+  if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
+  const int n = s->n;
+  if (cap < (int64_t)(n - 1) * (n - 1)) return IB_ERR_CAPACITY;
+  std::vector<double> sf((size_t)(n + 1) * (n + 1));
+  ib_status st = ib_read_streamfunction(s, level, sf.data(), (int64_t)sf.size());
+  if (st) return st;
+  const double h = s->lv[level].h;
+  const double inv = 1.0 / (h * h);
+  for (int j = 1; j < n; ++j)
+    for (int i = 1; i < n; ++i) {
+      const size_t c = (size_t)j * (n + 1) + i;
+      const double l = 4.0 * sf[c] - sf[c + 1] - sf[c - 1] - sf[c + n + 1] - sf[c - n - 1];
+      out[(size_t)(j - 1) * (n - 1) + (i - 1)] = l * inv;
+    }
+  return IB_OK;
+}
+
+ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
+  if (check(s) || !out) return IB_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->step = s->step;
+  out->newton_iters = s->iters_last;
+  out->newton_iters_max = s->iters_max;
+  out->newton_delta = s->delta_last;
+  out->subdomain_points = s->use_sd ? 2 * (int64_t)s->sd_total : 0;
+  out->subdomain_nnz = s->bp_nnz;
+  out->prepare_seconds = s->prepare_seconds;
+  return IB_OK;
+}
+
+ib_status ib_destroy(ib_solver* s) {
+  if (!s) return IB_ERR_ARG;
+  (void)hipStreamSynchronize(s->stream);
+  while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
+  if (s->hflags) (void)hipHostFree(s->hflags);
+  if (s->hdelta) (void)hipHostFree(s->hdelta);
+  delete s;
+  return IB_OK;
+}
+
+ib_status ib_op_solve(int32_t n, int32_t precision, double alpha, const void* in, void* out,
+                      int32_t pitch, void* hip_stream) {
+  if (!supported_n(n) || !in || !out || pitch < n - 1 ||
+      (precision != IB_FP64 && precision != IB_FP32_FLOW))
+    return IB_ERR_ARG;
+  ib_solver tmp;
+  ib_solver* s = &tmp;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->n = n;
+  s->pitch = pitch;
+  ib_status st = IB_OK;
+  const double scale = 4.0 / ((double)n * n);
+  if (precision == IB_FP64) {
+    st = make_tables<double>(s, n, &s->tw, &s->lam);
+    if (!st) {
+      RowArgs<double> r{};
+      r.in = static_cast<const double*>(in);
+      r.out = static_cast<double*>(out);
+      r.pi = r.po = pitch;
+      r.r0 = 1;
+      r.r1 = n - 1;
+      if (launch_rowdst<double>(r, n, 1, s->tw, s->stream) != hipSuccess) st = IB_ERR_HIP;
+      if (!st) st = solve_into<double>(s, out, alpha, scale, 1, n - 1, s->tw, s->lam);
+      r.in = static_cast<const double*>(out);
+      r.interior_out = 1;
+      if (!st && launch_row_idst<double>(r, n, 1, s->tw, nullptr, 0, s->stream) != hipSuccess)
+        st = IB_ERR_HIP;
+    }
+  } else {
+    st = make_tables<float>(s, n, &s->tw, &s->lam);
+    if (!st) {
+      RowArgs<float> r{};
+      r.in = static_cast<const float*>(in);
+      r.out = static_cast<float*>(out);
+      r.pi = r.po = pitch;
+      r.r0 = 1;
+      r.r1 = n - 1;
+      if (launch_rowdst<float>(r, n, 1, s->tw, s->stream) != hipSuccess) st = IB_ERR_HIP;
+      if (!st) st = solve_into<float>(s, out, alpha, scale, 1, n - 1, s->tw, s->lam);
+      r.in = static_cast<const float*>(out);
+      r.interior_out = 1;
+      if (!st && launch_row_idst<float>(r, n, 1, s->tw, nullptr, 0, s->stream) != hipSuccess)
+        st = IB_ERR_HIP;
+    }
+  }
+  (void)hipStreamSynchronize(s->stream);
+  while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// LDS-resident complex FFT and the type-I discrete sine transform built on it.
+//
+// The lattice Laplacian C^T C of a level is diagonalised by the DST-I of size
+// n - 1 along each axis (Sec. 3.2.1 of the paper).  A DST-I of length n - 1 is
+// computed here from one complex FFT of length n:
+//
+//   z  = odd extension of x (length 2n, z_j = x_j, z_{2n-j} = -x_j, z_0 = z_n = 0)
+//   w_m = z_{2m} + i z_{2m+1}                      (m = 0 .. n-1)
+//   W  = FFT_n(w)
+//   E_k = (W_k + conj W_{n-k}) / 2,  O_k = (W_k - conj W_{n-k}) / (2i)
+//   X_k = sum_j x_j sin(pi j k / n) = -Im(E_k + e^{-i pi k / n} O_k) / 2
+//
+// The FFT is a Stockham autosort radix-4/2/3 transform working in place on LDS:
+// every stage loads its inputs into registers, synchronises the workgroup, and
+// writes the butterflies' outputs back.  Twiddles come from one table per n,
+// tw[m] = exp(-i pi m / n), m < 2n, prepared on the host in double precision.
+#pragma once
+
+#include "ib_common.hpp"
+
+namespace ib {
+
+constexpr int ilog2c(int m) { return m <= 1 ? 0 : 1 + ilog2c(m / 2); }
+constexpr int pow3c(int l) { return (l % 3) ? 0 : 1 + pow3c(l / 3); }
+constexpr int ipow3(int p) { return p == 0 ? 1 : 3 * ipow3(p - 1); }
+
+template <int L>
+struct FftPlan {
+  static constexpr int p3 = pow3c(L);
+  static constexpr int p2 = ilog2c(L / ipow3(p3));
+  static constexpr int n4 = p2 / 2;
+  static constexpr int n2 = p2 % 2;
+  static constexpr int nst = n4 + n2 + p3;
+  static_assert(ipow3(p3) * (1 << p2) == L, "FFT length must be 2^a 3^b");
+  static constexpr int radix(int s) { return s < n4 ? 4 : (s < n4 + n2 ? 2 : 3); }
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(c2<T>* v) {
+  if constexpr (R == 2) {
+    c2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    c2<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    c2<T> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    c2<T> md = cmul_mi(d13);
+    v[1] = cadd(d02, md);
+    v[3] = csub(d02, md);
+  } else {
+    // e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
+    const T h3 = T(0.86602540378443864676372317075294);
+    c2<T> t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    c2<T> m = c2<T>{v[0].x - T(0.5) * t1.x, v[0].y - T(0.5) * t1.y};
+    c2<T> r = cmul_mi(t2);
+    v[0] = cadd(v[0], t1);
+    v[1] = c2<T>{m.x + h3 * r.x, m.y + h3 * r.y};
+    v[2] = c2<T>{m.x - h3 * r.x, m.y - h3 * r.y};
+  }
+}
+
+// One Stockham stage on COUNT transforms of length L stored back to back in buf.
+template <typename T, int L, int R, int NS, int COUNT, int NT>
+__device__ __forceinline__ void fft_stage(c2<T>* buf, const c2<T>* __restrict__ tw, int tid) {
+  constexpr int LR = L / R;
+  constexpr int NB = COUNT * LR;
+  constexpr int PER = (NB + NT - 1) / NT;
+  constexpr int TWS = (2 * L) / (NS * R);
+  c2<T> v[PER][R];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    int jj = tid + b * NT;
+    if (jj < NB) {
+      int t = jj / LR, j = jj % LR;
+      const c2<T>* base = buf + t * L;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = base[j + r * LR];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    int jj = tid + b * NT;
+    if (jj < NB) {
+      int t = jj / LR, j = jj % LR;
+      int k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[TWS * r * k]);
+      }
+      dft_small<T, R>(v[b]);
+      int d = (j / NS) * NS * R + k;
+      c2<T>* base = buf + t * L;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[d + r * NS] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int S, int NS, int COUNT, int NT>
+__device__ __forceinline__ void fft_run(c2<T>* buf, const c2<T>* __restrict__ tw, int tid) {
+  if constexpr (S < FftPlan<L>::nst) {
+    constexpr int R = FftPlan<L>::radix(S);
+    fft_stage<T, L, R, NS, COUNT, NT>(buf, tw, tid);
+    fft_run<T, L, S + 1, NS * R, COUNT, NT>(buf, tw, tid);
+  }
+}
+
+// Forward complex FFT (e^{-2 pi i m k / L}) of COUNT sequences in LDS, natural order.
+// Requires a workgroup barrier before (inputs written) and leaves one after.
+template <typename T, int L, int COUNT, int NT>
+__device__ __forceinline__ void fft_lds(c2<T>* buf, const c2<T>* __restrict__ tw, int tid) {
+  fft_run<T, L, 0, 1, COUNT, NT>(buf, tw, tid);
+}
+
+// Place x_j (j = 1 .. n-1) of sequence t into the packed odd extension w.
+template <typename T, int N>
+__device__ __forceinline__ void dst_pack(c2<T>* w, int j, T xj) {
+  T* wr = reinterpret_cast<T*>(w);
+  // z_j lives in w[j/2] (real part if j even), z_{2n-j} = -x_j in w[(2n-j)/2]
+  wr[2 * (j >> 1) + (j & 1)] = xj;
+  int jm = 2 * N - j;
+  wr[2 * (jm >> 1) + (jm & 1)] = -xj;
+}
+
+// Zero the two packed slots that hold z_0 and z_n.
+template <typename T, int N>
+__device__ __forceinline__ void dst_pack_zeros(c2<T>* w) {
+  T* wr = reinterpret_cast<T*>(w);
+  wr[0] = T(0);
+  wr[2 * (N >> 1)] = T(0);
+}
+
+// Unpack the DST-I outputs X_k and X_{n-k} (k = 1 .. n/2) from W = FFT_n(w).
+// Returns them through xk, xnk (for k = n/2 both hold X_{n/2}).
+template <typename T, int N>
+__device__ __forceinline__ void dst_unpack(const c2<T>* W, const c2<T>* __restrict__ tw, int k,
+                                           T& xk, T& xnk) {
+  c2<T> a = W[k];
+  c2<T> b = W[N - k];
+  // E = (a + conj b)/2, O = -i (a - conj b) / 2
+  T e_im = T(0.5) * (a.y - b.y);
+  c2<T> d = c2<T>{a.x - b.x, a.y + b.y};
+  c2<T> o = c2<T>{T(0.5) * d.y, -T(0.5) * d.x};
+  c2<T> p = cmul(tw[k], o);
+  xk = -T(0.5) * (e_im + p.y);
+  xnk = T(0.5) * (e_im - p.y);
+}
+
+}  // namespace ib

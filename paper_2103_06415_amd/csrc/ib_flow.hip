@@ -1,0 +1,458 @@
+// Flow kernels of one level: explicit right-hand side fused with the row sine
+// transform, the column transform + spectral solve, the inverse row transform, the
+// nested-level boundary rings, and a plain row transform for sparse sources.
+//
+// Per level g the predictor solves (Sec. 2.3 eq. (16), Appendix A r^f):
+//   (I + a L) L s_{n+1} = gamma_n - a L gamma_n + dt (3/2 C^T N_n - 1/2 C^T N_{n-1})
+//                         + a B(gamma_ring_{n+1}) + (I + a L) B(s_ring_{n+1}),
+// L = C^T C (5-point), a = dt / (2 Re h_g^2), B(.) = ring values adjacent to an
+// interior vertex.  (I + a L) L is diagonal in the 2-D DST-I basis (Sec. 3.2.1), so
+// the solve is row DST -> column DST, scale, inverse column DST -> inverse row DST.
+#include "ib_internal.hpp"
+#include "ib_fft.hpp"
+
+namespace ib {
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
+  return p[(size_t)j * pitch + i];
+}
+
+template <typename T>
+__device__ __forceinline__ T gamma_at(const RhsArgs<T>& a, int i, int j) {
+  const int n = a.n;
+  if (j == 0) return a.gring[RING_B * (n + 1) + i];
+  if (j == n) return a.gring[RING_T * (n + 1) + i];
+  if (i == 0) return a.gring[RING_L * (n + 1) + j];
+  if (i == n) return a.gring[RING_R * (n + 1) + j];
+  if (a.sf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
+    // coarsification on read: the finer level's circulation at the coincident vertex
+    const int fi = 2 * i - n / 2, fj = 2 * j - n / 2;
+    const T* f = a.sf;
+    const int p = a.psf;
+    T l = T(4) * ld(f, p, fj, fi) - ld(f, p, fj, fi + 1) - ld(f, p, fj, fi - 1) -
+          ld(f, p, fj + 1, fi) - ld(f, p, fj - 1, fi);
+    return T(4) * l;
+  }
+  const T* s = a.s;
+  const int p = a.ps;
+  return T(4) * ld(s, p, j, i) - ld(s, p, j, i + 1) - ld(s, p, j, i - 1) - ld(s, p, j + 1, i) -
+         ld(s, p, j - 1, i);
+}
+
+// Sum of the new boundary-ring values adjacent to interior vertex (i, j).
+template <typename T>
+__device__ __forceinline__ T ring_adj(const T* ring, int n, int i, int j) {
+  T v = T(0);
+  if (i == 1) v += ring[RING_L * (n + 1) + j];
+  if (i == n - 1) v += ring[RING_R * (n + 1) + j];
+  if (j == 1) v += ring[RING_B * (n + 1) + i];
+  if (j == n - 1) v += ring[RING_T * (n + 1) + i];
+  return v;
+}
+
+// Right-hand side at interior vertex (i, j); writes C^T N_n to the history.
+template <typename T>
+__device__ __forceinline__ T rhs_point(const RhsArgs<T>& a, int i, int j) {
+  const T* s = a.s;
+  const int p = a.ps;
+  const T g0 = gamma_at(a, i, j);
+  const T gE = gamma_at(a, i + 1, j), gW = gamma_at(a, i - 1, j);
+  const T gN = gamma_at(a, i, j + 1), gS = gamma_at(a, i, j - 1);
+  // vertex-averaged fluxes (total flux, free stream included)
+  const T uE = T(0.5) * (ld(s, p, j + 1, i + 1) - ld(s, p, j - 1, i + 1)) + a.ux;
+  const T uW = T(0.5) * (ld(s, p, j + 1, i - 1) - ld(s, p, j - 1, i - 1)) + a.ux;
+  const T vN = T(0.5) * (ld(s, p, j + 1, i - 1) - ld(s, p, j + 1, i + 1)) + a.uy;
+  const T vS = T(0.5) * (ld(s, p, j - 1, i - 1) - ld(s, p, j - 1, i + 1)) + a.uy;
+  // C^T N with N = (vbar gamma, -ubar gamma) / h^2 averaged onto the faces
+  const T ctn = a.cn * ((uE * gE - uW * gW) + (vN * gN - vS * gS));
+  const size_t hidx = (size_t)(j - 1) * a.ph + (i - 1);
+  const T hprev = a.hist_in ? a.hist_in[hidx] : ctn;
+  a.hist_out[hidx] = ctn;
+  const T lap = T(4) * g0 - gE - gW - gN - gS;
+  T r = g0 - a.alpha * lap + a.dt * (T(1.5) * ctn - T(0.5) * hprev);
+  if (a.sring_new != nullptr) {
+    const int n = a.n;
+    const T* sr = a.sring_new;
+    T bs = ring_adj(sr, n, i, j);
+    T nb = T(0);
+    if (i + 1 <= n - 1) nb += ring_adj(sr, n, i + 1, j);
+    if (i - 1 >= 1) nb += ring_adj(sr, n, i - 1, j);
+    if (j + 1 <= n - 1) nb += ring_adj(sr, n, i, j + 1);
+    if (j - 1 >= 1) nb += ring_adj(sr, n, i, j - 1);
+    T bg = ring_adj(a.gring_new, n, i, j);
+    r = r + a.alpha * bg + bs + a.alpha * (T(4) * bs - nb);
+  }
+  return r;
+}
+
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __restrict__ tw,
+                                                   int nblocks) {
+  __shared__ c2<T> buf[ROWS * N];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const int j0 = 1 + blk * ROWS;
+  for (int e = tid; e < ROWS * (N - 1); e += NT) {
+    const int t = e / (N - 1), i = 1 + e % (N - 1);
+    const int j = j0 + t;
+    T v = T(0);
+    if (j <= N - 1) v = rhs_point(a, i, j);
+    dst_pack<T, N>(buf + t * N, i, v);
+  }
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  __syncthreads();
+  fft_lds<T, N, ROWS, NT>(buf, tw, tid);
+  for (int e = tid; e < ROWS * (N / 2); e += NT) {
+    const int t = e / (N / 2), k = 1 + e % (N / 2);
+    const int j = j0 + t;
+    if (j > N - 1) continue;
+    T xk, xnk;
+    dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
+    T* o = a.out + (size_t)(j - 1) * a.po;
+    o[k - 1] = xk;
+    if (k != N / 2) o[N - k - 1] = xnk;
+  }
+}
+
+// Plain row DST of rows [r0, r1] (1-based interior rows) of a real array; batched
+// over blockIdx.y with the given strides.
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __restrict__ tw,
+                                               int nblocks) {
+  __shared__ c2<T> buf[ROWS * N];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  const int j0 = a.r0 + blk * ROWS;
+  for (int e = tid; e < ROWS * (N - 1); e += NT) {
+    const int t = e / (N - 1), i = 1 + e % (N - 1);
+    const int j = j0 + t;
+    T v = T(0);
+    if (j <= a.r1) v = in[(size_t)(j - 1) * a.pi + (i - 1)];
+    dst_pack<T, N>(buf + t * N, i, v);
+  }
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  __syncthreads();
+  fft_lds<T, N, ROWS, NT>(buf, tw, tid);
+  for (int e = tid; e < ROWS * (N / 2); e += NT) {
+    const int t = e / (N / 2), k = 1 + e % (N / 2);
+    const int j = j0 + t;
+    if (j > a.r1) continue;
+    T xk, xnk;
+    dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
+    T* o = out + (size_t)(j - 1) * a.po;
+    o[k - 1] = xk;
+    if (k != N / 2) o[N - k - 1] = xnk;
+  }
+}
+
+// Column DST, spectral scale scale / (lam (1 + alpha lam)), inverse column DST.
+// Reads input rows [r0, r1] (others are zero) and writes
+//   out = (accumulate ? out : 0) + result
+// for every row; input and output may alias when accumulate == 0.
+template <typename T, int N, int CW, int NT>
+__global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
+                                                  const T* __restrict__ lam) {
+  __shared__ c2<T> buf[CW * N];
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * CW;
+  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  for (int e = tid; e < (N - 1) * CW; e += NT) {
+    const int r = e / CW, c = e % CW;
+    const int col = k0 + c;
+    T v = T(0);
+    if (col < N - 1) {
+      if (a.rfirst != nullptr) {
+        const int q = r + 1 - a.rfirst[blockIdx.y];
+        if (q >= 0 && q < a.rcount) v = in[(size_t)q * a.pi + col];
+      } else if (r + 1 >= a.r0 && r + 1 <= a.r1) {
+        v = in[(size_t)r * a.pi + col];
+      }
+    }
+    dst_pack<T, N>(buf + c * N, r + 1, v);
+  }
+  for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
+  __syncthreads();
+  fft_lds<T, N, CW, NT>(buf, tw, tid);
+  constexpr int NP = CW * (N / 2);
+  constexpr int PER = (NP + NT - 1) / NT;
+  T xa[PER], xb[PER];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = tid + b * NT;
+    if (e < NP) {
+      const int c = e % CW, l = 1 + e / CW;
+      const int col = k0 + c;
+      T xk, xnk;
+      dst_unpack<T, N>(buf + c * N, tw, l, xk, xnk);
+      const T lk = (col < N - 1) ? lam[col] : T(1);
+      T l1 = lk + lam[l - 1];
+      T l2 = lk + lam[N - l - 1];
+      xa[b] = xk * (a.scale / (l1 * (T(1) + a.alpha * l1)));
+      xb[b] = xnk * (a.scale / (l2 * (T(1) + a.alpha * l2)));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = tid + b * NT;
+    if (e < NP) {
+      const int c = e % CW, l = 1 + e / CW;
+      dst_pack<T, N>(buf + c * N, l, xa[b]);
+      if (l != N / 2) dst_pack<T, N>(buf + c * N, N - l, xb[b]);
+    }
+  }
+  for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
+  __syncthreads();
+  fft_lds<T, N, CW, NT>(buf, tw, tid);
+  for (int e = tid; e < NP; e += NT) {
+    const int c = e % CW, j = 1 + e / CW;
+    const int col = k0 + c;
+    if (col >= N - 1) continue;
+    T yk, ynk;
+    dst_unpack<T, N>(buf + c * N, tw, j, yk, ynk);
+    if (j >= a.w0 && j <= a.w1) {
+      T* o1 = out + (size_t)(j - 1) * a.po + col;
+      *o1 = a.accumulate ? *o1 + yk : yk;
+    }
+    const int j2 = N - j;
+    if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) {
+      T* o2 = out + (size_t)(j2 - 1) * a.po + col;
+      *o2 = a.accumulate ? *o2 + ynk : ynk;
+    }
+  }
+}
+
+// Inverse row DST of rows [r0, r1] into the interior of a full (n+1)-row array; the
+// ring columns (and, when ring rows are requested, rows 0 and n) come from `ring`
+// (zero when null).
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __restrict__ tw,
+                                                 const T* __restrict__ ring, int ring_rows,
+                                                 int nblocks) {
+  __shared__ c2<T> buf[ROWS * N];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  const int j0 = a.r0 + blk * ROWS;
+  for (int e = tid; e < ROWS * (N - 1); e += NT) {
+    const int t = e / (N - 1), k = 1 + e % (N - 1);
+    const int j = j0 + t;
+    T v = T(0);
+    if (j <= a.r1) v = in[(size_t)(j - 1) * a.pi + (k - 1)];
+    dst_pack<T, N>(buf + t * N, k, v);
+  }
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  __syncthreads();
+  fft_lds<T, N, ROWS, NT>(buf, tw, tid);
+  for (int e = tid; e < ROWS * (N / 2); e += NT) {
+    const int t = e / (N / 2), k = 1 + e % (N / 2);
+    const int j = j0 + t;
+    if (j > a.r1) continue;
+    T xk, xnk;
+    dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
+    if (a.interior_out) {
+      T* o = out + (size_t)(j - 1) * a.po;
+      o[k - 1] = xk;
+      if (k != N / 2) o[N - k - 1] = xnk;
+    } else {
+      T* o = out + (size_t)j * a.po;
+      o[k] = xk;
+      if (k != N / 2) o[N - k] = xnk;
+    }
+  }
+  if (a.interior_out) return;
+  for (int t = tid; t < ROWS; t += NT) {
+    const int j = j0 + t;
+    if (j > a.r1) continue;
+    T* o = out + (size_t)j * a.po;
+    o[0] = ring ? ring[RING_L * (N + 1) + j] : T(0);
+    o[N] = ring ? ring[RING_R * (N + 1) + j] : T(0);
+  }
+  if (ring_rows && blk == 0) {
+    for (int i = tid; i <= N; i += NT) {
+      out[i] = ring ? ring[RING_B * (N + 1) + i] : T(0);
+      out[(size_t)N * a.po + i] = ring ? ring[RING_T * (N + 1) + i] : T(0);
+    }
+  }
+}
+
+// New boundary rings of a fine level from the next coarser level's streamfunction:
+// coincident vertices are copied, midpoints use the cubic (-1, 9, 9, -1)/16 along the
+// edge; the circulation ring is the same interpolation of the coarse C^T C s, scaled
+// by 1/4 (gamma = h^2 omega and h halves).
+template <typename T>
+__device__ __forceinline__ T coarse_val(const T* sc, int p, int edge, int line, int I, bool gam) {
+  const int j = (edge < 2) ? line : I;
+  const int i = (edge < 2) ? I : line;
+  if (!gam) return sc[(size_t)j * p + i];
+  return T(4) * sc[(size_t)j * p + i] - sc[(size_t)j * p + i + 1] - sc[(size_t)j * p + i - 1] -
+         sc[(size_t)(j + 1) * p + i] - sc[(size_t)(j - 1) * p + i];
+}
+
+template <typename T>
+__global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gring) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 4 * (n + 1)) return;
+  const int edge = e / (n + 1), idx = e % (n + 1);
+  const int q = n / 2;
+  const int line = (edge == RING_B || edge == RING_L) ? n / 4 : (3 * n) / 4;
+  T sv, gv;
+  if (((idx + q) & 1) == 0) {
+    const int I = (idx + q) / 2;
+    sv = coarse_val(sc, psc, edge, line, I, false);
+    gv = coarse_val(sc, psc, edge, line, I, true);
+  } else {
+    const int c = (idx + q - 1) / 2;
+    sv = (-coarse_val(sc, psc, edge, line, c - 1, false) +
+          T(9) * coarse_val(sc, psc, edge, line, c, false) +
+          T(9) * coarse_val(sc, psc, edge, line, c + 1, false) -
+          coarse_val(sc, psc, edge, line, c + 2, false)) / T(16);
+    gv = (-coarse_val(sc, psc, edge, line, c - 1, true) +
+          T(9) * coarse_val(sc, psc, edge, line, c, true) +
+          T(9) * coarse_val(sc, psc, edge, line, c + 1, true) -
+          coarse_val(sc, psc, edge, line, c + 2, true)) / T(16);
+  }
+  sring[e] = sv;
+  gring[e] = T(0.25) * gv;
+}
+
+// work[j][i] += sum of the ring values adjacent to interior vertex (i, j): lifts
+// non-zero boundary values of the Poisson problem into its right-hand side.
+template <typename T>
+__global__ void k_add_ring_lift(T* work, int pw, const T* sring, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = n - 1;
+  if (e >= 4 * m) return;
+  const int side = e / m, k = 1 + e % m;
+  int i, j;
+  if (side == 0) { i = k; j = 1; }
+  else if (side == 1) { i = k; j = n - 1; }
+  else if (side == 2) { i = 1; j = k; }
+  else { i = n - 1; j = k; }
+  // each interior vertex is owned by exactly one (side, k): skip duplicates at corners
+  if ((side == 2 || side == 3) && (j == 1 || j == n - 1)) return;
+  work[(size_t)(j - 1) * pw + (i - 1)] += ring_adj(sring, n, i, j);
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+struct Cfg {
+  static constexpr int ROWS = 2;
+  static constexpr int NTR = 256;
+  static constexpr int CW = sizeof(T) == 8 ? 4 : 8;
+  static constexpr int NTC = 256;
+};
+
+#define IB_DISPATCH_N(n, MACRO)                                \
+  switch (n) {                                                 \
+    case 16: MACRO(16); break;                                 \
+    case 32: MACRO(32); break;                                 \
+    case 48: MACRO(48); break;                                 \
+    case 64: MACRO(64); break;                                 \
+    case 96: MACRO(96); break;                                 \
+    case 128: MACRO(128); break;                               \
+    case 192: MACRO(192); break;                               \
+    case 256: MACRO(256); break;                               \
+    case 384: MACRO(384); break;                               \
+    case 512: MACRO(512); break;                               \
+    case 768: MACRO(768); break;                               \
+    case 1024: MACRO(1024); break;                             \
+    default: return hipErrorInvalidValue;                      \
+  }
+
+bool supported_n(int n) {
+  switch (n) {
+    case 16: case 32: case 48: case 64: case 96: case 128: case 192: case 256:
+    case 384: case 512: case 768: case 1024:
+      return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st) {
+  constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
+  const int nb = (a.n - 1 + R - 1) / R;
+  const c2<T>* t = static_cast<const c2<T>*>(tw);
+#define L_(NN) hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb)
+  IB_DISPATCH_N(a.n, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rowdst(const RowArgs<T>& a, int n, int batch, const void* tw, hipStream_t st) {
+  constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
+  const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;
+  if (nb <= 0) return hipSuccess;
+  const c2<T>* t = static_cast<const c2<T>*>(tw);
+#define L_(NN) hipLaunchKernelGGL((k_rowdst<T, NN, R, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, nb)
+  IB_DISPATCH_N(n, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* tw, const void* lam,
+                            hipStream_t st) {
+  constexpr int CW = Cfg<T>::CW, NT = Cfg<T>::NTC;
+  const int nb = (n - 1 + CW - 1) / CW;
+  const c2<T>* t = static_cast<const c2<T>*>(tw);
+  const T* l = static_cast<const T*>(lam);
+#define L_(NN) hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(nb, batch), dim3(NT), 0, st, a, t, l)
+  IB_DISPATCH_N(n, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw, const T* ring,
+                           int ring_rows, hipStream_t st) {
+  constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
+  const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;
+  if (nb <= 0) return hipSuccess;
+  const c2<T>* t = static_cast<const c2<T>*>(tw);
+#define L_(NN) hipLaunchKernelGGL((k_row_idst<T, NN, R, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb)
+  IB_DISPATCH_N(n, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStream_t st) {
+  const int tot = 4 * (n + 1);
+  hipLaunchKernelGGL((k_ring<T>), dim3((tot + 255) / 256), dim3(256), 0, st, sc, psc, n, sring, gring);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add_ring_lift(T* work, int pw, const T* sring, int n, hipStream_t st) {
+  const int tot = 4 * (n - 1);
+  hipLaunchKernelGGL((k_add_ring_lift<T>), dim3((tot + 255) / 256), dim3(256), 0, st, work, pw, sring, n);
+  return hipGetLastError();
+}
+
+#define IB_INST(T)                                                                              \
+  template hipError_t launch_rhs_rowdst<T>(const RhsArgs<T>&, const void*, hipStream_t);      \
+  template hipError_t launch_rowdst<T>(const RowArgs<T>&, int, int, const void*, hipStream_t); \
+  template hipError_t launch_col_solve<T>(const ColArgs<T>&, int, int, const void*, const void*, \
+                                          hipStream_t);                                        \
+  template hipError_t launch_row_idst<T>(const RowArgs<T>&, int, int, const void*, const T*, int, \
+                                         hipStream_t);                                         \
+  template hipError_t launch_ring<T>(const T*, int, int, T*, T*, hipStream_t);         \
+  template hipError_t launch_add_ring_lift<T>(T*, int, const T*, int, hipStream_t);
+IB_INST(float)
+IB_INST(double)
+#undef IB_INST
+
+}  // namespace ib

@@ -1,0 +1,67 @@
+// Internal interfaces between the kernel files and the host engine.
+#pragma once
+
+#include "ib_common.hpp"
+
+namespace ib {
+
+// Explicit right-hand side of one level (see ib_flow.hip).
+template <typename T>
+struct RhsArgs {
+  const T* s;          // state at time n, (n+1) rows x ps, ring included
+  const T* sf;         // finer level's state at time n (coarsification on read), or null
+  const T* gring;      // ring circulation at time n, [4][n+1]
+  const T* sring_new;  // new streamfunction ring [4][n+1], or null (zero ring)
+  const T* gring_new;  // new circulation ring [4][n+1] (used with sring_new)
+  const T* hist_in;    // C^T N_{n-1}, (n-1) rows x ph, or null on the first step
+  T* hist_out;         // C^T N_n (may alias hist_in)
+  T* out;              // row-transformed right-hand side, (n-1) rows x po
+  int n, ps, psf, ph, po;
+  T alpha, dt, ux, uy, cn;  // cn = -1 / (2 h^2); ux, uy = free-stream flux u_inf h
+};
+
+// Row-wise transform of rows [r0, r1] (1-based interior rows).
+template <typename T>
+struct RowArgs {
+  const T* in;
+  T* out;
+  int pi, po;
+  int r0, r1;
+  size_t bsi, bso;  // batch strides (elements)
+  int interior_out; // inverse transform: write an (n-1)-row interior array instead of a
+                    // full (n+1)-row array with its ring
+};
+
+// Column transform + spectral scale + inverse column transform.
+template <typename T>
+struct ColArgs {
+  const T* in;
+  T* out;
+  int pi, po;
+  int r0, r1;        // nonzero input rows (1-based interior rows)
+  T alpha, scale;    // multiplier scale / (lam (1 + alpha lam))
+  int accumulate;    // out += result instead of out = result
+  size_t bsi, bso;
+  const int* rfirst; // if set: slot b's input holds rows rfirst[b] .. rfirst[b] + rcount - 1
+  int rcount;        //   compactly (row rfirst[b] at input row 0)
+  int w0, w1;        // output rows written (1-based); others untouched
+};
+
+bool supported_n(int n);
+
+template <typename T>
+hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_rowdst(const RowArgs<T>& a, int n, int batch, const void* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* tw, const void* lam,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw, const T* ring,
+                           int ring_rows, hipStream_t st);
+template <typename T>
+hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStream_t st);
+template <typename T>
+hipError_t launch_add_ring_lift(T* work, int pw, const T* sring, int n, hipStream_t st);
+
+}  // namespace ib
