@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the strongly coupled IB step on one MI355X.
+
+Workload: 1024^2 cells per level, 4 nested levels, one deformable clamped flag
+(101 points, mass ratio 0.2, bending stiffness 1e-3), Re 500, sub-domain operator
+B' built offline (excluded from the timing, reported as prepare_s).  Metric: grid-cell
+steps per second = n^2 * levels * steps / wall time, for the FP32-flow form (value) and
+the plain FP64 form (value_fp64), inputs resident in HBM before the timed region.
+
+One JSON line on stdout.  ``--gpus`` above 1 is not supported (one GPU per run).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-cell steps/s (1024², 4 levels) fp32 vs fp64; served p50/p99 latency"
+PEAK_HBM = 8.0e12
+
+
+def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
+    """Bytes a launch class must move per timed region (roofline)."""
+    m = (n - 1) ** 2
+    full = (n + 1) ** 2
+    if cls == "col_solve":
+        # predictor per level: read spectral rows, write s and gamma rows;
+        # corrector: read the source rows, read + write both arrays
+        return steps * (levels * 3 * m + 4 * m + body_rows * (n - 1)) * es
+    if cls == "rhs_rowdst":
+        # read s (with ring), gamma, the history; write the history and the rows
+        coarsify = (levels - 1) * (n // 2) ** 2
+        return steps * (levels * (full + 4 * m) + coarsify) * es
+    if cls == "row_idst":
+        # read two spectral arrays, write s (with ring) and gamma; plus s* rows on level 0
+        return steps * (levels * (3 * m + full) + 2 * (body_rows + 6) * (n - 1)) * es
+    return 0
+
+
+def run(problem, precision, steps, warmup, timing=True):
+    import torch
+    from paper_2103_06415_amd import binding
+    s = binding.Solver(problem, precision=precision)
+    t0 = time.perf_counter()
+    s.prepare()
+    s.sync()
+    prep = time.perf_counter() - t0
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = {}
+    if timing:
+        # a second, instrumented pass gives the per-kernel durations (events add a few
+        # microseconds per launch, so it is kept out of the wall-clock region above)
+        s.set_kernel_timing(True)
+        s.step(steps)
+        s.sync()
+        names = ["rhs_rowdst", "col_solve", "row_idst", "fsi", "correct", "ring"]
+        for k, name in enumerate(names):
+            kt[name] = s.kernel_timing(k)
+        s.set_kernel_timing(False)
+    st = s.stats()
+    s.close()
+    return wall, prep, kt, st
+
+
+def cpu_baseline(n, levels, seconds=20.0):
+    """The FP64 oracle on the host: flow steps of the same grid (no body coupling)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle.step import Oracle
+    p = W.flag_problem(n=n, levels=levels)
+    flow = W.Problem("flow", p.flow, [], vorticity0=None)
+    o = Oracle(flow)
+    rng = np.random.default_rng(0)
+    o.s[0][1:-1, 1:-1] = 1e-3 * rng.normal(size=(n - 1, n - 1))
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step()
+        k += 1
+        if time.perf_counter() - t0 > seconds or k >= 50:
+            break
+    wall = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": n * n * levels * k / wall, "unit": "grid-cell steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{k} oracle flow steps of the {n}^2 x {levels}-level grid (dense FP64 "
+                      f"sine-matrix solves on every level, nonlinear term, rings; no body "
+                      f"coupling), {wall:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: each MI355X box here has one, and the "
+              "single-instance step does not shard across GPUs (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2103_06415_amd import binding
+    torch.cuda.set_device(0)
+    n, levels = args.n, args.levels
+    prob = W.flag_problem(n=n, levels=levels)
+    cells = n * n * levels
+    wall32, prep32, kt, st32 = run(prob, binding.IB_FP32_FLOW, args.steps, args.warmup)
+    value = cells * args.steps / wall32
+    value64 = None
+    if not args.no_fp64:
+        wall64, prep64, _, _ = run(prob, binding.IB_FP64, args.steps, args.warmup, timing=False)
+        value64 = cells * args.steps / wall64
+    # roofline of the dominant flow kernel class
+    body_rows = 0
+    sd = prob.subdomain
+    if sd is not None:
+        body_rows = int((sd[3] - sd[2]) / prob.flow.h) + 9
+    flow_classes = ["rhs_rowdst", "col_solve", "row_idst"]
+    dom = max(flow_classes, key=lambda c: kt[c][1])
+    launches, ms = kt[dom]
+    tot_bytes = algorithmic_bytes(dom, n, levels, args.steps, 4, body_rows)
+    achieved = tot_bytes / (ms * 1e-3) if ms > 0 else 0.0
+    times_ms = {k: round(v[1] / args.steps, 5) for k, v in kt.items()}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-cell steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"deformable flag, {n}^2 cells x {levels} levels, 101 body points, "
+                               "Re 500, sub-domain B' (eps 0.007), FSI tol 1e-7; FP32 flow + "
+                               "FP64 Schur/LU/structure",
+                   "n": n, "levels": levels, "subdomain_nnz": st32["subdomain_nnz"],
+                   "newton_iters_max": st32["newton_iters_max"]},
+        "value_fp64": value64,
+        "fp32_over_fp64": (value / value64) if value64 else None,
+        "prepare_s": prep32,
+        "kernel_ms_per_step": times_ms,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
+                     "bytes_per_launch": tot_bytes / max(launches, 1),
+                     "avg_launch_us": 1e3 * ms / max(launches, 1)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, levels)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

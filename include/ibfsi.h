@@ -150,13 +150,29 @@ ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap
  * (x, y, rotation per node); rigid -> its 2m point coordinates. */
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap);
 
-/* Vorticity omega = C^T C s / h^2 of a level at interior vertices, (n-1)^2 doubles. */
+/* Vorticity of a level at interior vertices, (n-1)^2 doubles: the level's circulation
+ * state gamma (= C^T C s, carried alongside s) divided by h^2. */
 ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap);
 
 /* Streamfunction of a level including its ring, (n+1)^2 doubles. */
 ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap);
 
 ib_status ib_get_stats(ib_solver* s, ib_stats* out);
+
+/* Kernel timing for measurement: while enabled, every launch of the classes below is
+ * bracketed by HIP events on the solver's stream (adds a few microseconds per launch).
+ * ib_get_kernel_timing synchronises and returns the launches and the summed kernel
+ * time (milliseconds) of one class since timing was last enabled. */
+#define IB_K_RHS_ROWDST 0   /* explicit right-hand side + row sine transform */
+#define IB_K_COL_SOLVE 1    /* column transform, spectral solve, inverse (s and gamma) */
+#define IB_K_ROW_IDST 2     /* inverse row transform into the level state */
+#define IB_K_FSI 3          /* one FSI iteration (operator, Schur, LU, update) */
+#define IB_K_CORRECT 4      /* corrector source + its row transform */
+#define IB_K_RING 5         /* nested-level boundary rings */
+#define IB_K_CLASSES 6
+ib_status ib_set_kernel_timing(ib_solver* s, int32_t enable);
+ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* launches,
+                               double* total_ms);
 
 ib_status ib_destroy(ib_solver* s);
 

@@ -79,7 +79,11 @@ _SIGS = {
     "ib_destroy": (c_int32, [c_void_p]),
     "ib_status_str": (ctypes.c_char_p, [c_int32]),
     "ib_op_solve": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_void_p, c_int32, c_void_p]),
+    "ib_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
+    "ib_get_kernel_timing": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
 }
+
+K_RHS_ROWDST, K_COL_SOLVE, K_ROW_IDST, K_FSI, K_CORRECT, K_RING = range(6)
 
 _LIB = None
 
@@ -233,6 +237,15 @@ class Solver:
         st = IbStats()
         _check(self.lib.ib_get_stats(self.handle, byref(st)), "ib_get_stats")
         return {k: getattr(st, k) for k, _ in IbStats._fields_}
+
+    def set_kernel_timing(self, on=True):
+        _check(self.lib.ib_set_kernel_timing(self.handle, 1 if on else 0), "ib_set_kernel_timing")
+
+    def kernel_timing(self, cls):
+        n, ms = c_int64(), c_double()
+        _check(self.lib.ib_get_kernel_timing(self.handle, cls, byref(n), byref(ms)),
+               "ib_get_kernel_timing")
+        return n.value, ms.value
 
     def close(self):
         if self.handle:

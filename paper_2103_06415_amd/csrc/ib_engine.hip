@@ -41,7 +41,8 @@ struct HostBody {
 
 struct LevelState {
   double h = 0, alpha = 0;
-  void* s = nullptr;
+  void* s = nullptr;     // streamfunction, (n+1) rows with the ring
+  void* g = nullptr;     // circulation C^T C s at interior vertices, (n-1) rows
   void* hist = nullptr;
   void* sring = nullptr;
   void* gring[2] = {nullptr, nullptr};
@@ -61,7 +62,8 @@ struct ib_solver {
   bool fp64 = true;
   size_t es = 8;
   std::vector<LevelState> lv;
-  void* work = nullptr;
+  void* work = nullptr;   // spectral rows of s (then s-transform rows)
+  void* workg = nullptr;  // the same for the circulation
   void* work2 = nullptr;
   void* sstar = nullptr;
   void* tw = nullptr;
@@ -96,6 +98,13 @@ struct ib_solver {
   int* hflags = nullptr;  // pinned mirrors
   double* hdelta = nullptr;
   std::vector<double> ds_rows;
+  // kernel timing
+  bool timing = false;
+  struct Ev { hipEvent_t a, b; int cls; };
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> event_pool;
+  int64_t t_count[IB_K_CLASSES] = {0};
+  double t_ms[IB_K_CLASSES] = {0};
 };
 
 namespace {
@@ -159,10 +168,11 @@ ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
 
 template <typename T>
 ib_status solve_into(ib_solver* s, void* work, double alpha, double scale, int r0, int r1,
-                     const void* tw, const void* lam) {
+                     const void* tw, const void* lam, void* workg = nullptr) {
   ColArgs<T> c{};
   c.in = static_cast<T*>(work);
   c.out = static_cast<T*>(work);
+  c.out2 = static_cast<T*>(workg);
   c.pi = c.po = s->pitch;
   c.r0 = r0;
   c.r1 = r1;
@@ -193,6 +203,8 @@ ib_status init_streamfunction(ib_solver* s) {
           host[(size_t)j * P + i] = (T)(h2 * s->omega0[g][(size_t)j * (n - 1) + i]);
     }
     HIPCHK(hipMemcpyAsync(s->work, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(L.g, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice,
                           s->stream));
     if (g < G - 1)
       HIPCHK(launch_add_ring_lift<T>(static_cast<T*>(s->work), P, static_cast<T*>(L.sring), n,
@@ -292,6 +304,49 @@ int offline_slots(ib_solver* s, int ntarget) {
   if (k > 256) k = 256;
   if (k < 1) k = 1;
   return (int)k;
+}
+
+// Bracket the enclosed launches with events when timing is enabled.
+struct TimeScope {
+  ib_solver* s;
+  int cls;
+  hipEvent_t b = nullptr;
+  hipEvent_t e = nullptr;
+  hipEvent_t take() {
+    if (!s->event_pool.empty()) {
+      hipEvent_t v = s->event_pool.back();
+      s->event_pool.pop_back();
+      return v;
+    }
+    hipEvent_t v = nullptr;
+    (void)hipEventCreate(&v);
+    return v;
+  }
+  TimeScope(ib_solver* s_, int c) : s(s_), cls(c) {
+    if (!s->timing) return;
+    b = take();
+    e = take();
+    (void)hipEventRecord(b, s->stream);
+  }
+  ~TimeScope() {
+    if (!s->timing || !b) return;
+    (void)hipEventRecord(e, s->stream);
+    s->events.push_back({b, e, cls});
+  }
+};
+
+void harvest_events(ib_solver* s) {
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& ev : s->events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+      s->t_count[ev.cls] += 1;
+      s->t_ms[ev.cls] += ms;
+    }
+    s->event_pool.push_back(ev.a);
+    s->event_pool.push_back(ev.b);
+  }
+  s->events.clear();
 }
 
 template <typename T>
@@ -677,18 +732,23 @@ ib_status fsi_and_correct(ib_solver* s) {
   const int kmax = s->cfg.newton_max_iter > 0 ? s->cfg.newton_max_iter : 20;
   for (;;) {
     a.iter = it;
-    HIPCHK(launch_body_ops<T>(a, s->stream));
     if (s->stationary) {
+      TimeScope ts(s, IB_K_FSI);
+      HIPCHK(launch_body_ops<T>(a, s->stream));
       HIPCHK(launch_structure(a, 0, s->stream));
       HIPCHK(launch_matvec(s->Minv, a.pm, s->rhs, s->f, s->nf, s->stream));
       s->iters_last = 1;
       s->delta_last = 0.0;
       break;
     }
-    HIPCHK(launch_schur_sd(a, s->stream));
-    HIPCHK(launch_structure(a, 1, s->stream));
-    HIPCHK(launch_lu_solve(a.M, a.pm, s->f, 1, s->nf, 1, s->flags, s->stream));
-    HIPCHK(launch_update(a, s->stream));
+    {
+      TimeScope ts(s, IB_K_FSI);
+      HIPCHK(launch_body_ops<T>(a, s->stream));
+      HIPCHK(launch_schur_sd(a, s->stream));
+      HIPCHK(launch_structure(a, 1, s->stream));
+      HIPCHK(launch_lu_solve(a.M, a.pm, s->f, 1, s->nf, 1, s->flags, s->stream));
+      HIPCHK(launch_update(a, s->stream));
+    }
     bool done = false;
     if (fixed > 0) {
       done = it + 1 >= fixed;
@@ -727,15 +787,18 @@ ib_status fsi_and_correct(ib_solver* s) {
   }
   s->iters_max = std::max(s->iters_max, s->iters_last);
   // corrector: s_{n+1} = s* - dt K C^T E^T (ds/h) f on level 0
-  HIPCHK(launch_spread<T>(a, s->blo, s->bhi, s->bilo, s->bihi, static_cast<T*>(s->work2), P,
-                          s->stream));
-  RowArgs<T> r{};
-  r.in = static_cast<T*>(s->work2);
-  r.out = static_cast<T*>(s->work2);
-  r.pi = r.po = P;
-  r.r0 = s->blo;
-  r.r1 = s->bhi;
-  HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
+  {
+    TimeScope ts(s, IB_K_CORRECT);
+    HIPCHK(launch_spread<T>(a, s->blo, s->bhi, s->bilo, s->bihi, static_cast<T*>(s->work2), P,
+                            s->stream));
+    RowArgs<T> r{};
+    r.in = static_cast<T*>(s->work2);
+    r.out = static_cast<T*>(s->work2);
+    r.pi = r.po = P;
+    r.r0 = s->blo;
+    r.r1 = s->bhi;
+    HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
+  }
   ColArgs<T> c{};
   c.in = static_cast<T*>(s->work2);
   c.out = static_cast<T*>(s->work);
@@ -744,10 +807,14 @@ ib_status fsi_and_correct(ib_solver* s) {
   c.r1 = s->bhi;
   c.alpha = (T)L0.alpha;
   c.scale = (T)(-s->cfg.dt * 4.0 / ((double)n * n));
+  c.out2 = static_cast<T*>(s->workg);
   c.accumulate = 1;
   c.w0 = 1;
   c.w1 = n - 1;
-  HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
+  {
+    TimeScope ts(s, IB_K_COL_SOLVE);
+    HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
+  }
   return IB_OK;
 }
 
@@ -759,12 +826,15 @@ ib_status do_step(ib_solver* s) {
     LevelState& L = s->lv[g];
     const bool has_ring = g < G - 1;
     const int nxt = 1 - L.gcur;
-    if (has_ring)
+    if (has_ring) {
+      TimeScope ts(s, IB_K_RING);
       HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
                             static_cast<T*>(L.gring[nxt]), s->stream));
+    }
     RhsArgs<T> a{};
     a.s = static_cast<T*>(L.s);
-    a.sf = g > 0 ? static_cast<T*>(s->lv[g - 1].s) : nullptr;
+    a.g = static_cast<T*>(L.g);
+    a.gf = g > 0 ? static_cast<T*>(s->lv[g - 1].g) : nullptr;
     a.gring = static_cast<T*>(L.gring[L.gcur]);
     a.sring_new = has_ring ? static_cast<T*>(L.sring) : nullptr;
     a.gring_new = has_ring ? static_cast<T*>(L.gring[nxt]) : nullptr;
@@ -772,14 +842,22 @@ ib_status do_step(ib_solver* s) {
     a.hist_out = static_cast<T*>(L.hist);
     a.out = static_cast<T*>(s->work);
     a.n = n;
-    a.ps = a.psf = a.ph = a.po = P;
+    a.ps = a.pg = a.pgf = a.ph = a.po = P;
     a.alpha = (T)L.alpha;
     a.dt = (T)s->cfg.dt;
     a.ux = (T)(s->cfg.u_inf[0] * L.h);
     a.uy = (T)(s->cfg.u_inf[1] * L.h);
     a.cn = (T)(-1.0 / (2.0 * L.h * L.h));
-    HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
-    ib_status st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam);
+    {
+      TimeScope ts(s, IB_K_RHS_ROWDST);
+      HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
+    }
+    ib_status st;
+    {
+      TimeScope ts(s, IB_K_COL_SOLVE);
+      st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
+                         s->workg);
+    }
     if (st) return st;
     RowArgs<T> r{};
     r.in = static_cast<T*>(s->work);
@@ -790,14 +868,29 @@ ib_status do_step(ib_solver* s) {
       r.out = static_cast<T*>(s->sstar);
       r.r0 = std::max(1, s->blo - 3);
       r.r1 = std::min(n - 1, s->bhi + 3);
-      HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 0, s->stream));
+      {
+        TimeScope ts(s, IB_K_ROW_IDST);
+        HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 0, s->stream));
+      }
       st = fsi_and_correct<T>(s);
       if (st) return st;
     }
     r.out = static_cast<T*>(L.s);
     r.r0 = 1;
     r.r1 = n - 1;
-    HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
+    RowArgs<T> rg = r;
+    rg.in = static_cast<T*>(s->workg);
+    rg.out = static_cast<T*>(L.g);
+    rg.interior_out = 1;
+    rg.ring_sub = ring;
+    {
+      TimeScope ts(s, IB_K_ROW_IDST);
+      HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
+    }
+    {
+      TimeScope ts(s, IB_K_ROW_IDST);
+      HIPCHK(launch_row_idst<T>(rg, n, 1, s->tw, nullptr, 0, s->stream));
+    }
     if (has_ring) L.gcur = nxt;
   }
   s->first = false;
@@ -864,6 +957,8 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
     L.h = cfg->h * std::ldexp(1.0, g);
     L.alpha = cfg->dt / (2.0 * cfg->re * L.h * L.h);
     L.s = dalloc(s, full);
+    L.g = dalloc(s, inner);
+    if (!L.g) st = IB_ERR_OOM;
     L.hist = dalloc(s, inner);
     L.sring = dalloc(s, ring);
     L.gring[0] = dalloc(s, ring);
@@ -872,9 +967,10 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
     s->lv.push_back(L);
   }
   s->work = dalloc(s, inner);
+  s->workg = dalloc(s, inner);
   s->work2 = dalloc(s, inner);
   s->sstar = dalloc(s, full);
-  if (!s->work || !s->work2 || !s->sstar) st = IB_ERR_OOM;
+  if (!s->work || !s->workg || !s->work2 || !s->sstar) st = IB_ERR_OOM;
   if (st == IB_OK) {
     st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
                  : make_tables<float>(s, s->n, &s->tw, &s->lam);
@@ -883,6 +979,7 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   if (st == IB_OK) {
     for (auto& L : s->lv) {
       if (hipMemset(L.s, 0, full) != hipSuccess || hipMemset(L.hist, 0, inner) != hipSuccess ||
+          hipMemset(L.g, 0, inner) != hipSuccess ||
           hipMemset(L.sring, 0, ring) != hipSuccess || hipMemset(L.gring[0], 0, ring) != hipSuccess ||
           hipMemset(L.gring[1], 0, ring) != hipSuccess)
         st = IB_ERR_HIP;
@@ -1065,16 +1162,17 @@ ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t ca
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
   const int n = s->n;
   if (cap < (int64_t)(n - 1) * (n - 1)) return IB_ERR_CAPACITY;
-  std::vector<double> sf((size_t)(n + 1) * (n + 1));
-  ib_status st = ib_read_streamfunction(s, level, sf.data(), (int64_t)sf.size());
-  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  std::vector<char> buf((size_t)(n - 1) * s->pitch * s->es);
+  HIPCHK(hipMemcpy(buf.data(), s->lv[level].g, buf.size(), hipMemcpyDeviceToHost));
   const double h = s->lv[level].h;
   const double inv = 1.0 / (h * h);
-  for (int j = 1; j < n; ++j)
-    for (int i = 1; i < n; ++i) {
-      const size_t c = (size_t)j * (n + 1) + i;
-      const double l = 4.0 * sf[c] - sf[c + 1] - sf[c - 1] - sf[c + n + 1] - sf[c - n - 1];
-      out[(size_t)(j - 1) * (n - 1) + (i - 1)] = l * inv;
+  for (int j = 0; j < n - 1; ++j)
+    for (int i = 0; i < n - 1; ++i) {
+      const size_t k = (size_t)j * s->pitch + i;
+      const double g = s->fp64 ? reinterpret_cast<double*>(buf.data())[k]
+                               : reinterpret_cast<float*>(buf.data())[k];
+      out[(size_t)j * (n - 1) + i] = g * inv;
     }
   return IB_OK;
 }
@@ -1092,9 +1190,33 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   return IB_OK;
 }
 
+ib_status ib_set_kernel_timing(ib_solver* s, int32_t enable) {
+  if (check(s)) return IB_ERR_ARG;
+  harvest_events(s);
+  s->timing = enable != 0;
+  for (int k = 0; k < IB_K_CLASSES; ++k) {
+    s->t_count[k] = 0;
+    s->t_ms[k] = 0.0;
+  }
+  return IB_OK;
+}
+
+ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* launches,
+                               double* total_ms) {
+  if (check(s) || kernel_class < 0 || kernel_class >= IB_K_CLASSES || !launches || !total_ms)
+    return IB_ERR_ARG;
+  harvest_events(s);
+  *launches = s->t_count[kernel_class];
+  *total_ms = s->t_ms[kernel_class];
+  return IB_OK;
+}
+
 ib_status ib_destroy(ib_solver* s) {
   if (!s) return IB_ERR_ARG;
   (void)hipStreamSynchronize(s->stream);
+  harvest_events(s);
+  for (auto e : s->event_pool) (void)hipEventDestroy(e);
+  s->event_pool.clear();
   while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->hdelta) (void)hipHostFree(s->hdelta);

@@ -8,6 +8,9 @@
 // L = C^T C (5-point), a = dt / (2 Re h_g^2), B(.) = ring values adjacent to an
 // interior vertex.  (I + a L) L is diagonal in the 2-D DST-I basis (Sec. 3.2.1), so
 // the solve is row DST -> column DST, scale, inverse column DST -> inverse row DST.
+// The circulation gamma_{n+1} = C^T C s_{n+1} is produced from the same spectral
+// data (gamma^ = rhs^ / (1 + a lam), minus the lifted ring) instead of by differencing
+// s, which would lose about log10((n/pi)^2) digits in single precision.
 #include "ib_internal.hpp"
 #include "ib_fft.hpp"
 
@@ -25,19 +28,13 @@ __device__ __forceinline__ T gamma_at(const RhsArgs<T>& a, int i, int j) {
   if (j == n) return a.gring[RING_T * (n + 1) + i];
   if (i == 0) return a.gring[RING_L * (n + 1) + j];
   if (i == n) return a.gring[RING_R * (n + 1) + j];
-  if (a.sf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
-    // coarsification on read: the finer level's circulation at the coincident vertex
+  if (a.gf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
+    // coarsification on read: the finer level's circulation at the coincident vertex,
+    // scaled by (h_coarse / h_fine)^2 = 4
     const int fi = 2 * i - n / 2, fj = 2 * j - n / 2;
-    const T* f = a.sf;
-    const int p = a.psf;
-    T l = T(4) * ld(f, p, fj, fi) - ld(f, p, fj, fi + 1) - ld(f, p, fj, fi - 1) -
-          ld(f, p, fj + 1, fi) - ld(f, p, fj - 1, fi);
-    return T(4) * l;
+    return T(4) * a.gf[(size_t)(fj - 1) * a.pgf + (fi - 1)];
   }
-  const T* s = a.s;
-  const int p = a.ps;
-  return T(4) * ld(s, p, j, i) - ld(s, p, j, i + 1) - ld(s, p, j, i - 1) - ld(s, p, j + 1, i) -
-         ld(s, p, j - 1, i);
+  return a.g[(size_t)(j - 1) * a.pg + (i - 1)];
 }
 
 // Sum of the new boundary-ring values adjacent to interior vertex (i, j).
@@ -181,49 +178,58 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   fft_lds<T, N, CW, NT>(buf, tw, tid);
   constexpr int NP = CW * (N / 2);
   constexpr int PER = (NP + NT - 1) / NT;
-  T xa[PER], xb[PER];
+  T xa[PER], xb[PER];   // forward column transform, raw
+  T da[PER], db[PER];   // lam (1 + alpha lam) and 1 + alpha lam of each pair
+  T ea[PER], eb[PER];
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int e = tid + b * NT;
     if (e < NP) {
       const int c = e % CW, l = 1 + e / CW;
       const int col = k0 + c;
-      T xk, xnk;
-      dst_unpack<T, N>(buf + c * N, tw, l, xk, xnk);
+      dst_unpack<T, N>(buf + c * N, tw, l, xa[b], xb[b]);
       const T lk = (col < N - 1) ? lam[col] : T(1);
-      T l1 = lk + lam[l - 1];
-      T l2 = lk + lam[N - l - 1];
-      xa[b] = xk * (a.scale / (l1 * (T(1) + a.alpha * l1)));
-      xb[b] = xnk * (a.scale / (l2 * (T(1) + a.alpha * l2)));
+      const T l1 = lk + lam[l - 1];
+      const T l2 = lk + lam[N - l - 1];
+      ea[b] = T(1) + a.alpha * l1;
+      eb[b] = T(1) + a.alpha * l2;
+      da[b] = l1 * ea[b];
+      db[b] = l2 * eb[b];
     }
   }
-  __syncthreads();
+  const int nout = a.out2 != nullptr ? 2 : 1;
+  for (int o = 0; o < nout; ++o) {
+    T* dst = (o == 0 ? a.out : a.out2) + (size_t)blockIdx.y * a.bso;
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < PER; ++b) {
-    const int e = tid + b * NT;
-    if (e < NP) {
-      const int c = e % CW, l = 1 + e / CW;
-      dst_pack<T, N>(buf + c * N, l, xa[b]);
-      if (l != N / 2) dst_pack<T, N>(buf + c * N, N - l, xb[b]);
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < NP) {
+        const int c = e % CW, l = 1 + e / CW;
+        const T va = o == 0 ? xa[b] * (a.scale / da[b]) : xa[b] * (a.scale / ea[b]);
+        const T vb = o == 0 ? xb[b] * (a.scale / db[b]) : xb[b] * (a.scale / eb[b]);
+        dst_pack<T, N>(buf + c * N, l, va);
+        if (l != N / 2) dst_pack<T, N>(buf + c * N, N - l, vb);
+      }
     }
-  }
-  for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
-  __syncthreads();
-  fft_lds<T, N, CW, NT>(buf, tw, tid);
-  for (int e = tid; e < NP; e += NT) {
-    const int c = e % CW, j = 1 + e / CW;
-    const int col = k0 + c;
-    if (col >= N - 1) continue;
-    T yk, ynk;
-    dst_unpack<T, N>(buf + c * N, tw, j, yk, ynk);
-    if (j >= a.w0 && j <= a.w1) {
-      T* o1 = out + (size_t)(j - 1) * a.po + col;
-      *o1 = a.accumulate ? *o1 + yk : yk;
-    }
-    const int j2 = N - j;
-    if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) {
-      T* o2 = out + (size_t)(j2 - 1) * a.po + col;
-      *o2 = a.accumulate ? *o2 + ynk : ynk;
+    for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
+    __syncthreads();
+    fft_lds<T, N, CW, NT>(buf, tw, tid);
+    for (int e = tid; e < NP; e += NT) {
+      const int c = e % CW, j = 1 + e / CW;
+      const int col = k0 + c;
+      if (col >= N - 1) continue;
+      T yk, ynk;
+      dst_unpack<T, N>(buf + c * N, tw, j, yk, ynk);
+      if (j >= a.w0 && j <= a.w1) {
+        T* o1 = dst + (size_t)(j - 1) * a.po + col;
+        *o1 = a.accumulate ? *o1 + yk : yk;
+      }
+      const int j2 = N - j;
+      if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) {
+        T* o2 = dst + (size_t)(j2 - 1) * a.po + col;
+        *o2 = a.accumulate ? *o2 + ynk : ynk;
+      }
     }
   }
 }
@@ -260,6 +266,10 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
     dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
     if (a.interior_out) {
       T* o = out + (size_t)(j - 1) * a.po;
+      if (a.ring_sub != nullptr) {
+        xk -= ring_adj(a.ring_sub, N, k, j);
+        if (k != N / 2) xnk -= ring_adj(a.ring_sub, N, N - k, j);
+      }
       o[k - 1] = xk;
       if (k != N / 2) o[N - k - 1] = xnk;
     } else {

@@ -8,15 +8,16 @@ namespace ib {
 // Explicit right-hand side of one level (see ib_flow.hip).
 template <typename T>
 struct RhsArgs {
-  const T* s;          // state at time n, (n+1) rows x ps, ring included
-  const T* sf;         // finer level's state at time n (coarsification on read), or null
+  const T* s;          // streamfunction at time n, (n+1) rows x ps, ring included
+  const T* g;          // circulation gamma = C^T C s at time n, interior, (n-1) rows x pg
+  const T* gf;         // finer level's circulation at time n (coarsification on read), or null
   const T* gring;      // ring circulation at time n, [4][n+1]
   const T* sring_new;  // new streamfunction ring [4][n+1], or null (zero ring)
   const T* gring_new;  // new circulation ring [4][n+1] (used with sring_new)
   const T* hist_in;    // C^T N_{n-1}, (n-1) rows x ph, or null on the first step
   T* hist_out;         // C^T N_n (may alias hist_in)
   T* out;              // row-transformed right-hand side, (n-1) rows x po
-  int n, ps, psf, ph, po;
+  int n, ps, pg, pgf, ph, po;
   T alpha, dt, ux, uy, cn;  // cn = -1 / (2 h^2); ux, uy = free-stream flux u_inf h
 };
 
@@ -30,6 +31,7 @@ struct RowArgs {
   size_t bsi, bso;  // batch strides (elements)
   int interior_out; // inverse transform: write an (n-1)-row interior array instead of a
                     // full (n+1)-row array with its ring
+  const T* ring_sub;// interior output: subtract the adjacent values of this ring
 };
 
 // Column transform + spectral scale + inverse column transform.
@@ -39,7 +41,8 @@ struct ColArgs {
   T* out;
   int pi, po;
   int r0, r1;        // nonzero input rows (1-based interior rows)
-  T alpha, scale;    // multiplier scale / (lam (1 + alpha lam))
+  T alpha, scale;    // multiplier scale / (lam (1 + alpha lam)) for `out` and
+  T* out2;           //   scale / (1 + alpha lam) for `out2` (if set; pitch po, stride bso)
   int accumulate;    // out += result instead of out = result
   size_t bsi, bso;
   const int* rfirst; // if set: slot b's input holds rows rfirst[b] .. rfirst[b] + rcount - 1
