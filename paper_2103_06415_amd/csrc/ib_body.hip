@@ -272,20 +272,6 @@ __device__ void beam_element(const double* x, double l0, double beta0, double ea
     }
 }
 
-// Band LU (half-bandwidth 5, no pivoting: J_d is dominated by its mass term) of an
-// nd system stored as band[u * 11 + (v - u + 5)]; one thread.
-__device__ void band_factor(double* band, int nd) {
-  for (int k = 0; k < nd; ++k) {
-    const double piv = band[k * 11 + 5];
-    const int hi = k + 5 > nd - 1 ? nd - 1 : k + 5;
-    for (int i = k + 1; i <= hi; ++i) {
-      const double l = band[i * 11 + (k - i + 5)] / piv;
-      band[i * 11 + (k - i + 5)] = l;
-      for (int j = k + 1; j <= hi; ++j) band[i * 11 + (j - i + 5)] -= l * band[k * 11 + (j - k + 5)];
-    }
-  }
-}
-
 // Forward and back substitution with a sliding register window; x is read through
 // `in(u)` and the result written to out[u * stride].
 template <typename F>
@@ -401,7 +387,30 @@ __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_
         res[g] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint[g];
       }
       __syncthreads();
-      if (tid == 0) band_factor(band, nd);
+      // band LU without pivoting by one wave: lane (p, q) updates entry (k+1+p, k+1+q)
+      // of the trailing 5 x 5 block; LDS operations of one wave complete in order
+      if (tid < 64) {
+        const int p = tid / 5, q = tid % 5;
+        for (int k = 0; k < nd; ++k) {
+          const double piv = band[k * 11 + 5];
+          const int i = k + 1 + p, j = k + 1 + q;
+          const bool act = tid < 25 && i < nd && j < nd;
+          double l = 0.0, u = 0.0, aij = 0.0;
+          if (act) {
+            l = band[i * 11 + (k - i + 5)] / piv;
+            u = band[k * 11 + (j - k + 5)];
+            aij = band[i * 11 + (j - i + 5)];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          if (act) {
+            band[i * 11 + (j - i + 5)] = aij - l * u;
+            if (q == 0) band[i * 11 + (k - i + 5)] = l;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
       __syncthreads();
       double* lu = a.band + (size_t)b.band0 * 11;
       for (int e = tid; e < nd * 11; e += STRUCT_NT) lu[e] = band[e];
@@ -567,28 +576,19 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
         ts[TS_NEW] = thn;
       }
     } else if (b.kind == BODY_DEFORMABLE) {
-      __shared__ double band[MAX_BEAM_DOF * 11];
-      const int nd = 3 * m - 3;
-      const double* lu = a.band + (size_t)b.band0 * 11;
-      for (int e = tid; e < nd * 11; e += STRUCT_NT) band[e] = lu[e];
-      __syncthreads();
+      // delta chi = J_d^{-1} (res + ds T^T f) = y_res + ds Y f with Y = J_d^{-1} T^T
+      const int nd = 3 * m - 3, ncol = 2 * m + 1;
+      const double* y = a.ywork + b.yoff;
+      const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
+      double* cn = a.chi_new + b.dof0;
+      for (int u = tid; u < nd; u += STRUCT_NT) {
+        double acc = 0.0;
+        for (int c = 0; c < 2 * m; ++c) acc += y[(size_t)u * ncol + c] * a.f[r0 + c];
+        const double dx = y[(size_t)u * ncol + 2 * m] + b.ds * acc;
+        my = fmax(my, fabs(dx));
+        cn[u + 3] = ck[u + 3] + dx;  // ck may alias cn: same thread reads then writes
+      }
       if (tid == 0) {
-        const double* res = a.dres + b.dof0;
-        double* xw = a.ywork + b.yoff;  // column 0 of J_d^{-1} T^T reused as scratch
-        band_solve(band, nd, [&](int u) {
-          const int node = (u + 3) / 3, cmp = (u + 3) % 3;
-          double v = res[u + 3];
-          if (cmp < 2) v += b.ds * a.f[r0 + cmp * m + node];
-          return v;
-        }, xw, 2 * m + 1);
-        const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
-        double* cn = a.chi_new + b.dof0;
-        // ck may alias cn: each DOF is read before it is written
-        for (int u = 0; u < nd; ++u) {
-          const double dx = xw[(size_t)u * (2 * m + 1)];
-          my = fmax(my, fabs(dx));
-          cn[u + 3] = ck[u + 3] + dx;
-        }
         cn[0] = ck[0];
         cn[1] = ck[1];
         cn[2] = ck[2];
@@ -800,7 +800,140 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
   if (threadIdx.x == 0) counts[b] = base_s;
 }
 
+// ------------------------------------------------- Schur solve by refinement
+// The Schur matrix changes little between FSI iterations and between steps, so the
+// solve keeps X ~ M^{-1}: refreshed once per step by one Newton-Schulz iteration
+// X <- X (2I - M X) (two GEMMs), then f = X b corrected by iterative refinement
+// f <- f + X (b - M f) to working accuracy.  A fresh inverse (LU) is made at the
+// first use and whenever the refinement stops contracting.
+
+constexpr int REF_NT = 1024;
+constexpr int REF_MAXN = 4096;
+
+// y = A x for one workgroup; x in LDS, one wave per row.
+__device__ void wg_matvec(const double* A, int pa, const double* x, double* y, int n) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = w; r < n; r += REF_NT / 64) {
+    const double* row = A + (size_t)r * pa;
+    double acc = 0.0;
+    for (int c = lane; c < n; c += 64) acc += row[c] * x[c];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if (lane == 0) y[r] = acc;
+  }
+}
+
+__device__ double wg_absmax(const double* v, int n, double* red) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += REF_NT) m = fmax(m, fabs(v[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double r = 0.0;
+  for (int k = 0; k < REF_NT / 64; ++k) r = fmax(r, red[k]);
+  __syncthreads();
+  return r;
+}
+
+// info[0] = final relative residual, info[1] = refinement iterations
+__global__ __launch_bounds__(REF_NT) void k_solve_refine(const double* M, int pm, const double* X,
+                                                         const double* b, double* f, int n,
+                                                         int maxit, double* info, int* flags) {
+  __shared__ double sb[REF_MAXN], sf[REF_MAXN], sr[REF_MAXN];
+  __shared__ double red[REF_NT / 64];
+  for (int i = threadIdx.x; i < n; i += REF_NT) sb[i] = b[i];
+  __syncthreads();
+  wg_matvec(X, pm, sb, sf, n);
+  __syncthreads();
+  const double nb = wg_absmax(sb, n, red);
+  double prev = 1e300, rel = 0.0;
+  int it = 0;
+  for (; it < maxit; ++it) {
+    wg_matvec(M, pm, sf, sr, n);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += REF_NT) sr[i] = sb[i] - sr[i];
+    __syncthreads();
+    const double nr = wg_absmax(sr, n, red);
+    rel = nb > 0.0 ? nr / nb : 0.0;
+    if (!(rel > 1e-16 * n) || !(nr < 0.5 * prev)) break;  // converged or no longer contracting
+    prev = nr;
+    // sf += X sr  (through the scratch vector sb2 = X sr written into sr's partner)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int r = w; r < n; r += REF_NT / 64) {
+      const double* row = X + (size_t)r * pm;
+      double acc = 0.0;
+      for (int c = lane; c < n; c += 64) acc += row[c] * sr[c];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+      if (lane == 0) sf[r] += acc;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += REF_NT) f[i] = sf[i];
+  if (threadIdx.x == 0) {
+    info[0] = rel;
+    info[1] = it;
+    if (!(rel < 1e-9)) atomicMax(&flags[1], 1);  // refinement failed: the inverse is stale
+  }
+}
+
+// C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B.  32 x 32 tiles.
+__global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
+                                                int p, int two_minus) {
+  __shared__ double ta[32][33], tb[32][33];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int k0 = 0; k0 < n; k0 += 32) {
+    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+      const int rr = e / 32, cc = e % 32;
+      ta[rr][cc] = (r0 + rr < n && k0 + cc < n) ? A[(size_t)(r0 + rr) * p + k0 + cc] : 0.0;
+      tb[rr][cc] = (k0 + rr < n && c0 + cc < n) ? B[(size_t)(k0 + rr) * p + c0 + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 32; ++kk) {
+      const double a0 = ta[ty * 2][kk], a1 = ta[ty * 2 + 1][kk];
+      const double b0 = tb[kk][tx * 2], b1 = tb[kk][tx * 2 + 1];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const int r = r0 + ty * 2 + u, c = c0 + tx * 2 + v;
+      if (r < n && c < n) {
+        double val = acc[u][v];
+        if (two_minus) val = (r == c ? 2.0 : 0.0) - val;
+        C[(size_t)r * p + c] = val;
+      }
+    }
+}
+
+__global__ void k_identity(double* X, int p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[(size_t)i * p + i] = 1.0;
+}
+
 // ----------------------------------------------------------------- launchers
+hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_identity, dim3((n + 255) / 256), dim3(256), 0, st, X, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
+                               int n, int maxit, double* info, int* flags, hipStream_t st) {
+  if (n > REF_MAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_solve_refine, dim3(1), dim3(REF_NT), 0, st, M, pm, X, b, f, n, maxit, info, flags);
+  return hipGetLastError();
+}
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
+                         hipStream_t st) {
+  const int nb = (n + 31) / 32;
+  hipLaunchKernelGGL(k_gemm64, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus);
+  return hipGetLastError();
+}
+
 
 template <typename T>
 hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st) {

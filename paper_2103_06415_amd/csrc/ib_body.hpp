@@ -70,7 +70,7 @@ struct FsiArgs {
   double* band;        // band LU factors, 11 per DOF
   double* dres;        // residual per DOF
   double* ywork;       // J_d^{-1} T^T, per deformable body: (3m) x (2m)
-  int* flags;          // [0] error code, [1] reserved
+  int* flags;          // [0] error code, [1] refinement failure
   double* delta;       // [0] max |delta| of the last update
 };
 
@@ -110,5 +110,10 @@ hipError_t launch_gather_batch(const int* cols, const double* vals, int ntarget,
 hipError_t launch_scale_cols(double* M, int pm, int n, const double* colscale, double s,
                              hipStream_t st);
 hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
+hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
+                               int n, int maxit, double* info, int* flags, hipStream_t st);
+hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
+                         hipStream_t st);
 
 }  // namespace ib

@@ -65,6 +65,7 @@ struct ib_solver {
   void* work = nullptr;   // spectral rows of s (then s-transform rows)
   void* workg = nullptr;  // the same for the circulation
   void* work2 = nullptr;
+  void* lift = nullptr;   // edge transforms of a new streamfunction ring, [4][n-1]
   void* sstar = nullptr;
   void* tw = nullptr;
   void* lam = nullptr;
@@ -92,7 +93,14 @@ struct ib_solver {
   FsiArgs fa{};
   double* f = nullptr;
   double* rhs = nullptr;
-  double* Minv = nullptr;
+  double* Minv = nullptr;   // stationary: exact inverse; moving: approximate inverse X
+  double* Xn = nullptr;     // Newton-Schulz workspace
+  double* W = nullptr;
+  double* Mtmp = nullptr;
+  double* rinfo = nullptr;  // refinement info (device)
+  double* hrinfo = nullptr; // pinned mirror
+  bool x_valid = false;
+  bool x_valid_retry = false;
   int* flags = nullptr;
   double* delta = nullptr;
   int* hflags = nullptr;  // pinned mirrors
@@ -168,11 +176,13 @@ ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
 
 template <typename T>
 ib_status solve_into(ib_solver* s, void* work, double alpha, double scale, int r0, int r1,
-                     const void* tw, const void* lam, void* workg = nullptr) {
+                     const void* tw, const void* lam, void* workg = nullptr,
+                     const void* lift = nullptr) {
   ColArgs<T> c{};
   c.in = static_cast<T*>(work);
   c.out = static_cast<T*>(work);
   c.out2 = static_cast<T*>(workg);
+  c.lift = static_cast<const T*>(lift);
   c.pi = c.po = s->pitch;
   c.r0 = r0;
   c.r1 = r1;
@@ -207,7 +217,7 @@ ib_status init_streamfunction(ib_solver* s) {
     HIPCHK(hipMemcpyAsync(L.g, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice,
                           s->stream));
     if (g < G - 1)
-      HIPCHK(launch_add_ring_lift<T>(static_cast<T*>(s->work), P, static_cast<T*>(L.sring), n,
+      HIPCHK(launch_ring_edge_dst<T>(static_cast<T*>(L.sring), n, s->tw, static_cast<T*>(s->lift),
                                      s->stream));
     RowArgs<T> r{};
     r.in = static_cast<T*>(s->work);
@@ -216,7 +226,8 @@ ib_status init_streamfunction(ib_solver* s) {
     r.r0 = 1;
     r.r1 = n - 1;
     HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
-    ib_status st = solve_into<T>(s, s->work, 0.0, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam);
+    ib_status st = solve_into<T>(s, s->work, 0.0, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
+                                 nullptr, g < G - 1 ? s->lift : nullptr);
     if (st) return st;
     RowArgs<T> q = r;
     q.out = static_cast<T*>(L.s);
@@ -558,9 +569,20 @@ ib_status prepare_bodies(ib_solver* s) {
   s->f = static_cast<double*>(dalloc(s, (size_t)nf * 8));
   s->rhs = static_cast<double*>(dalloc(s, (size_t)nf * 8));
   a.f = s->f;
-  a.rhs = s->stationary ? s->rhs : s->f;
+  a.rhs = s->rhs;
   a.pm = round_up(nf, 8);
   a.M = static_cast<double*>(dalloc(s, (size_t)nf * a.pm * 8 + 8));
+  if (!s->stationary) {
+    const size_t mb = (size_t)nf * a.pm * 8 + 8;
+    s->Minv = static_cast<double*>(dalloc(s, mb));
+    s->Xn = static_cast<double*>(dalloc(s, mb));
+    s->W = static_cast<double*>(dalloc(s, mb));
+    s->Mtmp = static_cast<double*>(dalloc(s, mb));
+    s->rinfo = static_cast<double*>(dalloc(s, 16));
+    if (!s->Minv || !s->Xn || !s->W || !s->Mtmp || !s->rinfo) return IB_ERR_OOM;
+    if (!s->hrinfo) HIPCHK(hipHostMalloc((void**)&s->hrinfo, 16, hipHostMallocDefault));
+    s->x_valid = false;
+  }
   a.tors = up(tors);
   a.chi = up(chi);
   a.zeta = up(std::vector<double>(chi.size(), 0.0));
@@ -746,7 +768,23 @@ ib_status fsi_and_correct(ib_solver* s) {
       HIPCHK(launch_body_ops<T>(a, s->stream));
       HIPCHK(launch_schur_sd(a, s->stream));
       HIPCHK(launch_structure(a, 1, s->stream));
-      HIPCHK(launch_lu_solve(a.M, a.pm, s->f, 1, s->nf, 1, s->flags, s->stream));
+      const int nf = s->nf;
+      const size_t mb = (size_t)nf * a.pm * 8;
+      if (!s->x_valid) {
+        // fresh inverse of the current Schur matrix by LU on a copy
+        HIPCHK(hipMemcpyAsync(s->Mtmp, a.M, mb, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemsetAsync(s->Minv, 0, mb, s->stream));
+        HIPCHK(launch_identity(s->Minv, a.pm, nf, s->stream));
+        HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
+        s->x_valid = true;
+      } else if (it == 0) {
+        // one Newton-Schulz step towards the new matrix: X <- X (2I - M X)
+        HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream));
+        HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream));
+        std::swap(s->Minv, s->Xn);
+      }
+      HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, 12, s->rinfo, s->flags,
+                                 s->stream));
       HIPCHK(launch_update(a, s->stream));
     }
     bool done = false;
@@ -756,6 +794,10 @@ ib_status fsi_and_correct(ib_solver* s) {
         HIPCHK(hipMemcpyAsync(s->hflags, s->flags, 8, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipMemcpyAsync(s->hdelta, s->delta, 8, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
+        if (s->hflags[1]) {
+          s->last_error = "Schur refinement did not converge";
+          return IB_ERR_NONFINITE;
+        }
       }
     } else {
       HIPCHK(hipMemcpyAsync(s->hflags, s->flags, 8, hipMemcpyDeviceToHost, s->stream));
@@ -763,6 +805,18 @@ ib_status fsi_and_correct(ib_solver* s) {
       HIPCHK(hipStreamSynchronize(s->stream));
       ib_status st = map_flags(s, s->hflags[0]);
       if (st) return st;
+      if (s->hflags[1]) {
+        // the approximate inverse no longer contracts: rebuild it and redo this iteration
+        if (!s->x_valid_retry) {
+          s->x_valid = false;
+          s->x_valid_retry = true;
+          HIPCHK(hipMemsetAsync(s->flags + 1, 0, 4, s->stream));
+          continue;
+        }
+        s->last_error = "Schur refinement did not converge";
+        return IB_ERR_NONFINITE;
+      }
+      s->x_valid_retry = false;
       if (!std::isfinite(s->hdelta[0])) {
         s->last_error = "non-finite structure update";
         return IB_ERR_NONFINITE;
@@ -830,13 +884,14 @@ ib_status do_step(ib_solver* s) {
       TimeScope ts(s, IB_K_RING);
       HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
                             static_cast<T*>(L.gring[nxt]), s->stream));
+      HIPCHK(launch_ring_edge_dst<T>(static_cast<T*>(L.sring), n, s->tw, static_cast<T*>(s->lift),
+                                     s->stream));
     }
     RhsArgs<T> a{};
     a.s = static_cast<T*>(L.s);
     a.g = static_cast<T*>(L.g);
     a.gf = g > 0 ? static_cast<T*>(s->lv[g - 1].g) : nullptr;
     a.gring = static_cast<T*>(L.gring[L.gcur]);
-    a.sring_new = has_ring ? static_cast<T*>(L.sring) : nullptr;
     a.gring_new = has_ring ? static_cast<T*>(L.gring[nxt]) : nullptr;
     a.hist_in = s->first ? nullptr : static_cast<T*>(L.hist);
     a.hist_out = static_cast<T*>(L.hist);
@@ -856,7 +911,7 @@ ib_status do_step(ib_solver* s) {
     {
       TimeScope ts(s, IB_K_COL_SOLVE);
       st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
-                         s->workg);
+                         s->workg, has_ring ? s->lift : nullptr);
     }
     if (st) return st;
     RowArgs<T> r{};
@@ -882,7 +937,6 @@ ib_status do_step(ib_solver* s) {
     rg.in = static_cast<T*>(s->workg);
     rg.out = static_cast<T*>(L.g);
     rg.interior_out = 1;
-    rg.ring_sub = ring;
     {
       TimeScope ts(s, IB_K_ROW_IDST);
       HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
@@ -969,8 +1023,9 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   s->work = dalloc(s, inner);
   s->workg = dalloc(s, inner);
   s->work2 = dalloc(s, inner);
+  s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
   s->sstar = dalloc(s, full);
-  if (!s->work || !s->workg || !s->work2 || !s->sstar) st = IB_ERR_OOM;
+  if (!s->work || !s->workg || !s->work2 || !s->sstar || !s->lift) st = IB_ERR_OOM;
   if (st == IB_OK) {
     st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
                  : make_tables<float>(s, s->n, &s->tw, &s->lam);

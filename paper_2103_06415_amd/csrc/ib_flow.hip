@@ -2,15 +2,18 @@
 // transform, the column transform + spectral solve, the inverse row transform, the
 // nested-level boundary rings, and a plain row transform for sparse sources.
 //
-// Per level g the predictor solves (Sec. 2.3 eq. (16), Appendix A r^f):
+// Per level g the predictor solves (Sec. 2.3 eq. (16), Appendix A r^f)
 //   (I + a L) L s_{n+1} = gamma_n - a L gamma_n + dt (3/2 C^T N_n - 1/2 C^T N_{n-1})
 //                         + a B(gamma_ring_{n+1}) + (I + a L) B(s_ring_{n+1}),
 // L = C^T C (5-point), a = dt / (2 Re h_g^2), B(.) = ring values adjacent to an
 // interior vertex.  (I + a L) L is diagonal in the 2-D DST-I basis (Sec. 3.2.1), so
 // the solve is row DST -> column DST, scale, inverse column DST -> inverse row DST.
-// The circulation gamma_{n+1} = C^T C s_{n+1} is produced from the same spectral
-// data (gamma^ = rhs^ / (1 + a lam), minus the lifted ring) instead of by differencing
-// s, which would lose about log10((n/pi)^2) digits in single precision.
+// It is split into its two factors, both formed from one spectral right-hand side:
+//   gamma_{n+1} = (I + a L)^{-1} [rhs without the s ring]           (gamma^ = r^/(1 + a lam))
+//   s_{n+1}     = L^{-1} [gamma_{n+1} + B(s_ring_{n+1})]            (s^ = (gamma^ + B^)/lam)
+// so the circulation state never passes through the large streamfunction values
+// (differencing s would lose about log10((n/pi)^2) digits in single precision), and
+// B(s_ring)^ is a sum of four outer products of 1-D edge transforms.
 #include "ib_internal.hpp"
 #include "ib_fft.hpp"
 
@@ -68,18 +71,7 @@ __device__ __forceinline__ T rhs_point(const RhsArgs<T>& a, int i, int j) {
   a.hist_out[hidx] = ctn;
   const T lap = T(4) * g0 - gE - gW - gN - gS;
   T r = g0 - a.alpha * lap + a.dt * (T(1.5) * ctn - T(0.5) * hprev);
-  if (a.sring_new != nullptr) {
-    const int n = a.n;
-    const T* sr = a.sring_new;
-    T bs = ring_adj(sr, n, i, j);
-    T nb = T(0);
-    if (i + 1 <= n - 1) nb += ring_adj(sr, n, i + 1, j);
-    if (i - 1 >= 1) nb += ring_adj(sr, n, i - 1, j);
-    if (j + 1 <= n - 1) nb += ring_adj(sr, n, i, j + 1);
-    if (j - 1 >= 1) nb += ring_adj(sr, n, i, j - 1);
-    T bg = ring_adj(a.gring_new, n, i, j);
-    r = r + a.alpha * bg + bs + a.alpha * (T(4) * bs - nb);
-  }
+  if (a.gring_new != nullptr) r += a.alpha * ring_adj(a.gring_new, a.n, i, j);
   return r;
 }
 
@@ -179,8 +171,9 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   constexpr int NP = CW * (N / 2);
   constexpr int PER = (NP + NT - 1) / NT;
   T xa[PER], xb[PER];   // forward column transform, raw
-  T da[PER], db[PER];   // lam (1 + alpha lam) and 1 + alpha lam of each pair
-  T ea[PER], eb[PER];
+  T la[PER], lb[PER];   // lam of each pair
+  T ea[PER], eb[PER];   // 1 + alpha lam
+  T fa[PER], fb[PER];   // spectral B(s_ring) of each pair
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int e = tid + b * NT;
@@ -191,10 +184,25 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       const T lk = (col < N - 1) ? lam[col] : T(1);
       const T l1 = lk + lam[l - 1];
       const T l2 = lk + lam[N - l - 1];
+      la[b] = l1;
+      lb[b] = l2;
       ea[b] = T(1) + a.alpha * l1;
       eb[b] = T(1) + a.alpha * l2;
-      da[b] = l1 * ea[b];
-      db[b] = l2 * eb[b];
+      fa[b] = T(0);
+      fb[b] = T(0);
+      if (a.lift != nullptr && col < N - 1) {
+        // sum_{i,j} B(s_ring)_{ij} sin(pi i k / n) sin(pi j l / n) over the four edges
+        const int k = col + 1;
+        const T sk = -tw[k].y, sl = -tw[l].y;  // sin(pi k/n), sin(pi l/n) = sin(pi (n-l)/n)
+        const T pk = (k & 1) ? T(1) : T(-1);   // (-1)^(k+1)
+        const T pl = (l & 1) ? T(1) : T(-1);   // (-1)^(l+1) = (-1)^(n-l+1)
+        const T* L = a.lift;
+        const T eb_k = L[0 * (N - 1) + k - 1], et_k = L[1 * (N - 1) + k - 1];
+        fa[b] = eb_k * sl + et_k * sl * pl + sk * L[2 * (N - 1) + l - 1] +
+                sk * pk * L[3 * (N - 1) + l - 1];
+        fb[b] = eb_k * sl + et_k * sl * pl + sk * L[2 * (N - 1) + N - l - 1] +
+                sk * pk * L[3 * (N - 1) + N - l - 1];
+      }
     }
   }
   const int nout = a.out2 != nullptr ? 2 : 1;
@@ -206,8 +214,9 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       const int e = tid + b * NT;
       if (e < NP) {
         const int c = e % CW, l = 1 + e / CW;
-        const T va = o == 0 ? xa[b] * (a.scale / da[b]) : xa[b] * (a.scale / ea[b]);
-        const T vb = o == 0 ? xb[b] * (a.scale / db[b]) : xb[b] * (a.scale / eb[b]);
+        const T ga = xa[b] / ea[b], gb = xb[b] / eb[b];
+        const T va = o == 0 ? (ga + fa[b]) * (a.scale / la[b]) : ga * a.scale;
+        const T vb = o == 0 ? (gb + fb[b]) * (a.scale / lb[b]) : gb * a.scale;
         dst_pack<T, N>(buf + c * N, l, va);
         if (l != N / 2) dst_pack<T, N>(buf + c * N, N - l, vb);
       }
@@ -266,10 +275,6 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
     dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
     if (a.interior_out) {
       T* o = out + (size_t)(j - 1) * a.po;
-      if (a.ring_sub != nullptr) {
-        xk -= ring_adj(a.ring_sub, N, k, j);
-        if (k != N / 2) xnk -= ring_adj(a.ring_sub, N, N - k, j);
-      }
       o[k - 1] = xk;
       if (k != N / 2) o[N - k - 1] = xnk;
     } else {
@@ -334,22 +339,28 @@ __global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gr
   gring[e] = T(0.25) * gv;
 }
 
-// work[j][i] += sum of the ring values adjacent to interior vertex (i, j): lifts
-// non-zero boundary values of the Poisson problem into its right-hand side.
-template <typename T>
-__global__ void k_add_ring_lift(T* work, int pw, const T* sring, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = n - 1;
-  if (e >= 4 * m) return;
-  const int side = e / m, k = 1 + e % m;
-  int i, j;
-  if (side == 0) { i = k; j = 1; }
-  else if (side == 1) { i = k; j = n - 1; }
-  else if (side == 2) { i = 1; j = k; }
-  else { i = n - 1; j = k; }
-  // each interior vertex is owned by exactly one (side, k): skip duplicates at corners
-  if ((side == 2 || side == 3) && (j == 1 || j == n - 1)) return;
-  work[(size_t)(j - 1) * pw + (i - 1)] += ring_adj(sring, n, i, j);
+// Unnormalised 1-D DSTs of the four edges of a streamfunction ring, as they appear in
+// B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top s(i, n) on row
+// n-1, left s(0, j) on column 1, right s(n, j) on column n-1.  One workgroup.
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
+                                                      const c2<T>* __restrict__ tw, T* lift) {
+  __shared__ c2<T> buf[4 * N];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 4 * (N - 1); e += NT) {
+    const int edge = e / (N - 1), idx = 1 + e % (N - 1);
+    dst_pack<T, N>(buf + edge * N, idx, sring[edge * (N + 1) + idx]);
+  }
+  for (int edge = tid; edge < 4; edge += NT) dst_pack_zeros<T, N>(buf + edge * N);
+  __syncthreads();
+  fft_lds<T, N, 4, NT>(buf, tw, tid);
+  for (int e = tid; e < 4 * (N / 2); e += NT) {
+    const int edge = e / (N / 2), k = 1 + e % (N / 2);
+    T xk, xnk;
+    dst_unpack<T, N>(buf + edge * N, tw, k, xk, xnk);
+    lift[edge * (N - 1) + k - 1] = xk;
+    if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -446,9 +457,11 @@ hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStrea
 }
 
 template <typename T>
-hipError_t launch_add_ring_lift(T* work, int pw, const T* sring, int n, hipStream_t st) {
-  const int tot = 4 * (n - 1);
-  hipLaunchKernelGGL((k_add_ring_lift<T>), dim3((tot + 255) / 256), dim3(256), 0, st, work, pw, sring, n);
+hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, hipStream_t st) {
+  const c2<T>* t = static_cast<const c2<T>*>(tw);
+#define L_(NN) hipLaunchKernelGGL((k_ring_edge_dst<T, NN, 256>), dim3(1), dim3(256), 0, st, sring, t, lift)
+  IB_DISPATCH_N(n, L_)
+#undef L_
   return hipGetLastError();
 }
 
@@ -460,7 +473,7 @@ hipError_t launch_add_ring_lift(T* work, int pw, const T* sring, int n, hipStrea
   template hipError_t launch_row_idst<T>(const RowArgs<T>&, int, int, const void*, const T*, int, \
                                          hipStream_t);                                         \
   template hipError_t launch_ring<T>(const T*, int, int, T*, T*, hipStream_t);         \
-  template hipError_t launch_add_ring_lift<T>(T*, int, const T*, int, hipStream_t);
+  template hipError_t launch_ring_edge_dst<T>(const T*, int, const void*, T*, hipStream_t);
 IB_INST(float)
 IB_INST(double)
 #undef IB_INST

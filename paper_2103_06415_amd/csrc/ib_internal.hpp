@@ -12,8 +12,7 @@ struct RhsArgs {
   const T* g;          // circulation gamma = C^T C s at time n, interior, (n-1) rows x pg
   const T* gf;         // finer level's circulation at time n (coarsification on read), or null
   const T* gring;      // ring circulation at time n, [4][n+1]
-  const T* sring_new;  // new streamfunction ring [4][n+1], or null (zero ring)
-  const T* gring_new;  // new circulation ring [4][n+1] (used with sring_new)
+  const T* gring_new;  // new circulation ring [4][n+1], or null (zero ring)
   const T* hist_in;    // C^T N_{n-1}, (n-1) rows x ph, or null on the first step
   T* hist_out;         // C^T N_n (may alias hist_in)
   T* out;              // row-transformed right-hand side, (n-1) rows x po
@@ -31,7 +30,6 @@ struct RowArgs {
   size_t bsi, bso;  // batch strides (elements)
   int interior_out; // inverse transform: write an (n-1)-row interior array instead of a
                     // full (n+1)-row array with its ring
-  const T* ring_sub;// interior output: subtract the adjacent values of this ring
 };
 
 // Column transform + spectral scale + inverse column transform.
@@ -43,6 +41,8 @@ struct ColArgs {
   int r0, r1;        // nonzero input rows (1-based interior rows)
   T alpha, scale;    // multiplier scale / (lam (1 + alpha lam)) for `out` and
   T* out2;           //   scale / (1 + alpha lam) for `out2` (if set; pitch po, stride bso)
+  const T* lift;     // if set: 1-D DSTs of the new streamfunction ring's four edges,
+                     //   [4][n-1]; `out` then solves L s = gamma + B(s_ring) instead
   int accumulate;    // out += result instead of out = result
   size_t bsi, bso;
   const int* rfirst; // if set: slot b's input holds rows rfirst[b] .. rfirst[b] + rcount - 1
@@ -65,6 +65,6 @@ hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw
 template <typename T>
 hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStream_t st);
 template <typename T>
-hipError_t launch_add_ring_lift(T* work, int pw, const T* sring, int n, hipStream_t st);
+hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, hipStream_t st);
 
 }  // namespace ib
