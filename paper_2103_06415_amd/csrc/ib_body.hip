@@ -161,10 +161,19 @@ __global__ void k_body_ops(FsiArgs a) {
         for (int e = 0; e < 16; ++e) w[e] = 0.0;
         const double hw[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};
         const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
+        // E0 row of a vertex: the kernel at offsets (-1, 0, 1) across the component's
+        // faces and (-1/2, 1/2) along them (the same pattern at every vertex)
+        const double k0 = roma3(0.0), k1 = roma3(1.0), kh = roma3(0.5);
+        const double across[3] = {k1, k0, k1};
         for (int e = 0; e < 4; ++e) {
           pidx[e] = comp * a.sd_total + (iy + dy[e]) * a.sd_npx + (ix + dx[e]);
           pw[e] = hw[e];
-          add_e0_vertex(gp + dx[e], gq + dy[e], comp, hw[e], a.x0, a.y0, a.h, base, w);
+          for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 2; ++v) {
+              const double c = hw[e] * (across[u] * kh);
+              if (comp == 0) w[(dy[e] + v) * 4 + dx[e] + u] += c;
+              else w[(dy[e] + u) * 4 + dx[e] + v] += c;
+            }
         }
       }
     }
@@ -273,33 +282,62 @@ __device__ void beam_element(const double* x, double l0, double beta0, double ea
 }
 
 // Forward and back substitution with a sliding register window; x is read through
-// `in(u)` and the result written to out[u * stride].
+// `in(u)` and the result written to out[u * stride].  Reads of `in` and of the forward
+// results are issued a group of 8 rows ahead to hide the memory latency.
 template <typename F>
 __device__ void band_solve(const double* lu, int nd, F in, double* out, size_t stride) {
+  constexpr int G = 8;
   double w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0;  // x[u-1] .. x[u-5]
-  for (int u = 0; u < nd; ++u) {
-    const double* row = lu + u * 11;
-    double v = in(u);
-    if (u >= 1) v -= row[4] * w0;
-    if (u >= 2) v -= row[3] * w1;
-    if (u >= 3) v -= row[2] * w2;
-    if (u >= 4) v -= row[1] * w3;
-    if (u >= 5) v -= row[0] * w4;
-    out[(size_t)u * stride] = v;
-    w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
+  double q[G];
+#pragma unroll
+  for (int e = 0; e < G; ++e) q[e] = e < nd ? in(e) : 0.0;
+  for (int u0 = 0; u0 < nd; u0 += G) {
+    double nq[G];
+#pragma unroll
+    for (int e = 0; e < G; ++e) nq[e] = u0 + G + e < nd ? in(u0 + G + e) : 0.0;
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const int u = u0 + e;
+      if (u < nd) {
+        const double* row = lu + u * 11;
+        double v = q[e];
+        if (u >= 1) v -= row[4] * w0;
+        if (u >= 2) v -= row[3] * w1;
+        if (u >= 3) v -= row[2] * w2;
+        if (u >= 4) v -= row[1] * w3;
+        if (u >= 5) v -= row[0] * w4;
+        out[(size_t)u * stride] = v;
+        w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < G; ++e) q[e] = nq[e];
   }
   w0 = w1 = w2 = w3 = w4 = 0;  // x[u+1] .. x[u+5]
-  for (int u = nd - 1; u >= 0; --u) {
-    const double* row = lu + u * 11;
-    double v = out[(size_t)u * stride];
-    if (u + 1 < nd) v -= row[6] * w0;
-    if (u + 2 < nd) v -= row[7] * w1;
-    if (u + 3 < nd) v -= row[8] * w2;
-    if (u + 4 < nd) v -= row[9] * w3;
-    if (u + 5 < nd) v -= row[10] * w4;
-    v /= row[5];
-    out[(size_t)u * stride] = v;
-    w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
+#pragma unroll
+  for (int e = 0; e < G; ++e) q[e] = nd - 1 - e >= 0 ? out[(size_t)(nd - 1 - e) * stride] : 0.0;
+  for (int u0 = nd - 1; u0 >= 0; u0 -= G) {
+    double nq[G];
+#pragma unroll
+    for (int e = 0; e < G; ++e) nq[e] = u0 - G - e >= 0 ? out[(size_t)(u0 - G - e) * stride] : 0.0;
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const int u = u0 - e;
+      if (u >= 0) {
+        const double* row = lu + u * 11;
+        double v = q[e];
+        if (u + 1 < nd) v -= row[6] * w0;
+        if (u + 2 < nd) v -= row[7] * w1;
+        if (u + 3 < nd) v -= row[8] * w2;
+        if (u + 4 < nd) v -= row[9] * w3;
+        if (u + 5 < nd) v -= row[10] * w4;
+        v /= row[5];
+        out[(size_t)u * stride] = v;
+        w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < G; ++e) q[e] = nq[e];
   }
 }
 
@@ -583,7 +621,16 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
       double* cn = a.chi_new + b.dof0;
       for (int u = tid; u < nd; u += STRUCT_NT) {
         double acc = 0.0;
-        for (int c = 0; c < 2 * m; ++c) acc += y[(size_t)u * ncol + c] * a.f[r0 + c];
+        const double* yr = y + (size_t)u * ncol;
+        int c = 0;
+        for (; c + 8 <= 2 * m; c += 8) {
+          double v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = yr[c + e];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) acc += v[e] * a.f[r0 + c + e];
+        }
+        for (; c < 2 * m; ++c) acc += yr[c] * a.f[r0 + c];
         const double dx = y[(size_t)u * ncol + 2 * m] + b.ds * acc;
         my = fmax(my, fabs(dx));
         cn[u + 3] = ck[u + 3] + dx;  // ck may alias cn: same thread reads then writes
@@ -644,19 +691,56 @@ __global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) {
 }
 
 // Corrector source C^T E^T lambda at interior vertices of rows [jlo, jhi]; entries
-// outside columns [ilo, ihi] are zero.  lambda_a = (ds_a / h) f_a.  Deterministic:
-// every vertex sums the rows in a fixed order.
+// outside columns [ilo, ihi] are zero.  lambda_a = (ds_a / h) f_a.  Each workgroup
+// covers a 64 x 4 tile of vertices, first collects (in row order) the operator rows
+// whose window reaches the tile, then every vertex sums those rows in that fixed order,
+// so the result is deterministic.
+constexpr int SPREAD_TX = 64, SPREAD_TY = 4, SPREAD_NT = SPREAD_TX * SPREAD_TY;
+constexpr int SPREAD_MAXROWS = 4096;
+
 template <typename T>
-__global__ void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi, T* out, int po) {
-  const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = jlo + blockIdx.y;
+__global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi,
+                                                      T* out, int po) {
+  __shared__ int list[SPREAD_MAXROWS];
+  __shared__ int scan[SPREAD_NT];
+  __shared__ int count_s;
+  const int tx = threadIdx.x % SPREAD_TX, ty = threadIdx.x / SPREAD_TX;
+  const int ti0 = 1 + blockIdx.x * SPREAD_TX, tj0 = jlo + blockIdx.y * SPREAD_TY;
+  const int i = ti0 + tx, j = tj0 + ty;
+  const bool tile_hit = !(ti0 + SPREAD_TX - 1 < ilo || ti0 > ihi);
+  if (tile_hit) {
+    if (threadIdx.x == 0) count_s = 0;
+    __syncthreads();
+    for (int r0 = 0; r0 < a.nf; r0 += SPREAD_NT) {
+      const int r = r0 + threadIdx.x;
+      int hit = 0;
+      if (r < a.nf) {
+        const int i0 = a.st_base[3 * r], j0 = a.st_base[3 * r + 1];
+        // vertices touched by the window's faces: columns i0 .. i0+4, rows j0 .. j0+4
+        hit = !(i0 + 4 < ti0 || i0 > ti0 + SPREAD_TX - 1 || j0 + 4 < tj0 || j0 > tj0 + SPREAD_TY - 1);
+      }
+      scan[threadIdx.x] = hit;
+      __syncthreads();
+      for (int off = 1; off < SPREAD_NT; off <<= 1) {
+        const int add = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += add;
+        __syncthreads();
+      }
+      if (hit) list[count_s + scan[threadIdx.x] - 1] = r;
+      __syncthreads();
+      if (threadIdx.x == 0) count_s += scan[SPREAD_NT - 1];
+      __syncthreads();
+    }
+  }
   if (i > a.n - 1 || j > jhi) return;
   double src = 0.0;
-  if (i >= ilo && i <= ihi) {
-    for (int r = 0; r < a.nf; ++r) {
+  if (tile_hit && i >= ilo && i <= ihi) {
+    const int cnt = count_s;
+    for (int q = 0; q < cnt; ++q) {
+      const int r = list[q];
       const int i0 = a.st_base[3 * r], j0 = a.st_base[3 * r + 1], comp = a.st_base[3 * r + 2];
       const int di = i - i0, dj = j - j0;
-      if (di < -1 || di > 4 || dj < -1 || dj > 4) continue;
       const double* w = a.st_w + 16 * r;
       double c = 0.0;
       if (comp == 0) {
@@ -810,15 +894,29 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 constexpr int REF_NT = 1024;
 constexpr int REF_MAXN = 4096;
 
-// y = A x for one workgroup; x in LDS, one wave per row.
-__device__ void wg_matvec(const double* A, int pa, const double* x, double* y, int n) {
+// y = A x (+ y if accumulate) for one workgroup; x in LDS; each wave takes four rows at
+// a time so that enough loads are in flight.
+__device__ void wg_matvec(const double* A, int pa, const double* x, double* y, int n,
+                          bool accumulate = false) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int r = w; r < n; r += REF_NT / 64) {
-    const double* row = A + (size_t)r * pa;
-    double acc = 0.0;
-    for (int c = lane; c < n; c += 64) acc += row[c] * x[c];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
-    if (lane == 0) y[r] = acc;
+  constexpr int NW = REF_NT / 64;
+  for (int r0 = w; r0 < n; r0 += 4 * NW) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = lane; c < n; c += 64) {
+      const double xc = x[c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + q * NW;
+        if (r < n) acc[q] += A[(size_t)r * pa + c] * xc;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v = acc[q];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+      const int r = r0 + q * NW;
+      if (lane == 0 && r < n) y[r] = accumulate ? y[r] + v : v;
+    }
   }
 }
 
@@ -857,15 +955,7 @@ __global__ __launch_bounds__(REF_NT) void k_solve_refine(const double* M, int pm
     rel = nb > 0.0 ? nr / nb : 0.0;
     if (!(rel > 1e-16 * n) || !(nr < 0.5 * prev)) break;  // converged or no longer contracting
     prev = nr;
-    // sf += X sr  (through the scratch vector sb2 = X sr written into sr's partner)
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int r = w; r < n; r += REF_NT / 64) {
-      const double* row = X + (size_t)r * pm;
-      double acc = 0.0;
-      for (int c = lane; c < n; c += 64) acc += row[c] * sr[c];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
-      if (lane == 0) sf[r] += acc;
-    }
+    wg_matvec(X, pm, sr, sf, n, true);  // f += X r
     __syncthreads();
   }
   for (int i = threadIdx.x; i < n; i += REF_NT) f[i] = sf[i];
@@ -969,8 +1059,9 @@ hipError_t launch_finish(const FsiArgs& a, hipStream_t st) {
 template <typename T>
 hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,
                          hipStream_t st) {
-  dim3 g((a.n - 1 + 127) / 128, jhi - jlo + 1);
-  hipLaunchKernelGGL((k_spread<T>), g, dim3(128), 0, st, a, jlo, jhi, ilo, ihi, out, po);
+  if (a.nf > SPREAD_MAXROWS) return hipErrorInvalidValue;
+  dim3 g((a.n - 1 + SPREAD_TX - 1) / SPREAD_TX, (jhi - jlo + 1 + SPREAD_TY - 1) / SPREAD_TY);
+  hipLaunchKernelGGL((k_spread<T>), g, dim3(SPREAD_NT), 0, st, a, jlo, jhi, ilo, ihi, out, po);
   return hipGetLastError();
 }
 hipError_t launch_point_source_rowdst(const OffRows& o, int col0, int ncols, int nslots,

@@ -933,17 +933,11 @@ ib_status do_step(ib_solver* s) {
     r.out = static_cast<T*>(L.s);
     r.r0 = 1;
     r.r1 = n - 1;
-    RowArgs<T> rg = r;
-    rg.in = static_cast<T*>(s->workg);
-    rg.out = static_cast<T*>(L.g);
-    rg.interior_out = 1;
+    r.in2 = static_cast<T*>(s->workg);
+    r.out2 = static_cast<T*>(L.g);
     {
       TimeScope ts(s, IB_K_ROW_IDST);
       HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
-    }
-    {
-      TimeScope ts(s, IB_K_ROW_IDST);
-      HIPCHK(launch_row_idst<T>(rg, n, 1, s->tw, nullptr, 0, s->stream));
     }
     if (has_ring) L.gcur = nxt;
   }

@@ -145,10 +145,12 @@ __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __rest
 // for every row; input and output may alias when accumulate == 0.
 template <typename T, int N, int CW, int NT>
 __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
-                                                  const T* __restrict__ lam) {
+                                                  const T* __restrict__ lam, int nblocks) {
   __shared__ c2<T> buf[CW * N];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
   const int tid = threadIdx.x;
-  const int k0 = blockIdx.x * CW;
+  const int k0 = blk * CW;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
   T* out = a.out + (size_t)blockIdx.y * a.bso;
   for (int e = tid; e < (N - 1) * CW; e += NT) {
@@ -245,35 +247,43 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
 
 // Inverse row DST of rows [r0, r1] into the interior of a full (n+1)-row array; the
 // ring columns (and, when ring rows are requested, rows 0 and n) come from `ring`
-// (zero when null).
-template <typename T, int N, int ROWS, int NT>
+// (zero when null).  With interior_out the output is an (n-1)-row interior array.
+// With in2/out2 set the same rows of a second array are transformed in the same
+// workgroup into the interior array out2 (the level's circulation).
+template <typename T, int N, int ROWS, int NT, int DUAL>
 __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __restrict__ tw,
                                                  const T* __restrict__ ring, int ring_rows,
                                                  int nblocks) {
-  __shared__ c2<T> buf[ROWS * N];
+  constexpr int NS = ROWS * (DUAL ? 2 : 1);
+  __shared__ c2<T> buf[NS * N];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
   T* out = a.out + (size_t)blockIdx.y * a.bso;
   const int j0 = a.r0 + blk * ROWS;
-  for (int e = tid; e < ROWS * (N - 1); e += NT) {
+  for (int e = tid; e < NS * (N - 1); e += NT) {
     const int t = e / (N - 1), k = 1 + e % (N - 1);
-    const int j = j0 + t;
+    const int j = j0 + (t % ROWS);
+    const T* src = t < ROWS ? in : a.in2;
     T v = T(0);
-    if (j <= a.r1) v = in[(size_t)(j - 1) * a.pi + (k - 1)];
+    if (j <= a.r1) v = src[(size_t)(j - 1) * a.pi + (k - 1)];
     dst_pack<T, N>(buf + t * N, k, v);
   }
-  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  for (int t = tid; t < NS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
   __syncthreads();
-  fft_lds<T, N, ROWS, NT>(buf, tw, tid);
-  for (int e = tid; e < ROWS * (N / 2); e += NT) {
+  fft_lds<T, N, NS, NT>(buf, tw, tid);
+  for (int e = tid; e < NS * (N / 2); e += NT) {
     const int t = e / (N / 2), k = 1 + e % (N / 2);
-    const int j = j0 + t;
+    const int j = j0 + (t % ROWS);
     if (j > a.r1) continue;
     T xk, xnk;
     dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
-    if (a.interior_out) {
+    if (t >= ROWS) {
+      T* o = a.out2 + (size_t)(j - 1) * a.po;
+      o[k - 1] = xk;
+      if (k != N / 2) o[N - k - 1] = xnk;
+    } else if (a.interior_out) {
       T* o = out + (size_t)(j - 1) * a.po;
       o[k - 1] = xk;
       if (k != N / 2) o[N - k - 1] = xnk;
@@ -369,7 +379,7 @@ template <typename T>
 struct Cfg {
   static constexpr int ROWS = 2;
   static constexpr int NTR = 256;
-  static constexpr int CW = sizeof(T) == 8 ? 4 : 8;
+  static constexpr int CW = 4;
   static constexpr int NTC = 256;
 };
 
@@ -430,7 +440,7 @@ hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* t
   const int nb = (n - 1 + CW - 1) / CW;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
   const T* l = static_cast<const T*>(lam);
-#define L_(NN) hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(nb, batch), dim3(NT), 0, st, a, t, l)
+#define L_(NN) hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, l, nb)
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();
@@ -443,7 +453,9 @@ hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw
   const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;
   if (nb <= 0) return hipSuccess;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
-#define L_(NN) hipLaunchKernelGGL((k_row_idst<T, NN, R, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb)
+#define L_(NN)                                                                                   \
+  if (a.in2) hipLaunchKernelGGL((k_row_idst<T, NN, R, NT, 1>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb); \
+  else hipLaunchKernelGGL((k_row_idst<T, NN, R, NT, 0>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb)
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();

@@ -30,6 +30,8 @@ struct RowArgs {
   size_t bsi, bso;  // batch strides (elements)
   int interior_out; // inverse transform: write an (n-1)-row interior array instead of a
                     // full (n+1)-row array with its ring
+  const T* in2;     // inverse transform: a second array transformed alongside `in`
+  T* out2;          //   into the interior array out2 (pitch po); batch 1 only
 };
 
 // Column transform + spectral scale + inverse column transform.
