@@ -218,7 +218,16 @@ __device__ __forceinline__ double row_ds(const FsiArgs& a, int row) {
   return a.bodies[bi].ds;
 }
 
-// Flow block of the Schur matrix in sub-domain mode: (dt/h^2) (P B' P^T)_ab ds_b.
+__device__ __forceinline__ int row_body(const FsiArgs& a, int row) {
+  int bi = 0;
+  while (bi + 1 < a.nbodies && 2 * a.bodies[bi + 1].pt0 <= row) ++bi;
+  return bi;
+}
+
+// Schur matrix in sub-domain mode, one entry per thread:
+//   M_ab = (dt/h^2) (P B' P^T)_ab ds_b + structural block of the body owning a and b:
+//   torsional (2 ds/dt) S_a S_b / J,  deformable (2 ds/dt) (T J_d^{-1} T^T)_ab, the latter
+//   from the columns J_d^{-1} T^T that k_structure left in ywork (so it runs first).
 __global__ void k_schur_sd(FsiArgs a) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nf * a.nf) return;
@@ -236,7 +245,32 @@ __global__ void k_schur_sd(FsiArgs a) {
     }
     acc += wu * inner;
   }
-  a.M[(size_t)r * a.pm + c] = (a.dt / (a.h * a.h)) * acc * row_ds(a, c);
+  const int bc = row_body(a, c);
+  double m = (a.dt / (a.h * a.h)) * acc * a.bodies[bc].ds;
+  const BodyDev& b = a.bodies[bc];
+  const int r0 = 2 * b.pt0, mpts = b.npts;
+  if (r >= r0 && r < r0 + 2 * mpts && b.kind != BODY_RIGID) {
+    const int u = r - r0, v = c - r0;
+    const double coef = 2.0 * b.ds / a.dt;
+    if (b.kind == BODY_TORSIONAL) {
+      const double* ts = a.tors + b.tors * TS_COUNT;
+      const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
+      const double ang = b.theta0 + th;
+      const double sn = sin(ang), cs = cos(ang);
+      const double dt = a.dt;
+      const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
+      const double su = (u < mpts ? -sn : cs) * (u % mpts) * b.ds;
+      const double sv = (v < mpts ? -sn : cs) * (v % mpts) * b.ds;
+      m += (coef / jt) * su * sv;
+    } else {
+      const int node = u % mpts, cmp = u / mpts;
+      if (node > 0) {
+        const int du = 3 * node + cmp - 3;
+        m += coef * a.ywork[b.yoff + (size_t)du * (2 * mpts + 1) + v];
+      }
+    }
+  }
+  a.M[(size_t)r * a.pm + c] = m;
 }
 
 // -------------------------------------------------------- corotational beam
@@ -345,11 +379,12 @@ constexpr int MAX_BEAM_DOF = 600;  // free DOFs of one deformable body (<= 201 n
 
 constexpr int STRUCT_NT = 256;
 
-// Structural blocks of the Schur matrix and right-hand side (one workgroup).
+// Structural part of the Schur right-hand side (one workgroup); the structural blocks
+// of the matrix are added by k_schur_sd, which runs after this kernel.
 //   rigid       rhs -= u_b
-//   torsional   M += (2 ds/dt) S^T S / J,  rhs -= S ((2/dt) r_phi / J - r_theta)
-//   deformable  M += (2 ds/dt) T J_d^{-1} T^T,
-//               rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
+//   torsional   rhs -= S ((2/dt) r_phi / J - r_theta)
+//   deformable  rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi), and the columns
+//               J_d^{-1} T^T (band LU of J_d = 4 M/dt^2 + K(chi^k))
 __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_M) {
   const int tid = threadIdx.x;
   (void)flow_in_M;  // the flow block is either already in M or not used (stationary inverse)
@@ -374,14 +409,7 @@ __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_
       const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
                           b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
       const double rth = ts[TS_PHI] + 2.0 * ts[TS_THETA] / dt;
-      const double coef = (2.0 * b.ds / dt) / jt;
       const double rc = (2.0 / dt) * rphi / jt - rth;
-      for (int e = tid; e < 4 * m * m; e += STRUCT_NT) {
-        const int u = e / (2 * m), v = e % (2 * m);
-        const double su = (u < m ? -sn : cs) * (u % m) * b.ds;
-        const double sv = (v < m ? -sn : cs) * (v % m) * b.ds;
-        a.M[(size_t)(r0 + u) * a.pm + r0 + v] += coef * su * sv;
-      }
       for (int e = tid; e < 2 * m; e += STRUCT_NT) {
         const double su = (e < m ? -sn : cs) * (e % m) * b.ds;
         a.rhs[r0 + e] -= su * rc;
@@ -465,14 +493,6 @@ __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_
         }
       }
       __syncthreads();
-      const double coef = 2.0 * b.ds / dt;
-      for (int e = tid; e < 4 * m * m; e += STRUCT_NT) {
-        const int u = e / (2 * m), v = e % (2 * m);
-        const int node = u % m, cmp = u / m;
-        if (node == 0) continue;
-        const int du = 3 * node + cmp - 3;
-        a.M[(size_t)(r0 + u) * a.pm + r0 + v] += coef * y[(size_t)du * ncol + v];
-      }
       for (int u = tid; u < 2 * m; u += STRUCT_NT) {
         const int node = u % m, cmp = u / m;
         if (node == 0) continue;
@@ -894,28 +914,40 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 constexpr int REF_NT = 1024;
 constexpr int REF_MAXN = 4096;
 
-// y = A x (+ y if accumulate) for one workgroup; x in LDS; each wave takes four rows at
-// a time so that enough loads are in flight.
+// y = A x (+ y if accumulate) for one workgroup; x in LDS.  Each wave takes eight rows at
+// a time and issues all their loads for four 64-column chunks before accumulating, so
+// about 32 loads per lane are in flight.
 __device__ void wg_matvec(const double* A, int pa, const double* x, double* y, int n,
                           bool accumulate = false) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = REF_NT / 64;
-  for (int r0 = w; r0 < n; r0 += 4 * NW) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = lane; c < n; c += 64) {
-      const double xc = x[c];
+  constexpr int NW = REF_NT / 64, RQ = 8, CQ = 4;
+  for (int r0 = w; r0 < n; r0 += RQ * NW) {
+    double acc[RQ];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = r0 + q * NW;
-        if (r < n) acc[q] += A[(size_t)r * pa + c] * xc;
+    for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
+    for (int c0 = 0; c0 < n; c0 += 64 * CQ) {
+      double v[RQ][CQ];
+#pragma unroll
+      for (int q = 0; q < RQ; ++q)
+#pragma unroll
+        for (int k = 0; k < CQ; ++k) {
+          const int r = r0 + q * NW, c = c0 + k * 64 + lane;
+          v[q][k] = (r < n && c < n) ? A[(size_t)r * pa + c] : 0.0;
+        }
+#pragma unroll
+      for (int k = 0; k < CQ; ++k) {
+        const int c = c0 + k * 64 + lane;
+        const double xc = c < n ? x[c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) acc[q] += v[q][k] * xc;
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double v = acc[q];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    for (int q = 0; q < RQ; ++q) {
+      double s = acc[q];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
       const int r = r0 + q * NW;
-      if (lane == 0 && r < n) y[r] = accumulate ? y[r] + v : v;
+      if (lane == 0 && r < n) y[r] = accumulate ? y[r] + s : s;
     }
   }
 }

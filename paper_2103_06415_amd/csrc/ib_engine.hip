@@ -766,8 +766,8 @@ ib_status fsi_and_correct(ib_solver* s) {
     {
       TimeScope ts(s, IB_K_FSI);
       HIPCHK(launch_body_ops<T>(a, s->stream));
-      HIPCHK(launch_schur_sd(a, s->stream));
       HIPCHK(launch_structure(a, 1, s->stream));
+      HIPCHK(launch_schur_sd(a, s->stream));
       const int nf = s->nf;
       const size_t mb = (size_t)nf * a.pm * 8;
       if (!s->x_valid) {
