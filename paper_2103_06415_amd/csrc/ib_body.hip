@@ -315,8 +315,9 @@ __device__ void beam_element(const double* x, double l0, double beta0, double ea
     }
 }
 
-// Forward and back substitution with a sliding register window; x is read through
-// `in(u)` and the result written to out[u * stride].  Reads of `in` and of the forward
+// Forward and back substitution with a sliding register window (unit lower factor,
+// upper factor with its diagonal stored as reciprocals); x is read through `in(u)` and
+// the result written to out[u * stride].  Reads of `in` and of the forward
 // results are issued a group of 8 rows ahead to hide the memory latency.
 template <typename F>
 __device__ void band_solve(const double* lu, int nd, F in, double* out, size_t stride) {
@@ -365,7 +366,7 @@ __device__ void band_solve(const double* lu, int nd, F in, double* out, size_t s
         if (u + 3 < nd) v -= row[8] * w2;
         if (u + 4 < nd) v -= row[9] * w3;
         if (u + 5 < nd) v -= row[10] * w4;
-        v /= row[5];
+        v *= row[5];  // reciprocal of the pivot
         out[(size_t)u * stride] = v;
         w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
       }
@@ -454,56 +455,80 @@ __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_
       }
       __syncthreads();
       // band LU without pivoting by one wave: lane (p, q) updates entry (k+1+p, k+1+q)
-      // of the trailing 5 x 5 block; LDS operations of one wave complete in order
+      // of the trailing 5 x 5 block; LDS operations of one wave complete in order.  The
+      // diagonal is replaced by its reciprocal for the substitutions.
       if (tid < 64) {
         const int p = tid / 5, q = tid % 5;
         for (int k = 0; k < nd; ++k) {
-          const double piv = band[k * 11 + 5];
+          const double rp = 1.0 / band[k * 11 + 5];
           const int i = k + 1 + p, j = k + 1 + q;
           const bool act = tid < 25 && i < nd && j < nd;
           double l = 0.0, u = 0.0, aij = 0.0;
           if (act) {
-            l = band[i * 11 + (k - i + 5)] / piv;
+            l = band[i * 11 + (k - i + 5)] * rp;
             u = band[k * 11 + (j - k + 5)];
             aij = band[i * 11 + (j - i + 5)];
           }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           if (act) {
             band[i * 11 + (j - i + 5)] = aij - l * u;
             if (q == 0) band[i * 11 + (k - i + 5)] = l;
           }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
         }
       }
       __syncthreads();
       double* lu = a.band + (size_t)b.band0 * 11;
-      for (int e = tid; e < nd * 11; e += STRUCT_NT) lu[e] = band[e];
-      // columns of J_d^{-1} T^T (2m, node 0's are zero) and J_d^{-1} res
-      const int ncol = 2 * m + 1;
-      double* y = a.ywork + b.yoff;  // [nd][2m+1]
-      for (int col = tid; col < ncol; col += STRUCT_NT) {
-        if (col < 2 * m) {
-          const int node = col % m, cmp = col / m;
-          const int hot = node > 0 ? 3 * node + cmp - 3 : -1;
-          band_solve(band, nd, [&](int u) { return u == hot ? 1.0 : 0.0; }, y + col, ncol);
-        } else {
-          band_solve(band, nd, [&](int u) { return res[u + 3]; }, y + col, ncol);
-        }
-      }
-      __syncthreads();
-      for (int u = tid; u < 2 * m; u += STRUCT_NT) {
-        const int node = u % m, cmp = u / m;
-        if (node == 0) continue;
-        const int g = 3 * node + cmp;
-        const double pred = ck[g] + y[(size_t)(g - 3) * ncol + 2 * m];
-        const double rchi = zn[g] + 2.0 * xn[g] / dt;
-        a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
-      }
+      for (int e = tid; e < nd * 11; e += STRUCT_NT)
+        lu[e] = (e % 11 == 5) ? 1.0 / band[e] : band[e];
       __syncthreads();
     }
     __syncthreads();
+  }
+}
+
+// Columns of J_d^{-1} T^T (2m; node 0's are zero) and J_d^{-1} res of one deformable
+// body from its band LU factors (diagonal stored as reciprocals); one column per thread,
+// many workgroups.
+constexpr int BCOL_NT = 64;
+__global__ __launch_bounds__(BCOL_NT) void k_band_columns(FsiArgs a, int bi) {
+  __shared__ double band[MAX_BEAM_DOF * 11];
+  const BodyDev& b = a.bodies[bi];
+  const int m = b.npts, nd = 3 * m - 3, ncol = 2 * m + 1;
+  const double* lu = a.band + (size_t)b.band0 * 11;
+  for (int e = threadIdx.x; e < nd * 11; e += BCOL_NT) band[e] = lu[e];
+  __syncthreads();
+  const int col = blockIdx.x * BCOL_NT + threadIdx.x;
+  if (col >= ncol) return;
+  double* y = a.ywork + b.yoff;  // [nd][2m+1]
+  const double* res = a.dres + b.dof0;
+  if (col < 2 * m) {
+    const int node = col % m, cmp = col / m;
+    const int hot = node > 0 ? 3 * node + cmp - 3 : -1;
+    band_solve(band, nd, [&](int u) { return u == hot ? 1.0 : 0.0; }, y + col, ncol);
+  } else {
+    band_solve(band, nd, [&](int u) { return res[u + 3]; }, y + col, ncol);
+  }
+}
+
+// Deformable part of the Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi).
+__global__ void k_struct_rhs_def(FsiArgs a, int bi) {
+  const BodyDev& b = a.bodies[bi];
+  const int m = b.npts, ncol = 2 * m + 1, r0 = 2 * b.pt0;
+  const double dt = a.dt;
+  const double* y = a.ywork + b.yoff;
+  const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
+  const double* xn = a.chi + b.dof0;
+  const double* zn = a.zeta + b.dof0;
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < 2 * m; u += gridDim.x * blockDim.x) {
+    const int node = u % m, cmp = u / m;
+    if (node == 0) continue;
+    const int g = 3 * node + cmp;
+    const double pred = ck[g] + y[(size_t)(g - 3) * ncol + 2 * m];
+    const double rchi = zn[g] + 2.0 * xn[g] / dt;
+    a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
   }
 }
 
@@ -914,13 +939,13 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 constexpr int REF_NT = 1024;
 constexpr int REF_MAXN = 4096;
 
-// y = A x (+ y if accumulate) for one workgroup; x in LDS.  Each wave takes eight rows at
+// y = A x (+ y if accumulate) for one workgroup; x in LDS.  Each wave takes four rows at
 // a time and issues all their loads for four 64-column chunks before accumulating, so
-// about 32 loads per lane are in flight.
+// 16 loads per lane are in flight.
 __device__ void wg_matvec(const double* A, int pa, const double* x, double* y, int n,
                           bool accumulate = false) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = REF_NT / 64, RQ = 8, CQ = 4;
+  constexpr int NW = REF_NT / 64, RQ = 4, CQ = 4;
   for (int r0 = w; r0 < n; r0 += RQ * NW) {
     double acc[RQ];
 #pragma unroll
@@ -1078,6 +1103,12 @@ hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs
 }
 hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_matvec, dim3(n), dim3(256), 0, st, A, pa, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_band_columns(const FsiArgs& a, int bi, int m, hipStream_t st) {
+  const int ncol = 2 * m + 1;
+  hipLaunchKernelGGL(k_band_columns, dim3((ncol + BCOL_NT - 1) / BCOL_NT), dim3(BCOL_NT), 0, st, a, bi);
+  hipLaunchKernelGGL(k_struct_rhs_def, dim3(1), dim3(256), 0, st, a, bi);
   return hipGetLastError();
 }
 hipError_t launch_update(const FsiArgs& a, hipStream_t st) {

@@ -93,6 +93,7 @@ hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs
                            hipStream_t st);
 hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st);
 hipError_t launch_update(const FsiArgs& a, hipStream_t st);
+hipError_t launch_band_columns(const FsiArgs& a, int bi, int m, hipStream_t st);
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st);
 template <typename T>
 hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,

@@ -767,6 +767,9 @@ ib_status fsi_and_correct(ib_solver* s) {
       TimeScope ts(s, IB_K_FSI);
       HIPCHK(launch_body_ops<T>(a, s->stream));
       HIPCHK(launch_structure(a, 1, s->stream));
+      for (size_t bi = 0; bi < s->bodies.size(); ++bi)
+        if (s->bodies[bi].kind == BODY_DEFORMABLE)
+          HIPCHK(launch_band_columns(a, (int)bi, s->bodies[bi].m, s->stream));
       HIPCHK(launch_schur_sd(a, s->stream));
       const int nf = s->nf;
       const size_t mb = (size_t)nf * a.pm * 8;
