@@ -154,7 +154,9 @@ def main():
                                "Re 500, sub-domain B' (eps 0.007), FSI tol 1e-7; FP32 flow + "
                                "FP64 Schur/LU/structure",
                    "n": n, "levels": levels, "subdomain_nnz": st32["subdomain_nnz"],
-                   "newton_iters_max": st32["newton_iters_max"]},
+                   "newton_iters_max": st32["newton_iters_max"],
+                   "schur_refine_sweeps_last": st32["refine_iters"],
+                   "schur_inverse_rebuilds": st32["inverse_rebuilds"]},
         "value_fp64": value64,
         "fp32_over_fp64": (value / value64) if value64 else None,
         "prepare_s": prep32,

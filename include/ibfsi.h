@@ -99,6 +99,9 @@ typedef struct {
   int64_t subdomain_points;  /* 2 n_sd (rows of B'), 0 when not used */
   int64_t subdomain_nnz;     /* stored entries of B' */
   double prepare_seconds;    /* wall time of the offline stage */
+  int32_t refine_iters;      /* Schur refinement sweeps in the last FSI iteration */
+  int32_t inverse_rebuilds;  /* fresh Schur inverses (LU) made so far */
+  double refine_residual;    /* relative residual of the last Schur solve */
 } ib_stats;
 
 /* Create a solver.  `alloc` may be NULL (hipMalloc); `hip_stream` is a hipStream_t

@@ -54,7 +54,8 @@ class IbStats(ctypes.Structure):
     _fields_ = [
         ("step", c_int64), ("newton_iters", c_int32), ("newton_iters_max", c_int32),
         ("newton_delta", c_double), ("subdomain_points", c_int64), ("subdomain_nnz", c_int64),
-        ("prepare_seconds", c_double),
+        ("prepare_seconds", c_double), ("refine_iters", c_int32), ("inverse_rebuilds", c_int32),
+        ("refine_residual", c_double),
     ]
 
 

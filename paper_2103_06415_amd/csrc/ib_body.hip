@@ -315,67 +315,6 @@ __device__ void beam_element(const double* x, double l0, double beta0, double ea
     }
 }
 
-// Forward and back substitution with a sliding register window (unit lower factor,
-// upper factor with its diagonal stored as reciprocals); x is read through `in(u)` and
-// the result written to out[u * stride].  Reads of `in` and of the forward
-// results are issued a group of 8 rows ahead to hide the memory latency.
-template <typename F>
-__device__ void band_solve(const double* lu, int nd, F in, double* out, size_t stride) {
-  constexpr int G = 8;
-  double w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0;  // x[u-1] .. x[u-5]
-  double q[G];
-#pragma unroll
-  for (int e = 0; e < G; ++e) q[e] = e < nd ? in(e) : 0.0;
-  for (int u0 = 0; u0 < nd; u0 += G) {
-    double nq[G];
-#pragma unroll
-    for (int e = 0; e < G; ++e) nq[e] = u0 + G + e < nd ? in(u0 + G + e) : 0.0;
-#pragma unroll
-    for (int e = 0; e < G; ++e) {
-      const int u = u0 + e;
-      if (u < nd) {
-        const double* row = lu + u * 11;
-        double v = q[e];
-        if (u >= 1) v -= row[4] * w0;
-        if (u >= 2) v -= row[3] * w1;
-        if (u >= 3) v -= row[2] * w2;
-        if (u >= 4) v -= row[1] * w3;
-        if (u >= 5) v -= row[0] * w4;
-        out[(size_t)u * stride] = v;
-        w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < G; ++e) q[e] = nq[e];
-  }
-  w0 = w1 = w2 = w3 = w4 = 0;  // x[u+1] .. x[u+5]
-#pragma unroll
-  for (int e = 0; e < G; ++e) q[e] = nd - 1 - e >= 0 ? out[(size_t)(nd - 1 - e) * stride] : 0.0;
-  for (int u0 = nd - 1; u0 >= 0; u0 -= G) {
-    double nq[G];
-#pragma unroll
-    for (int e = 0; e < G; ++e) nq[e] = u0 - G - e >= 0 ? out[(size_t)(u0 - G - e) * stride] : 0.0;
-#pragma unroll
-    for (int e = 0; e < G; ++e) {
-      const int u = u0 - e;
-      if (u >= 0) {
-        const double* row = lu + u * 11;
-        double v = q[e];
-        if (u + 1 < nd) v -= row[6] * w0;
-        if (u + 2 < nd) v -= row[7] * w1;
-        if (u + 3 < nd) v -= row[8] * w2;
-        if (u + 4 < nd) v -= row[9] * w3;
-        if (u + 5 < nd) v -= row[10] * w4;
-        v *= row[5];  // reciprocal of the pivot
-        out[(size_t)u * stride] = v;
-        w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = v;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < G; ++e) q[e] = nq[e];
-  }
-}
-
 constexpr int MAX_BEAM_DOF = 600;  // free DOFs of one deformable body (<= 201 nodes)
 
 constexpr int STRUCT_NT = 256;
@@ -384,11 +323,11 @@ constexpr int STRUCT_NT = 256;
 // of the matrix are added by k_schur_sd, which runs after this kernel.
 //   rigid       rhs -= u_b
 //   torsional   rhs -= S ((2/dt) r_phi / J - r_theta)
-//   deformable  rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi), and the columns
-//               J_d^{-1} T^T (band LU of J_d = 4 M/dt^2 + K(chi^k))
+//   deformable  handled by k_beam and k_struct_rhs_def
 __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_M) {
   const int tid = threadIdx.x;
   (void)flow_in_M;  // the flow block is either already in M or not used (stationary inverse)
+  if (tid == 0) a.delta[0] = 0.0;  // k_update folds its maxima in with atomicMax
   for (int r = tid; r < a.nf; r += STRUCT_NT) a.rhs[r] = a.ustar[r];
   __syncthreads();
   const double dt = a.dt;
@@ -415,102 +354,196 @@ __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_
         const double su = (e < m ? -sn : cs) * (e % m) * b.ds;
         a.rhs[r0 + e] -= su * rc;
       }
-    } else {
-      // deformable: assemble J_d in band form over the free DOFs in LDS
-      __shared__ double band[MAX_BEAM_DOF * 11];
-      __shared__ double rint[MAX_BEAM_DOF + 3];
-      const int nd = 3 * m - 3;
-      const double* chi = a.iter == 0 ? a.chi : a.chi_new;
-      const double* xn = a.chi + b.dof0;
-      const double* zn = a.zeta + b.dof0;
-      const double* an = a.zetadot + b.dof0;
-      const double* ms = a.dmass + b.dof0;
-      const double* ck = chi + b.dof0;
-      for (int e = tid; e < nd * 11; e += STRUCT_NT) band[e] = 0.0;
-      for (int e = tid; e < 3 * m; e += STRUCT_NT) rint[e] = 0.0;
-      __syncthreads();
-      for (int parity = 0; parity < 2; ++parity) {
-        for (int el = 2 * tid + parity; el < m - 1; el += 2 * STRUCT_NT) {
-          double fe[6], ke[36];
-          beam_element(ck + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el], b.ea, b.ei, fe, ke);
-          for (int p = 0; p < 6; ++p) {
-            const int gp = 3 * el + p;
-            rint[gp] += fe[p];
-            if (gp < 3) continue;
-            for (int q = 0; q < 6; ++q) {
-              const int gq = 3 * el + q;
-              if (gq < 3) continue;
-              band[(gp - 3) * 11 + (gq - gp + 5)] += ke[p * 6 + q];
-            }
-          }
-        }
-        __syncthreads();
-      }
-      double* res = a.dres + b.dof0;
-      for (int u = tid; u < nd; u += STRUCT_NT) {
-        const int g = u + 3;
-        band[u * 11 + 5] += 4.0 * ms[g] / (dt * dt);
-        const double rz = ms[g] * (4.0 * xn[g] / (dt * dt) + 4.0 * zn[g] / dt + an[g]);
-        res[g] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint[g];
-      }
-      __syncthreads();
-      // band LU without pivoting by one wave: lane (p, q) updates entry (k+1+p, k+1+q)
-      // of the trailing 5 x 5 block; LDS operations of one wave complete in order.  The
-      // diagonal is replaced by its reciprocal for the substitutions.
-      if (tid < 64) {
-        const int p = tid / 5, q = tid % 5;
-        for (int k = 0; k < nd; ++k) {
-          const double rp = 1.0 / band[k * 11 + 5];
-          const int i = k + 1 + p, j = k + 1 + q;
-          const bool act = tid < 25 && i < nd && j < nd;
-          double l = 0.0, u = 0.0, aij = 0.0;
-          if (act) {
-            l = band[i * 11 + (k - i + 5)] * rp;
-            u = band[k * 11 + (j - k + 5)];
-            aij = band[i * 11 + (j - i + 5)];
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          if (act) {
-            band[i * 11 + (j - i + 5)] = aij - l * u;
-            if (q == 0) band[i * 11 + (k - i + 5)] = l;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-      __syncthreads();
-      double* lu = a.band + (size_t)b.band0 * 11;
-      for (int e = tid; e < nd * 11; e += STRUCT_NT)
-        lu[e] = (e % 11 == 5) ? 1.0 / band[e] : band[e];
-      __syncthreads();
     }
     __syncthreads();
   }
 }
 
-// Columns of J_d^{-1} T^T (2m; node 0's are zero) and J_d^{-1} res of one deformable
-// body from its band LU factors (diagonal stored as reciprocals); one column per thread,
-// many workgroups.
-constexpr int BCOL_NT = 64;
-__global__ __launch_bounds__(BCOL_NT) void k_band_columns(FsiArgs a, int bi) {
-  __shared__ double band[MAX_BEAM_DOF * 11];
+// ------------------------------------------------ beam Jacobian: cyclic reduction
+// J_d = 4 M/dt^2 + K(chi^k) over the free nodes is block tridiagonal with 3 x 3 blocks
+// (node k+1 is block k): A_k on the diagonal, U_k = J(k, k+1), L_k = J(k, k-1).  It is
+// factored by block cyclic reduction: at the level of stride s the blocks j with
+// (j+1) mod 2s = s are eliminated into their neighbours j -+ s, which stay; every level
+// is data parallel, so the sequential depth is log2(K) instead of K.  J_d is symmetric
+// positive definite, so no pivoting is needed.  Each workgroup factors the same matrix
+// (redundantly, no inter-workgroup traffic) and solves `nc` of the right-hand sides
+// [T^T columns (2m, node 0's are zero), res].  Results go to ywork[u][2m+1].
+
+// row-major 3 x 3 inverse entry (r, c) = cofactor(c, r) / det
+__device__ inline double inv3_entry(const double* a, int r, int c) {
+  auto cof = [&](int i, int j) {
+    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+    return a[3 * i1 + j1] * a[3 * i2 + j2] - a[3 * i1 + j2] * a[3 * i2 + j1];
+  };
+  const double det = a[0] * cof(0, 0) + a[1] * cof(0, 1) + a[2] * cof(0, 2);
+  return cof(c, r) / det;
+}
+
+constexpr int BEAM_NT = 256;
+__global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi, int nc) {
+  extern __shared__ double bsm[];
   const BodyDev& b = a.bodies[bi];
-  const int m = b.npts, nd = 3 * m - 3, ncol = 2 * m + 1;
-  const double* lu = a.band + (size_t)b.band0 * 11;
-  for (int e = threadIdx.x; e < nd * 11; e += BCOL_NT) band[e] = lu[e];
+  const int m = b.npts, K = m - 1, nd = 3 * K, ncol = 2 * m + 1;
+  const int tid = threadIdx.x;
+  const double dt = a.dt;
+  double* A = bsm;           // 9K each: A, L, U contiguous
+  double* Lb = A + 9 * K;
+  double* Ub = Lb + 9 * K;
+  double* Ai = Ub + 9 * K;   // inverse of A_j at the level that eliminates j
+  double* P = Ai + 9 * K;    // per kept block and level: L_i A_{i-s}^{-1}, U_i A_{i+s}^{-1}
+  double* rint = P + 18 * K; // 3m internal forces
+  double* sres = rint + 3 * m;
+  double* rhs = sres + nd;   // [nd][nc]
+  const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
+  const double* xn = a.chi + b.dof0;
+  const double* zn = a.zeta + b.dof0;
+  const double* an = a.zetadot + b.dof0;
+  const double* ms = a.dmass + b.dof0;
+
+  for (int e = tid; e < 27 * K; e += BEAM_NT) A[e] = 0.0;
+  for (int e = tid; e < 3 * m; e += BEAM_NT) rint[e] = 0.0;
   __syncthreads();
-  const int col = blockIdx.x * BCOL_NT + threadIdx.x;
-  if (col >= ncol) return;
-  double* y = a.ywork + b.yoff;  // [nd][2m+1]
-  const double* res = a.dres + b.dof0;
-  if (col < 2 * m) {
-    const int node = col % m, cmp = col / m;
-    const int hot = node > 0 ? 3 * node + cmp - 3 : -1;
-    band_solve(band, nd, [&](int u) { return u == hot ? 1.0 : 0.0; }, y + col, ncol);
-  } else {
-    band_solve(band, nd, [&](int u) { return res[u + 3]; }, y + col, ncol);
+  // element assembly: even then odd elements, so no two threads add to one block
+  for (int parity = 0; parity < 2; ++parity) {
+    for (int el = 2 * tid + parity; el < m - 1; el += 2 * BEAM_NT) {
+      double fe[6], ke[36];
+      beam_element(ck + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el], b.ea, b.ei, fe, ke);
+      for (int p = 0; p < 6; ++p) rint[3 * el + p] += fe[p];
+      const int k0 = el - 1, k1 = el;  // blocks of nodes el and el + 1
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+          if (el >= 1) {
+            A[9 * k0 + 3 * p + q] += ke[p * 6 + q];
+            Ub[9 * k0 + 3 * p + q] += ke[p * 6 + q + 3];
+            Lb[9 * k1 + 3 * p + q] += ke[(p + 3) * 6 + q];
+          }
+          A[9 * k1 + 3 * p + q] += ke[(p + 3) * 6 + q + 3];
+        }
+    }
+    __syncthreads();
   }
+  for (int u = tid; u < nd; u += BEAM_NT) {
+    const int g = u + 3, k = u / 3, c = u % 3;
+    A[9 * k + 4 * c] += 4.0 * ms[g] / (dt * dt);
+    const double rz = ms[g] * (4.0 * xn[g] / (dt * dt) + 4.0 * zn[g] / dt + an[g]);
+    sres[u] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint[g];
+  }
+  __syncthreads();
+
+  // factorisation
+  int po = 0, top = 0;
+  for (int s = 1, lev = 0; s <= K; s *= 2, ++lev) {
+    top = lev;
+    const int ne = (K - s) / (2 * s) + 1;  // eliminated: j = s - 1 + 2 s q
+    for (int t = tid; t < 9 * ne; t += BEAM_NT) {
+      const int j = s - 1 + 2 * s * (t / 9), e = t % 9;
+      Ai[9 * j + e] = inv3_entry(A + 9 * j, e / 3, e % 3);
+    }
+    __syncthreads();
+    const int nk = K >> (lev + 1);  // kept: i = 2 s (q + 1) - 1
+    for (int t = tid; t < 9 * nk; t += BEAM_NT) {
+      const int q = t / 9, e = t % 9, r = e / 3, c = e % 3;
+      const int i = 2 * s * (q + 1) - 1, j1 = i - s, j2 = i + s;
+      double pl = 0.0, pu = 0.0;
+      for (int k = 0; k < 3; ++k) pl += Lb[9 * i + 3 * r + k] * Ai[9 * j1 + 3 * k + c];
+      if (j2 < K)
+        for (int k = 0; k < 3; ++k) pu += Ub[9 * i + 3 * r + k] * Ai[9 * j2 + 3 * k + c];
+      P[18 * (po + q) + e] = pl;
+      P[18 * (po + q) + 9 + e] = pu;
+    }
+    __syncthreads();
+    for (int t = tid; t < 9 * nk; t += BEAM_NT) {
+      const int q = t / 9, e = t % 9, r = e / 3, c = e % 3;
+      const int i = 2 * s * (q + 1) - 1, j1 = i - s, j2 = i + s;
+      const double* pl = P + 18 * (po + q);
+      const double* pu = pl + 9;
+      double av = A[9 * i + e], lv = 0.0, uv = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        av -= pl[3 * r + k] * Ub[9 * j1 + 3 * k + c];
+        lv -= pl[3 * r + k] * Lb[9 * j1 + 3 * k + c];
+      }
+      if (j2 < K)
+        for (int k = 0; k < 3; ++k) {
+          av -= pu[3 * r + k] * Lb[9 * j2 + 3 * k + c];
+          uv -= pu[3 * r + k] * Ub[9 * j2 + 3 * k + c];
+        }
+      A[9 * i + e] = av;
+      Lb[9 * i + e] = lv;
+      Ub[9 * i + e] = uv;
+    }
+    __syncthreads();
+    po += nk;
+  }
+
+  // right-hand sides of this workgroup: columns c0 .. c0 + nc - 1
+  const int c0 = blockIdx.x * nc;
+  for (int t = tid; t < nd * nc; t += BEAM_NT) {
+    const int u = t / nc, col = c0 + t % nc;
+    double v = 0.0;
+    if (col < 2 * m) {
+      const int node = col % m, cmp = col / m;
+      v = (node > 0 && u == 3 * node + cmp - 3) ? 1.0 : 0.0;
+    } else if (col == 2 * m) {
+      v = sres[u];
+    }
+    rhs[t] = v;
+  }
+  __syncthreads();
+  po = 0;
+  for (int s = 1, lev = 0; s <= K; s *= 2, ++lev) {
+    const int nk = K >> (lev + 1);
+    for (int t = tid; t < nk * nc; t += BEAM_NT) {
+      const int q = t / nc, cl = t % nc;
+      const int i = 2 * s * (q + 1) - 1, j1 = i - s, j2 = i + s;
+      const double* pl = P + 18 * (po + q);
+      const double* pu = pl + 9;
+      double bj1[3], bj2[3] = {0.0, 0.0, 0.0}, v[3];
+      for (int k = 0; k < 3; ++k) bj1[k] = rhs[(3 * j1 + k) * nc + cl];
+      if (j2 < K)
+        for (int k = 0; k < 3; ++k) bj2[k] = rhs[(3 * j2 + k) * nc + cl];
+      for (int r = 0; r < 3; ++r) {
+        double x = rhs[(3 * i + r) * nc + cl];
+        for (int k = 0; k < 3; ++k) x -= pl[3 * r + k] * bj1[k] + pu[3 * r + k] * bj2[k];
+        v[r] = x;
+      }
+      for (int r = 0; r < 3; ++r) rhs[(3 * i + r) * nc + cl] = v[r];
+    }
+    __syncthreads();
+    po += nk;
+  }
+  for (int lev = top; lev >= 0; --lev) {
+    const int s = 1 << lev;
+    const int ne = (K - s) / (2 * s) + 1;
+    for (int t = tid; t < ne * nc; t += BEAM_NT) {
+      const int j = s - 1 + 2 * s * (t / nc), cl = t % nc;
+      double w[3];
+      for (int r = 0; r < 3; ++r) w[r] = rhs[(3 * j + r) * nc + cl];
+      if (j - s >= 0)
+        for (int k = 0; k < 3; ++k) {
+          const double x = rhs[(3 * (j - s) + k) * nc + cl];
+          for (int r = 0; r < 3; ++r) w[r] -= Lb[9 * j + 3 * r + k] * x;
+        }
+      if (j + s < K)
+        for (int k = 0; k < 3; ++k) {
+          const double x = rhs[(3 * (j + s) + k) * nc + cl];
+          for (int r = 0; r < 3; ++r) w[r] -= Ub[9 * j + 3 * r + k] * x;
+        }
+      for (int r = 0; r < 3; ++r)
+        rhs[(3 * j + r) * nc + cl] =
+            Ai[9 * j + 3 * r] * w[0] + Ai[9 * j + 3 * r + 1] * w[1] + Ai[9 * j + 3 * r + 2] * w[2];
+    }
+    __syncthreads();
+  }
+  double* y = a.ywork + b.yoff;
+  for (int t = tid; t < nd * nc; t += BEAM_NT) {
+    const int u = t / nc, col = c0 + t % nc;
+    if (col < ncol) y[(size_t)u * ncol + col] = rhs[t];
+  }
+}
+
+size_t beam_lds_bytes(int m, int nc) {
+  const size_t K = m - 1;
+  return (size_t)(54 * K + 3 * m + 3 * K + 3 * K * nc) * 8;
 }
 
 // Deformable part of the Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi).
@@ -634,16 +667,25 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
   if (threadIdx.x == 0) y[r] = red[0];
 }
 
-// Structure update from the new stresses and the convergence measure (one workgroup).
+// Structure update from the new stresses and the convergence measure max |delta|,
+// folded into delta[0] (zeroed by k_structure) with atomicMax on the bit pattern of the
+// non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
+// group of 4 beam rows.
 __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
-  __shared__ double dmax[STRUCT_NT];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int NW = STRUCT_NT / 64;
+  const int gw = blockIdx.x * NW + w, nwaves = gridDim.x * NW;
   double my = 0.0;
+  bool bad = false;
+  auto fold = [&](double d) {
+    if (!(d == d) || d > 1e308) bad = true;
+    else my = fmax(my, d);
+  };
   for (int bi = 0; bi < a.nbodies; ++bi) {
     const BodyDev& b = a.bodies[bi];
     const int m = b.npts, r0 = 2 * b.pt0;
     if (b.kind == BODY_TORSIONAL) {
-      if (tid == 0) {
+      if (gw == 0) {
         double* ts = a.tors + b.tors * TS_COUNT;
         const double dt = a.dt;
         const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
@@ -653,48 +695,66 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
         const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
                             b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
         double sf = 0.0;
-        for (int u = 0; u < 2 * m; ++u) sf += (u < m ? -sn : cs) * (u % m) * b.ds * a.f[r0 + u];
-        const double thn = (rphi + b.ds * sf) / jt;
-        my = fmax(my, fabs(thn - th));
-        ts[TS_NEW] = thn;
+        for (int u = lane; u < 2 * m; u += 64) sf += (u < m ? -sn : cs) * (u % m) * b.ds * a.f[r0 + u];
+        for (int off = 32; off > 0; off >>= 1) sf += __shfl_xor(sf, off);
+        if (lane == 0) {
+          const double thn = (rphi + b.ds * sf) / jt;
+          fold(fabs(thn - th));
+          ts[TS_NEW] = thn;
+        }
       }
     } else if (b.kind == BODY_DEFORMABLE) {
-      // delta chi = J_d^{-1} (res + ds T^T f) = y_res + ds Y f with Y = J_d^{-1} T^T
+      // delta chi = J_d^{-1} (res + ds T^T f) = y_res + ds Y f with Y = J_d^{-1} T^T; lanes
+      // across the columns, every load of a group of rows in flight at once
       const int nd = 3 * m - 3, ncol = 2 * m + 1;
       const double* y = a.ywork + b.yoff;
       const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
       double* cn = a.chi_new + b.dof0;
-      for (int u = tid; u < nd; u += STRUCT_NT) {
-        double acc = 0.0;
-        const double* yr = y + (size_t)u * ncol;
-        int c = 0;
-        for (; c + 8 <= 2 * m; c += 8) {
-          double v[8];
+      constexpr int CQ = 7;  // 2m <= 448 columns
+      for (int u0 = 4 * gw; u0 < nd; u0 += 4 * nwaves) {
+        double v[4][CQ], yr[4], fc[CQ];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = yr[c + e];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) acc += v[e] * a.f[r0 + c + e];
+        for (int k = 0; k < CQ; ++k) {
+          const int c = lane + 64 * k;
+          fc[k] = c < 2 * m ? a.f[r0 + c] : 0.0;
         }
-        for (; c < 2 * m; ++c) acc += yr[c] * a.f[r0 + c];
-        const double dx = y[(size_t)u * ncol + 2 * m] + b.ds * acc;
-        my = fmax(my, fabs(dx));
-        cn[u + 3] = ck[u + 3] + dx;  // ck may alias cn: same thread reads then writes
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = u0 + q;
+          yr[q] = u < nd ? y[(size_t)u * ncol + 2 * m] : 0.0;
+#pragma unroll
+          for (int k = 0; k < CQ; ++k) {
+            const int c = lane + 64 * k;
+            v[q][k] = (u < nd && c < 2 * m) ? y[(size_t)u * ncol + c] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < CQ; ++k) acc += v[q][k] * fc[k];
+          for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+          const int u = u0 + q;
+          if (lane == 0 && u < nd) {
+            const double dx = yr[q] + b.ds * acc;
+            fold(fabs(dx));
+            cn[u + 3] = ck[u + 3] + dx;  // ck may alias cn: this lane reads, then writes
+          }
+        }
       }
-      if (tid == 0) {
+      if (gw == 0 && lane == 0) {
         cn[0] = ck[0];
         cn[1] = ck[1];
         cn[2] = ck[2];
       }
     }
-    __syncthreads();
   }
-  dmax[tid] = my;
-  __syncthreads();
-  for (int s = STRUCT_NT / 2; s > 0; s >>= 1) {
-    if (tid < s) dmax[tid] = fmax(dmax[tid], dmax[tid + s]);
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) my = fmax(my, __shfl_xor(my, off));
+  const bool anybad = __any(bad);
+  if (lane == 0) {
+    const double v = anybad ? INFINITY : my;
+    atomicMax(reinterpret_cast<unsigned long long*>(a.delta), (unsigned long long)__double_as_longlong(v));
   }
-  if (tid == 0) a.delta[0] = dmax[0];
 }
 
 // Newmark completion of the step with the accepted iterate.
@@ -936,91 +996,111 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 // f <- f + X (b - M f) to working accuracy.  A fresh inverse (LU) is made at the
 // first use and whenever the refinement stops contracting.
 
-constexpr int REF_NT = 1024;
-constexpr int REF_MAXN = 4096;
+// ---------------------------------------------- Schur solve by iterative refinement
+// f = X b, then sweeps r = b - M f, f += X r while the relative residual |r|/|b| (max
+// norms) still exceeds 1e-16 n and still halves.  Each matrix-vector product is one
+// launch over many workgroups (one wave per row), so the matrices stream through many
+// CUs; a sweep that follows convergence returns at once.  Workspace `ws` (doubles):
+//   [0] relative residual, [1] sweeps, [2] |b| bits, [3] done flag,
+//   [4 .. 4+maxit) residual norms (bit patterns of non-negative doubles, atomicMax),
+//   [REF_HDR + maxit ..) the residual vector r.
+constexpr int REF_HDR = 8;
+size_t refine_ws_doubles(int n, int maxit) { return (size_t)REF_HDR + maxit + n; }
 
-// y = A x (+ y if accumulate) for one workgroup; x in LDS.  Each wave takes four rows at
-// a time and issues all their loads for four 64-column chunks before accumulating, so
-// 16 loads per lane are in flight.
-__device__ void wg_matvec(const double* A, int pa, const double* x, double* y, int n,
-                          bool accumulate = false) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = REF_NT / 64, RQ = 4, CQ = 4;
-  for (int r0 = w; r0 < n; r0 += RQ * NW) {
-    double acc[RQ];
-#pragma unroll
-    for (int q = 0; q < RQ; ++q) acc[q] = 0.0;
-    for (int c0 = 0; c0 < n; c0 += 64 * CQ) {
-      double v[RQ][CQ];
-#pragma unroll
-      for (int q = 0; q < RQ; ++q)
-#pragma unroll
-        for (int k = 0; k < CQ; ++k) {
-          const int r = r0 + q * NW, c = c0 + k * 64 + lane;
-          v[q][k] = (r < n && c < n) ? A[(size_t)r * pa + c] : 0.0;
-        }
-#pragma unroll
-      for (int k = 0; k < CQ; ++k) {
-        const int c = c0 + k * 64 + lane;
-        const double xc = c < n ? x[c] : 0.0;
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) acc[q] += v[q][k] * xc;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < RQ; ++q) {
-      double s = acc[q];
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
-      const int r = r0 + q * NW;
-      if (lane == 0 && r < n) y[r] = accumulate ? y[r] + s : s;
-    }
-  }
+__device__ inline unsigned long long dbits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
 }
+__device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
 
-__device__ double wg_absmax(const double* v, int n, double* red) {
+__global__ __launch_bounds__(256) void k_ref_reset(const double* b, int n, double* ws, int maxit) {
+  __shared__ double red[4];
+  unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
+  for (int i = threadIdx.x; i < REF_HDR + maxit; i += 256) wu[i] = 0ull;
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += REF_NT) m = fmax(m, fabs(v[i]));
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
-  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = fabs(b[i]);
+    m = (v > m || v != v) ? v : m;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off);
+    m = (o > m || o != o) ? o : m;
+  }
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  double r = 0.0;
-  for (int k = 0; k < REF_NT / 64; ++k) r = fmax(r, red[k]);
-  __syncthreads();
-  return r;
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int k = 1; k < 4; ++k) r = (red[k] > r || red[k] != red[k]) ? red[k] : r;
+    ws[2] = r;
+  }
 }
 
-// info[0] = final relative residual, info[1] = refinement iterations
-__global__ __launch_bounds__(REF_NT) void k_solve_refine(const double* M, int pm, const double* X,
-                                                         const double* b, double* f, int n,
-                                                         int maxit, double* info, int* flags) {
-  __shared__ double sb[REF_MAXN], sf[REF_MAXN], sr[REF_MAXN];
-  __shared__ double red[REF_NT / 64];
-  for (int i = threadIdx.x; i < n; i += REF_NT) sb[i] = b[i];
-  __syncthreads();
-  wg_matvec(X, pm, sb, sf, n);
-  __syncthreads();
-  const double nb = wg_absmax(sb, n, red);
-  double prev = 1e300, rel = 0.0;
-  int it = 0;
-  for (; it < maxit; ++it) {
-    wg_matvec(M, pm, sf, sr, n);
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += REF_NT) sr[i] = sb[i] - sr[i];
-    __syncthreads();
-    const double nr = wg_absmax(sr, n, red);
-    rel = nb > 0.0 ? nr / nb : 0.0;
-    if (!(rel > 1e-16 * n) || !(nr < 0.5 * prev)) break;  // converged or no longer contracting
-    prev = nr;
-    wg_matvec(X, pm, sr, sf, n, true);  // f += X r
-    __syncthreads();
+// mode 0: y = A x;  mode 1: y = b - A x and its max norm into slot `it`;
+// mode 2: convergence test of sweep `it`, then y += A x unless converged.
+__global__ __launch_bounds__(256) void k_ref_matvec(const double* A, int pa, const double* x,
+                                                    const double* b, double* y, int n, int mode,
+                                                    double* ws, int it) {
+  unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
+  if (mode != 0) {
+    if (wu[3] != 0ull) return;
+    if (mode == 2) {
+      const double nr = bitsd(wu[4 + it]);
+      const double prev = it > 0 ? bitsd(wu[4 + it - 1]) : 1e300;
+      const double nb = ws[2];
+      const double rel = nb > 0.0 ? nr / nb : 0.0;
+      if (!(rel > 1e-16 * n) || !(nr < 0.5 * prev)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          ws[0] = rel;
+          ws[1] = it;
+          wu[3] = 1ull;
+        }
+        return;
+      }
+    }
   }
-  for (int i = threadIdx.x; i < n; i += REF_NT) f[i] = sf[i];
-  if (threadIdx.x == 0) {
-    info[0] = rel;
-    info[1] = it;
-    if (!(rel < 1e-9)) atomicMax(&flags[1], 1);  // refinement failed: the inverse is stale
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* ar = A + (size_t)row * pa;
+  constexpr int CQ = 8;
+  double acc = 0.0;
+  for (int c0 = 0; c0 < n; c0 += 64 * CQ) {
+    double av[CQ], xv[CQ];
+#pragma unroll
+    for (int k = 0; k < CQ; ++k) {
+      const int c = c0 + 64 * k + lane;
+      av[k] = c < n ? ar[c] : 0.0;
+      xv[k] = c < n ? x[c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < CQ; ++k) acc += av[k] * xv[k];
   }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    if (mode == 0) {
+      y[row] = acc;
+    } else if (mode == 1) {
+      const double r = b[row] - acc;
+      y[row] = r;
+      const double ar2 = fabs(r);
+      atomicMax(&wu[4 + it], ar2 != ar2 ? 0x7ff8000000000000ull : dbits(ar2));
+    } else {
+      y[row] += acc;
+    }
+  }
+}
+
+__global__ void k_ref_final(double* ws, int maxit, int* flags, double* out) {
+  if (threadIdx.x != 0) return;
+  unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
+  if (wu[3] == 0ull) {
+    const double nr = bitsd(wu[4 + maxit - 1]);
+    const double nb = ws[2];
+    ws[0] = nb > 0.0 ? nr / nb : 0.0;
+    ws[1] = maxit;
+  }
+  if (!(ws[0] < 1e-9)) atomicMax(&flags[1], 1);  // refinement failed: the inverse is stale
+  out[0] = ws[0];
+  out[1] = ws[1];
 }
 
 // C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B.  32 x 32 tiles.
@@ -1069,9 +1149,17 @@ hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
-                               int n, int maxit, double* info, int* flags, hipStream_t st) {
-  if (n > REF_MAXN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_solve_refine, dim3(1), dim3(REF_NT), 0, st, M, pm, X, b, f, n, maxit, info, flags);
+                               int n, int maxit, double* ws, double* out, int* flags, hipStream_t st) {
+  if (n < 1 || maxit < 1) return hipErrorInvalidValue;
+  double* r = ws + REF_HDR + maxit;
+  const dim3 grid((n + 3) / 4), blk(256);
+  hipLaunchKernelGGL(k_ref_reset, dim3(1), blk, 0, st, b, n, ws, maxit);
+  hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, b, b, f, n, 0, ws, 0);
+  for (int it = 0; it < maxit; ++it) {
+    hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, M, pm, f, b, r, n, 1, ws, it);
+    hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, r, b, f, n, 2, ws, it);
+  }
+  hipLaunchKernelGGL(k_ref_final, dim3(1), dim3(64), 0, st, ws, maxit, flags, out);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
@@ -1107,12 +1195,21 @@ hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, in
 }
 hipError_t launch_band_columns(const FsiArgs& a, int bi, int m, hipStream_t st) {
   const int ncol = 2 * m + 1;
-  hipLaunchKernelGGL(k_band_columns, dim3((ncol + BCOL_NT - 1) / BCOL_NT), dim3(BCOL_NT), 0, st, a, bi);
+  // right-hand sides per workgroup: as many as 150 KB of LDS allow, at most 32; the
+  // factorisation is repeated per workgroup, which costs no extra latency
+  int nc = 32;
+  while (nc > 1 && beam_lds_bytes(m, nc) > 150 * 1024) nc /= 2;
+  const size_t lds = beam_lds_bytes(m, nc);
+  if (m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_beam, dim3((ncol + nc - 1) / nc), dim3(BEAM_NT), lds, st, a, bi, nc);
   hipLaunchKernelGGL(k_struct_rhs_def, dim3(1), dim3(256), 0, st, a, bi);
   return hipGetLastError();
 }
 hipError_t launch_update(const FsiArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_update, dim3(1), dim3(STRUCT_NT), 0, st, a);
+  // enough waves for one group of 4 rows of the largest beam (3m - 3 <= 1.5 nf rows)
+  const int groups = (3 * a.nf / 2 + 3) / 4;
+  const int nb = std::max(1, (groups + STRUCT_NT / 64 - 1) / (STRUCT_NT / 64));
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(STRUCT_NT), 0, st, a);
   return hipGetLastError();
 }
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st) {

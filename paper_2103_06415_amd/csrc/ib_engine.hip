@@ -28,6 +28,10 @@ using namespace ib;
 
 namespace {
 
+// refinement sweeps launched per Schur solve; one that has not converged by then makes
+// the solver rebuild its approximate inverse
+constexpr int REFINE_MAXIT = 16;
+
 struct HostBody {
   int kind = BODY_RIGID;
   int m = 0;
@@ -97,14 +101,20 @@ struct ib_solver {
   double* Xn = nullptr;     // Newton-Schulz workspace
   double* W = nullptr;
   double* Mtmp = nullptr;
-  double* rinfo = nullptr;  // refinement info (device)
-  double* hrinfo = nullptr; // pinned mirror
+  double* rinfo = nullptr;  // refinement workspace (device)
   bool x_valid = false;
   bool x_valid_retry = false;
+  int inverse_rebuilds = 0;
+  // control block read back once per FSI iteration: error flags (2 ints), max |delta|,
+  // refinement residual and sweeps; one device copy and its pinned host mirror
+  void* ctl = nullptr;
+  void* hctl = nullptr;
   int* flags = nullptr;
   double* delta = nullptr;
-  int* hflags = nullptr;  // pinned mirrors
+  double* rout = nullptr;
+  int* hflags = nullptr;
   double* hdelta = nullptr;
+  double* hrinfo = nullptr;
   std::vector<double> ds_rows;
   // kernel timing
   bool timing = false;
@@ -578,9 +588,8 @@ ib_status prepare_bodies(ib_solver* s) {
     s->Xn = static_cast<double*>(dalloc(s, mb));
     s->W = static_cast<double*>(dalloc(s, mb));
     s->Mtmp = static_cast<double*>(dalloc(s, mb));
-    s->rinfo = static_cast<double*>(dalloc(s, 16));
+    s->rinfo = static_cast<double*>(dalloc(s, refine_ws_doubles(nf, REFINE_MAXIT) * 8));
     if (!s->Minv || !s->Xn || !s->W || !s->Mtmp || !s->rinfo) return IB_ERR_OOM;
-    if (!s->hrinfo) HIPCHK(hipHostMalloc((void**)&s->hrinfo, 16, hipHostMallocDefault));
     s->x_valid = false;
   }
   a.tors = up(tors);
@@ -596,15 +605,20 @@ ib_status prepare_bodies(ib_solver* s) {
   size_t yw = 0;
   for (auto& hb : s->bodies) if (hb.kind == BODY_DEFORMABLE) yw += (size_t)3 * hb.m * (2 * hb.m + 1);
   a.ywork = static_cast<double*>(dalloc(s, std::max<size_t>(1, yw) * 8));
-  s->flags = static_cast<int*>(dalloc(s, 16));
-  s->delta = static_cast<double*>(dalloc(s, 16));
+  s->ctl = dalloc(s, 64);
+  if (!a.st_base || !a.st_w || !a.M || !s->f || !s->ctl) return IB_ERR_OOM;
+  s->flags = static_cast<int*>(s->ctl);
+  s->delta = reinterpret_cast<double*>(static_cast<char*>(s->ctl) + 8);
+  s->rout = reinterpret_cast<double*>(static_cast<char*>(s->ctl) + 16);
   a.flags = s->flags;
   a.delta = s->delta;
-  if (!a.st_base || !a.st_w || !a.M || !s->f || !s->flags) return IB_ERR_OOM;
-  HIPCHK(hipMemset(s->flags, 0, 16));
-  if (!s->hflags) {
-    HIPCHK(hipHostMalloc((void**)&s->hflags, 16, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&s->hdelta, 16, hipHostMallocDefault));
+  HIPCHK(hipMemset(s->ctl, 0, 64));
+  if (!s->hctl) {
+    HIPCHK(hipHostMalloc(&s->hctl, 64, hipHostMallocDefault));
+    std::memset(s->hctl, 0, 64);
+    s->hflags = static_cast<int*>(s->hctl);
+    s->hdelta = reinterpret_cast<double*>(static_cast<char*>(s->hctl) + 8);
+    s->hrinfo = reinterpret_cast<double*>(static_cast<char*>(s->hctl) + 16);
   }
   if (dof > 0) HIPCHK(launch_beam_init(a, s->stream));
   // operator at the initial configuration
@@ -780,13 +794,14 @@ ib_status fsi_and_correct(ib_solver* s) {
         HIPCHK(launch_identity(s->Minv, a.pm, nf, s->stream));
         HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
         s->x_valid = true;
+        s->inverse_rebuilds++;
       } else if (it == 0) {
         // one Newton-Schulz step towards the new matrix: X <- X (2I - M X)
         HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream));
         HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream));
         std::swap(s->Minv, s->Xn);
       }
-      HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, 12, s->rinfo, s->flags,
+      HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, REFINE_MAXIT, s->rinfo, s->rout, s->flags,
                                  s->stream));
       HIPCHK(launch_update(a, s->stream));
     }
@@ -794,8 +809,7 @@ ib_status fsi_and_correct(ib_solver* s) {
     if (fixed > 0) {
       done = it + 1 >= fixed;
       if (done) {
-        HIPCHK(hipMemcpyAsync(s->hflags, s->flags, 8, hipMemcpyDeviceToHost, s->stream));
-        HIPCHK(hipMemcpyAsync(s->hdelta, s->delta, 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 32, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         if (s->hflags[1]) {
           s->last_error = "Schur refinement did not converge";
@@ -803,8 +817,7 @@ ib_status fsi_and_correct(ib_solver* s) {
         }
       }
     } else {
-      HIPCHK(hipMemcpyAsync(s->hflags, s->flags, 8, hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(hipMemcpyAsync(s->hdelta, s->delta, 8, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 32, hipMemcpyDeviceToHost, s->stream));
       HIPCHK(hipStreamSynchronize(s->stream));
       ib_status st = map_flags(s, s->hflags[0]);
       if (st) return st;
@@ -1239,6 +1252,9 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   out->subdomain_points = s->use_sd ? 2 * (int64_t)s->sd_total : 0;
   out->subdomain_nnz = s->bp_nnz;
   out->prepare_seconds = s->prepare_seconds;
+  out->refine_iters = s->hrinfo ? (int32_t)s->hrinfo[1] : 0;
+  out->refine_residual = s->hrinfo ? s->hrinfo[0] : 0.0;
+  out->inverse_rebuilds = s->inverse_rebuilds;
   return IB_OK;
 }
 
@@ -1270,8 +1286,7 @@ ib_status ib_destroy(ib_solver* s) {
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
   s->event_pool.clear();
   while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
-  if (s->hflags) (void)hipHostFree(s->hflags);
-  if (s->hdelta) (void)hipHostFree(s->hdelta);
+  if (s->hctl) (void)hipHostFree(s->hctl);
   delete s;
   return IB_OK;
 }

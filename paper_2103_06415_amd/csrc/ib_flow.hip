@@ -24,20 +24,43 @@ __device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
   return p[(size_t)j * pitch + i];
 }
 
+// Circulation seen by the stencil at vertex (i, j) of the level, 0 <= i, j <= n:
+// boundary ring, coarsification on read (the finer level's circulation at the
+// coincident vertex, scaled by (h_coarse / h_fine)^2 = 4) or the level's own interior.
+// Written with selects so that the single load can be issued early.
 template <typename T>
 __device__ __forceinline__ T gamma_at(const RhsArgs<T>& a, int i, int j) {
   const int n = a.n;
-  if (j == 0) return a.gring[RING_B * (n + 1) + i];
-  if (j == n) return a.gring[RING_T * (n + 1) + i];
-  if (i == 0) return a.gring[RING_L * (n + 1) + j];
-  if (i == n) return a.gring[RING_R * (n + 1) + j];
+  const T* p = a.g;
+  long idx = (long)(j - 1) * a.pg + (i - 1);
+  T sc = T(1);
   if (a.gf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
-    // coarsification on read: the finer level's circulation at the coincident vertex,
-    // scaled by (h_coarse / h_fine)^2 = 4
-    const int fi = 2 * i - n / 2, fj = 2 * j - n / 2;
-    return T(4) * a.gf[(size_t)(fj - 1) * a.pgf + (fi - 1)];
+    p = a.gf;
+    idx = (long)(2 * j - n / 2 - 1) * a.pgf + (2 * i - n / 2 - 1);
+    sc = T(4);
   }
-  return a.g[(size_t)(j - 1) * a.pg + (i - 1)];
+  if (i == n) { p = a.gring; idx = RING_R * (n + 1) + j; sc = T(1); }
+  if (i == 0) { p = a.gring; idx = RING_L * (n + 1) + j; sc = T(1); }
+  if (j == n) { p = a.gring; idx = RING_T * (n + 1) + i; sc = T(1); }
+  if (j == 0) { p = a.gring; idx = RING_B * (n + 1) + i; sc = T(1); }
+  return sc * p[idx];
+}
+
+// Copy the twiddle table (2N entries) into LDS, all loads of a thread in flight at once.
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_table(c2<T>* stw, const c2<T>* __restrict__ tw, int tid) {
+  constexpr int PER = (2 * N + NT - 1) / NT;
+  c2<T> v[PER];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = tid + b * NT;
+    if (e < 2 * N) v[b] = tw[e];
+  }
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = tid + b * NT;
+    if (e < 2 * N) stw[e] = v[b];
+  }
 }
 
 // Sum of the new boundary-ring values adjacent to interior vertex (i, j).
@@ -51,54 +74,112 @@ __device__ __forceinline__ T ring_adj(const T* ring, int n, int i, int j) {
   return v;
 }
 
-// Right-hand side at interior vertex (i, j); writes C^T N_n to the history.
-template <typename T>
-__device__ __forceinline__ T rhs_point(const RhsArgs<T>& a, int i, int j) {
-  const T* s = a.s;
-  const int p = a.ps;
-  const T g0 = gamma_at(a, i, j);
-  const T gE = gamma_at(a, i + 1, j), gW = gamma_at(a, i - 1, j);
-  const T gN = gamma_at(a, i, j + 1), gS = gamma_at(a, i, j - 1);
+// Right-hand side at interior vertex (i, j) from staged rows: ss / sg hold s and gamma
+// of rows j-1, j, j+1 (each W wide, column index = i); hprev is C^T N_{n-1} (or NaN-free
+// copy of the new value on the first step); writes C^T N_n to the history.
+template <typename T, int W>
+__device__ __forceinline__ T rhs_staged(const RhsArgs<T>& a, const T* ss, const T* sg, int i, int j,
+                                        T hprev_in, bool has_prev) {
+  const T* sm = ss;          // row j-1
+  const T* sp = ss + 2 * W;  // row j+1
+  const T* gm = sg;
+  const T* g0r = sg + W;
+  const T* gp = sg + 2 * W;
+  const T g0 = g0r[i];
+  const T gE = g0r[i + 1], gW = g0r[i - 1];
+  const T gN = gp[i], gS = gm[i];
   // vertex-averaged fluxes (total flux, free stream included)
-  const T uE = T(0.5) * (ld(s, p, j + 1, i + 1) - ld(s, p, j - 1, i + 1)) + a.ux;
-  const T uW = T(0.5) * (ld(s, p, j + 1, i - 1) - ld(s, p, j - 1, i - 1)) + a.ux;
-  const T vN = T(0.5) * (ld(s, p, j + 1, i - 1) - ld(s, p, j + 1, i + 1)) + a.uy;
-  const T vS = T(0.5) * (ld(s, p, j - 1, i - 1) - ld(s, p, j - 1, i + 1)) + a.uy;
+  const T uE = T(0.5) * (sp[i + 1] - sm[i + 1]) + a.ux;
+  const T uW = T(0.5) * (sp[i - 1] - sm[i - 1]) + a.ux;
+  const T vN = T(0.5) * (sp[i - 1] - sp[i + 1]) + a.uy;
+  const T vS = T(0.5) * (sm[i - 1] - sm[i + 1]) + a.uy;
   // C^T N with N = (vbar gamma, -ubar gamma) / h^2 averaged onto the faces
   const T ctn = a.cn * ((uE * gE - uW * gW) + (vN * gN - vS * gS));
-  const size_t hidx = (size_t)(j - 1) * a.ph + (i - 1);
-  const T hprev = a.hist_in ? a.hist_in[hidx] : ctn;
-  a.hist_out[hidx] = ctn;
+  a.hist_out[(size_t)(j - 1) * a.ph + (i - 1)] = ctn;
+  const T hprev = has_prev ? hprev_in : ctn;
   const T lap = T(4) * g0 - gE - gW - gN - gS;
   T r = g0 - a.alpha * lap + a.dt * (T(1.5) * ctn - T(0.5) * hprev);
   if (a.gring_new != nullptr) r += a.alpha * ring_adj(a.gring_new, a.n, i, j);
   return r;
 }
 
+// Explicit right-hand side of ROWS interior rows fused with their row DST.  The rows
+// j-1 .. j+ROWS of s and gamma are staged in LDS (every load of a thread in flight at
+// once); the staging area is then reused as the transform buffer.
 template <typename T, int N, int ROWS, int NT>
 __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __restrict__ tw,
                                                    int nblocks) {
-  __shared__ c2<T> buf[ROWS * N];
+  constexpr int W = N + 1;           // staged row width, ring columns included
+  constexpr int SR = ROWS + 2;       // staged rows j0-1 .. j0+ROWS
+  constexpr int STG = 2 * SR * W;    // s and gamma, in T units
+  constexpr int BUFT = 2 * ROWS * N; // transform buffer, in T units
+  constexpr int UNI = (STG > BUFT ? STG : BUFT) / 2 + 1;
+  __shared__ c2<T> uni[UNI];
+  __shared__ c2<T> stw[2 * N];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
   const int j0 = 1 + blk * ROWS;
-  for (int e = tid; e < ROWS * (N - 1); e += NT) {
-    const int t = e / (N - 1), i = 1 + e % (N - 1);
-    const int j = j0 + t;
-    T v = T(0);
-    if (j <= N - 1) v = rhs_point(a, i, j);
-    dst_pack<T, N>(buf + t * N, i, v);
+  T* ss = reinterpret_cast<T*>(uni);
+  T* sg = ss + SR * W;
+  constexpr int NPT = ROWS * (N - 1);
+  constexpr int PP = (NPT + NT - 1) / NT;
+  T hp[PP];
+  {
+    constexpr int CNT = SR * W;
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T vs[PER], vg[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int r = e / W, i = e % W, j = j0 - 1 + r;
+      const bool ok = e < CNT && j <= N;
+      vs[b] = ok ? a.s[(size_t)j * a.ps + i] : T(0);
+      vg[b] = ok ? gamma_at(a, i, j) : T(0);
+    }
+#pragma unroll
+    for (int b = 0; b < PP; ++b) {
+      const int e = tid + b * NT;
+      const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
+      hp[b] = (a.hist_in != nullptr && e < NPT && j <= N - 1)
+                  ? a.hist_in[(size_t)(j - 1) * a.ph + (i - 1)] : T(0);
+    }
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) {
+        ss[e] = vs[b];
+        sg[e] = vg[b];
+      }
+    }
+  }
+  __syncthreads();
+  T rv[PP];
+#pragma unroll
+  for (int b = 0; b < PP; ++b) {
+    const int e = tid + b * NT;
+    const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
+    rv[b] = (e < NPT && j <= N - 1)
+                ? rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr)
+                : T(0);
+  }
+  __syncthreads();  // the staging area becomes the transform buffer
+  c2<T>* buf = uni;
+#pragma unroll
+  for (int b = 0; b < PP; ++b) {
+    const int e = tid + b * NT;
+    if (e < NPT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), rv[b]);
   }
   for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
   __syncthreads();
-  fft_lds<T, N, ROWS, NT>(buf, tw, tid);
+  fft_lds<T, N, ROWS, NT>(buf, stw, tid);
   for (int e = tid; e < ROWS * (N / 2); e += NT) {
     const int t = e / (N / 2), k = 1 + e % (N / 2);
     const int j = j0 + t;
     if (j > N - 1) continue;
     T xk, xnk;
-    dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
+    dst_unpack<T, N>(buf + t * N, stw, k, xk, xnk);
     T* o = a.out + (size_t)(j - 1) * a.po;
     o[k - 1] = xk;
     if (k != N / 2) o[N - k - 1] = xnk;
@@ -111,28 +192,39 @@ template <typename T, int N, int ROWS, int NT>
 __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __restrict__ tw,
                                                int nblocks) {
   __shared__ c2<T> buf[ROWS * N];
+  __shared__ c2<T> stw[2 * N];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
   T* out = a.out + (size_t)blockIdx.y * a.bso;
   const int j0 = a.r0 + blk * ROWS;
-  for (int e = tid; e < ROWS * (N - 1); e += NT) {
-    const int t = e / (N - 1), i = 1 + e % (N - 1);
-    const int j = j0 + t;
-    T v = T(0);
-    if (j <= a.r1) v = in[(size_t)(j - 1) * a.pi + (i - 1)];
-    dst_pack<T, N>(buf + t * N, i, v);
+  {
+    constexpr int CNT = ROWS * (N - 1);
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
+      v[b] = (e < CNT && j <= a.r1) ? in[(size_t)(j - 1) * a.pi + (i - 1)] : T(0);
+    }
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), v[b]);
+    }
   }
   for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
   __syncthreads();
-  fft_lds<T, N, ROWS, NT>(buf, tw, tid);
+  fft_lds<T, N, ROWS, NT>(buf, stw, tid);
   for (int e = tid; e < ROWS * (N / 2); e += NT) {
     const int t = e / (N / 2), k = 1 + e % (N / 2);
     const int j = j0 + t;
     if (j > a.r1) continue;
     T xk, xnk;
-    dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
+    dst_unpack<T, N>(buf + t * N, stw, k, xk, xnk);
     T* o = out + (size_t)(j - 1) * a.po;
     o[k - 1] = xk;
     if (k != N / 2) o[N - k - 1] = xnk;
@@ -147,29 +239,43 @@ template <typename T, int N, int CW, int NT>
 __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
                                                   const T* __restrict__ lam, int nblocks) {
   __shared__ c2<T> buf[CW * N];
+  __shared__ c2<T> stw[2 * N];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
   const int k0 = blk * CW;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
-  T* out = a.out + (size_t)blockIdx.y * a.bso;
-  for (int e = tid; e < (N - 1) * CW; e += NT) {
-    const int r = e / CW, c = e % CW;
-    const int col = k0 + c;
-    T v = T(0);
-    if (col < N - 1) {
+  {
+    constexpr int CNT = (N - 1) * CW;
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+    const int rf = a.rfirst != nullptr ? a.rfirst[blockIdx.y] : 0;
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int r = e / CW, col = k0 + e % CW;
+      bool ok = e < CNT && col < N - 1;
+      long idx;
       if (a.rfirst != nullptr) {
-        const int q = r + 1 - a.rfirst[blockIdx.y];
-        if (q >= 0 && q < a.rcount) v = in[(size_t)q * a.pi + col];
-      } else if (r + 1 >= a.r0 && r + 1 <= a.r1) {
-        v = in[(size_t)r * a.pi + col];
+        const int q = r + 1 - rf;
+        ok = ok && q >= 0 && q < a.rcount;
+        idx = (long)q * a.pi + col;
+      } else {
+        ok = ok && r + 1 >= a.r0 && r + 1 <= a.r1;
+        idx = (long)r * a.pi + col;
       }
+      v[b] = ok ? in[idx] : T(0);
     }
-    dst_pack<T, N>(buf + c * N, r + 1, v);
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e % CW) * N, e / CW + 1, v[b]);
+    }
   }
   for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
   __syncthreads();
-  fft_lds<T, N, CW, NT>(buf, tw, tid);
+  fft_lds<T, N, CW, NT>(buf, stw, tid);
   constexpr int NP = CW * (N / 2);
   constexpr int PER = (NP + NT - 1) / NT;
   T xa[PER], xb[PER];   // forward column transform, raw
@@ -182,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
     if (e < NP) {
       const int c = e % CW, l = 1 + e / CW;
       const int col = k0 + c;
-      dst_unpack<T, N>(buf + c * N, tw, l, xa[b], xb[b]);
+      dst_unpack<T, N>(buf + c * N, stw, l, xa[b], xb[b]);
       const T lk = (col < N - 1) ? lam[col] : T(1);
       const T l1 = lk + lam[l - 1];
       const T l2 = lk + lam[N - l - 1];
@@ -195,9 +301,9 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       if (a.lift != nullptr && col < N - 1) {
         // sum_{i,j} B(s_ring)_{ij} sin(pi i k / n) sin(pi j l / n) over the four edges
         const int k = col + 1;
-        const T sk = -tw[k].y, sl = -tw[l].y;  // sin(pi k/n), sin(pi l/n) = sin(pi (n-l)/n)
-        const T pk = (k & 1) ? T(1) : T(-1);   // (-1)^(k+1)
-        const T pl = (l & 1) ? T(1) : T(-1);   // (-1)^(l+1) = (-1)^(n-l+1)
+        const T sk = -stw[k].y, sl = -stw[l].y;  // sin(pi k/n), sin(pi l/n) = sin(pi (n-l)/n)
+        const T pk = (k & 1) ? T(1) : T(-1);     // (-1)^(k+1)
+        const T pl = (l & 1) ? T(1) : T(-1);     // (-1)^(l+1) = (-1)^(n-l+1)
         const T* L = a.lift;
         const T eb_k = L[0 * (N - 1) + k - 1], et_k = L[1 * (N - 1) + k - 1];
         fa[b] = eb_k * sl + et_k * sl * pl + sk * L[2 * (N - 1) + l - 1] +
@@ -210,6 +316,17 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   const int nout = a.out2 != nullptr ? 2 : 1;
   for (int o = 0; o < nout; ++o) {
     T* dst = (o == 0 ? a.out : a.out2) + (size_t)blockIdx.y * a.bso;
+    // previous values of the accumulated outputs, fetched while the transform runs
+    T pa[PER], pb[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int c = e % CW, j = 1 + e / CW, col = k0 + c, j2 = N - j;
+      const bool ok = a.accumulate && e < NP && col < N - 1;
+      pa[b] = (ok && j >= a.w0 && j <= a.w1) ? dst[(size_t)(j - 1) * a.po + col] : T(0);
+      pb[b] = (ok && j != N / 2 && j2 >= a.w0 && j2 <= a.w1) ? dst[(size_t)(j2 - 1) * a.po + col]
+                                                              : T(0);
+    }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
@@ -225,22 +342,19 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
     }
     for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
     __syncthreads();
-    fft_lds<T, N, CW, NT>(buf, tw, tid);
-    for (int e = tid; e < NP; e += NT) {
+    fft_lds<T, N, CW, NT>(buf, stw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e >= NP) continue;
       const int c = e % CW, j = 1 + e / CW;
       const int col = k0 + c;
       if (col >= N - 1) continue;
       T yk, ynk;
-      dst_unpack<T, N>(buf + c * N, tw, j, yk, ynk);
-      if (j >= a.w0 && j <= a.w1) {
-        T* o1 = dst + (size_t)(j - 1) * a.po + col;
-        *o1 = a.accumulate ? *o1 + yk : yk;
-      }
+      dst_unpack<T, N>(buf + c * N, stw, j, yk, ynk);
+      if (j >= a.w0 && j <= a.w1) dst[(size_t)(j - 1) * a.po + col] = pa[b] + yk;
       const int j2 = N - j;
-      if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) {
-        T* o2 = dst + (size_t)(j2 - 1) * a.po + col;
-        *o2 = a.accumulate ? *o2 + ynk : ynk;
-      }
+      if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) dst[(size_t)(j2 - 1) * a.po + col] = pb[b] + ynk;
     }
   }
 }
@@ -256,29 +370,40 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
                                                  int nblocks) {
   constexpr int NS = ROWS * (DUAL ? 2 : 1);
   __shared__ c2<T> buf[NS * N];
+  __shared__ c2<T> stw[2 * N];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
   T* out = a.out + (size_t)blockIdx.y * a.bso;
   const int j0 = a.r0 + blk * ROWS;
-  for (int e = tid; e < NS * (N - 1); e += NT) {
-    const int t = e / (N - 1), k = 1 + e % (N - 1);
-    const int j = j0 + (t % ROWS);
-    const T* src = t < ROWS ? in : a.in2;
-    T v = T(0);
-    if (j <= a.r1) v = src[(size_t)(j - 1) * a.pi + (k - 1)];
-    dst_pack<T, N>(buf + t * N, k, v);
+  {
+    constexpr int CNT = NS * (N - 1);
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int t = e / (N - 1), k = 1 + e % (N - 1), j = j0 + (t % ROWS);
+      const T* src = t < ROWS ? in : a.in2;
+      v[b] = (e < CNT && j <= a.r1) ? src[(size_t)(j - 1) * a.pi + (k - 1)] : T(0);
+    }
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), v[b]);
+    }
   }
   for (int t = tid; t < NS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
   __syncthreads();
-  fft_lds<T, N, NS, NT>(buf, tw, tid);
+  fft_lds<T, N, NS, NT>(buf, stw, tid);
   for (int e = tid; e < NS * (N / 2); e += NT) {
     const int t = e / (N / 2), k = 1 + e % (N / 2);
     const int j = j0 + (t % ROWS);
     if (j > a.r1) continue;
     T xk, xnk;
-    dst_unpack<T, N>(buf + t * N, tw, k, xk, xnk);
+    dst_unpack<T, N>(buf + t * N, stw, k, xk, xnk);
     if (t >= ROWS) {
       T* o = a.out2 + (size_t)(j - 1) * a.po;
       o[k - 1] = xk;
@@ -356,18 +481,31 @@ template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
                                                       const c2<T>* __restrict__ tw, T* lift) {
   __shared__ c2<T> buf[4 * N];
+  __shared__ c2<T> stw[2 * N];
   const int tid = threadIdx.x;
-  for (int e = tid; e < 4 * (N - 1); e += NT) {
-    const int edge = e / (N - 1), idx = 1 + e % (N - 1);
-    dst_pack<T, N>(buf + edge * N, idx, sring[edge * (N + 1) + idx]);
+  {
+    constexpr int CNT = 4 * (N - 1);
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      v[b] = e < CNT ? sring[(e / (N - 1)) * (N + 1) + 1 + e % (N - 1)] : T(0);
+    }
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), v[b]);
+    }
   }
   for (int edge = tid; edge < 4; edge += NT) dst_pack_zeros<T, N>(buf + edge * N);
   __syncthreads();
-  fft_lds<T, N, 4, NT>(buf, tw, tid);
+  fft_lds<T, N, 4, NT>(buf, stw, tid);
   for (int e = tid; e < 4 * (N / 2); e += NT) {
     const int edge = e / (N / 2), k = 1 + e % (N / 2);
     T xk, xnk;
-    dst_unpack<T, N>(buf + edge * N, tw, k, xk, xnk);
+    dst_unpack<T, N>(buf + edge * N, stw, k, xk, xnk);
     lift[edge * (N - 1) + k - 1] = xk;
     if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
   }
