@@ -138,6 +138,7 @@ __global__ void k_body_ops(FsiArgs a) {
         pidx[e] = comp * a.sd_total + app;
         pw[e] = e == 0 ? 1.0 : 0.0;
       }
+      a.act[pidx[0]] = 4 * row;
     } else {
       const double xs0 = a.x0 + a.sd_i0 * a.h, ys0 = a.y0 + a.sd_j0 * a.h;
       const double rx = (px - xs0) / a.h, ry = (py - ys0) / a.h;
@@ -168,6 +169,7 @@ __global__ void k_body_ops(FsiArgs a) {
         for (int e = 0; e < 4; ++e) {
           pidx[e] = comp * a.sd_total + (iy + dy[e]) * a.sd_npx + (ix + dx[e]);
           pw[e] = hw[e];
+          if (hw[e] != 0.0) a.act[pidx[e]] = 4 * row + e;  // any writer of a shared row wins
           for (int u = 0; u < 3; ++u)
             for (int v = 0; v < 2; ++v) {
               const double c = hw[e] * (across[u] * kh);
@@ -197,24 +199,10 @@ __global__ void k_body_ops(FsiArgs a) {
   }
 }
 
-// Entry (c, d) of B' by binary search in CSR row c.
-__device__ __forceinline__ double bp_lookup(const FsiArgs& a, int c, int d) {
-  int64_t lo = a.bp_ptr[c], hi = a.bp_ptr[c + 1];
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    const int v = a.bp_col[mid];
-    if (v == d) return a.bp_val[mid];
-    if (v < d) lo = mid + 1;
-    else hi = mid;
-  }
-  return 0.0;
-}
-
 __device__ __forceinline__ double row_ds(const FsiArgs& a, int row) {
-  const int p = row >> 1;  // rows of a body are 2 pt0 .. 2 pt0 + 2m - 1
+  // rows of body bi are 2 pt0 .. 2 pt0 + 2m - 1
   int bi = 0;
   while (bi + 1 < a.nbodies && 2 * a.bodies[bi + 1].pt0 <= row) ++bi;
-  (void)p;
   return a.bodies[bi].ds;
 }
 
@@ -224,53 +212,102 @@ __device__ __forceinline__ int row_body(const FsiArgs& a, int row) {
   return bi;
 }
 
-// Schur matrix in sub-domain mode, one entry per thread:
+// Schur matrix in sub-domain mode, one workgroup per row a:
 //   M_ab = (dt/h^2) (P B' P^T)_ab ds_b + structural block of the body owning a and b:
 //   torsional (2 ds/dt) S_a S_b / J,  deformable (2 ds/dt) (T J_d^{-1} T^T)_ab, the latter
-//   from the columns J_d^{-1} T^T that k_structure left in ywork (so it runs first).
-__global__ void k_schur_sd(FsiArgs a) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nf * a.nf) return;
-  const int r = e / a.nf, c = e % a.nf;
-  double acc = 0.0;
-  for (int u = 0; u < 4; ++u) {
-    const double wu = a.p_w[4 * r + u];
-    if (wu == 0.0) continue;
-    const int cu = a.p_idx[4 * r + u];
-    double inner = 0.0;
-    for (int v = 0; v < 4; ++v) {
-      const double wv = a.p_w[4 * c + v];
-      if (wv == 0.0) continue;
-      inner += wv * bp_lookup(a, cu, a.p_idx[4 * c + v]);
-    }
-    acc += wu * inner;
+//   from the columns J_d^{-1} T^T that k_beam left in ywork (so it runs first).
+// For each of the (up to 4) B' rows that P uses in row a, the CSR row is scanned once
+// and the entries in columns that P uses anywhere are scattered into an LDS vector
+// indexed by the P slot that names the column (act/canon, set by k_body_ops and
+// k_structure); row a of P B' P^T is then a gather from that vector.
+// Dynamic LDS: acc, pw (4 nf doubles each), cid, pidx (4 nf ints each).
+constexpr int SCHUR_NT = 256;
+constexpr int SCHUR_CPT = 8;  // columns per thread: nf <= 2048
+__global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a) {
+  extern __shared__ double ssm[];
+  const int nf = a.nf, ns = 4 * nf, r = blockIdx.x, tid = threadIdx.x;
+  double* acc = ssm;
+  double* pw = acc + ns;
+  int* cid = reinterpret_cast<int*>(pw + ns);
+  int* pidx = cid + ns;
+  for (int e = tid; e < ns; e += SCHUR_NT) {
+    pw[e] = a.p_w[e];
+    cid[e] = a.canon[e];
+    pidx[e] = a.p_idx[e];
   }
-  const int bc = row_body(a, c);
-  double m = (a.dt / (a.h * a.h)) * acc * a.bodies[bc].ds;
-  const BodyDev& b = a.bodies[bc];
-  const int r0 = 2 * b.pt0, mpts = b.npts;
-  if (r >= r0 && r < r0 + 2 * mpts && b.kind != BODY_RIGID) {
-    const int u = r - r0, v = c - r0;
-    const double coef = 2.0 * b.ds / a.dt;
-    if (b.kind == BODY_TORSIONAL) {
-      const double* ts = a.tors + b.tors * TS_COUNT;
-      const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
-      const double ang = b.theta0 + th;
-      const double sn = sin(ang), cs = cos(ang);
-      const double dt = a.dt;
-      const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
-      const double su = (u < mpts ? -sn : cs) * (u % mpts) * b.ds;
-      const double sv = (v < mpts ? -sn : cs) * (v % mpts) * b.ds;
-      m += (coef / jt) * su * sv;
-    } else {
-      const int node = u % mpts, cmp = u / mpts;
-      if (node > 0) {
-        const int du = 3 * node + cmp - 3;
-        m += coef * a.ywork[b.yoff + (size_t)du * (2 * mpts + 1) + v];
+  __syncthreads();
+  double m[SCHUR_CPT];
+#pragma unroll
+  for (int k = 0; k < SCHUR_CPT; ++k) m[k] = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const double wu = pw[4 * r + u];
+    if (wu == 0.0) continue;  // uniform over the workgroup
+    const int cu = pidx[4 * r + u];
+    for (int e = tid; e < ns; e += SCHUR_NT) acc[e] = 0.0;
+    __syncthreads();
+    const int64_t lo = a.bp_ptr[cu], hi = a.bp_ptr[cu + 1];
+    constexpr int Q = 4;
+    for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)Q * SCHUR_NT) {
+      int j[Q], id[Q];
+      double v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t e = e0 + tid + (int64_t)q * SCHUR_NT;
+        j[q] = e < hi ? a.bp_col[e] : -1;
+        v[q] = e < hi ? a.bp_val[e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) id[q] = j[q] >= 0 ? a.act[j[q]] : -1;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (id[q] >= 0 && id[q] < ns && pw[id[q]] != 0.0 && pidx[id[q]] == j[q]) acc[id[q]] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCHUR_CPT; ++k) {
+      const int c = tid + k * SCHUR_NT;
+      if (c < nf) {
+        double inner = 0.0;
+        for (int v = 0; v < 4; ++v) {
+          const double wv = pw[4 * c + v];
+          if (wv != 0.0) inner += wv * acc[cid[4 * c + v]];
+        }
+        m[k] += wu * inner;
       }
     }
+    __syncthreads();
   }
-  a.M[(size_t)r * a.pm + c] = m;
+#pragma unroll
+  for (int k = 0; k < SCHUR_CPT; ++k) {
+    const int c = tid + k * SCHUR_NT;
+    if (c >= nf) continue;
+    const int bc = row_body(a, c);
+    const BodyDev& b = a.bodies[bc];
+    double mv = (a.dt / (a.h * a.h)) * m[k] * b.ds;
+    const int r0 = 2 * b.pt0, mpts = b.npts;
+    if (r >= r0 && r < r0 + 2 * mpts && b.kind != BODY_RIGID) {
+      const int u = r - r0, v = c - r0;
+      const double coef = 2.0 * b.ds / a.dt;
+      if (b.kind == BODY_TORSIONAL) {
+        const double* ts = a.tors + b.tors * TS_COUNT;
+        const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
+        const double ang = b.theta0 + th;
+        const double sn = sin(ang), cs = cos(ang);
+        const double dt = a.dt;
+        const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
+        const double su = (u < mpts ? -sn : cs) * (u % mpts) * b.ds;
+        const double sv = (v < mpts ? -sn : cs) * (v % mpts) * b.ds;
+        mv += (coef / jt) * su * sv;
+      } else {
+        const int node = u % mpts, cmp = u / mpts;
+        if (node > 0) {
+          const int du = 3 * node + cmp - 3;
+          mv += coef * a.ywork[b.yoff + (size_t)du * (2 * mpts + 1) + v];
+        }
+      }
+    }
+    a.M[(size_t)r * a.pm + c] = mv;
+  }
 }
 
 // -------------------------------------------------------- corotational beam
@@ -329,6 +366,9 @@ __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_
   (void)flow_in_M;  // the flow block is either already in M or not used (stationary inverse)
   if (tid == 0) a.delta[0] = 0.0;  // k_update folds its maxima in with atomicMax
   for (int r = tid; r < a.nf; r += STRUCT_NT) a.rhs[r] = a.ustar[r];
+  if (a.act != nullptr)
+    for (int e = tid; e < 4 * a.nf; e += STRUCT_NT)
+      a.canon[e] = a.p_w[e] != 0.0 ? a.act[a.p_idx[e]] : -1;
   __syncthreads();
   const double dt = a.dt;
   for (int bi = 0; bi < a.nbodies; ++bi) {
@@ -1176,8 +1216,9 @@ hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
-  const int tot = a.nf * a.nf;
-  hipLaunchKernelGGL(k_schur_sd, dim3((tot + 255) / 256), dim3(256), 0, st, a);
+  const size_t lds = (size_t)a.nf * SCHUR_LDS_PER_ROW;
+  if (lds > SCHUR_LDS_MAX || a.nf > SCHUR_CPT * SCHUR_NT) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_schur_sd, dim3(a.nf), dim3(SCHUR_NT), lds, st, a);
   return hipGetLastError();
 }
 hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st) {

@@ -50,6 +50,8 @@ struct FsiArgs {
   double* st_w;
   int* p_idx;
   double* p_w;
+  int* act;            // per B' row: a slot e (= 4 row + corner) of P that uses it
+  int* canon;          // per slot of P: the slot act[] names for its B' row (-1 if weight 0)
   double* pos;         // current point positions (2 per point)
   // FSI vectors and matrix
   double* ustar;       // (1/h) E (C s* + q_inf)
@@ -87,6 +89,9 @@ struct OffRows {
 
 template <typename T>
 hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st);
+// LDS of the sub-domain Schur assembly per body row (acc, pw, cid, pidx) and its cap
+constexpr size_t SCHUR_LDS_PER_ROW = 4 * (8 + 8 + 4 + 4);
+constexpr size_t SCHUR_LDS_MAX = 150 * 1024;
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st);
 hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st);
 hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,

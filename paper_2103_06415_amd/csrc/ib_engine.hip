@@ -574,6 +574,17 @@ ib_status prepare_bodies(ib_solver* s) {
   a.st_w = static_cast<double*>(dalloc(s, (size_t)nf * 16 * 8));
   a.p_idx = static_cast<int*>(dalloc(s, (size_t)nf * 4 * 4));
   a.p_w = static_cast<double*>(dalloc(s, (size_t)nf * 4 * 8));
+  a.canon = static_cast<int*>(dalloc(s, (size_t)nf * 4 * 4));
+  a.act = nullptr;
+  if (s->use_sd) {
+    if ((size_t)nf * SCHUR_LDS_PER_ROW > SCHUR_LDS_MAX) {
+      s->last_error = "too many body points for the sub-domain Schur assembly";
+      return IB_ERR_CAPACITY;
+    }
+    a.act = static_cast<int*>(dalloc(s, (size_t)2 * s->sd_total * 4));
+    if (!a.act) return IB_ERR_OOM;
+    HIPCHK(hipMemset(a.act, 0xff, (size_t)2 * s->sd_total * 4));
+  }
   a.pos = static_cast<double*>(dalloc(s, (size_t)s->npts * 2 * 8));
   a.ustar = static_cast<double*>(dalloc(s, (size_t)nf * 8));
   s->f = static_cast<double*>(dalloc(s, (size_t)nf * 8));
