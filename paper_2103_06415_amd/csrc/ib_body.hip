@@ -419,8 +419,10 @@ __device__ inline double inv3_entry(const double* a, int r, int c) {
   return cof(c, r) / det;
 }
 
-constexpr int BEAM_NT = 256;
-__global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi, int nc) {
+constexpr int BEAM_NT = 512;
+constexpr int BEAM_NC = 8;  // right-hand sides per workgroup
+__global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
+  constexpr int NC = BEAM_NC;
   extern __shared__ double bsm[];
   const BodyDev& b = a.bodies[bi];
   const int m = b.npts, K = m - 1, nd = 3 * K, ncol = 2 * m + 1;
@@ -431,42 +433,43 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi, int nc) {
   double* Ub = Lb + 9 * K;
   double* Ai = Ub + 9 * K;   // inverse of A_j at the level that eliminates j
   double* P = Ai + 9 * K;    // per kept block and level: L_i A_{i-s}^{-1}, U_i A_{i+s}^{-1}
-  double* rint = P + 18 * K; // 3m internal forces
-  double* sres = rint + 3 * m;
-  double* rhs = sres + nd;   // [nd][nc]
+  double* rhs = P + 18 * K;  // [nd][NC]
+  double* sres = rhs + nd * NC;
+  double* ek = Ai;           // element forces and tangents [m-1][42], before Ai is used
   const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
   const double* xn = a.chi + b.dof0;
   const double* zn = a.zeta + b.dof0;
   const double* an = a.zetadot + b.dof0;
   const double* ms = a.dmass + b.dof0;
 
-  for (int e = tid; e < 27 * K; e += BEAM_NT) A[e] = 0.0;
-  for (int e = tid; e < 3 * m; e += BEAM_NT) rint[e] = 0.0;
+  // element internal forces and tangents, one element per thread
+  for (int el = tid; el < m - 1; el += BEAM_NT)
+    beam_element(ck + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el], b.ea, b.ei,
+                 ek + 42 * el, ek + 42 * el + 6);
   __syncthreads();
-  // element assembly: even then odd elements, so no two threads add to one block
-  for (int parity = 0; parity < 2; ++parity) {
-    for (int el = 2 * tid + parity; el < m - 1; el += 2 * BEAM_NT) {
-      double fe[6], ke[36];
-      beam_element(ck + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el], b.ea, b.ei, fe, ke);
-      for (int p = 0; p < 6; ++p) rint[3 * el + p] += fe[p];
-      const int k0 = el - 1, k1 = el;  // blocks of nodes el and el + 1
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) {
-          if (el >= 1) {
-            A[9 * k0 + 3 * p + q] += ke[p * 6 + q];
-            Ub[9 * k0 + 3 * p + q] += ke[p * 6 + q + 3];
-            Lb[9 * k1 + 3 * p + q] += ke[(p + 3) * 6 + q];
-          }
-          A[9 * k1 + 3 * p + q] += ke[(p + 3) * 6 + q + 3];
-        }
+  // blocks of node k+1: A_k from elements k (second node) and k+1 (first node),
+  // U_k = J(k, k+1) from element k+1, L_k = J(k, k-1) from element k (node 0 is clamped)
+  for (int e = tid; e < 27 * K; e += BEAM_NT) {
+    const int blk = e / 9, w = e % 9, r = w / 3, c = w % 3;
+    const int which = blk / K, k = blk % K;  // 0: A, 1: L, 2: U
+    double v = 0.0;
+    if (which == 0) {
+      v = ek[42 * k + 6 + (r + 3) * 6 + c + 3];
+      if (k + 1 <= m - 2) v += ek[42 * (k + 1) + 6 + r * 6 + c];
+      if (r == c) v += 4.0 * ms[3 * (k + 1) + c] / (dt * dt);
+    } else if (which == 1) {
+      if (k >= 1) v = ek[42 * k + 6 + (r + 3) * 6 + c];
+    } else {
+      if (k + 1 <= m - 2) v = ek[42 * (k + 1) + 6 + r * 6 + c + 3];
     }
-    __syncthreads();
+    bsm[e] = v;
   }
   for (int u = tid; u < nd; u += BEAM_NT) {
-    const int g = u + 3, k = u / 3, c = u % 3;
-    A[9 * k + 4 * c] += 4.0 * ms[g] / (dt * dt);
+    const int g = u + 3, node = g / 3, c = g % 3;
+    double rint = ek[42 * (node - 1) + 3 + c];
+    if (node <= m - 2) rint += ek[42 * node + c];
     const double rz = ms[g] * (4.0 * xn[g] / (dt * dt) + 4.0 * zn[g] / dt + an[g]);
-    sres[u] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint[g];
+    sres[u] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint;
   }
   __syncthreads();
 
@@ -515,10 +518,10 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi, int nc) {
     po += nk;
   }
 
-  // right-hand sides of this workgroup: columns c0 .. c0 + nc - 1
-  const int c0 = blockIdx.x * nc;
-  for (int t = tid; t < nd * nc; t += BEAM_NT) {
-    const int u = t / nc, col = c0 + t % nc;
+  // right-hand sides of this workgroup: columns c0 .. c0 + NC - 1
+  const int c0 = blockIdx.x * NC;
+  for (int t = tid; t < nd * NC; t += BEAM_NT) {
+    const int u = t / NC, col = c0 + t % NC;
     double v = 0.0;
     if (col < 2 * m) {
       const int node = col % m, cmp = col / m;
@@ -532,21 +535,21 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi, int nc) {
   po = 0;
   for (int s = 1, lev = 0; s <= K; s *= 2, ++lev) {
     const int nk = K >> (lev + 1);
-    for (int t = tid; t < nk * nc; t += BEAM_NT) {
-      const int q = t / nc, cl = t % nc;
+    for (int t = tid; t < nk * NC; t += BEAM_NT) {
+      const int q = t / NC, cl = t % NC;
       const int i = 2 * s * (q + 1) - 1, j1 = i - s, j2 = i + s;
       const double* pl = P + 18 * (po + q);
       const double* pu = pl + 9;
       double bj1[3], bj2[3] = {0.0, 0.0, 0.0}, v[3];
-      for (int k = 0; k < 3; ++k) bj1[k] = rhs[(3 * j1 + k) * nc + cl];
+      for (int k = 0; k < 3; ++k) bj1[k] = rhs[(3 * j1 + k) * NC + cl];
       if (j2 < K)
-        for (int k = 0; k < 3; ++k) bj2[k] = rhs[(3 * j2 + k) * nc + cl];
+        for (int k = 0; k < 3; ++k) bj2[k] = rhs[(3 * j2 + k) * NC + cl];
       for (int r = 0; r < 3; ++r) {
-        double x = rhs[(3 * i + r) * nc + cl];
+        double x = rhs[(3 * i + r) * NC + cl];
         for (int k = 0; k < 3; ++k) x -= pl[3 * r + k] * bj1[k] + pu[3 * r + k] * bj2[k];
         v[r] = x;
       }
-      for (int r = 0; r < 3; ++r) rhs[(3 * i + r) * nc + cl] = v[r];
+      for (int r = 0; r < 3; ++r) rhs[(3 * i + r) * NC + cl] = v[r];
     }
     __syncthreads();
     po += nk;
@@ -554,36 +557,38 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi, int nc) {
   for (int lev = top; lev >= 0; --lev) {
     const int s = 1 << lev;
     const int ne = (K - s) / (2 * s) + 1;
-    for (int t = tid; t < ne * nc; t += BEAM_NT) {
-      const int j = s - 1 + 2 * s * (t / nc), cl = t % nc;
+    for (int t = tid; t < ne * NC; t += BEAM_NT) {
+      const int j = s - 1 + 2 * s * (t / NC), cl = t % NC;
       double w[3];
-      for (int r = 0; r < 3; ++r) w[r] = rhs[(3 * j + r) * nc + cl];
+      for (int r = 0; r < 3; ++r) w[r] = rhs[(3 * j + r) * NC + cl];
       if (j - s >= 0)
         for (int k = 0; k < 3; ++k) {
-          const double x = rhs[(3 * (j - s) + k) * nc + cl];
+          const double x = rhs[(3 * (j - s) + k) * NC + cl];
           for (int r = 0; r < 3; ++r) w[r] -= Lb[9 * j + 3 * r + k] * x;
         }
       if (j + s < K)
         for (int k = 0; k < 3; ++k) {
-          const double x = rhs[(3 * (j + s) + k) * nc + cl];
+          const double x = rhs[(3 * (j + s) + k) * NC + cl];
           for (int r = 0; r < 3; ++r) w[r] -= Ub[9 * j + 3 * r + k] * x;
         }
       for (int r = 0; r < 3; ++r)
-        rhs[(3 * j + r) * nc + cl] =
+        rhs[(3 * j + r) * NC + cl] =
             Ai[9 * j + 3 * r] * w[0] + Ai[9 * j + 3 * r + 1] * w[1] + Ai[9 * j + 3 * r + 2] * w[2];
     }
     __syncthreads();
   }
   double* y = a.ywork + b.yoff;
-  for (int t = tid; t < nd * nc; t += BEAM_NT) {
-    const int u = t / nc, col = c0 + t % nc;
+  for (int t = tid; t < nd * NC; t += BEAM_NT) {
+    const int u = t / NC, col = c0 + t % NC;
     if (col < ncol) y[(size_t)u * ncol + col] = rhs[t];
   }
 }
 
-size_t beam_lds_bytes(int m, int nc) {
+// LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K); the
+// element scratch (42 (m-1)) overlays A^{-1} .. rhs, which is large enough for NC >= 5
+size_t beam_lds_bytes(int m) {
   const size_t K = m - 1;
-  return (size_t)(54 * K + 3 * m + 3 * K + 3 * K * nc) * 8;
+  return (size_t)(54 * K + 3 * K * BEAM_NC + 3 * K) * 8;
 }
 
 // Deformable part of the Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi).
@@ -712,6 +717,7 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
 __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
+  if (a.rmore != nullptr && *a.rmore != 0.0) return;  // the stress solve is not finished
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = STRUCT_NT / 64;
   const int gw = blockIdx.x * NW + w, nwaves = gridDim.x * NW;
@@ -837,69 +843,84 @@ __global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) {
 
 // Corrector source C^T E^T lambda at interior vertices of rows [jlo, jhi]; entries
 // outside columns [ilo, ihi] are zero.  lambda_a = (ds_a / h) f_a.  Each workgroup
-// covers a 64 x 4 tile of vertices, first collects (in row order) the operator rows
-// whose window reaches the tile, then every vertex sums those rows in that fixed order,
-// so the result is deterministic.
+// covers a 64 x 4 tile of vertices.  It first lists (in row order, by wave ballots) the
+// operator rows whose window reaches the tile, stages their windows and coefficients
+// in LDS, and then every vertex sums those rows in that fixed order, so the result is
+// deterministic.
 constexpr int SPREAD_TX = 64, SPREAD_TY = 4, SPREAD_NT = SPREAD_TX * SPREAD_TY;
 constexpr int SPREAD_MAXROWS = 4096;
 
 template <typename T>
 __global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi,
                                                       T* out, int po) {
+  constexpr int NW = SPREAD_NT / 64;
   __shared__ int list[SPREAD_MAXROWS];
-  __shared__ int scan[SPREAD_NT];
-  __shared__ int count_s;
-  const int tx = threadIdx.x % SPREAD_TX, ty = threadIdx.x / SPREAD_TX;
+  __shared__ int wcount[NW];
+  __shared__ int sb[SPREAD_NT][3];
+  __shared__ double sw[SPREAD_NT][16];
+  __shared__ double sc[SPREAD_NT];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tx = tid % SPREAD_TX, ty = tid / SPREAD_TX;
   const int ti0 = 1 + blockIdx.x * SPREAD_TX, tj0 = jlo + blockIdx.y * SPREAD_TY;
   const int i = ti0 + tx, j = tj0 + ty;
   const bool tile_hit = !(ti0 + SPREAD_TX - 1 < ilo || ti0 > ihi);
+  int cnt = 0;
   if (tile_hit) {
-    if (threadIdx.x == 0) count_s = 0;
-    __syncthreads();
     for (int r0 = 0; r0 < a.nf; r0 += SPREAD_NT) {
-      const int r = r0 + threadIdx.x;
-      int hit = 0;
+      const int r = r0 + tid;
+      bool hit = false;
       if (r < a.nf) {
         const int i0 = a.st_base[3 * r], j0 = a.st_base[3 * r + 1];
         // vertices touched by the window's faces: columns i0 .. i0+4, rows j0 .. j0+4
         hit = !(i0 + 4 < ti0 || i0 > ti0 + SPREAD_TX - 1 || j0 + 4 < tj0 || j0 > tj0 + SPREAD_TY - 1);
       }
-      scan[threadIdx.x] = hit;
+      const unsigned long long bal = __ballot(hit);
+      const int below = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) wcount[wv] = __popcll(bal);
       __syncthreads();
-      for (int off = 1; off < SPREAD_NT; off <<= 1) {
-        const int add = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        scan[threadIdx.x] += add;
-        __syncthreads();
-      }
-      if (hit) list[count_s + scan[threadIdx.x] - 1] = r;
-      __syncthreads();
-      if (threadIdx.x == 0) count_s += scan[SPREAD_NT - 1];
+      int off = cnt;
+      for (int w = 0; w < wv; ++w) off += wcount[w];
+      if (hit) list[off + below] = r;
+      for (int w = 0; w < NW; ++w) cnt += wcount[w];
       __syncthreads();
     }
+  }
+  double src = 0.0;
+  for (int q0 = 0; q0 < cnt; q0 += SPREAD_NT) {
+    const int nq = min(SPREAD_NT, cnt - q0);
+    if (tid < nq) {
+      const int r = list[q0 + tid];
+      int bb[3];
+      double ww[16];
+      for (int k = 0; k < 3; ++k) bb[k] = a.st_base[3 * r + k];
+      for (int k = 0; k < 16; ++k) ww[k] = a.st_w[16 * r + k];
+      const double coef = (row_ds(a, r) / a.h) * a.f[r];
+      for (int k = 0; k < 3; ++k) sb[tid][k] = bb[k];
+      for (int k = 0; k < 16; ++k) sw[tid][k] = ww[k];
+      sc[tid] = coef;
+    }
+    __syncthreads();
+    if (i >= ilo && i <= ihi && i <= a.n - 1 && j <= jhi) {
+      for (int q = 0; q < nq; ++q) {
+        const int di = i - sb[q][0], dj = j - sb[q][1];
+        if (di < 0 || di > 4 || dj < 0 || dj > 4) continue;
+        const double* w = sw[q];
+        double c = 0.0;
+        if (sb[q][2] == 0) {
+          // x-faces [j][i] (-) and [j-1][i] (+)
+          if (di < 4 && dj < 4) c -= w[dj * 4 + di];
+          if (di < 4 && dj >= 1) c += w[(dj - 1) * 4 + di];
+        } else {
+          // y-faces [j][i] (+) and [j][i-1] (-)
+          if (di < 4 && dj < 4) c += w[dj * 4 + di];
+          if (di >= 1 && dj < 4) c -= w[dj * 4 + di - 1];
+        }
+        if (c != 0.0) src += c * sc[q];
+      }
+    }
+    __syncthreads();
   }
   if (i > a.n - 1 || j > jhi) return;
-  double src = 0.0;
-  if (tile_hit && i >= ilo && i <= ihi) {
-    const int cnt = count_s;
-    for (int q = 0; q < cnt; ++q) {
-      const int r = list[q];
-      const int i0 = a.st_base[3 * r], j0 = a.st_base[3 * r + 1], comp = a.st_base[3 * r + 2];
-      const int di = i - i0, dj = j - j0;
-      const double* w = a.st_w + 16 * r;
-      double c = 0.0;
-      if (comp == 0) {
-        // x-faces [j][i] (-) and [j-1][i] (+)
-        if (di >= 0 && di < 4 && dj >= 0 && dj < 4) c -= w[dj * 4 + di];
-        if (di >= 0 && di < 4 && dj - 1 >= 0 && dj - 1 < 4) c += w[(dj - 1) * 4 + di];
-      } else {
-        // y-faces [j][i] (+) and [j][i-1] (-)
-        if (di >= 0 && di < 4 && dj >= 0 && dj < 4) c += w[dj * 4 + di];
-        if (di - 1 >= 0 && di - 1 < 4 && dj >= 0 && dj < 4) c -= w[dj * 4 + di - 1];
-      }
-      if (c != 0.0) src += c * (row_ds(a, r) / a.h) * a.f[r];
-    }
-  }
   out[(size_t)(j - 1) * po + (i - 1)] = (T)src;
 }
 
@@ -1037,7 +1058,7 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 // first use and whenever the refinement stops contracting.
 
 // ---------------------------------------------- Schur solve by iterative refinement
-// f = X b, then sweeps r = b - M f, f += X r while the relative residual |r|/|b| (max
+// f = X b (or the caller's guess in f), then sweeps r = b - M f, f += X r while the relative residual |r|/|b| (max
 // norms) still exceeds 1e-16 n and still halves.  Each matrix-vector product is one
 // launch over many workgroups (one wave per row), so the matrices stream through many
 // CUs; a sweep that follows convergence returns at once.  Workspace `ws` (doubles):
@@ -1129,18 +1150,22 @@ __global__ __launch_bounds__(256) void k_ref_matvec(const double* A, int pa, con
   }
 }
 
-__global__ void k_ref_final(double* ws, int maxit, int* flags, double* out) {
+__global__ void k_ref_final(double* ws, int maxit, int* flags, double* out, int partial) {
   if (threadIdx.x != 0) return;
   unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
-  if (wu[3] == 0ull) {
+  const bool done = wu[3] != 0ull;
+  if (!done) {
     const double nr = bitsd(wu[4 + maxit - 1]);
     const double nb = ws[2];
     ws[0] = nb > 0.0 ? nr / nb : 0.0;
     ws[1] = maxit;
   }
-  if (!(ws[0] < 1e-9)) atomicMax(&flags[1], 1);  // refinement failed: the inverse is stale
   out[0] = ws[0];
   out[1] = ws[1];
+  // with `partial`, running out of sweeps while still contracting asks the caller for
+  // more sweeps (out[2] = 1) instead of counting as a failure
+  out[2] = (!done && partial) ? 1.0 : 0.0;
+  if (!(!done && partial) && !(ws[0] < 1e-9)) atomicMax(&flags[1], 1);  // the inverse is stale
 }
 
 // C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B.  32 x 32 tiles.
@@ -1189,17 +1214,18 @@ hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
-                               int n, int maxit, double* ws, double* out, int* flags, hipStream_t st) {
+                               int n, int maxit, int guess, int partial, double* ws, double* out,
+                               int* flags, hipStream_t st) {
   if (n < 1 || maxit < 1) return hipErrorInvalidValue;
   double* r = ws + REF_HDR + maxit;
   const dim3 grid((n + 3) / 4), blk(256);
   hipLaunchKernelGGL(k_ref_reset, dim3(1), blk, 0, st, b, n, ws, maxit);
-  hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, b, b, f, n, 0, ws, 0);
+  if (!guess) hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, b, b, f, n, 0, ws, 0);
   for (int it = 0; it < maxit; ++it) {
     hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, M, pm, f, b, r, n, 1, ws, it);
     hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, r, b, f, n, 2, ws, it);
   }
-  hipLaunchKernelGGL(k_ref_final, dim3(1), dim3(64), 0, st, ws, maxit, flags, out);
+  hipLaunchKernelGGL(k_ref_final, dim3(1), dim3(64), 0, st, ws, maxit, flags, out, partial);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
@@ -1236,13 +1262,11 @@ hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, in
 }
 hipError_t launch_band_columns(const FsiArgs& a, int bi, int m, hipStream_t st) {
   const int ncol = 2 * m + 1;
-  // right-hand sides per workgroup: as many as 150 KB of LDS allow, at most 32; the
-  // factorisation is repeated per workgroup, which costs no extra latency
-  int nc = 32;
-  while (nc > 1 && beam_lds_bytes(m, nc) > 150 * 1024) nc /= 2;
-  const size_t lds = beam_lds_bytes(m, nc);
+  // BEAM_NC right-hand sides per workgroup; every workgroup repeats the factorisation,
+  // which costs no extra latency and spreads the solves over more CUs
+  const size_t lds = beam_lds_bytes(m);
   if (m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_beam, dim3((ncol + nc - 1) / nc), dim3(BEAM_NT), lds, st, a, bi, nc);
+  hipLaunchKernelGGL(k_beam, dim3((ncol + BEAM_NC - 1) / BEAM_NC), dim3(BEAM_NT), lds, st, a, bi);
   hipLaunchKernelGGL(k_struct_rhs_def, dim3(1), dim3(256), 0, st, a, bi);
   return hipGetLastError();
 }

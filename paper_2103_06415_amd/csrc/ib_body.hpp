@@ -73,6 +73,7 @@ struct FsiArgs {
   double* dres;        // residual per DOF
   double* ywork;       // J_d^{-1} T^T, per deformable body: (3m) x (2m)
   int* flags;          // [0] error code, [1] refinement failure
+  const double* rmore; // non-zero: the stress solve needs more sweeps, k_update waits
   double* delta;       // [0] max |delta| of the last update
 };
 
@@ -116,12 +117,14 @@ hipError_t launch_gather_batch(const int* cols, const double* vals, int ntarget,
 hipError_t launch_scale_cols(double* M, int pm, int n, const double* colscale, double s,
                              hipStream_t st);
 hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
-// f = M^{-1} b by refinement with the approximate inverse X; ws holds
-// refine_ws_doubles(n, maxit) doubles; out[0] = final relative residual, out[1] = sweeps;
-// flags[1] is raised when the residual stays above 1e-9
+// f = M^{-1} b by refinement with the approximate inverse X, starting from X b or, with
+// guess != 0, from the f passed in; ws holds refine_ws_doubles(n, maxit) doubles;
+// out[0] = final relative residual, out[1] = sweeps, out[2] = 1 when `partial` is set and
+// the maxit sweeps ran out before convergence (the caller continues with guess = 1);
+// otherwise flags[1] is raised when the residual stays above 1e-9
 hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
-                               int n, int maxit, double* ws, double* out, int* flags,
-                               hipStream_t st);
+                               int n, int maxit, int guess, int partial, double* ws, double* out,
+                               int* flags, hipStream_t st);
 size_t refine_ws_doubles(int n, int maxit);
 hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,

@@ -105,6 +105,8 @@ struct ib_solver {
   bool x_valid = false;
   bool x_valid_retry = false;
   int inverse_rebuilds = 0;
+  // sweeps launched per stress solve in tolerance mode, per FSI iteration index (0, 1, 2, 3+)
+  int refine_budget[4] = {REFINE_MAXIT, REFINE_MAXIT, REFINE_MAXIT, REFINE_MAXIT};
   // control block read back once per FSI iteration: error flags (2 ints), max |delta|,
   // refinement residual and sweeps; one device copy and its pinned host mirror
   void* ctl = nullptr;
@@ -623,6 +625,7 @@ ib_status prepare_bodies(ib_solver* s) {
   s->rout = reinterpret_cast<double*>(static_cast<char*>(s->ctl) + 16);
   a.flags = s->flags;
   a.delta = s->delta;
+  a.rmore = s->rout + 2;
   HIPCHK(hipMemset(s->ctl, 0, 64));
   if (!s->hctl) {
     HIPCHK(hipHostMalloc(&s->hctl, 64, hipHostMallocDefault));
@@ -812,15 +815,19 @@ ib_status fsi_and_correct(ib_solver* s) {
         HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream));
         std::swap(s->Minv, s->Xn);
       }
-      HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, REFINE_MAXIT, s->rinfo, s->rout, s->flags,
-                                 s->stream));
+      // in tolerance mode the sweeps launched follow the last solve's need (no-op sweeps
+      // after convergence still cost a launch each); running short asks for more below
+      const int budget = fixed > 0 ? REFINE_MAXIT : s->refine_budget[std::min(it, 3)];
+      HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, budget,
+                                 it > 0 && !s->x_valid_retry, budget < REFINE_MAXIT, s->rinfo,
+                                 s->rout, s->flags, s->stream));
       HIPCHK(launch_update(a, s->stream));
     }
     bool done = false;
     if (fixed > 0) {
       done = it + 1 >= fixed;
       if (done) {
-        HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 32, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         if (s->hflags[1]) {
           s->last_error = "Schur refinement did not converge";
@@ -828,8 +835,22 @@ ib_status fsi_and_correct(ib_solver* s) {
         }
       }
     } else {
-      HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 32, hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
       HIPCHK(hipStreamSynchronize(s->stream));
+      if (s->hrinfo[2] != 0.0) {
+        // the sweep budget ran out while the refinement still contracted: continue it
+        // from the current f with the full budget, then update the structure
+        TimeScope ts(s, IB_K_FSI);
+        HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, s->nf, REFINE_MAXIT, 1, 0,
+                                   s->rinfo, s->rout, s->flags, s->stream));
+        HIPCHK(launch_update(a, s->stream));
+        HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        int& rb = s->refine_budget[std::min(it, 3)];
+        rb = std::min(REFINE_MAXIT, rb + (int)s->hrinfo[1] + 2);
+      } else {
+        s->refine_budget[std::min(it, 3)] = std::min(REFINE_MAXIT, std::max(3, (int)s->hrinfo[1] + 2));
+      }
       ib_status st = map_flags(s, s->hflags[0]);
       if (st) return st;
       if (s->hflags[1]) {

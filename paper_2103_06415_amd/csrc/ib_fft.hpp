@@ -10,9 +10,11 @@
 //   E_k = (W_k + conj W_{n-k}) / 2,  O_k = (W_k - conj W_{n-k}) / (2i)
 //   X_k = sum_j x_j sin(pi j k / n) = -Im(E_k + e^{-i pi k / n} O_k) / 2
 //
-// The FFT is a Stockham autosort radix-4/2/3 transform working in place on LDS:
-// every stage loads its inputs into registers, synchronises the workgroup, and
-// writes the butterflies' outputs back.  Twiddles come from one table per n,
+// The FFT is a Stockham autosort transform working in place on LDS with radix-16
+// stages first (then one radix-8, -4 or -2 stage for the rest of the power of two, then
+// radix-3 stages): every stage loads its inputs into registers, synchronises the
+// workgroup, and writes the butterflies' outputs back, so large radices mean fewer
+// barriers and less LDS traffic.  Twiddles come from one table per n,
 // tw[m] = exp(-i pi m / n), m < 2n, prepared on the host in double precision.
 #pragma once
 
@@ -28,13 +30,28 @@ template <int L>
 struct FftPlan {
   static constexpr int p3 = pow3c(L);
   static constexpr int p2 = ilog2c(L / ipow3(p3));
-  static constexpr int n4 = p2 / 2;
-  static constexpr int n2 = p2 % 2;
-  static constexpr int nst = n4 + n2 + p3;
+  static constexpr int n16 = p2 / 4;
+  static constexpr int rem = p2 % 4;  // 3: one radix-8 stage, 2: radix-4, 1: radix-2
+  static constexpr int nmid = rem ? 1 : 0;
+  static constexpr int nst = n16 + nmid + p3;
   static_assert(ipow3(p3) * (1 << p2) == L, "FFT length must be 2^a 3^b");
-  static constexpr int radix(int s) { return s < n4 ? 4 : (s < n4 + n2 ? 2 : 3); }
+  static constexpr int radix(int s) {
+    return s < n16 ? 16 : (s < n16 + nmid ? (1 << rem) : 3);
+  }
 };
 
+template <typename T>
+__device__ __forceinline__ void dft4(c2<T>& a0, c2<T>& a1, c2<T>& a2, c2<T>& a3) {
+  c2<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  c2<T> s13 = cadd(a1, a3), d13 = csub(a1, a3);
+  c2<T> md = cmul_mi(d13);
+  a0 = cadd(s02, s13);
+  a2 = csub(s02, s13);
+  a1 = cadd(d02, md);
+  a3 = csub(d02, md);
+}
+
+// In-place DFT of R values in natural order, X_k = sum_m v_m e^{-2 pi i m k / R}.
 template <typename T, int R>
 __device__ __forceinline__ void dft_small(c2<T>* v) {
   if constexpr (R == 2) {
@@ -42,13 +59,53 @@ __device__ __forceinline__ void dft_small(c2<T>* v) {
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
   } else if constexpr (R == 4) {
-    c2<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-    c2<T> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
-    v[0] = cadd(s02, s13);
-    v[2] = csub(s02, s13);
-    c2<T> md = cmul_mi(d13);
-    v[1] = cadd(d02, md);
-    v[3] = csub(d02, md);
+    dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // even / odd halves, then the twiddles e^{-i pi k / 4}
+    c2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    c2<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    const T h = T(0.70710678118654752440084436210485);
+    o1 = c2<T>{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    o2 = cmul_mi(o2);
+    o3 = c2<T>{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+  } else if constexpr (R == 16) {
+    // four DFT4 over m = r + 4 j, the twiddles e^{-2 pi i r k / 16}, four DFT4 over r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dft4(v[r], v[r + 4], v[r + 8], v[r + 12]);
+    const T c1 = T(0.92387953251128675612818318939679);  // cos(pi/8)
+    const T s1 = T(0.38268343236508977172845998403040);  // sin(pi/8)
+    const T h = T(0.70710678118654752440084436210485);
+    // Y_r[k] sits in v[r + 4k]; multiply by w^{r k}, w = e^{-i pi / 8}
+    auto tw = [](c2<T> z, T c, T s) { return c2<T>{z.x * c + z.y * s, z.y * c - z.x * s}; };
+    v[5] = tw(v[5], c1, s1);     // r=1 k=1: w^1
+    v[9] = tw(v[9], h, h);       // r=1 k=2: w^2
+    v[13] = tw(v[13], s1, c1);   // r=1 k=3: w^3
+    v[6] = tw(v[6], h, h);       // r=2 k=1: w^2
+    v[10] = cmul_mi(v[10]);      // r=2 k=2: w^4
+    v[14] = tw(v[14], -h, h);    // r=2 k=3: w^6
+    v[7] = tw(v[7], s1, c1);     // r=3 k=1: w^3
+    v[11] = tw(v[11], -h, h);    // r=3 k=2: w^6
+    v[15] = tw(v[15], -c1, -s1); // r=3 k=3: w^9
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dft4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    // X[k + 4 q] = DFT4 over r of row k, now in v[4 k + q]: transpose to natural order
+    c2<T> u[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u[k + 4 * q] = v[4 * k + q];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = u[e];
   } else {
     // e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
     const T h3 = T(0.86602540378443864676372317075294);

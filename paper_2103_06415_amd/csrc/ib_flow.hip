@@ -24,16 +24,17 @@ __device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
   return p[(size_t)j * pitch + i];
 }
 
-// Circulation seen by the stencil at vertex (i, j) of the level, 0 <= i, j <= n:
+// Where the circulation seen by the stencil at vertex (i, j), 0 <= i, j <= n, lives:
 // boundary ring, coarsification on read (the finer level's circulation at the
 // coincident vertex, scaled by (h_coarse / h_fine)^2 = 4) or the level's own interior.
-// Written with selects so that the single load can be issued early.
+// Returned as pointer, index and scale (selects only), so that the caller can issue all
+// of its loads before it uses any of them.
 template <typename T>
-__device__ __forceinline__ T gamma_at(const RhsArgs<T>& a, int i, int j) {
+__device__ __forceinline__ const T* gamma_src(const RhsArgs<T>& a, int i, int j, long& idx, T& sc) {
   const int n = a.n;
   const T* p = a.g;
-  long idx = (long)(j - 1) * a.pg + (i - 1);
-  T sc = T(1);
+  idx = (long)(j - 1) * a.pg + (i - 1);
+  sc = T(1);
   if (a.gf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
     p = a.gf;
     idx = (long)(2 * j - n / 2 - 1) * a.pgf + (2 * i - n / 2 - 1);
@@ -43,7 +44,7 @@ __device__ __forceinline__ T gamma_at(const RhsArgs<T>& a, int i, int j) {
   if (i == 0) { p = a.gring; idx = RING_L * (n + 1) + j; sc = T(1); }
   if (j == n) { p = a.gring; idx = RING_T * (n + 1) + i; sc = T(1); }
   if (j == 0) { p = a.gring; idx = RING_B * (n + 1) + i; sc = T(1); }
-  return sc * p[idx];
+  return p;
 }
 
 // Copy the twiddle table (2N entries) into LDS, all loads of a thread in flight at once.
@@ -75,11 +76,12 @@ __device__ __forceinline__ T ring_adj(const T* ring, int n, int i, int j) {
 }
 
 // Right-hand side at interior vertex (i, j) from staged rows: ss / sg hold s and gamma
-// of rows j-1, j, j+1 (each W wide, column index = i); hprev is C^T N_{n-1} (or NaN-free
-// copy of the new value on the first step); writes C^T N_n to the history.
+// of rows j-1, j, j+1 (each W wide, column index = i); hprev_in is C^T N_{n-1} (unused
+// on the first step, which takes the new value); ring_term the adjacent new ring
+// circulation; writes C^T N_n to the history.
 template <typename T, int W>
 __device__ __forceinline__ T rhs_staged(const RhsArgs<T>& a, const T* ss, const T* sg, int i, int j,
-                                        T hprev_in, bool has_prev) {
+                                        T hprev_in, bool has_prev, T ring_term) {
   const T* sm = ss;          // row j-1
   const T* sp = ss + 2 * W;  // row j+1
   const T* gm = sg;
@@ -98,9 +100,7 @@ __device__ __forceinline__ T rhs_staged(const RhsArgs<T>& a, const T* ss, const 
   a.hist_out[(size_t)(j - 1) * a.ph + (i - 1)] = ctn;
   const T hprev = has_prev ? hprev_in : ctn;
   const T lap = T(4) * g0 - gE - gW - gN - gS;
-  T r = g0 - a.alpha * lap + a.dt * (T(1.5) * ctn - T(0.5) * hprev);
-  if (a.gring_new != nullptr) r += a.alpha * ring_adj(a.gring_new, a.n, i, j);
-  return r;
+  return g0 - a.alpha * lap + a.dt * (T(1.5) * ctn - T(0.5) * hprev) + a.alpha * ring_term;
 }
 
 // Explicit right-hand side of ROWS interior rows fused with their row DST.  The rows
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
   constexpr int UNI = (STG > BUFT ? STG : BUFT) / 2 + 1;
   __shared__ c2<T> uni[UNI];
   __shared__ c2<T> stw[2 * N];
+  __shared__ T sring[4][W];          // new circulation ring: bottom, top, left, right
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
@@ -126,31 +127,51 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
   constexpr int PP = (NPT + NT - 1) / NT;
   T hp[PP];
   {
+    // every load of this thread is issued before any is used; indices are clamped to
+    // valid memory and the unused values are dropped afterwards
     constexpr int CNT = SR * W;
     constexpr int PER = (CNT + NT - 1) / NT;
-    T vs[PER], vg[PER];
+    T vs[PER], vg[PER], gsc[PER];
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
-      const int r = e / W, i = e % W, j = j0 - 1 + r;
-      const bool ok = e < CNT && j <= N;
-      vs[b] = ok ? a.s[(size_t)j * a.ps + i] : T(0);
-      vg[b] = ok ? gamma_at(a, i, j) : T(0);
+      const int r = e / W, i = e % W;
+      const int j = min(j0 - 1 + r, N);
+      long gi;
+      const T* gp = gamma_src(a, i, j, gi, gsc[b]);
+      vs[b] = a.s[(size_t)j * a.ps + i];
+      vg[b] = gp[gi];
     }
 #pragma unroll
     for (int b = 0; b < PP; ++b) {
       const int e = tid + b * NT;
-      const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
-      hp[b] = (a.hist_in != nullptr && e < NPT && j <= N - 1)
-                  ? a.hist_in[(size_t)(j - 1) * a.ph + (i - 1)] : T(0);
+      const int t = e / (N - 1), i = 1 + e % (N - 1), j = min(j0 + t, N - 1);
+      hp[b] = a.hist_in != nullptr ? a.hist_in[(size_t)(j - 1) * a.ph + (i - 1)] : T(0);
+    }
+    constexpr int PR = (4 * W + NT - 1) / NT;
+    T rv0[PR];
+    if (a.gring_new != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PR; ++b) {
+        const int e = tid + b * NT;
+        rv0[b] = e < 4 * W ? a.gring_new[e] : T(0);
+      }
     }
     load_table<T, N, NT>(stw, tw, tid);
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
       if (e < CNT) {
-        ss[e] = vs[b];
-        sg[e] = vg[b];
+        const bool ok = j0 - 1 + e / W <= N;
+        ss[e] = ok ? vs[b] : T(0);
+        sg[e] = ok ? gsc[b] * vg[b] : T(0);
+      }
+    }
+    if (a.gring_new != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PR; ++b) {
+        const int e = tid + b * NT;
+        if (e < 4 * W) (&sring[0][0])[e] = rv0[b];
       }
     }
   }
@@ -160,9 +181,17 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
   for (int b = 0; b < PP; ++b) {
     const int e = tid + b * NT;
     const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
-    rv[b] = (e < NPT && j <= N - 1)
-                ? rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr)
-                : T(0);
+    rv[b] = T(0);
+    if (e < NPT && j <= N - 1) {
+      T ring = T(0);
+      if (a.gring_new != nullptr) {
+        if (i == 1) ring += sring[RING_L][j];
+        if (i == N - 1) ring += sring[RING_R][j];
+        if (j == 1) ring += sring[RING_B][i];
+        if (j == N - 1) ring += sring[RING_T][i];
+      }
+      rv[b] = rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr, ring);
+    }
   }
   __syncthreads();  // the staging area becomes the transform buffer
   c2<T>* buf = uni;
@@ -240,6 +269,9 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
                                                   const T* __restrict__ lam, int nblocks) {
   __shared__ c2<T> buf[CW * N];
   __shared__ c2<T> stw[2 * N];
+  __shared__ T slam[N];
+  __shared__ T slift[2 * N];    // edge transforms of the left and right ring columns
+  __shared__ T slift01[2 * CW]; // bottom and top edge transforms at this block's columns
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
@@ -267,10 +299,37 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       v[b] = ok ? in[idx] : T(0);
     }
     load_table<T, N, NT>(stw, tw, tid);
+    constexpr int PL = (N - 1 + NT - 1) / NT;
+    T lv[PL];
+#pragma unroll
+    for (int b = 0; b < PL; ++b) lv[b] = tid + b * NT < N - 1 ? lam[tid + b * NT] : T(1);
+    constexpr int PF = (2 * (N - 1) + NT - 1) / NT;
+    T fv[PF];
+    T f01 = T(0);
+    if (a.lift != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PF; ++b) {
+        const int e = tid + b * NT;
+        fv[b] = e < 2 * (N - 1) ? a.lift[2 * (N - 1) + e] : T(0);
+      }
+      if (tid < 2 * CW) {
+        const int col = k0 + tid % CW;
+        f01 = col < N - 1 ? a.lift[(tid / CW) * (N - 1) + col] : T(0);
+      }
+    }
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
       if (e < CNT) dst_pack<T, N>(buf + (e % CW) * N, e / CW + 1, v[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < PL; ++b)
+      if (tid + b * NT < N) slam[tid + b * NT] = lv[b];
+    if (a.lift != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PF; ++b)
+        if (tid + b * NT < 2 * (N - 1)) slift[tid + b * NT] = fv[b];
+      if (tid < 2 * CW) slift01[tid] = f01;
     }
   }
   for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
@@ -289,9 +348,9 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       const int c = e % CW, l = 1 + e / CW;
       const int col = k0 + c;
       dst_unpack<T, N>(buf + c * N, stw, l, xa[b], xb[b]);
-      const T lk = (col < N - 1) ? lam[col] : T(1);
-      const T l1 = lk + lam[l - 1];
-      const T l2 = lk + lam[N - l - 1];
+      const T lk = (col < N - 1) ? slam[col] : T(1);
+      const T l1 = lk + slam[l - 1];
+      const T l2 = lk + slam[N - l - 1];
       la[b] = l1;
       lb[b] = l2;
       ea[b] = T(1) + a.alpha * l1;
@@ -304,12 +363,10 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
         const T sk = -stw[k].y, sl = -stw[l].y;  // sin(pi k/n), sin(pi l/n) = sin(pi (n-l)/n)
         const T pk = (k & 1) ? T(1) : T(-1);     // (-1)^(k+1)
         const T pl = (l & 1) ? T(1) : T(-1);     // (-1)^(l+1) = (-1)^(n-l+1)
-        const T* L = a.lift;
-        const T eb_k = L[0 * (N - 1) + k - 1], et_k = L[1 * (N - 1) + k - 1];
-        fa[b] = eb_k * sl + et_k * sl * pl + sk * L[2 * (N - 1) + l - 1] +
-                sk * pk * L[3 * (N - 1) + l - 1];
-        fb[b] = eb_k * sl + et_k * sl * pl + sk * L[2 * (N - 1) + N - l - 1] +
-                sk * pk * L[3 * (N - 1) + N - l - 1];
+        const T eb_k = slift01[c], et_k = slift01[CW + c];
+        fa[b] = eb_k * sl + et_k * sl * pl + sk * slift[l - 1] + sk * pk * slift[(N - 1) + l - 1];
+        fb[b] = eb_k * sl + et_k * sl * pl + sk * slift[N - l - 1] +
+                sk * pk * slift[(N - 1) + N - l - 1];
       }
     }
   }
