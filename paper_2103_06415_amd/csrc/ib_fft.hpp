@@ -118,22 +118,64 @@ __device__ __forceinline__ void dft_small(c2<T>* v) {
   }
 }
 
-// One Stockham stage on COUNT transforms of length L stored back to back in buf.
-template <typename T, int L, int R, int NS, int COUNT, int NT>
-__device__ __forceinline__ void fft_stage(c2<T>* buf, const c2<T>* __restrict__ tw, int tid) {
+// LDS layout.  A transform of length L occupies fft_pad_len<L>() slots: element x sits
+// at fpad(x) = x + x / 16, which keeps the stride-16 stores of a radix-16 stage off a
+// single LDS bank.  The twiddle table in LDS holds first tu[k] = e^{-i pi k / L},
+// k = 0 .. L/2 (for the sine-transform unpacking), then, for every stage with NS > 1,
+// its (R - 1) NS factors e^{-2 pi i r k / (NS R)} at [(r - 1) NS + k], so that the
+// lanes of a wave read consecutive entries.
+template <int L>
+constexpr int fft_pad_len() { return L + L / 16; }
+__device__ __forceinline__ int fpad(int x) { return x + (x >> 4); }
+
+template <int L>
+struct TwLayout {
+  static constexpr int U = L / 2 + 1;
+  static constexpr int off(int S) {
+    int o = U, ns = 1;
+    for (int s = 0; s < S; ++s) {
+      const int r = FftPlan<L>::radix(s);
+      if (ns > 1) o += (r - 1) * ns;
+      ns *= r;
+    }
+    return o;
+  }
+  static constexpr int total = off(FftPlan<L>::nst);
+};
+
+// Index into the global table exp(-i pi m / L), m < 2L, of LDS table entry e.
+template <int L, int S = 0, int NS = 1>
+__device__ __forceinline__ int tw_source(int e) {
+  if constexpr (S >= FftPlan<L>::nst) {
+    return 0;
+  } else {
+    constexpr int R = FftPlan<L>::radix(S);
+    constexpr int O = TwLayout<L>::off(S);
+    if (NS > 1 && e >= O && e < O + (R - 1) * NS) {
+      const int q = e - O, r = 1 + q / NS, k = q % NS;
+      return ((2 * L) / (NS * R)) * r * k;
+    }
+    return tw_source<L, S + 1, NS * R>(e);
+  }
+}
+
+// One Stockham stage S on COUNT transforms of length L stored back to back in buf.
+template <typename T, int L, int S, int R, int NS, int COUNT, int NT>
+__device__ __forceinline__ void fft_stage(c2<T>* buf, const c2<T>* __restrict__ tws, int tid) {
   constexpr int LR = L / R;
   constexpr int NB = COUNT * LR;
   constexpr int PER = (NB + NT - 1) / NT;
-  constexpr int TWS = (2 * L) / (NS * R);
+  constexpr int PL = fft_pad_len<L>();
+  constexpr int TO = TwLayout<L>::off(S);
   c2<T> v[PER][R];
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     int jj = tid + b * NT;
     if (jj < NB) {
       int t = jj / LR, j = jj % LR;
-      const c2<T>* base = buf + t * L;
+      const c2<T>* base = buf + t * PL;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = base[j + r * LR];
+      for (int r = 0; r < R; ++r) v[b][r] = base[fpad(j + r * LR)];
     }
   }
   __syncthreads();
@@ -145,42 +187,43 @@ __device__ __forceinline__ void fft_stage(c2<T>* buf, const c2<T>* __restrict__ 
       int k = j % NS;
       if constexpr (NS > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[TWS * r * k]);
+        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tws[TO + (r - 1) * NS + k]);
       }
       dft_small<T, R>(v[b]);
       int d = (j / NS) * NS * R + k;
-      c2<T>* base = buf + t * L;
+      c2<T>* base = buf + t * PL;
 #pragma unroll
-      for (int r = 0; r < R; ++r) base[d + r * NS] = v[b][r];
+      for (int r = 0; r < R; ++r) base[fpad(d + r * NS)] = v[b][r];
     }
   }
   __syncthreads();
 }
 
 template <typename T, int L, int S, int NS, int COUNT, int NT>
-__device__ __forceinline__ void fft_run(c2<T>* buf, const c2<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_run(c2<T>* buf, const c2<T>* __restrict__ tws, int tid) {
   if constexpr (S < FftPlan<L>::nst) {
     constexpr int R = FftPlan<L>::radix(S);
-    fft_stage<T, L, R, NS, COUNT, NT>(buf, tw, tid);
-    fft_run<T, L, S + 1, NS * R, COUNT, NT>(buf, tw, tid);
+    fft_stage<T, L, S, R, NS, COUNT, NT>(buf, tws, tid);
+    fft_run<T, L, S + 1, NS * R, COUNT, NT>(buf, tws, tid);
   }
 }
 
-// Forward complex FFT (e^{-2 pi i m k / L}) of COUNT sequences in LDS, natural order.
-// Requires a workgroup barrier before (inputs written) and leaves one after.
+// Forward complex FFT (e^{-2 pi i m k / L}) of COUNT sequences in LDS (padded layout,
+// natural order); tws is the LDS table described above.  Requires a workgroup barrier
+// before (inputs written) and leaves one after.
 template <typename T, int L, int COUNT, int NT>
-__device__ __forceinline__ void fft_lds(c2<T>* buf, const c2<T>* __restrict__ tw, int tid) {
-  fft_run<T, L, 0, 1, COUNT, NT>(buf, tw, tid);
+__device__ __forceinline__ void fft_lds(c2<T>* buf, const c2<T>* __restrict__ tws, int tid) {
+  fft_run<T, L, 0, 1, COUNT, NT>(buf, tws, tid);
 }
 
-// Place x_j (j = 1 .. n-1) of sequence t into the packed odd extension w.
+// Place x_j (j = 1 .. n-1) of one sequence into its packed odd extension w.
 template <typename T, int N>
 __device__ __forceinline__ void dst_pack(c2<T>* w, int j, T xj) {
   T* wr = reinterpret_cast<T*>(w);
   // z_j lives in w[j/2] (real part if j even), z_{2n-j} = -x_j in w[(2n-j)/2]
-  wr[2 * (j >> 1) + (j & 1)] = xj;
+  wr[2 * fpad(j >> 1) + (j & 1)] = xj;
   int jm = 2 * N - j;
-  wr[2 * (jm >> 1) + (jm & 1)] = -xj;
+  wr[2 * fpad(jm >> 1) + (jm & 1)] = -xj;
 }
 
 // Zero the two packed slots that hold z_0 and z_n.
@@ -188,23 +231,29 @@ template <typename T, int N>
 __device__ __forceinline__ void dst_pack_zeros(c2<T>* w) {
   T* wr = reinterpret_cast<T*>(w);
   wr[0] = T(0);
-  wr[2 * (N >> 1)] = T(0);
+  wr[2 * fpad(N >> 1)] = T(0);
 }
 
 // Unpack the DST-I outputs X_k and X_{n-k} (k = 1 .. n/2) from W = FFT_n(w).
-// Returns them through xk, xnk (for k = n/2 both hold X_{n/2}).
+// Returns them through xk, xnk (for k = n/2 both hold X_{n/2}).  tws: LDS table.
 template <typename T, int N>
-__device__ __forceinline__ void dst_unpack(const c2<T>* W, const c2<T>* __restrict__ tw, int k,
+__device__ __forceinline__ void dst_unpack(const c2<T>* W, const c2<T>* __restrict__ tws, int k,
                                            T& xk, T& xnk) {
-  c2<T> a = W[k];
-  c2<T> b = W[N - k];
+  c2<T> a = W[fpad(k)];
+  c2<T> b = W[fpad(N - k)];
   // E = (a + conj b)/2, O = -i (a - conj b) / 2
   T e_im = T(0.5) * (a.y - b.y);
   c2<T> d = c2<T>{a.x - b.x, a.y + b.y};
   c2<T> o = c2<T>{T(0.5) * d.y, -T(0.5) * d.x};
-  c2<T> p = cmul(tw[k], o);
+  c2<T> p = cmul(tws[k], o);
   xk = -T(0.5) * (e_im + p.y);
   xnk = T(0.5) * (e_im - p.y);
+}
+
+// sin(pi k / n) for 0 <= k <= n from the LDS table (the table holds k <= n/2).
+template <typename T, int N>
+__device__ __forceinline__ T tw_sin(const c2<T>* __restrict__ tws, int k) {
+  return -tws[k <= N / 2 ? k : N - k].y;
 }
 
 }  // namespace ib

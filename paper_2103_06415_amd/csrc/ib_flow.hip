@@ -30,14 +30,14 @@ __device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
 // Returned as pointer, index and scale (selects only), so that the caller can issue all
 // of its loads before it uses any of them.
 template <typename T>
-__device__ __forceinline__ const T* gamma_src(const RhsArgs<T>& a, int i, int j, long& idx, T& sc) {
+__device__ __forceinline__ const T* gamma_src(const RhsArgs<T>& a, int i, int j, int& idx, T& sc) {
   const int n = a.n;
   const T* p = a.g;
-  idx = (long)(j - 1) * a.pg + (i - 1);
+  idx = (j - 1) * a.pg + (i - 1);
   sc = T(1);
   if (a.gf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
     p = a.gf;
-    idx = (long)(2 * j - n / 2 - 1) * a.pgf + (2 * i - n / 2 - 1);
+    idx = (2 * j - n / 2 - 1) * a.pgf + (2 * i - n / 2 - 1);
     sc = T(4);
   }
   if (i == n) { p = a.gring; idx = RING_R * (n + 1) + j; sc = T(1); }
@@ -47,20 +47,22 @@ __device__ __forceinline__ const T* gamma_src(const RhsArgs<T>& a, int i, int j,
   return p;
 }
 
-// Copy the twiddle table (2N entries) into LDS, all loads of a thread in flight at once.
+// Build the LDS twiddle table (layout TwLayout<N>) from the global table
+// exp(-i pi m / N), m < 2N; all loads of a thread in flight at once.
 template <typename T, int N, int NT>
 __device__ __forceinline__ void load_table(c2<T>* stw, const c2<T>* __restrict__ tw, int tid) {
-  constexpr int PER = (2 * N + NT - 1) / NT;
+  constexpr int TOT = TwLayout<N>::total;
+  constexpr int PER = (TOT + NT - 1) / NT;
   c2<T> v[PER];
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
-    const int e = tid + b * NT;
-    if (e < 2 * N) v[b] = tw[e];
+    const int e = min(tid + b * NT, TOT - 1);  // clamped: every lane loads, no branch
+    v[b] = tw[e < TwLayout<N>::U ? e : tw_source<N>(e)];
   }
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int e = tid + b * NT;
-    if (e < 2 * N) stw[e] = v[b];
+    if (e < TOT) stw[e] = v[b];
   }
 }
 
@@ -112,10 +114,10 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
   constexpr int W = N + 1;           // staged row width, ring columns included
   constexpr int SR = ROWS + 2;       // staged rows j0-1 .. j0+ROWS
   constexpr int STG = 2 * SR * W;    // s and gamma, in T units
-  constexpr int BUFT = 2 * ROWS * N; // transform buffer, in T units
+  constexpr int BUFT = 2 * ROWS * fft_pad_len<N>(); // transform buffer, in T units
   constexpr int UNI = (STG > BUFT ? STG : BUFT) / 2 + 1;
   __shared__ c2<T> uni[UNI];
-  __shared__ c2<T> stw[2 * N];
+  __shared__ c2<T> stw[TwLayout<N>::total];
   __shared__ T sring[4][W];          // new circulation ring: bottom, top, left, right
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
@@ -137,25 +139,22 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
       const int e = tid + b * NT;
       const int r = e / W, i = e % W;
       const int j = min(j0 - 1 + r, N);
-      long gi;
+      int gi;
       const T* gp = gamma_src(a, i, j, gi, gsc[b]);
-      vs[b] = a.s[(size_t)j * a.ps + i];
+      vs[b] = a.s[j * a.ps + i];  // indices fit in 32 bits (n <= 1024)
       vg[b] = gp[gi];
     }
 #pragma unroll
     for (int b = 0; b < PP; ++b) {
       const int e = tid + b * NT;
       const int t = e / (N - 1), i = 1 + e % (N - 1), j = min(j0 + t, N - 1);
-      hp[b] = a.hist_in != nullptr ? a.hist_in[(size_t)(j - 1) * a.ph + (i - 1)] : T(0);
+      hp[b] = a.hist_in != nullptr ? a.hist_in[(j - 1) * a.ph + (i - 1)] : T(0);
     }
     constexpr int PR = (4 * W + NT - 1) / NT;
     T rv0[PR];
     if (a.gring_new != nullptr) {
 #pragma unroll
-      for (int b = 0; b < PR; ++b) {
-        const int e = tid + b * NT;
-        rv0[b] = e < 4 * W ? a.gring_new[e] : T(0);
-      }
+      for (int b = 0; b < PR; ++b) rv0[b] = a.gring_new[min(tid + b * NT, 4 * W - 1)];
     }
     load_table<T, N, NT>(stw, tw, tid);
 #pragma unroll
@@ -198,9 +197,9 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
 #pragma unroll
   for (int b = 0; b < PP; ++b) {
     const int e = tid + b * NT;
-    if (e < NPT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), rv[b]);
+    if (e < NPT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), rv[b]);
   }
-  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, ROWS, NT>(buf, stw, tid);
   for (int e = tid; e < ROWS * (N / 2); e += NT) {
@@ -208,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
     const int j = j0 + t;
     if (j > N - 1) continue;
     T xk, xnk;
-    dst_unpack<T, N>(buf + t * N, stw, k, xk, xnk);
+    dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
     T* o = a.out + (size_t)(j - 1) * a.po;
     o[k - 1] = xk;
     if (k != N / 2) o[N - k - 1] = xnk;
@@ -220,8 +219,8 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
 template <typename T, int N, int ROWS, int NT>
 __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __restrict__ tw,
                                                int nblocks) {
-  __shared__ c2<T> buf[ROWS * N];
-  __shared__ c2<T> stw[2 * N];
+  __shared__ c2<T> buf[ROWS * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
@@ -242,10 +241,10 @@ __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __rest
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
-      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), v[b]);
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
     }
   }
-  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, ROWS, NT>(buf, stw, tid);
   for (int e = tid; e < ROWS * (N / 2); e += NT) {
@@ -253,7 +252,7 @@ __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __rest
     const int j = j0 + t;
     if (j > a.r1) continue;
     T xk, xnk;
-    dst_unpack<T, N>(buf + t * N, stw, k, xk, xnk);
+    dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
     T* o = out + (size_t)(j - 1) * a.po;
     o[k - 1] = xk;
     if (k != N / 2) o[N - k - 1] = xnk;
@@ -267,8 +266,8 @@ __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __rest
 template <typename T, int N, int CW, int NT>
 __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
                                                   const T* __restrict__ lam, int nblocks) {
-  __shared__ c2<T> buf[CW * N];
-  __shared__ c2<T> stw[2 * N];
+  __shared__ c2<T> buf[CW * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
   __shared__ T slam[N];
   __shared__ T slift[2 * N];    // edge transforms of the left and right ring columns
   __shared__ T slift01[2 * CW]; // bottom and top edge transforms at this block's columns
@@ -320,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
-      if (e < CNT) dst_pack<T, N>(buf + (e % CW) * N, e / CW + 1, v[b]);
+      if (e < CNT) dst_pack<T, N>(buf + (e % CW) * fft_pad_len<N>(), e / CW + 1, v[b]);
     }
 #pragma unroll
     for (int b = 0; b < PL; ++b)
@@ -332,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       if (tid < 2 * CW) slift01[tid] = f01;
     }
   }
-  for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
+  for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, CW, NT>(buf, stw, tid);
   constexpr int NP = CW * (N / 2);
@@ -347,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
     if (e < NP) {
       const int c = e % CW, l = 1 + e / CW;
       const int col = k0 + c;
-      dst_unpack<T, N>(buf + c * N, stw, l, xa[b], xb[b]);
+      dst_unpack<T, N>(buf + c * fft_pad_len<N>(), stw, l, xa[b], xb[b]);
       const T lk = (col < N - 1) ? slam[col] : T(1);
       const T l1 = lk + slam[l - 1];
       const T l2 = lk + slam[N - l - 1];
@@ -360,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       if (a.lift != nullptr && col < N - 1) {
         // sum_{i,j} B(s_ring)_{ij} sin(pi i k / n) sin(pi j l / n) over the four edges
         const int k = col + 1;
-        const T sk = -stw[k].y, sl = -stw[l].y;  // sin(pi k/n), sin(pi l/n) = sin(pi (n-l)/n)
+        const T sk = tw_sin<T, N>(stw, k), sl = tw_sin<T, N>(stw, l);  // sin(pi k/n), sin(pi l/n)
         const T pk = (k & 1) ? T(1) : T(-1);     // (-1)^(k+1)
         const T pl = (l & 1) ? T(1) : T(-1);     // (-1)^(l+1) = (-1)^(n-l+1)
         const T eb_k = slift01[c], et_k = slift01[CW + c];
@@ -393,11 +392,11 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
         const T ga = xa[b] / ea[b], gb = xb[b] / eb[b];
         const T va = o == 0 ? (ga + fa[b]) * (a.scale / la[b]) : ga * a.scale;
         const T vb = o == 0 ? (gb + fb[b]) * (a.scale / lb[b]) : gb * a.scale;
-        dst_pack<T, N>(buf + c * N, l, va);
-        if (l != N / 2) dst_pack<T, N>(buf + c * N, N - l, vb);
+        dst_pack<T, N>(buf + c * fft_pad_len<N>(), l, va);
+        if (l != N / 2) dst_pack<T, N>(buf + c * fft_pad_len<N>(), N - l, vb);
       }
     }
-    for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * N);
+    for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * fft_pad_len<N>());
     __syncthreads();
     fft_lds<T, N, CW, NT>(buf, stw, tid);
 #pragma unroll
@@ -408,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
       const int col = k0 + c;
       if (col >= N - 1) continue;
       T yk, ynk;
-      dst_unpack<T, N>(buf + c * N, stw, j, yk, ynk);
+      dst_unpack<T, N>(buf + c * fft_pad_len<N>(), stw, j, yk, ynk);
       if (j >= a.w0 && j <= a.w1) dst[(size_t)(j - 1) * a.po + col] = pa[b] + yk;
       const int j2 = N - j;
       if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) dst[(size_t)(j2 - 1) * a.po + col] = pb[b] + ynk;
@@ -426,8 +425,8 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
                                                  const T* __restrict__ ring, int ring_rows,
                                                  int nblocks) {
   constexpr int NS = ROWS * (DUAL ? 2 : 1);
-  __shared__ c2<T> buf[NS * N];
-  __shared__ c2<T> stw[2 * N];
+  __shared__ c2<T> buf[NS * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
   const int blk = xcd_block(blockIdx.x, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
@@ -449,10 +448,10 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
-      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), v[b]);
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
     }
   }
-  for (int t = tid; t < NS; t += NT) dst_pack_zeros<T, N>(buf + t * N);
+  for (int t = tid; t < NS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, NS, NT>(buf, stw, tid);
   for (int e = tid; e < NS * (N / 2); e += NT) {
@@ -460,7 +459,7 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
     const int j = j0 + (t % ROWS);
     if (j > a.r1) continue;
     T xk, xnk;
-    dst_unpack<T, N>(buf + t * N, stw, k, xk, xnk);
+    dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
     if (t >= ROWS) {
       T* o = a.out2 + (size_t)(j - 1) * a.po;
       o[k - 1] = xk;
@@ -537,8 +536,8 @@ __global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gr
 template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
                                                       const c2<T>* __restrict__ tw, T* lift) {
-  __shared__ c2<T> buf[4 * N];
-  __shared__ c2<T> stw[2 * N];
+  __shared__ c2<T> buf[4 * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
   const int tid = threadIdx.x;
   {
     constexpr int CNT = 4 * (N - 1);
@@ -553,16 +552,16 @@ __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ srin
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
-      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * N, 1 + e % (N - 1), v[b]);
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
     }
   }
-  for (int edge = tid; edge < 4; edge += NT) dst_pack_zeros<T, N>(buf + edge * N);
+  for (int edge = tid; edge < 4; edge += NT) dst_pack_zeros<T, N>(buf + edge * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, 4, NT>(buf, stw, tid);
   for (int e = tid; e < 4 * (N / 2); e += NT) {
     const int edge = e / (N / 2), k = 1 + e % (N / 2);
     T xk, xnk;
-    dst_unpack<T, N>(buf + edge * N, stw, k, xk, xnk);
+    dst_unpack<T, N>(buf + edge * fft_pad_len<N>(), stw, k, xk, xnk);
     lift[edge * (N - 1) + k - 1] = xk;
     if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
   }
