@@ -20,6 +20,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-cell steps/s (1024², 4 levels) fp32 vs fp64; served p50/p99 latency"
 PEAK_HBM = 8.0e12
+# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes recorded in
+# profiles/flow_1024x4_fp32_hbm_traffic.md (scaled by a 256 MiB reference copy); valid for
+# the kernels as measured there, at n = 1024 in FP32
+TRAFFIC_PER_LAUNCH = {"col_solve": 13.66e6, "rhs_rowdst": 22.01e6, "row_idst": 17.10e6}
 
 
 def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
@@ -108,6 +112,9 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a reference "
+                         "dispatch of known traffic for hardware counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: each MI355X box here has one, and the "
@@ -117,6 +124,12 @@ def main():
     import workloads as W
     from paper_2103_06415_amd import binding
     torch.cuda.set_device(0)
+    if args.copy_ref_mb > 0:
+        src = torch.ones(args.copy_ref_mb * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, levels = args.n, args.levels
     prob = W.flag_problem(n=n, levels=levels)
     cells = n * n * levels
@@ -162,7 +175,8 @@ def main():
         "prepare_s": prep32,
         "kernel_ms_per_step": times_ms,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM,
+                     "traffic": (TRAFFIC_PER_LAUNCH.get(dom) if n == 1024 else None),
                      "bytes_per_launch": tot_bytes / max(launches, 1),
                      "avg_launch_us": 1e3 * ms / max(launches, 1)},
     }

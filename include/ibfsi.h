@@ -179,6 +179,55 @@ ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* laun
 
 ib_status ib_destroy(ib_solver* s);
 
+/* ---- device memory and streams (for schedulers running many solvers) ----
+ * ib_create allocates no device memory; ib_prepare allocates all of it. */
+
+/* Move the solver to another HIP stream (waits for the work on the current one). */
+ib_status ib_set_stream(ib_solver* s, void* hip_stream);
+
+/* Give all device memory back after copying the results to the host: afterwards
+ * ib_read_stresses, ib_read_deflection and ib_read_vorticity (level 0 only) still work,
+ * ib_step returns IB_ERR_STATE.  Safe to call on an unprepared solver. */
+ib_status ib_release(ib_solver* s);
+
+/* Device memory the solver will hold after ib_prepare (resident) and at most during
+ * it (peak, including the offline stage's batch buffers), from its configuration and
+ * bodies.  An estimate for admission control; B' is counted at 800 stored entries
+ * per row at the drop tolerance 0.007. */
+ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak);
+
+/* ---- continuous-batching scheduler ----
+ * A server runs submitted solvers (created, bodies added, not prepared) to completion
+ * on max_active concurrent slots, each a host thread with its own non-blocking stream.
+ * A request is admitted once its arrival time has passed, a slot is free and its peak
+ * memory estimate fits in what the running requests leave of hbm_budget_bytes; in the
+ * slot it is prepared, stepped (chunk_steps per call), synchronised and released
+ * (results stay readable through the solver handle, which the caller destroys).  The
+ * clock starts when ib_server_run is called; times are in seconds on that clock. */
+typedef struct ib_server ib_server;
+
+typedef struct {
+  int64_t ticket;
+  int32_t status;      /* 1 waiting, 2 running, 0 done, < 0 the solver's error */
+  int32_t steps_done;
+  double arrival;      /* as submitted */
+  double admitted;     /* slot and memory granted */
+  double started;      /* prepare finished, stepping begins */
+  double finished;     /* results on the host */
+  int64_t bytes;       /* admission estimate (peak) */
+} ib_request_info;
+
+ib_status ib_server_create(int32_t max_active, int64_t hbm_budget_bytes, int32_t chunk_steps,
+                           ib_server** out);
+/* Errors: IB_ERR_CAPACITY when the request's estimate exceeds the whole budget. */
+ib_status ib_server_submit(ib_server* sv, ib_solver* s, int32_t nsteps, double arrival,
+                           int64_t* ticket);
+/* Run until every submitted request has finished or failed (blocking). */
+ib_status ib_server_run(ib_server* sv);
+ib_status ib_server_info(ib_server* sv, int64_t ticket, ib_request_info* out);
+/* Destroys the server and its streams, not the solvers. */
+ib_status ib_server_destroy(ib_server* sv);
+
 const char* ib_status_str(ib_status st);
 
 /* ---- operator-level entry points (device pointers, enqueued on hip_stream) ---- */

@@ -59,6 +59,13 @@ class IbStats(ctypes.Structure):
     ]
 
 
+class IbRequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("ticket", c_int64), ("status", c_int32), ("steps_done", c_int32), ("arrival", c_double),
+        ("admitted", c_double), ("started", c_double), ("finished", c_double), ("bytes", c_int64),
+    ]
+
+
 _SIGS = {
     "ib_create": (c_int32, [POINTER(IbConfig), POINTER(IbAllocator), c_void_p, POINTER(c_void_p)]),
     "ib_add_rigid": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, POINTER(c_double),
@@ -82,6 +89,14 @@ _SIGS = {
     "ib_op_solve": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_void_p, c_int32, c_void_p]),
     "ib_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
     "ib_get_kernel_timing": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
+    "ib_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "ib_release": (c_int32, [c_void_p]),
+    "ib_estimate_bytes": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
+    "ib_server_create": (c_int32, [c_int32, c_int64, c_int32, POINTER(c_void_p)]),
+    "ib_server_submit": (c_int32, [c_void_p, c_void_p, c_int32, c_double, POINTER(c_int64)]),
+    "ib_server_run": (c_int32, [c_void_p]),
+    "ib_server_info": (c_int32, [c_void_p, c_int64, POINTER(IbRequestInfo)]),
+    "ib_server_destroy": (c_int32, [c_void_p]),
 }
 
 K_RHS_ROWDST, K_COL_SOLVE, K_ROW_IDST, K_FSI, K_CORRECT, K_RING = range(6)
@@ -169,7 +184,8 @@ class Solver:
         self._alloc = TorchAllocator(torch.cuda.current_device(), self.stream) if torch_alloc else None
         self.handle = c_void_p()
         _check(self.lib.ib_create(byref(cfg), byref(self._alloc.struct) if self._alloc else None,
-                                  c_void_p(self.stream.cuda_stream), byref(self.handle)), "ib_create")
+                                  c_void_p(self.stream.cuda_stream if self.stream is not False else 0),
+                                  byref(self.handle)), "ib_create")
         self.npts = []
         for b in problem.bodies:
             bid = c_int32()
@@ -248,9 +264,57 @@ class Solver:
                "ib_get_kernel_timing")
         return n.value, ms.value
 
+    def release(self):
+        """Give the device memory back; stresses, deflections and level-0 vorticity stay readable."""
+        _check(self.lib.ib_release(self.handle), "ib_release")
+
+    def estimate_bytes(self):
+        res, peak = c_int64(), c_int64()
+        _check(self.lib.ib_estimate_bytes(self.handle, byref(res), byref(peak)), "ib_estimate_bytes")
+        return res.value, peak.value
+
     def close(self):
         if self.handle:
             self.lib.ib_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching scheduler (ib_server_*): solvers built with torch_alloc=False and
+    stream=False (the server gives each its own stream), submitted with step counts and
+    arrival times, run to completion by ``run``."""
+
+    def __init__(self, max_active, hbm_budget_bytes, chunk_steps=50):
+        self.lib = load()
+        self.handle = c_void_p()
+        _check(self.lib.ib_server_create(max_active, int(hbm_budget_bytes), chunk_steps,
+                                         byref(self.handle)), "ib_server_create")
+        self.solvers = []
+
+    def submit(self, solver, nsteps, arrival=0.0):
+        t = c_int64()
+        _check(self.lib.ib_server_submit(self.handle, solver.handle, nsteps, arrival, byref(t)),
+               "ib_server_submit")
+        self.solvers.append(solver)
+        return t.value
+
+    def run(self):
+        _check(self.lib.ib_server_run(self.handle), "ib_server_run")
+
+    def info(self, ticket):
+        r = IbRequestInfo()
+        _check(self.lib.ib_server_info(self.handle, ticket, byref(r)), "ib_server_info")
+        return {k: getattr(r, k) for k, _ in IbRequestInfo._fields_}
+
+    def close(self):
+        if self.handle:
+            self.lib.ib_server_destroy(self.handle)
             self.handle = c_void_p()
 
     def __del__(self):

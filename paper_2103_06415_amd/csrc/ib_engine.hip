@@ -80,6 +80,9 @@ struct ib_solver {
   bool has_sd = false;
   double sd[4] = {0, 0, 0, 0};
   bool prepared = false, failed = false, first = true;
+  bool allocated = false;  // level state lives on the device (from ib_prepare on)
+  bool released = false;   // device memory given back; results kept on the host
+  std::vector<double> h_f, h_tors, h_chi, h_vort0;
   int64_t step = 0;
   int iters_last = 0, iters_max = 0;
   double delta_last = 0;
@@ -994,6 +997,45 @@ ib_status do_step(ib_solver* s) {
   return IB_OK;
 }
 
+// Device state of the levels (allocated by ib_prepare, so that creating a solver costs
+// no device memory and a scheduler can admit it later).
+ib_status alloc_state(ib_solver* s) {
+  const size_t full = (size_t)(s->n + 1) * s->pitch * s->es;
+  const size_t inner = (size_t)(s->n - 1) * s->pitch * s->es;
+  const size_t ring = (size_t)4 * (s->n + 1) * s->es;
+  for (auto& L : s->lv) {
+    L.s = dalloc(s, full);
+    L.g = dalloc(s, inner);
+    L.hist = dalloc(s, inner);
+    L.sring = dalloc(s, ring);
+    L.gring[0] = dalloc(s, ring);
+    L.gring[1] = dalloc(s, ring);
+    if (!L.s || !L.g || !L.hist || !L.sring || !L.gring[0] || !L.gring[1]) return IB_ERR_OOM;
+  }
+  s->work = dalloc(s, inner);
+  s->workg = dalloc(s, inner);
+  s->work2 = dalloc(s, inner);
+  s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
+  s->sstar = dalloc(s, full);
+  if (!s->work || !s->workg || !s->work2 || !s->sstar || !s->lift) return IB_ERR_OOM;
+  ib_status st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
+                         : make_tables<float>(s, s->n, &s->tw, &s->lam);
+  if (st == IB_OK) st = make_tables<double>(s, s->n, &s->tw64, &s->lam64);
+  if (st) return st;
+  for (auto& L : s->lv) {
+    HIPCHK(hipMemsetAsync(L.s, 0, full, s->stream));
+    HIPCHK(hipMemsetAsync(L.hist, 0, inner, s->stream));
+    HIPCHK(hipMemsetAsync(L.g, 0, inner, s->stream));
+    HIPCHK(hipMemsetAsync(L.sring, 0, ring, s->stream));
+    HIPCHK(hipMemsetAsync(L.gring[0], 0, ring, s->stream));
+    HIPCHK(hipMemsetAsync(L.gring[1], 0, ring, s->stream));
+  }
+  HIPCHK(hipMemsetAsync(s->work2, 0, inner, s->stream));
+  HIPCHK(hipMemsetAsync(s->sstar, 0, full, s->stream));
+  s->allocated = true;
+  return IB_OK;
+}
+
 ib_status check(ib_solver* s) {
   if (!s) return IB_ERR_ARG;
   return IB_OK;
@@ -1044,49 +1086,11 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   s->fp64 = cfg->precision == IB_FP64;
   s->es = s->fp64 ? 8 : 4;
   s->pitch = round_up(s->n + 1, 64);
-  const size_t full = (size_t)(s->n + 1) * s->pitch * s->es;
-  const size_t inner = (size_t)(s->n - 1) * s->pitch * s->es;
-  const size_t ring = (size_t)4 * (s->n + 1) * s->es;
-  ib_status st = IB_OK;
   for (int g = 0; g < cfg->levels; ++g) {
     LevelState L;
     L.h = cfg->h * std::ldexp(1.0, g);
     L.alpha = cfg->dt / (2.0 * cfg->re * L.h * L.h);
-    L.s = dalloc(s, full);
-    L.g = dalloc(s, inner);
-    if (!L.g) st = IB_ERR_OOM;
-    L.hist = dalloc(s, inner);
-    L.sring = dalloc(s, ring);
-    L.gring[0] = dalloc(s, ring);
-    L.gring[1] = dalloc(s, ring);
-    if (!L.s || !L.hist || !L.sring || !L.gring[0] || !L.gring[1]) st = IB_ERR_OOM;
     s->lv.push_back(L);
-  }
-  s->work = dalloc(s, inner);
-  s->workg = dalloc(s, inner);
-  s->work2 = dalloc(s, inner);
-  s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
-  s->sstar = dalloc(s, full);
-  if (!s->work || !s->workg || !s->work2 || !s->sstar || !s->lift) st = IB_ERR_OOM;
-  if (st == IB_OK) {
-    st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
-                 : make_tables<float>(s, s->n, &s->tw, &s->lam);
-  }
-  if (st == IB_OK) st = make_tables<double>(s, s->n, &s->tw64, &s->lam64);
-  if (st == IB_OK) {
-    for (auto& L : s->lv) {
-      if (hipMemset(L.s, 0, full) != hipSuccess || hipMemset(L.hist, 0, inner) != hipSuccess ||
-          hipMemset(L.g, 0, inner) != hipSuccess ||
-          hipMemset(L.sring, 0, ring) != hipSuccess || hipMemset(L.gring[0], 0, ring) != hipSuccess ||
-          hipMemset(L.gring[1], 0, ring) != hipSuccess)
-        st = IB_ERR_HIP;
-    }
-    if (hipMemset(s->work2, 0, inner) != hipSuccess || hipMemset(s->sstar, 0, full) != hipSuccess)
-      st = IB_ERR_HIP;
-  }
-  if (st != IB_OK) {
-    ib_destroy(s);
-    return st;
   }
   *out = s;
   return IB_OK;
@@ -1175,8 +1179,9 @@ ib_status ib_set_vorticity(ib_solver* s, int32_t level, const double* omega) {
 
 ib_status ib_prepare(ib_solver* s) {
   if (check(s)) return IB_ERR_ARG;
-  if (s->prepared) return IB_ERR_STATE;
-  ib_status st = s->fp64 ? do_prepare<double>(s) : do_prepare<float>(s);
+  if (s->prepared || s->released) return IB_ERR_STATE;
+  ib_status st = s->allocated ? IB_OK : alloc_state(s);
+  if (st == IB_OK) st = s->fp64 ? do_prepare<double>(s) : do_prepare<float>(s);
   if (st) {
     s->failed = true;
     return st;
@@ -1187,7 +1192,7 @@ ib_status ib_prepare(ib_solver* s) {
 
 ib_status ib_step(ib_solver* s, int32_t nsteps) {
   if (check(s) || nsteps < 0) return IB_ERR_ARG;
-  if (!s->prepared || s->failed) return IB_ERR_STATE;
+  if (!s->prepared || s->failed || s->released) return IB_ERR_STATE;
   for (int k = 0; k < nsteps; ++k) {
     ib_status st = s->fp64 ? do_step<double>(s) : do_step<float>(s);
     if (st) {
@@ -1206,11 +1211,15 @@ ib_status ib_sync(ib_solver* s) {
 
 ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap) {
   if (check(s) || !f || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
-  if (!s->prepared || !s->f) return IB_ERR_STATE;
+  if (!s->prepared || (!s->f && !s->released)) return IB_ERR_STATE;
   int pt0 = 0;
   for (int k = 0; k < body_id; ++k) pt0 += s->bodies[k].m;
   const int m = s->bodies[body_id].m;
   if (cap < 2 * m) return IB_ERR_CAPACITY;
+  if (s->released) {
+    std::memcpy(f, s->h_f.data() + 2 * pt0, (size_t)2 * m * 8);
+    return IB_OK;
+  }
   HIPCHK(hipStreamSynchronize(s->stream));
   HIPCHK(hipMemcpy(f, s->f + 2 * pt0, (size_t)2 * m * 8, hipMemcpyDeviceToHost));
   return IB_OK;
@@ -1219,7 +1228,7 @@ ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap) {
   if (check(s) || !out || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
   if (!s->prepared) return IB_ERR_STATE;
-  HIPCHK(hipStreamSynchronize(s->stream));
+  if (!s->released) HIPCHK(hipStreamSynchronize(s->stream));
   const HostBody& hb = s->bodies[body_id];
   int tors = 0, dof = 0;
   for (int k = 0; k < body_id; ++k) {
@@ -1228,10 +1237,12 @@ ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t
   }
   if (hb.kind == BODY_TORSIONAL) {
     if (cap < 3) return IB_ERR_CAPACITY;
-    HIPCHK(hipMemcpy(out, s->fa.tors + tors * TS_COUNT, 3 * 8, hipMemcpyDeviceToHost));
+    if (s->released) std::memcpy(out, s->h_tors.data() + tors * TS_COUNT, 3 * 8);
+    else HIPCHK(hipMemcpy(out, s->fa.tors + tors * TS_COUNT, 3 * 8, hipMemcpyDeviceToHost));
   } else if (hb.kind == BODY_DEFORMABLE) {
     if (cap < 3 * hb.m) return IB_ERR_CAPACITY;
-    HIPCHK(hipMemcpy(out, s->fa.chi + dof, (size_t)3 * hb.m * 8, hipMemcpyDeviceToHost));
+    if (s->released) std::memcpy(out, s->h_chi.data() + dof, (size_t)3 * hb.m * 8);
+    else HIPCHK(hipMemcpy(out, s->fa.chi + dof, (size_t)3 * hb.m * 8, hipMemcpyDeviceToHost));
   } else {
     if (cap < 2 * hb.m) return IB_ERR_CAPACITY;
     std::memcpy(out, hb.xy.data(), (size_t)2 * hb.m * 8);
@@ -1241,6 +1252,7 @@ ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t
 
 ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap) {
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
+  if (!s->allocated) return IB_ERR_STATE;
   const int n = s->n;
   if (cap < (int64_t)(n + 1) * (n + 1)) return IB_ERR_CAPACITY;
   HIPCHK(hipStreamSynchronize(s->stream));
@@ -1259,6 +1271,12 @@ ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t ca
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
   const int n = s->n;
   if (cap < (int64_t)(n - 1) * (n - 1)) return IB_ERR_CAPACITY;
+  if (s->released) {
+    if (level != 0) return IB_ERR_STATE;
+    std::memcpy(out, s->h_vort0.data(), s->h_vort0.size() * 8);
+    return IB_OK;
+  }
+  if (!s->allocated) return IB_ERR_STATE;
   HIPCHK(hipStreamSynchronize(s->stream));
   std::vector<char> buf((size_t)(n - 1) * s->pitch * s->es);
   HIPCHK(hipMemcpy(buf.data(), s->lv[level].g, buf.size(), hipMemcpyDeviceToHost));
@@ -1308,6 +1326,77 @@ ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* laun
   harvest_events(s);
   *launches = s->t_count[kernel_class];
   *total_ms = s->t_ms[kernel_class];
+  return IB_OK;
+}
+
+ib_status ib_set_stream(ib_solver* s, void* hip_stream) {
+  if (check(s)) return IB_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  return IB_OK;
+}
+
+ib_status ib_release(ib_solver* s) {
+  if (check(s)) return IB_ERR_ARG;
+  if (s->released) return IB_OK;
+  if (s->allocated) {
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->prepared && s->f) {
+      s->h_f.resize(s->nf);
+      HIPCHK(hipMemcpy(s->h_f.data(), s->f, (size_t)s->nf * 8, hipMemcpyDeviceToHost));
+      s->h_tors.resize((size_t)s->ntors * TS_COUNT);
+      if (s->ntors)
+        HIPCHK(hipMemcpy(s->h_tors.data(), s->fa.tors, s->h_tors.size() * 8, hipMemcpyDeviceToHost));
+      s->h_chi.resize(s->ndof);
+      if (s->ndof)
+        HIPCHK(hipMemcpy(s->h_chi.data(), s->fa.chi, s->h_chi.size() * 8, hipMemcpyDeviceToHost));
+    }
+    std::vector<double> v((size_t)(s->n - 1) * (s->n - 1));
+    ib_status st = ib_read_vorticity(s, 0, v.data(), (int64_t)v.size());
+    if (st) return st;
+    s->h_vort0.swap(v);
+  }
+  harvest_events(s);
+  while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
+  s->f = nullptr;
+  s->allocated = false;
+  s->released = true;
+  return IB_OK;
+}
+
+ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak) {
+  if (!s || !resident || !peak) return IB_ERR_ARG;
+  const int n = s->n, G = (int)s->lv.size();
+  const size_t es = s->es, P = s->pitch;
+  const size_t full = (size_t)(n + 1) * P * es, inner = (size_t)(n - 1) * P * es;
+  size_t r = (size_t)G * (full + 2 * inner + 3 * 4 * (n + 1) * es);
+  r += 3 * inner + full + 4 * (size_t)(n - 1) * es + 2 * (size_t)2 * n * (8 + es);
+  size_t npts = 0, ndef_y = 0, app = 0;
+  for (auto& hb : s->bodies) {
+    npts += hb.m;
+    if (hb.kind == BODY_DEFORMABLE) ndef_y += (size_t)(3 * hb.m) * (2 * hb.m + 1);
+    if (hb.kind == BODY_RIGID) app += hb.m;
+  }
+  const size_t nf = 2 * npts, pm = (nf + 7) / 8 * 8;
+  size_t peak_extra = 0;
+  if (nf) {
+    r += 5 * nf * pm * 8 + nf * (16 * 8 + 3 * 4 + 4 * 12 + 4 * 8) + ndef_y * 8 + (1 << 20);
+    if (s->has_sd) {
+      // B' rows and an allowance of 800 stored entries per row (about 750 measured at
+      // the drop tolerance 0.007), plus the offline batch buffers
+      const double h = s->cfg.h;
+      const size_t npx = (size_t)((s->sd[1] - s->sd[0]) / h) + 3;
+      const size_t npy = (size_t)((s->sd[3] - s->sd[2]) / h) + 3;
+      const size_t rows = 2 * (npx * npy + app);
+      const double scale = s->cfg.drop_tol > 0 ? std::min(4.0, 0.007 / s->cfg.drop_tol) : 4.0;
+      r += rows * (size_t)(800 * scale) * 12 + rows * 12;
+      peak_extra = (size_t)1 << 30;
+    } else {
+      peak_extra = std::min<size_t>((size_t)1 << 30, nf * ((size_t)(2 * n + 6) * P * 8 + nf * 8));
+    }
+  }
+  *resident = (int64_t)r;
+  *peak = (int64_t)(r + peak_extra);
   return IB_OK;
 }
 

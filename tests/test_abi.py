@@ -58,3 +58,54 @@ def test_null_handles_are_rejected(lib):
     assert lib.ib_prepare(None) == -1
     assert lib.ib_step(None, 1) == -1
     assert lib.ib_destroy(None) == -1
+
+
+def _config(binding, n, levels):
+    return binding.IbConfig(n=n, levels=levels, h=2.0 / n, re=200.0, dt=0.4 / n, cx=0.0, cy=0.0,
+                            precision=binding.IB_FP32_FLOW, newton_tol=1e-7, newton_max_iter=20,
+                            drop_tol=0.007)
+
+
+def test_create_allocates_nothing_and_estimates_memory(lib):
+    """ib_create holds no device memory (so it works without a GPU); the admission
+    estimate grows with the grid, the levels and the precision."""
+    from paper_2103_06415_amd import binding
+    est = {}
+    for n, levels, prec in ((64, 1, binding.IB_FP32_FLOW), (128, 1, binding.IB_FP32_FLOW),
+                            (128, 3, binding.IB_FP32_FLOW), (128, 3, binding.IB_FP64)):
+        cfg = _config(binding, n, levels)
+        cfg.precision = prec
+        h = ctypes.c_void_p()
+        assert lib.ib_create(ctypes.byref(cfg), None, None, ctypes.byref(h)) == 0
+        res, peak = ctypes.c_int64(), ctypes.c_int64()
+        assert lib.ib_estimate_bytes(h, ctypes.byref(res), ctypes.byref(peak)) == 0
+        assert 0 < res.value <= peak.value
+        est[(n, levels, prec)] = res.value
+        out = (ctypes.c_double * ((n - 1) * (n - 1)))()
+        assert lib.ib_read_vorticity(h, 0, out, (n - 1) * (n - 1)) == -2  # nothing on the device yet
+        assert lib.ib_release(h) == 0
+        assert lib.ib_destroy(h) == 0
+    f32, f64 = binding.IB_FP32_FLOW, binding.IB_FP64
+    assert est[(64, 1, f32)] < est[(128, 1, f32)] < est[(128, 3, f32)] < est[(128, 3, f64)]
+    # one FP32 level of n^2 cells holds about 6 arrays of n^2 floats (state, history,
+    # work): the estimate is of that order, not wildly off
+    n2 = 128 * 128 * 4
+    assert 3 * n2 < est[(128, 1, f32)] < 40 * n2
+
+
+def test_estimate_counts_the_subdomain_operator(lib):
+    from paper_2103_06415_amd import binding
+    cfg = _config(binding, 128, 2)
+    h = ctypes.c_void_p()
+    assert lib.ib_create(ctypes.byref(cfg), None, None, ctypes.byref(h)) == 0
+    bid = ctypes.c_int32()
+    assert lib.ib_add_torsional(h, 11, 0.0, 0.0, 0.5, -0.3, 5.0, 1.0, 0.1, 0.0, 0.0,
+                                ctypes.byref(bid)) == 0
+    r0, p0 = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.ib_estimate_bytes(h, ctypes.byref(r0), ctypes.byref(p0)) == 0
+    assert lib.ib_set_subdomain(h, -0.05, 0.55, -0.4, 0.4) == 0
+    r1, p1 = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.ib_estimate_bytes(h, ctypes.byref(r1), ctypes.byref(p1)) == 0
+    rows = 2 * (int(0.6 / cfg.h) + 3) * (int(0.8 / cfg.h) + 3)
+    assert r1.value - r0.value >= rows * 800 * 12
+    assert lib.ib_destroy(h) == 0

@@ -1,0 +1,103 @@
+"""Serving: requests run through the continuous-batching scheduler give the same results
+as the same solvers run alone, and the scheduler's bookkeeping is consistent."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _problems():
+    return [
+        (W.cylinder_problem(n=32, steps=6), 6),
+        (W.plate_problem(n=32, levels=2, steps=5), 5),
+        (W.flag_problem(n=32, levels=2, steps=4), 4),
+        (W.cylinder_problem(n=48, seed=5, steps=7), 7),
+        (W.plate_problem(n=48, levels=1, steps=6), 6),
+    ]
+
+
+def _results(s, problem):
+    out = {"vort": s.vorticity(0)}
+    for b in range(len(problem.bodies)):
+        out[f"f{b}"] = s.stresses(b)
+        out[f"d{b}"] = s.deflection(b)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_served_results_equal_the_same_runs_alone(torch_cuda, gpu_lib, prec):
+    from paper_2103_06415_amd import binding
+    p_ = binding.IB_FP64 if prec == "fp64" else binding.IB_FP32_FLOW
+    print(f"serve mix {prec}", flush=True)
+    alone = []
+    for problem, steps in _problems():
+        s = binding.Solver(problem, precision=p_, torch_alloc=False)
+        s.prepare()
+        s.step(steps)
+        s.sync()
+        alone.append(_results(s, problem))
+        s.close()
+    server = binding.Server(max_active=3, hbm_budget_bytes=8 << 30, chunk_steps=2)
+    solvers, tickets = [], []
+    for k, (problem, steps) in enumerate(_problems()):
+        s = binding.Solver(problem, precision=p_, torch_alloc=False, stream=False)
+        solvers.append(s)
+        tickets.append(server.submit(s, steps, arrival=0.01 * k))
+    server.run()
+    infos = [server.info(t) for t in tickets]
+    for k, ((problem, steps), s, info) in enumerate(zip(_problems(), solvers, infos)):
+        print(f"  request {k}: {info}", flush=True)
+        assert info["status"] == 0
+        assert info["steps_done"] == steps
+        assert info["admitted"] >= info["arrival"] - 1e-9
+        assert info["started"] >= info["admitted"] and info["finished"] >= info["started"]
+        got = _results(s, problem)
+        for key, ref in alone[k].items():
+            err = float(np.max(np.abs(got[key] - ref))) if ref.size else 0.0
+            assert err == 0.0, (k, key, err)
+        s.close()
+    # at most max_active requests ran at once
+    events = sorted([(i["admitted"], 1) for i in infos] + [(i["finished"], -1) for i in infos])
+    live = peak = 0
+    for _, d in events:
+        live += d
+        peak = max(peak, live)
+    assert peak <= 3
+    server.close()
+
+
+def test_admission_respects_the_memory_budget(torch_cuda, gpu_lib):
+    from paper_2103_06415_amd import binding
+    problems = _problems()[:3]
+    sizes = []
+    solvers = []
+    for problem, _ in problems:
+        s = binding.Solver(problem, precision=binding.IB_FP32_FLOW, torch_alloc=False, stream=False)
+        sizes.append(s.estimate_bytes()[1])
+        solvers.append(s)
+    # a budget that fits the largest request but no two of them at once
+    s0, s1 = sorted(sizes)[:2]
+    budget = s0 + s1 - 1
+    if budget < max(sizes):
+        pytest.skip("request sizes do not allow such a budget")
+    server = binding.Server(max_active=3, hbm_budget_bytes=budget, chunk_steps=3)
+    tickets = [server.submit(s, steps) for s, (_, steps) in zip(solvers, problems)]
+    server.run()
+    infos = sorted((server.info(t) for t in tickets), key=lambda i: i["admitted"])
+    for a, b in zip(infos, infos[1:]):
+        assert b["admitted"] >= a["finished"] - 1e-6, (a, b)
+    for i in infos:
+        assert i["status"] == 0
+    for s in solvers:
+        s.close()
+    server.close()
