@@ -11,6 +11,7 @@ One JSON line on stdout.  ``--gpus`` above 1 is not supported (one GPU per run).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -76,6 +77,42 @@ def run(problem, precision, steps, warmup, timing=True):
     return wall, prep, kt, st
 
 
+def serve(problems, max_active=8, budget=200 << 30, precision=None):
+    """Run (arrival, Problem) requests through the continuous-batching server."""
+    from paper_2103_06415_amd import binding
+    prec = binding.IB_FP32_FLOW if precision is None else precision
+    server = binding.Server(max_active=max_active, hbm_budget_bytes=budget, chunk_steps=50)
+    solvers, tickets, cells = [], [], 0
+    for arrival, p in problems:
+        s = binding.Solver(p, precision=prec, torch_alloc=False, stream=False)
+        solvers.append(s)
+        tickets.append(server.submit(s, p.steps, arrival=arrival))
+        cells += p.flow.n * p.flow.n * p.flow.levels * p.steps
+    t0 = time.perf_counter()
+    server.run()
+    wall = time.perf_counter() - t0
+    infos = [server.info(t) for t in tickets]
+    sources = [s.stats()["operator_source"] for s in solvers]
+    for s in solvers:
+        s.close()
+    server.close()
+    ok = [i for i in infos if i["status"] == 0]
+    lat = sorted(i["finished"] - i["arrival"] for i in ok)
+    done_cells = sum(p.flow.n ** 2 * p.flow.levels * p.steps
+                     for (_, p), i in zip(problems, infos) if i["status"] == 0)
+    makespan = max(i["finished"] for i in infos) if infos else 0.0
+
+    def pct(q):
+        return lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)] if lat else None
+    return {"requests": len(infos), "failed": len(infos) - len(ok),
+            "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99),
+            "makespan_s": makespan, "wall_s": wall,
+            "throughput": done_cells / makespan if makespan > 0 else None,
+            "throughput_unit": "grid-cell steps/s", "requests_per_s": len(ok) / makespan if makespan else None,
+            "max_active": max_active,
+            "operators_built": sources.count(0), "operators_from_cache": sources.count(1)}
+
+
 def cpu_baseline(n, levels, seconds=20.0):
     """The FP64 oracle on the host: flow steps of the same grid (no body coupling)."""
     import numpy as np
@@ -112,6 +149,10 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving trace (48 Poisson arrivals at 40/s, 256^2..1024^2)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also run the 64-instance batch (sizes 128^2..768^2, 200 steps each)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware counter calibration)")
@@ -180,6 +221,15 @@ def main():
                      "bytes_per_launch": tot_bytes / max(launches, 1),
                      "avg_launch_us": 1e3 * ms / max(launches, 1)},
     }
+    if not args.no_serve:
+        # continuous batching of a seeded Poisson trace; latency = finish - arrival
+        out["served"] = serve(W.serve_trace())
+        out["served"]["workload"] = ("48 requests, Poisson arrivals 40/s, 6 families of "
+                                     "256^2x1 .. 1024^2x4 grids with 1-3 rigid/torsional/"
+                                     "deformable bodies, 200-2000 steps, FP32 flow")
+    if args.batch:
+        out["batched"] = serve([(0.0, p) for p in W.batch_problems()], max_active=16)
+        out["batched"]["workload"] = "64 instances, 128^2..768^2 x 1-3 levels, 200 steps"
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, levels)
     print(json.dumps(out))

@@ -102,6 +102,8 @@ typedef struct {
   int32_t refine_iters;      /* Schur refinement sweeps in the last FSI iteration */
   int32_t inverse_rebuilds;  /* fresh Schur inverses (LU) made so far */
   double refine_residual;    /* relative residual of the last Schur solve */
+  int32_t operator_source;   /* offline operator: 0 built, 1 from the cache, 2 imported,
+                                -1 none (no bodies) */
 } ib_stats;
 
 /* Create a solver.  `alloc` may be NULL (hipMalloc); `hip_stream` is a hipStream_t
@@ -195,6 +197,24 @@ ib_status ib_release(ib_solver* s);
  * bodies.  An estimate for admission control; B' is counted at 800 stored entries
  * per row at the drop tolerance 0.007. */
 ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak);
+
+/* ---- offline operator reuse (Sec. 3.2.2: the offline stage depends only on the grid,
+ * dt, Re and the sub-domain, so it can serve many problems) ----
+ * ib_prepare keeps every operator it builds (B' for moving bodies, the unscaled Schur
+ * matrix for stationary ones) in a process-wide host cache keyed by exactly the numbers
+ * it depends on (grid, dt, Re, drop tolerance, sub-domain, stationary points), and takes
+ * it from there when a later solver has the same key. */
+
+/* Cache capacity in bytes (default 8 GiB; 0 disables caching and empties the cache). */
+ib_status ib_set_operator_cache(int64_t limit_bytes);
+
+/* Serialise the operator the prepared solver uses into buf (cap bytes); *used receives the
+ * size needed (IB_ERR_CAPACITY, with *used set, when buf is NULL or too small). */
+ib_status ib_export_operator(ib_solver* s, void* buf, int64_t cap, int64_t* used);
+
+/* Give an unprepared solver an operator exported earlier; ib_prepare checks that its key
+ * matches the solver's problem (IB_ERR_ARG otherwise) and skips the offline stage. */
+ib_status ib_import_operator(ib_solver* s, const void* buf, int64_t size);
 
 /* ---- continuous-batching scheduler ----
  * A server runs submitted solvers (created, bodies added, not prepared) to completion

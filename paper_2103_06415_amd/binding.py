@@ -55,7 +55,7 @@ class IbStats(ctypes.Structure):
         ("step", c_int64), ("newton_iters", c_int32), ("newton_iters_max", c_int32),
         ("newton_delta", c_double), ("subdomain_points", c_int64), ("subdomain_nnz", c_int64),
         ("prepare_seconds", c_double), ("refine_iters", c_int32), ("inverse_rebuilds", c_int32),
-        ("refine_residual", c_double),
+        ("refine_residual", c_double), ("operator_source", c_int32),
     ]
 
 
@@ -90,6 +90,9 @@ _SIGS = {
     "ib_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
     "ib_get_kernel_timing": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "ib_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "ib_set_operator_cache": (c_int32, [c_int64]),
+    "ib_export_operator": (c_int32, [c_void_p, c_void_p, c_int64, POINTER(c_int64)]),
+    "ib_import_operator": (c_int32, [c_void_p, c_void_p, c_int64]),
     "ib_release": (c_int32, [c_void_p]),
     "ib_estimate_bytes": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     "ib_server_create": (c_int32, [c_int32, c_int64, c_int32, POINTER(c_void_p)]),
@@ -154,6 +157,10 @@ class TorchAllocator:
         self._alloc = ALLOC_FN(_alloc)
         self._free = FREE_FN(_free)
         self.struct = IbAllocator(self._alloc, self._free, None)
+
+
+def set_operator_cache(limit_bytes):
+    _check(load().ib_set_operator_cache(int(limit_bytes)), "ib_set_operator_cache")
 
 
 def op_solve(n, precision, alpha, in_ptr, out_ptr, pitch, stream=0):
@@ -267,6 +274,20 @@ class Solver:
     def release(self):
         """Give the device memory back; stresses, deflections and level-0 vorticity stay readable."""
         _check(self.lib.ib_release(self.handle), "ib_release")
+
+    def export_operator(self):
+        """The offline operator as bytes (see ib_export_operator)."""
+        used = c_int64()
+        code = self.lib.ib_export_operator(self.handle, None, 0, byref(used))
+        if code not in (0, -9):
+            raise IbError(code, "ib_export_operator")
+        buf = ctypes.create_string_buffer(used.value)
+        _check(self.lib.ib_export_operator(self.handle, buf, used.value, byref(used)),
+               "ib_export_operator")
+        return buf.raw
+
+    def import_operator(self, data):
+        _check(self.lib.ib_import_operator(self.handle, data, len(data)), "ib_import_operator")
 
     def estimate_bytes(self):
         res, peak = c_int64(), c_int64()

@@ -16,7 +16,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +35,75 @@ namespace {
 // refinement sweeps launched per Schur solve; one that has not converged by then makes
 // the solver rebuild its approximate inverse
 constexpr int REFINE_MAXIT = 16;
+
+// ---- offline operator cache
+// The offline stage's product depends only on the grid, dt, Re and the sub-domain (plus
+// the points of stationary bodies): B' for moving bodies (Algorithm 1), the unscaled
+// Schur matrix G = E C (C^T A C)^{-1} C^T E^T for stationary ones.  A process-wide host
+// cache keyed by exactly those numbers lets later solvers (e.g. the requests of a
+// parametric study) skip the offline stage; entries are shared read-only, evicted least
+// recently used beyond a byte limit, and a solver that finds its key being built by
+// another thread waits for it.  ib_export_operator / ib_import_operator move the same
+// data across processes.
+struct OpData {
+  std::vector<double> key;
+  std::vector<int64_t> ptr;  // B': CSR rows (empty for G)
+  std::vector<int32_t> col;
+  std::vector<double> val;   // B' values, or G row-major with pitch pm
+  size_t bytes() const { return ptr.size() * 8 + col.size() * 4 + val.size() * 8 + key.size() * 8; }
+};
+using OpPtr = std::shared_ptr<const OpData>;
+
+struct OpCache {
+  std::mutex mu;
+  std::condition_variable cv;
+  std::list<OpPtr> lru;                 // most recent first
+  std::vector<std::vector<double>> building;
+  size_t bytes = 0;
+  size_t limit = (size_t)8 << 30;
+};
+OpCache& op_cache() {
+  static OpCache c;
+  return c;
+}
+
+// Find key; if another thread is building it, wait.  Returns null when absent (and then
+// registers the caller as its builder, who must call op_cache_put or op_cache_abandon).
+OpPtr op_cache_get(const std::vector<double>& key) {
+  OpCache& c = op_cache();
+  std::unique_lock<std::mutex> lk(c.mu);
+  if (c.limit == 0) return nullptr;
+  for (;;) {
+    for (auto it = c.lru.begin(); it != c.lru.end(); ++it)
+      if ((*it)->key == key) {
+        OpPtr p = *it;
+        c.lru.erase(it);
+        c.lru.push_front(p);
+        return p;
+      }
+    if (std::find(c.building.begin(), c.building.end(), key) == c.building.end()) {
+      c.building.push_back(key);
+      return nullptr;
+    }
+    c.cv.wait(lk);
+  }
+}
+
+void op_cache_done(const std::vector<double>& key, OpPtr p) {
+  OpCache& c = op_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto b = std::find(c.building.begin(), c.building.end(), key);
+  if (b != c.building.end()) c.building.erase(b);
+  if (p && c.limit > 0 && p->bytes() <= c.limit) {
+    c.lru.push_front(p);
+    c.bytes += p->bytes();
+    while (c.bytes > c.limit && !c.lru.empty()) {
+      c.bytes -= c.lru.back()->bytes();
+      c.lru.pop_back();
+    }
+  }
+  c.cv.notify_all();
+}
 
 struct HostBody {
   int kind = BODY_RIGID;
@@ -96,6 +169,9 @@ struct ib_solver {
   int sd_i0 = 0, sd_i1 = 0, sd_j0 = 0, sd_j1 = 0, sd_npx = 0, sd_npy = 0, sd_ngrid = 0,
       sd_total = 0;
   int64_t bp_nnz = 0;
+  std::shared_ptr<const OpData> op;        // offline operator in use (built, cached or imported)
+  std::shared_ptr<const OpData> imported;  // from ib_import_operator, checked at prepare
+  int op_source = 0;                       // 0 built, 1 from the cache, 2 imported
   int blo = 1, bhi = 1, bilo = 1, bihi = 1;  // rows / columns the bodies can touch
   FsiArgs fa{};
   double* f = nullptr;
@@ -398,6 +474,35 @@ ib_status map_flags(ib_solver* s, int code) {
 }
 
 // Device body data, the stationary Schur inverse or B' (Algorithm 1).
+// The offline operator for `key`: the imported one (which must match), a cached one, or
+// a new one from `build`, which then enters the cache.
+template <typename F>
+ib_status acquire_op(ib_solver* s, const std::vector<double>& key, F build) {
+  if (s->imported) {
+    if (s->imported->key != key) {
+      s->last_error = "imported operator does not match this problem";
+      return IB_ERR_ARG;
+    }
+    s->op = s->imported;
+    s->op_source = 2;
+    return IB_OK;
+  }
+  OpPtr p = op_cache_get(key);
+  if (p) {
+    s->op = p;
+    s->op_source = 1;
+    return IB_OK;
+  }
+  auto d = std::make_shared<OpData>();
+  d->key = key;
+  ib_status st = build(*d);
+  op_cache_done(key, st ? nullptr : d);
+  if (st) return st;
+  s->op = d;
+  s->op_source = 0;
+  return IB_OK;
+}
+
 template <typename T>
 ib_status prepare_bodies(ib_solver* s) {
   const int n = s->n;
@@ -657,33 +762,55 @@ ib_status prepare_bodies(ib_solver* s) {
     rows.kind = 0;
     rows.st_base = a.st_base;
     rows.st_w = a.st_w;
-    Offline w;
-    const int slots = std::min(offline_slots(s, nf), nf);
-    if ((st = offline_alloc(s, w, slots, nf))) return st;
+    // the cached product is M^{-1} itself (stationary bodies: the whole Schur inverse
+    // depends only on the key, which includes the points' arc lengths)
     double* G = a.M;  // G then M in place
     const int tlo = std::max(1, s->blo), thi = std::min(n - 1, s->bhi);
-    std::vector<double> hv((size_t)slots * nf);
-    std::vector<double> gm((size_t)nf * a.pm, 0.0);
-    for (int c0 = 0; c0 < nf; c0 += slots) {
-      if ((st = offline_columns(s, w, rows, c0, nf, rows, nf, tlo, thi))) return st;
-      const int ns = std::min(slots, nf - c0);
-      HIPCHK(hipMemcpyAsync(hv.data(), w.vals, (size_t)ns * nf * 8, hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(hipStreamSynchronize(s->stream));
-      for (int b = 0; b < ns; ++b)
-        for (int t = 0; t < nf; ++t) gm[(size_t)t * a.pm + c0 + b] = hv[(size_t)b * nf + t];
-    }
-    offline_free(s, w);
-    HIPCHK(hipMemcpy(G, gm.data(), gm.size() * 8, hipMemcpyHostToDevice));
-    HIPCHK(launch_scale_cols(G, a.pm, nf, dsr, s->cfg.dt / (h * h), s->stream));
-    // inverse: solve M X = I
+    std::vector<double> key = {0.0, (double)n, h, x0, y0, s->cfg.dt, s->cfg.re, (double)nf,
+                               (double)a.pm};
+    key.insert(key.end(), rigid_xy.begin(), rigid_xy.end());
+    key.insert(key.end(), s->ds_rows.begin(), s->ds_rows.end());
     s->Minv = static_cast<double*>(dalloc(s, (size_t)nf * a.pm * 8 + 8));
-    std::vector<double> eye((size_t)nf * a.pm, 0.0);
-    for (int k = 0; k < nf; ++k) eye[(size_t)k * a.pm + k] = 1.0;
-    HIPCHK(hipMemcpy(s->Minv, eye.data(), eye.size() * 8, hipMemcpyHostToDevice));
-    HIPCHK(launch_lu_solve(G, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
-    if ((st = map_flags(s, s->hflags[0]))) return st;
+    if (!s->Minv) return IB_ERR_OOM;
+    st = acquire_op(s, key, [&](OpData& d) -> ib_status {
+      Offline w;
+      const int slots = std::min(offline_slots(s, nf), nf);
+      ib_status e = offline_alloc(s, w, slots, nf);
+      if (e) return e;
+      std::vector<double> hv((size_t)slots * nf);
+      std::vector<double> gm((size_t)nf * a.pm, 0.0);
+      for (int c0 = 0; c0 < nf; c0 += slots) {
+        if ((e = offline_columns(s, w, rows, c0, nf, rows, nf, tlo, thi))) return e;
+        const int ns = std::min(slots, nf - c0);
+        HIPCHK(hipMemcpyAsync(hv.data(), w.vals, (size_t)ns * nf * 8, hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        for (int b = 0; b < ns; ++b)
+          for (int t = 0; t < nf; ++t) gm[(size_t)t * a.pm + c0 + b] = hv[(size_t)b * nf + t];
+      }
+      offline_free(s, w);
+      HIPCHK(hipMemcpy(G, gm.data(), gm.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(launch_scale_cols(G, a.pm, nf, dsr, s->cfg.dt / (h * h), s->stream));
+      // inverse: solve M X = I
+      std::vector<double> eye((size_t)nf * a.pm, 0.0);
+      for (int k = 0; k < nf; ++k) eye[(size_t)k * a.pm + k] = 1.0;
+      HIPCHK(hipMemcpy(s->Minv, eye.data(), eye.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(launch_lu_solve(G, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+      HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
+      if ((e = map_flags(s, s->hflags[0]))) return e;
+      d.val.resize((size_t)nf * a.pm);
+      HIPCHK(hipMemcpy(d.val.data(), s->Minv, d.val.size() * 8, hipMemcpyDeviceToHost));
+      return IB_OK;
+    });
+    if (st) return st;
+    if (s->op_source != 0) {
+      if (s->op->val.size() != (size_t)nf * a.pm) {
+        s->last_error = "offline operator has the wrong size";
+        return IB_ERR_ARG;
+      }
+      HIPCHK(hipMemcpy(s->Minv, s->op->val.data(), s->op->val.size() * 8, hipMemcpyHostToDevice));
+    }
     a.Minv = s->Minv;
   } else if (s->use_sd) {
     OffRows rows = geo;
@@ -704,51 +831,64 @@ ib_status prepare_bodies(ib_solver* s) {
     }
     tlo = std::max(1, tlo);
     thi = std::min(n - 1, thi);
-    Offline w;
-    const int slots = std::min(offline_slots(s, nsd), nsd);
-    if ((st = offline_alloc(s, w, slots, nsd))) return st;
-    int* ccol = static_cast<int*>(dalloc(s, (size_t)slots * nsd * 4));
-    double* cval = static_cast<double*>(dalloc(s, (size_t)slots * nsd * 8));
-    int* counts = static_cast<int*>(dalloc(s, (size_t)slots * 4));
-    int* gcol = static_cast<int*>(dalloc(s, (size_t)slots * nsd * 4));
-    double* gval = static_cast<double*>(dalloc(s, (size_t)slots * nsd * 8));
-    if (!ccol || !cval || !counts || !gcol || !gval) return IB_ERR_OOM;
-    std::vector<int64_t> rowptr(1, 0);
-    std::vector<int32_t> hcol;
-    std::vector<double> hval;
-    std::vector<int> hcounts(slots);
-    for (int c0 = 0; c0 < nsd; c0 += slots) {
-      if ((st = offline_columns(s, w, rows, c0, nsd, rows, nsd, tlo, thi))) return st;
-      const int ns = std::min(slots, nsd - c0);
-      HIPCHK(launch_filter_compact(w.vals, nsd, c0, nsd, ns, s->cfg.drop_tol, ccol, cval, counts,
-                                   s->stream));
-      HIPCHK(launch_gather_batch(ccol, cval, nsd, counts, ns, gcol, gval, s->stream));
-      HIPCHK(hipMemcpyAsync(hcounts.data(), counts, (size_t)ns * 4, hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(hipStreamSynchronize(s->stream));
-      int64_t tot = 0;
-      for (int b = 0; b < ns; ++b) tot += hcounts[b];
-      const size_t old = hcol.size();
-      hcol.resize(old + tot);
-      hval.resize(old + tot);
-      HIPCHK(hipMemcpy(hcol.data() + old, gcol, (size_t)tot * 4, hipMemcpyDeviceToHost));
-      HIPCHK(hipMemcpy(hval.data() + old, gval, (size_t)tot * 8, hipMemcpyDeviceToHost));
-      for (int b = 0; b < ns; ++b) rowptr.push_back(rowptr.back() + hcounts[b]);
+    std::vector<double> key = {1.0, (double)n, h, x0, y0, s->cfg.dt, s->cfg.re, s->cfg.drop_tol,
+                               (double)s->sd_i0, (double)s->sd_i1, (double)s->sd_j0,
+                               (double)s->sd_j1, (double)appxy.size()};
+    key.insert(key.end(), appxy.begin(), appxy.end());
+    st = acquire_op(s, key, [&](OpData& d) -> ib_status {
+      Offline w;
+      const int slots = std::min(offline_slots(s, nsd), nsd);
+      ib_status e = offline_alloc(s, w, slots, nsd);
+      if (e) return e;
+      int* ccol = static_cast<int*>(dalloc(s, (size_t)slots * nsd * 4));
+      double* cval = static_cast<double*>(dalloc(s, (size_t)slots * nsd * 8));
+      int* counts = static_cast<int*>(dalloc(s, (size_t)slots * 4));
+      int* gcol = static_cast<int*>(dalloc(s, (size_t)slots * nsd * 4));
+      double* gval = static_cast<double*>(dalloc(s, (size_t)slots * nsd * 8));
+      if (!ccol || !cval || !counts || !gcol || !gval) return IB_ERR_OOM;
+      d.ptr.assign(1, 0);
+      std::vector<int> hcounts(slots);
+      for (int c0 = 0; c0 < nsd; c0 += slots) {
+        if ((e = offline_columns(s, w, rows, c0, nsd, rows, nsd, tlo, thi))) return e;
+        const int ns = std::min(slots, nsd - c0);
+        HIPCHK(launch_filter_compact(w.vals, nsd, c0, nsd, ns, s->cfg.drop_tol, ccol, cval, counts,
+                                     s->stream));
+        HIPCHK(launch_gather_batch(ccol, cval, nsd, counts, ns, gcol, gval, s->stream));
+        HIPCHK(hipMemcpyAsync(hcounts.data(), counts, (size_t)ns * 4, hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        int64_t tot = 0;
+        for (int b = 0; b < ns; ++b) tot += hcounts[b];
+        const size_t old = d.col.size();
+        d.col.resize(old + tot);
+        d.val.resize(old + tot);
+        HIPCHK(hipMemcpy(d.col.data() + old, gcol, (size_t)tot * 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(d.val.data() + old, gval, (size_t)tot * 8, hipMemcpyDeviceToHost));
+        for (int b = 0; b < ns; ++b) d.ptr.push_back(d.ptr.back() + hcounts[b]);
+      }
+      dfree(s, ccol);
+      dfree(s, cval);
+      dfree(s, counts);
+      dfree(s, gcol);
+      dfree(s, gval);
+      offline_free(s, w);
+      return IB_OK;
+    });
+    if (st) return st;
+    const OpData& op = *s->op;
+    if ((int64_t)op.ptr.size() != (int64_t)nsd + 1) {
+      s->last_error = "offline operator has the wrong number of rows";
+      return IB_ERR_ARG;
     }
-    dfree(s, ccol);
-    dfree(s, cval);
-    dfree(s, counts);
-    dfree(s, gcol);
-    dfree(s, gval);
-    offline_free(s, w);
-    s->bp_nnz = (int64_t)hcol.size();
-    int64_t* dptr = static_cast<int64_t*>(dalloc(s, rowptr.size() * 8));
-    int32_t* dcol = static_cast<int32_t*>(dalloc(s, std::max<size_t>(1, hcol.size()) * 4));
-    double* dval = static_cast<double*>(dalloc(s, std::max<size_t>(1, hval.size()) * 8));
+    s->bp_nnz = (int64_t)op.col.size();
+    int64_t* dptr = static_cast<int64_t*>(dalloc(s, op.ptr.size() * 8));
+    int32_t* dcol = static_cast<int32_t*>(dalloc(s, std::max<size_t>(1, op.col.size()) * 4));
+    double* dval = static_cast<double*>(dalloc(s, std::max<size_t>(1, op.val.size()) * 8));
     if (!dptr || !dcol || !dval) return IB_ERR_OOM;
-    HIPCHK(hipMemcpy(dptr, rowptr.data(), rowptr.size() * 8, hipMemcpyHostToDevice));
-    if (!hcol.empty()) {
-      HIPCHK(hipMemcpy(dcol, hcol.data(), hcol.size() * 4, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(dval, hval.data(), hval.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dptr, op.ptr.data(), op.ptr.size() * 8, hipMemcpyHostToDevice));
+    if (!op.col.empty()) {
+      HIPCHK(hipMemcpy(dcol, op.col.data(), op.col.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dval, op.val.data(), op.val.size() * 8, hipMemcpyHostToDevice));
     }
     a.bp_ptr = dptr;
     a.bp_col = dcol;
@@ -1305,6 +1445,7 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   out->refine_iters = s->hrinfo ? (int32_t)s->hrinfo[1] : 0;
   out->refine_residual = s->hrinfo ? s->hrinfo[0] : 0.0;
   out->inverse_rebuilds = s->inverse_rebuilds;
+  out->operator_source = s->op ? s->op_source : -1;
   return IB_OK;
 }
 
@@ -1397,6 +1538,80 @@ ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak
   }
   *resident = (int64_t)r;
   *peak = (int64_t)(r + peak_extra);
+  return IB_OK;
+}
+
+// Serialised operator: "IBOP0001", then int64 counts (key, ptr, col, val) and the arrays.
+ib_status ib_export_operator(ib_solver* s, void* buf, int64_t cap, int64_t* used) {
+  if (check(s) || !used) return IB_ERR_ARG;
+  if (!s->op) return IB_ERR_STATE;
+  const OpData& d = *s->op;
+  const int64_t size = 8 + 4 * 8 + (int64_t)(d.key.size() * 8 + d.ptr.size() * 8 +
+                                             d.col.size() * 4 + d.val.size() * 8);
+  *used = size;
+  if (!buf || cap < size) return IB_ERR_CAPACITY;
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, "IBOP0001", 8);
+  p += 8;
+  const int64_t cnt[4] = {(int64_t)d.key.size(), (int64_t)d.ptr.size(), (int64_t)d.col.size(),
+                          (int64_t)d.val.size()};
+  std::memcpy(p, cnt, sizeof(cnt));
+  p += sizeof(cnt);
+  auto put = [&](const void* src, size_t bytes) {
+    if (bytes) std::memcpy(p, src, bytes);
+    p += bytes;
+  };
+  put(d.key.data(), d.key.size() * 8);
+  put(d.ptr.data(), d.ptr.size() * 8);
+  put(d.col.data(), d.col.size() * 4);
+  put(d.val.data(), d.val.size() * 8);
+  return IB_OK;
+}
+
+ib_status ib_import_operator(ib_solver* s, const void* buf, int64_t size) {
+  if (check(s) || !buf || size < 40) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  const char* p = static_cast<const char*>(buf);
+  if (std::memcmp(p, "IBOP0001", 8) != 0) return IB_ERR_ARG;
+  int64_t cnt[4];
+  std::memcpy(cnt, p + 8, sizeof(cnt));
+  for (int k = 0; k < 4; ++k)
+    if (cnt[k] < 0 || cnt[k] > size) return IB_ERR_ARG;
+  const int64_t need = 40 + cnt[0] * 8 + cnt[1] * 8 + cnt[2] * 4 + cnt[3] * 8;
+  if (need != size) return IB_ERR_ARG;
+  auto d = std::make_shared<OpData>();
+  const char* q = p + 40;
+  d->key.resize(cnt[0]);
+  d->ptr.resize(cnt[1]);
+  d->col.resize(cnt[2]);
+  d->val.resize(cnt[3]);
+  auto get = [&](void* dst, size_t bytes) {
+    if (bytes) std::memcpy(dst, q, bytes);
+    q += bytes;
+  };
+  get(d->key.data(), cnt[0] * 8);
+  get(d->ptr.data(), cnt[1] * 8);
+  get(d->col.data(), cnt[2] * 4);
+  get(d->val.data(), cnt[3] * 8);
+  // CSR consistency: monotone row pointers ending at the entry count
+  if (!d->ptr.empty()) {
+    if (d->ptr.front() != 0 || d->ptr.back() != cnt[2] || cnt[2] != cnt[3]) return IB_ERR_ARG;
+    for (size_t k = 1; k < d->ptr.size(); ++k)
+      if (d->ptr[k] < d->ptr[k - 1]) return IB_ERR_ARG;
+  }
+  s->imported = d;
+  return IB_OK;
+}
+
+ib_status ib_set_operator_cache(int64_t limit_bytes) {
+  if (limit_bytes < 0) return IB_ERR_ARG;
+  OpCache& c = op_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.limit = (size_t)limit_bytes;
+  while (c.bytes > c.limit && !c.lru.empty()) {
+    c.bytes -= c.lru.back()->bytes();
+    c.lru.pop_back();
+  }
   return IB_OK;
 }
 

@@ -109,3 +109,19 @@ def test_estimate_counts_the_subdomain_operator(lib):
     rows = 2 * (int(0.6 / cfg.h) + 3) * (int(0.8 / cfg.h) + 3)
     assert r1.value - r0.value >= rows * 800 * 12
     assert lib.ib_destroy(h) == 0
+
+
+def test_operator_import_validates_its_input(lib):
+    from paper_2103_06415_amd import binding
+    cfg = _config(binding, 64, 1)
+    h = ctypes.c_void_p()
+    assert lib.ib_create(ctypes.byref(cfg), None, None, ctypes.byref(h)) == 0
+    bad = b"NOTANOP!" + bytes(32)
+    assert lib.ib_import_operator(h, bad, len(bad)) == -1
+    good_header = b"IBOP0001" + (1).to_bytes(8, "little") + (0).to_bytes(24, "little") + bytes(8)
+    assert lib.ib_import_operator(h, good_header, len(good_header)) == 0
+    assert lib.ib_import_operator(h, good_header, len(good_header) - 1) == -1
+    used = ctypes.c_int64()
+    assert lib.ib_export_operator(h, None, 0, ctypes.byref(used)) == -2  # nothing built yet
+    assert lib.ib_set_operator_cache(-1) == -1
+    assert lib.ib_destroy(h) == 0

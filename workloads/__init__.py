@@ -82,9 +82,9 @@ class Problem:
     steps: int = 1
 
 
-def cylinder(center, diameter, h):
-    """Points on a circle at angle 2*pi*j/n with spacing close to h."""
-    n = int(round(math.pi * diameter / h))
+def cylinder(center, diameter, h, spacing=1.0):
+    """Points on a circle at angle 2*pi*j/n with spacing close to spacing*h."""
+    n = int(round(math.pi * diameter / (spacing * h)))
     ang = 2.0 * math.pi * np.arange(n) / n
     xy = np.stack([center[0] + 0.5 * diameter * np.cos(ang),
                    center[1] + 0.5 * diameter * np.sin(ang)], axis=1)
@@ -147,12 +147,58 @@ def flag_problem(n=1024, levels=4, seed=3, steps=1000, subdomain=True):
     return Problem("flag", flow, [body], sd, None, steps)
 
 
+def flag_body(hinge, length, h, mass=0.2, ei=1e-3, ea=1e3, a=0.075, spacing=2.0):
+    """Deformable flag clamped at `hinge` along +x with node spacing about spacing*h and an
+    initial deflection w(s) = a (s/L)^2 L, nodes at equal arc length, at rest."""
+    npts = max(3, int(round(length / (spacing * h))) + 1)
+    ds = length / (npts - 1)
+    xy_ref = np.stack([hinge[0] + np.arange(npts) * ds, np.full(npts, float(hinge[1]))], axis=1)
+    k = a / length
+    xs = np.linspace(0.0, 1.2 * length, 240001)
+    seg = np.hypot(np.diff(xs), np.diff(k * xs * xs))
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    sx = np.interp(np.arange(npts) * ds, arc, xs)
+    xy0 = np.stack([hinge[0] + sx, hinge[1] + k * sx * sx], axis=1)
+    rot0 = np.arctan(2.0 * k * sx)
+    return Deformable(xy_ref=xy_ref, mass=mass, ei=ei, ea=ea, xy0=xy0, rot0=rot0)
+
+
+def plate_box(hinge, length, theta0, spread=math.radians(55.0), margin=0.05):
+    """Bounding box of the sector a hinged plate can sweep (theta0 +- spread)."""
+    angs = [theta0 - spread, theta0 + spread]
+    for k in range(-4, 5):
+        a = k * math.pi / 2.0
+        if theta0 - spread < a < theta0 + spread:
+            angs.append(a)
+    xs = [hinge[0]] + [hinge[0] + length * math.cos(a) for a in angs]
+    ys = [hinge[1]] + [hinge[1] + length * math.sin(a) for a in angs]
+    return (min(xs) - margin, max(xs) + margin, min(ys) - margin, max(ys) + margin)
+
+
+def _place(rng, sizes_wanted, h, lim=1.2, boxes=None):
+    """Centres for bodies of the given sizes inside [-lim, lim]^2 without overlap."""
+    boxes = [] if boxes is None else boxes
+    out = []
+    for size in sizes_wanted:
+        for _ in range(400):
+            c = rng.uniform(-lim + size / 2, lim - size / 2, size=2)
+            box = (c[0] - size / 2 - 4 * h, c[0] + size / 2 + 4 * h,
+                   c[1] - size / 2 - 4 * h, c[1] + size / 2 + 4 * h)
+            if all(box[1] < b[0] or b[1] < box[0] or box[3] < b[2] or b[3] < box[2] for b in boxes):
+                boxes.append(box)
+                out.append((float(c[0]), float(c[1])))
+                break
+    return out
+
+
 def batch_problems(count=64, seed=4, steps=200, sizes=(128, 256, 384, 512, 768)):
     """Independent instances: seeded grid size, level count, Re and 1-3 bodies each.
 
     Bodies are rigid circles (D ~ U[0.3, 0.8]) or torsional plates (L ~ U[0.3, 0.8],
     theta0 ~ U[-30, 30] degrees, inertia 5, stiffness 1, damping 0.1) placed without
-    overlap in [-1.2, 1.2]^2 on a finest level of side 4.
+    overlap in [-1.2, 1.2]^2 on a finest level of side 4 (h = 4/n, dt = 0.2 h), Re ~
+    U[50, 400]; body points 2h apart (Sec. 5).  At most one plate per instance, and its sub-domain is the box of the
+    sector it can sweep; instances with only circles use the exact stationary operator.
     """
     out = []
     for i in range(count):
@@ -163,30 +209,77 @@ def batch_problems(count=64, seed=4, steps=200, sizes=(128, 256, 384, 512, 768))
         h = 4.0 / n
         flow = Flow(n=n, levels=levels, h=h, dt=0.2 * h, re=re)
         nb = int(rng.integers(1, 4))
-        bodies, boxes = [], []
-        tries = 0
-        while len(bodies) < nb and tries < 200:
-            tries += 1
-            size = float(rng.uniform(0.3, 0.8))
-            c = rng.uniform(-1.2 + size / 2, 1.2 - size / 2, size=2)
-            box = (c[0] - size / 2 - 4 * h, c[0] + size / 2 + 4 * h,
-                   c[1] - size / 2 - 4 * h, c[1] + size / 2 + 4 * h)
-            if any(not (box[1] < b[0] or b[1] < box[0] or box[3] < b[2] or b[3] < box[2])
-                   for b in boxes):
-                continue
-            boxes.append(box)
-            if rng.uniform() < 0.5:
-                bodies.append(cylinder((float(c[0]), float(c[1])), size, h))
+        kinds = ["plate" if (k == 0 and rng.uniform() < 0.5) else "circle" for k in range(nb)]
+        sizes_ = [float(rng.uniform(0.3, 0.8)) for _ in range(nb)]
+        centres = _place(rng, sizes_, h)
+        bodies, sd = [], None
+        for kind, size, c in zip(kinds, sizes_, centres):
+            if kind == "circle":
+                bodies.append(cylinder(c, size, h, spacing=2.0))
             else:
                 npts = int(round(size / (2.0 * h))) + 1
                 th0 = math.radians(float(rng.uniform(-30.0, 30.0)))
-                hinge = (float(c[0] - 0.5 * size * math.cos(th0)),
-                         float(c[1] - 0.5 * size * math.sin(th0)))
+                hinge = (c[0] - 0.5 * size * math.cos(th0), c[1] - 0.5 * size * math.sin(th0))
                 bodies.append(Torsional(n=npts, hinge=hinge, length=size, theta0=th0,
                                         inertia=5.0, stiffness=1.0, damping=0.1))
-        # sub-domain: bounding box of all bodies' reach, when any body moves
-        sd = None
-        if any(isinstance(b, Torsional) for b in bodies):
-            sd = (-1.3, 1.3, -1.3, 1.3)
+                sd = plate_box(hinge, size, th0)
         out.append(Problem(f"batch{i}", flow, bodies, sd, None, steps))
+    return out
+
+
+# Families of the serving trace: grid, levels, Re, stationary circles (centre, D) and
+# the moving body, whose geometry (and so the offline operator) the requests of a family
+# share; a request varies the moving body's parameters, the initial noise and the steps.
+SERVE_FAMILIES = (
+    dict(n=256, levels=1, re=100.0, circles=[((0.0, 0.0), 0.8)], moving=None, weight=3),
+    dict(n=384, levels=2, re=200.0, circles=[((0.6, 0.5), 0.4)],
+         moving=("plate", (-0.6, 0.0), 0.6, -0.35), weight=3),
+    dict(n=512, levels=3, re=300.0, circles=[], moving=("flag", (-0.4, 0.0), 0.6), weight=2),
+    dict(n=768, levels=2, re=150.0, circles=[((0.7, 0.7), 0.4), ((0.7, -0.7), 0.4)],
+         moving=("plate", (-0.8, 0.0), 0.6, 0.0), weight=2),
+    dict(n=1024, levels=4, re=500.0, circles=[], moving=("flag", (-0.3, 0.0), 0.6), weight=1),
+    dict(n=512, levels=1, re=250.0, circles=[((-0.5, 0.3), 0.5), ((0.5, -0.3), 0.5)],
+         moving=None, weight=2),
+)
+
+
+def serve_request(family, rng, steps, noise=1e-3):
+    """One request of a family (see SERVE_FAMILIES)."""
+    n, levels = family["n"], family["levels"]
+    h = 4.0 / n
+    flow = Flow(n=n, levels=levels, h=h, dt=0.2 * h, re=family["re"])
+    bodies = [cylinder(c, d, h, spacing=2.0) for c, d in family["circles"]]
+    sd = None
+    mv = family["moving"]
+    if mv is not None and mv[0] == "plate":
+        _, hinge, length, th0c = mv
+        npts = int(round(length / (2.0 * h))) + 1
+        th0 = th0c + math.radians(float(rng.uniform(-10.0, 10.0)))
+        bodies.append(Torsional(n=npts, hinge=hinge, length=length, theta0=th0,
+                                inertia=float(rng.uniform(2.0, 8.0)),
+                                stiffness=float(rng.uniform(0.5, 2.0)), damping=0.1))
+        sd = plate_box(hinge, length, th0c, spread=math.radians(65.0))
+    elif mv is not None:
+        _, hinge, length = mv
+        bodies.append(flag_body(hinge, length, h, mass=float(rng.uniform(0.1, 0.4)),
+                                ei=float(rng.uniform(5e-4, 2e-3)),
+                                a=float(rng.uniform(0.05, 0.1)) * length))
+        sd = (hinge[0] - 0.02, hinge[0] + length + 0.02, hinge[1] - 0.6 * length,
+              hinge[1] + 0.6 * length)
+    w0 = [rng.normal(0.0, noise, size=(n - 1, n - 1))] + [None] * (levels - 1)
+    return Problem("serve", flow, bodies, sd, w0, steps)
+
+
+def serve_trace(count=48, rate=40.0, seed=5, steps=(200, 2000), families=SERVE_FAMILIES):
+    """Poisson arrivals (mean rate per second) of requests drawn from the families by
+    weight, steps ~ U{steps[0] .. steps[1]}: a list of (arrival seconds, Problem)."""
+    rng = np.random.default_rng(seed)
+    w = np.array([f["weight"] for f in families], dtype=float)
+    w /= w.sum()
+    t, out = 0.0, []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        fam = families[int(rng.choice(len(families), p=w))]
+        st = int(rng.integers(steps[0], steps[1] + 1))
+        out.append((t, serve_request(fam, rng, st)))
     return out
