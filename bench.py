@@ -113,6 +113,53 @@ def serve(problems, max_active=8, budget=200 << 30, precision=None):
             "operators_built": sources.count(0), "operators_from_cache": sources.count(1)}
 
 
+def exact_compare(n=512, levels=3, steps=200):
+    """Sub-domain operator against the exact one rebuilt at every FSI iterate (the paper's
+    "true E"), on the torsional plate: time per step and the difference in the hinge
+    angle and the force on the plate over the run."""
+    import numpy as np
+    import workloads as W
+    from paper_2103_06415_amd import binding
+    out = {}
+    hist = {}
+    for mode, sd in (("subdomain", True), ("exact", False)):
+        p = W.plate_problem(n=n, levels=levels, steps=steps, subdomain=sd)
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        s.sync()
+        th, fy = [], []
+        for _ in range(steps):
+            s.step(1)
+            th.append(s.deflection(0)[0])
+            f = s.stresses(0)
+            fy.append(float(f[f.size // 2:].sum() * p.bodies[0].ds))
+        # timing pass without host reads
+        t0 = time.perf_counter()
+        s.step(20)
+        s.sync()
+        out[f"ms_per_step_{mode}"] = 1e3 * (time.perf_counter() - t0) / 20
+        hist[mode] = (np.array(th), np.array(fy))
+        s.close()
+    th_sd, fy_sd = hist["subdomain"]
+    th_ex, fy_ex = hist["exact"]
+    out["speedup_subdomain_over_exact"] = out["ms_per_step_exact"] / out["ms_per_step_subdomain"]
+    # after the impulsive start's transient (first quarter of the run): largest
+    # difference relative to the largest value, and the difference of the means
+    k0 = steps // 4
+    out["theta_rel_diff"] = float(np.max(np.abs(th_sd[k0:] - th_ex[k0:])) /
+                                  max(np.max(np.abs(th_ex[k0:])), 1e-30))
+    out["lift_rel_diff"] = float(np.max(np.abs(fy_sd[k0:] - fy_ex[k0:])) /
+                                 max(np.max(np.abs(fy_ex[k0:])), 1e-30))
+    out["mean_lift_rel_diff"] = float(abs(fy_sd[k0:].mean() - fy_ex[k0:].mean()) /
+                                      max(abs(fy_ex[k0:].mean()), 1e-30))
+    out["lift_rel_diff_incl_start"] = float(np.max(np.abs(fy_sd - fy_ex)) /
+                                            max(np.max(np.abs(fy_ex)), 1e-30))
+    out["workload"] = (f"torsional plate, {n}^2 x {levels} levels, {steps} steps from an "
+                       "impulsive start, FP32 flow; exact mode rebuilds E C K C^T E^T by "
+                       "point-source solves at every FSI iterate")
+    return out
+
+
 def cpu_baseline(n, levels, seconds=20.0):
     """The FP64 oracle on the host: flow steps of the same grid (no body coupling)."""
     import numpy as np
@@ -151,6 +198,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving trace (48 Poisson arrivals at 40/s, 256^2..1024^2)")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the sub-domain vs exact-operator comparison (plate, 512^2 x 3)")
     ap.add_argument("--batch", action="store_true",
                     help="also run the 64-instance batch (sizes 128^2..768^2, 200 steps each)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
@@ -227,6 +276,8 @@ def main():
         out["served"]["workload"] = ("48 requests, Poisson arrivals 40/s, 6 families of "
                                      "256^2x1 .. 1024^2x4 grids with 1-3 rigid/torsional/"
                                      "deformable bodies, 200-2000 steps, FP32 flow")
+    if not args.no_exact:
+        out["subdomain_vs_exact"] = exact_compare()
     if args.batch:
         out["batched"] = serve([(0.0, p) for p in W.batch_problems()], max_active=16)
         out["batched"]["workload"] = "64 instances, 128^2..768^2 x 1-3 levels, 200 steps"

@@ -226,56 +226,65 @@ constexpr int SCHUR_CPT = 8;  // columns per thread: nf <= 2048
 __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a) {
   extern __shared__ double ssm[];
   const int nf = a.nf, ns = 4 * nf, r = blockIdx.x, tid = threadIdx.x;
-  double* acc = ssm;
-  double* pw = acc + ns;
-  int* cid = reinterpret_cast<int*>(pw + ns);
-  int* pidx = cid + ns;
-  for (int e = tid; e < ns; e += SCHUR_NT) {
-    pw[e] = a.p_w[e];
-    cid[e] = a.canon[e];
-    pidx[e] = a.p_idx[e];
-  }
-  __syncthreads();
   double m[SCHUR_CPT];
-#pragma unroll
-  for (int k = 0; k < SCHUR_CPT; ++k) m[k] = 0.0;
-  for (int u = 0; u < 4; ++u) {
-    const double wu = pw[4 * r + u];
-    if (wu == 0.0) continue;  // uniform over the workgroup
-    const int cu = pidx[4 * r + u];
-    for (int e = tid; e < ns; e += SCHUR_NT) acc[e] = 0.0;
-    __syncthreads();
-    const int64_t lo = a.bp_ptr[cu], hi = a.bp_ptr[cu + 1];
-    constexpr int Q = 4;
-    for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)Q * SCHUR_NT) {
-      int j[Q], id[Q];
-      double v[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int64_t e = e0 + tid + (int64_t)q * SCHUR_NT;
-        j[q] = e < hi ? a.bp_col[e] : -1;
-        v[q] = e < hi ? a.bp_val[e] : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) id[q] = j[q] >= 0 ? a.act[j[q]] : -1;
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-        if (id[q] >= 0 && id[q] < ns && pw[id[q]] != 0.0 && pidx[id[q]] == j[q]) acc[id[q]] = v[q];
-    }
-    __syncthreads();
+  if (a.gx != nullptr) {
+    // exact operator of this iterate (moving bodies without a sub-domain)
 #pragma unroll
     for (int k = 0; k < SCHUR_CPT; ++k) {
       const int c = tid + k * SCHUR_NT;
-      if (c < nf) {
-        double inner = 0.0;
-        for (int v = 0; v < 4; ++v) {
-          const double wv = pw[4 * c + v];
-          if (wv != 0.0) inner += wv * acc[cid[4 * c + v]];
-        }
-        m[k] += wu * inner;
-      }
+      m[k] = c < nf ? a.gx[(size_t)r * a.pm + c] : 0.0;
+    }
+  } else {
+    double* acc = ssm;
+    double* pw = acc + ns;
+    int* cid = reinterpret_cast<int*>(pw + ns);
+    int* pidx = cid + ns;
+    for (int e = tid; e < ns; e += SCHUR_NT) {
+      pw[e] = a.p_w[e];
+      cid[e] = a.canon[e];
+      pidx[e] = a.p_idx[e];
     }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCHUR_CPT; ++k) m[k] = 0.0;
+    for (int u = 0; u < 4; ++u) {
+      const double wu = pw[4 * r + u];
+      if (wu == 0.0) continue;  // uniform over the workgroup
+      const int cu = pidx[4 * r + u];
+      for (int e = tid; e < ns; e += SCHUR_NT) acc[e] = 0.0;
+      __syncthreads();
+      const int64_t lo = a.bp_ptr[cu], hi = a.bp_ptr[cu + 1];
+      constexpr int Q = 4;
+      for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)Q * SCHUR_NT) {
+        int j[Q], id[Q];
+        double v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int64_t e = e0 + tid + (int64_t)q * SCHUR_NT;
+          j[q] = e < hi ? a.bp_col[e] : -1;
+          v[q] = e < hi ? a.bp_val[e] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) id[q] = j[q] >= 0 ? a.act[j[q]] : -1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          if (id[q] >= 0 && id[q] < ns && pw[id[q]] != 0.0 && pidx[id[q]] == j[q]) acc[id[q]] = v[q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < SCHUR_CPT; ++k) {
+        const int c = tid + k * SCHUR_NT;
+        if (c < nf) {
+          double inner = 0.0;
+          for (int v = 0; v < 4; ++v) {
+            const double wv = pw[4 * c + v];
+            if (wv != 0.0) inner += wv * acc[cid[4 * c + v]];
+          }
+          m[k] += wu * inner;
+        }
+      }
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int k = 0; k < SCHUR_CPT; ++k) {
@@ -1241,8 +1250,24 @@ hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_body_ops<T>), dim3((a.npts + 63) / 64), dim3(64), 0, st, a);
   return hipGetLastError();
 }
+__global__ void k_cols_to_matrix(const double* vals, int nf, int ns, int c0, double* G, int pm) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nf * ns) return;
+  const int t = e % nf, b = e / nf;
+  G[(size_t)t * pm + c0 + b] = vals[(size_t)b * nf + t];
+}
+
+hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, double* G, int pm,
+                                 hipStream_t st) {
+  const int tot = nf * ns;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cols_to_matrix, dim3((tot + 255) / 256), dim3(256), 0, st, vals, nf, ns,
+                     c0, G, pm);
+  return hipGetLastError();
+}
+
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)a.nf * SCHUR_LDS_PER_ROW;
+  const size_t lds = a.gx != nullptr ? 8 : (size_t)a.nf * SCHUR_LDS_PER_ROW;
   if (lds > SCHUR_LDS_MAX || a.nf > SCHUR_CPT * SCHUR_NT) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_schur_sd, dim3(a.nf), dim3(SCHUR_NT), lds, st, a);
   return hipGetLastError();

@@ -50,6 +50,7 @@ struct FsiArgs {
   double* st_w;
   int* p_idx;
   double* p_w;
+  const double* gx;    // exact mode with moving bodies: E C K C^T E^T of this iterate (pitch pm)
   int* act;            // per B' row: a slot e (= 4 row + corner) of P that uses it
   int* canon;          // per slot of P: the slot act[] names for its B' row (-1 if weight 0)
   double* pos;         // current point positions (2 per point)
@@ -94,6 +95,9 @@ hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st);
 constexpr size_t SCHUR_LDS_PER_ROW = 4 * (8 + 8 + 4 + 4);
 constexpr size_t SCHUR_LDS_MAX = 150 * 1024;
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st);
+// G[t][c0 + b] = vals[b][t] for the ns point-source columns of one offline batch
+hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, double* G, int pm,
+                                 hipStream_t st);
 hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st);
 hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,
                            hipStream_t st);

@@ -130,6 +130,15 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 }  // namespace
 
+struct Offline {
+  int nslots = 0;
+  double* srcrows = nullptr;  // [nslots][6][pitch]
+  int* rfirst = nullptr;
+  double* X = nullptr;        // [nslots][(n-1) pitch]
+  double* S = nullptr;        // [nslots][(n+1) pitch]
+  double* vals = nullptr;     // [nslots][ntarget]
+};
+
 struct ib_solver {
   ib_config cfg{};
   ib_allocator alloc{};
@@ -169,6 +178,12 @@ struct ib_solver {
   int sd_i0 = 0, sd_i1 = 0, sd_j0 = 0, sd_j1 = 0, sd_npx = 0, sd_npy = 0, sd_ngrid = 0,
       sd_total = 0;
   int64_t bp_nnz = 0;
+  // exact operator for moving bodies: G = E C (C^T A C)^{-1} C^T E^T rebuilt at every FSI
+  // iterate from point-source columns (no sub-domain)
+  bool exact_moving = false;
+  Offline xo;
+  OffRows xrows{};
+  double* gx = nullptr;
   std::shared_ptr<const OpData> op;        // offline operator in use (built, cached or imported)
   std::shared_ptr<const OpData> imported;  // from ib_import_operator, checked at prepare
   int op_source = 0;                       // 0 built, 1 from the cache, 2 imported
@@ -333,14 +348,6 @@ ib_status init_streamfunction(ib_solver* s) {
 
 // Batched columns of E C K C^T E^T (K = [L (I + alpha L)]^{-1}) for the rows of
 // `src` sampled at the rows of `dst`: vals[b * ntarget + t] for b < nslots.
-struct Offline {
-  int nslots = 0;
-  double* srcrows = nullptr;  // [nslots][6][pitch]
-  int* rfirst = nullptr;
-  double* X = nullptr;        // [nslots][(n-1) pitch]
-  double* S = nullptr;        // [nslots][(n+1) pitch]
-  double* vals = nullptr;     // [nslots][ntarget]
-};
 
 ib_status offline_columns(ib_solver* s, Offline& w, const OffRows& src, int col0, int ncols,
                           const OffRows& dst, int ntarget, int tlo, int thi) {
@@ -599,10 +606,7 @@ ib_status prepare_bodies(ib_solver* s) {
     return IB_ERR_STATE;
   }
   s->stationary = !s->use_sd && !any_moving;
-  if (!s->use_sd && any_moving) {
-    s->last_error = "moving bodies need the sub-domain operator (set a sub-domain)";
-    return IB_ERR_ARG;
-  }
+  s->exact_moving = !s->use_sd && any_moving;
   for (auto& hb : s->bodies)
     if (hb.kind == BODY_DEFORMABLE && 3 * hb.m - 3 > 600) {
       s->last_error = "deformable body with more than 201 nodes";
@@ -643,6 +647,11 @@ ib_status prepare_bodies(ib_solver* s) {
     s->bihi = std::min(n - 1, (int)std::ceil((xmax - x0) / h) + 4);
     s->blo = std::max(1, (int)std::floor((ymin - y0) / h) - 4);
     s->bhi = std::min(n - 1, (int)std::ceil((ymax - y0) / h) + 4);
+    if (s->exact_moving) {
+      // moving bodies without a sub-domain may go anywhere on level 0
+      s->bilo = s->blo = 1;
+      s->bihi = s->bhi = n - 1;
+    }
   }
   // ---- device arrays
   auto up = [&](const std::vector<double>& v) -> double* {
@@ -757,6 +766,18 @@ ib_status prepare_bodies(ib_solver* s) {
   geo.h = h;
   geo.x0 = x0;
   geo.y0 = y0;
+  if (s->exact_moving) {
+    // buffers for rebuilding the exact flow block at every FSI iterate
+    s->xrows = geo;
+    s->xrows.kind = 0;
+    s->xrows.st_base = a.st_base;
+    s->xrows.st_w = a.st_w;
+    const int slots = std::min(offline_slots(s, nf), nf);
+    if ((st = offline_alloc(s, s->xo, slots, nf))) return st;
+    s->gx = static_cast<double*>(dalloc(s, (size_t)nf * a.pm * 8));
+    if (!s->gx) return IB_ERR_OOM;
+    a.gx = s->gx;
+  }
   if (s->stationary) {
     OffRows rows = geo;
     rows.kind = 0;
@@ -941,6 +962,16 @@ ib_status fsi_and_correct(ib_solver* s) {
       for (size_t bi = 0; bi < s->bodies.size(); ++bi)
         if (s->bodies[bi].kind == BODY_DEFORMABLE)
           HIPCHK(launch_band_columns(a, (int)bi, s->bodies[bi].m, s->stream));
+      if (s->exact_moving) {
+        // the exact flow block at this iterate: one point-source solve per body row
+        const int nfr = s->nf;
+        for (int c0 = 0; c0 < nfr; c0 += s->xo.nslots) {
+          ib_status e = offline_columns(s, s->xo, s->xrows, c0, nfr, s->xrows, nfr, 1, n - 1);
+          if (e) return e;
+          HIPCHK(launch_cols_to_matrix(s->xo.vals, nfr, std::min(s->xo.nslots, nfr - c0), c0,
+                                       s->gx, a.pm, s->stream));
+        }
+      }
       HIPCHK(launch_schur_sd(a, s->stream));
       const int nf = s->nf;
       const size_t mb = (size_t)nf * a.pm * 8;

@@ -203,3 +203,27 @@ def test_plate_converged_mode(torch_cuda, gpu_lib):
     gpu.close()
     assert it == ora.last_iters
     assert e < fp64_tol(32, 3)
+
+
+@pytest.mark.parametrize("which", ["plate", "flag"])
+def test_exact_operator_for_moving_bodies(torch_cuda, gpu_lib, which):
+    """No sub-domain: the exact E C (C^T A C)^{-1} C^T E^T is rebuilt at every FSI iterate
+    (the paper's "true E" reference method), against the oracle doing the same."""
+    print(f"exact moving {which}", flush=True)
+    make = W.plate_problem if which == "plate" else W.flag_problem
+    p = make(n=32, levels=2, steps=3, subdomain=False)
+    steps, iters = 3, 3
+    gpu = _run(p, steps, "fp64", fixed_iters=iters)
+    ora = Oracle(p, fixed_iters=iters)
+    for _ in range(steps):
+        ora.step()
+    errs = [rel(gpu.vorticity(g), ora.vorticity(g)) for g in range(2)]
+    ef = rel(gpu.stresses(0), ora.f)
+    d = gpu.deflection(0)
+    b = ora.bodies[0][1]
+    ed = abs(d[0] - b.theta) if which == "plate" else float(np.max(np.abs(d - b.chi)))
+    print(f"  vorticity {errs}; stresses {ef:.3e}; deflection {ed:.3e}", flush=True)
+    gpu.close()
+    assert max(errs) < fp64_tol(32, steps)
+    assert ef < 1e-9
+    assert ed < 1e-10
