@@ -1285,7 +1285,7 @@ hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, in
   hipLaunchKernelGGL(k_matvec, dim3(n), dim3(256), 0, st, A, pa, x, y, n);
   return hipGetLastError();
 }
-hipError_t launch_band_columns(const FsiArgs& a, int bi, int m, hipStream_t st) {
+hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
   const int ncol = 2 * m + 1;
   // BEAM_NC right-hand sides per workgroup; every workgroup repeats the factorisation,
   // which costs no extra latency and spreads the solves over more CUs

@@ -15,7 +15,6 @@ struct BodyDev {
   int app0;   // sub-domain mode: first appended sub-domain point of a rigid body
   int tors;   // index into the torsional state array
   int dof0;   // deformable: offset of node 0's DOFs in the DOF arrays (3 per node)
-  int band0;  // deformable: offset of its band matrix / workspace
   int has_ub; // rigid: prescribed velocity present
   int64_t yoff; // deformable: offset of its J_d^{-1} T^T workspace
   double ds;
@@ -70,8 +69,6 @@ struct FsiArgs {
   const double* dmass; // lumped mass per DOF
   const double* l0;    // per element (indexed like DOFs / 3)
   const double* beta0;
-  double* band;        // band LU factors, 11 per DOF
-  double* dres;        // residual per DOF
   double* ywork;       // J_d^{-1} T^T, per deformable body: (3m) x (2m)
   int* flags;          // [0] error code, [1] refinement failure
   const double* rmore; // non-zero: the stress solve needs more sweeps, k_update waits
@@ -103,7 +100,7 @@ hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs
                            hipStream_t st);
 hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st);
 hipError_t launch_update(const FsiArgs& a, hipStream_t st);
-hipError_t launch_band_columns(const FsiArgs& a, int bi, int m, hipStream_t st);
+hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st);
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st);
 template <typename T>
 hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,

@@ -68,7 +68,7 @@ OpCache& op_cache() {
 }
 
 // Find key; if another thread is building it, wait.  Returns null when absent (and then
-// registers the caller as its builder, who must call op_cache_put or op_cache_abandon).
+// registers the caller as its builder, who must then call op_cache_done).
 OpPtr op_cache_get(const std::vector<double>& key) {
   OpCache& c = op_cache();
   std::unique_lock<std::mutex> lk(c.mu);
@@ -519,7 +519,7 @@ ib_status prepare_bodies(ib_solver* s) {
   // ---- host-side layout
   std::vector<BodyDev> bd;
   std::vector<double> rigid_xy, rigid_ub, tors, chi, dmass, l0v, beta0v, appxy;
-  int pt = 0, app = 0, ntors = 0, dof = 0, band0 = 0;
+  int pt = 0, app = 0, ntors = 0, dof = 0;
   int64_t yoff = 0;
   bool any_moving = false;
   s->ds_rows.clear();
@@ -558,7 +558,6 @@ ib_status prepare_bodies(ib_solver* s) {
     } else {
       any_moving = true;
       b.dof0 = dof;
-      b.band0 = band0;
       b.yoff = yoff;
       yoff += (int64_t)3 * hb.m * (2 * hb.m + 1);
       b.mass = hb.mass;
@@ -588,7 +587,6 @@ ib_status prepare_bodies(ib_solver* s) {
         }
       }
       dof += 3 * m;
-      band0 += 3 * m;
     }
     bd.push_back(b);
     pt += hb.m;
@@ -730,8 +728,6 @@ ib_status prepare_bodies(ib_solver* s) {
   a.dmass = up(dmass);
   a.l0 = up(l0v);
   a.beta0 = up(beta0v);
-  a.band = static_cast<double*>(dalloc(s, std::max<size_t>(1, (size_t)band0 * 11) * 8));
-  a.dres = up(std::vector<double>(chi.size(), 0.0));
   size_t yw = 0;
   for (auto& hb : s->bodies) if (hb.kind == BODY_DEFORMABLE) yw += (size_t)3 * hb.m * (2 * hb.m + 1);
   a.ywork = static_cast<double*>(dalloc(s, std::max<size_t>(1, yw) * 8));
@@ -961,7 +957,7 @@ ib_status fsi_and_correct(ib_solver* s) {
       HIPCHK(launch_structure(a, 1, s->stream));
       for (size_t bi = 0; bi < s->bodies.size(); ++bi)
         if (s->bodies[bi].kind == BODY_DEFORMABLE)
-          HIPCHK(launch_band_columns(a, (int)bi, s->bodies[bi].m, s->stream));
+          HIPCHK(launch_beam(a, (int)bi, s->bodies[bi].m, s->stream));
       if (s->exact_moving) {
         // the exact flow block at this iterate: one point-source solve per body row
         const int nfr = s->nf;
