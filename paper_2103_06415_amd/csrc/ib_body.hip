@@ -1177,39 +1177,40 @@ __global__ void k_ref_final(double* ws, int maxit, int* flags, double* out, int 
   if (!(!done && partial) && !(ws[0] < 1e-9)) atomicMax(&flags[1], 1);  // the inverse is stale
 }
 
-// C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B.  32 x 32 tiles.
+// C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B, on the FP64 matrix
+// cores: each wave owns a 16 x 16 tile of C (v_mfma_f64_16x16x4f64; A fragment: lane l
+// holds A[i0 + l % 16][k + l / 16], B fragment B[k + l / 16][j0 + l % 16], result item v
+// of lane l is C[i0 + l / 16 + 4 v][j0 + l % 16]); 2 x 2 waves per 32 x 32 workgroup
+// tile; the k loop loads 16 fragments ahead.
+typedef double v4d __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
                                                 int p, int two_minus) {
-  __shared__ double ta[32][33], tb[32][33];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  for (int k0 = 0; k0 < n; k0 += 32) {
-    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-      const int rr = e / 32, cc = e % 32;
-      ta[rr][cc] = (r0 + rr < n && k0 + cc < n) ? A[(size_t)(r0 + rr) * p + k0 + cc] : 0.0;
-      tb[rr][cc] = (k0 + rr < n && c0 + cc < n) ? B[(size_t)(k0 + rr) * p + c0 + cc] : 0.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * 32 + (w >> 1) * 16, j0 = blockIdx.x * 32 + (w & 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ai = i0 + li, bj = j0 + li;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int KC = 16;  // k steps of 4 per chunk
+  for (int k0 = 0; k0 < n; k0 += 4 * KC) {
+    double av[KC], bv[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const int k = k0 + 4 * c + lk;
+      av[c] = (ai < n && k < n) ? A[(size_t)ai * p + k] : 0.0;
+      bv[c] = (bj < n && k < n) ? B[(size_t)k * p + bj] : 0.0;
     }
-    __syncthreads();
-    for (int kk = 0; kk < 32; ++kk) {
-      const double a0 = ta[ty * 2][kk], a1 = ta[ty * 2 + 1][kk];
-      const double b0 = tb[kk][tx * 2], b1 = tb[kk][tx * 2 + 1];
-      acc[0][0] += a0 * b0;
-      acc[0][1] += a0 * b1;
-      acc[1][0] += a1 * b0;
-      acc[1][1] += a1 * b1;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c], bv[c], acc, 0, 0, 0);
   }
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v) {
-      const int r = r0 + ty * 2 + u, c = c0 + tx * 2 + v;
-      if (r < n && c < n) {
-        double val = acc[u][v];
-        if (two_minus) val = (r == c ? 2.0 : 0.0) - val;
-        C[(size_t)r * p + c] = val;
-      }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + lk + 4 * v, j = j0 + li;
+    if (i < n && j < n) {
+      double val = acc[v];
+      if (two_minus) val = (i == j ? 2.0 : 0.0) - val;
+      C[(size_t)i * p + j] = val;
     }
+  }
 }
 
 __global__ void k_identity(double* X, int p, int n) {

@@ -197,11 +197,16 @@ def test_plate_converged_mode(torch_cuda, gpu_lib):
     ora = Oracle(p, newton_tol=1e-9)
     for _ in range(3):
         ora.step()
-    it = gpu.stats()["newton_iters"]
+    st = gpu.stats()
+    it = st["newton_iters"]
     e = rel(gpu.vorticity(0), ora.vorticity(0))
-    print(f"  iterations {it} vs {ora.last_iters}; vorticity {e:.3e}", flush=True)
+    print(f"  iterations {it} vs {ora.last_iters}; vorticity {e:.3e}; inverse rebuilds "
+          f"{st['inverse_rebuilds']}; refinement sweeps {st['refine_iters']}", flush=True)
     gpu.close()
     assert it == ora.last_iters
+    # the Newton-Schulz refresh keeps the approximate inverse contracting: only the first
+    # inverse is built by LU
+    assert st["inverse_rebuilds"] == 1
     assert e < fp64_tol(32, 3)
 
 
