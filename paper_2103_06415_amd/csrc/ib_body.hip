@@ -1213,6 +1213,32 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B
   }
 }
 
+// out (bits of a non-negative double, atomicMax) = max |W_ij - delta_ij| over n x n.
+__global__ __launch_bounds__(256) void k_eye_resid(const double* W, int p, int n, double* out) {
+  double m = 0.0;
+  bool bad = false;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < (size_t)n * n;
+       e += (size_t)gridDim.x * 256) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const double d = fabs(W[(size_t)i * p + j] - (i == j ? 1.0 : 0.0));
+    if (!(d == d)) bad = true;
+    else m = fmax(m, d);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  const bool anybad = __any(bad);
+  if ((threadIdx.x & 63) == 0) {
+    const double v = anybad ? INFINITY : m;
+    atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+hipError_t launch_eye_resid(const double* W, int p, int n, double* out, hipStream_t st) {
+  const size_t tot = (size_t)n * n;
+  const int nb = (int)std::min<size_t>(1024, (tot + 255) / 256);
+  hipLaunchKernelGGL(k_eye_resid, dim3(nb), dim3(256), 0, st, W, p, n, out);
+  return hipGetLastError();
+}
+
 __global__ void k_identity(double* X, int p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) X[(size_t)i * p + i] = 1.0;
@@ -1350,12 +1376,6 @@ __global__ void k_gather_batch(const int* cols, const double* vals, int ntarget,
 }
 
 // M[:, c] *= s * colscale[c]
-__global__ void k_scale_cols(double* M, int pm, int n, const double* colscale, double s) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n) return;
-  const int r = e / n, c = e % n;
-  M[(size_t)r * pm + c] *= s * colscale[c];
-}
 
 // Initial acceleration of the deformable bodies at rest: zetadot = -R(chi) / m.
 __global__ __launch_bounds__(STRUCT_NT) void k_beam_init(FsiArgs a) {
@@ -1389,11 +1409,6 @@ hipError_t launch_gather_batch(const int* cols, const double* vals, int ntarget,
                                int nslots, int* out_col, double* out_val, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_batch, dim3(nslots), dim3(256), 0, st, cols, vals, ntarget, counts,
                      out_col, out_val);
-  return hipGetLastError();
-}
-hipError_t launch_scale_cols(double* M, int pm, int n, const double* colscale, double s,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_cols, dim3((n * n + 255) / 256), dim3(256), 0, st, M, pm, n, colscale, s);
   return hipGetLastError();
 }
 hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st) {

@@ -115,8 +115,6 @@ hipError_t launch_filter_compact(const double* vals, int ntarget, int col0, int 
                                  hipStream_t st);
 hipError_t launch_gather_batch(const int* cols, const double* vals, int ntarget, const int* counts,
                                int nslots, int* out_col, double* out_val, hipStream_t st);
-hipError_t launch_scale_cols(double* M, int pm, int n, const double* colscale, double s,
-                             hipStream_t st);
 hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
 // f = M^{-1} b by refinement with the approximate inverse X, starting from X b or, with
 // guess != 0, from the f passed in; ws holds refine_ws_doubles(n, maxit) doubles;
@@ -128,6 +126,8 @@ hipError_t launch_solve_refine(const double* M, int pm, const double* X, const d
                                int* flags, hipStream_t st);
 size_t refine_ws_doubles(int n, int maxit);
 hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
+// *out (zeroed by the caller) folds in max |W - I| over the n x n matrix (+Inf if not finite)
+hipError_t launch_eye_resid(const double* W, int p, int n, double* out, hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
                          hipStream_t st);
 

@@ -481,6 +481,74 @@ ib_status map_flags(ib_solver* s, int code) {
 }
 
 // Device body data, the stationary Schur inverse or B' (Algorithm 1).
+// Dense inverse X of the n x n matrix M (device, pitch pm) by Newton-Schulz iterations
+// X <- X (2I - M X) on the FP64 matrix cores, from X0 = M^T / (|M|_1 |M|_inf) (which
+// makes the iteration converge for any nonsingular M); mh is M on the host (for the
+// norms and X0).  Stops when max |M X - I| < 1e-13, or fails (returns false) after 100
+// iterations or on a non-finite or diverging residual.
+bool newton_schulz_inverse(ib_solver* s, const double* M, double* X, int n, int pm,
+                           const std::vector<double>& mh, ib_status* err) {
+  *err = IB_OK;
+  double n1 = 0.0, ninf = 0.0;
+  std::vector<double> col(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double v = std::fabs(mh[(size_t)i * pm + j]);
+      r += v;
+      col[j] += v;
+    }
+    ninf = std::max(ninf, r);
+  }
+  for (int j = 0; j < n; ++j) n1 = std::max(n1, col[j]);
+  if (!(n1 > 0.0) || !(ninf > 0.0)) return false;
+  const double alpha = 1.0 / (n1 * ninf);
+  std::vector<double> x0((size_t)n * pm, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) x0[(size_t)i * pm + j] = alpha * mh[(size_t)j * pm + i];
+  double* W = static_cast<double*>(dalloc(s, (size_t)n * pm * 8));
+  double* Y = static_cast<double*>(dalloc(s, (size_t)n * pm * 8));
+  double* r = static_cast<double*>(dalloc(s, 8));
+  if (!W || !Y || !r) {
+    *err = IB_ERR_OOM;
+    return false;
+  }
+  auto fail = [&](hipError_t e) {
+    *err = hip_fail(s, e, "Newton-Schulz inverse");
+    return false;
+  };
+  hipError_t e = hipMemcpy(X, x0.data(), x0.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(e);
+  double* cur = X;
+  double* nxt = Y;
+  double prev = 1e300, res = 1e300;
+  bool ok = false;
+  for (int it = 0; it < 100; ++it) {
+    if ((e = launch_gemm64(M, cur, W, n, pm, 1, s->stream)) != hipSuccess) return fail(e);
+    if ((e = hipMemsetAsync(r, 0, 8, s->stream)) != hipSuccess) return fail(e);
+    if ((e = launch_eye_resid(W, pm, n, r, s->stream)) != hipSuccess) return fail(e);  // W - I = I - M X
+    if ((e = hipMemcpyAsync(&res, r, 8, hipMemcpyDeviceToHost, s->stream)) != hipSuccess) return fail(e);
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(e);
+    if (!std::isfinite(res) || (it > 40 && res > prev)) break;
+    if (res < 1e-13) {
+      ok = true;
+      break;
+    }
+    prev = res;
+    if ((e = launch_gemm64(cur, W, nxt, n, pm, 0, s->stream)) != hipSuccess) return fail(e);
+    std::swap(cur, nxt);
+  }
+  if (ok && cur != X) {
+    e = hipMemcpyAsync(X, cur, (size_t)n * pm * 8, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return fail(e);
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(e);
+  }
+  dfree(s, W);
+  dfree(s, Y);
+  dfree(s, r);
+  return ok;
+}
+
 // The offline operator for `key`: the imported one (which must match), a cached one, or
 // a new one from `build`, which then enters the cache.
 template <typename F>
@@ -755,7 +823,6 @@ ib_status prepare_bodies(ib_solver* s) {
   HIPCHK(hipStreamSynchronize(s->stream));
   HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
   if ((st = map_flags(s, s->hflags[0]))) return st;
-  double* dsr = up(s->ds_rows);
   // ---- offline operator
   OffRows geo{};
   geo.n = n;
@@ -806,16 +873,22 @@ ib_status prepare_bodies(ib_solver* s) {
           for (int t = 0; t < nf; ++t) gm[(size_t)t * a.pm + c0 + b] = hv[(size_t)b * nf + t];
       }
       offline_free(s, w);
+      // M = (dt / h^2) G diag(ds), on the host too (for the inverse's starting point)
+      const double sc = s->cfg.dt / (h * h);
+      for (int i = 0; i < nf; ++i)
+        for (int j = 0; j < nf; ++j) gm[(size_t)i * a.pm + j] *= sc * s->ds_rows[j];
       HIPCHK(hipMemcpy(G, gm.data(), gm.size() * 8, hipMemcpyHostToDevice));
-      HIPCHK(launch_scale_cols(G, a.pm, nf, dsr, s->cfg.dt / (h * h), s->stream));
-      // inverse: solve M X = I
-      std::vector<double> eye((size_t)nf * a.pm, 0.0);
-      for (int k = 0; k < nf; ++k) eye[(size_t)k * a.pm + k] = 1.0;
-      HIPCHK(hipMemcpy(s->Minv, eye.data(), eye.size() * 8, hipMemcpyHostToDevice));
-      HIPCHK(launch_lu_solve(G, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
-      HIPCHK(hipStreamSynchronize(s->stream));
-      HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
-      if ((e = map_flags(s, s->hflags[0]))) return e;
+      // inverse: Newton-Schulz on the matrix cores; LU with partial pivoting if that fails
+      if (!newton_schulz_inverse(s, G, s->Minv, nf, a.pm, gm, &e)) {
+        if (e) return e;
+        std::vector<double> eye((size_t)nf * a.pm, 0.0);
+        for (int k = 0; k < nf; ++k) eye[(size_t)k * a.pm + k] = 1.0;
+        HIPCHK(hipMemcpy(s->Minv, eye.data(), eye.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(launch_lu_solve(G, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        HIPCHK(hipMemcpy(s->hflags, s->flags, 8, hipMemcpyDeviceToHost));
+        if ((e = map_flags(s, s->hflags[0]))) return e;
+      }
       d.val.resize((size_t)nf * a.pm);
       HIPCHK(hipMemcpy(d.val.data(), s->Minv, d.val.size() * 8, hipMemcpyDeviceToHost));
       return IB_OK;
