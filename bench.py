@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the run with the predictor's sine transforms on the BF16 matrix cores")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving trace (48 Poisson arrivals at 40/s, 256^2..1024^2)")
     ap.add_argument("--no-exact", action="store_true",
@@ -229,6 +231,10 @@ def main():
     if not args.no_fp64:
         wall64, prep64, _, _ = run(prob, binding.IB_FP64, args.steps, args.warmup, timing=False)
         value64 = cells * args.steps / wall64
+    value_bf16 = None
+    if not args.no_bf16:
+        wall_b, _, kt_b, _ = run(prob, binding.IB_FP32_FLOW_BF16_DST, args.steps, args.warmup)
+        value_bf16 = cells * args.steps / wall_b
     # roofline of the dominant flow kernel class
     body_rows = 0
     sd = prob.subdomain
@@ -261,6 +267,9 @@ def main():
                    "schur_refine_sweeps_last": st32["refine_iters"],
                    "schur_inverse_rebuilds": st32["inverse_rebuilds"]},
         "value_fp64": value64,
+        "value_bf16_dst_gemm": value_bf16,
+        "kernel_ms_per_step_bf16_dst_gemm": ({k: round(v[1] / args.steps, 5) for k, v in kt_b.items()}
+                                             if value_bf16 else None),
         "fp32_over_fp64": (value / value64) if value64 else None,
         "prepare_s": prep32,
         "kernel_ms_per_step": times_ms,

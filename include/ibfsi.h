@@ -59,6 +59,10 @@ typedef int32_t ib_status;
 #define IB_FP64 0        /* everything in double precision */
 #define IB_FP32_FLOW 1   /* stencils, sine transforms, spreading in float; Schur, LU and
                             structure in double */
+#define IB_FP32_FLOW_BF16_DST 2  /* IB_FP32_FLOW with the predictor's sine transforms done as
+                            dense products with the sine matrix on the BF16 matrix cores, each
+                            operand split in two BF16 parts (three products, FP32
+                            accumulation; about 16 significant bits per transform) */
 
 /* Schur operator */
 #define IB_SCHUR_AUTO 0       /* sub-domain if a sub-domain is set, else exact */
@@ -77,7 +81,7 @@ typedef struct {
   double re;          /* Reynolds number */
   double dt;          /* time step */
   double u_inf[2];    /* free stream */
-  int32_t precision;  /* IB_FP64 or IB_FP32_FLOW */
+  int32_t precision;  /* IB_FP64, IB_FP32_FLOW or IB_FP32_FLOW_BF16_DST */
   int32_t schur_mode; /* IB_SCHUR_* */
   double newton_tol;  /* FSI tolerance on max |delta theta|, |delta chi| (1e-7, Sec. 5) */
   int32_t newton_max_iter;   /* give up after this many FSI iterations (e.g. 20) */

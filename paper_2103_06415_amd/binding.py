@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libi
 
 IB_FP64 = 0
 IB_FP32_FLOW = 1
+IB_FP32_FLOW_BF16_DST = 2
 IB_SCHUR_AUTO = 0
 IB_SCHUR_EXACT = 1
 IB_SCHUR_SUBDOMAIN = 2

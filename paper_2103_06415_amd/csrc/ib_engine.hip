@@ -146,6 +146,13 @@ struct ib_solver {
   hipStream_t stream = nullptr;
   int n = 0, pitch = 0;
   bool fp64 = true;
+  bool gemm = false;  // predictor transforms as BF16-split products on the matrix cores
+  int kpad = 0;       // size of the padded sine matrix
+  void* shi = nullptr;
+  void* slo = nullptr;
+  float* sinv = nullptr;
+  float* ys = nullptr;
+  float* yg = nullptr;
   size_t es = 8;
   std::vector<LevelState> lv;
   void* work = nullptr;   // spectral rows of s (then s-transform rows)
@@ -1163,6 +1170,67 @@ ib_status fsi_and_correct(ib_solver* s) {
   return IB_OK;
 }
 
+// The predictor's solve with the sine transforms on the matrix cores (FP32 flow only):
+// right-hand side rows -> (rows) . S -> S . (columns) with the spectral solve -> S . for s and
+// gamma, leaving the same row-spectral arrays as the transform kernels (work, workg).
+template <typename T>
+ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
+  if constexpr (sizeof(T) != 4) {
+    return IB_ERR_STATE;
+  } else {
+    const int n = s->n, P = s->pitch;
+    a.out = static_cast<T*>(s->work2);
+    {
+      TimeScope ts(s, IB_K_RHS_ROWDST);
+      HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream, 0));
+      GemmArgs g{};
+      g.shi = static_cast<const __bf16*>(s->shi);
+      g.slo = static_cast<const __bf16*>(s->slo);
+      g.ps = s->kpad;
+      g.nv = n - 1;
+      g.kpad = s->kpad;
+      g.x = static_cast<const float*>(s->work2);
+      g.px = P;
+      g.c = static_cast<float*>(s->work);
+      g.pc = P;
+      HIPCHK(launch_dst_gemm(g, 1, s->stream));
+    }
+    TimeScope ts(s, IB_K_COL_SOLVE);
+    GemmArgs g{};
+    g.shi = static_cast<const __bf16*>(s->shi);
+    g.slo = static_cast<const __bf16*>(s->slo);
+    g.ps = s->kpad;
+    g.nv = n - 1;
+    g.kpad = s->kpad;
+    g.x = static_cast<const float*>(s->work);
+    g.px = P;
+    g.c = s->ys;
+    g.pc = P;
+    g.c2 = s->yg;
+    g.pc2 = P;
+    g.lam = static_cast<const float*>(s->lam);
+    g.alpha = (float)alpha;
+    g.scale = (float)(4.0 / ((double)n * n));
+    g.lift = has_ring ? static_cast<const float*>(s->lift) : nullptr;
+    g.sinv = s->sinv;
+    HIPCHK(launch_dst_gemm(g, 0, s->stream));
+    GemmArgs h{};
+    h.shi = g.shi;
+    h.slo = g.slo;
+    h.ps = g.ps;
+    h.nv = g.nv;
+    h.kpad = g.kpad;
+    h.px = h.pc = P;
+    h.x = s->ys;
+    h.c = static_cast<float*>(s->work);
+    HIPCHK(launch_dst_gemm(h, 0, s->stream));
+    h.x = s->yg;
+    h.c = static_cast<float*>(s->workg);
+    HIPCHK(launch_dst_gemm(h, 0, s->stream));
+    return IB_OK;
+  }
+}
+
 template <typename T>
 ib_status do_step(ib_solver* s) {
   const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
@@ -1194,12 +1262,14 @@ ib_status do_step(ib_solver* s) {
     a.ux = (T)(s->cfg.u_inf[0] * L.h);
     a.uy = (T)(s->cfg.u_inf[1] * L.h);
     a.cn = (T)(-1.0 / (2.0 * L.h * L.h));
-    {
-      TimeScope ts(s, IB_K_RHS_ROWDST);
-      HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
-    }
-    ib_status st;
-    {
+    ib_status st = IB_OK;
+    if (s->gemm) {
+      st = gemm_solve(s, a, L.alpha, has_ring);
+    } else {
+      {
+        TimeScope ts(s, IB_K_RHS_ROWDST);
+        HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
+      }
       TimeScope ts(s, IB_K_COL_SOLVE);
       st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
                          s->workg, has_ring ? s->lift : nullptr);
@@ -1237,6 +1307,46 @@ ib_status do_step(ib_solver* s) {
   return IB_OK;
 }
 
+// BF16 split of the sine matrix S_jk = sin(pi (j+1)(k+1) / n), zero padded to kpad, plus
+// sin(pi k / n), k <= n, and the two spectral work arrays of the matrix-core transforms.
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+ib_status make_gemm_tables(ib_solver* s) {
+  const int n = s->n, nv = n - 1;
+  s->kpad = round_up(nv, 64);
+  const int kp = s->kpad;
+  std::vector<uint16_t> hi((size_t)kp * kp, 0), lo((size_t)kp * kp, 0);
+  for (int j = 0; j < nv; ++j)
+    for (int k = 0; k < nv; ++k) {
+      const float v = (float)std::sin(M_PI * (double)(j + 1) * (double)(k + 1) / n);
+      const uint16_t h = bf16_bits(v);
+      hi[(size_t)j * kp + k] = h;
+      lo[(size_t)j * kp + k] = bf16_bits(v - bf16_value(h));
+    }
+  std::vector<float> sv(n + 1);
+  for (int k = 0; k <= n; ++k) sv[k] = (float)std::sin(M_PI * k / n);
+  s->shi = dalloc(s, hi.size() * 2);
+  s->slo = dalloc(s, lo.size() * 2);
+  s->sinv = static_cast<float*>(dalloc(s, sv.size() * 4));
+  s->ys = static_cast<float*>(dalloc(s, (size_t)nv * s->pitch * 4));
+  s->yg = static_cast<float*>(dalloc(s, (size_t)nv * s->pitch * 4));
+  if (!s->shi || !s->slo || !s->sinv || !s->ys || !s->yg) return IB_ERR_OOM;
+  HIPCHK(hipMemcpy(s->shi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->slo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->sinv, sv.data(), sv.size() * 4, hipMemcpyHostToDevice));
+  return IB_OK;
+}
+
 // Device state of the levels (allocated by ib_prepare, so that creating a solver costs
 // no device memory and a scheduler can admit it later).
 ib_status alloc_state(ib_solver* s) {
@@ -1261,6 +1371,7 @@ ib_status alloc_state(ib_solver* s) {
   ib_status st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
                          : make_tables<float>(s, s->n, &s->tw, &s->lam);
   if (st == IB_OK) st = make_tables<double>(s, s->n, &s->tw64, &s->lam64);
+  if (st == IB_OK && s->gemm) st = make_gemm_tables(s);
   if (st) return st;
   for (auto& L : s->lv) {
     HIPCHK(hipMemsetAsync(L.s, 0, full, s->stream));
@@ -1309,7 +1420,8 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   *out = nullptr;
   if (!supported_n(cfg->n) || cfg->n % 4 != 0 || cfg->levels < 1 || cfg->levels > 12 ||
       !(cfg->h > 0) || !(cfg->dt > 0) || !(cfg->re > 0) ||
-      (cfg->precision != IB_FP64 && cfg->precision != IB_FP32_FLOW) || cfg->schur_mode < 0 ||
+      (cfg->precision != IB_FP64 && cfg->precision != IB_FP32_FLOW &&
+       cfg->precision != IB_FP32_FLOW_BF16_DST) || cfg->schur_mode < 0 ||
       cfg->schur_mode > 2)
     return IB_ERR_ARG;
   ib_solver* s = new ib_solver();
@@ -1324,6 +1436,7 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->n = cfg->n;
   s->fp64 = cfg->precision == IB_FP64;
+  s->gemm = cfg->precision == IB_FP32_FLOW_BF16_DST;
   s->es = s->fp64 ? 8 : 4;
   s->pitch = round_up(s->n + 1, 64);
   for (int g = 0; g < cfg->levels; ++g) {

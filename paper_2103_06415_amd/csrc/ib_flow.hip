@@ -108,7 +108,7 @@ __device__ __forceinline__ T rhs_staged(const RhsArgs<T>& a, const T* ss, const 
 // Explicit right-hand side of ROWS interior rows fused with their row DST.  The rows
 // j-1 .. j+ROWS of s and gamma are staged in LDS (every load of a thread in flight at
 // once); the staging area is then reused as the transform buffer.
-template <typename T, int N, int ROWS, int NT>
+template <typename T, int N, int ROWS, int NT, int DST>
 __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __restrict__ tw,
                                                    int nblocks) {
   constexpr int W = N + 1;           // staged row width, ring columns included
@@ -191,6 +191,16 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
       }
       rv[b] = rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr, ring);
     }
+  }
+  if constexpr (DST == 0) {
+    // right-hand side only (the transforms run elsewhere)
+#pragma unroll
+    for (int b = 0; b < PP; ++b) {
+      const int e = tid + b * NT;
+      const int j = j0 + e / (N - 1);
+      if (e < NPT && j <= N - 1) a.out[(size_t)(j - 1) * a.po + e % (N - 1)] = rv[b];
+    }
+    return;
   }
   __syncthreads();  // the staging area becomes the transform buffer
   c2<T>* buf = uni;
@@ -605,11 +615,13 @@ bool supported_n(int n) {
 }
 
 template <typename T>
-hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st) {
+hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st, int transform) {
   constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
   const int nb = (a.n - 1 + R - 1) / R;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
-#define L_(NN) hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb)
+#define L_(NN)                                                                                   \
+  if (transform) hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 1>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb); \
+  else hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 0>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb)
   IB_DISPATCH_N(a.n, L_)
 #undef L_
   return hipGetLastError();
@@ -672,7 +684,7 @@ hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, 
 }
 
 #define IB_INST(T)                                                                              \
-  template hipError_t launch_rhs_rowdst<T>(const RhsArgs<T>&, const void*, hipStream_t);      \
+  template hipError_t launch_rhs_rowdst<T>(const RhsArgs<T>&, const void*, hipStream_t, int); \
   template hipError_t launch_rowdst<T>(const RowArgs<T>&, int, int, const void*, hipStream_t); \
   template hipError_t launch_col_solve<T>(const ColArgs<T>&, int, int, const void*, const void*, \
                                           hipStream_t);                                        \

@@ -52,10 +52,35 @@ struct ColArgs {
   int w0, w1;        // output rows written (1-based); others untouched
 };
 
+// Sine transform as a BF16-split matrix product (ib_gemm.hip): C = S X (mode 0) or
+// C = X S (mode 1), S = shi + slo the (kpad x kpad, zero padded) DST-I matrix of size nv,
+// X FP32 (nv x nv valid, pitch px).  With lam set (mode 0 only) the output is the spectral
+// solve of the column pass: c = (y / (1 + alpha L) + lift) scale / L and
+// c2 = y / (1 + alpha L) scale, L = lam[row] + lam[col], lift from the ring edge transforms
+// (as in k_col_solve) with sinv[k] = sin(pi k / n).
+struct GemmArgs {
+  const __bf16* shi;
+  const __bf16* slo;
+  int ps;
+  const float* x;
+  int px;
+  float* c;
+  int pc;
+  float* c2;
+  int pc2;
+  int nv, kpad;
+  const float* lam;
+  float alpha, scale;
+  const float* lift;
+  const float* sinv;
+};
+hipError_t launch_dst_gemm(const GemmArgs& g, int mode, hipStream_t st);
+
 bool supported_n(int n);
 
+// transform = 0: only the explicit right-hand side, written to a.out row by row
 template <typename T>
-hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st);
+hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st, int transform = 1);
 template <typename T>
 hipError_t launch_rowdst(const RowArgs<T>& a, int n, int batch, const void* tw, hipStream_t st);
 template <typename T>
