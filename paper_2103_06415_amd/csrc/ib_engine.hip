@@ -1725,6 +1725,11 @@ ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak
   const size_t full = (size_t)(n + 1) * P * es, inner = (size_t)(n - 1) * P * es;
   size_t r = (size_t)G * (full + 2 * inner + 3 * 4 * (n + 1) * es);
   r += 3 * inner + full + 4 * (size_t)(n - 1) * es + 2 * (size_t)2 * n * (8 + es);
+  if (s->gemm) {
+    // split sine matrix (two BF16 copies of kpad^2) and two FP32 product buffers
+    const size_t kp = (size_t)(n - 1 + 63) / 64 * 64;
+    r += 2 * kp * kp * 2 + 2 * (size_t)(n - 1) * P * 4 + (size_t)(n + 1) * 4;
+  }
   size_t npts = 0, ndef_y = 0, app = 0;
   for (auto& hb : s->bodies) {
     npts += hb.m;
