@@ -73,6 +73,7 @@ def run(problem, precision, steps, warmup, timing=True):
             kt[name] = s.kernel_timing(k)
         s.set_kernel_timing(False)
     st = s.stats()
+    st["flow_tuning"] = s.flow_tuning()
     s.close()
     return wall, prep, kt, st
 
@@ -187,6 +188,19 @@ def cpu_baseline(n, levels, seconds=20.0):
                       f"coupling), {wall:.1f} s"}
 
 
+def tuning_summary(t):
+    """Chosen transform-kernel configurations and the measured launch times (us)."""
+    from paper_2103_06415_amd import binding
+    out = {"n": t["n"]}
+    for kind, k in (("rhs_rowdst", "rhs"), ("col_solve", "col"), ("row_idst", "idst")):
+        v = t[k + "_variant"]
+        w, th, r = binding.flow_variant_info(1 if k == "col" else 0, v)
+        out[kind] = {"variant": v, ("columns" if k == "col" else "rows") + "_per_wg": w,
+                     "threads": th, "max_radix": r,
+                     "us_by_variant": [round(u, 2) for u in t[k + "_us"]]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +287,7 @@ def main():
         "fp32_over_fp64": (value / value64) if value64 else None,
         "prepare_s": prep32,
         "kernel_ms_per_step": times_ms,
+        "flow_tuning": tuning_summary(st32["flow_tuning"]),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM,
                      "traffic": (TRAFFIC_PER_LAUNCH.get(dom) if n == 1024 else None),

@@ -60,6 +60,17 @@ class IbStats(ctypes.Structure):
     ]
 
 
+FLOW_VARIANTS = 8
+
+
+class IbFlowTuning(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32), ("rhs_variant", c_int32), ("col_variant", c_int32),
+        ("idst_variant", c_int32), ("rhs_us", c_double * FLOW_VARIANTS),
+        ("col_us", c_double * FLOW_VARIANTS), ("idst_us", c_double * FLOW_VARIANTS),
+    ]
+
+
 class IbRequestInfo(ctypes.Structure):
     _fields_ = [
         ("ticket", c_int64), ("status", c_int32), ("steps_done", c_int32), ("arrival", c_double),
@@ -101,6 +112,10 @@ _SIGS = {
     "ib_server_run": (c_int32, [c_void_p]),
     "ib_server_info": (c_int32, [c_void_p, c_int64, POINTER(IbRequestInfo)]),
     "ib_server_destroy": (c_int32, [c_void_p]),
+    "ib_get_flow_tuning": (c_int32, [c_void_p, POINTER(IbFlowTuning)]),
+    "ib_set_flow_variants": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "ib_flow_variant_info": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_int32)]),
 }
 
 K_RHS_ROWDST, K_COL_SOLVE, K_ROW_IDST, K_FSI, K_CORRECT, K_RING = range(6)
@@ -158,6 +173,14 @@ class TorchAllocator:
         self._alloc = ALLOC_FN(_alloc)
         self._free = FREE_FN(_free)
         self.struct = IbAllocator(self._alloc, self._free, None)
+
+
+def flow_variant_info(kind, variant):
+    """(width, threads, largest radix) of configuration `variant`; kind 0 rows, 1 columns."""
+    w, t, r = c_int32(), c_int32(), c_int32()
+    _check(load().ib_flow_variant_info(kind, variant, byref(w), byref(t), byref(r)),
+           "ib_flow_variant_info")
+    return w.value, t.value, r.value
 
 
 def set_operator_cache(limit_bytes):
@@ -271,6 +294,17 @@ class Solver:
         _check(self.lib.ib_get_kernel_timing(self.handle, cls, byref(n), byref(ms)),
                "ib_get_kernel_timing")
         return n.value, ms.value
+
+    def flow_tuning(self):
+        """The measured transform-kernel configurations (see ib_get_flow_tuning)."""
+        t = IbFlowTuning()
+        _check(self.lib.ib_get_flow_tuning(self.handle, byref(t)), "ib_get_flow_tuning")
+        return {"n": t.n, "rhs_variant": t.rhs_variant, "col_variant": t.col_variant,
+                "idst_variant": t.idst_variant, "rhs_us": list(t.rhs_us),
+                "col_us": list(t.col_us), "idst_us": list(t.idst_us)}
+
+    def set_flow_variants(self, rhs=-1, col=-1, idst=-1):
+        _check(self.lib.ib_set_flow_variants(self.handle, rhs, col, idst), "ib_set_flow_variants")
 
     def release(self):
         """Give the device memory back; stresses, deflections and level-0 vorticity stay readable."""

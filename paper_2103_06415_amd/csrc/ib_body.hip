@@ -726,7 +726,6 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
 __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
-  if (a.rmore != nullptr && *a.rmore != 0.0) return;  // the stress solve is not finished
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = STRUCT_NT / 64;
   const int gw = blockIdx.x * NW + w, nwaves = gridDim.x * NW;
@@ -1065,116 +1064,214 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 // X <- X (2I - M X) (two GEMMs), then f = X b corrected by iterative refinement
 // f <- f + X (b - M f) to working accuracy.  A fresh inverse (LU) is made at the
 // first use and whenever the refinement stops contracting.
-
-// ---------------------------------------------- Schur solve by iterative refinement
-// f = X b (or the caller's guess in f), then sweeps r = b - M f, f += X r while the relative residual |r|/|b| (max
-// norms) still exceeds 1e-16 n and still halves.  Each matrix-vector product is one
-// launch over many workgroups (one wave per row), so the matrices stream through many
-// CUs; a sweep that follows convergence returns at once.  Workspace `ws` (doubles):
-//   [0] relative residual, [1] sweeps, [2] |b| bits, [3] done flag,
-//   [4 .. 4+maxit) residual norms (bit patterns of non-negative doubles, atomicMax),
-//   [REF_HDR + maxit ..) the residual vector r.
-constexpr int REF_HDR = 8;
-size_t refine_ws_doubles(int n, int maxit) { return (size_t)REF_HDR + maxit + n; }
+//
+// The refinement is one launch of nb co-resident workgroups.  Workgroup w owns rows R_w of
+// M and columns R_w of X (held in LDS when they fit).  Each sweep it forms r = b - M f on R_w,
+// its share X[:, R_w] r_{R_w} of the update and max |r| over R_w, and publishes both; after
+// one grid barrier every workgroup reads all shares and maxima and adds the shares in
+// workgroup order, so all hold the same f and take the same decision.  Sweeps stop when the
+// relative residual |r|/|b| (max norms) is at most 1e-16 n or no longer halves, after at most
+// maxit sweeps; f then keeps the value whose residual was tested.  With no guess, f starts at
+// 0, so the first sweep gives f = X b.  Workspace `ws` (doubles): [0] relative residual,
+// [1] sweeps, [2] barrier arrivals, [3] exits (32-bit counters), then two buffers of nb rows
+// of n + 1 values (the share, then the maximum); alternate sweeps use alternate buffers, so a
+// row is never overwritten while another workgroup may still read it.  The last workgroup to
+// leave zeroes the counters for the next launch.
+constexpr int REF_HDR = 4;
+constexpr int REF_NB_MAX = 32;
+constexpr size_t REF_LDS_CACHE = 48 * 1024;
+size_t refine_ws_doubles(int n, int) { return (size_t)REF_HDR + (size_t)2 * REF_NB_MAX * (n + 1); }
 
 __device__ inline unsigned long long dbits(double v) {
   return (unsigned long long)__double_as_longlong(v);
 }
 __device__ inline double bitsd(unsigned long long v) { return __longlong_as_double((long long)v); }
 
-__global__ __launch_bounds__(256) void k_ref_reset(const double* b, int n, double* ws, int maxit) {
-  __shared__ double red[4];
-  unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
-  for (int i = threadIdx.x; i < REF_HDR + maxit; i += 256) wu[i] = 0ull;
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const double v = fabs(b[i]);
-    m = (v > m || v != v) ? v : m;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(m, off);
-    m = (o > m || o != o) ? o : m;
-  }
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+// Barrier over the workgroups of one launch, which must all be resident.  Arrivals count up
+// in `cnt` (the k-th barrier waits for k * gridDim.x).  Data that crosses it is written and
+// read only with agent-scope atomic stores and loads, which are coherent across the chip's
+// L2 caches, so readers need no cache invalidation; every thread's agent-scope release fence
+// before the workgroup barrier makes its stores complete before the arrival.  The wait is bounded:
+// on time-out it records FLAG_BARRIER in flags[0] and returns false, and every other
+// waiting workgroup then leaves its wait at once.
+constexpr long BARRIER_SPIN_LIMIT = 1L << 22;
+__device__ bool grid_barrier(unsigned* cnt, unsigned target, int* flags) {
+  __shared__ int ok_s;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
-    double r = red[0];
-    for (int k = 1; k < 4; ++k) r = (red[k] > r || red[k] != red[k]) ? red[k] : r;
-    ws[2] = r;
-  }
-}
-
-// mode 0: y = A x;  mode 1: y = b - A x and its max norm into slot `it`;
-// mode 2: convergence test of sweep `it`, then y += A x unless converged.
-__global__ __launch_bounds__(256) void k_ref_matvec(const double* A, int pa, const double* x,
-                                                    const double* b, double* y, int n, int mode,
-                                                    double* ws, int it) {
-  unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
-  if (mode != 0) {
-    if (wu[3] != 0ull) return;
-    if (mode == 2) {
-      const double nr = bitsd(wu[4 + it]);
-      const double prev = it > 0 ? bitsd(wu[4 + it - 1]) : 1e300;
-      const double nb = ws[2];
-      const double rel = nb > 0.0 ? nr / nb : 0.0;
-      if (!(rel > 1e-16 * n) || !(nr < 0.5 * prev)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-          ws[0] = rel;
-          ws[1] = it;
-          wu[3] = 1ull;
-        }
-        return;
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    long spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255) == 0 &&
+          (spins > BARRIER_SPIN_LIMIT ||
+           __hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == FLAG_BARRIER)) {
+        atomicMax(&flags[0], FLAG_BARRIER);
+        ok = 0;
+        break;
       }
     }
+    ok_s = ok;
   }
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const double* ar = A + (size_t)row * pa;
-  constexpr int CQ = 8;
-  double acc = 0.0;
-  for (int c0 = 0; c0 < n; c0 += 64 * CQ) {
-    double av[CQ], xv[CQ];
-#pragma unroll
-    for (int k = 0; k < CQ; ++k) {
-      const int c = c0 + 64 * k + lane;
-      av[k] = c < n ? ar[c] : 0.0;
-      xv[k] = c < n ? x[c] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < CQ; ++k) acc += av[k] * xv[k];
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) {
-    if (mode == 0) {
-      y[row] = acc;
-    } else if (mode == 1) {
-      const double r = b[row] - acc;
-      y[row] = r;
-      const double ar2 = fabs(r);
-      atomicMax(&wu[4 + it], ar2 != ar2 ? 0x7ff8000000000000ull : dbits(ar2));
-    } else {
-      y[row] += acc;
-    }
-  }
+  __syncthreads();
+  return ok_s != 0;
 }
 
-__global__ void k_ref_final(double* ws, int maxit, int* flags, double* out, int partial) {
-  if (threadIdx.x != 0) return;
-  unsigned long long* wu = reinterpret_cast<unsigned long long*>(ws);
-  const bool done = wu[3] != 0ull;
-  if (!done) {
-    const double nr = bitsd(wu[4 + maxit - 1]);
-    const double nb = ws[2];
-    ws[0] = nb > 0.0 ? nr / nb : 0.0;
-    ws[1] = maxit;
+__device__ inline void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
+
+template <bool CACHE>
+__global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
+                                                const double* __restrict__ X, int pm,
+                                                const double* __restrict__ b, double* f, int n,
+                                                int rw, int tpr, int maxit, int guess, double* ws,
+                                                double* out, int* flags) {
+  extern __shared__ double lds[];
+  double* sf = lds;           // f (n)
+  double* sd = sf + n;        // the update of this sweep (n)
+  double* sr = sd + n;        // r on the own rows (rw)
+  double* sb = sr + rw;       // b on the own rows (rw)
+  double* sred = sb + rw;     // 4 partial maxima
+  double* sm = sred + 4;      // rows R_w of M (rw x n) when CACHE
+  double* sx = sm + (size_t)rw * n;  // columns R_w of X (n x rw) when CACHE
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = gridDim.x, w = blockIdx.x, ns = n + 1;
+  const int r0 = w * rw, r1 = min(n, r0 + rw), nr = max(0, r1 - r0);
+  unsigned* cnt = reinterpret_cast<unsigned*>(ws + 2);
+  unsigned* ext = reinterpret_cast<unsigned*>(ws + 3);
+  double* shares = ws + REF_HDR;
+  // |b| and the starting f (the same in every workgroup)
+  double mb = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    mb = nanmax(mb, fabs(b[i]));
+    sf[i] = guess ? f[i] : 0.0;
   }
-  out[0] = ws[0];
-  out[1] = ws[1];
-  // with `partial`, running out of sweeps while still contracting asks the caller for
-  // more sweeps (out[2] = 1) instead of counting as a failure
-  out[2] = (!done && partial) ? 1.0 : 0.0;
-  if (!(!done && partial) && !(ws[0] < 1e-9)) atomicMax(&flags[1], 1);  // the inverse is stale
+  for (int off = 32; off > 0; off >>= 1) mb = nanmax(mb, __shfl_xor(mb, off));
+  if (lane == 0) sred[wv] = mb;
+  for (int k = tid; k < nr; k += 256) sb[k] = b[r0 + k];
+  if (CACHE) {
+    for (int e = tid; e < nr * n; e += 256) {
+      const int k = e / n, j = e % n;
+      sm[e] = M[(size_t)(r0 + k) * pm + j];
+    }
+    for (int e = tid; e < nr * n; e += 256) {
+      const int j = e / nr, k = e % nr;
+      sx[(size_t)j * rw + k] = X[(size_t)j * pm + r0 + k];
+    }
+  }
+  __syncthreads();
+  const double nbv = nanmax(nanmax(sred[0], sred[1]), nanmax(sred[2], sred[3]));
+  double prev = 1e300, rel = 0.0;
+  int sweeps = maxit;
+  bool ok = true;
+  unsigned target = 0;
+  const int rk = tid / tpr, rp = tid % tpr;  // row and part of this thread in r = b - M f
+  for (int it = 0; it < maxit; ++it) {
+    // r = b - M f on the own rows: tpr threads per row
+    {
+      double acc = 0.0;
+      if (rk < nr) {
+        const double* mr = CACHE ? sm + (size_t)rk * n : M + (size_t)(r0 + rk) * pm;
+        for (int j0 = rp; j0 < n; j0 += 8 * tpr) {
+          double mv[8], fv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u * tpr, n - 1);
+            mv[u] = mr[j];
+            fv[u] = j0 + u * tpr < n ? sf[j] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += mv[u] * fv[u];
+        }
+      }
+      for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (rk < nr && rp == 0) sr[rk] = sb[rk] - acc;
+    }
+    __syncthreads();
+    double* sh = shares + (size_t)(it & 1) * REF_NB_MAX * ns + (size_t)w * ns;
+    if (wv == 0) {
+      double m = 0.0;
+      for (int k = lane; k < nr; k += 64) m = nanmax(m, fabs(sr[k]));
+      for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+      if (lane == 0) st_agent(&sh[n], m);
+    }
+    // this workgroup's share of X r
+    for (int j = tid; j < n; j += 256) {
+      double acc = 0.0;
+      for (int k0 = 0; k0 < nr; k0 += 8) {
+        double xv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = min(k0 + u, nr - 1);
+          xv[u] = CACHE ? sx[(size_t)j * rw + k] : X[(size_t)j * pm + r0 + k];
+          rv[u] = k0 + u < nr ? sr[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += xv[u] * rv[u];
+      }
+      st_agent(&sh[j], acc);
+    }
+    target += (unsigned)nb;
+    if (!grid_barrier(cnt, target, flags)) {
+      ok = false;
+      break;
+    }
+    // all maxima and shares, loads in flight together; shares summed in workgroup order
+    const double* all = shares + (size_t)(it & 1) * REF_NB_MAX * ns;
+    double nrm = 0.0;
+    for (int j0 = 0; j0 < n; j0 += 256) {
+      const int j = j0 + tid, jc = min(j, n - 1);
+      double acc = 0.0;
+      for (int q0 = 0; q0 < nb; q0 += 16) {
+        double v[16], u[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = ld_agent(&all[(size_t)min(q0 + q, nb - 1) * ns + jc]);
+        if (j0 == 0) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) u[q] = ld_agent(&all[(size_t)min(q0 + q, nb - 1) * ns + n]);
+#pragma unroll
+          for (int q = 0; q < 16; ++q) nrm = nanmax(nrm, u[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc += q0 + q < nb ? v[q] : 0.0;
+      }
+      if (j < n) sd[j] = acc;
+    }
+    rel = nbv > 0.0 ? nrm / nbv : 0.0;
+    if (!(rel > 1e-16 * n) || !(nrm < 0.5 * prev)) {
+      sweeps = it;
+      break;
+    }
+    prev = nrm;
+    for (int j = tid; j < n; j += 256) sf[j] += sd[j];
+    __syncthreads();
+  }
+  if (ok) {
+    for (int i = r0 + tid; i < r1; i += 256) f[i] = sf[i];
+    if (w == 0 && tid == 0) {
+      ws[0] = rel;
+      ws[1] = sweeps;
+      out[0] = rel;
+      out[1] = sweeps;
+      out[2] = 0.0;
+      if (!(rel < 1e-9)) atomicMax(&flags[1], 1);  // the inverse is stale
+    }
+  }
+  if (tid == 0) {
+    if (__hip_atomic_fetch_add(ext, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        (unsigned)nb - 1) {
+      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ext, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B, on the FP64 matrix
@@ -1249,19 +1346,29 @@ hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_identity, dim3((n + 255) / 256), dim3(256), 0, st, X, p, n);
   return hipGetLastError();
 }
-hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
-                               int n, int maxit, int guess, int partial, double* ws, double* out,
-                               int* flags, hipStream_t st) {
+hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
+                         int n, int maxit, int guess, double* ws, double* out, int* flags,
+                         hipStream_t st) {
   if (n < 1 || maxit < 1) return hipErrorInvalidValue;
-  double* r = ws + REF_HDR + maxit;
-  const dim3 grid((n + 3) / 4), blk(256);
-  hipLaunchKernelGGL(k_ref_reset, dim3(1), blk, 0, st, b, n, ws, maxit);
-  if (!guess) hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, b, b, f, n, 0, ws, 0);
-  for (int it = 0; it < maxit; ++it) {
-    hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, M, pm, f, b, r, n, 1, ws, it);
-    hipLaunchKernelGGL(k_ref_matvec, grid, blk, 0, st, X, pm, r, b, f, n, 2, ws, it);
+  int nb = std::min(16, (n + 7) / 8);
+  int rw = (n + nb - 1) / nb;
+  if ((size_t)2 * rw * n * 8 > REF_LDS_CACHE) {
+    nb = std::min(REF_NB_MAX, (n + 7) / 8);
+    rw = (n + nb - 1) / nb;
   }
-  hipLaunchKernelGGL(k_ref_final, dim3(1), dim3(64), 0, st, ws, maxit, flags, out, partial);
+  nb = (n + rw - 1) / rw;  // no workgroup without rows
+  int tpr = 64;            // threads per row of r = b - M f: a power of two, tpr * rw <= 256
+  while (tpr > 1 && tpr * rw > 256) tpr >>= 1;
+  if (tpr * rw > 256) return hipErrorInvalidValue;
+  const bool cache = (size_t)2 * rw * n * 8 <= REF_LDS_CACHE;
+  const size_t lds = ((size_t)2 * n + 2 * rw + 4 + (cache ? (size_t)2 * rw * n : 0)) * 8;
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  if (cache)
+    hipLaunchKernelGGL(k_refine<true>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
+                       maxit, guess, ws, out, flags);
+  else
+    hipLaunchKernelGGL(k_refine<false>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
+                       maxit, guess, ws, out, flags);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,

@@ -26,6 +26,11 @@ struct BodyDev {
 enum { TS_THETA = 0, TS_PHI, TS_PHIDOT, TS_NEW, TS_G, TS_COUNT };
 
 // Everything the FSI kernels need.  Pointers are device pointers.
+// flags[0] codes (the largest wins): 1 point outside the sub-domain, 2 delta support at
+// the level-0 boundary, 3 singular or non-finite Schur matrix, 4 a device-wide barrier
+// timed out.
+constexpr int FLAG_BARRIER = 4;
+
 struct FsiArgs {
   const BodyDev* bodies;
   int nbodies, npts, nf, ntors, ndef;
@@ -71,7 +76,6 @@ struct FsiArgs {
   const double* beta0;
   double* ywork;       // J_d^{-1} T^T, per deformable body: (3m) x (2m)
   int* flags;          // [0] error code, [1] refinement failure
-  const double* rmore; // non-zero: the stress solve needs more sweeps, k_update waits
   double* delta;       // [0] max |delta| of the last update
 };
 
@@ -121,9 +125,9 @@ hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
 // out[0] = final relative residual, out[1] = sweeps, out[2] = 1 when `partial` is set and
 // the maxit sweeps ran out before convergence (the caller continues with guess = 1);
 // otherwise flags[1] is raised when the residual stays above 1e-9
-hipError_t launch_solve_refine(const double* M, int pm, const double* X, const double* b, double* f,
-                               int n, int maxit, int guess, int partial, double* ws, double* out,
-                               int* flags, hipStream_t st);
+hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
+                         int n, int maxit, int guess, double* ws, double* out, int* flags,
+                         hipStream_t st);
 size_t refine_ws_doubles(int n, int maxit);
 hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
 // *out (zeroed by the caller) folds in max |W - I| over the n x n matrix (+Inf if not finite)

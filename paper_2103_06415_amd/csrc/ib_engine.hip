@@ -19,6 +19,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <list>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -139,6 +140,15 @@ struct Offline {
   double* vals = nullptr;     // [nslots][ntarget]
 };
 
+// Configurations of the single-precision transform kernels chosen for one grid size, with
+// the measured average launch times (microseconds; 0 = not measured).
+struct FlowTuning {
+  int n = 0;
+  int rhs = 0, col = 0, idst = 0;
+  double rhs_us[ib::FLOW_VARIANTS] = {}, col_us[ib::FLOW_VARIANTS] = {},
+         idst_us[ib::FLOW_VARIANTS] = {};
+};
+
 struct ib_solver {
   ib_config cfg{};
   ib_allocator alloc{};
@@ -147,6 +157,8 @@ struct ib_solver {
   int n = 0, pitch = 0;
   bool fp64 = true;
   bool gemm = false;  // predictor transforms as BF16-split products on the matrix cores
+  FlowTuning tune;    // kernel configurations of the row and column transforms
+  bool tune_forced = false;
   int kpad = 0;       // size of the padded sine matrix
   void* shi = nullptr;
   void* slo = nullptr;
@@ -207,7 +219,6 @@ struct ib_solver {
   bool x_valid_retry = false;
   int inverse_rebuilds = 0;
   // sweeps launched per stress solve in tolerance mode, per FSI iteration index (0, 1, 2, 3+)
-  int refine_budget[4] = {REFINE_MAXIT, REFINE_MAXIT, REFINE_MAXIT, REFINE_MAXIT};
   // control block read back once per FSI iteration: error flags (2 ints), max |delta|,
   // refinement residual and sweeps; one device copy and its pinned host mirror
   void* ctl = nullptr;
@@ -290,8 +301,9 @@ ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
 template <typename T>
 ib_status solve_into(ib_solver* s, void* work, double alpha, double scale, int r0, int r1,
                      const void* tw, const void* lam, void* workg = nullptr,
-                     const void* lift = nullptr) {
+                     const void* lift = nullptr, int var = 0) {
   ColArgs<T> c{};
+  c.var = var;
   c.in = static_cast<T*>(work);
   c.out = static_cast<T*>(work);
   c.out2 = static_cast<T*>(workg);
@@ -483,6 +495,10 @@ ib_status map_flags(ib_solver* s, int code) {
   if (code == 3) {
     s->last_error = "singular or non-finite Schur matrix";
     return IB_ERR_NONFINITE;
+  }
+  if (code == FLAG_BARRIER) {
+    s->last_error = "a device-wide barrier timed out";
+    return IB_ERR_HIP;
   }
   return IB_OK;
 }
@@ -793,6 +809,8 @@ ib_status prepare_bodies(ib_solver* s) {
     s->Mtmp = static_cast<double*>(dalloc(s, mb));
     s->rinfo = static_cast<double*>(dalloc(s, refine_ws_doubles(nf, REFINE_MAXIT) * 8));
     if (!s->Minv || !s->Xn || !s->W || !s->Mtmp || !s->rinfo) return IB_ERR_OOM;
+    // the refinement's barrier counters and norms start at zero (each launch leaves them so)
+    HIPCHK(hipMemset(s->rinfo, 0, refine_ws_doubles(nf, REFINE_MAXIT) * 8));
     s->x_valid = false;
   }
   a.tors = up(tors);
@@ -813,7 +831,6 @@ ib_status prepare_bodies(ib_solver* s) {
   s->rout = reinterpret_cast<double*>(static_cast<char*>(s->ctl) + 16);
   a.flags = s->flags;
   a.delta = s->delta;
-  a.rmore = s->rout + 2;
   HIPCHK(hipMemset(s->ctl, 0, 64));
   if (!s->hctl) {
     HIPCHK(hipHostMalloc(&s->hctl, 64, hipHostMallocDefault));
@@ -1065,12 +1082,8 @@ ib_status fsi_and_correct(ib_solver* s) {
         HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream));
         std::swap(s->Minv, s->Xn);
       }
-      // in tolerance mode the sweeps launched follow the last solve's need (no-op sweeps
-      // after convergence still cost a launch each); running short asks for more below
-      const int budget = fixed > 0 ? REFINE_MAXIT : s->refine_budget[std::min(it, 3)];
-      HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, budget,
-                                 it > 0 && !s->x_valid_retry, budget < REFINE_MAXIT, s->rinfo,
-                                 s->rout, s->flags, s->stream));
+      HIPCHK(launch_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, REFINE_MAXIT,
+                           it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, s->stream));
       HIPCHK(launch_update(a, s->stream));
     }
     bool done = false;
@@ -1079,6 +1092,8 @@ ib_status fsi_and_correct(ib_solver* s) {
       if (done) {
         HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
+        ib_status st = map_flags(s, s->hflags[0]);
+        if (st) return st;
         if (s->hflags[1]) {
           s->last_error = "Schur refinement did not converge";
           return IB_ERR_NONFINITE;
@@ -1087,20 +1102,6 @@ ib_status fsi_and_correct(ib_solver* s) {
     } else {
       HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
       HIPCHK(hipStreamSynchronize(s->stream));
-      if (s->hrinfo[2] != 0.0) {
-        // the sweep budget ran out while the refinement still contracted: continue it
-        // from the current f with the full budget, then update the structure
-        TimeScope ts(s, IB_K_FSI);
-        HIPCHK(launch_solve_refine(a.M, a.pm, s->Minv, s->rhs, s->f, s->nf, REFINE_MAXIT, 1, 0,
-                                   s->rinfo, s->rout, s->flags, s->stream));
-        HIPCHK(launch_update(a, s->stream));
-        HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
-        HIPCHK(hipStreamSynchronize(s->stream));
-        int& rb = s->refine_budget[std::min(it, 3)];
-        rb = std::min(REFINE_MAXIT, rb + (int)s->hrinfo[1] + 2);
-      } else {
-        s->refine_budget[std::min(it, 3)] = std::min(REFINE_MAXIT, std::max(3, (int)s->hrinfo[1] + 2));
-      }
       ib_status st = map_flags(s, s->hflags[0]);
       if (st) return st;
       if (s->hflags[1]) {
@@ -1163,6 +1164,7 @@ ib_status fsi_and_correct(ib_solver* s) {
   c.accumulate = 1;
   c.w0 = 1;
   c.w1 = n - 1;
+  c.var = s->tune.col;
   {
     TimeScope ts(s, IB_K_COL_SOLVE);
     HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
@@ -1262,8 +1264,10 @@ ib_status do_step(ib_solver* s) {
     a.ux = (T)(s->cfg.u_inf[0] * L.h);
     a.uy = (T)(s->cfg.u_inf[1] * L.h);
     a.cn = (T)(-1.0 / (2.0 * L.h * L.h));
+    a.var = s->tune.rhs;
     ib_status st = IB_OK;
     if (s->gemm) {
+      a.var = 0;
       st = gemm_solve(s, a, L.alpha, has_ring);
     } else {
       {
@@ -1272,7 +1276,7 @@ ib_status do_step(ib_solver* s) {
       }
       TimeScope ts(s, IB_K_COL_SOLVE);
       st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
-                         s->workg, has_ring ? s->lift : nullptr);
+                         s->workg, has_ring ? s->lift : nullptr, s->tune.col);
     }
     if (st) return st;
     RowArgs<T> r{};
@@ -1296,6 +1300,7 @@ ib_status do_step(ib_solver* s) {
     r.r1 = n - 1;
     r.in2 = static_cast<T*>(s->workg);
     r.out2 = static_cast<T*>(L.g);
+    r.var = s->tune.idst;
     {
       TimeScope ts(s, IB_K_ROW_IDST);
       HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
@@ -1395,6 +1400,141 @@ ib_status check(ib_solver* s) {
 }  // namespace
 
 // ======================================================================== C ABI
+
+// Measured choice of the single-precision transform kernel configurations for one grid
+// size (process-wide, by n): every configuration of the right-hand side + row transform,
+// the column solve and the inverse row transform runs on scratch buffers of a level's
+// shape, and the fastest average launch time wins.  One solver measures at a time.
+std::mutex g_tune_mu;
+std::map<int, FlowTuning> g_tune;
+
+ib_status tune_flow(ib_solver* s) {
+  const int n = s->n, P = s->pitch;
+  if (s->tune_forced) return IB_OK;
+  s->tune = FlowTuning{};
+  if (s->fp64 || !ib::flow_variant_available(n, 0)) return IB_OK;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(n);
+  if (it != g_tune.end()) {
+    s->tune = it->second;
+    return IB_OK;
+  }
+  const size_t full = (size_t)(n + 1) * P * 4, inner = (size_t)(n - 1) * P * 4;
+  const size_t ring = (size_t)4 * (n + 1) * 4, edges = (size_t)4 * (n - 1) * 4;
+  float* sf = static_cast<float*>(dalloc(s, full));
+  float* gi = static_cast<float*>(dalloc(s, inner));
+  float* hist = static_cast<float*>(dalloc(s, inner));
+  float* out = static_cast<float*>(dalloc(s, inner));
+  float* out2 = static_cast<float*>(dalloc(s, inner));
+  float* gr = static_cast<float*>(dalloc(s, ring));
+  float* gr2 = static_cast<float*>(dalloc(s, ring));
+  float* lift = static_cast<float*>(dalloc(s, edges));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    for (void* p : {(void*)sf, (void*)gi, (void*)hist, (void*)out, (void*)out2, (void*)gr,
+                    (void*)gr2, (void*)lift})
+      dfree(s, p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (!sf || !gi || !hist || !out || !out2 || !gr || !gr2 || !lift) {
+    release();
+    return IB_ERR_OOM;
+  }
+  hipError_t e = hipSuccess;
+  for (auto pr : {std::make_pair((void*)sf, full), std::make_pair((void*)gi, inner),
+                  std::make_pair((void*)hist, inner), std::make_pair((void*)out, inner),
+                  std::make_pair((void*)out2, inner), std::make_pair((void*)gr, ring),
+                  std::make_pair((void*)gr2, ring), std::make_pair((void*)lift, edges)})
+    if (e == hipSuccess) e = hipMemsetAsync(pr.first, 0, pr.second, s->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    release();
+    return hip_fail(s, e, "flow tuning set-up");
+  }
+  const double h = s->cfg.h;
+  RhsArgs<float> a{};
+  a.s = sf;
+  a.g = gi;
+  a.gring = gr;
+  a.gring_new = gr2;
+  a.hist_in = hist;
+  a.hist_out = hist;
+  a.out = out;
+  a.n = n;
+  a.ps = a.pg = a.pgf = a.ph = a.po = P;
+  a.alpha = (float)(s->cfg.dt / (2.0 * s->cfg.re * h * h));
+  a.dt = (float)s->cfg.dt;
+  a.cn = (float)(-1.0 / (2.0 * h * h));
+  ColArgs<float> c{};
+  c.in = c.out = out;
+  c.out2 = out2;
+  c.lift = lift;
+  c.pi = c.po = P;
+  c.r0 = 1;
+  c.r1 = n - 1;
+  c.alpha = a.alpha;
+  c.scale = (float)(4.0 / ((double)n * n));
+  c.w0 = 1;
+  c.w1 = n - 1;
+  RowArgs<float> r{};
+  r.in = out;
+  r.in2 = out2;
+  r.out = sf;
+  r.out2 = gi;
+  r.pi = r.po = P;
+  r.r0 = 1;
+  r.r1 = n - 1;
+  constexpr int REPS = 3, K = 8;
+  // average launch time of configuration v of kernel kind k (0 rhs, 1 col, 2 idst)
+  auto measure = [&](int k, int v, double* us) -> hipError_t {
+    auto launch = [&]() -> hipError_t {
+      if (k == 0) {
+        a.var = v;
+        return launch_rhs_rowdst<float>(a, s->tw, s->stream);
+      }
+      if (k == 1) {
+        c.var = v;
+        return launch_col_solve<float>(c, n, 1, s->tw, s->lam, s->stream);
+      }
+      r.var = v;
+      return launch_row_idst<float>(r, n, 1, s->tw, static_cast<float*>(gr), 1, s->stream);
+    };
+    double best = 1e30;
+    for (int rep = 0; rep < REPS; ++rep) {
+      hipError_t q = launch();  // warm-up
+      if (q == hipSuccess) q = hipEventRecord(e0, s->stream);
+      for (int i = 0; i < K && q == hipSuccess; ++i) q = launch();
+      if (q == hipSuccess) q = hipEventRecord(e1, s->stream);
+      if (q == hipSuccess) q = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (q == hipSuccess) q = hipEventElapsedTime(&ms, e0, e1);
+      if (q != hipSuccess) return q;
+      best = std::min(best, 1e3 * ms / K);
+    }
+    *us = best;
+    return hipSuccess;
+  };
+  FlowTuning t;
+  t.n = n;
+  double* tabs[3] = {t.rhs_us, t.col_us, t.idst_us};
+  int* pick[3] = {&t.rhs, &t.col, &t.idst};
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    if (k == 0 && s->gemm) continue;  // the matrix-core path has its own right-hand side pass
+    for (int v = 0; v < ib::FLOW_VARIANTS && e == hipSuccess; ++v) e = measure(k, v, &tabs[k][v]);
+    int b = 0;
+    for (int v = 1; v < ib::FLOW_VARIANTS; ++v)
+      if (tabs[k][v] < tabs[k][b]) b = v;
+    *pick[k] = b;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  release();
+  if (e != hipSuccess) return hip_fail(s, e, "flow tuning");
+  if (!s->gemm) g_tune[n] = t;
+  s->tune = t;
+  return IB_OK;
+}
 
 extern "C" {
 
@@ -1534,6 +1674,7 @@ ib_status ib_prepare(ib_solver* s) {
   if (check(s)) return IB_ERR_ARG;
   if (s->prepared || s->released) return IB_ERR_STATE;
   ib_status st = s->allocated ? IB_OK : alloc_state(s);
+  if (st == IB_OK) st = tune_flow(s);
   if (st == IB_OK) st = s->fp64 ? do_prepare<double>(s) : do_prepare<float>(s);
   if (st) {
     s->failed = true;
@@ -1659,6 +1800,49 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   out->refine_residual = s->hrinfo ? s->hrinfo[0] : 0.0;
   out->inverse_rebuilds = s->inverse_rebuilds;
   out->operator_source = s->op ? s->op_source : -1;
+  return IB_OK;
+}
+
+ib_status ib_get_flow_tuning(ib_solver* s, ib_flow_tuning* out) {
+  if (check(s) || !out) return IB_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  static_assert(IB_FLOW_VARIANTS == ib::FLOW_VARIANTS, "variant count");
+  out->n = s->tune.n;
+  out->rhs_variant = s->tune.rhs;
+  out->col_variant = s->tune.col;
+  out->idst_variant = s->tune.idst;
+  for (int v = 0; v < IB_FLOW_VARIANTS; ++v) {
+    out->rhs_us[v] = s->tune.rhs_us[v];
+    out->col_us[v] = s->tune.col_us[v];
+    out->idst_us[v] = s->tune.idst_us[v];
+  }
+  return IB_OK;
+}
+
+ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t idst) {
+  if (check(s)) return IB_ERR_ARG;
+  const int32_t v[3] = {rhs, col, idst};
+  for (int k = 0; k < 3; ++k) {
+    if (v[k] < -1 || v[k] >= IB_FLOW_VARIANTS) return IB_ERR_ARG;
+    if (v[k] > 0 && !ib::flow_variant_available(s->n, s->fp64 ? 1 : 0)) return IB_ERR_ARG;
+  }
+  if (rhs > 0 && s->gemm) return IB_ERR_ARG;
+  if (rhs >= 0) s->tune.rhs = rhs;
+  if (col >= 0) s->tune.col = col;
+  if (idst >= 0) s->tune.idst = idst;
+  s->tune_forced = true;
+  return IB_OK;
+}
+
+ib_status ib_flow_variant_info(int32_t kind, int32_t variant, int32_t* width, int32_t* threads,
+                               int32_t* max_radix) {
+  if ((kind != 0 && kind != 1) || variant < 0 || variant >= IB_FLOW_VARIANTS || !width ||
+      !threads || !max_radix)
+    return IB_ERR_ARG;
+  const ib::FlowVariant& f = kind == 0 ? ib::ROW_VARIANTS[variant] : ib::COL_VARIANTS[variant];
+  *width = f.width;
+  *threads = f.nt;
+  *max_radix = f.maxr;
   return IB_OK;
 }
 

@@ -10,11 +10,13 @@
 //   E_k = (W_k + conj W_{n-k}) / 2,  O_k = (W_k - conj W_{n-k}) / (2i)
 //   X_k = sum_j x_j sin(pi j k / n) = -Im(E_k + e^{-i pi k / n} O_k) / 2
 //
-// The FFT is a Stockham autosort transform working in place on LDS with radix-16
-// stages first (then one radix-8, -4 or -2 stage for the rest of the power of two, then
-// radix-3 stages): every stage loads its inputs into registers, synchronises the
-// workgroup, and writes the butterflies' outputs back, so large radices mean fewer
-// barriers and less LDS traffic.  Twiddles come from one table per n,
+// The FFT is a Stockham autosort transform working in place on LDS with stages of the
+// largest radix MAXR (16, 8 or 4) first, then one smaller power-of-two stage for the rest
+// of the power of two, then radix-3 stages: every stage loads its inputs into registers,
+// synchronises the workgroup, and writes the butterflies' outputs back.  Large radices
+// mean fewer barriers and less LDS traffic; small ones more butterflies per stage (more
+// waves in flight to hide latency) and fewer registers per thread.  The choice is made per
+// size by measurement.  Twiddles come from one table per n,
 // tw[m] = exp(-i pi m / n), m < 2n, prepared on the host in double precision.
 #pragma once
 
@@ -26,17 +28,19 @@ constexpr int ilog2c(int m) { return m <= 1 ? 0 : 1 + ilog2c(m / 2); }
 constexpr int pow3c(int l) { return (l % 3) ? 0 : 1 + pow3c(l / 3); }
 constexpr int ipow3(int p) { return p == 0 ? 1 : 3 * ipow3(p - 1); }
 
-template <int L>
+template <int L, int MAXR = 16>
 struct FftPlan {
+  static_assert(MAXR == 16 || MAXR == 8 || MAXR == 4, "largest radix 16, 8 or 4");
+  static constexpr int lr = ilog2c(MAXR);
   static constexpr int p3 = pow3c(L);
   static constexpr int p2 = ilog2c(L / ipow3(p3));
-  static constexpr int n16 = p2 / 4;
-  static constexpr int rem = p2 % 4;  // 3: one radix-8 stage, 2: radix-4, 1: radix-2
+  static constexpr int nbig = p2 / lr;
+  static constexpr int rem = p2 % lr;  // one more stage of radix 2^rem
   static constexpr int nmid = rem ? 1 : 0;
-  static constexpr int nst = n16 + nmid + p3;
+  static constexpr int nst = nbig + nmid + p3;
   static_assert(ipow3(p3) * (1 << p2) == L, "FFT length must be 2^a 3^b");
   static constexpr int radix(int s) {
-    return s < n16 ? 16 : (s < n16 + nmid ? (1 << rem) : 3);
+    return s < nbig ? MAXR : (s < nbig + nmid ? (1 << rem) : 3);
   }
 };
 
@@ -128,45 +132,45 @@ template <int L>
 constexpr int fft_pad_len() { return L + L / 16; }
 __device__ __forceinline__ int fpad(int x) { return x + (x >> 4); }
 
-template <int L>
+template <int L, int MAXR = 16>
 struct TwLayout {
   static constexpr int U = L / 2 + 1;
   static constexpr int off(int S) {
     int o = U, ns = 1;
     for (int s = 0; s < S; ++s) {
-      const int r = FftPlan<L>::radix(s);
+      const int r = FftPlan<L, MAXR>::radix(s);
       if (ns > 1) o += (r - 1) * ns;
       ns *= r;
     }
     return o;
   }
-  static constexpr int total = off(FftPlan<L>::nst);
+  static constexpr int total = off(FftPlan<L, MAXR>::nst);
 };
 
 // Index into the global table exp(-i pi m / L), m < 2L, of LDS table entry e.
-template <int L, int S = 0, int NS = 1>
+template <int L, int MAXR = 16, int S = 0, int NS = 1>
 __device__ __forceinline__ int tw_source(int e) {
-  if constexpr (S >= FftPlan<L>::nst) {
+  if constexpr (S >= FftPlan<L, MAXR>::nst) {
     return 0;
   } else {
-    constexpr int R = FftPlan<L>::radix(S);
-    constexpr int O = TwLayout<L>::off(S);
+    constexpr int R = FftPlan<L, MAXR>::radix(S);
+    constexpr int O = TwLayout<L, MAXR>::off(S);
     if (NS > 1 && e >= O && e < O + (R - 1) * NS) {
       const int q = e - O, r = 1 + q / NS, k = q % NS;
       return ((2 * L) / (NS * R)) * r * k;
     }
-    return tw_source<L, S + 1, NS * R>(e);
+    return tw_source<L, MAXR, S + 1, NS * R>(e);
   }
 }
 
 // One Stockham stage S on COUNT transforms of length L stored back to back in buf.
-template <typename T, int L, int S, int R, int NS, int COUNT, int NT>
+template <typename T, int L, int MAXR, int S, int R, int NS, int COUNT, int NT>
 __device__ __forceinline__ void fft_stage(c2<T>* buf, const c2<T>* __restrict__ tws, int tid) {
   constexpr int LR = L / R;
   constexpr int NB = COUNT * LR;
   constexpr int PER = (NB + NT - 1) / NT;
   constexpr int PL = fft_pad_len<L>();
-  constexpr int TO = TwLayout<L>::off(S);
+  constexpr int TO = TwLayout<L, MAXR>::off(S);
   c2<T> v[PER][R];
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
@@ -199,21 +203,21 @@ __device__ __forceinline__ void fft_stage(c2<T>* buf, const c2<T>* __restrict__ 
   __syncthreads();
 }
 
-template <typename T, int L, int S, int NS, int COUNT, int NT>
+template <typename T, int L, int MAXR, int S, int NS, int COUNT, int NT>
 __device__ __forceinline__ void fft_run(c2<T>* buf, const c2<T>* __restrict__ tws, int tid) {
-  if constexpr (S < FftPlan<L>::nst) {
-    constexpr int R = FftPlan<L>::radix(S);
-    fft_stage<T, L, S, R, NS, COUNT, NT>(buf, tws, tid);
-    fft_run<T, L, S + 1, NS * R, COUNT, NT>(buf, tws, tid);
+  if constexpr (S < FftPlan<L, MAXR>::nst) {
+    constexpr int R = FftPlan<L, MAXR>::radix(S);
+    fft_stage<T, L, MAXR, S, R, NS, COUNT, NT>(buf, tws, tid);
+    fft_run<T, L, MAXR, S + 1, NS * R, COUNT, NT>(buf, tws, tid);
   }
 }
 
 // Forward complex FFT (e^{-2 pi i m k / L}) of COUNT sequences in LDS (padded layout,
 // natural order); tws is the LDS table described above.  Requires a workgroup barrier
 // before (inputs written) and leaves one after.
-template <typename T, int L, int COUNT, int NT>
+template <typename T, int L, int COUNT, int NT, int MAXR = 16>
 __device__ __forceinline__ void fft_lds(c2<T>* buf, const c2<T>* __restrict__ tws, int tid) {
-  fft_run<T, L, 0, 1, COUNT, NT>(buf, tws, tid);
+  fft_run<T, L, MAXR, 0, 1, COUNT, NT>(buf, tws, tid);
 }
 
 // Place x_j (j = 1 .. n-1) of one sequence into its packed odd extension w.

@@ -1,0 +1,614 @@
+#pragma once
+// Flow kernels of one level (templates; instantiated by ib_flow.hip and ib_flow_tuned.hip): explicit right-hand side fused with the row sine
+// transform, the column transform + spectral solve, the inverse row transform, the
+// nested-level boundary rings, and a plain row transform for sparse sources.
+//
+// Per level g the predictor solves (Sec. 2.3 eq. (16), Appendix A r^f)
+//   (I + a L) L s_{n+1} = gamma_n - a L gamma_n + dt (3/2 C^T N_n - 1/2 C^T N_{n-1})
+//                         + a B(gamma_ring_{n+1}) + (I + a L) B(s_ring_{n+1}),
+// L = C^T C (5-point), a = dt / (2 Re h_g^2), B(.) = ring values adjacent to an
+// interior vertex.  (I + a L) L is diagonal in the 2-D DST-I basis (Sec. 3.2.1), so
+// the solve is row DST -> column DST, scale, inverse column DST -> inverse row DST.
+// It is split into its two factors, both formed from one spectral right-hand side:
+//   gamma_{n+1} = (I + a L)^{-1} [rhs without the s ring]           (gamma^ = r^/(1 + a lam))
+//   s_{n+1}     = L^{-1} [gamma_{n+1} + B(s_ring_{n+1})]            (s^ = (gamma^ + B^)/lam)
+// so the circulation state never passes through the large streamfunction values
+// (differencing s would lose about log10((n/pi)^2) digits in single precision), and
+// B(s_ring)^ is a sum of four outer products of 1-D edge transforms.
+#include "ib_internal.hpp"
+#include "ib_fft.hpp"
+
+namespace ib {
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
+  return p[(size_t)j * pitch + i];
+}
+
+// Where the circulation seen by the stencil at vertex (i, j), 0 <= i, j <= n, lives:
+// boundary ring, coarsification on read (the finer level's circulation at the
+// coincident vertex, scaled by (h_coarse / h_fine)^2 = 4) or the level's own interior.
+// Returned as pointer, index and scale (selects only), so that the caller can issue all
+// of its loads before it uses any of them.
+template <typename T>
+__device__ __forceinline__ const T* gamma_src(const RhsArgs<T>& a, int i, int j, int& idx, T& sc) {
+  const int n = a.n;
+  const T* p = a.g;
+  idx = (j - 1) * a.pg + (i - 1);
+  sc = T(1);
+  if (a.gf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
+    p = a.gf;
+    idx = (2 * j - n / 2 - 1) * a.pgf + (2 * i - n / 2 - 1);
+    sc = T(4);
+  }
+  if (i == n) { p = a.gring; idx = RING_R * (n + 1) + j; sc = T(1); }
+  if (i == 0) { p = a.gring; idx = RING_L * (n + 1) + j; sc = T(1); }
+  if (j == n) { p = a.gring; idx = RING_T * (n + 1) + i; sc = T(1); }
+  if (j == 0) { p = a.gring; idx = RING_B * (n + 1) + i; sc = T(1); }
+  return p;
+}
+
+// Build the LDS twiddle table (layout TwLayout<N, MAXR>) from the global table
+// exp(-i pi m / N), m < 2N; all loads of a thread in flight at once.
+template <typename T, int N, int NT, int MAXR = 16>
+__device__ __forceinline__ void load_table(c2<T>* stw, const c2<T>* __restrict__ tw, int tid) {
+  constexpr int TOT = TwLayout<N, MAXR>::total;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  c2<T> v[PER];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = min(tid + b * NT, TOT - 1);  // clamped: every lane loads, no branch
+    v[b] = tw[e < TwLayout<N, MAXR>::U ? e : tw_source<N, MAXR>(e)];
+  }
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = tid + b * NT;
+    if (e < TOT) stw[e] = v[b];
+  }
+}
+
+// Sum of the new boundary-ring values adjacent to interior vertex (i, j).
+template <typename T>
+__device__ __forceinline__ T ring_adj(const T* ring, int n, int i, int j) {
+  T v = T(0);
+  if (i == 1) v += ring[RING_L * (n + 1) + j];
+  if (i == n - 1) v += ring[RING_R * (n + 1) + j];
+  if (j == 1) v += ring[RING_B * (n + 1) + i];
+  if (j == n - 1) v += ring[RING_T * (n + 1) + i];
+  return v;
+}
+
+// Right-hand side at interior vertex (i, j) from staged rows: ss / sg hold s and gamma
+// of rows j-1, j, j+1 (each W wide, column index = i); hprev_in is C^T N_{n-1} (unused
+// on the first step, which takes the new value); ring_term the adjacent new ring
+// circulation; writes C^T N_n to the history.
+template <typename T, int W>
+__device__ __forceinline__ T rhs_staged(const RhsArgs<T>& a, const T* ss, const T* sg, int i, int j,
+                                        T hprev_in, bool has_prev, T ring_term) {
+  const T* sm = ss;          // row j-1
+  const T* sp = ss + 2 * W;  // row j+1
+  const T* gm = sg;
+  const T* g0r = sg + W;
+  const T* gp = sg + 2 * W;
+  const T g0 = g0r[i];
+  const T gE = g0r[i + 1], gW = g0r[i - 1];
+  const T gN = gp[i], gS = gm[i];
+  // vertex-averaged fluxes (total flux, free stream included)
+  const T uE = T(0.5) * (sp[i + 1] - sm[i + 1]) + a.ux;
+  const T uW = T(0.5) * (sp[i - 1] - sm[i - 1]) + a.ux;
+  const T vN = T(0.5) * (sp[i - 1] - sp[i + 1]) + a.uy;
+  const T vS = T(0.5) * (sm[i - 1] - sm[i + 1]) + a.uy;
+  // C^T N with N = (vbar gamma, -ubar gamma) / h^2 averaged onto the faces
+  const T ctn = a.cn * ((uE * gE - uW * gW) + (vN * gN - vS * gS));
+  a.hist_out[(size_t)(j - 1) * a.ph + (i - 1)] = ctn;
+  const T hprev = has_prev ? hprev_in : ctn;
+  const T lap = T(4) * g0 - gE - gW - gN - gS;
+  return g0 - a.alpha * lap + a.dt * (T(1.5) * ctn - T(0.5) * hprev) + a.alpha * ring_term;
+}
+
+// Explicit right-hand side of ROWS interior rows fused with their row DST.  The rows
+// j-1 .. j+ROWS of s and gamma are staged in LDS (every load of a thread in flight at
+// once); the staging area is then reused as the transform buffer.
+template <typename T, int N, int ROWS, int NT, int DST, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __restrict__ tw,
+                                                   int nblocks) {
+  constexpr int W = N + 1;           // staged row width, ring columns included
+  constexpr int SR = ROWS + 2;       // staged rows j0-1 .. j0+ROWS
+  constexpr int STG = 2 * SR * W;    // s and gamma, in T units
+  constexpr int BUFT = 2 * ROWS * fft_pad_len<N>(); // transform buffer, in T units
+  constexpr int UNI = (STG > BUFT ? STG : BUFT) / 2 + 1;
+  __shared__ c2<T> uni[UNI];
+  __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
+  __shared__ T sring[4][W];          // new circulation ring: bottom, top, left, right
+  static_assert(sizeof(uni) + sizeof(stw) + sizeof(sring) <= 160 * 1024, "LDS");
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const int j0 = 1 + blk * ROWS;
+  T* ss = reinterpret_cast<T*>(uni);
+  T* sg = ss + SR * W;
+  constexpr int NPT = ROWS * (N - 1);
+  constexpr int PP = (NPT + NT - 1) / NT;
+  T hp[PP];
+  {
+    // every load of this thread is issued before any is used; indices are clamped to
+    // valid memory and the unused values are dropped afterwards
+    constexpr int CNT = SR * W;
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T vs[PER], vg[PER], gsc[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int r = e / W, i = e % W;
+      const int j = min(j0 - 1 + r, N);
+      int gi;
+      const T* gp = gamma_src(a, i, j, gi, gsc[b]);
+      vs[b] = a.s[j * a.ps + i];  // indices fit in 32 bits (n <= 1024)
+      vg[b] = gp[gi];
+    }
+#pragma unroll
+    for (int b = 0; b < PP; ++b) {
+      const int e = tid + b * NT;
+      const int t = e / (N - 1), i = 1 + e % (N - 1), j = min(j0 + t, N - 1);
+      hp[b] = a.hist_in != nullptr ? a.hist_in[(j - 1) * a.ph + (i - 1)] : T(0);
+    }
+    constexpr int PR = (4 * W + NT - 1) / NT;
+    T rv0[PR];
+    if (a.gring_new != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PR; ++b) rv0[b] = a.gring_new[min(tid + b * NT, 4 * W - 1)];
+    }
+    load_table<T, N, NT, MAXR>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) {
+        const bool ok = j0 - 1 + e / W <= N;
+        ss[e] = ok ? vs[b] : T(0);
+        sg[e] = ok ? gsc[b] * vg[b] : T(0);
+      }
+    }
+    if (a.gring_new != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PR; ++b) {
+        const int e = tid + b * NT;
+        if (e < 4 * W) (&sring[0][0])[e] = rv0[b];
+      }
+    }
+  }
+  __syncthreads();
+  T rv[PP];
+#pragma unroll
+  for (int b = 0; b < PP; ++b) {
+    const int e = tid + b * NT;
+    const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
+    rv[b] = T(0);
+    if (e < NPT && j <= N - 1) {
+      T ring = T(0);
+      if (a.gring_new != nullptr) {
+        if (i == 1) ring += sring[RING_L][j];
+        if (i == N - 1) ring += sring[RING_R][j];
+        if (j == 1) ring += sring[RING_B][i];
+        if (j == N - 1) ring += sring[RING_T][i];
+      }
+      rv[b] = rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr, ring);
+    }
+  }
+  if constexpr (DST == 0) {
+    // right-hand side only (the transforms run elsewhere)
+#pragma unroll
+    for (int b = 0; b < PP; ++b) {
+      const int e = tid + b * NT;
+      const int j = j0 + e / (N - 1);
+      if (e < NPT && j <= N - 1) a.out[(size_t)(j - 1) * a.po + e % (N - 1)] = rv[b];
+    }
+    return;
+  }
+  __syncthreads();  // the staging area becomes the transform buffer
+  c2<T>* buf = uni;
+#pragma unroll
+  for (int b = 0; b < PP; ++b) {
+    const int e = tid + b * NT;
+    if (e < NPT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), rv[b]);
+  }
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
+  __syncthreads();
+  fft_lds<T, N, ROWS, NT, MAXR>(buf, stw, tid);
+  for (int e = tid; e < ROWS * (N / 2); e += NT) {
+    const int t = e / (N / 2), k = 1 + e % (N / 2);
+    const int j = j0 + t;
+    if (j > N - 1) continue;
+    T xk, xnk;
+    dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
+    T* o = a.out + (size_t)(j - 1) * a.po;
+    o[k - 1] = xk;
+    if (k != N / 2) o[N - k - 1] = xnk;
+  }
+}
+
+// Plain row DST of rows [r0, r1] (1-based interior rows) of a real array; batched
+// over blockIdx.y with the given strides.
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __restrict__ tw,
+                                               int nblocks) {
+  __shared__ c2<T> buf[ROWS * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  const int j0 = a.r0 + blk * ROWS;
+  {
+    constexpr int CNT = ROWS * (N - 1);
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
+      v[b] = (e < CNT && j <= a.r1) ? in[(size_t)(j - 1) * a.pi + (i - 1)] : T(0);
+    }
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
+    }
+  }
+  for (int t = tid; t < ROWS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
+  __syncthreads();
+  fft_lds<T, N, ROWS, NT>(buf, stw, tid);
+  for (int e = tid; e < ROWS * (N / 2); e += NT) {
+    const int t = e / (N / 2), k = 1 + e % (N / 2);
+    const int j = j0 + t;
+    if (j > a.r1) continue;
+    T xk, xnk;
+    dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
+    T* o = out + (size_t)(j - 1) * a.po;
+    o[k - 1] = xk;
+    if (k != N / 2) o[N - k - 1] = xnk;
+  }
+}
+
+// Column DST, spectral scale scale / (lam (1 + alpha lam)), inverse column DST.
+// Reads input rows [r0, r1] (others are zero) and writes
+//   out = (accumulate ? out : 0) + result
+// for every row; input and output may alias when accumulate == 0.
+template <typename T, int N, int CW, int NT, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
+                                                  const T* __restrict__ lam, int nblocks) {
+  __shared__ c2<T> buf[CW * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
+  __shared__ T slam[N];
+  __shared__ T slift[2 * N];    // edge transforms of the left and right ring columns
+  __shared__ T slift01[2 * CW]; // bottom and top edge transforms at this block's columns
+  static_assert(sizeof(buf) + sizeof(stw) + sizeof(slam) + sizeof(slift) + sizeof(slift01) <=
+                    160 * 1024, "LDS");
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const int k0 = blk * CW;
+  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  {
+    constexpr int CNT = (N - 1) * CW;
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+    const int rf = a.rfirst != nullptr ? a.rfirst[blockIdx.y] : 0;
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int r = e / CW, col = k0 + e % CW;
+      bool ok = e < CNT && col < N - 1;
+      long idx;
+      if (a.rfirst != nullptr) {
+        const int q = r + 1 - rf;
+        ok = ok && q >= 0 && q < a.rcount;
+        idx = (long)q * a.pi + col;
+      } else {
+        ok = ok && r + 1 >= a.r0 && r + 1 <= a.r1;
+        idx = (long)r * a.pi + col;
+      }
+      v[b] = ok ? in[idx] : T(0);
+    }
+    load_table<T, N, NT, MAXR>(stw, tw, tid);
+    constexpr int PL = (N - 1 + NT - 1) / NT;
+    T lv[PL];
+#pragma unroll
+    for (int b = 0; b < PL; ++b) lv[b] = tid + b * NT < N - 1 ? lam[tid + b * NT] : T(1);
+    constexpr int PF = (2 * (N - 1) + NT - 1) / NT;
+    T fv[PF];
+    T f01 = T(0);
+    if (a.lift != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PF; ++b) {
+        const int e = tid + b * NT;
+        fv[b] = e < 2 * (N - 1) ? a.lift[2 * (N - 1) + e] : T(0);
+      }
+      if (tid < 2 * CW) {
+        const int col = k0 + tid % CW;
+        f01 = col < N - 1 ? a.lift[(tid / CW) * (N - 1) + col] : T(0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e % CW) * fft_pad_len<N>(), e / CW + 1, v[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < PL; ++b)
+      if (tid + b * NT < N) slam[tid + b * NT] = lv[b];
+    if (a.lift != nullptr) {
+#pragma unroll
+      for (int b = 0; b < PF; ++b)
+        if (tid + b * NT < 2 * (N - 1)) slift[tid + b * NT] = fv[b];
+      if (tid < 2 * CW) slift01[tid] = f01;
+    }
+  }
+  for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * fft_pad_len<N>());
+  __syncthreads();
+  fft_lds<T, N, CW, NT, MAXR>(buf, stw, tid);
+  constexpr int NP = CW * (N / 2);
+  constexpr int PER = (NP + NT - 1) / NT;
+  T xa[PER], xb[PER];   // forward column transform, raw
+  T la[PER], lb[PER];   // lam of each pair
+  T ea[PER], eb[PER];   // 1 + alpha lam
+  T fa[PER], fb[PER];   // spectral B(s_ring) of each pair
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int e = tid + b * NT;
+    if (e < NP) {
+      const int c = e % CW, l = 1 + e / CW;
+      const int col = k0 + c;
+      dst_unpack<T, N>(buf + c * fft_pad_len<N>(), stw, l, xa[b], xb[b]);
+      const T lk = (col < N - 1) ? slam[col] : T(1);
+      const T l1 = lk + slam[l - 1];
+      const T l2 = lk + slam[N - l - 1];
+      la[b] = l1;
+      lb[b] = l2;
+      ea[b] = T(1) + a.alpha * l1;
+      eb[b] = T(1) + a.alpha * l2;
+      fa[b] = T(0);
+      fb[b] = T(0);
+      if (a.lift != nullptr && col < N - 1) {
+        // sum_{i,j} B(s_ring)_{ij} sin(pi i k / n) sin(pi j l / n) over the four edges
+        const int k = col + 1;
+        const T sk = tw_sin<T, N>(stw, k), sl = tw_sin<T, N>(stw, l);  // sin(pi k/n), sin(pi l/n)
+        const T pk = (k & 1) ? T(1) : T(-1);     // (-1)^(k+1)
+        const T pl = (l & 1) ? T(1) : T(-1);     // (-1)^(l+1) = (-1)^(n-l+1)
+        const T eb_k = slift01[c], et_k = slift01[CW + c];
+        fa[b] = eb_k * sl + et_k * sl * pl + sk * slift[l - 1] + sk * pk * slift[(N - 1) + l - 1];
+        fb[b] = eb_k * sl + et_k * sl * pl + sk * slift[N - l - 1] +
+                sk * pk * slift[(N - 1) + N - l - 1];
+      }
+    }
+  }
+  const int nout = a.out2 != nullptr ? 2 : 1;
+  for (int o = 0; o < nout; ++o) {
+    T* dst = (o == 0 ? a.out : a.out2) + (size_t)blockIdx.y * a.bso;
+    // previous values of the accumulated outputs, fetched while the transform runs
+    T pa[PER], pb[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int c = e % CW, j = 1 + e / CW, col = k0 + c, j2 = N - j;
+      const bool ok = a.accumulate && e < NP && col < N - 1;
+      pa[b] = (ok && j >= a.w0 && j <= a.w1) ? dst[(size_t)(j - 1) * a.po + col] : T(0);
+      pb[b] = (ok && j != N / 2 && j2 >= a.w0 && j2 <= a.w1) ? dst[(size_t)(j2 - 1) * a.po + col]
+                                                              : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < NP) {
+        const int c = e % CW, l = 1 + e / CW;
+        const T ga = xa[b] / ea[b], gb = xb[b] / eb[b];
+        const T va = o == 0 ? (ga + fa[b]) * (a.scale / la[b]) : ga * a.scale;
+        const T vb = o == 0 ? (gb + fb[b]) * (a.scale / lb[b]) : gb * a.scale;
+        dst_pack<T, N>(buf + c * fft_pad_len<N>(), l, va);
+        if (l != N / 2) dst_pack<T, N>(buf + c * fft_pad_len<N>(), N - l, vb);
+      }
+    }
+    for (int c = tid; c < CW; c += NT) dst_pack_zeros<T, N>(buf + c * fft_pad_len<N>());
+    __syncthreads();
+    fft_lds<T, N, CW, NT, MAXR>(buf, stw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e >= NP) continue;
+      const int c = e % CW, j = 1 + e / CW;
+      const int col = k0 + c;
+      if (col >= N - 1) continue;
+      T yk, ynk;
+      dst_unpack<T, N>(buf + c * fft_pad_len<N>(), stw, j, yk, ynk);
+      if (j >= a.w0 && j <= a.w1) dst[(size_t)(j - 1) * a.po + col] = pa[b] + yk;
+      const int j2 = N - j;
+      if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1) dst[(size_t)(j2 - 1) * a.po + col] = pb[b] + ynk;
+    }
+  }
+}
+
+// Inverse row DST of rows [r0, r1] into the interior of a full (n+1)-row array; the
+// ring columns (and, when ring rows are requested, rows 0 and n) come from `ring`
+// (zero when null).  With interior_out the output is an (n-1)-row interior array.
+// With in2/out2 set the same rows of a second array are transformed in the same
+// workgroup into the interior array out2 (the level's circulation).
+template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __restrict__ tw,
+                                                 const T* __restrict__ ring, int ring_rows,
+                                                 int nblocks) {
+  constexpr int NS = ROWS * (DUAL ? 2 : 1);
+  __shared__ c2<T> buf[NS * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
+  static_assert(sizeof(buf) + sizeof(stw) <= 160 * 1024, "LDS");
+  const int blk = xcd_block(blockIdx.x, nblocks);
+  if (blk < 0) return;
+  const int tid = threadIdx.x;
+  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  const int j0 = a.r0 + blk * ROWS;
+  {
+    constexpr int CNT = NS * (N - 1);
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      const int t = e / (N - 1), k = 1 + e % (N - 1), j = j0 + (t % ROWS);
+      const T* src = t < ROWS ? in : a.in2;
+      v[b] = (e < CNT && j <= a.r1) ? src[(size_t)(j - 1) * a.pi + (k - 1)] : T(0);
+    }
+    load_table<T, N, NT, MAXR>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
+    }
+  }
+  for (int t = tid; t < NS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
+  __syncthreads();
+  fft_lds<T, N, NS, NT, MAXR>(buf, stw, tid);
+  for (int e = tid; e < NS * (N / 2); e += NT) {
+    const int t = e / (N / 2), k = 1 + e % (N / 2);
+    const int j = j0 + (t % ROWS);
+    if (j > a.r1) continue;
+    T xk, xnk;
+    dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
+    if (t >= ROWS) {
+      T* o = a.out2 + (size_t)(j - 1) * a.po;
+      o[k - 1] = xk;
+      if (k != N / 2) o[N - k - 1] = xnk;
+    } else if (a.interior_out) {
+      T* o = out + (size_t)(j - 1) * a.po;
+      o[k - 1] = xk;
+      if (k != N / 2) o[N - k - 1] = xnk;
+    } else {
+      T* o = out + (size_t)j * a.po;
+      o[k] = xk;
+      if (k != N / 2) o[N - k] = xnk;
+    }
+  }
+  if (a.interior_out) return;
+  for (int t = tid; t < ROWS; t += NT) {
+    const int j = j0 + t;
+    if (j > a.r1) continue;
+    T* o = out + (size_t)j * a.po;
+    o[0] = ring ? ring[RING_L * (N + 1) + j] : T(0);
+    o[N] = ring ? ring[RING_R * (N + 1) + j] : T(0);
+  }
+  if (ring_rows && blk == 0) {
+    for (int i = tid; i <= N; i += NT) {
+      out[i] = ring ? ring[RING_B * (N + 1) + i] : T(0);
+      out[(size_t)N * a.po + i] = ring ? ring[RING_T * (N + 1) + i] : T(0);
+    }
+  }
+}
+
+// New boundary rings of a fine level from the next coarser level's streamfunction:
+// coincident vertices are copied, midpoints use the cubic (-1, 9, 9, -1)/16 along the
+// edge; the circulation ring is the same interpolation of the coarse C^T C s, scaled
+// by 1/4 (gamma = h^2 omega and h halves).
+template <typename T>
+__device__ __forceinline__ T coarse_val(const T* sc, int p, int edge, int line, int I, bool gam) {
+  const int j = (edge < 2) ? line : I;
+  const int i = (edge < 2) ? I : line;
+  if (!gam) return sc[(size_t)j * p + i];
+  return T(4) * sc[(size_t)j * p + i] - sc[(size_t)j * p + i + 1] - sc[(size_t)j * p + i - 1] -
+         sc[(size_t)(j + 1) * p + i] - sc[(size_t)(j - 1) * p + i];
+}
+
+template <typename T>
+__global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gring) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 4 * (n + 1)) return;
+  const int edge = e / (n + 1), idx = e % (n + 1);
+  const int q = n / 2;
+  const int line = (edge == RING_B || edge == RING_L) ? n / 4 : (3 * n) / 4;
+  T sv, gv;
+  if (((idx + q) & 1) == 0) {
+    const int I = (idx + q) / 2;
+    sv = coarse_val(sc, psc, edge, line, I, false);
+    gv = coarse_val(sc, psc, edge, line, I, true);
+  } else {
+    const int c = (idx + q - 1) / 2;
+    sv = (-coarse_val(sc, psc, edge, line, c - 1, false) +
+          T(9) * coarse_val(sc, psc, edge, line, c, false) +
+          T(9) * coarse_val(sc, psc, edge, line, c + 1, false) -
+          coarse_val(sc, psc, edge, line, c + 2, false)) / T(16);
+    gv = (-coarse_val(sc, psc, edge, line, c - 1, true) +
+          T(9) * coarse_val(sc, psc, edge, line, c, true) +
+          T(9) * coarse_val(sc, psc, edge, line, c + 1, true) -
+          coarse_val(sc, psc, edge, line, c + 2, true)) / T(16);
+  }
+  sring[e] = sv;
+  gring[e] = T(0.25) * gv;
+}
+
+// Unnormalised 1-D DSTs of the four edges of a streamfunction ring, as they appear in
+// B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top s(i, n) on row
+// n-1, left s(0, j) on column 1, right s(n, j) on column n-1.  One workgroup.
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
+                                                      const c2<T>* __restrict__ tw, T* lift) {
+  __shared__ c2<T> buf[4 * fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
+  const int tid = threadIdx.x;
+  {
+    constexpr int CNT = 4 * (N - 1);
+    constexpr int PER = (CNT + NT - 1) / NT;
+    T v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      v[b] = e < CNT ? sring[(e / (N - 1)) * (N + 1) + 1 + e % (N - 1)] : T(0);
+    }
+    load_table<T, N, NT>(stw, tw, tid);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int e = tid + b * NT;
+      if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
+    }
+  }
+  for (int edge = tid; edge < 4; edge += NT) dst_pack_zeros<T, N>(buf + edge * fft_pad_len<N>());
+  __syncthreads();
+  fft_lds<T, N, 4, NT>(buf, stw, tid);
+  for (int e = tid; e < 4 * (N / 2); e += NT) {
+    const int edge = e / (N / 2), k = 1 + e % (N / 2);
+    T xk, xnk;
+    dst_unpack<T, N>(buf + edge * fft_pad_len<N>(), stw, k, xk, xnk);
+    lift[edge * (N - 1) + k - 1] = xk;
+    if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
+  }
+}
+
+// ------------------------------------------------ launches of one kernel configuration
+
+template <typename T, int N, int ROWS, int NT, int DST, int MAXR>
+hipError_t launch_rhs_cfg(const RhsArgs<T>& a, const c2<T>* t, hipStream_t st) {
+  const int nb = (a.n - 1 + ROWS - 1) / ROWS;
+  hipLaunchKernelGGL((k_rhs_rowdst<T, N, ROWS, NT, DST, MAXR>), dim3(xcd_grid(nb)), dim3(NT), 0, st,
+                     a, t, nb);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int CW, int NT, int MAXR>
+hipError_t launch_col_cfg(const ColArgs<T>& a, int n, int batch, const c2<T>* t, const T* l,
+                          hipStream_t st) {
+  const int nb = (n - 1 + CW - 1) / CW;
+  hipLaunchKernelGGL((k_col_solve<T, N, CW, NT, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st,
+                     a, t, l, nb);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR>
+hipError_t launch_idst_cfg(const RowArgs<T>& a, int batch, const c2<T>* t, const T* ring,
+                           int ring_rows, hipStream_t st) {
+  const int nb = (a.r1 - a.r0 + 1 + ROWS - 1) / ROWS;
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_row_idst<T, N, ROWS, NT, DUAL, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT),
+                     0, st, a, t, ring, ring_rows, nb);
+  return hipGetLastError();
+}
+
+}  // namespace ib

@@ -18,6 +18,7 @@ struct RhsArgs {
   T* out;              // row-transformed right-hand side, (n-1) rows x po
   int n, ps, pg, pgf, ph, po;
   T alpha, dt, ux, uy, cn;  // cn = -1 / (2 h^2); ux, uy = free-stream flux u_inf h
+  int var;             // kernel configuration (ROW_VARIANTS; 0 = default)
 };
 
 // Row-wise transform of rows [r0, r1] (1-based interior rows).
@@ -32,6 +33,7 @@ struct RowArgs {
                     // full (n+1)-row array with its ring
   const T* in2;     // inverse transform: a second array transformed alongside `in`
   T* out2;          //   into the interior array out2 (pitch po); batch 1 only
+  int var;          // inverse transform with in2: kernel configuration (ROW_VARIANTS)
 };
 
 // Column transform + spectral scale + inverse column transform.
@@ -50,7 +52,31 @@ struct ColArgs {
   const int* rfirst; // if set: slot b's input holds rows rfirst[b] .. rfirst[b] + rcount - 1
   int rcount;        //   compactly (row rfirst[b] at input row 0)
   int w0, w1;        // output rows written (1-based); others untouched
+  int var;           // kernel configuration (COL_VARIANTS; 0 = default)
 };
+
+// Kernel configurations of the row and column sine-transform kernels, selected per grid
+// size by measurement (single precision, n >= FLOW_TUNE_MIN_N; otherwise entry 0).
+// Rows: rows per workgroup, threads, largest radix; columns: columns per workgroup,
+// threads, largest radix.
+struct FlowVariant {
+  int width, nt, maxr;
+};
+constexpr int FLOW_VARIANTS = 8;
+constexpr int FLOW_TUNE_MIN_N = 256;
+constexpr FlowVariant ROW_VARIANTS[FLOW_VARIANTS] = {
+    {2, 256, 16}, {2, 256, 8}, {2, 512, 16}, {2, 512, 8},
+    {2, 512, 4},  {4, 512, 8}, {4, 1024, 8}, {4, 1024, 16}};
+constexpr FlowVariant COL_VARIANTS[FLOW_VARIANTS] = {
+    {4, 256, 16}, {4, 256, 8}, {2, 256, 4},  {4, 512, 16},
+    {4, 512, 8},  {4, 1024, 16}, {8, 512, 16}, {8, 1024, 16}};
+bool flow_variant_available(int n, int fp64);
+// Single-precision launches of configuration var (1 .. FLOW_VARIANTS-1), n >= FLOW_TUNE_MIN_N.
+hipError_t launch_rhs_rowdst_var(const RhsArgs<float>& a, const void* tw, hipStream_t st);
+hipError_t launch_col_solve_var(const ColArgs<float>& a, int n, int batch, const void* tw,
+                                const void* lam, hipStream_t st);
+hipError_t launch_row_idst_var(const RowArgs<float>& a, int n, int batch, const void* tw,
+                               const float* ring, int ring_rows, hipStream_t st);
 
 // Sine transform as a BF16-split matrix product (ib_gemm.hip): C = S X (mode 0) or
 // C = X S (mode 1), S = shi + slo the (kpad x kpad, zero padded) DST-I matrix of size nv,

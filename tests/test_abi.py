@@ -125,3 +125,37 @@ def test_operator_import_validates_its_input(lib):
     assert lib.ib_export_operator(h, None, 0, ctypes.byref(used)) == -2  # nothing built yet
     assert lib.ib_set_operator_cache(-1) == -1
     assert lib.ib_destroy(h) == 0
+
+
+def test_flow_variant_table_and_forcing(lib):
+    """The transform-kernel configurations are listed, and forcing one is validated: only
+    single precision at n >= 256 has alternatives to configuration 0."""
+    from paper_2103_06415_amd import binding
+    for kind in (0, 1):
+        seen = set()
+        for v in range(binding.FLOW_VARIANTS):
+            w, t, r = binding.flow_variant_info(kind, v)
+            assert w >= 1 and t in (64, 128, 256, 512, 1024) and r in (4, 8, 16)
+            assert t % 64 == 0 and t >= 2 * w
+            seen.add((w, t, r))
+        assert len(seen) == binding.FLOW_VARIANTS  # all distinct
+    w, t, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.ib_flow_variant_info(2, 0, ctypes.byref(w), ctypes.byref(t), ctypes.byref(r)) == -1
+    assert lib.ib_flow_variant_info(0, 8, ctypes.byref(w), ctypes.byref(t), ctypes.byref(r)) == -1
+    for n, prec, ok in ((256, binding.IB_FP32_FLOW, True), (128, binding.IB_FP32_FLOW, False),
+                        (256, binding.IB_FP64, False)):
+        cfg = _config(binding, n, 1)
+        cfg.precision = prec
+        h = ctypes.c_void_p()
+        assert lib.ib_create(ctypes.byref(cfg), None, None, ctypes.byref(h)) == 0
+        assert lib.ib_set_flow_variants(h, 0, 0, 0) == 0  # defaults are always allowed
+        assert lib.ib_set_flow_variants(h, 1, 2, 3) == (0 if ok else -1)
+        assert lib.ib_set_flow_variants(h, 0, 8, 0) == -1
+        tun = binding.IbFlowTuning()
+        assert lib.ib_get_flow_tuning(h, ctypes.byref(tun)) == 0
+        if ok:
+            assert (tun.rhs_variant, tun.col_variant, tun.idst_variant) == (1, 2, 3)
+            assert lib.ib_set_flow_variants(h, -1, 5, -1) == 0
+            assert lib.ib_get_flow_tuning(h, ctypes.byref(tun)) == 0
+            assert (tun.rhs_variant, tun.col_variant, tun.idst_variant) == (1, 5, 3)
+        assert lib.ib_destroy(h) == 0

@@ -1,0 +1,85 @@
+"""Every measured configuration of the single-precision transform kernels (rows or columns
+per workgroup, threads, largest FFT radix) against the FP64 oracle, and the measurement
+itself.  The configurations only exist for n >= 256; they change the rounding order of
+the transforms, so each meets the FP32-form bar of 1e-5 (vorticity, relative L2)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.step import Oracle
+
+pytestmark = pytest.mark.gpu
+
+N, LEVELS, STEPS = 256, 2, 3
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _problem():
+    rng = np.random.default_rng(11)
+    flow = W.Flow(n=N, levels=LEVELS, h=3.2 / N, dt=0.2 * 3.2 / N, re=150.0, cx=0.1, cy=-0.05,
+                  u_inf=(1.0, 0.3))
+    x = flow.cx - 0.5 * N * flow.h + flow.h * np.arange(1, N)
+    y = flow.cy - 0.5 * N * flow.h + flow.h * np.arange(1, N)
+    yy, xx = np.meshgrid(y, x, indexing="ij")
+    w = 4.0 * np.exp(-((xx + 0.2) ** 2 + (yy - 0.1) ** 2) / 0.08) + 0.05 * rng.normal(size=xx.shape)
+    return W.Problem("flow", flow, [], vorticity0=[w] + [None] * (LEVELS - 1))
+
+
+@pytest.fixture(scope="module")
+def oracle_vorticity():
+    p = _problem()
+    ora = Oracle(p)
+    for _ in range(STEPS):
+        ora.step()
+    return [ora.vorticity(g) for g in range(LEVELS)]
+
+
+@pytest.mark.parametrize("var", range(8))
+def test_each_configuration_matches_the_oracle(torch_cuda, gpu_lib, oracle_vorticity, var):
+    from paper_2103_06415_amd import binding
+    print(f"flow variants rhs/col/idst = {var}, n={N} levels={LEVELS}", flush=True)
+    s = binding.Solver(_problem(), precision=binding.IB_FP32_FLOW)
+    s.set_flow_variants(var, var, var)
+    s.prepare()
+    t = s.flow_tuning()
+    assert (t["rhs_variant"], t["col_variant"], t["idst_variant"]) == (var, var, var)
+    s.step(STEPS)
+    s.sync()
+    errs = [rel(s.vorticity(g), oracle_vorticity[g]) for g in range(LEVELS)]
+    print(f"  rows {binding.flow_variant_info(0, var)} cols {binding.flow_variant_info(1, var)}:"
+          f" vorticity rel L2 {errs}", flush=True)
+    s.close()
+    assert max(errs) < 1e-5, errs
+
+
+def test_measurement_picks_the_fastest(torch_cuda, gpu_lib, oracle_vorticity):
+    from paper_2103_06415_amd import binding
+    s = binding.Solver(_problem(), precision=binding.IB_FP32_FLOW)
+    s.prepare()
+    t = s.flow_tuning()
+    print(f"  tuning {t}", flush=True)
+    assert t["n"] == N
+    for kind in ("rhs", "col", "idst"):
+        us = t[kind + "_us"]
+        assert all(u > 0 for u in us), (kind, us)
+        assert t[kind + "_variant"] == int(np.argmin(us))
+    s.step(STEPS)
+    s.sync()
+    assert max(rel(s.vorticity(g), oracle_vorticity[g]) for g in range(LEVELS)) < 1e-5
+    # a second solver of the same size reuses the choice without measuring again
+    s2 = binding.Solver(_problem(), precision=binding.IB_FP32_FLOW)
+    s2.prepare()
+    assert s2.flow_tuning() == t
+    s.close()
+    s2.close()
