@@ -48,7 +48,8 @@ def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
 def run(problem, precision, steps, warmup, timing=True):
     import torch
     from paper_2103_06415_amd import binding
-    s = binding.Solver(problem, precision=precision)
+    # a stream of its own: steps on it are recorded once and replayed as HIP graphs
+    s = binding.Solver(problem, precision=precision, stream=torch.cuda.Stream())
     t0 = time.perf_counter()
     s.prepare()
     s.sync()
@@ -279,7 +280,9 @@ def main():
                    "n": n, "levels": levels, "subdomain_nnz": st32["subdomain_nnz"],
                    "newton_iters_max": st32["newton_iters_max"],
                    "schur_refine_sweeps_last": st32["refine_iters"],
-                   "schur_inverse_rebuilds": st32["inverse_rebuilds"]},
+                   "schur_inverse_rebuilds": st32["inverse_rebuilds"],
+                   "graph_launches": st32["graph_launches"],
+                   "fsi_host_resumes": st32["fsi_resumes"]},
         "value_fp64": value64,
         "value_bf16_dst_gemm": value_bf16,
         "kernel_ms_per_step_bf16_dst_gemm": ({k: round(v[1] / args.steps, 5) for k, v in kt_b.items()}

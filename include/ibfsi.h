@@ -108,6 +108,10 @@ typedef struct {
   double refine_residual;    /* relative residual of the last Schur solve */
   int32_t operator_source;   /* offline operator: 0 built, 1 from the cache, 2 imported,
                                 -1 none (no bodies) */
+  int64_t graph_launches;    /* steps replayed from a recorded graph (IB_OPT_GRAPHS) */
+  int64_t graph_captures;    /* graphs recorded */
+  int64_t fsi_resumes;       /* steps whose FSI iterations launched ahead did not suffice
+                                and were continued on the host (IB_OPT_FSI_AHEAD) */
 } ib_stats;
 
 /* Create a solver.  `alloc` may be NULL (hipMalloc); `hip_stream` is a hipStream_t
@@ -184,6 +188,19 @@ ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* laun
                                double* total_ms);
 
 ib_status ib_destroy(ib_solver* s);
+
+/* ---- execution options ----
+ * IB_OPT_FSI_AHEAD (default 1): launch a step's FSI iterations ahead of their convergence
+ *   tests (as many as the last step needed), each followed by a device-side test that stops
+ *   the remaining ones; the host synchronises once per step and continues on its own only
+ *   when they did not suffice.  0: the host tests after every iteration (Algorithm 2 as
+ *   written).  Both give the same results.
+ * IB_OPT_GRAPHS (default 1): with IB_OPT_FSI_AHEAD, record a step's launches once as a HIP
+ *   graph (one per alternation of the ring buffers) and replay it for later steps.
+ * Errors: IB_ERR_ARG for an unknown option or value. */
+#define IB_OPT_FSI_AHEAD 1
+#define IB_OPT_GRAPHS 2
+ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value);
 
 /* ---- measured kernel configurations of the sine transforms ----
  * For single-precision flow and n >= 256, ib_prepare times IB_FLOW_VARIANTS configurations

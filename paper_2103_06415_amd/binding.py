@@ -57,10 +57,12 @@ class IbStats(ctypes.Structure):
         ("newton_delta", c_double), ("subdomain_points", c_int64), ("subdomain_nnz", c_int64),
         ("prepare_seconds", c_double), ("refine_iters", c_int32), ("inverse_rebuilds", c_int32),
         ("refine_residual", c_double), ("operator_source", c_int32),
+        ("graph_launches", c_int64), ("graph_captures", c_int64), ("fsi_resumes", c_int64),
     ]
 
 
 FLOW_VARIANTS = 8
+IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS = 1, 2
 
 
 class IbFlowTuning(ctypes.Structure):
@@ -113,6 +115,7 @@ _SIGS = {
     "ib_server_info": (c_int32, [c_void_p, c_int64, POINTER(IbRequestInfo)]),
     "ib_server_destroy": (c_int32, [c_void_p]),
     "ib_get_flow_tuning": (c_int32, [c_void_p, POINTER(IbFlowTuning)]),
+    "ib_set_option": (c_int32, [c_void_p, c_int32, c_int64]),
     "ib_set_flow_variants": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "ib_flow_variant_info": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
                                        POINTER(c_int32)]),
@@ -302,6 +305,9 @@ class Solver:
         return {"n": t.n, "rhs_variant": t.rhs_variant, "col_variant": t.col_variant,
                 "idst_variant": t.idst_variant, "rhs_us": list(t.rhs_us),
                 "col_us": list(t.col_us), "idst_us": list(t.idst_us)}
+
+    def set_option(self, option, value):
+        _check(self.lib.ib_set_option(self.handle, option, int(value)), "ib_set_option")
 
     def set_flow_variants(self, rhs=-1, col=-1, idst=-1):
         _check(self.lib.ib_set_flow_variants(self.handle, rhs, col, idst), "ib_set_flow_variants")

@@ -18,6 +18,16 @@
 
 namespace ib {
 
+// FSI iteration kernels: skip when the step's iterations have converged or were stopped.
+__device__ __forceinline__ bool iter_gated(const int* gate) {
+  return gate != nullptr && (gate[0] != 0 || gate[1] != 0);
+}
+// Kernels after convergence: run only when the iterations converged and were not stopped.
+__device__ __forceinline__ bool post_gated(const int* gate) {
+  return gate != nullptr && (gate[0] != 1 || gate[1] != 0);
+}
+
+
 __device__ __forceinline__ double roma3(double r) {
   const double a = fabs(r);
   if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
@@ -112,6 +122,7 @@ __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, do
 // Body operator rows and u* for every point; one thread per point.
 template <typename T>
 __global__ void k_body_ops(FsiArgs a) {
+  if (iter_gated(a.gate)) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.npts) return;
   int bi = 0;
@@ -224,6 +235,7 @@ __device__ __forceinline__ int row_body(const FsiArgs& a, int row) {
 constexpr int SCHUR_NT = 256;
 constexpr int SCHUR_CPT = 8;  // columns per thread: nf <= 2048
 __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a) {
+  if (iter_gated(a.gate)) return;
   extern __shared__ double ssm[];
   const int nf = a.nf, ns = 4 * nf, r = blockIdx.x, tid = threadIdx.x;
   double m[SCHUR_CPT];
@@ -371,6 +383,7 @@ constexpr int STRUCT_NT = 256;
 //   torsional   rhs -= S ((2/dt) r_phi / J - r_theta)
 //   deformable  handled by k_beam and k_struct_rhs_def
 __global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_M) {
+  if (iter_gated(a.gate)) return;
   const int tid = threadIdx.x;
   (void)flow_in_M;  // the flow block is either already in M or not used (stationary inverse)
   if (tid == 0) a.delta[0] = 0.0;  // k_update folds its maxima in with atomicMax
@@ -431,6 +444,7 @@ __device__ inline double inv3_entry(const double* a, int r, int c) {
 constexpr int BEAM_NT = 512;
 constexpr int BEAM_NC = 8;  // right-hand sides per workgroup
 __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
+  if (iter_gated(a.gate)) return;
   constexpr int NC = BEAM_NC;
   extern __shared__ double bsm[];
   const BodyDev& b = a.bodies[bi];
@@ -602,6 +616,7 @@ size_t beam_lds_bytes(int m) {
 
 // Deformable part of the Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi).
 __global__ void k_struct_rhs_def(FsiArgs a, int bi) {
+  if (iter_gated(a.gate)) return;
   const BodyDev& b = a.bodies[bi];
   const int m = b.npts, ncol = 2 * m + 1, r0 = 2 * b.pt0;
   const double dt = a.dt;
@@ -726,6 +741,7 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
 __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
+  if (iter_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = STRUCT_NT / 64;
   const int gw = blockIdx.x * NW + w, nwaves = gridDim.x * NW;
@@ -813,6 +829,7 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
 
 // Newmark completion of the step with the accepted iterate.
 __global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) {
+  if (post_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const double dt = a.dt;
   for (int bi = 0; bi < a.nbodies; ++bi) {
@@ -867,6 +884,7 @@ __global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jh
   __shared__ int sb[SPREAD_NT][3];
   __shared__ double sw[SPREAD_NT][16];
   __shared__ double sc[SPREAD_NT];
+  if (post_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tx = tid % SPREAD_TX, ty = tid / SPREAD_TX;
   const int ti0 = 1 + blockIdx.x * SPREAD_TX, tj0 = jlo + blockIdx.y * SPREAD_TY;
@@ -1133,7 +1151,8 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
                                                 const double* __restrict__ X, int pm,
                                                 const double* __restrict__ b, double* f, int n,
                                                 int rw, int tpr, int maxit, int guess, double* ws,
-                                                double* out, int* flags) {
+                                                double* out, int* flags, const int* gate) {
+  if (iter_gated(gate)) return;  // the same for every workgroup: none enters a barrier
   extern __shared__ double lds[];
   double* sf = lds;           // f (n)
   double* sd = sf + n;        // the update of this sweep (n)
@@ -1281,7 +1300,8 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
 // tile; the k loop loads 16 fragments ahead.
 typedef double v4d __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
-                                                int p, int two_minus) {
+                                                int p, int two_minus, const int* gate) {
+  if (iter_gated(gate)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i0 = blockIdx.y * 32 + (w >> 1) * 16, j0 = blockIdx.x * 32 + (w & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
@@ -1336,6 +1356,61 @@ hipError_t launch_eye_resid(const double* W, int p, int n, double* out, hipStrea
   return hipGetLastError();
 }
 
+// Start of a step's FSI control: clears the error and refinement flags, the gates and the
+// iteration count (ctl layout in FsiCtl).
+__global__ void k_step_reset(int* ctl) {
+  if (threadIdx.x < FsiCtl::INTS) ctl[threadIdx.x] = 0;
+}
+
+// Convergence test after FSI iteration `it` of K launched ahead (Algorithm 2's test on
+// max |delta|, or a fixed count): sets gate[0] and the iteration count on convergence;
+// stops the iterations (gate[1]) on an error or refinement flag, a non-finite update, or
+// when iteration K - 1 has not converged, recording where the host should go on.
+__global__ void k_converge(int* ctl, const double* delta, int it, int K, double tol, int fixed) {
+  if (threadIdx.x != 0) return;
+  int* gate = ctl + FsiCtl::GATE;
+  if (gate[0] != 0 || gate[1] != 0) return;
+  const double d = *delta;
+  if (ctl[FsiCtl::FLAGS] != 0 || ctl[FsiCtl::FLAGS + 1] != 0 || !(d == d) || d > 1e308) {
+    ctl[FsiCtl::NEXT] = it;  // the host handles it (a refinement failure redoes iteration it)
+    gate[1] = 1;
+    return;
+  }
+  if (fixed > 0 ? it + 1 >= fixed : d <= tol) {
+    ctl[FsiCtl::NEXT] = it + 1;
+    gate[0] = 1;
+    return;
+  }
+  if (it + 1 >= K) {
+    ctl[FsiCtl::NEXT] = it + 1;
+    gate[1] = 1;
+  }
+}
+
+// dst = src (count doubles), skipped like the FSI iteration kernels.
+__global__ void k_copy64(double* dst, const double* src, size_t count, const int* gate) {
+  if (iter_gated(gate)) return;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+hipError_t launch_copy64(double* dst, const double* src, size_t count, const int* gate,
+                         hipStream_t st) {
+  const int nb = (int)std::min<size_t>(1024, (count + 255) / 256);
+  if (nb > 0) hipLaunchKernelGGL(k_copy64, dim3(nb), dim3(256), 0, st, dst, src, count, gate);
+  return hipGetLastError();
+}
+hipError_t launch_step_reset(int* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, st, ctl);
+  return hipGetLastError();
+}
+hipError_t launch_converge(int* ctl, const double* delta, int it, int K, double tol, int fixed,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_converge, dim3(1), dim3(64), 0, st, ctl, delta, it, K, tol, fixed);
+  return hipGetLastError();
+}
+
 __global__ void k_identity(double* X, int p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) X[(size_t)i * p + i] = 1.0;
@@ -1348,7 +1423,7 @@ hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
 }
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         hipStream_t st) {
+                         const int* gate, hipStream_t st) {
   if (n < 1 || maxit < 1) return hipErrorInvalidValue;
   int nb = std::min(16, (n + 7) / 8);
   int rw = (n + nb - 1) / nb;
@@ -1365,16 +1440,16 @@ hipError_t launch_refine(const double* M, int pm, const double* X, const double*
   if (lds > 64 * 1024) return hipErrorInvalidValue;
   if (cache)
     hipLaunchKernelGGL(k_refine<true>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
-                       maxit, guess, ws, out, flags);
+                       maxit, guess, ws, out, flags, gate);
   else
     hipLaunchKernelGGL(k_refine<false>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
-                       maxit, guess, ws, out, flags);
+                       maxit, guess, ws, out, flags, gate);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
-                         hipStream_t st) {
+                         hipStream_t st, const int* gate) {
   const int nb = (n + 31) / 32;
-  hipLaunchKernelGGL(k_gemm64, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus);
+  hipLaunchKernelGGL(k_gemm64, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus, gate);
   return hipGetLastError();
 }
 

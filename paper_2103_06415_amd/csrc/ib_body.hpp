@@ -31,6 +31,19 @@ enum { TS_THETA = 0, TS_PHI, TS_PHIDOT, TS_NEW, TS_G, TS_COUNT };
 // timed out.
 constexpr int FLAG_BARRIER = 4;
 
+// The solver's control block (device, 64 bytes), in int units: flags[2] (error code,
+// refinement failure), the last max |delta| (double), the refinement report (3 doubles:
+// relative residual, sweeps, 0), gate[2] and the next FSI iteration index.
+struct FsiCtl {
+  static constexpr int FLAGS = 0;   // ints 0, 1
+  static constexpr int DELTA = 2;   // ints 2, 3 (double)
+  static constexpr int ROUT = 4;    // ints 4 .. 9 (3 doubles)
+  static constexpr int GATE = 10;   // ints 10, 11
+  static constexpr int NEXT = 12;   // int 12
+  static constexpr int INTS = 13;   // ints cleared at the start of a step
+  static constexpr int BYTES = 64;
+};
+
 struct FsiArgs {
   const BodyDev* bodies;
   int nbodies, npts, nf, ntors, ndef;
@@ -76,6 +89,13 @@ struct FsiArgs {
   const double* beta0;
   double* ywork;       // J_d^{-1} T^T, per deformable body: (3m) x (2m)
   int* flags;          // [0] error code, [1] refinement failure
+  // Device-side control of FSI iterations launched ahead of their convergence test (null:
+  // the host decides).  gate[0] = 1 once this step's iterations have converged,
+  // gate[1] = 1 when they must stop for the host (error, refinement failure, or the
+  // launched iterations ran out).  Iteration kernels return at once when either is set;
+  // the kernels after convergence (finish, corrector) run only when gate[0] = 1 and
+  // gate[1] = 0.
+  const int* gate;
   double* delta;       // [0] max |delta| of the last update
 };
 
@@ -127,12 +147,20 @@ hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
 // otherwise flags[1] is raised when the residual stays above 1e-9
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         hipStream_t st);
+                         const int* gate, hipStream_t st);
 size_t refine_ws_doubles(int n, int maxit);
 hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
 // *out (zeroed by the caller) folds in max |W - I| over the n x n matrix (+Inf if not finite)
 hipError_t launch_eye_resid(const double* W, int p, int n, double* out, hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
+                         hipStream_t st, const int* gate = nullptr);
+// Device-side FSI control (FsiCtl): clear it at the start of a step; test convergence
+// after iteration `it` of K launched ahead.
+hipError_t launch_step_reset(int* ctl, hipStream_t st);
+// dst = src (count doubles), skipped like an FSI iteration kernel when gate is set.
+hipError_t launch_copy64(double* dst, const double* src, size_t count, const int* gate,
                          hipStream_t st);
+hipError_t launch_converge(int* ctl, const double* delta, int it, int K, double tol, int fixed,
+                           hipStream_t st);
 
 }  // namespace ib

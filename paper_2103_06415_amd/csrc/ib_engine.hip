@@ -149,6 +149,12 @@ struct FlowTuning {
          idst_us[ib::FLOW_VARIANTS] = {};
 };
 
+// A recorded step: its executable graph and the number of FSI iterations it launches ahead.
+struct StepGraph {
+  hipGraphExec_t exec = nullptr;
+  int K = 0;
+};
+
 struct ib_solver {
   ib_config cfg{};
   ib_allocator alloc{};
@@ -217,6 +223,11 @@ struct ib_solver {
   double* rinfo = nullptr;  // refinement workspace (device)
   bool x_valid = false;
   bool x_valid_retry = false;
+  int* gate = nullptr;      // device gates of the FSI iterations launched ahead (in ctl)
+  bool fsi_ahead = true;    // launch a step's FSI iterations ahead of their tests
+  bool graphs = true;       // replay recorded steps as HIP graphs
+  StepGraph step_graphs[2]; // by ring-buffer alternation
+  int64_t graph_captures = 0, graph_launches = 0, fsi_resumes = 0;
   int inverse_rebuilds = 0;
   // sweeps launched per stress solve in tolerance mode, per FSI iteration index (0, 1, 2, 3+)
   // control block read back once per FSI iteration: error flags (2 ints), max |delta|,
@@ -827,6 +838,7 @@ ib_status prepare_bodies(ib_solver* s) {
   s->ctl = dalloc(s, 64);
   if (!a.st_base || !a.st_w || !a.M || !s->f || !s->ctl) return IB_ERR_OOM;
   s->flags = static_cast<int*>(s->ctl);
+  s->gate = s->flags + FsiCtl::GATE;
   s->delta = reinterpret_cast<double*>(static_cast<char*>(s->ctl) + 8);
   s->rout = reinterpret_cast<double*>(static_cast<char*>(s->ctl) + 16);
   a.flags = s->flags;
@@ -1028,118 +1040,62 @@ ib_status do_prepare(ib_solver* s) {
 
 // --------------------------------------------------------------------- step
 
+// One FSI iteration (the loop body of Algorithm 2): body operators and u*, the structure's
+// right-hand side, the beam Jacobian solves, the Schur matrix (eqs. (17), (37)), the inverse
+// it is solved with (fresh LU, or one Newton-Schulz refresh at the first iteration of a
+// step), the refined stress solve and the structure update.  With a.gate set every kernel
+// skips itself once the step's iterations have converged or stopped on the device.
 template <typename T>
-ib_status fsi_and_correct(ib_solver* s) {
+ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it) {
+  FsiArgs a = a0;
+  a.iter = it;
+  const int n = s->n, nf = s->nf;
+  TimeScope ts(s, IB_K_FSI);
+  HIPCHK(launch_body_ops<T>(a, s->stream));
+  HIPCHK(launch_structure(a, 1, s->stream));
+  for (size_t bi = 0; bi < s->bodies.size(); ++bi)
+    if (s->bodies[bi].kind == BODY_DEFORMABLE)
+      HIPCHK(launch_beam(a, (int)bi, s->bodies[bi].m, s->stream));
+  if (s->exact_moving) {
+    // the exact flow block at this iterate: one point-source solve per body row
+    for (int c0 = 0; c0 < nf; c0 += s->xo.nslots) {
+      ib_status e = offline_columns(s, s->xo, s->xrows, c0, nf, s->xrows, nf, 1, n - 1);
+      if (e) return e;
+      HIPCHK(launch_cols_to_matrix(s->xo.vals, nf, std::min(s->xo.nslots, nf - c0), c0, s->gx,
+                                   a.pm, s->stream));
+    }
+  }
+  HIPCHK(launch_schur_sd(a, s->stream));
+  const size_t mb = (size_t)nf * a.pm * 8;
+  if (!s->x_valid) {
+    // fresh inverse of the current Schur matrix by LU on a copy
+    HIPCHK(hipMemcpyAsync(s->Mtmp, a.M, mb, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->Minv, 0, mb, s->stream));
+    HIPCHK(launch_identity(s->Minv, a.pm, nf, s->stream));
+    HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
+    s->x_valid = true;
+    s->inverse_rebuilds++;
+  } else if (it == 0) {
+    // one Newton-Schulz step towards the new matrix: X <- X (2I - M X)
+    HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream, a.gate));
+    HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream, a.gate));
+    HIPCHK(launch_copy64(s->Minv, s->Xn, (size_t)nf * a.pm, a.gate, s->stream));
+  }
+  HIPCHK(launch_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, REFINE_MAXIT,
+                       it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, a.gate,
+                       s->stream));
+  HIPCHK(launch_update(a, s->stream));
+  return IB_OK;
+}
+
+// Corrector s_{n+1} = s* - dt K C^T E^T (ds/h) f on level 0 (eqs. (20), (40)); with `gate`
+// set it runs only if the step's iterations converged on the device.
+template <typename T>
+ib_status corrector(ib_solver* s, const int* gate) {
   const int n = s->n, P = s->pitch;
   LevelState& L0 = s->lv[0];
-  FsiArgs& a = s->fa;
-  HIPCHK(hipMemsetAsync(s->flags, 0, 8, s->stream));
-  int it = 0;
-  const int fixed = s->cfg.newton_fixed_iter;
-  const int kmax = s->cfg.newton_max_iter > 0 ? s->cfg.newton_max_iter : 20;
-  for (;;) {
-    a.iter = it;
-    if (s->stationary) {
-      TimeScope ts(s, IB_K_FSI);
-      HIPCHK(launch_body_ops<T>(a, s->stream));
-      HIPCHK(launch_structure(a, 0, s->stream));
-      HIPCHK(launch_matvec(s->Minv, a.pm, s->rhs, s->f, s->nf, s->stream));
-      s->iters_last = 1;
-      s->delta_last = 0.0;
-      break;
-    }
-    {
-      TimeScope ts(s, IB_K_FSI);
-      HIPCHK(launch_body_ops<T>(a, s->stream));
-      HIPCHK(launch_structure(a, 1, s->stream));
-      for (size_t bi = 0; bi < s->bodies.size(); ++bi)
-        if (s->bodies[bi].kind == BODY_DEFORMABLE)
-          HIPCHK(launch_beam(a, (int)bi, s->bodies[bi].m, s->stream));
-      if (s->exact_moving) {
-        // the exact flow block at this iterate: one point-source solve per body row
-        const int nfr = s->nf;
-        for (int c0 = 0; c0 < nfr; c0 += s->xo.nslots) {
-          ib_status e = offline_columns(s, s->xo, s->xrows, c0, nfr, s->xrows, nfr, 1, n - 1);
-          if (e) return e;
-          HIPCHK(launch_cols_to_matrix(s->xo.vals, nfr, std::min(s->xo.nslots, nfr - c0), c0,
-                                       s->gx, a.pm, s->stream));
-        }
-      }
-      HIPCHK(launch_schur_sd(a, s->stream));
-      const int nf = s->nf;
-      const size_t mb = (size_t)nf * a.pm * 8;
-      if (!s->x_valid) {
-        // fresh inverse of the current Schur matrix by LU on a copy
-        HIPCHK(hipMemcpyAsync(s->Mtmp, a.M, mb, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(hipMemsetAsync(s->Minv, 0, mb, s->stream));
-        HIPCHK(launch_identity(s->Minv, a.pm, nf, s->stream));
-        HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
-        s->x_valid = true;
-        s->inverse_rebuilds++;
-      } else if (it == 0) {
-        // one Newton-Schulz step towards the new matrix: X <- X (2I - M X)
-        HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream));
-        HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream));
-        std::swap(s->Minv, s->Xn);
-      }
-      HIPCHK(launch_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, REFINE_MAXIT,
-                           it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, s->stream));
-      HIPCHK(launch_update(a, s->stream));
-    }
-    bool done = false;
-    if (fixed > 0) {
-      done = it + 1 >= fixed;
-      if (done) {
-        HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
-        HIPCHK(hipStreamSynchronize(s->stream));
-        ib_status st = map_flags(s, s->hflags[0]);
-        if (st) return st;
-        if (s->hflags[1]) {
-          s->last_error = "Schur refinement did not converge";
-          return IB_ERR_NONFINITE;
-        }
-      }
-    } else {
-      HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, 40, hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(hipStreamSynchronize(s->stream));
-      ib_status st = map_flags(s, s->hflags[0]);
-      if (st) return st;
-      if (s->hflags[1]) {
-        // the approximate inverse no longer contracts: rebuild it and redo this iteration
-        if (!s->x_valid_retry) {
-          s->x_valid = false;
-          s->x_valid_retry = true;
-          HIPCHK(hipMemsetAsync(s->flags + 1, 0, 4, s->stream));
-          continue;
-        }
-        s->last_error = "Schur refinement did not converge";
-        return IB_ERR_NONFINITE;
-      }
-      s->x_valid_retry = false;
-      if (!std::isfinite(s->hdelta[0])) {
-        s->last_error = "non-finite structure update";
-        return IB_ERR_NONFINITE;
-      }
-      done = s->hdelta[0] <= s->cfg.newton_tol;
-      if (!done && it + 1 >= kmax) {
-        s->iters_last = it + 1;
-        s->delta_last = s->hdelta[0];
-        s->last_error = "FSI iteration did not converge";
-        return IB_ERR_NOT_CONVERGED;
-      }
-    }
-    if (done) {
-      ib_status st = map_flags(s, s->hflags[0]);
-      if (st) return st;
-      s->iters_last = it + 1;
-      s->delta_last = s->hdelta[0];
-      HIPCHK(launch_finish(a, s->stream));
-      break;
-    }
-    ++it;
-  }
-  s->iters_max = std::max(s->iters_max, s->iters_last);
-  // corrector: s_{n+1} = s* - dt K C^T E^T (ds/h) f on level 0
+  FsiArgs a = s->fa;
+  a.gate = gate;
   {
     TimeScope ts(s, IB_K_CORRECT);
     HIPCHK(launch_spread<T>(a, s->blo, s->bhi, s->bilo, s->bihi, static_cast<T*>(s->work2), P,
@@ -1150,6 +1106,7 @@ ib_status fsi_and_correct(ib_solver* s) {
     r.pi = r.po = P;
     r.r0 = s->blo;
     r.r1 = s->bhi;
+    r.gate = gate;
     HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
   }
   ColArgs<T> c{};
@@ -1165,11 +1122,130 @@ ib_status fsi_and_correct(ib_solver* s) {
   c.w0 = 1;
   c.w1 = n - 1;
   c.var = s->tune.col;
-  {
-    TimeScope ts(s, IB_K_COL_SOLVE);
-    HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
-  }
+  c.gate = gate;
+  TimeScope ts(s, IB_K_COL_SOLVE);
+  HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
   return IB_OK;
+}
+
+// Whether this step's FSI iterations can be launched ahead of their convergence tests
+// (device-side control, one host synchronisation per step).  The first use of the Schur
+// inverse (LU) and the exact operator (host-driven column solves) stay on the host path.
+bool fsi_ahead(const ib_solver* s) {
+  return !s->stationary && !s->exact_moving && s->x_valid && s->fsi_ahead;
+}
+
+int fsi_ahead_count(const ib_solver* s) {
+  const int fixed = s->cfg.newton_fixed_iter;
+  const int kmax = s->cfg.newton_max_iter > 0 ? s->cfg.newton_max_iter : 20;
+  if (fixed > 0) return std::min(fixed, kmax);
+  return std::max(1, std::min(kmax, s->iters_last > 0 ? s->iters_last : 2));
+}
+
+// Launch the step's FSI iterations ahead: K iterations, each followed by the device-side
+// convergence test, then the structure's finish and the corrector, all gated.
+template <typename T>
+ib_status fsi_launch_ahead(ib_solver* s, int K) {
+  FsiArgs g = s->fa;
+  g.gate = s->gate;
+  const int fixed = s->cfg.newton_fixed_iter;
+  for (int it = 0; it < K; ++it) {
+    ib_status e = fsi_iteration<T>(s, g, it);
+    if (e) return e;
+    HIPCHK(launch_converge(s->flags, s->delta, it, K, s->cfg.newton_tol, fixed, s->stream));
+  }
+  HIPCHK(launch_finish(g, s->stream));
+  return corrector<T>(s, s->gate);
+}
+
+// After the iterations launched ahead (and a synchronisation that brought the control block
+// to the host): converged, or go on on the host from where the device stopped.  *resume
+// receives the iteration to continue with, or -1 when the step's FSI part is complete.
+ib_status fsi_after_ahead(ib_solver* s, int* resume) {
+  *resume = -1;
+  const int* hc = static_cast<const int*>(s->hctl);
+  const int next = hc[FsiCtl::NEXT];
+  if (hc[FsiCtl::GATE] == 1 && hc[FsiCtl::GATE + 1] == 0) {
+    s->iters_last = next;
+    s->delta_last = s->hdelta[0];
+    s->iters_max = std::max(s->iters_max, s->iters_last);
+    return IB_OK;
+  }
+  ib_status st = map_flags(s, s->hflags[0]);
+  if (st) return st;
+  if (s->hflags[1]) {
+    // the approximate inverse no longer contracts: rebuild it and redo that iteration
+    s->x_valid = false;
+    s->x_valid_retry = true;
+  } else if (!std::isfinite(s->hdelta[0])) {
+    s->last_error = "non-finite structure update";
+    return IB_ERR_NONFINITE;
+  }
+  // clear the flags and gates (the host continues without them)
+  HIPCHK(launch_step_reset(s->flags, s->stream));
+  *resume = next;
+  return IB_OK;
+}
+
+// FSI iterations with the convergence test on the host, from iteration `it0`, then the
+// finish and the corrector.
+template <typename T>
+ib_status fsi_host(ib_solver* s, int it0) {
+  FsiArgs& a = s->fa;
+  const int fixed = s->cfg.newton_fixed_iter;
+  const int kmax = s->cfg.newton_max_iter > 0 ? s->cfg.newton_max_iter : 20;
+  int it = it0;
+  for (;;) {
+    if (s->stationary) {
+      FsiArgs b = a;
+      b.iter = 0;
+      TimeScope ts(s, IB_K_FSI);
+      HIPCHK(launch_body_ops<T>(b, s->stream));
+      HIPCHK(launch_structure(b, 0, s->stream));
+      HIPCHK(launch_matvec(s->Minv, b.pm, s->rhs, s->f, s->nf, s->stream));
+      s->iters_last = 1;
+      s->delta_last = 0.0;
+      break;
+    }
+    ib_status e = fsi_iteration<T>(s, a, it);
+    if (e) return e;
+    HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    ib_status st = map_flags(s, s->hflags[0]);
+    if (st) return st;
+    if (s->hflags[1]) {
+      // the approximate inverse no longer contracts: rebuild it and redo this iteration
+      if (!s->x_valid_retry) {
+        s->x_valid = false;
+        s->x_valid_retry = true;
+        HIPCHK(launch_step_reset(s->flags, s->stream));
+        continue;
+      }
+      s->last_error = "Schur refinement did not converge";
+      return IB_ERR_NONFINITE;
+    }
+    s->x_valid_retry = false;
+    if (!std::isfinite(s->hdelta[0])) {
+      s->last_error = "non-finite structure update";
+      return IB_ERR_NONFINITE;
+    }
+    const bool done = fixed > 0 ? it + 1 >= fixed : s->hdelta[0] <= s->cfg.newton_tol;
+    if (!done && it + 1 >= kmax) {
+      s->iters_last = it + 1;
+      s->delta_last = s->hdelta[0];
+      s->last_error = "FSI iteration did not converge";
+      return IB_ERR_NOT_CONVERGED;
+    }
+    if (done) {
+      s->iters_last = it + 1;
+      s->delta_last = s->hdelta[0];
+      HIPCHK(launch_finish(a, s->stream));
+      break;
+    }
+    ++it;
+  }
+  s->iters_max = std::max(s->iters_max, s->iters_last);
+  return corrector<T>(s, nullptr);
 }
 
 // The predictor's solve with the sine transforms on the matrix cores (FP32 flow only):
@@ -1233,8 +1309,15 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
   }
 }
 
+// Enqueue one step (Algorithm 2): for every level, coarse to fine, the ring from the coarser
+// level, the explicit right-hand side and the predictor solve; on level 0 with bodies the
+// FSI iterations and the corrector; then each level's inverse row transform into its state.
+// With `ahead` (moving bodies) the FSI iterations, the corrector and level 0's final
+// transform are launched ahead under the device gates and nothing here waits for the GPU,
+// so the launches can be recorded as a graph; otherwise the host tests every FSI iteration.
+// Host state that changes per step (ring buffer alternation, step count) is left alone.
 template <typename T>
-ib_status do_step(ib_solver* s) {
+ib_status enqueue_step(ib_solver* s, bool ahead, int K) {
   const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
   const bool bodies = !s->bodies.empty();
   for (int g = G - 1; g >= 0; --g) {
@@ -1283,6 +1366,7 @@ ib_status do_step(ib_solver* s) {
     r.in = static_cast<T*>(s->work);
     r.pi = r.po = P;
     const T* ring = has_ring ? static_cast<T*>(L.sring) : nullptr;
+    const int* gate = nullptr;
     if (g == 0 && bodies) {
       // s* on the rows the body operators can reach
       r.out = static_cast<T*>(s->sstar);
@@ -1292,7 +1376,13 @@ ib_status do_step(ib_solver* s) {
         TimeScope ts(s, IB_K_ROW_IDST);
         HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 0, s->stream));
       }
-      st = fsi_and_correct<T>(s);
+      HIPCHK(launch_step_reset(s->flags, s->stream));
+      if (ahead) {
+        st = fsi_launch_ahead<T>(s, K);
+        gate = s->gate;
+      } else {
+        st = fsi_host<T>(s, 0);
+      }
       if (st) return st;
     }
     r.out = static_cast<T*>(L.s);
@@ -1301,12 +1391,100 @@ ib_status do_step(ib_solver* s) {
     r.in2 = static_cast<T*>(s->workg);
     r.out2 = static_cast<T*>(L.g);
     r.var = s->tune.idst;
+    r.gate = gate;
     {
       TimeScope ts(s, IB_K_ROW_IDST);
       HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
     }
-    if (has_ring) L.gcur = nxt;
   }
+  return IB_OK;
+}
+
+// Level 0's inverse row transform into its state (the last launch of a step), after the
+// FSI part was finished on the host.
+template <typename T>
+ib_status final_transform_level0(ib_solver* s) {
+  const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
+  LevelState& L = s->lv[0];
+  RowArgs<T> r{};
+  r.in = static_cast<T*>(s->work);
+  r.pi = r.po = P;
+  r.out = static_cast<T*>(L.s);
+  r.r0 = 1;
+  r.r1 = n - 1;
+  r.in2 = static_cast<T*>(s->workg);
+  r.out2 = static_cast<T*>(L.g);
+  r.var = s->tune.idst;
+  const T* ring = G > 1 ? static_cast<T*>(L.sring) : nullptr;
+  TimeScope ts(s, IB_K_ROW_IDST);
+  HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
+  return IB_OK;
+}
+
+void destroy_graphs(ib_solver* s) {
+  for (auto& g : s->step_graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = StepGraph{};
+  }
+}
+
+template <typename T>
+ib_status do_step(ib_solver* s) {
+  const int G = (int)s->lv.size();
+  const bool bodies = !s->bodies.empty();
+  const bool ahead = bodies && fsi_ahead(s);
+  const bool sync_free = !bodies || s->stationary || ahead;
+  const int K = ahead ? fsi_ahead_count(s) : 0;
+  // (the legacy null stream cannot be recorded)
+  const bool use_graph = s->graphs && s->fsi_ahead && sync_free && !s->first && !s->timing &&
+                         s->stream != nullptr;
+  ib_status st = IB_OK;
+  if (use_graph) {
+    StepGraph& sg = s->step_graphs[G > 1 ? s->lv[0].gcur : 0];
+    if (!sg.exec || sg.K != K) {
+      if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+      sg = StepGraph{};
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+      st = enqueue_step<T>(s, ahead, K);
+      const hipError_t e = hipStreamEndCapture(s->stream, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+      const hipError_t e2 = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e2 != hipSuccess) {
+        sg = StepGraph{};
+        return hip_fail(s, e2, "hipGraphInstantiate");
+      }
+      sg.K = K;
+      s->graph_captures++;
+    }
+    HIPCHK(hipGraphLaunch(sg.exec, s->stream));
+    s->graph_launches++;
+  } else {
+    st = enqueue_step<T>(s, ahead, K);
+    if (st) return st;
+  }
+  if (ahead) {
+    HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    int resume = -1;
+    st = fsi_after_ahead(s, &resume);
+    if (st) return st;
+    if (resume >= 0) {
+      // the launched iterations did not suffice: finish the FSI part on the host, then
+      // level 0's final transform (skipped on the device)
+      s->fsi_resumes++;
+      st = fsi_host<T>(s, resume);
+      if (st) return st;
+      st = final_transform_level0<T>(s);
+      if (st) return st;
+    }
+  }
+  for (int g = 0; g < G - 1; ++g) s->lv[g].gcur = 1 - s->lv[g].gcur;
   s->first = false;
   s->step++;
   return IB_OK;
@@ -1800,7 +1978,25 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   out->refine_residual = s->hrinfo ? s->hrinfo[0] : 0.0;
   out->inverse_rebuilds = s->inverse_rebuilds;
   out->operator_source = s->op ? s->op_source : -1;
+  out->graph_launches = s->graph_launches;
+  out->graph_captures = s->graph_captures;
+  out->fsi_resumes = s->fsi_resumes;
   return IB_OK;
+}
+
+ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
+  if (check(s) || (value != 0 && value != 1)) return IB_ERR_ARG;
+  if (option == IB_OPT_FSI_AHEAD) {
+    s->fsi_ahead = value != 0;
+    destroy_graphs(s);
+    return IB_OK;
+  }
+  if (option == IB_OPT_GRAPHS) {
+    s->graphs = value != 0;
+    destroy_graphs(s);
+    return IB_OK;
+  }
+  return IB_ERR_ARG;
 }
 
 ib_status ib_get_flow_tuning(ib_solver* s, ib_flow_tuning* out) {
@@ -1831,6 +2027,7 @@ ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t i
   if (col >= 0) s->tune.col = col;
   if (idst >= 0) s->tune.idst = idst;
   s->tune_forced = true;
+  destroy_graphs(s);  // recorded steps launch the previous configurations
   return IB_OK;
 }
 
@@ -1879,6 +2076,7 @@ ib_status ib_release(ib_solver* s) {
   if (s->released) return IB_OK;
   if (s->allocated) {
     HIPCHK(hipStreamSynchronize(s->stream));
+    destroy_graphs(s);
     if (s->prepared && s->f) {
       s->h_f.resize(s->nf);
       HIPCHK(hipMemcpy(s->h_f.data(), s->f, (size_t)s->nf * 8, hipMemcpyDeviceToHost));
@@ -2020,6 +2218,7 @@ ib_status ib_set_operator_cache(int64_t limit_bytes) {
 ib_status ib_destroy(ib_solver* s) {
   if (!s) return IB_ERR_ARG;
   (void)hipStreamSynchronize(s->stream);
+  destroy_graphs(s);
   harvest_events(s);
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
   s->event_pool.clear();

@@ -20,6 +20,12 @@
 
 namespace ib {
 
+// Kernels after the FSI iterations of a step (corrector, final inverse transform) run
+// only when those converged: gate[0] = 1 and gate[1] = 0 (null: always).
+__device__ __forceinline__ bool flow_gated(const int* gate) {
+  return gate != nullptr && (gate[0] != 1 || gate[1] != 0);
+}
+
 template <typename T>
 __device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
   return p[(size_t)j * pitch + i];
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __rest
   __shared__ c2<T> buf[ROWS * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
   const int blk = xcd_block(blockIdx.x, nblocks);
-  if (blk < 0) return;
+  if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
   T* out = a.out + (size_t)blockIdx.y * a.bso;
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   static_assert(sizeof(buf) + sizeof(stw) + sizeof(slam) + sizeof(slift) + sizeof(slift01) <=
                     160 * 1024, "LDS");
   const int blk = xcd_block(blockIdx.x, nblocks);
-  if (blk < 0) return;
+  if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const int k0 = blk * CW;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
   static_assert(sizeof(buf) + sizeof(stw) <= 160 * 1024, "LDS");
   const int blk = xcd_block(blockIdx.x, nblocks);
-  if (blk < 0) return;
+  if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const T* in = a.in + (size_t)blockIdx.y * a.bsi;
   T* out = a.out + (size_t)blockIdx.y * a.bso;

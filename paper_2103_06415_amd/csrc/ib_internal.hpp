@@ -34,6 +34,7 @@ struct RowArgs {
   const T* in2;     // inverse transform: a second array transformed alongside `in`
   T* out2;          //   into the interior array out2 (pitch po); batch 1 only
   int var;          // inverse transform with in2: kernel configuration (ROW_VARIANTS)
+  const int* gate;  // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
 };
 
 // Column transform + spectral scale + inverse column transform.
@@ -53,6 +54,7 @@ struct ColArgs {
   int rcount;        //   compactly (row rfirst[b] at input row 0)
   int w0, w1;        // output rows written (1-based); others untouched
   int var;           // kernel configuration (COL_VARIANTS; 0 = default)
+  const int* gate;   // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
 };
 
 // Kernel configurations of the row and column sine-transform kernels, selected per grid
