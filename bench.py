@@ -79,6 +79,45 @@ def run(problem, precision, steps, warmup, timing=True):
     return wall, prep, kt, st
 
 
+def concurrent(problem, count, steps, warmup=3):
+    """`count` copies of the workload, each on its own stream driven by its own host thread
+    (steps recorded as graphs); aggregate grid-cell steps/s over the timed steps."""
+    import threading
+    import torch
+    from paper_2103_06415_amd import binding
+    sol = []
+    for _ in range(count):
+        s = binding.Solver(problem, precision=binding.IB_FP32_FLOW, stream=torch.cuda.Stream())
+        s.prepare()
+        sol.append(s)
+    torch.cuda.synchronize()
+    bar = threading.Barrier(count + 1)
+
+    def work(s):
+        s.step(warmup)
+        s.sync()
+        bar.wait()
+        s.step(steps)
+        s.sync()
+        bar.wait()
+
+    th = [threading.Thread(target=work, args=(s,)) for s in sol]
+    for t in th:
+        t.start()
+    bar.wait()
+    t0 = time.perf_counter()
+    bar.wait()
+    wall = time.perf_counter() - t0
+    for t in th:
+        t.join()
+    for s in sol:
+        s.close()
+    fl = problem.flow
+    return {"instances": count, "steps_each": steps, "wall_s": wall,
+            "throughput": count * fl.n * fl.n * fl.levels * steps / wall,
+            "throughput_unit": "grid-cell steps/s", "ms_per_step_each": 1e3 * wall / steps}
+
+
 def serve(problems, max_active=8, budget=200 << 30, precision=None):
     """Run (arrival, Problem) requests through the continuous-batching server."""
     from paper_2103_06415_amd import binding
@@ -217,6 +256,8 @@ def main():
                     help="skip the serving trace (48 Poisson arrivals at 40/s, 256^2..1024^2)")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the sub-domain vs exact-operator comparison (plate, 512^2 x 3)")
+    ap.add_argument("--concurrent", type=int, default=4,
+                    help="also run this many copies of the workload concurrently (0: skip)")
     ap.add_argument("--batch", action="store_true",
                     help="also run the 64-instance batch (sizes 128^2..768^2, 200 steps each)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
@@ -297,6 +338,10 @@ def main():
                      "bytes_per_launch": tot_bytes / max(launches, 1),
                      "avg_launch_us": 1e3 * ms / max(launches, 1)},
     }
+    if args.concurrent > 1:
+        out["concurrent"] = concurrent(prob, args.concurrent, args.steps)
+        out["concurrent"]["workload"] = (f"{args.concurrent} copies of the flag workload, one stream "
+                                         "and host thread each, FP32 flow")
     if not args.no_serve:
         # continuous batching of a seeded Poisson trace; latency = finish - arrival
         out["served"] = serve(W.serve_trace())

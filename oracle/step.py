@@ -20,6 +20,11 @@ Signs: f is the stress the fluid exerts on the body (this makes eqs. (A.3), (9) 
 (11) consistent); the paper's S = [0, -QR ds, 0] carries one ds too many against
 eq. (A.17)'s second row, and the reading here is S_t = Q R.
 
+Rigid bodies in prescribed motion (Sec. 2.1, eq. (5); the driven plate of Sec. 5.1): their
+points sit at the pose of the new time level t_{n+1}, (x, y) + R(angle) xy_ref, and carry
+the prescribed velocity (vx, vy) + omega e_z x (R xy_ref) into b; in sub-domain mode they are
+interpolated through P like the other moving points (not appended to B').
+
 FSI iteration (Algorithm 2): start from the old structure state, stop when
 max |delta theta|, |delta chi| <= tol (both tests of Sec. 5 and Algorithm 2), at most
 ``newton_max`` iterations, or run exactly ``fixed_iters`` iterations (parity mode).
@@ -35,6 +40,21 @@ from . import delta, dst, grid, multidomain as md, structure, subdomain
 
 class NotConverged(RuntimeError):
     pass
+
+
+def moving_positions(b, t):
+    """Points of a rigid body in prescribed motion at time t: (x, y) + R(angle) xy_ref."""
+    x, y, ang, _, _, _ = b.pose(t)
+    rot = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+    return b.xy_ref @ rot.T + np.array([x, y])
+
+
+def moving_velocities(b, t):
+    """Their velocities: (vx, vy) + omega e_z x (R(angle) xy_ref)."""
+    x, y, ang, vx, vy, om = b.pose(t)
+    rot = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+    r = b.xy_ref @ rot.T
+    return np.stack([vx - om * r[:, 1], vy + om * r[:, 0]], axis=1)
 
 
 class Oracle:
@@ -62,6 +82,8 @@ class Oracle:
         for b in problem.bodies:
             if isinstance(b, W.Rigid):
                 self.bodies.append(("rigid", b))
+            elif isinstance(b, W.MovingRigid):
+                self.bodies.append(("moving", b))
             elif isinstance(b, W.Torsional):
                 self.bodies.append(("torsional", structure.TorsionalState(b, flow.dt)))
             elif isinstance(b, W.Deformable):
@@ -91,18 +113,26 @@ class Oracle:
             self.s[g] = grid.pad(dst.solve_poisson(gam + bs), ring_s)
             self.gring[g] = ring_g
 
+    @staticmethod
+    def _count(kind, b):
+        if kind == "rigid":
+            return b.xy.shape[0]
+        if kind == "moving":
+            return b.xy_ref.shape[0]
+        return b.npts
+
     def npts_per_body(self):
-        out = []
-        for kind, b in self.bodies:
-            out.append(b.xy.shape[0] if kind == "rigid" else b.npts)
-        return out
+        return [self._count(kind, b) for kind, b in self.bodies]
 
     def ds_vector(self):
         v = []
         for kind, b in self.bodies:
-            m = b.xy.shape[0] if kind == "rigid" else b.npts
-            v.append(np.full(2 * m, b.ds))
+            v.append(np.full(2 * self._count(kind, b), b.ds))
         return np.concatenate(v) if v else np.zeros(0)
+
+    def t_new(self):
+        """Time level t_{n+1} of the step being taken (the constraint holds there)."""
+        return (self.step_count + 1) * self.dt
 
     def prepare(self):
         """Offline stage: stationary exact Schur block, or B' (Algorithm 1)."""
@@ -133,6 +163,8 @@ class Oracle:
     def positions(self, kind, b, it=None):
         if kind == "rigid":
             return b.xy
+        if kind == "moving":
+            return moving_positions(b, self.t_new())
         if kind == "torsional":
             return b.positions(b.theta_k)
         return b.positions(b.chi_k)
@@ -249,6 +281,9 @@ class Oracle:
                 if kind == "rigid":
                     if b.u_b is not None:
                         rhs[blk] -= np.concatenate([b.u_b[:, 0], b.u_b[:, 1]])
+                elif kind == "moving":
+                    ub = moving_velocities(b, self.t_new())
+                    rhs[blk] -= np.concatenate([ub[:, 0], ub[:, 1]])
                 elif kind == "torsional":
                     jt = b.jac()
                     srow = b.s_row(b.theta_k)
@@ -319,7 +354,8 @@ class Oracle:
         return out
 
     def noslip_residual(self):
-        """max |(1/h) E (C s_{n+1} + q_inf) - U_b| with the operator of the last solve."""
+        """max |(1/h) E (C s_{n+1} + q_inf) - U_b| with the operator of the last solve
+        (call after step(); moving bodies at the time level just reached)."""
         lv = self.levels[0]
         q = grid.flatten_faces(*lv.flux(self.s[0]))
         u = self.eh_used @ q / lv.h
@@ -329,6 +365,10 @@ class Oracle:
             if kind == "rigid" and b.u_b is not None:
                 ub[off:off + m] = b.u_b[:, 0]
                 ub[off + m:off + 2 * m] = b.u_b[:, 1]
+            elif kind == "moving":
+                v = moving_velocities(b, self.step_count * self.dt)
+                ub[off:off + m] = v[:, 0]
+                ub[off + m:off + 2 * m] = v[:, 1]
             elif kind == "torsional":
                 ang = b.b.theta0 + b.theta_used
                 j = np.arange(m) * b.ds

@@ -164,10 +164,13 @@ class TorchAllocator:
         self.device = device
         self.stream = stream
 
+        self.last_error = None
+
         def _alloc(nbytes, ctx):
             try:
                 return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
-            except Exception:
+            except Exception as e:  # reported to the library as out of memory
+                self.last_error = e
                 return None
 
         def _free(ptr, ctx):

@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 
@@ -38,6 +38,19 @@ class Rigid:
     xy: np.ndarray                      # (n, 2) body point positions
     ds: float                           # body point spacing (arc length per point)
     u_b: Optional[np.ndarray] = None    # (n, 2) prescribed velocity, None = stationary
+
+
+@dataclasses.dataclass
+class MovingRigid:
+    """Rigid body with prescribed motion: points xy_ref in the body frame, and
+    motion(t) -> (x, y, angle, vx, vy, omega), the pose of the body frame at time t and
+    its rates (an input of the problem)."""
+    xy_ref: np.ndarray                  # (n, 2) body-frame point coordinates
+    ds: float
+    motion: Callable[[float], tuple]
+
+    def pose(self, t):
+        return tuple(float(v) for v in self.motion(t))
 
 
 @dataclasses.dataclass
@@ -80,6 +93,68 @@ class Problem:
     subdomain: Optional[tuple] = None          # (x0, x1, y0, y1) or None = exact operators
     vorticity0: Optional[List[np.ndarray]] = None  # per level, (n-1, n-1) interior omega
     steps: int = 1
+
+
+def flapping_motion(a0=1.4, beta=math.pi / 4, sigma_t=0.628, sigma_r=0.628, freq=1.0,
+                    center=(0.0, 0.0)):
+    """Driven-plate kinematics of Sec. 5.1 (lengths in chords, time in 1/freq units):
+    X(t) = (A0/2) G_t(ft)/max G_t C(ft), Y = 0, alpha(t) = -beta G_r(ft)/max G_r, with
+    G_t(t) = int_0^t tanh(sigma_t cos 2 pi t') dt', G_r(t) = tanh(sigma_r cos 2 pi t) and the
+    start-up conditioner C(t) = (tanh(8t - 2) + tanh 2)/(1 + tanh 2).  Returns
+    motion(t) -> (x, y, angle, vx, vy, omega) with the rates in closed form (G_t by
+    Gauss-Legendre quadrature; max G_t = G_t(1/4), max G_r = tanh sigma_r)."""
+    xg, wg = np.polynomial.legendre.leggauss(48)
+
+    def g_t(t):
+        # integrate over whole quarter periods and the remainder, 48 points each
+        q = math.floor(4.0 * t)
+        total = 0.0
+        for a, b in [(k / 4.0, (k + 1) / 4.0) for k in range(int(q))] + [(q / 4.0, t)]:
+            if b <= a:
+                continue
+            u = 0.5 * (b - a) * xg + 0.5 * (b + a)
+            total += 0.5 * (b - a) * float(np.sum(wg * np.tanh(sigma_t * np.cos(2 * math.pi * u))))
+        return total
+
+    gt_max = g_t(0.25)
+    gr_max = math.tanh(sigma_r)
+    th2 = math.tanh(2.0)
+
+    def motion(t):
+        ft = freq * t
+        cnd = (math.tanh(8.0 * ft - 2.0) + th2) / (1.0 + th2)
+        dcnd = 8.0 * freq * (1.0 - math.tanh(8.0 * ft - 2.0) ** 2) / (1.0 + th2)
+        gt = g_t(ft) if ft >= 0 else -g_t(-ft)
+        dgt = freq * math.tanh(sigma_t * math.cos(2 * math.pi * ft))
+        x = 0.5 * a0 * gt / gt_max * cnd
+        vx = 0.5 * a0 / gt_max * (dgt * cnd + gt * dcnd)
+        gr = math.tanh(sigma_r * math.cos(2 * math.pi * ft))
+        dgr = (1.0 - gr * gr) * sigma_r * (-2 * math.pi * freq * math.sin(2 * math.pi * ft))
+        ang = -beta * gr / gr_max
+        om = -beta * dgr / gr_max
+        return (center[0] + x, center[1], ang, vx, 0.0, om)
+
+    return motion
+
+
+def driven_plate_problem(n=256, levels=2, steps=50, case=2, subdomain=True):
+    """A flat plate of chord 1.05 (its centre at the origin) driven by the Sec. 5.1
+    flapping kinematics (Table kineparams case 1 or 2, f = 1) in fluid at rest; ds = 2h.
+    Re = f c^2 / nu from the rotational Reynolds number 100 of the table.  Finest level
+    6.4 x 6.4; sub-domain [-1.95, 1.95] x [-0.85, 0.85] holds every plate position."""
+    sigma = 3.770 if case == 1 else 0.628
+    beta = math.pi / 4
+    re = 100.0 * math.tanh(sigma) / (2 * math.pi * beta * sigma)
+    width = 6.4
+    h = width / n
+    flow = Flow(n=n, levels=levels, h=h, dt=0.05 * h, re=re, cx=0.0, cy=0.0, u_inf=(0.0, 0.0))
+    chord = 1.05
+    npts = int(round(chord / (2.0 * h))) + 1
+    xs = np.linspace(-0.5 * chord, 0.5 * chord, npts)
+    body = MovingRigid(xy_ref=np.stack([xs, np.zeros(npts)], axis=1), ds=chord / (npts - 1),
+                       motion=flapping_motion(sigma_t=sigma, sigma_r=sigma))
+    sd = (-1.95, 1.95, -0.85, 0.85) if subdomain else None
+    return Problem("driven_plate", flow, [body], sd, None, steps)
 
 
 def cylinder(center, diameter, h, spacing=1.0):
