@@ -125,6 +125,21 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
 ib_status ib_add_rigid(ib_solver* s, int32_t m, const double* xy, double ds,
                        const double* u_b, int32_t* body_id);
 
+/* Pose of a rigid body's frame at time t and its rates: pose[0..5] = x, y, angle, vx, vy,
+ * omega.  Called on the thread that calls ib_prepare / ib_step. */
+typedef void (*ib_motion_fn)(double t, double* pose, void* ctx);
+
+/* Rigid body in prescribed motion (Sec. 2.1, eq. (5): a rigid body moves with a prescribed
+ * velocity; the driven plate of Sec. 5.1): m points xy_ref[2m] in the body frame, arc length
+ * per point ds.  Before each step the library calls motion(t_{n+1}, pose, ctx) and enforces
+ * no-slip at the points (x, y) + R(angle) xy_ref with velocity (vx, vy) + omega e_z x
+ * (R(angle) xy_ref).  In sub-domain mode the points are interpolated through P like the
+ * other moving points and must stay inside the sub-domain.  ib_read_deflection returns
+ * the point positions (2m, as xy) at the last step's time level.  Errors: IB_ERR_ARG for
+ * m < 1, ds <= 0 or no callback; IB_ERR_NONFINITE if a returned pose is not finite. */
+ib_status ib_add_moving_rigid(ib_solver* s, int32_t m, const double* xy_ref, double ds,
+                              ib_motion_fn motion, void* ctx, int32_t* body_id);
+
 /* Torsionally hinged flat plate of m points at hinge + j ds (cos, sin)(theta0 + theta),
  * j = 0 .. m-1, ds = length / (m - 1); moment of inertia, spring stiffness and
  * damping about the hinge; initial deflection theta and rate phi.  Eqs. (3), (6),

@@ -44,6 +44,7 @@ class IbConfig(ctypes.Structure):
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+MOTION_FN = ctypes.CFUNCTYPE(None, c_double, POINTER(c_double), c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
 
 
@@ -85,6 +86,8 @@ _SIGS = {
     "ib_add_rigid": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, POINTER(c_double),
                                POINTER(c_int32)]),
     "ib_add_torsional": (c_int32, [c_void_p, c_int32] + [c_double] * 9 + [POINTER(c_int32)]),
+    "ib_add_moving_rigid": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, MOTION_FN,
+                                      c_void_p, POINTER(c_int32)]),
     "ib_add_deformable": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, c_double,
                                     c_double, POINTER(c_double), POINTER(c_double),
                                     POINTER(c_int32)]),
@@ -224,9 +227,23 @@ class Solver:
                                   c_void_p(self.stream.cuda_stream if self.stream is not False else 0),
                                   byref(self.handle)), "ib_create")
         self.npts = []
+        self._motion_cbs = []  # keep the callbacks alive as long as the solver
         for b in problem.bodies:
             bid = c_int32()
-            if isinstance(b, W.Rigid):
+            if isinstance(b, W.MovingRigid):
+                ref = _f64(b.xy_ref)
+
+                def _cb(t, pose, ctx, body=b):
+                    q = body.pose(t)
+                    for k in range(6):
+                        pose[k] = q[k]
+
+                cb = MOTION_FN(_cb)
+                self._motion_cbs.append(cb)
+                _check(self.lib.ib_add_moving_rigid(self.handle, ref.shape[0], _dptr(ref), b.ds, cb,
+                                                    None, byref(bid)), "ib_add_moving_rigid")
+                self.npts.append(ref.shape[0])
+            elif isinstance(b, W.Rigid):
                 xy = _f64(b.xy)
                 ub = None if b.u_b is None else _f64(b.u_b)
                 _check(self.lib.ib_add_rigid(self.handle, xy.shape[0], _dptr(xy), b.ds,

@@ -105,6 +105,12 @@ __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, do
   if (b.kind == BODY_RIGID) {
     *px = a.rigid_xy[2 * (b.pt0 + local)];
     *py = a.rigid_xy[2 * (b.pt0 + local) + 1];
+  } else if (b.kind == BODY_MOVING) {
+    const double* q = a.poses + 6 * b.tors;
+    const double rx = a.rigid_xy[2 * (b.pt0 + local)], ry = a.rigid_xy[2 * (b.pt0 + local) + 1];
+    const double c = cos(q[2]), sn = sin(q[2]);
+    *px = q[0] + c * rx - sn * ry;
+    *py = q[1] + sn * rx + c * ry;
   } else if (b.kind == BODY_TORSIONAL) {
     const double* ts = a.tors + b.tors * TS_COUNT;
     const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
@@ -119,7 +125,41 @@ __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, do
   }
 }
 
-// Body operator rows and u* for every point; one thread per point.
+// The structural part subtracted from row (comp, local) of the Schur right-hand side:
+//   rigid       the prescribed velocity u_b (if any)
+//   moving      (vx, vy) + omega e_z x (R(angle) xy_ref) at t_{n+1}
+//   torsional   S ((2/dt) r_phi / J - r_theta)
+//   deformable  0 here; k_beam subtracts T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
+__device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, int comp) {
+  const int m = b.npts;
+  if (b.kind == BODY_RIGID) {
+    return b.has_ub ? a.rigid_ub[2 * (b.pt0 + local) + comp] : 0.0;
+  } else if (b.kind == BODY_MOVING) {
+    const double* q = a.poses + 6 * b.tors;
+    const double c = cos(q[2]), sn = sin(q[2]);
+    const double rx = a.rigid_xy[2 * (b.pt0 + local)], ry = a.rigid_xy[2 * (b.pt0 + local) + 1];
+    const double wx = c * rx - sn * ry, wy = sn * rx + c * ry;
+    return comp == 0 ? q[3] - q[5] * wy : q[4] + q[5] * wx;
+  } else if (b.kind == BODY_TORSIONAL) {
+    const double dt = a.dt;
+    const double* ts = a.tors + b.tors * TS_COUNT;
+    const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
+    const double ang = b.theta0 + th;
+    const double sn = sin(ang), cs = cos(ang);
+    const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
+    const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
+                        b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
+    const double rth = ts[TS_PHI] + 2.0 * ts[TS_THETA] / dt;
+    const double rc = (2.0 / dt) * rphi / jt - rth;
+    const double su = (comp == 0 ? -sn : cs) * local * b.ds;
+    (void)m;
+    return su * rc;
+  }
+  return 0.0;
+}
+
+// Body operator rows, u* and the Schur right-hand side for every point (one thread per
+// point); point 0 also clears the convergence maximum that k_update folds into.
 template <typename T>
 __global__ void k_body_ops(FsiArgs a) {
   if (iter_gated(a.gate)) return;
@@ -129,6 +169,7 @@ __global__ void k_body_ops(FsiArgs a) {
   while (bi + 1 < a.nbodies && a.bodies[bi + 1].pt0 <= p) ++bi;
   const BodyDev& b = a.bodies[bi];
   const int local = p - b.pt0;
+  if (p == 0) a.delta[0] = 0.0;
   double px, py;
   point_position(a, b, local, &px, &py);
   a.pos[2 * p] = px;
@@ -198,15 +239,26 @@ __global__ void k_body_ops(FsiArgs a) {
     a.st_base[3 * row] = base[0];
     a.st_base[3 * row + 1] = base[1];
     a.st_base[3 * row + 2] = comp;
+    // all 16 face fluxes of the window are loaded at once, then summed in window order;
+    // indices are clamped to [0, n-1] (every access stays inside the (n+1)-row array):
+    // that changes none of the nonzero-weight faces (window_ok), and the others carry
+    // weight 0 on a finite value
+    double fl[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int fi = min(max(base[0] + (e & 3), 0), a.n - 1);
+      const int fj = min(max(base[1] + (e >> 2), 0), a.n - 1);
+      fl[e] = face_flux(s, a.ps, comp, fi, fj, a.ux, a.uy);
+    }
     double acc = 0.0;
-    for (int dj = 0; dj < 4; ++dj)
-      for (int di = 0; di < 4; ++di) {
-        const double ww = w[dj * 4 + di];
-        a.st_w[16 * row + dj * 4 + di] = ww;
-        if (ww != 0.0)
-          acc += ww * face_flux(s, a.ps, comp, base[0] + di, base[1] + dj, a.ux, a.uy);
-      }
-    a.ustar[row] = acc / a.h;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      a.st_w[16 * row + e] = w[e];
+      acc += w[e] * fl[e];
+    }
+    const double us = acc / a.h;
+    a.ustar[row] = us;
+    a.rhs[row] = us - rhs_body_term(a, b, local, comp);
   }
 }
 
@@ -229,17 +281,83 @@ __device__ __forceinline__ int row_body(const FsiArgs& a, int row) {
 //   from the columns J_d^{-1} T^T that k_beam left in ywork (so it runs first).
 // For each of the (up to 4) B' rows that P uses in row a, the CSR row is scanned once
 // and the entries in columns that P uses anywhere are scattered into an LDS vector
-// indexed by the P slot that names the column (act/canon, set by k_body_ops and
-// k_structure); row a of P B' P^T is then a gather from that vector.
+// indexed by the P slot that names the column (act, set by k_body_ops: one slot per used
+// B' row; each slot's canonical id is the act entry of its row); row a of P B' P^T is then
+// a gather from that vector.  With all4 (when the LDS allows) the four CSR rows are
+// scanned together into four vectors.
 // Dynamic LDS: acc, pw (4 nf doubles each), cid, pidx (4 nf ints each).
 constexpr int SCHUR_NT = 256;
 constexpr int SCHUR_CPT = 8;  // columns per thread: nf <= 2048
-__global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a) {
+__global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a, int all4) {
   if (iter_gated(a.gate)) return;
   extern __shared__ double ssm[];
   const int nf = a.nf, ns = 4 * nf, r = blockIdx.x, tid = threadIdx.x;
   double m[SCHUR_CPT];
-  if (a.gx != nullptr) {
+  if (a.gx == nullptr && all4) {
+    // the CSR rows of all four hat points of row r are scanned together into four LDS
+    // vectors (one round of dependent loads instead of four)
+    double* acc = ssm;  // 4 x ns
+    double* pw = acc + 4 * ns;
+    int* cid = reinterpret_cast<int*>(pw + ns);
+    int* pidx = cid + ns;
+    for (int e = tid; e < ns; e += SCHUR_NT) {
+      const double w = a.p_w[e];
+      const int pi = a.p_idx[e];
+      pw[e] = w;
+      pidx[e] = pi;
+      cid[e] = w != 0.0 ? a.act[pi] : -1;  // the slot that names this B' row (act)
+    }
+    for (int e = tid; e < 4 * ns; e += SCHUR_NT) acc[e] = 0.0;
+    __syncthreads();
+    double wu[4];
+    int64_t lo[4], off[5];
+    off[0] = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      wu[u] = pw[4 * r + u];
+      const int cu = pidx[4 * r + u];
+      lo[u] = wu[u] != 0.0 ? a.bp_ptr[cu] : 0;
+      const int64_t hi = wu[u] != 0.0 ? a.bp_ptr[cu + 1] : 0;
+      off[u + 1] = off[u] + (hi - lo[u]);
+    }
+    constexpr int Q = 8;
+    for (int64_t e0 = 0; e0 < off[4]; e0 += (int64_t)Q * SCHUR_NT) {
+      int j[Q], id[Q], uq[Q];
+      double v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t e = e0 + tid + (int64_t)q * SCHUR_NT;
+        const int u = e < off[1] ? 0 : (e < off[2] ? 1 : (e < off[3] ? 2 : 3));
+        const int64_t src = lo[u] + (e - off[u]);
+        uq[q] = u;
+        j[q] = e < off[4] ? a.bp_col[src] : -1;
+        v[q] = e < off[4] ? a.bp_val[src] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) id[q] = j[q] >= 0 ? a.act[j[q]] : -1;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (id[q] >= 0 && id[q] < ns && pw[id[q]] != 0.0 && pidx[id[q]] == j[q])
+          acc[uq[q] * ns + id[q]] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCHUR_CPT; ++k) {
+      m[k] = 0.0;
+      const int c = tid + k * SCHUR_NT;
+      if (c >= nf) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (wu[u] == 0.0) continue;
+        double inner = 0.0;
+        for (int w = 0; w < 4; ++w) {
+          const double wv = pw[4 * c + w];
+          if (wv != 0.0) inner += wv * acc[u * ns + cid[4 * c + w]];
+        }
+        m[k] += wu[u] * inner;
+      }
+    }
+  } else if (a.gx != nullptr) {
     // exact operator of this iterate (moving bodies without a sub-domain)
 #pragma unroll
     for (int k = 0; k < SCHUR_CPT; ++k) {
@@ -252,9 +370,11 @@ __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a) {
     int* cid = reinterpret_cast<int*>(pw + ns);
     int* pidx = cid + ns;
     for (int e = tid; e < ns; e += SCHUR_NT) {
-      pw[e] = a.p_w[e];
-      cid[e] = a.canon[e];
-      pidx[e] = a.p_idx[e];
+      const double w = a.p_w[e];
+      const int pi = a.p_idx[e];
+      pw[e] = w;
+      pidx[e] = pi;
+      cid[e] = w != 0.0 ? a.act[pi] : -1;
     }
     __syncthreads();
 #pragma unroll
@@ -306,7 +426,7 @@ __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a) {
     const BodyDev& b = a.bodies[bc];
     double mv = (a.dt / (a.h * a.h)) * m[k] * b.ds;
     const int r0 = 2 * b.pt0, mpts = b.npts;
-    if (r >= r0 && r < r0 + 2 * mpts && b.kind != BODY_RIGID) {
+    if (r >= r0 && r < r0 + 2 * mpts && (b.kind == BODY_TORSIONAL || b.kind == BODY_DEFORMABLE)) {
       const int u = r - r0, v = c - r0;
       const double coef = 2.0 * b.ds / a.dt;
       if (b.kind == BODY_TORSIONAL) {
@@ -376,50 +496,6 @@ __device__ void beam_element(const double* x, double l0, double beta0, double ea
 constexpr int MAX_BEAM_DOF = 600;  // free DOFs of one deformable body (<= 201 nodes)
 
 constexpr int STRUCT_NT = 256;
-
-// Structural part of the Schur right-hand side (one workgroup); the structural blocks
-// of the matrix are added by k_schur_sd, which runs after this kernel.
-//   rigid       rhs -= u_b
-//   torsional   rhs -= S ((2/dt) r_phi / J - r_theta)
-//   deformable  handled by k_beam and k_struct_rhs_def
-__global__ __launch_bounds__(STRUCT_NT) void k_structure(FsiArgs a, int flow_in_M) {
-  if (iter_gated(a.gate)) return;
-  const int tid = threadIdx.x;
-  (void)flow_in_M;  // the flow block is either already in M or not used (stationary inverse)
-  if (tid == 0) a.delta[0] = 0.0;  // k_update folds its maxima in with atomicMax
-  for (int r = tid; r < a.nf; r += STRUCT_NT) a.rhs[r] = a.ustar[r];
-  if (a.act != nullptr)
-    for (int e = tid; e < 4 * a.nf; e += STRUCT_NT)
-      a.canon[e] = a.p_w[e] != 0.0 ? a.act[a.p_idx[e]] : -1;
-  __syncthreads();
-  const double dt = a.dt;
-  for (int bi = 0; bi < a.nbodies; ++bi) {
-    const BodyDev& b = a.bodies[bi];
-    const int m = b.npts, r0 = 2 * b.pt0;
-    if (b.kind == BODY_RIGID) {
-      if (b.has_ub)
-        for (int e = tid; e < 2 * m; e += STRUCT_NT) {
-          const int pt = b.pt0 + (e % m);
-          a.rhs[r0 + e] -= a.rigid_ub[2 * pt + e / m];
-        }
-    } else if (b.kind == BODY_TORSIONAL) {
-      const double* ts = a.tors + b.tors * TS_COUNT;
-      const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
-      const double ang = b.theta0 + th;
-      const double sn = sin(ang), cs = cos(ang);
-      const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
-      const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
-                          b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
-      const double rth = ts[TS_PHI] + 2.0 * ts[TS_THETA] / dt;
-      const double rc = (2.0 / dt) * rphi / jt - rth;
-      for (int e = tid; e < 2 * m; e += STRUCT_NT) {
-        const double su = (e < m ? -sn : cs) * (e % m) * b.ds;
-        a.rhs[r0 + e] -= su * rc;
-      }
-    }
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------ beam Jacobian: cyclic reduction
 // J_d = 4 M/dt^2 + K(chi^k) over the free nodes is block tridiagonal with 3 x 3 blocks
@@ -605,6 +681,23 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
     const int u = t / NC, col = c0 + t % NC;
     if (col < ncol) y[(size_t)u * ncol + col] = rhs[t];
   }
+  // the workgroup that solved J_d^{-1} res (column 2m) adds the deformable part of the
+  // Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
+  if (c0 <= 2 * m && 2 * m < c0 + NC) {
+    const int cl = 2 * m - c0, r0 = 2 * b.pt0;
+    const double dt = a.dt;
+    const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
+    const double* xn = a.chi + b.dof0;
+    const double* zn = a.zeta + b.dof0;
+    for (int u = tid; u < 2 * m; u += BEAM_NT) {
+      const int node = u % m, cmp = u / m;
+      if (node == 0) continue;
+      const int g = 3 * node + cmp;
+      const double pred = ck[g] + rhs[(g - 3) * NC + cl];
+      const double rchi = zn[g] + 2.0 * xn[g] / dt;
+      a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
+    }
+  }
 }
 
 // LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K); the
@@ -612,26 +705,6 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
 size_t beam_lds_bytes(int m) {
   const size_t K = m - 1;
   return (size_t)(54 * K + 3 * K * BEAM_NC + 3 * K) * 8;
-}
-
-// Deformable part of the Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi).
-__global__ void k_struct_rhs_def(FsiArgs a, int bi) {
-  if (iter_gated(a.gate)) return;
-  const BodyDev& b = a.bodies[bi];
-  const int m = b.npts, ncol = 2 * m + 1, r0 = 2 * b.pt0;
-  const double dt = a.dt;
-  const double* y = a.ywork + b.yoff;
-  const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
-  const double* xn = a.chi + b.dof0;
-  const double* zn = a.zeta + b.dof0;
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < 2 * m; u += gridDim.x * blockDim.x) {
-    const int node = u % m, cmp = u / m;
-    if (node == 0) continue;
-    const int g = 3 * node + cmp;
-    const double pred = ck[g] + y[(size_t)(g - 3) * ncol + 2 * m];
-    const double rchi = zn[g] + 2.0 * xn[g] / dt;
-    a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
-  }
 }
 
 constexpr int LU_NT = 1024;
@@ -737,7 +810,7 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
 }
 
 // Structure update from the new stresses and the convergence measure max |delta|,
-// folded into delta[0] (zeroed by k_structure) with atomicMax on the bit pattern of the
+// folded into delta[0] (zeroed by k_body_ops) with atomicMax on the bit pattern of the
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
 __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
@@ -1476,13 +1549,11 @@ hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, dou
 }
 
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
-  const size_t lds = a.gx != nullptr ? 8 : (size_t)a.nf * SCHUR_LDS_PER_ROW;
+  size_t lds = a.gx != nullptr ? 8 : (size_t)a.nf * SCHUR_LDS_PER_ROW;
   if (lds > SCHUR_LDS_MAX || a.nf > SCHUR_CPT * SCHUR_NT) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_schur_sd, dim3(a.nf), dim3(SCHUR_NT), lds, st, a);
-  return hipGetLastError();
-}
-hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st) {
-  hipLaunchKernelGGL(k_structure, dim3(1), dim3(STRUCT_NT), 0, st, a, flow_in_M);
+  const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
+  if (all4) lds = (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4;
+  hipLaunchKernelGGL(k_schur_sd, dim3(a.nf), dim3(SCHUR_NT), lds, st, a, all4);
   return hipGetLastError();
 }
 hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,
@@ -1501,7 +1572,6 @@ hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
   const size_t lds = beam_lds_bytes(m);
   if (m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_beam, dim3((ncol + BEAM_NC - 1) / BEAM_NC), dim3(BEAM_NT), lds, st, a, bi);
-  hipLaunchKernelGGL(k_struct_rhs_def, dim3(1), dim3(256), 0, st, a, bi);
   return hipGetLastError();
 }
 hipError_t launch_update(const FsiArgs& a, hipStream_t st) {

@@ -5,7 +5,7 @@
 
 namespace ib {
 
-enum { BODY_RIGID = 0, BODY_TORSIONAL = 1, BODY_DEFORMABLE = 2 };
+enum { BODY_RIGID = 0, BODY_TORSIONAL = 1, BODY_DEFORMABLE = 2, BODY_MOVING = 3 };
 
 // Per-body data in device memory (double precision throughout).
 struct BodyDev {
@@ -13,7 +13,7 @@ struct BodyDev {
   int npts;   // m
   int pt0;    // first point in the solver-wide point list; its rows start at 2 * pt0
   int app0;   // sub-domain mode: first appended sub-domain point of a rigid body
-  int tors;   // index into the torsional state array
+  int tors;   // index into the torsional state array; BODY_MOVING: index of its pose
   int dof0;   // deformable: offset of node 0's DOFs in the DOF arrays (3 per node)
   int has_ub; // rigid: prescribed velocity present
   int64_t yoff; // deformable: offset of its J_d^{-1} T^T workspace
@@ -60,8 +60,9 @@ struct FsiArgs {
   const int32_t* bp_col;
   const double* bp_val;
   // rigid geometry and prescribed velocities (2 per point, per body at pt0)
-  const double* rigid_xy;
+  const double* rigid_xy;   // BODY_MOVING: body-frame coordinates
   const double* rigid_ub;
+  const double* poses;      // BODY_MOVING: x, y, angle, vx, vy, omega at t_{n+1}, 6 per body
   // per-row operator: window base (i0, j0) and 4 x 4 weights; P (4 entries)
   int* st_base;
   double* st_w;
@@ -69,7 +70,6 @@ struct FsiArgs {
   double* p_w;
   const double* gx;    // exact mode with moving bodies: E C K C^T E^T of this iterate (pitch pm)
   int* act;            // per B' row: a slot e (= 4 row + corner) of P that uses it
-  int* canon;          // per slot of P: the slot act[] names for its B' row (-1 if weight 0)
   double* pos;         // current point positions (2 per point)
   // FSI vectors and matrix
   double* ustar;       // (1/h) E (C s* + q_inf)
@@ -114,12 +114,12 @@ template <typename T>
 hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st);
 // LDS of the sub-domain Schur assembly per body row (acc, pw, cid, pidx) and its cap
 constexpr size_t SCHUR_LDS_PER_ROW = 4 * (8 + 8 + 4 + 4);
+constexpr size_t SCHUR_LDS_PER_ROW_ALL4 = 4 * (4 * 8 + 8 + 4 + 4);  // four hat points at once
 constexpr size_t SCHUR_LDS_MAX = 150 * 1024;
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st);
 // G[t][c0 + b] = vals[b][t] for the ns point-source columns of one offline batch
 hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, double* G, int pm,
                                  hipStream_t st);
-hipError_t launch_structure(const FsiArgs& a, int flow_in_M, hipStream_t st);
 hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,
                            hipStream_t st);
 hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st);

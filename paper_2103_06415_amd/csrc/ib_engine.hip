@@ -115,6 +115,9 @@ struct HostBody {
   double theta = 0, phi = 0;                        // torsional
   std::vector<double> xy_ref, xy0, rot0;            // deformable
   double mass = 0, ei = 0, ea = 0;
+  ib_motion_fn motion = nullptr;                    // moving rigid: pose callback
+  void* motion_ctx = nullptr;
+  double pose[6] = {0, 0, 0, 0, 0, 0};              // its pose at the last step's time
 };
 
 struct LevelState {
@@ -225,6 +228,8 @@ struct ib_solver {
   bool x_valid_retry = false;
   int* gate = nullptr;      // device gates of the FSI iterations launched ahead (in ctl)
   bool fsi_ahead = true;    // launch a step's FSI iterations ahead of their tests
+  int nmov = 0;             // rigid bodies in prescribed motion
+  double* hpose = nullptr;  // pinned staging of their poses, two sets (alternate steps)
   bool graphs = true;       // replay recorded steps as HIP graphs
   StepGraph step_graphs[2]; // by ring-buffer alternation
   int64_t graph_captures = 0, graph_launches = 0, fsi_resumes = 0;
@@ -612,6 +617,33 @@ ib_status acquire_op(ib_solver* s, const std::vector<double>& key, F build) {
   return IB_OK;
 }
 
+// Poses of the rigid bodies in prescribed motion at time t (x, y, angle, vx, vy, omega from
+// their callbacks) into the device array the FSI kernels read; the staging alternates
+// between two pinned sets, so a copy still pending from the previous step is not
+// overwritten.
+ib_status update_poses(ib_solver* s, double t) {
+  if (!s->nmov) return IB_OK;
+  double* hp = s->hpose + (size_t)6 * s->nmov * (s->step & 1);
+  int k = 0;
+  for (auto& hb : s->bodies) {
+    if (hb.kind != BODY_MOVING) continue;
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    hb.motion(t, q, hb.motion_ctx);
+    for (int e = 0; e < 6; ++e) {
+      if (!std::isfinite(q[e])) {
+        s->last_error = "non-finite pose from a motion callback";
+        return IB_ERR_NONFINITE;
+      }
+      hp[6 * k + e] = q[e];
+      hb.pose[e] = q[e];
+    }
+    ++k;
+  }
+  HIPCHK(hipMemcpyAsync(const_cast<double*>(s->fa.poses), hp, (size_t)6 * s->nmov * 8,
+                        hipMemcpyHostToDevice, s->stream));
+  return IB_OK;
+}
+
 template <typename T>
 ib_status prepare_bodies(ib_solver* s) {
   const int n = s->n;
@@ -621,7 +653,7 @@ ib_status prepare_bodies(ib_solver* s) {
   // ---- host-side layout
   std::vector<BodyDev> bd;
   std::vector<double> rigid_xy, rigid_ub, tors, chi, dmass, l0v, beta0v, appxy;
-  int pt = 0, app = 0, ntors = 0, dof = 0;
+  int pt = 0, app = 0, ntors = 0, dof = 0, nmov = 0;
   int64_t yoff = 0;
   bool any_moving = false;
   s->ds_rows.clear();
@@ -644,6 +676,10 @@ ib_status prepare_bodies(ib_solver* s) {
       b.app0 = app;
       for (int k = 0; k < 2 * hb.m; ++k) appxy.push_back(hb.xy[k]);
       app += hb.m;
+    } else if (hb.kind == BODY_MOVING) {
+      any_moving = true;
+      b.tors = nmov++;
+      for (int k = 0; k < 2 * hb.m; ++k) rigid_xy[2 * pt + k] = hb.xy[k];  // body frame
     } else if (hb.kind == BODY_TORSIONAL) {
       any_moving = true;
       b.tors = ntors++;
@@ -735,8 +771,6 @@ ib_status prepare_bodies(ib_solver* s) {
       xmin = std::min(xmin, x); xmax = std::max(xmax, x);
       ymin = std::min(ymin, y); ymax = std::max(ymax, y);
     };
-    for (int k = 0; k < (int)rigid_xy.size() / 2; ++k)
-      if (rigid_xy[2 * k] != 0.0 || rigid_xy[2 * k + 1] != 0.0) acc(rigid_xy[2 * k], rigid_xy[2 * k + 1]);
     for (auto& hb : s->bodies) if (hb.kind == BODY_RIGID) for (int k = 0; k < hb.m; ++k) acc(hb.xy[2 * k], hb.xy[2 * k + 1]);
     if (s->use_sd) {
       acc(x0 + s->sd_i0 * h, y0 + s->sd_j0 * h);
@@ -788,12 +822,22 @@ ib_status prepare_bodies(ib_solver* s) {
   a.app_xy = up(appxy);
   a.rigid_xy = up(rigid_xy);
   a.rigid_ub = up(rigid_ub);
+  s->nmov = nmov;
+  a.poses = nullptr;
+  if (nmov) {
+    a.poses = static_cast<double*>(dalloc(s, (size_t)6 * nmov * 8));
+    if (!a.poses) return IB_ERR_OOM;
+    if (!s->hpose) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->hpose), (size_t)12 * nmov * 8,
+                                        hipHostMallocDefault));
+    ib_status pst = update_poses(s, (s->step + 1) * s->cfg.dt);
+    if (pst) return pst;
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
   const int nf = s->nf;
   a.st_base = static_cast<int*>(dalloc(s, (size_t)nf * 3 * 4));
   a.st_w = static_cast<double*>(dalloc(s, (size_t)nf * 16 * 8));
   a.p_idx = static_cast<int*>(dalloc(s, (size_t)nf * 4 * 4));
   a.p_w = static_cast<double*>(dalloc(s, (size_t)nf * 4 * 8));
-  a.canon = static_cast<int*>(dalloc(s, (size_t)nf * 4 * 4));
   a.act = nullptr;
   if (s->use_sd) {
     if ((size_t)nf * SCHUR_LDS_PER_ROW > SCHUR_LDS_MAX) {
@@ -1052,7 +1096,6 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it) {
   const int n = s->n, nf = s->nf;
   TimeScope ts(s, IB_K_FSI);
   HIPCHK(launch_body_ops<T>(a, s->stream));
-  HIPCHK(launch_structure(a, 1, s->stream));
   for (size_t bi = 0; bi < s->bodies.size(); ++bi)
     if (s->bodies[bi].kind == BODY_DEFORMABLE)
       HIPCHK(launch_beam(a, (int)bi, s->bodies[bi].m, s->stream));
@@ -1201,7 +1244,6 @@ ib_status fsi_host(ib_solver* s, int it0) {
       b.iter = 0;
       TimeScope ts(s, IB_K_FSI);
       HIPCHK(launch_body_ops<T>(b, s->stream));
-      HIPCHK(launch_structure(b, 0, s->stream));
       HIPCHK(launch_matvec(s->Minv, b.pm, s->rhs, s->f, s->nf, s->stream));
       s->iters_last = 1;
       s->delta_last = 0.0;
@@ -1432,6 +1474,10 @@ template <typename T>
 ib_status do_step(ib_solver* s) {
   const int G = (int)s->lv.size();
   const bool bodies = !s->bodies.empty();
+  if (s->nmov) {
+    ib_status pst = update_poses(s, (s->step + 1) * s->cfg.dt);  // constraint at t_{n+1}
+    if (pst) return pst;
+  }
   const bool ahead = bodies && fsi_ahead(s);
   const bool sync_free = !bodies || s->stationary || ahead;
   const int K = ahead ? fsi_ahead_count(s) : 0;
@@ -1782,6 +1828,22 @@ ib_status ib_add_rigid(ib_solver* s, int32_t m, const double* xy, double ds, con
   return IB_OK;
 }
 
+ib_status ib_add_moving_rigid(ib_solver* s, int32_t m, const double* xy_ref, double ds,
+                              ib_motion_fn motion, void* ctx, int32_t* body_id) {
+  if (check(s) || m < 1 || !xy_ref || !(ds > 0) || !motion) return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  HostBody b;
+  b.kind = BODY_MOVING;
+  b.m = m;
+  b.ds = ds;
+  b.xy.assign(xy_ref, xy_ref + 2 * m);
+  b.motion = motion;
+  b.motion_ctx = ctx;
+  s->bodies.push_back(b);
+  if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
+  return IB_OK;
+}
+
 ib_status ib_add_torsional(ib_solver* s, int32_t m, double hinge_x, double hinge_y, double length,
                            double theta0, double inertia, double stiffness, double damping,
                            double theta, double phi, int32_t* body_id) {
@@ -1915,6 +1977,15 @@ ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t
     if (cap < 3 * hb.m) return IB_ERR_CAPACITY;
     if (s->released) std::memcpy(out, s->h_chi.data() + dof, (size_t)3 * hb.m * 8);
     else HIPCHK(hipMemcpy(out, s->fa.chi + dof, (size_t)3 * hb.m * 8, hipMemcpyDeviceToHost));
+  } else if (hb.kind == BODY_MOVING) {
+    // point positions at the pose of the last step's time level
+    if (cap < 2 * hb.m) return IB_ERR_CAPACITY;
+    const double c = std::cos(hb.pose[2]), sn = std::sin(hb.pose[2]);
+    for (int k = 0; k < hb.m; ++k) {
+      const double rx = hb.xy[2 * k], ry = hb.xy[2 * k + 1];
+      out[2 * k] = hb.pose[0] + c * rx - sn * ry;
+      out[2 * k + 1] = hb.pose[1] + sn * rx + c * ry;
+    }
   } else {
     if (cap < 2 * hb.m) return IB_ERR_CAPACITY;
     std::memcpy(out, hb.xy.data(), (size_t)2 * hb.m * 8);
@@ -2224,6 +2295,7 @@ ib_status ib_destroy(ib_solver* s) {
   s->event_pool.clear();
   while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
   if (s->hctl) (void)hipHostFree(s->hctl);
+  if (s->hpose) (void)hipHostFree(s->hpose);
   delete s;
   return IB_OK;
 }
