@@ -315,6 +315,10 @@ ib_status ib_server_destroy(ib_server* sv);
 
 const char* ib_status_str(ib_status st);
 
+/* What the last failing call on this solver reported (empty if none); valid until the
+ * next call on the solver. */
+const char* ib_last_error(const ib_solver* s);
+
 /* ---- operator-level entry points (device pointers, enqueued on hip_stream) ---- */
 
 /* out = [L (I + alpha L)]^{-1} in, L = C^T C with zero boundary values (the solve of

@@ -119,6 +119,7 @@ _SIGS = {
     "ib_server_destroy": (c_int32, [c_void_p]),
     "ib_get_flow_tuning": (c_int32, [c_void_p, POINTER(IbFlowTuning)]),
     "ib_set_option": (c_int32, [c_void_p, c_int32, c_int64]),
+    "ib_last_error": (ctypes.c_char_p, [c_void_p]),
     "ib_set_flow_variants": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "ib_flow_variant_info": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
                                        POINTER(c_int32)]),
@@ -177,7 +178,10 @@ class TorchAllocator:
                 return None
 
         def _free(ptr, ctx):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch is gone, and so is its memory
+                pass
 
         self._alloc = ALLOC_FN(_alloc)
         self._free = FREE_FN(_free)
@@ -325,6 +329,9 @@ class Solver:
         return {"n": t.n, "rhs_variant": t.rhs_variant, "col_variant": t.col_variant,
                 "idst_variant": t.idst_variant, "rhs_us": list(t.rhs_us),
                 "col_us": list(t.col_us), "idst_us": list(t.idst_us)}
+
+    def last_error(self):
+        return self.lib.ib_last_error(self.handle).decode()
 
     def set_option(self, option, value):
         _check(self.lib.ib_set_option(self.handle, option, int(value)), "ib_set_option")

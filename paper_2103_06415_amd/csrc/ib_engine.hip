@@ -22,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -152,6 +153,22 @@ struct FlowTuning {
          idst_us[ib::FLOW_VARIANTS] = {};
 };
 
+// Recording a graph and the library's other HIP calls exclude each other across threads:
+// while a stream records, this runtime rejects synchronising calls (and synchronous copies
+// on the legacy stream) from every thread.  Entry points that call HIP hold the shared
+// side; recording holds the exclusive side.  (HIP calls that the application makes
+// itself on other threads while a solver records are not covered.)
+static std::shared_mutex g_hip_mu;
+std::shared_lock<std::shared_mutex> ib::hip_shared_lock() {
+  return std::shared_lock<std::shared_mutex>(g_hip_mu);
+}
+struct HipShared {
+  std::shared_lock<std::shared_mutex> l{g_hip_mu};
+};
+struct HipExclusive {
+  std::unique_lock<std::shared_mutex> l{g_hip_mu};
+};
+
 // A recorded step: its executable graph and the number of FSI iterations it launches ahead.
 struct StepGraph {
   hipGraphExec_t exec = nullptr;
@@ -232,7 +249,7 @@ struct ib_solver {
   double* hpose = nullptr;  // pinned staging of their poses, two sets (alternate steps)
   bool graphs = true;       // replay recorded steps as HIP graphs
   StepGraph step_graphs[2]; // by ring-buffer alternation
-  int64_t graph_captures = 0, graph_launches = 0, fsi_resumes = 0;
+  int64_t graph_captures = 0, graph_launches = 0, fsi_resumes = 0, graph_failures = 0;
   int inverse_rebuilds = 0;
   // sweeps launched per stress solve in tolerance mode, per FSI iteration index (0, 1, 2, 3+)
   // control block read back once per FSI iteration: error flags (2 ints), max |delta|,
@@ -1470,51 +1487,82 @@ void destroy_graphs(ib_solver* s) {
   }
 }
 
-template <typename T>
-ib_status do_step(ib_solver* s) {
-  const int G = (int)s->lv.size();
+// How the next step runs: FSI iterations launched ahead (and how many), and whether it
+// is replayed from a recorded graph (for which ring-buffer alternation).
+struct StepPlan {
+  bool ahead = false, use_graph = false;
+  int K = 0, parity = 0;
+};
+
+StepPlan plan_step(const ib_solver* s) {
+  StepPlan p;
   const bool bodies = !s->bodies.empty();
+  p.ahead = bodies && fsi_ahead(s);
+  const bool sync_free = !bodies || s->stationary || p.ahead;
+  p.K = p.ahead ? fsi_ahead_count(s) : 0;
+  // (the legacy null stream cannot be recorded)
+  p.use_graph = s->graphs && s->fsi_ahead && sync_free && !s->first && !s->timing &&
+                s->stream != nullptr;
+  p.parity = s->lv.size() > 1 ? s->lv[0].gcur : 0;
+  return p;
+}
+
+bool needs_record(const ib_solver* s, const StepPlan& p) {
+  const StepGraph& sg = s->step_graphs[p.parity];
+  return p.use_graph && (!sg.exec || sg.K != p.K);
+}
+
+// Record the step's launches as a graph (nothing runs).  The caller holds the library's
+// exclusive HIP lock: on this runtime another thread's synchronising calls fail while a
+// stream records.  A failed recording turns graphs off for this solver.
+template <typename T>
+ib_status record_step(ib_solver* s, const StepPlan& p) {
+  StepGraph& sg = s->step_graphs[p.parity];
+  if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+  sg = StepGraph{};
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    ib_status st = enqueue_step<T>(s, p.ahead, p.K);
+    e = hipStreamEndCapture(s->stream, &graph);
+    if (st) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+  }
+  if (e == hipSuccess) {
+    e = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) sg = StepGraph{};
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e == hipSuccess) {
+    sg.K = p.K;
+    s->graph_captures++;
+  } else {
+    (void)hipGetLastError();
+    s->graphs = false;
+    s->graph_failures++;
+  }
+  return IB_OK;
+}
+
+template <typename T>
+ib_status do_step(ib_solver* s, const StepPlan& p) {
+  const int G = (int)s->lv.size();
   if (s->nmov) {
     ib_status pst = update_poses(s, (s->step + 1) * s->cfg.dt);  // constraint at t_{n+1}
     if (pst) return pst;
   }
-  const bool ahead = bodies && fsi_ahead(s);
-  const bool sync_free = !bodies || s->stationary || ahead;
-  const int K = ahead ? fsi_ahead_count(s) : 0;
-  // (the legacy null stream cannot be recorded)
-  const bool use_graph = s->graphs && s->fsi_ahead && sync_free && !s->first && !s->timing &&
-                         s->stream != nullptr;
   ib_status st = IB_OK;
-  if (use_graph) {
-    StepGraph& sg = s->step_graphs[G > 1 ? s->lv[0].gcur : 0];
-    if (!sg.exec || sg.K != K) {
-      if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
-      sg = StepGraph{};
-      hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-      st = enqueue_step<T>(s, ahead, K);
-      const hipError_t e = hipStreamEndCapture(s->stream, &graph);
-      if (st) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
-      }
-      if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
-      const hipError_t e2 = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e2 != hipSuccess) {
-        sg = StepGraph{};
-        return hip_fail(s, e2, "hipGraphInstantiate");
-      }
-      sg.K = K;
-      s->graph_captures++;
-    }
+  const StepGraph& sg = s->step_graphs[p.parity];
+  if (p.use_graph && s->graphs && sg.exec && sg.K == p.K) {
     HIPCHK(hipGraphLaunch(sg.exec, s->stream));
     s->graph_launches++;
   } else {
-    st = enqueue_step<T>(s, ahead, K);
+    st = enqueue_step<T>(s, p.ahead, p.K);
     if (st) return st;
   }
-  if (ahead) {
+  if (p.ahead) {
     HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     int resume = -1;
@@ -1911,6 +1959,7 @@ ib_status ib_set_vorticity(ib_solver* s, int32_t level, const double* omega) {
 }
 
 ib_status ib_prepare(ib_solver* s) {
+  HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
   if (s->prepared || s->released) return IB_ERR_STATE;
   ib_status st = s->allocated ? IB_OK : alloc_state(s);
@@ -1928,7 +1977,16 @@ ib_status ib_step(ib_solver* s, int32_t nsteps) {
   if (check(s) || nsteps < 0) return IB_ERR_ARG;
   if (!s->prepared || s->failed || s->released) return IB_ERR_STATE;
   for (int k = 0; k < nsteps; ++k) {
-    ib_status st = s->fp64 ? do_step<double>(s) : do_step<float>(s);
+    const StepPlan p = plan_step(s);
+    ib_status st = IB_OK;
+    if (needs_record(s, p)) {
+      HipExclusive lk;
+      st = s->fp64 ? record_step<double>(s, p) : record_step<float>(s, p);
+    }
+    if (!st) {
+      HipShared lk;
+      st = s->fp64 ? do_step<double>(s, p) : do_step<float>(s, p);
+    }
     if (st) {
       s->failed = true;
       return st;
@@ -1938,12 +1996,14 @@ ib_status ib_step(ib_solver* s, int32_t nsteps) {
 }
 
 ib_status ib_sync(ib_solver* s) {
+  HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
   hipError_t e = hipStreamSynchronize(s->stream);
   return e == hipSuccess ? IB_OK : hip_fail(s, e, "hipStreamSynchronize");
 }
 
 ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap) {
+  HipShared hip_lock;
   if (check(s) || !f || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
   if (!s->prepared || (!s->f && !s->released)) return IB_ERR_STATE;
   int pt0 = 0;
@@ -1960,6 +2020,7 @@ ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap
 }
 
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap) {
+  HipShared hip_lock;
   if (check(s) || !out || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
   if (!s->prepared) return IB_ERR_STATE;
   if (!s->released) HIPCHK(hipStreamSynchronize(s->stream));
@@ -1994,6 +2055,7 @@ ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t
 }
 
 ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap) {
+  HipShared hip_lock;
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
   if (!s->allocated) return IB_ERR_STATE;
   const int n = s->n;
@@ -2010,7 +2072,7 @@ ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64
   return IB_OK;
 }
 
-ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap) {
+ib_status read_vorticity_impl(ib_solver* s, int32_t level, double* out, int64_t cap) {
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
   const int n = s->n;
   if (cap < (int64_t)(n - 1) * (n - 1)) return IB_ERR_CAPACITY;
@@ -2035,6 +2097,16 @@ ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t ca
   return IB_OK;
 }
 
+ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap) {
+  HipShared hip_lock;
+  return read_vorticity_impl(s, level, out, cap);
+}
+
+const char* ib_last_error(const ib_solver* s) {
+  if (!s) return "null solver";
+  return s->last_error.c_str();
+}
+
 ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   if (check(s) || !out) return IB_ERR_ARG;
   std::memset(out, 0, sizeof(*out));
@@ -2056,6 +2128,7 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
 }
 
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
+  HipShared hip_lock;
   if (check(s) || (value != 0 && value != 1)) return IB_ERR_ARG;
   if (option == IB_OPT_FSI_AHEAD) {
     s->fsi_ahead = value != 0;
@@ -2087,6 +2160,7 @@ ib_status ib_get_flow_tuning(ib_solver* s, ib_flow_tuning* out) {
 }
 
 ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t idst) {
+  HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
   const int32_t v[3] = {rhs, col, idst};
   for (int k = 0; k < 3; ++k) {
@@ -2115,6 +2189,7 @@ ib_status ib_flow_variant_info(int32_t kind, int32_t variant, int32_t* width, in
 }
 
 ib_status ib_set_kernel_timing(ib_solver* s, int32_t enable) {
+  HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
   harvest_events(s);
   s->timing = enable != 0;
@@ -2127,6 +2202,7 @@ ib_status ib_set_kernel_timing(ib_solver* s, int32_t enable) {
 
 ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* launches,
                                double* total_ms) {
+  HipShared hip_lock;
   if (check(s) || kernel_class < 0 || kernel_class >= IB_K_CLASSES || !launches || !total_ms)
     return IB_ERR_ARG;
   harvest_events(s);
@@ -2136,13 +2212,15 @@ ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* laun
 }
 
 ib_status ib_set_stream(ib_solver* s, void* hip_stream) {
+  HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
-  HIPCHK(hipStreamSynchronize(s->stream));
+  if (s->allocated) HIPCHK(hipStreamSynchronize(s->stream));  // work queued on the old stream
   s->stream = static_cast<hipStream_t>(hip_stream);
   return IB_OK;
 }
 
 ib_status ib_release(ib_solver* s) {
+  HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
   if (s->released) return IB_OK;
   if (s->allocated) {
@@ -2159,7 +2237,7 @@ ib_status ib_release(ib_solver* s) {
         HIPCHK(hipMemcpy(s->h_chi.data(), s->fa.chi, s->h_chi.size() * 8, hipMemcpyDeviceToHost));
     }
     std::vector<double> v((size_t)(s->n - 1) * (s->n - 1));
-    ib_status st = ib_read_vorticity(s, 0, v.data(), (int64_t)v.size());
+    ib_status st = read_vorticity_impl(s, 0, v.data(), (int64_t)v.size());
     if (st) return st;
     s->h_vort0.swap(v);
   }
@@ -2287,8 +2365,9 @@ ib_status ib_set_operator_cache(int64_t limit_bytes) {
 }
 
 ib_status ib_destroy(ib_solver* s) {
+  HipShared hip_lock;
   if (!s) return IB_ERR_ARG;
-  (void)hipStreamSynchronize(s->stream);
+  if (s->allocated) (void)hipStreamSynchronize(s->stream);
   destroy_graphs(s);
   harvest_events(s);
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
@@ -2302,6 +2381,7 @@ ib_status ib_destroy(ib_solver* s) {
 
 ib_status ib_op_solve(int32_t n, int32_t precision, double alpha, const void* in, void* out,
                       int32_t pitch, void* hip_stream) {
+  HipShared hip_lock;
   if (!supported_n(n) || !in || !out || pitch < n - 1 ||
       (precision != IB_FP64 && precision != IB_FP32_FLOW))
     return IB_ERR_ARG;

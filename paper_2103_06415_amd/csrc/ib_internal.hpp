@@ -1,6 +1,8 @@
 // Internal interfaces between the kernel files and the host engine.
 #pragma once
 
+#include <shared_mutex>
+
 #include "ib_common.hpp"
 
 namespace ib {
@@ -73,6 +75,8 @@ constexpr FlowVariant COL_VARIANTS[FLOW_VARIANTS] = {
     {4, 256, 16}, {4, 256, 8}, {2, 256, 4},  {4, 512, 16},
     {4, 512, 8},  {4, 1024, 16}, {8, 512, 16}, {8, 1024, 16}};
 bool flow_variant_available(int n, int fp64);
+// Shared side of the lock between graph recording and the library's other HIP calls.
+std::shared_lock<std::shared_mutex> hip_shared_lock();
 // Single-precision launches of configuration var (1 .. FLOW_VARIANTS-1), n >= FLOW_TUNE_MIN_N.
 hipError_t launch_rhs_rowdst_var(const RhsArgs<float>& a, const void* tw, hipStream_t st);
 hipError_t launch_col_solve_var(const ColArgs<float>& a, int n, int batch, const void* tw,

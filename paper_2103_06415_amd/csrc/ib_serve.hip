@@ -19,6 +19,7 @@
 #include <thread>
 #include <vector>
 
+#include "ib_internal.hpp"
 #include "ibfsi.h"
 
 namespace {
@@ -185,6 +186,7 @@ ib_status ib_server_info(ib_server* sv, int64_t ticket, ib_request_info* out) {
 
 ib_status ib_server_destroy(ib_server* sv) {
   if (!sv) return IB_ERR_ARG;
+  auto lk = ib::hip_shared_lock();
   for (auto st : sv->streams) (void)hipStreamDestroy(st);
   delete sv;
   return IB_OK;

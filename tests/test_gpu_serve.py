@@ -101,3 +101,42 @@ def test_admission_respects_the_memory_budget(torch_cuda, gpu_lib):
     for s in solvers:
         s.close()
     server.close()
+
+
+def test_many_concurrent_requests_record_graphs_safely(torch_cuda, gpu_lib):
+    """Twelve requests on six slots: every solver records its steps as graphs while the
+    other slots prepare, step, synchronise and release; all must complete, each result the
+    same as the request run alone."""
+    from paper_2103_06415_amd import binding
+    probs = []
+    for k in range(12):
+        maker = (W.plate_problem, W.flag_problem, W.cylinder_problem)[k % 3]
+        kw = {"n": 64 if k % 2 else 32, "steps": 12 + k}
+        if maker is not W.cylinder_problem:
+            kw["levels"] = 2
+        probs.append((maker(**kw), 12 + k))
+    alone = []
+    for p, steps in probs:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW, torch_alloc=False)
+        s.prepare()
+        s.step(steps)
+        s.sync()
+        alone.append(s.vorticity(0))
+        s.close()
+    server = binding.Server(max_active=6, hbm_budget_bytes=16 << 30, chunk_steps=5)
+    sols, tickets = [], []
+    for k, (p, steps) in enumerate(probs):
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW, torch_alloc=False, stream=False)
+        sols.append(s)
+        tickets.append(server.submit(s, steps, arrival=0.002 * k))
+    server.run()
+    captures = 0
+    for k, (s, t) in enumerate(zip(sols, tickets)):
+        info = server.info(t)
+        assert info["status"] == 0, (k, info, s.last_error())
+        assert np.array_equal(s.vorticity(0), alone[k]), k
+        captures += s.stats()["graph_captures"]
+        s.close()
+    server.close()
+    print(f"  graphs recorded: {captures}", flush=True)
+    assert captures > 0
