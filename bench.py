@@ -24,7 +24,11 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes recorded in
 # profiles/flow_1024x4_fp32_hbm_traffic.md (scaled by a 256 MiB reference copy); valid for
 # the kernels as measured there, at n = 1024 in FP32
-TRAFFIC_PER_LAUNCH = {"col_solve": 13.66e6, "rhs_rowdst": 22.01e6, "row_idst": 17.10e6}
+# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a reference
+# copy; profiles/flow_1024x4_fp32_hbm_traffic.md), by kernel class and the configuration
+# (variant) measured; a configuration without a measurement reports no traffic
+TRAFFIC_PER_LAUNCH = {("col_solve", 0): 13.66e6, ("rhs_rowdst", 0): 22.01e6,
+                      ("row_idst", 0): 17.10e6}
 
 
 def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
@@ -299,6 +303,8 @@ def main():
     flow_classes = ["rhs_rowdst", "col_solve", "row_idst"]
     dom = max(flow_classes, key=lambda c: kt[c][1])
     launches, ms = kt[dom]
+    dom_variant = st32["flow_tuning"][{"rhs_rowdst": "rhs", "col_solve": "col",
+                                       "row_idst": "idst"}[dom] + "_variant"]
     tot_bytes = algorithmic_bytes(dom, n, levels, args.steps, 4, body_rows)
     achieved = tot_bytes / (ms * 1e-3) if ms > 0 else 0.0
     times_ms = {k: round(v[1] / args.steps, 5) for k, v in kt.items()}
@@ -334,7 +340,8 @@ def main():
         "flow_tuning": tuning_summary(st32["flow_tuning"]),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM,
-                     "traffic": (TRAFFIC_PER_LAUNCH.get(dom) if n == 1024 else None),
+                     "traffic": (TRAFFIC_PER_LAUNCH.get((dom, dom_variant)) if n == 1024 else None),
+                     "variant": dom_variant,
                      "bytes_per_launch": tot_bytes / max(launches, 1),
                      "avg_launch_us": 1e3 * ms / max(launches, 1)},
     }

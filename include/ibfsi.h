@@ -212,9 +212,13 @@ ib_status ib_destroy(ib_solver* s);
  *   written).  Both give the same results.
  * IB_OPT_GRAPHS (default 1): with IB_OPT_FSI_AHEAD, record a step's launches once as a HIP
  *   graph (one per alternation of the ring buffers) and replay it for later steps.
+ * IB_OPT_REFRESH_EVERY_ITER (default 0): refresh the approximate Schur inverse (one
+ *   Newton-Schulz step) at every FSI iteration instead of once per step; the refined stress
+ *   solve then needs fewer sweeps.  The solution is the same to round-off either way.
  * Errors: IB_ERR_ARG for an unknown option or value. */
 #define IB_OPT_FSI_AHEAD 1
 #define IB_OPT_GRAPHS 2
+#define IB_OPT_REFRESH_EVERY_ITER 3
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value);
 
 /* ---- measured kernel configurations of the sine transforms ----

@@ -63,7 +63,7 @@ class IbStats(ctypes.Structure):
 
 
 FLOW_VARIANTS = 8
-IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS = 1, 2
+IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS, IB_OPT_REFRESH_EVERY_ITER = 1, 2, 3
 
 
 class IbFlowTuning(ctypes.Structure):

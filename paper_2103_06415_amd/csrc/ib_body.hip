@@ -1372,6 +1372,10 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
 // of lane l is C[i0 + l / 16 + 4 v][j0 + l % 16]); 2 x 2 waves per 32 x 32 workgroup
 // tile; the k loop loads 16 fragments ahead.
 typedef double v4d __attribute__((ext_vector_type(4)));
+// KC k steps (of 4) per chunk, loaded before any is used; for n <= 4 KC the whole k range
+// is one chunk, so each wave waits for memory once.  Two accumulators alternate over k
+// (halving the dependent MFMA chain) and are added at the end.
+template <int KC>
 __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
                                                 int p, int two_minus, const int* gate) {
   if (iter_gated(gate)) return;
@@ -1379,8 +1383,7 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B
   const int i0 = blockIdx.y * 32 + (w >> 1) * 16, j0 = blockIdx.x * 32 + (w & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
   const int ai = i0 + li, bj = j0 + li;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  constexpr int KC = 16;  // k steps of 4 per chunk
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < n; k0 += 4 * KC) {
     double av[KC], bv[KC];
 #pragma unroll
@@ -1390,13 +1393,16 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B
       bv[c] = (bj < n && k < n) ? B[(size_t)k * p + bj] : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < KC; ++c) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c], bv[c], acc, 0, 0, 0);
+    for (int c = 0; c < KC; c += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c], bv[c], acc0, 0, 0, 0);
+      if (c + 1 < KC) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c + 1], bv[c + 1], acc1, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = i0 + lk + 4 * v, j = j0 + li;
     if (i < n && j < n) {
-      double val = acc[v];
+      double val = acc0[v] + acc1[v];
       if (two_minus) val = (i == j ? 2.0 : 0.0) - val;
       C[(size_t)i * p + j] = val;
     }
@@ -1522,7 +1528,10 @@ hipError_t launch_refine(const double* M, int pm, const double* X, const double*
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
                          hipStream_t st, const int* gate) {
   const int nb = (n + 31) / 32;
-  hipLaunchKernelGGL(k_gemm64, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus, gate);
+  if (n <= 4 * 52)
+    hipLaunchKernelGGL(k_gemm64<52>, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus, gate);
+  else
+    hipLaunchKernelGGL(k_gemm64<16>, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus, gate);
   return hipGetLastError();
 }
 

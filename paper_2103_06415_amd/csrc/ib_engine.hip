@@ -156,7 +156,7 @@ struct FlowTuning {
 // Recording a graph and the library's other HIP calls exclude each other across threads:
 // while a stream records, this runtime rejects synchronising calls (and synchronous copies
 // on the legacy stream) from every thread.  Entry points that call HIP hold the shared
-// side; recording holds the exclusive side.  (HIP calls that the application makes
+// side; recording takes the exclusive side when it is free.  (HIP calls that the application makes
 // itself on other threads while a solver records are not covered.)
 static std::shared_mutex g_hip_mu;
 std::shared_lock<std::shared_mutex> ib::hip_shared_lock() {
@@ -164,9 +164,6 @@ std::shared_lock<std::shared_mutex> ib::hip_shared_lock() {
 }
 struct HipShared {
   std::shared_lock<std::shared_mutex> l{g_hip_mu};
-};
-struct HipExclusive {
-  std::unique_lock<std::shared_mutex> l{g_hip_mu};
 };
 
 // A recorded step: its executable graph and the number of FSI iterations it launches ahead.
@@ -248,7 +245,10 @@ struct ib_solver {
   int nmov = 0;             // rigid bodies in prescribed motion
   double* hpose = nullptr;  // pinned staging of their poses, two sets (alternate steps)
   bool graphs = true;       // replay recorded steps as HIP graphs
-  StepGraph step_graphs[2]; // by ring-buffer alternation
+  bool refresh_every_iter = false;  // Newton-Schulz refresh of X at every FSI iteration
+  static constexpr int GRAPH_SLOTS = 4;
+  StepGraph step_graphs[2][GRAPH_SLOTS];  // by ring-buffer alternation, then by K
+  int graph_next[2] = {0, 0};             // slot to reuse next (round robin)
   int64_t graph_captures = 0, graph_launches = 0, fsi_resumes = 0, graph_failures = 0;
   int inverse_rebuilds = 0;
   // sweeps launched per stress solve in tolerance mode, per FSI iteration index (0, 1, 2, 3+)
@@ -1135,7 +1135,7 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it) {
     HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
     s->x_valid = true;
     s->inverse_rebuilds++;
-  } else if (it == 0) {
+  } else if (it == 0 || s->refresh_every_iter) {
     // one Newton-Schulz step towards the new matrix: X <- X (2I - M X)
     HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream, a.gate));
     HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream, a.gate));
@@ -1481,10 +1481,11 @@ ib_status final_transform_level0(ib_solver* s) {
 }
 
 void destroy_graphs(ib_solver* s) {
-  for (auto& g : s->step_graphs) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    g = StepGraph{};
-  }
+  for (auto& row : s->step_graphs)
+    for (auto& g : row) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g = StepGraph{};
+    }
 }
 
 // How the next step runs: FSI iterations launched ahead (and how many), and whether it
@@ -1507,9 +1508,14 @@ StepPlan plan_step(const ib_solver* s) {
   return p;
 }
 
+const StepGraph* find_graph(const ib_solver* s, const StepPlan& p) {
+  for (const StepGraph& g : s->step_graphs[p.parity])
+    if (g.exec && g.K == p.K) return &g;
+  return nullptr;
+}
+
 bool needs_record(const ib_solver* s, const StepPlan& p) {
-  const StepGraph& sg = s->step_graphs[p.parity];
-  return p.use_graph && (!sg.exec || sg.K != p.K);
+  return p.use_graph && find_graph(s, p) == nullptr;
 }
 
 // Record the step's launches as a graph (nothing runs).  The caller holds the library's
@@ -1517,7 +1523,9 @@ bool needs_record(const ib_solver* s, const StepPlan& p) {
 // stream records.  A failed recording turns graphs off for this solver.
 template <typename T>
 ib_status record_step(ib_solver* s, const StepPlan& p) {
-  StepGraph& sg = s->step_graphs[p.parity];
+  int& next = s->graph_next[p.parity];
+  StepGraph& sg = s->step_graphs[p.parity][next];
+  next = (next + 1) % ib_solver::GRAPH_SLOTS;
   if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
   sg = StepGraph{};
   hipGraph_t graph = nullptr;
@@ -1554,9 +1562,9 @@ ib_status do_step(ib_solver* s, const StepPlan& p) {
     if (pst) return pst;
   }
   ib_status st = IB_OK;
-  const StepGraph& sg = s->step_graphs[p.parity];
-  if (p.use_graph && s->graphs && sg.exec && sg.K == p.K) {
-    HIPCHK(hipGraphLaunch(sg.exec, s->stream));
+  const StepGraph* sg = p.use_graph && s->graphs ? find_graph(s, p) : nullptr;
+  if (sg) {
+    HIPCHK(hipGraphLaunch(sg->exec, s->stream));
     s->graph_launches++;
   } else {
     st = enqueue_step<T>(s, p.ahead, p.K);
@@ -1980,8 +1988,10 @@ ib_status ib_step(ib_solver* s, int32_t nsteps) {
     const StepPlan p = plan_step(s);
     ib_status st = IB_OK;
     if (needs_record(s, p)) {
-      HipExclusive lk;
-      st = s->fp64 ? record_step<double>(s, p) : record_step<float>(s, p);
+      // only when no other thread is inside the library's HIP calls: recording never
+      // waits (under load from other solvers the step simply runs without a graph)
+      std::unique_lock<std::shared_mutex> lk(g_hip_mu, std::try_to_lock);
+      if (lk.owns_lock()) st = s->fp64 ? record_step<double>(s, p) : record_step<float>(s, p);
     }
     if (!st) {
       HipShared lk;
@@ -2137,6 +2147,11 @@ ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
   }
   if (option == IB_OPT_GRAPHS) {
     s->graphs = value != 0;
+    destroy_graphs(s);
+    return IB_OK;
+  }
+  if (option == IB_OPT_REFRESH_EVERY_ITER) {
+    s->refresh_every_iter = value != 0;
     destroy_graphs(s);
     return IB_OK;
   }
