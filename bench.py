@@ -49,11 +49,12 @@ def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
     return 0
 
 
-def run(problem, precision, steps, warmup, timing=True):
+def run(problem, precision, steps, warmup, timing=True, graphs=False):
     import torch
     from paper_2103_06415_amd import binding
-    # a stream of its own: steps on it are recorded once and replayed as HIP graphs
+    # a stream of its own (which graph recording needs)
     s = binding.Solver(problem, precision=precision, stream=torch.cuda.Stream())
+    s.set_option(binding.IB_OPT_GRAPHS, 1 if graphs else 0)
     t0 = time.perf_counter()
     s.prepare()
     s.sync()
@@ -291,6 +292,10 @@ def main():
     if not args.no_fp64:
         wall64, prep64, _, _ = run(prob, binding.IB_FP64, args.steps, args.warmup, timing=False)
         value64 = cells * args.steps / wall64
+    # the same step replayed from recorded HIP graphs
+    wall_g, _, _, st_g = run(prob, binding.IB_FP32_FLOW, args.steps, args.warmup, timing=False,
+                             graphs=True)
+    value_graph = cells * args.steps / wall_g
     value_bf16 = None
     if not args.no_bf16:
         wall_b, _, kt_b, _ = run(prob, binding.IB_FP32_FLOW_BF16_DST, args.steps, args.warmup)
@@ -328,9 +333,10 @@ def main():
                    "newton_iters_max": st32["newton_iters_max"],
                    "schur_refine_sweeps_last": st32["refine_iters"],
                    "schur_inverse_rebuilds": st32["inverse_rebuilds"],
-                   "graph_launches": st32["graph_launches"],
                    "fsi_host_resumes": st32["fsi_resumes"]},
         "value_fp64": value64,
+        "value_graph_replay": value_graph,
+        "graph_launches": st_g["graph_launches"],
         "value_bf16_dst_gemm": value_bf16,
         "kernel_ms_per_step_bf16_dst_gemm": ({k: round(v[1] / args.steps, 5) for k, v in kt_b.items()}
                                              if value_bf16 else None),

@@ -210,11 +210,14 @@ ib_status ib_destroy(ib_solver* s);
  *   the remaining ones; the host synchronises once per step and continues on its own only
  *   when they did not suffice.  0: the host tests after every iteration (Algorithm 2 as
  *   written).  Both give the same results.
- * IB_OPT_GRAPHS (default 1): with IB_OPT_FSI_AHEAD, record a step's launches once as a HIP
- *   graph (one per alternation of the ring buffers) and replay it for later steps.
- * IB_OPT_REFRESH_EVERY_ITER (default 0): refresh the approximate Schur inverse (one
- *   Newton-Schulz step) at every FSI iteration instead of once per step; the refined stress
- *   solve then needs fewer sweeps.  The solution is the same to round-off either way.
+ * IB_OPT_GRAPHS (default 0): with IB_OPT_FSI_AHEAD, record a step's launches once as a HIP
+ *   graph (per alternation of the ring buffers and count of iterations launched ahead) and
+ *   replay it for later steps (a non-null stream is needed).  Measured on the flag workload,
+ *   replay neither shortens a step nor raises the throughput of concurrent solvers, hence
+ *   the default.
+ * IB_OPT_REFRESH_EVERY_ITER (default 1): refresh the approximate Schur inverse (one
+ *   Newton-Schulz step) at every FSI iteration instead of once per step (0); the refined
+ *   stress solve then needs fewer sweeps.  The solution is the same to round-off either way.
  * Errors: IB_ERR_ARG for an unknown option or value. */
 #define IB_OPT_FSI_AHEAD 1
 #define IB_OPT_GRAPHS 2

@@ -244,8 +244,8 @@ struct ib_solver {
   bool fsi_ahead = true;    // launch a step's FSI iterations ahead of their tests
   int nmov = 0;             // rigid bodies in prescribed motion
   double* hpose = nullptr;  // pinned staging of their poses, two sets (alternate steps)
-  bool graphs = true;       // replay recorded steps as HIP graphs
-  bool refresh_every_iter = false;  // Newton-Schulz refresh of X at every FSI iteration
+  bool graphs = false;      // replay recorded steps as HIP graphs
+  bool refresh_every_iter = true;   // Newton-Schulz refresh of X at every FSI iteration
   static constexpr int GRAPH_SLOTS = 4;
   StepGraph step_graphs[2][GRAPH_SLOTS];  // by ring-buffer alternation, then by K
   int graph_next[2] = {0, 0};             // slot to reuse next (round robin)

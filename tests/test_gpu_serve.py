@@ -127,6 +127,7 @@ def test_many_concurrent_requests_record_graphs_safely(torch_cuda, gpu_lib):
     sols, tickets = [], []
     for k, (p, steps) in enumerate(probs):
         s = binding.Solver(p, precision=binding.IB_FP32_FLOW, torch_alloc=False, stream=False)
+        s.set_option(binding.IB_OPT_GRAPHS, 1)
         sols.append(s)
         tickets.append(server.submit(s, steps, arrival=0.002 * k))
     server.run()
