@@ -27,8 +27,17 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a reference
 # copy; profiles/flow_1024x4_fp32_hbm_traffic.md), by kernel class and the configuration
 # (variant) measured; a configuration without a measurement reports no traffic
-TRAFFIC_PER_LAUNCH = {("col_solve", 0): 13.66e6, ("rhs_rowdst", 0): 22.01e6,
-                      ("row_idst", 0): 17.10e6}
+TRAFFIC_PER_LAUNCH = {
+    ("rhs_rowdst", 0): 21.80e6, ("rhs_rowdst", 1): 21.79e6, ("rhs_rowdst", 2): 21.69e6,
+    ("rhs_rowdst", 3): 21.68e6, ("rhs_rowdst", 4): 21.67e6, ("rhs_rowdst", 5): 21.76e6,
+    ("rhs_rowdst", 6): 21.69e6, ("rhs_rowdst", 7): 21.72e6,
+    ("col_solve", 0): 12.23e6, ("col_solve", 1): 13.23e6, ("col_solve", 2): 13.04e6,
+    ("col_solve", 3): 13.04e6, ("col_solve", 4): 13.02e6, ("col_solve", 5): 13.66e6,
+    ("col_solve", 6): 13.16e6, ("col_solve", 7): 37.95e6,
+    ("row_idst", 0): 17.11e6, ("row_idst", 1): 17.14e6, ("row_idst", 2): 17.06e6,
+    ("row_idst", 3): 17.05e6, ("row_idst", 4): 17.05e6, ("row_idst", 5): 17.10e6,
+    ("row_idst", 6): 17.05e6, ("row_idst", 7): 17.07e6,
+}
 
 
 def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
