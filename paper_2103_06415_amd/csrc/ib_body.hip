@@ -809,11 +809,35 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
   if (threadIdx.x == 0) y[r] = red[0];
 }
 
+// Convergence test after FSI iteration `it` of K launched ahead (Algorithm 2's test on
+// max |delta|, or a fixed count): sets gate[0] and the iteration count on convergence;
+// stops the iterations (gate[1]) on an error or refinement flag, a non-finite update, or
+// when iteration K - 1 has not converged, recording where the host should go on.
+__device__ void convergence_test(int* ctl, double d, int it, int K, double tol, int fixed) {
+  int* gate = ctl + FsiCtl::GATE;
+  if (gate[0] != 0 || gate[1] != 0) return;
+  if (ctl[FsiCtl::FLAGS] != 0 || ctl[FsiCtl::FLAGS + 1] != 0 || !(d == d) || d > 1e308) {
+    ctl[FsiCtl::NEXT] = it;  // the host handles it (a refinement failure redoes iteration it)
+    gate[1] = 1;
+    return;
+  }
+  if (fixed > 0 ? it + 1 >= fixed : d <= tol) {
+    ctl[FsiCtl::NEXT] = it + 1;
+    gate[0] = 1;
+    return;
+  }
+  if (it + 1 >= K) {
+    ctl[FsiCtl::NEXT] = it + 1;
+    gate[1] = 1;
+  }
+}
+
 // Structure update from the new stresses and the convergence measure max |delta|,
 // folded into delta[0] (zeroed by k_body_ops) with atomicMax on the bit pattern of the
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
-__global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
+__global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a, int it, int K, double tol,
+                                                     int fixed) {
   if (iter_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = STRUCT_NT / 64;
@@ -897,6 +921,20 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a) {
   if (lane == 0) {
     const double v = anybad ? INFINITY : my;
     atomicMax(reinterpret_cast<unsigned long long*>(a.delta), (unsigned long long)__double_as_longlong(v));
+  }
+  if (a.gate == nullptr) return;  // the host tests convergence
+  // iterations launched ahead: the last workgroup to finish runs the convergence test
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int* ctl = a.flags;
+    __threadfence();
+    if (atomicAdd(&ctl[FsiCtl::UDONE], 1) == (int)gridDim.x - 1) {
+      __threadfence();
+      const unsigned long long bits = __hip_atomic_load(
+          reinterpret_cast<unsigned long long*>(a.delta), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      convergence_test(ctl, __longlong_as_double((long long)bits), it, K, tol, fixed);
+      atomicExch(&ctl[FsiCtl::UDONE], 0);
+    }
   }
 }
 
@@ -1224,7 +1262,8 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
                                                 const double* __restrict__ X, int pm,
                                                 const double* __restrict__ b, double* f, int n,
                                                 int rw, int tpr, int maxit, int guess, double* ws,
-                                                double* out, int* flags, const int* gate) {
+                                                double* out, int* flags, const int* gate,
+                                                double* xcopy) {
   if (iter_gated(gate)) return;  // the same for every workgroup: none enters a barrier
   extern __shared__ double lds[];
   double* sf = lds;           // f (n)
@@ -1256,7 +1295,14 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
     }
     for (int e = tid; e < nr * n; e += 256) {
       const int j = e / nr, k = e % nr;
-      sx[(size_t)j * rw + k] = X[(size_t)j * pm + r0 + k];
+      const double x = X[(size_t)j * pm + r0 + k];
+      sx[(size_t)j * rw + k] = x;
+      if (xcopy) xcopy[(size_t)j * pm + r0 + k] = x;
+    }
+  } else if (xcopy) {
+    for (int e = tid; e < nr * n; e += 256) {
+      const int j = e / nr, k = e % nr;
+      xcopy[(size_t)j * pm + r0 + k] = X[(size_t)j * pm + r0 + k];
     }
   }
   __syncthreads();
@@ -1441,52 +1487,8 @@ __global__ void k_step_reset(int* ctl) {
   if (threadIdx.x < FsiCtl::INTS) ctl[threadIdx.x] = 0;
 }
 
-// Convergence test after FSI iteration `it` of K launched ahead (Algorithm 2's test on
-// max |delta|, or a fixed count): sets gate[0] and the iteration count on convergence;
-// stops the iterations (gate[1]) on an error or refinement flag, a non-finite update, or
-// when iteration K - 1 has not converged, recording where the host should go on.
-__global__ void k_converge(int* ctl, const double* delta, int it, int K, double tol, int fixed) {
-  if (threadIdx.x != 0) return;
-  int* gate = ctl + FsiCtl::GATE;
-  if (gate[0] != 0 || gate[1] != 0) return;
-  const double d = *delta;
-  if (ctl[FsiCtl::FLAGS] != 0 || ctl[FsiCtl::FLAGS + 1] != 0 || !(d == d) || d > 1e308) {
-    ctl[FsiCtl::NEXT] = it;  // the host handles it (a refinement failure redoes iteration it)
-    gate[1] = 1;
-    return;
-  }
-  if (fixed > 0 ? it + 1 >= fixed : d <= tol) {
-    ctl[FsiCtl::NEXT] = it + 1;
-    gate[0] = 1;
-    return;
-  }
-  if (it + 1 >= K) {
-    ctl[FsiCtl::NEXT] = it + 1;
-    gate[1] = 1;
-  }
-}
-
-// dst = src (count doubles), skipped like the FSI iteration kernels.
-__global__ void k_copy64(double* dst, const double* src, size_t count, const int* gate) {
-  if (iter_gated(gate)) return;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += (size_t)gridDim.x * blockDim.x)
-    dst[e] = src[e];
-}
-
-hipError_t launch_copy64(double* dst, const double* src, size_t count, const int* gate,
-                         hipStream_t st) {
-  const int nb = (int)std::min<size_t>(1024, (count + 255) / 256);
-  if (nb > 0) hipLaunchKernelGGL(k_copy64, dim3(nb), dim3(256), 0, st, dst, src, count, gate);
-  return hipGetLastError();
-}
 hipError_t launch_step_reset(int* ctl, hipStream_t st) {
   hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, st, ctl);
-  return hipGetLastError();
-}
-hipError_t launch_converge(int* ctl, const double* delta, int it, int K, double tol, int fixed,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_converge, dim3(1), dim3(64), 0, st, ctl, delta, it, K, tol, fixed);
   return hipGetLastError();
 }
 
@@ -1502,7 +1504,7 @@ hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
 }
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, hipStream_t st) {
+                         const int* gate, double* xcopy, hipStream_t st) {
   if (n < 1 || maxit < 1) return hipErrorInvalidValue;
   int nb = std::min(16, (n + 7) / 8);
   int rw = (n + nb - 1) / nb;
@@ -1519,10 +1521,10 @@ hipError_t launch_refine(const double* M, int pm, const double* X, const double*
   if (lds > 64 * 1024) return hipErrorInvalidValue;
   if (cache)
     hipLaunchKernelGGL(k_refine<true>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
-                       maxit, guess, ws, out, flags, gate);
+                       maxit, guess, ws, out, flags, gate, xcopy);
   else
     hipLaunchKernelGGL(k_refine<false>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
-                       maxit, guess, ws, out, flags, gate);
+                       maxit, guess, ws, out, flags, gate, xcopy);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
@@ -1583,11 +1585,11 @@ hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
   hipLaunchKernelGGL(k_beam, dim3((ncol + BEAM_NC - 1) / BEAM_NC), dim3(BEAM_NT), lds, st, a, bi);
   return hipGetLastError();
 }
-hipError_t launch_update(const FsiArgs& a, hipStream_t st) {
+hipError_t launch_update(const FsiArgs& a, int it, int K, double tol, int fixed, hipStream_t st) {
   // enough waves for one group of 4 rows of the largest beam (3m - 3 <= 1.5 nf rows)
   const int groups = (3 * a.nf / 2 + 3) / 4;
   const int nb = std::max(1, (groups + STRUCT_NT / 64 - 1) / (STRUCT_NT / 64));
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(STRUCT_NT), 0, st, a);
+  hipLaunchKernelGGL(k_update, dim3(nb), dim3(STRUCT_NT), 0, st, a, it, K, tol, fixed);
   return hipGetLastError();
 }
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st) {

@@ -40,7 +40,8 @@ struct FsiCtl {
   static constexpr int ROUT = 4;    // ints 4 .. 9 (3 doubles)
   static constexpr int GATE = 10;   // ints 10, 11
   static constexpr int NEXT = 12;   // int 12
-  static constexpr int INTS = 13;   // ints cleared at the start of a step
+  static constexpr int UDONE = 13;  // int 13: workgroups of k_update finished (then reset)
+  static constexpr int INTS = 14;   // ints cleared at the start of a step
   static constexpr int BYTES = 64;
 };
 
@@ -123,7 +124,9 @@ hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, dou
 hipError_t launch_lu_solve(double* M, int pm, double* B, int pb, int n, int nrhs, int* flags,
                            hipStream_t st);
 hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, int n, hipStream_t st);
-hipError_t launch_update(const FsiArgs& a, hipStream_t st);
+// Structure update; with a.gate set the last workgroup also runs the convergence test of
+// iteration `it` of K launched ahead (tolerance tol, or a fixed count).
+hipError_t launch_update(const FsiArgs& a, int it, int K, double tol, int fixed, hipStream_t st);
 hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st);
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st);
 template <typename T>
@@ -147,20 +150,14 @@ hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
 // otherwise flags[1] is raised when the residual stays above 1e-9
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, hipStream_t st);
+                         const int* gate, double* xcopy, hipStream_t st);
 size_t refine_ws_doubles(int n, int maxit);
 hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
 // *out (zeroed by the caller) folds in max |W - I| over the n x n matrix (+Inf if not finite)
 hipError_t launch_eye_resid(const double* W, int p, int n, double* out, hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
                          hipStream_t st, const int* gate = nullptr);
-// Device-side FSI control (FsiCtl): clear it at the start of a step; test convergence
-// after iteration `it` of K launched ahead.
+// Device-side FSI control (FsiCtl): clear it at the start of a step.
 hipError_t launch_step_reset(int* ctl, hipStream_t st);
-// dst = src (count doubles), skipped like an FSI iteration kernel when gate is set.
-hipError_t launch_copy64(double* dst, const double* src, size_t count, const int* gate,
-                         hipStream_t st);
-hipError_t launch_converge(int* ctl, const double* delta, int it, int K, double tol, int fixed,
-                           hipStream_t st);
 
 }  // namespace ib

@@ -1107,7 +1107,7 @@ ib_status do_prepare(ib_solver* s) {
 // step), the refined stress solve and the structure update.  With a.gate set every kernel
 // skips itself once the step's iterations have converged or stopped on the device.
 template <typename T>
-ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it) {
+ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   FsiArgs a = a0;
   a.iter = it;
   const int n = s->n, nf = s->nf;
@@ -1127,7 +1127,8 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it) {
   }
   HIPCHK(launch_schur_sd(a, s->stream));
   const size_t mb = (size_t)nf * a.pm * 8;
-  if (!s->x_valid) {
+  const bool fresh = !s->x_valid;
+  if (fresh) {
     // fresh inverse of the current Schur matrix by LU on a copy
     HIPCHK(hipMemcpyAsync(s->Mtmp, a.M, mb, hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemsetAsync(s->Minv, 0, mb, s->stream));
@@ -1135,16 +1136,21 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it) {
     HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->Minv, a.pm, nf, nf, s->flags, s->stream));
     s->x_valid = true;
     s->inverse_rebuilds++;
-  } else if (it == 0 || s->refresh_every_iter) {
-    // one Newton-Schulz step towards the new matrix: X <- X (2I - M X)
+  }
+  const double* X = s->Minv;
+  double* xcopy = nullptr;
+  if (!fresh && (it == 0 || s->refresh_every_iter)) {
+    // one Newton-Schulz step towards the new matrix, X <- X (2I - M X), into Xn; the
+    // refinement solves with it and copies it back to Minv as it loads it
     HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream, a.gate));
     HIPCHK(launch_gemm64(s->Minv, s->W, s->Xn, nf, a.pm, 0, s->stream, a.gate));
-    HIPCHK(launch_copy64(s->Minv, s->Xn, (size_t)nf * a.pm, a.gate, s->stream));
+    X = s->Xn;
+    xcopy = s->Minv;
   }
-  HIPCHK(launch_refine(a.M, a.pm, s->Minv, s->rhs, s->f, nf, REFINE_MAXIT,
-                       it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, a.gate,
+  HIPCHK(launch_refine(a.M, a.pm, X, s->rhs, s->f, nf, REFINE_MAXIT,
+                       it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, a.gate, xcopy,
                        s->stream));
-  HIPCHK(launch_update(a, s->stream));
+  HIPCHK(launch_update(a, it, K, s->cfg.newton_tol, s->cfg.newton_fixed_iter, s->stream));
   return IB_OK;
 }
 
@@ -1208,11 +1214,9 @@ template <typename T>
 ib_status fsi_launch_ahead(ib_solver* s, int K) {
   FsiArgs g = s->fa;
   g.gate = s->gate;
-  const int fixed = s->cfg.newton_fixed_iter;
   for (int it = 0; it < K; ++it) {
-    ib_status e = fsi_iteration<T>(s, g, it);
+    ib_status e = fsi_iteration<T>(s, g, it, K);  // k_update runs the convergence test
     if (e) return e;
-    HIPCHK(launch_converge(s->flags, s->delta, it, K, s->cfg.newton_tol, fixed, s->stream));
   }
   HIPCHK(launch_finish(g, s->stream));
   return corrector<T>(s, s->gate);
