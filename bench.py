@@ -132,6 +132,49 @@ def concurrent(problem, count, steps, warmup=3):
             "throughput_unit": "grid-cell steps/s", "ms_per_step_each": 1e3 * wall / steps}
 
 
+def batch_run(problems, steps, warmup, alone_steps=None):
+    """The problems as one batch (ib_batch_*): every launch of a step covers all members.
+    Reports the aggregate grid-cell steps/s and, for comparison, the same members stepped
+    one after another on their own (alone_steps each, after the batched steps)."""
+    import torch
+    from paper_2103_06415_amd import binding
+    st = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    sol = []
+    for p in problems:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW, stream=st)
+        s.prepare()
+        sol.append(s)
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t0
+    b = binding.Batch(sol, stream=st)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = b.stats()
+    b.close()
+    cells = sum(p.flow.n ** 2 * p.flow.levels for p in problems)
+    out = {"instances": len(problems), "steps": steps, "wall_s": wall,
+           "throughput": cells * steps / wall, "throughput_unit": "grid-cell steps/s",
+           "ms_per_step": 1e3 * wall / steps, "prepare_s": prep,
+           "launches_per_step": stats["launches"] / max(1, stats["member_steps_batched"] / len(problems)),
+           "member_steps_alone": stats["member_steps_alone"], "fsi_resumes": stats["fsi_resumes"]}
+    if alone_steps:
+        t0 = time.perf_counter()
+        for s in sol:
+            s.step(alone_steps)
+        torch.cuda.synchronize()
+        wall_a = time.perf_counter() - t0
+        out["throughput_alone_sequential"] = cells * alone_steps / wall_a
+        out["batched_over_alone"] = out["throughput"] / out["throughput_alone_sequential"]
+    for s in sol:
+        s.close()
+    return out
+
+
 def serve(problems, max_active=8, budget=200 << 30, precision=None):
     """Run (arrival, Problem) requests through the continuous-batching server."""
     from paper_2103_06415_amd import binding
@@ -273,7 +316,10 @@ def main():
     ap.add_argument("--concurrent", type=int, default=4,
                     help="also run this many copies of the workload concurrently (0: skip)")
     ap.add_argument("--batch", action="store_true",
-                    help="also run the 64-instance batch (sizes 128^2..768^2, 200 steps each)")
+                    help="also run the 64-instance batch (sizes 128^2..768^2) as one ib_batch "
+                         "and through the scheduler")
+    ap.add_argument("--batch-copies", type=int, default=4,
+                    help="also step this many copies of the workload as one ib_batch (0: skip)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware counter calibration)")
@@ -372,9 +418,18 @@ def main():
                                      "deformable bodies, 200-2000 steps, FP32 flow")
     if not args.no_exact:
         out["subdomain_vs_exact"] = exact_compare()
+    if args.batch_copies > 0:
+        out["batch_copies"] = batch_run([prob] * args.batch_copies, args.steps, 3,
+                                        alone_steps=max(1, args.steps // 4))
+        out["batch_copies"]["workload"] = (f"{args.batch_copies} copies of the flag workload as "
+                                           "one batch (one launch per kernel for all), FP32 flow")
     if args.batch:
+        out["batch64"] = batch_run(W.batch_problems(), 20, 3, alone_steps=5)
+        out["batch64"]["workload"] = ("64 instances, 128^2..768^2 x 1-3 levels, 1-3 rigid or "
+                                      "torsional bodies, one batch, FP32 flow")
         out["batched"] = serve([(0.0, p) for p in W.batch_problems()], max_active=16)
-        out["batched"]["workload"] = "64 instances, 128^2..768^2 x 1-3 levels, 200 steps"
+        out["batched"]["workload"] = ("the same 64 instances (200 steps) through the scheduler, "
+                                      "16 slots")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, levels)
     print(json.dumps(out))

@@ -320,6 +320,48 @@ ib_status ib_server_info(ib_server* sv, int64_t ticket, ib_request_info* out);
 /* Destroys the server and its streams, not the solvers. */
 ib_status ib_server_destroy(ib_server* sv);
 
+/* ---- batches: many solvers per launch ----
+ * A batch steps many independent solvers together (each is its own instance of
+ * Algorithm 2).  Every kernel launch of a batched step covers all members that need it:
+ * one launch per grid size (and transform configuration) for each flow kernel of the
+ * predictor (Sec. 2.3 eq. (16), Sec. 3.2.1), the corrector (eq. (20)) and the level
+ * coupling, and one launch over all members for each kernel of the FSI iterations (body
+ * operators, Schur assembly eqs. (17), (37), its refreshed inverse and stress solve, the
+ * structure update and convergence test), so a step costs a few dozen launches however many
+ * members there are.  Members' FSI iterations run on the device with their own convergence
+ * tests; a member that needs more than the iterations launched continues on the host.
+ * Each member's results equal those of the same solver stepped alone.
+ * A member's step runs alone (as ib_step would run it) when it is its first step, when its
+ * Schur inverse must be rebuilt, or when it uses IB_FP32_FLOW_BF16_DST, the exact operator
+ * for moving bodies, kernel timing or IB_OPT_FSI_AHEAD = 0.
+ * members: `count` distinct prepared solvers of one precision class (IB_FP64, or the FP32
+ * flow forms), owned by the caller, who must keep them alive and not step them elsewhere
+ * while the batch exists.  From ib_batch_create on, every member's work runs on hip_stream
+ * (the solvers' stream is set to it; NULL = the null stream).
+ * Errors: IB_ERR_ARG (count < 1, a null or repeated member, mixed precision),
+ * IB_ERR_STATE (a member not prepared, failed or released); ib_batch_step returns the
+ * first failing member's error, marks that member failed, and ib_batch_last_error says
+ * what happened. */
+typedef struct ib_batch ib_batch;
+
+typedef struct {
+  int64_t steps;                 /* batched steps taken (ib_batch_step's nsteps summed) */
+  int64_t member_steps_batched;  /* member steps that ran in batched launches */
+  int64_t member_steps_alone;    /* member steps that ran alone */
+  int64_t launches;              /* batched launches issued (tables copy excluded) */
+  int64_t fsi_resumes;           /* members whose FSI part continued on the host */
+} ib_batch_stats;
+
+ib_status ib_batch_create(ib_solver* const* members, int32_t count, void* hip_stream,
+                          ib_batch** out);
+/* nsteps steps of every member; returns after the last step's convergence tests (the
+ * flow of the last step may still run on hip_stream when no member has moving bodies). */
+ib_status ib_batch_step(ib_batch* b, int32_t nsteps);
+ib_status ib_batch_get_stats(const ib_batch* b, ib_batch_stats* out);
+const char* ib_batch_last_error(const ib_batch* b);
+/* Waits for the batch's work and frees the batch, not its members. */
+ib_status ib_batch_destroy(ib_batch* b);
+
 const char* ib_status_str(ib_status st);
 
 /* What the last failing call on this solver reported (empty if none); valid until the

@@ -21,6 +21,9 @@ IB_SCHUR_AUTO = 0
 IB_SCHUR_EXACT = 1
 IB_SCHUR_SUBDOMAIN = 2
 
+(IB_OK, IB_ERR_ARG, IB_ERR_STATE, IB_ERR_OOM, IB_ERR_HIP, IB_ERR_NOT_CONVERGED,
+ IB_ERR_OUT_OF_SUBDOMAIN, IB_ERR_NEAR_BOUNDARY, IB_ERR_NONFINITE, IB_ERR_CAPACITY) = range(0, -10, -1)
+
 STATUS = {
     0: "IB_OK", -1: "IB_ERR_ARG", -2: "IB_ERR_STATE", -3: "IB_ERR_OOM", -4: "IB_ERR_HIP",
     -5: "IB_ERR_NOT_CONVERGED", -6: "IB_ERR_OUT_OF_SUBDOMAIN", -7: "IB_ERR_NEAR_BOUNDARY",
@@ -81,6 +84,13 @@ class IbRequestInfo(ctypes.Structure):
     ]
 
 
+class IbBatchStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", c_int64), ("member_steps_batched", c_int64), ("member_steps_alone", c_int64),
+        ("launches", c_int64), ("fsi_resumes", c_int64),
+    ]
+
+
 _SIGS = {
     "ib_create": (c_int32, [POINTER(IbConfig), POINTER(IbAllocator), c_void_p, POINTER(c_void_p)]),
     "ib_add_rigid": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, POINTER(c_double),
@@ -123,6 +133,11 @@ _SIGS = {
     "ib_set_flow_variants": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "ib_flow_variant_info": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
                                        POINTER(c_int32)]),
+    "ib_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_void_p, POINTER(c_void_p)]),
+    "ib_batch_step": (c_int32, [c_void_p, c_int32]),
+    "ib_batch_get_stats": (c_int32, [c_void_p, POINTER(IbBatchStats)]),
+    "ib_batch_last_error": (ctypes.c_char_p, [c_void_p]),
+    "ib_batch_destroy": (c_int32, [c_void_p]),
 }
 
 K_RHS_ROWDST, K_COL_SOLVE, K_ROW_IDST, K_FSI, K_CORRECT, K_RING = range(6)
@@ -365,6 +380,48 @@ class Solver:
     def close(self):
         if self.handle:
             self.lib.ib_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many prepared solvers of one precision class stepped together, each kernel launch
+    covering all members (ib_batch_*).  From construction on the members' work runs on
+    ``stream`` (default: the current torch stream)."""
+
+    def __init__(self, solvers, stream=None):
+        import torch
+        self.lib = load()
+        self.solvers = list(solvers)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (c_void_p * len(self.solvers))(*[s.handle.value for s in self.solvers])
+        self.handle = c_void_p()
+        _check(self.lib.ib_batch_create(arr, len(self.solvers), c_void_p(self.stream.cuda_stream),
+                                        byref(self.handle)), "ib_batch_create")
+        for s in self.solvers:
+            s.stream = self.stream
+
+    def step(self, nsteps=1):
+        code = self.lib.ib_batch_step(self.handle, nsteps)
+        if code != 0:
+            raise IbError(code, "ib_batch_step: " + self.last_error())
+
+    def stats(self):
+        r = IbBatchStats()
+        _check(self.lib.ib_batch_get_stats(self.handle, byref(r)), "ib_batch_get_stats")
+        return {k: getattr(r, k) for k, _ in IbBatchStats._fields_}
+
+    def last_error(self):
+        return self.lib.ib_batch_last_error(self.handle).decode()
+
+    def close(self):
+        if self.handle:
+            self.lib.ib_batch_destroy(self.handle)
             self.handle = c_void_p()
 
     def __del__(self):

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["ib_flow.hip", "ib_flow_tuned.hip", "ib_body.hip", "ib_engine.hip", "ib_serve.hip", "ib_gemm.hip"]
+SOURCES = ["ib_flow.hip", "ib_flow_tuned.hip", "ib_flow_multi.hip", "ib_flow_multi_tuned.hip", "ib_body.hip", "ib_engine.hip", "ib_serve.hip", "ib_gemm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -161,9 +161,9 @@ __device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, i
 // Body operator rows, u* and the Schur right-hand side for every point (one thread per
 // point); point 0 also clears the convergence maximum that k_update folds into.
 template <typename T>
-__global__ void k_body_ops(FsiArgs a) {
+__device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
   if (iter_gated(a.gate)) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = bx * blockDim.x + threadIdx.x;
   if (p >= a.npts) return;
   int bi = 0;
   while (bi + 1 < a.nbodies && a.bodies[bi + 1].pt0 <= p) ++bi;
@@ -262,6 +262,20 @@ __global__ void k_body_ops(FsiArgs a) {
   }
 }
 
+template <typename T>
+__global__ void k_body_ops(FsiArgs a) {
+  body_ops_body<T>(a, blockIdx.x);
+}
+
+// Many instances per launch (ib_batch_*): instance blockIdx.y's arguments from tab, at FSI
+// iteration `it`.
+template <typename T>
+__global__ void k_body_ops_multi(const FsiArgs* __restrict__ tab, int it) {
+  FsiArgs a = tab[blockIdx.y];
+  a.iter = it;
+  body_ops_body<T>(a, blockIdx.x);
+}
+
 __device__ __forceinline__ double row_ds(const FsiArgs& a, int row) {
   // rows of body bi are 2 pt0 .. 2 pt0 + 2m - 1
   int bi = 0;
@@ -288,10 +302,10 @@ __device__ __forceinline__ int row_body(const FsiArgs& a, int row) {
 // Dynamic LDS: acc, pw (4 nf doubles each), cid, pidx (4 nf ints each).
 constexpr int SCHUR_NT = 256;
 constexpr int SCHUR_CPT = 8;  // columns per thread: nf <= 2048
-__global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a, int all4) {
+__device__ __forceinline__ void schur_sd_body(const FsiArgs& a, int all4, int bx) {
   if (iter_gated(a.gate)) return;
   extern __shared__ double ssm[];
-  const int nf = a.nf, ns = 4 * nf, r = blockIdx.x, tid = threadIdx.x;
+  const int nf = a.nf, ns = 4 * nf, r = bx, tid = threadIdx.x;
   double m[SCHUR_CPT];
   if (a.gx == nullptr && all4) {
     // the CSR rows of all four hat points of row r are scanned together into four LDS
@@ -451,6 +465,22 @@ __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a, int all4) {
   }
 }
 
+__global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a, int all4) {
+  schur_sd_body(a, all4, blockIdx.x);
+}
+
+__device__ __forceinline__ int schur_all4(const FsiArgs& a) {
+  return a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
+}
+
+__global__ __launch_bounds__(SCHUR_NT) void k_schur_sd_multi(const FsiArgs* __restrict__ tab,
+                                                             int it) {
+  FsiArgs a = tab[blockIdx.y];
+  a.iter = it;
+  if ((int)blockIdx.x >= a.nf) return;
+  schur_sd_body(a, schur_all4(a), blockIdx.x);
+}
+
 // -------------------------------------------------------- corotational beam
 // Element internal force fe[6] and tangent ke[36] (Crisfield's 2-D corotational
 // Euler-Bernoulli element; rotations relative to the straight reference).
@@ -519,7 +549,7 @@ __device__ inline double inv3_entry(const double* a, int r, int c) {
 
 constexpr int BEAM_NT = 512;
 constexpr int BEAM_NC = 8;  // right-hand sides per workgroup
-__global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
+__device__ __forceinline__ void beam_body(const FsiArgs& a, int bi, int bx) {
   if (iter_gated(a.gate)) return;
   constexpr int NC = BEAM_NC;
   extern __shared__ double bsm[];
@@ -618,7 +648,7 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
   }
 
   // right-hand sides of this workgroup: columns c0 .. c0 + NC - 1
-  const int c0 = blockIdx.x * NC;
+  const int c0 = bx * NC;
   for (int t = tid; t < nd * NC; t += BEAM_NT) {
     const int u = t / NC, col = c0 + t % NC;
     double v = 0.0;
@@ -698,6 +728,19 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
       a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
     }
   }
+}
+
+__global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
+  beam_body(a, bi, blockIdx.x);
+}
+
+__global__ __launch_bounds__(BEAM_NT) void k_beam_multi(const BeamJob* __restrict__ tab, int it) {
+  const BeamJob& j = tab[blockIdx.y];
+  FsiArgs a = j.a;
+  a.iter = it;
+  const int bi = j.bi, ncol = 2 * j.m + 1;
+  if ((int)blockIdx.x >= (ncol + BEAM_NC - 1) / BEAM_NC) return;
+  beam_body(a, bi, blockIdx.x);
 }
 
 // LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K); the
@@ -795,8 +838,8 @@ __global__ __launch_bounds__(LU_NT) void k_lu_solve(double* M, int pm, double* B
 }
 
 // f = Minv rhs (stationary bodies).
-__global__ void k_matvec(const double* A, int pa, const double* x, double* y, int n) {
-  const int r = blockIdx.x;
+__device__ __forceinline__ void matvec_body(const double* A, int pa, const double* x, double* y,
+                                            int n, int r) {
   __shared__ double red[256];
   double acc = 0.0;
   for (int c = threadIdx.x; c < n; c += blockDim.x) acc += A[(size_t)r * pa + c] * x[c];
@@ -807,6 +850,16 @@ __global__ void k_matvec(const double* A, int pa, const double* x, double* y, in
     __syncthreads();
   }
   if (threadIdx.x == 0) y[r] = red[0];
+}
+
+__global__ void k_matvec(const double* A, int pa, const double* x, double* y, int n) {
+  matvec_body(A, pa, x, y, n, blockIdx.x);
+}
+
+__global__ void k_matvec_multi(const MatvecJob* __restrict__ tab) {
+  const MatvecJob j = tab[blockIdx.y];
+  if ((int)blockIdx.x >= j.n) return;
+  matvec_body(j.A, j.pa, j.x, j.y, j.n, blockIdx.x);
 }
 
 // Convergence test after FSI iteration `it` of K launched ahead (Algorithm 2's test on
@@ -836,12 +889,12 @@ __device__ void convergence_test(int* ctl, double d, int it, int K, double tol, 
 // folded into delta[0] (zeroed by k_body_ops) with atomicMax on the bit pattern of the
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
-__global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a, int it, int K, double tol,
-                                                     int fixed) {
+__device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, double tol, int fixed,
+                                            int bx, int gx) {
   if (iter_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = STRUCT_NT / 64;
-  const int gw = blockIdx.x * NW + w, nwaves = gridDim.x * NW;
+  const int gw = bx * NW + w, nwaves = gx * NW;
   double my = 0.0;
   bool bad = false;
   auto fold = [&](double d) {
@@ -928,7 +981,7 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a, int it, int K, 
   if (threadIdx.x == 0) {
     int* ctl = a.flags;
     __threadfence();
-    if (atomicAdd(&ctl[FsiCtl::UDONE], 1) == (int)gridDim.x - 1) {
+    if (atomicAdd(&ctl[FsiCtl::UDONE], 1) == gx - 1) {
       __threadfence();
       const unsigned long long bits = __hip_atomic_load(
           reinterpret_cast<unsigned long long*>(a.delta), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -938,8 +991,23 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a, int it, int K, 
   }
 }
 
+__global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a, int it, int K, double tol,
+                                                     int fixed) {
+  update_body(a, it, K, tol, fixed, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(STRUCT_NT) void k_update_multi(const UpdateJob* __restrict__ tab,
+                                                           int it, int K) {
+  const UpdateJob& j = tab[blockIdx.y];
+  FsiArgs a = j.a;
+  a.iter = it;
+  const int nb = j.nb;
+  if ((int)blockIdx.x >= nb) return;
+  update_body(a, it, K, j.tol, j.fixed, blockIdx.x, nb);
+}
+
 // Newmark completion of the step with the accepted iterate.
-__global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) {
+__device__ __forceinline__ void finish_body(const FsiArgs& a) {
   if (post_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const double dt = a.dt;
@@ -977,18 +1045,25 @@ __global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) {
   }
 }
 
+__global__ __launch_bounds__(STRUCT_NT) void k_finish(FsiArgs a) { finish_body(a); }
+
+__global__ __launch_bounds__(STRUCT_NT) void k_finish_multi(const FsiArgs* __restrict__ tab) {
+  const FsiArgs a = tab[blockIdx.y];
+  finish_body(a);
+}
+
 // Corrector source C^T E^T lambda at interior vertices of rows [jlo, jhi]; entries
 // outside columns [ilo, ihi] are zero.  lambda_a = (ds_a / h) f_a.  Each workgroup
 // covers a 64 x 4 tile of vertices.  It first lists (in row order, by wave ballots) the
 // operator rows whose window reaches the tile, stages their windows and coefficients
 // in LDS, and then every vertex sums those rows in that fixed order, so the result is
 // deterministic.
-constexpr int SPREAD_TX = 64, SPREAD_TY = 4, SPREAD_NT = SPREAD_TX * SPREAD_TY;
-constexpr int SPREAD_MAXROWS = 4096;
+constexpr int SPREAD_TX = SPREAD_TILE_X, SPREAD_TY = SPREAD_TILE_Y, SPREAD_NT = SPREAD_TX * SPREAD_TY;
+constexpr int SPREAD_MAXROWS = SPREAD_ROWS_MAX;
 
 template <typename T>
-__global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi,
-                                                      T* out, int po) {
+__device__ __forceinline__ void spread_body(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi,
+                                            T* out, int po, int bx, int by) {
   constexpr int NW = SPREAD_NT / 64;
   __shared__ int list[SPREAD_MAXROWS];
   __shared__ int wcount[NW];
@@ -998,7 +1073,7 @@ __global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jh
   if (post_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tx = tid % SPREAD_TX, ty = tid / SPREAD_TX;
-  const int ti0 = 1 + blockIdx.x * SPREAD_TX, tj0 = jlo + blockIdx.y * SPREAD_TY;
+  const int ti0 = 1 + bx * SPREAD_TX, tj0 = jlo + by * SPREAD_TY;
   const int i = ti0 + tx, j = tj0 + ty;
   const bool tile_hit = !(ti0 + SPREAD_TX - 1 < ilo || ti0 > ihi);
   int cnt = 0;
@@ -1059,6 +1134,23 @@ __global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jh
   }
   if (i > a.n - 1 || j > jhi) return;
   out[(size_t)(j - 1) * po + (i - 1)] = (T)src;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi,
+                                                      T* out, int po) {
+  spread_body<T>(a, jlo, jhi, ilo, ihi, out, po, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(SPREAD_NT) void k_spread_multi(const SpreadJob<T>* __restrict__ tab) {
+  const SpreadJob<T>& j = tab[blockIdx.z];
+  const FsiArgs a = j.a;
+  const int jlo = j.jlo, jhi = j.jhi;
+  if ((int)blockIdx.x >= (a.n - 1 + SPREAD_TX - 1) / SPREAD_TX ||
+      (int)blockIdx.y >= (jhi - jlo + 1 + SPREAD_TY - 1) / SPREAD_TY)
+    return;
+  spread_body<T>(a, jlo, jhi, j.ilo, j.ihi, j.out, j.po, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------ offline stage
@@ -1258,12 +1350,12 @@ __device__ inline double ld_agent(const double* p) {
 __device__ inline double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
 
 template <bool CACHE>
-__global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
-                                                const double* __restrict__ X, int pm,
-                                                const double* __restrict__ b, double* f, int n,
-                                                int rw, int tpr, int maxit, int guess, double* ws,
-                                                double* out, int* flags, const int* gate,
-                                                double* xcopy) {
+__device__ __forceinline__ void refine_body(const double* __restrict__ M,
+                                            const double* __restrict__ X, int pm,
+                                            const double* __restrict__ b, double* f, int n,
+                                            int rw, int tpr, int maxit, int guess, double* ws,
+                                            double* out, int* flags, const int* gate,
+                                            double* xcopy, int bx, int gx) {
   if (iter_gated(gate)) return;  // the same for every workgroup: none enters a barrier
   extern __shared__ double lds[];
   double* sf = lds;           // f (n)
@@ -1274,7 +1366,7 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
   double* sm = sred + 4;      // rows R_w of M (rw x n) when CACHE
   double* sx = sm + (size_t)rw * n;  // columns R_w of X (n x rw) when CACHE
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nb = gridDim.x, w = blockIdx.x, ns = n + 1;
+  const int nb = gx, w = bx, ns = n + 1;
   const int r0 = w * rw, r1 = min(n, r0 + rw), nr = max(0, r1 - r0);
   unsigned* cnt = reinterpret_cast<unsigned*>(ws + 2);
   unsigned* ext = reinterpret_cast<unsigned*>(ws + 3);
@@ -1412,6 +1504,28 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
   }
 }
 
+template <bool CACHE>
+__global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
+                                                const double* __restrict__ X, int pm,
+                                                const double* __restrict__ b, double* f, int n,
+                                                int rw, int tpr, int maxit, int guess, double* ws,
+                                                double* out, int* flags, const int* gate,
+                                                double* xcopy) {
+  refine_body<CACHE>(M, X, pm, b, f, n, rw, tpr, maxit, guess, ws, out, flags, gate, xcopy,
+                     blockIdx.x, gridDim.x);
+}
+
+// Many instances per launch: instance blockIdx.y's nb workgroups are its own barrier group
+// (counters in its own workspace); the workgroups of one instance are consecutive in the
+// dispatch order.
+template <bool CACHE>
+__global__ __launch_bounds__(256) void k_refine_multi(const RefineJob* __restrict__ tab) {
+  const RefineJob j = tab[blockIdx.y];
+  if ((int)blockIdx.x >= j.nb) return;
+  refine_body<CACHE>(j.M, j.X, j.pm, j.b, j.f, j.n, j.rw, j.tpr, j.maxit, j.guess, j.ws, j.out,
+                     j.flags, j.gate, j.xcopy, blockIdx.x, j.nb);
+}
+
 // C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B, on the FP64 matrix
 // cores: each wave owns a 16 x 16 tile of C (v_mfma_f64_16x16x4f64; A fragment: lane l
 // holds A[i0 + l % 16][k + l / 16], B fragment B[k + l / 16][j0 + l % 16], result item v
@@ -1422,11 +1536,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // is one chunk, so each wave waits for memory once.  Two accumulators alternate over k
 // (halving the dependent MFMA chain) and are added at the end.
 template <int KC>
-__global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
-                                                int p, int two_minus, const int* gate) {
+__device__ __forceinline__ void gemm64_body(const double* A, const double* B, double* C, int n,
+                                            int p, int two_minus, const int* gate, int bx, int by) {
   if (iter_gated(gate)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = blockIdx.y * 32 + (w >> 1) * 16, j0 = blockIdx.x * 32 + (w & 1) * 16;
+  const int i0 = by * 32 + (w >> 1) * 16, j0 = bx * 32 + (w & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
   const int ai = i0 + li, bj = j0 + li;
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
@@ -1453,6 +1567,20 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B
       C[(size_t)i * p + j] = val;
     }
   }
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
+                                                int p, int two_minus, const int* gate) {
+  gemm64_body<KC>(A, B, C, n, p, two_minus, gate, blockIdx.x, blockIdx.y);
+}
+
+template <int KC>
+__global__ __launch_bounds__(256) void k_gemm64_multi(const GemmJob* __restrict__ tab) {
+  const GemmJob j = tab[blockIdx.z];
+  const int nb = (j.n + 31) / 32;
+  if ((int)blockIdx.x >= nb || (int)blockIdx.y >= nb) return;
+  gemm64_body<KC>(j.A, j.B, j.C, j.n, j.p, j.two_minus, j.gate, blockIdx.x, blockIdx.y);
 }
 
 // out (bits of a non-negative double, atomicMax) = max |W_ij - delta_ij| over n x n.
@@ -1487,6 +1615,19 @@ __global__ void k_step_reset(int* ctl) {
   if (threadIdx.x < FsiCtl::INTS) ctl[threadIdx.x] = 0;
 }
 
+__global__ void k_step_reset_multi(int* const* __restrict__ ctls) {
+  int* ctl = ctls[blockIdx.x];
+  if (threadIdx.x < FsiCtl::INTS) ctl[threadIdx.x] = 0;
+}
+
+// Copies the control blocks of many instances into one array (FsiCtl::BYTES each), so
+// that one transfer brings them all to the host.
+__global__ void k_gather_ctl(int* const* __restrict__ ctls, int* out) {
+  constexpr int W = FsiCtl::BYTES / 4;
+  const int* ctl = ctls[blockIdx.x];
+  if (threadIdx.x < W) out[blockIdx.x * W + threadIdx.x] = ctl[threadIdx.x];
+}
+
 hipError_t launch_step_reset(int* ctl, hipStream_t st) {
   hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, st, ctl);
   return hipGetLastError();
@@ -1502,10 +1643,8 @@ hipError_t launch_identity(double* X, int p, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_identity, dim3((n + 255) / 256), dim3(256), 0, st, X, p, n);
   return hipGetLastError();
 }
-hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
-                         int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, double* xcopy, hipStream_t st) {
-  if (n < 1 || maxit < 1) return hipErrorInvalidValue;
+bool refine_shape(int n, RefineShape* out) {
+  if (n < 1) return false;
   int nb = std::min(16, (n + 7) / 8);
   int rw = (n + nb - 1) / nb;
   if ((size_t)2 * rw * n * 8 > REF_LDS_CACHE) {
@@ -1515,16 +1654,25 @@ hipError_t launch_refine(const double* M, int pm, const double* X, const double*
   nb = (n + rw - 1) / rw;  // no workgroup without rows
   int tpr = 64;            // threads per row of r = b - M f: a power of two, tpr * rw <= 256
   while (tpr > 1 && tpr * rw > 256) tpr >>= 1;
-  if (tpr * rw > 256) return hipErrorInvalidValue;
+  if (tpr * rw > 256) return false;
   const bool cache = (size_t)2 * rw * n * 8 <= REF_LDS_CACHE;
   const size_t lds = ((size_t)2 * n + 2 * rw + 4 + (cache ? (size_t)2 * rw * n : 0)) * 8;
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  if (cache)
-    hipLaunchKernelGGL(k_refine<true>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
-                       maxit, guess, ws, out, flags, gate, xcopy);
+  if (lds > 64 * 1024) return false;
+  *out = RefineShape{nb, rw, tpr, cache, lds};
+  return true;
+}
+
+hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
+                         int n, int maxit, int guess, double* ws, double* out, int* flags,
+                         const int* gate, double* xcopy, hipStream_t st) {
+  RefineShape r;
+  if (maxit < 1 || !refine_shape(n, &r)) return hipErrorInvalidValue;
+  if (r.cache)
+    hipLaunchKernelGGL(k_refine<true>, dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n, r.rw,
+                       r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
   else
-    hipLaunchKernelGGL(k_refine<false>, dim3(nb), dim3(256), lds, st, M, X, pm, b, f, n, rw, tpr,
-                       maxit, guess, ws, out, flags, gate, xcopy);
+    hipLaunchKernelGGL(k_refine<false>, dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n, r.rw,
+                       r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
@@ -1559,11 +1707,18 @@ hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, dou
   return hipGetLastError();
 }
 
-hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
+size_t schur_lds_bytes(const FsiArgs& a) {
   size_t lds = a.gx != nullptr ? 8 : (size_t)a.nf * SCHUR_LDS_PER_ROW;
-  if (lds > SCHUR_LDS_MAX || a.nf > SCHUR_CPT * SCHUR_NT) return hipErrorInvalidValue;
+  if (lds > SCHUR_LDS_MAX || a.nf > SCHUR_CPT * SCHUR_NT) return 0;
   const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
   if (all4) lds = (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4;
+  return lds;
+}
+
+hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
+  const size_t lds = schur_lds_bytes(a);
+  if (lds == 0) return hipErrorInvalidValue;
+  const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
   hipLaunchKernelGGL(k_schur_sd, dim3(a.nf), dim3(SCHUR_NT), lds, st, a, all4);
   return hipGetLastError();
 }
@@ -1585,11 +1740,15 @@ hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
   hipLaunchKernelGGL(k_beam, dim3((ncol + BEAM_NC - 1) / BEAM_NC), dim3(BEAM_NT), lds, st, a, bi);
   return hipGetLastError();
 }
-hipError_t launch_update(const FsiArgs& a, int it, int K, double tol, int fixed, hipStream_t st) {
+int update_blocks(int nf) {
   // enough waves for one group of 4 rows of the largest beam (3m - 3 <= 1.5 nf rows)
-  const int groups = (3 * a.nf / 2 + 3) / 4;
-  const int nb = std::max(1, (groups + STRUCT_NT / 64 - 1) / (STRUCT_NT / 64));
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(STRUCT_NT), 0, st, a, it, K, tol, fixed);
+  const int groups = (3 * nf / 2 + 3) / 4;
+  return std::max(1, (groups + STRUCT_NT / 64 - 1) / (STRUCT_NT / 64));
+}
+
+hipError_t launch_update(const FsiArgs& a, int it, int K, double tol, int fixed, hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(a.nf)), dim3(STRUCT_NT), 0, st, a, it, K, tol,
+                     fixed);
   return hipGetLastError();
 }
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st) {
@@ -1679,6 +1838,92 @@ hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+size_t beam_lds(int m) { return beam_lds_bytes(m); }
+
+// ------------------------------------------------------- many instances per launch
+template <typename T>
+hipError_t launch_body_ops_multi(const FsiArgs* tab, int count, int max_npts, int it,
+                                 hipStream_t st) {
+  if (count <= 0 || max_npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_body_ops_multi<T>), dim3((max_npts + 63) / 64, count), dim3(64), 0, st,
+                     tab, it);
+  return hipGetLastError();
+}
+hipError_t launch_schur_sd_multi(const FsiArgs* tab, int count, int max_nf, size_t lds, int it,
+                                 hipStream_t st) {
+  if (count <= 0 || max_nf <= 0) return hipSuccess;
+  if (lds == 0 || lds > SCHUR_LDS_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_schur_sd_multi, dim3(max_nf, count), dim3(SCHUR_NT), lds, st, tab, it);
+  return hipGetLastError();
+}
+hipError_t launch_beam_multi(const BeamJob* tab, int count, int max_m, size_t lds, int it,
+                             hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (max_m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
+  const int ncol = 2 * max_m + 1;
+  hipLaunchKernelGGL(k_beam_multi, dim3((ncol + BEAM_NC - 1) / BEAM_NC, count), dim3(BEAM_NT), lds,
+                     st, tab, it);
+  return hipGetLastError();
+}
+hipError_t launch_update_multi(const UpdateJob* tab, int count, int max_nb, int it, int K,
+                               hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_multi, dim3(max_nb, count), dim3(STRUCT_NT), 0, st, tab, it, K);
+  return hipGetLastError();
+}
+hipError_t launch_finish_multi(const FsiArgs* tab, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finish_multi, dim3(1, count), dim3(STRUCT_NT), 0, st, tab);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_spread_multi(const SpreadJob<T>* tab, int count, int max_gx, int max_gy,
+                               hipStream_t st) {
+  if (count <= 0 || max_gx <= 0 || max_gy <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_spread_multi<T>), dim3(max_gx, max_gy, count), dim3(SPREAD_NT), 0, st, tab);
+  return hipGetLastError();
+}
+hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipStream_t st) {
+  if (count <= 0 || max_n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_matvec_multi, dim3(max_n, count), dim3(256), 0, st, tab);
+  return hipGetLastError();
+}
+hipError_t launch_gemm64_multi(const GemmJob* tab, int count, int max_n, int kc52,
+                               hipStream_t st) {
+  if (count <= 0 || max_n <= 0) return hipSuccess;
+  const int nb = (max_n + 31) / 32;
+  if (kc52)
+    hipLaunchKernelGGL(k_gemm64_multi<52>, dim3(nb, nb, count), dim3(256), 0, st, tab);
+  else
+    hipLaunchKernelGGL(k_gemm64_multi<16>, dim3(nb, nb, count), dim3(256), 0, st, tab);
+  return hipGetLastError();
+}
+hipError_t launch_refine_multi(const RefineJob* tab, int count, int max_nb, size_t lds, int cache,
+                               hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (lds > 64 * 1024 || max_nb < 1 || max_nb > REF_NB_MAX) return hipErrorInvalidValue;
+  if (cache)
+    hipLaunchKernelGGL(k_refine_multi<true>, dim3(max_nb, count), dim3(256), lds, st, tab);
+  else
+    hipLaunchKernelGGL(k_refine_multi<false>, dim3(max_nb, count), dim3(256), lds, st, tab);
+  return hipGetLastError();
+}
+hipError_t launch_step_reset_multi(int* const* ctls, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_step_reset_multi, dim3(count), dim3(64), 0, st, ctls);
+  return hipGetLastError();
+}
+hipError_t launch_gather_ctl(int* const* ctls, int count, int* out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_ctl, dim3(count), dim3(64), 0, st, ctls, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_body_ops_multi<float>(const FsiArgs*, int, int, int, hipStream_t);
+template hipError_t launch_body_ops_multi<double>(const FsiArgs*, int, int, int, hipStream_t);
+template hipError_t launch_spread_multi<float>(const SpreadJob<float>*, int, int, int, hipStream_t);
+template hipError_t launch_spread_multi<double>(const SpreadJob<double>*, int, int, int,
+                                                hipStream_t);
 template hipError_t launch_body_ops<float>(const FsiArgs&, hipStream_t);
 template hipError_t launch_body_ops<double>(const FsiArgs&, hipStream_t);
 template hipError_t launch_spread<float>(const FsiArgs&, int, int, int, int, float*, int, hipStream_t);

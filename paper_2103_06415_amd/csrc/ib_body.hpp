@@ -100,6 +100,89 @@ struct FsiArgs {
   double* delta;       // [0] max |delta| of the last update
 };
 
+// Per-instance entries of the FSI launches that take many instances at once (ib_batch_*).
+struct BeamJob {
+  FsiArgs a;
+  int bi, m;  // deformable body index and its point count
+};
+struct UpdateJob {
+  FsiArgs a;
+  double tol;
+  int fixed;
+  int nb;  // workgroups of this instance (update_blocks)
+};
+template <typename T>
+struct SpreadJob {
+  FsiArgs a;
+  int jlo, jhi, ilo, ihi;
+  T* out;
+  int po;
+};
+struct MatvecJob {
+  const double* A;
+  int pa;
+  const double* x;
+  double* y;
+  int n;
+};
+struct GemmJob {
+  const double* A;
+  const double* B;
+  double* C;
+  int n, p, two_minus;
+  const int* gate;
+};
+struct RefineJob {
+  const double* M;
+  const double* X;
+  int pm;
+  const double* b;
+  double* f;
+  int n, rw, tpr, maxit, guess;
+  double* ws;
+  double* out;
+  int* flags;
+  const int* gate;
+  double* xcopy;
+  int nb;
+};
+// Launch shape of one refinement (as launch_refine chooses it); false if n is too large.
+struct RefineShape {
+  int nb, rw, tpr;
+  bool cache;
+  size_t lds;
+};
+bool refine_shape(int n, RefineShape* out);
+// Workgroups of k_update for nf stress unknowns.
+int update_blocks(int nf);
+// Dynamic LDS of the sub-domain Schur assembly (0 if it does not fit).
+size_t schur_lds_bytes(const FsiArgs& a);
+size_t beam_lds(int m);
+constexpr int SPREAD_TILE_X = 64, SPREAD_TILE_Y = 4, SPREAD_ROWS_MAX = 4096;
+
+template <typename T>
+hipError_t launch_body_ops_multi(const FsiArgs* tab, int count, int max_npts, int it,
+                                 hipStream_t st);
+hipError_t launch_schur_sd_multi(const FsiArgs* tab, int count, int max_nf, size_t lds, int it,
+                                 hipStream_t st);
+hipError_t launch_beam_multi(const BeamJob* tab, int count, int max_m, size_t lds, int it,
+                             hipStream_t st);
+hipError_t launch_update_multi(const UpdateJob* tab, int count, int max_nb, int it, int K,
+                               hipStream_t st);
+hipError_t launch_finish_multi(const FsiArgs* tab, int count, hipStream_t st);
+template <typename T>
+hipError_t launch_spread_multi(const SpreadJob<T>* tab, int count, int max_gx, int max_gy,
+                               hipStream_t st);
+hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipStream_t st);
+// kc52: every entry has n <= 208 (the whole k range in one chunk); otherwise none has
+hipError_t launch_gemm64_multi(const GemmJob* tab, int count, int max_n, int kc52,
+                               hipStream_t st);
+hipError_t launch_refine_multi(const RefineJob* tab, int count, int max_nb, size_t lds, int cache,
+                               hipStream_t st);
+hipError_t launch_step_reset_multi(int* const* ctls, int count, hipStream_t st);
+// out[FsiCtl::BYTES / 4 * b + i] = ctls[b][i]
+hipError_t launch_gather_ctl(int* const* ctls, int count, int* out, hipStream_t st);
+
 // Rows of the offline stage: body rows (from the operator arrays) or sub-domain points.
 struct OffRows {
   int kind;  // 0: body rows from st arrays, 1: sub-domain points

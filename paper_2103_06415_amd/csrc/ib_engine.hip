@@ -18,6 +18,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <list>
 #include <map>
 #include <memory>
@@ -1681,6 +1682,540 @@ ib_status check(ib_solver* s) {
   return IB_OK;
 }
 
+// ------------------------------------------------------------------ batches
+//
+// A batch steps many solvers together: every launch of a step covers all members that
+// need it (one launch per grid size for the flow kernels, one for all members for the
+// FSI kernels), with each member's arguments in a table that is built on the host and
+// moved to the device with one copy before the step's first launch.  Each member keeps
+// its own state, scratch and control block, and every kernel computes exactly what it
+// computes for the member alone.
+
+// One step's launch tables (host bytes, 256-byte aligned entries) and the launches that
+// read them, in stream order.
+struct BatchPlan {
+  std::vector<char> tab;
+  std::vector<std::function<hipError_t(const char*)>> launches;
+
+  template <class J>
+  size_t put(const std::vector<J>& v) {
+    const size_t off = (tab.size() + 255) & ~size_t(255);
+    tab.resize(off + v.size() * sizeof(J));
+    std::memcpy(tab.data() + off, v.data(), v.size() * sizeof(J));
+    return off;
+  }
+  // f(device table, count) issues the launch
+  template <class J, class F>
+  void add(const std::vector<J>& v, F f) {
+    if (v.empty()) return;
+    const size_t off = put(v);
+    const int count = (int)v.size();
+    launches.push_back(
+        [off, count, f](const char* d) { return f(reinterpret_cast<const J*>(d + off), count); });
+  }
+};
+
+}  // namespace
+
+struct ib_batch {
+  std::vector<ib_solver*> mem;
+  hipStream_t stream = nullptr;
+  bool fp64 = false;
+  // launch tables: two slots (alternate steps), pinned host staging and device copies
+  char* hbuf[2] = {nullptr, nullptr};
+  char* dbuf[2] = {nullptr, nullptr};
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  size_t cap = 0;
+  int slot = 0;
+  // gathered control blocks of the members iterating on the device, and their mirror
+  int* dctl = nullptr;
+  int* hctl = nullptr;
+  int ctl_cap = 0;
+  int64_t steps = 0, member_steps_batched = 0, member_steps_alone = 0, launches = 0,
+          resumes = 0;
+  std::string last_error;
+};
+
+namespace {
+
+ib_status batch_hip(ib_batch* b, hipError_t e, const char* what) {
+  b->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return IB_ERR_HIP;
+}
+
+#define BCHK(expr)                                        \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return batch_hip(b, e_, #expr); \
+  } while (0)
+
+void batch_free_buffers(ib_batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->hbuf[k]) (void)hipHostFree(b->hbuf[k]);
+    if (b->dbuf[k]) (void)hipFree(b->dbuf[k]);
+    b->hbuf[k] = b->dbuf[k] = nullptr;
+  }
+  b->cap = 0;
+}
+
+ib_status batch_reserve(ib_batch* b, size_t bytes, int nctl) {
+  if (bytes > b->cap) {
+    BCHK(hipStreamSynchronize(b->stream));  // nothing may still read the old tables
+    batch_free_buffers(b);
+    const size_t cap = std::max<size_t>(bytes * 2, 64 * 1024);
+    for (int k = 0; k < 2; ++k) {
+      if (hipHostMalloc(reinterpret_cast<void**>(&b->hbuf[k]), cap, 0) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&b->dbuf[k]), cap) != hipSuccess) {
+        batch_free_buffers(b);
+        b->last_error = "launch tables of the batch";
+        return IB_ERR_OOM;
+      }
+    }
+    b->cap = cap;
+  }
+  if (nctl > b->ctl_cap) {
+    BCHK(hipStreamSynchronize(b->stream));
+    if (b->dctl) (void)hipFree(b->dctl);
+    if (b->hctl) (void)hipHostFree(b->hctl);
+    b->dctl = nullptr;
+    b->hctl = nullptr;
+    b->ctl_cap = 0;
+    const size_t bytes_ctl = (size_t)nctl * FsiCtl::BYTES;
+    if (hipMalloc(reinterpret_cast<void**>(&b->dctl), bytes_ctl) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->hctl), bytes_ctl, 0) != hipSuccess) {
+      b->last_error = "control blocks of the batch";
+      return IB_ERR_OOM;
+    }
+    b->ctl_cap = nctl;
+  }
+  return IB_OK;
+}
+
+// Members whose next step runs alone: their first step (no history yet), a step whose
+// Schur inverse must first be built (host-driven LU) or whose FSI part is host-driven, and
+// members with the matrix-core transforms or kernel timing on.
+bool steps_alone(const ib_solver* s) {
+  return s->first || s->gemm || s->timing ||
+         (!s->bodies.empty() && !s->stationary && !fsi_ahead(s));
+}
+
+// Members of one flow launch: the same grid size and kernel configurations.
+struct FlowGroup {
+  int n = 0, vr = 0, vc = 0, vi = 0;
+  std::vector<ib_solver*> m;
+};
+
+template <typename T>
+ib_status batch_step(ib_batch* b) {
+  // members that step alone this time (host-driven path, on the batch's stream)
+  std::vector<ib_solver*> ready;
+  for (ib_solver* s : b->mem) {
+    if (!steps_alone(s)) {
+      ready.push_back(s);
+      continue;
+    }
+    StepPlan p = plan_step(s);
+    p.use_graph = false;
+    ib_status st = do_step<T>(s, p);
+    if (st) {
+      s->failed = true;
+      b->last_error = s->last_error;
+      return st;
+    }
+    b->member_steps_alone++;
+  }
+  if (ready.empty()) return IB_OK;
+  for (ib_solver* s : ready) {
+    if (!s->nmov) continue;
+    ib_status st = update_poses(s, (s->step + 1) * s->cfg.dt);  // constraint at t_{n+1}
+    if (st) {
+      s->failed = true;
+      b->last_error = s->last_error;
+      return st;
+    }
+  }
+  std::vector<FlowGroup> groups;
+  std::vector<ib_solver*> bodied, iter, stat;
+  int gmax = 0, K = 0;
+  for (ib_solver* s : ready) {
+    FlowGroup* grp = nullptr;
+    for (auto& q : groups)
+      if (q.n == s->n && q.vr == s->tune.rhs && q.vc == s->tune.col && q.vi == s->tune.idst)
+        grp = &q;
+    if (!grp) {
+      groups.push_back(FlowGroup{s->n, s->tune.rhs, s->tune.col, s->tune.idst, {}});
+      grp = &groups.back();
+    }
+    grp->m.push_back(s);
+    gmax = std::max(gmax, (int)s->lv.size());
+    if (s->bodies.empty()) continue;
+    bodied.push_back(s);
+    if (s->stationary) {
+      stat.push_back(s);
+    } else {
+      iter.push_back(s);
+      K = std::max(K, fsi_ahead_count(s));
+    }
+  }
+  BatchPlan pl;
+  hipStream_t st = b->stream;
+  auto gate_of = [](const ib_solver* s) -> const int* { return s->stationary ? nullptr : s->gate; };
+
+  // ---- predictor, coarse to fine (levels counted from each member's finest)
+  for (int g = gmax - 1; g >= 0; --g) {
+    for (auto& q : groups) {
+      std::vector<RingJob<T>> rings;
+      std::vector<RhsArgs<T>> rhs;
+      std::vector<ColArgs<T>> cols;
+      std::vector<IdstJob<T>> star, fin;
+      int star_rows = 0;
+      const void* tw = q.m[0]->tw;
+      const void* lam = q.m[0]->lam;
+      for (ib_solver* s : q.m) {
+        const int G = (int)s->lv.size(), n = s->n, P = s->pitch;
+        if (g >= G) continue;
+        LevelState& L = s->lv[g];
+        const bool has_ring = g < G - 1;
+        const int nxt = 1 - L.gcur;
+        if (has_ring)
+          rings.push_back(RingJob<T>{static_cast<const T*>(s->lv[g + 1].s), P,
+                                     static_cast<T*>(L.sring), static_cast<T*>(L.gring[nxt]),
+                                     static_cast<T*>(s->lift)});
+        RhsArgs<T> a{};
+        a.s = static_cast<T*>(L.s);
+        a.g = static_cast<T*>(L.g);
+        a.gf = g > 0 ? static_cast<T*>(s->lv[g - 1].g) : nullptr;
+        a.gring = static_cast<T*>(L.gring[L.gcur]);
+        a.gring_new = has_ring ? static_cast<T*>(L.gring[nxt]) : nullptr;
+        a.hist_in = static_cast<T*>(L.hist);
+        a.hist_out = static_cast<T*>(L.hist);
+        a.out = static_cast<T*>(s->work);
+        a.n = n;
+        a.ps = a.pg = a.pgf = a.ph = a.po = P;
+        a.alpha = (T)L.alpha;
+        a.dt = (T)s->cfg.dt;
+        a.ux = (T)(s->cfg.u_inf[0] * L.h);
+        a.uy = (T)(s->cfg.u_inf[1] * L.h);
+        a.cn = (T)(-1.0 / (2.0 * L.h * L.h));
+        a.var = s->tune.rhs;
+        rhs.push_back(a);
+        ColArgs<T> c{};
+        c.var = s->tune.col;
+        c.in = static_cast<T*>(s->work);
+        c.out = static_cast<T*>(s->work);
+        c.out2 = static_cast<T*>(s->workg);
+        c.lift = has_ring ? static_cast<const T*>(s->lift) : nullptr;
+        c.pi = c.po = P;
+        c.r0 = 1;
+        c.r1 = n - 1;
+        c.alpha = (T)L.alpha;
+        c.scale = (T)(4.0 / ((double)n * n));
+        c.w0 = 1;
+        c.w1 = n - 1;
+        cols.push_back(c);
+        const T* ring = has_ring ? static_cast<T*>(L.sring) : nullptr;
+        if (g == 0 && !s->bodies.empty()) {
+          RowArgs<T> r{};
+          r.in = static_cast<T*>(s->work);
+          r.pi = r.po = P;
+          r.out = static_cast<T*>(s->sstar);
+          r.r0 = std::max(1, s->blo - 3);
+          r.r1 = std::min(n - 1, s->bhi + 3);
+          star.push_back(IdstJob<T>{r, ring, 0});
+          star_rows = std::max(star_rows, r.r1 - r.r0 + 1);
+        }
+        if (g > 0) {
+          RowArgs<T> r{};
+          r.in = static_cast<T*>(s->work);
+          r.pi = r.po = P;
+          r.out = static_cast<T*>(L.s);
+          r.r0 = 1;
+          r.r1 = n - 1;
+          r.in2 = static_cast<T*>(s->workg);
+          r.out2 = static_cast<T*>(L.g);
+          r.var = s->tune.idst;
+          fin.push_back(IdstJob<T>{r, ring, 1});
+        }
+      }
+      const int n = q.n, vr = q.vr, vc = q.vc, vi = q.vi;
+      pl.add(rings, [=](const RingJob<T>* d, int c) { return launch_ring_multi<T>(d, c, n, tw, st); });
+      pl.add(rhs, [=](const RhsArgs<T>* d, int c) {
+        return launch_rhs_rowdst_multi<T>(d, c, n, vr, tw, st);
+      });
+      pl.add(cols, [=](const ColArgs<T>* d, int c) {
+        return launch_col_solve_multi<T>(d, c, n, vc, tw, lam, st);
+      });
+      pl.add(star, [=](const IdstJob<T>* d, int c) {
+        return launch_row_idst_multi<T>(d, c, n, star_rows, 0, 0, tw, st);
+      });
+      pl.add(fin, [=](const IdstJob<T>* d, int c) {
+        return launch_row_idst_multi<T>(d, c, n, n - 1, 1, vi, tw, st);
+      });
+    }
+  }
+
+  // ---- FSI part (Algorithm 2's loop) for every member with bodies
+  std::vector<int*> ctls;
+  for (ib_solver* s : bodied) ctls.push_back(s->flags);
+  pl.add(ctls, [=](int* const* d, int c) { return launch_step_reset_multi(d, c, st); });
+  {
+    // stationary bodies: f = M^{-1} rhs
+    std::vector<FsiArgs> ops;
+    std::vector<MatvecJob> mv;
+    int max_pts = 0, max_nf = 0;
+    for (ib_solver* s : stat) {
+      FsiArgs a = s->fa;
+      a.iter = 0;
+      ops.push_back(a);
+      mv.push_back(MatvecJob{s->Minv, a.pm, s->rhs, s->f, s->nf});
+      max_pts = std::max(max_pts, a.npts);
+      max_nf = std::max(max_nf, s->nf);
+    }
+    pl.add(ops, [=](const FsiArgs* d, int c) { return launch_body_ops_multi<T>(d, c, max_pts, 0, st); });
+    pl.add(mv, [=](const MatvecJob* d, int c) { return launch_matvec_multi(d, c, max_nf, st); });
+  }
+  if (!iter.empty()) {
+    std::vector<FsiArgs> fa;
+    std::vector<BeamJob> beams;
+    std::vector<UpdateJob> upd;
+    int max_pts = 0, max_nf = 0, max_m = 0, max_ub = 0;
+    size_t schur_lds = 0, beam_lds_max = 0;
+    for (ib_solver* s : iter) {
+      FsiArgs a = s->fa;
+      a.gate = s->gate;
+      fa.push_back(a);
+      max_pts = std::max(max_pts, a.npts);
+      max_nf = std::max(max_nf, s->nf);
+      const size_t l = schur_lds_bytes(a);
+      if (l == 0) {
+        b->last_error = "Schur assembly does not fit a workgroup";
+        return IB_ERR_ARG;
+      }
+      schur_lds = std::max(schur_lds, l);
+      for (size_t bi = 0; bi < s->bodies.size(); ++bi) {
+        if (s->bodies[bi].kind != BODY_DEFORMABLE) continue;
+        const int m = s->bodies[bi].m;
+        beams.push_back(BeamJob{a, (int)bi, m});
+        max_m = std::max(max_m, m);
+        beam_lds_max = std::max(beam_lds_max, beam_lds(m));
+      }
+      const int nb = update_blocks(s->nf);
+      upd.push_back(UpdateJob{a, s->cfg.newton_tol, s->cfg.newton_fixed_iter, nb});
+      max_ub = std::max(max_ub, nb);
+    }
+    const size_t fa_off = pl.put(fa);
+    const size_t beam_off = beams.empty() ? 0 : pl.put(beams);
+    const size_t upd_off = pl.put(upd);
+    const int ni = (int)iter.size(), nbeam = (int)beams.size();
+    for (int it = 0; it < K; ++it) {
+      pl.launches.push_back([=](const char* d) {
+        return launch_body_ops_multi<T>(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, max_pts,
+                                        it, st);
+      });
+      if (nbeam)
+        pl.launches.push_back([=](const char* d) {
+          return launch_beam_multi(reinterpret_cast<const BeamJob*>(d + beam_off), nbeam, max_m,
+                                   beam_lds_max, it, st);
+        });
+      pl.launches.push_back([=](const char* d) {
+        return launch_schur_sd_multi(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, max_nf,
+                                     schur_lds, it, st);
+      });
+      // Newton-Schulz refresh of the inverse into Xn, then the refinement (split by the
+      // GEMM's k chunk and the refinement's LDS mode)
+      std::vector<GemmJob> g1[2], g2[2];
+      std::vector<RefineJob> rj[2];
+      int gmax_n[2] = {0, 0}, rnb[2] = {0, 0};
+      size_t rlds[2] = {0, 0};
+      for (ib_solver* s : iter) {
+        const FsiArgs& a = s->fa;
+        const int nf = s->nf;
+        const bool refresh = it == 0 || s->refresh_every_iter;
+        const double* X = s->Minv;
+        double* xcopy = nullptr;
+        if (refresh) {
+          const int k = nf <= 4 * 52 ? 1 : 0;
+          g1[k].push_back(GemmJob{a.M, s->Minv, s->W, nf, a.pm, 1, s->gate});
+          g2[k].push_back(GemmJob{s->Minv, s->W, s->Xn, nf, a.pm, 0, s->gate});
+          gmax_n[k] = std::max(gmax_n[k], nf);
+          X = s->Xn;
+          xcopy = s->Minv;
+        }
+        RefineShape sh;
+        if (!refine_shape(nf, &sh)) {
+          b->last_error = "Schur system too large for the refinement";
+          return IB_ERR_ARG;
+        }
+        const int c = sh.cache ? 1 : 0;
+        rj[c].push_back(RefineJob{a.M, X, a.pm, s->rhs, s->f, nf, sh.rw, sh.tpr, REFINE_MAXIT,
+                                  it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags,
+                                  s->gate, xcopy, sh.nb});
+        rnb[c] = std::max(rnb[c], sh.nb);
+        rlds[c] = std::max(rlds[c], sh.lds);
+      }
+      for (int k = 0; k < 2; ++k) {
+        const int mn = gmax_n[k];
+        pl.add(g1[k], [=](const GemmJob* d, int c) { return launch_gemm64_multi(d, c, mn, k, st); });
+      }
+      for (int k = 0; k < 2; ++k) {
+        const int mn = gmax_n[k];
+        pl.add(g2[k], [=](const GemmJob* d, int c) { return launch_gemm64_multi(d, c, mn, k, st); });
+      }
+      for (int c = 0; c < 2; ++c) {
+        const int mb = rnb[c];
+        const size_t l = rlds[c];
+        pl.add(rj[c], [=](const RefineJob* d, int cnt) {
+          return launch_refine_multi(d, cnt, mb, l, c, st);
+        });
+      }
+      pl.launches.push_back([=](const char* d) {
+        return launch_update_multi(reinterpret_cast<const UpdateJob*>(d + upd_off), ni, max_ub, it,
+                                   K, st);
+      });
+    }
+    pl.launches.push_back([=](const char* d) {
+      return launch_finish_multi(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, st);
+    });
+  }
+  {
+    // corrector source on level 0 (eqs. (20), (40)) for every member with bodies
+    std::vector<SpreadJob<T>> sp;
+    int gx = 0, gy = 0;
+    for (ib_solver* s : bodied) {
+      if (s->nf > SPREAD_ROWS_MAX) {
+        b->last_error = "too many body rows for the spread";
+        return IB_ERR_ARG;
+      }
+      FsiArgs a = s->fa;
+      a.gate = gate_of(s);
+      sp.push_back(SpreadJob<T>{a, s->blo, s->bhi, s->bilo, s->bihi, static_cast<T*>(s->work2),
+                                s->pitch});
+      gx = std::max(gx, (s->n - 1 + SPREAD_TILE_X - 1) / SPREAD_TILE_X);
+      gy = std::max(gy, (s->bhi - s->blo + 1 + SPREAD_TILE_Y - 1) / SPREAD_TILE_Y);
+    }
+    pl.add(sp, [=](const SpreadJob<T>* d, int c) { return launch_spread_multi<T>(d, c, gx, gy, st); });
+  }
+  for (auto& q : groups) {
+    std::vector<RowArgs<T>> rows;
+    std::vector<ColArgs<T>> cols;
+    std::vector<IdstJob<T>> fin;
+    int maxrows = 0;
+    for (ib_solver* s : q.m) {
+      const int n = s->n, P = s->pitch, G = (int)s->lv.size();
+      LevelState& L0 = s->lv[0];
+      const int* gate = s->bodies.empty() ? nullptr : gate_of(s);
+      if (!s->bodies.empty()) {
+        RowArgs<T> r{};
+        r.in = static_cast<T*>(s->work2);
+        r.out = static_cast<T*>(s->work2);
+        r.pi = r.po = P;
+        r.r0 = s->blo;
+        r.r1 = s->bhi;
+        r.gate = gate;
+        rows.push_back(r);
+        maxrows = std::max(maxrows, s->bhi - s->blo + 1);
+        ColArgs<T> c{};
+        c.in = static_cast<T*>(s->work2);
+        c.out = static_cast<T*>(s->work);
+        c.pi = c.po = P;
+        c.r0 = s->blo;
+        c.r1 = s->bhi;
+        c.alpha = (T)L0.alpha;
+        c.scale = (T)(-s->cfg.dt * 4.0 / ((double)n * n));
+        c.out2 = static_cast<T*>(s->workg);
+        c.accumulate = 1;
+        c.w0 = 1;
+        c.w1 = n - 1;
+        c.var = s->tune.col;
+        c.gate = gate;
+        cols.push_back(c);
+      }
+      RowArgs<T> r{};
+      r.in = static_cast<T*>(s->work);
+      r.pi = r.po = P;
+      r.out = static_cast<T*>(L0.s);
+      r.r0 = 1;
+      r.r1 = n - 1;
+      r.in2 = static_cast<T*>(s->workg);
+      r.out2 = static_cast<T*>(L0.g);
+      r.var = s->tune.idst;
+      r.gate = gate;
+      fin.push_back(IdstJob<T>{r, G > 1 ? static_cast<T*>(L0.sring) : nullptr, 1});
+    }
+    const int n = q.n, vc = q.vc, vi = q.vi;
+    const void* tw = q.m[0]->tw;
+    const void* lam = q.m[0]->lam;
+    pl.add(rows, [=](const RowArgs<T>* d, int c) {
+      return launch_rowdst_multi<T>(d, c, n, maxrows, tw, st);
+    });
+    pl.add(cols, [=](const ColArgs<T>* d, int c) {
+      return launch_col_solve_multi<T>(d, c, n, vc, tw, lam, st);
+    });
+    pl.add(fin, [=](const IdstJob<T>* d, int c) {
+      return launch_row_idst_multi<T>(d, c, n, n - 1, 1, vi, tw, st);
+    });
+  }
+  std::vector<int*> ictl;
+  for (ib_solver* s : iter) ictl.push_back(s->flags);
+  ib_status rs0 = batch_reserve(b, 0, (int)ictl.size());
+  if (rs0) return rs0;
+  int* const dctl_target = b->dctl;
+  pl.add(ictl, [=](int* const* d, int c) { return launch_gather_ctl(d, c, dctl_target, st); });
+  rs0 = batch_reserve(b, pl.tab.size(), (int)ictl.size());
+  if (rs0) return rs0;
+
+  // ---- tables to the device (one copy), then the launches
+  const int k = b->slot;
+  b->slot ^= 1;
+  BCHK(hipEventSynchronize(b->copied[k]));  // the copy from this slot two steps ago is done
+  std::memcpy(b->hbuf[k], pl.tab.data(), pl.tab.size());
+  BCHK(hipMemcpyAsync(b->dbuf[k], b->hbuf[k], pl.tab.size(), hipMemcpyHostToDevice, st));
+  BCHK(hipEventRecord(b->copied[k], st));
+  for (auto& f : pl.launches) BCHK(f(b->dbuf[k]));
+  b->launches += (int64_t)pl.launches.size();
+
+  // ---- convergence of the members iterating on the device
+  if (!iter.empty()) {
+    const size_t cb = (size_t)iter.size() * FsiCtl::BYTES;
+    BCHK(hipMemcpyAsync(b->hctl, b->dctl, cb, hipMemcpyDeviceToHost, st));
+    BCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < iter.size(); ++i) {
+      ib_solver* s = iter[i];
+      std::memcpy(s->hctl, reinterpret_cast<const char*>(b->hctl) + i * FsiCtl::BYTES,
+                  FsiCtl::BYTES);
+      int resume = -1;
+      ib_status rs = fsi_after_ahead(s, &resume);
+      if (!rs && resume >= 0) {
+        // the launched iterations did not suffice: finish on the host as a lone step would
+        s->fsi_resumes++;
+        b->resumes++;
+        rs = fsi_host<T>(s, resume);
+        if (!rs) rs = final_transform_level0<T>(s);
+      }
+      if (rs) {
+        s->failed = true;
+        b->last_error = s->last_error;
+        return rs;
+      }
+    }
+  }
+  for (ib_solver* s : stat) {
+    s->iters_last = 1;
+    s->delta_last = 0.0;
+    s->iters_max = std::max(s->iters_max, 1);
+  }
+  for (ib_solver* s : ready) {
+    const int G = (int)s->lv.size();
+    for (int g = 0; g < G - 1; ++g) s->lv[g].gcur = 1 - s->lv[g].gcur;
+    s->first = false;
+    s->step++;
+  }
+  b->member_steps_batched += (int64_t)ready.size();
+  return IB_OK;
+}
+
+#undef BCHK
+
 }  // namespace
 
 // ======================================================================== C ABI
@@ -2114,6 +2649,87 @@ ib_status read_vorticity_impl(ib_solver* s, int32_t level, double* out, int64_t 
 ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap) {
   HipShared hip_lock;
   return read_vorticity_impl(s, level, out, cap);
+}
+
+ib_status ib_batch_create(ib_solver* const* members, int32_t count, void* hip_stream,
+                          ib_batch** out) {
+  HipShared hip_lock;
+  if (!out || !members || count < 1) return IB_ERR_ARG;
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    ib_solver* s = members[i];
+    if (!s) return IB_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (members[j] == s) return IB_ERR_ARG;
+    if (s->fp64 != members[0]->fp64) return IB_ERR_ARG;
+    if (!s->prepared || s->failed || s->released) return IB_ERR_STATE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < count; ++i) {
+    ib_solver* s = members[i];
+    if (s->stream != st) {
+      hipError_t e = hipStreamSynchronize(s->stream);  // work queued on the old stream
+      if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+      s->stream = st;
+    }
+  }
+  ib_batch* b = new ib_batch();
+  b->mem.assign(members, members + count);
+  b->stream = st;
+  b->fp64 = members[0]->fp64;
+  for (auto& e : b->copied)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto f : b->copied)
+        if (f) (void)hipEventDestroy(f);
+      delete b;
+      return IB_ERR_HIP;
+    }
+  *out = b;
+  return IB_OK;
+}
+
+ib_status ib_batch_step(ib_batch* b, int32_t nsteps) {
+  if (!b || nsteps < 0) return IB_ERR_ARG;
+  HipShared hip_lock;
+  for (ib_solver* s : b->mem)
+    if (!s->prepared || s->failed || s->released) {
+      b->last_error = "a member is not prepared, has failed or was released";
+      return IB_ERR_STATE;
+    }
+  for (int k = 0; k < nsteps; ++k) {
+    ib_status st = b->fp64 ? batch_step<double>(b) : batch_step<float>(b);
+    if (st) return st;
+    b->steps++;
+  }
+  return IB_OK;
+}
+
+ib_status ib_batch_get_stats(const ib_batch* b, ib_batch_stats* out) {
+  if (!b || !out) return IB_ERR_ARG;
+  out->steps = b->steps;
+  out->member_steps_batched = b->member_steps_batched;
+  out->member_steps_alone = b->member_steps_alone;
+  out->launches = b->launches;
+  out->fsi_resumes = b->resumes;
+  return IB_OK;
+}
+
+const char* ib_batch_last_error(const ib_batch* b) {
+  if (!b) return "null batch";
+  return b->last_error.c_str();
+}
+
+ib_status ib_batch_destroy(ib_batch* b) {
+  if (!b) return IB_ERR_ARG;
+  HipShared hip_lock;
+  (void)hipStreamSynchronize(b->stream);
+  batch_free_buffers(b);
+  if (b->dctl) (void)hipFree(b->dctl);
+  if (b->hctl) (void)hipHostFree(b->hctl);
+  for (auto e : b->copied)
+    if (e) (void)hipEventDestroy(e);
+  delete b;
+  return IB_OK;
 }
 
 const char* ib_last_error(const ib_solver* s) {

@@ -115,9 +115,9 @@ __device__ __forceinline__ T rhs_staged(const RhsArgs<T>& a, const T* ss, const 
 // Explicit right-hand side of ROWS interior rows fused with their row DST.  The rows
 // j-1 .. j+ROWS of s and gamma are staged in LDS (every load of a thread in flight at
 // once); the staging area is then reused as the transform buffer.
-template <typename T, int N, int ROWS, int NT, int DST, int MAXR = 16>
-__global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __restrict__ tw,
-                                                   int nblocks) {
+template <typename T, int N, int ROWS, int NT, int DST, int MAXR>
+__device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>* __restrict__ tw,
+                                                int nblocks, int bx) {
   constexpr int W = N + 1;           // staged row width, ring columns included
   constexpr int SR = ROWS + 2;       // staged rows j0-1 .. j0+ROWS
   constexpr int STG = 2 * SR * W;    // s and gamma, in T units
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
   __shared__ T sring[4][W];          // new circulation ring: bottom, top, left, right
   static_assert(sizeof(uni) + sizeof(stw) + sizeof(sring) <= 160 * 1024, "LDS");
-  const int blk = xcd_block(blockIdx.x, nblocks);
+  const int blk = xcd_block(bx, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
   const int j0 = 1 + blk * ROWS;
@@ -232,18 +232,35 @@ __global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __
   }
 }
 
+template <typename T, int N, int ROWS, int NT, int DST, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_rhs_rowdst(RhsArgs<T> a, const c2<T>* __restrict__ tw,
+                                                   int nblocks) {
+  rhs_rowdst_body<T, N, ROWS, NT, DST, MAXR>(a, tw, nblocks, blockIdx.x);
+}
+
+// Many instances of one grid size in one launch: instance blockIdx.y takes its arguments
+// from tab[blockIdx.y]; workgroups beyond its own row blocks leave at once.
+template <typename T, int N, int ROWS, int NT, int DST, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_rhs_rowdst_multi(const RhsArgs<T>* __restrict__ tab,
+                                                         const c2<T>* __restrict__ tw) {
+  const RhsArgs<T> a = tab[blockIdx.y];
+  const int nb = (a.n - 1 + ROWS - 1) / ROWS;
+  if ((int)blockIdx.x >= xcd_grid(nb)) return;
+  rhs_rowdst_body<T, N, ROWS, NT, DST, MAXR>(a, tw, nb, blockIdx.x);
+}
+
 // Plain row DST of rows [r0, r1] (1-based interior rows) of a real array; batched
-// over blockIdx.y with the given strides.
+// over `by` (blockIdx.y) with the given strides.
 template <typename T, int N, int ROWS, int NT>
-__global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __restrict__ tw,
-                                               int nblocks) {
+__device__ __forceinline__ void rowdst_body(const RowArgs<T>& a, const c2<T>* __restrict__ tw,
+                                            int nblocks, int bx, int by) {
   __shared__ c2<T> buf[ROWS * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
-  const int blk = xcd_block(blockIdx.x, nblocks);
+  const int blk = xcd_block(bx, nblocks);
   if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
-  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
-  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  const T* in = a.in + (size_t)by * a.bsi;
+  T* out = a.out + (size_t)by * a.bso;
   const int j0 = a.r0 + blk * ROWS;
   {
     constexpr int CNT = ROWS * (N - 1);
@@ -277,13 +294,29 @@ __global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __rest
   }
 }
 
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_rowdst(RowArgs<T> a, const c2<T>* __restrict__ tw,
+                                               int nblocks) {
+  rowdst_body<T, N, ROWS, NT>(a, tw, nblocks, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int N, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_rowdst_multi(const RowArgs<T>* __restrict__ tab,
+                                                     const c2<T>* __restrict__ tw) {
+  const RowArgs<T> a = tab[blockIdx.y];
+  const int nb = (a.r1 - a.r0 + 1 + ROWS - 1) / ROWS;
+  if (nb <= 0 || (int)blockIdx.x >= xcd_grid(nb)) return;
+  rowdst_body<T, N, ROWS, NT>(a, tw, nb, blockIdx.x, 0);
+}
+
 // Column DST, spectral scale scale / (lam (1 + alpha lam)), inverse column DST.
 // Reads input rows [r0, r1] (others are zero) and writes
 //   out = (accumulate ? out : 0) + result
 // for every row; input and output may alias when accumulate == 0.
-template <typename T, int N, int CW, int NT, int MAXR = 16>
-__global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
-                                                  const T* __restrict__ lam, int nblocks) {
+template <typename T, int N, int CW, int NT, int MAXR>
+__device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>* __restrict__ tw,
+                                               const T* __restrict__ lam, int nblocks, int bx,
+                                               int by) {
   __shared__ c2<T> buf[CW * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
   __shared__ T slam[N];
@@ -291,16 +324,16 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   __shared__ T slift01[2 * CW]; // bottom and top edge transforms at this block's columns
   static_assert(sizeof(buf) + sizeof(stw) + sizeof(slam) + sizeof(slift) + sizeof(slift01) <=
                     160 * 1024, "LDS");
-  const int blk = xcd_block(blockIdx.x, nblocks);
+  const int blk = xcd_block(bx, nblocks);
   if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const int k0 = blk * CW;
-  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
+  const T* in = a.in + (size_t)by * a.bsi;
   {
     constexpr int CNT = (N - 1) * CW;
     constexpr int PER = (CNT + NT - 1) / NT;
     T v[PER];
-    const int rf = a.rfirst != nullptr ? a.rfirst[blockIdx.y] : 0;
+    const int rf = a.rfirst != nullptr ? a.rfirst[by] : 0;
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
@@ -391,7 +424,7 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   }
   const int nout = a.out2 != nullptr ? 2 : 1;
   for (int o = 0; o < nout; ++o) {
-    T* dst = (o == 0 ? a.out : a.out2) + (size_t)blockIdx.y * a.bso;
+    T* dst = (o == 0 ? a.out : a.out2) + (size_t)by * a.bso;
     // previous values of the accumulated outputs, fetched while the transform runs
     T pa[PER], pb[PER];
 #pragma unroll
@@ -435,24 +468,40 @@ __global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __r
   }
 }
 
+template <typename T, int N, int CW, int NT, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_col_solve(ColArgs<T> a, const c2<T>* __restrict__ tw,
+                                                  const T* __restrict__ lam, int nblocks) {
+  col_solve_body<T, N, CW, NT, MAXR>(a, tw, lam, nblocks, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int N, int CW, int NT, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_col_solve_multi(const ColArgs<T>* __restrict__ tab,
+                                                        const c2<T>* __restrict__ tw,
+                                                        const T* __restrict__ lam) {
+  const ColArgs<T> a = tab[blockIdx.y];
+  constexpr int nb = (N - 1 + CW - 1) / CW;
+  if ((int)blockIdx.x >= xcd_grid(nb)) return;
+  col_solve_body<T, N, CW, NT, MAXR>(a, tw, lam, nb, blockIdx.x, 0);
+}
+
 // Inverse row DST of rows [r0, r1] into the interior of a full (n+1)-row array; the
 // ring columns (and, when ring rows are requested, rows 0 and n) come from `ring`
 // (zero when null).  With interior_out the output is an (n-1)-row interior array.
 // With in2/out2 set the same rows of a second array are transformed in the same
 // workgroup into the interior array out2 (the level's circulation).
-template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR = 16>
-__global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __restrict__ tw,
-                                                 const T* __restrict__ ring, int ring_rows,
-                                                 int nblocks) {
+template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR>
+__device__ __forceinline__ void row_idst_body(const RowArgs<T>& a, const c2<T>* __restrict__ tw,
+                                              const T* __restrict__ ring, int ring_rows,
+                                              int nblocks, int bx, int by) {
   constexpr int NS = ROWS * (DUAL ? 2 : 1);
   __shared__ c2<T> buf[NS * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
   static_assert(sizeof(buf) + sizeof(stw) <= 160 * 1024, "LDS");
-  const int blk = xcd_block(blockIdx.x, nblocks);
+  const int blk = xcd_block(bx, nblocks);
   if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
-  const T* in = a.in + (size_t)blockIdx.y * a.bsi;
-  T* out = a.out + (size_t)blockIdx.y * a.bso;
+  const T* in = a.in + (size_t)by * a.bsi;
+  T* out = a.out + (size_t)by * a.bso;
   const int j0 = a.r0 + blk * ROWS;
   {
     constexpr int CNT = NS * (N - 1);
@@ -511,6 +560,23 @@ __global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __re
   }
 }
 
+template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_row_idst(RowArgs<T> a, const c2<T>* __restrict__ tw,
+                                                 const T* __restrict__ ring, int ring_rows,
+                                                 int nblocks) {
+  row_idst_body<T, N, ROWS, NT, DUAL, MAXR>(a, tw, ring, ring_rows, nblocks, blockIdx.x,
+                                            blockIdx.y);
+}
+
+template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR = 16>
+__global__ __launch_bounds__(NT) void k_row_idst_multi(const IdstJob<T>* __restrict__ tab,
+                                                       const c2<T>* __restrict__ tw) {
+  const IdstJob<T> j = tab[blockIdx.y];
+  const int nb = (j.a.r1 - j.a.r0 + 1 + ROWS - 1) / ROWS;
+  if (nb <= 0 || (int)blockIdx.x >= xcd_grid(nb)) return;
+  row_idst_body<T, N, ROWS, NT, DUAL, MAXR>(j.a, tw, j.ring, j.ring_rows, nb, blockIdx.x, 0);
+}
+
 // New boundary rings of a fine level from the next coarser level's streamfunction:
 // coincident vertices are copied, midpoints use the cubic (-1, 9, 9, -1)/16 along the
 // edge; the circulation ring is the same interpolation of the coarse C^T C s, scaled
@@ -525,8 +591,8 @@ __device__ __forceinline__ T coarse_val(const T* sc, int p, int edge, int line, 
 }
 
 template <typename T>
-__global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gring) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc, int n, T* sring,
+                                          T* gring, int e) {
   if (e >= 4 * (n + 1)) return;
   const int edge = e / (n + 1), idx = e % (n + 1);
   const int q = n / 2;
@@ -551,12 +617,23 @@ __global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gr
   gring[e] = T(0.25) * gv;
 }
 
+template <typename T>
+__global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gring) {
+  ring_body(sc, psc, n, sring, gring, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename T>
+__global__ void k_ring_multi(const RingJob<T>* __restrict__ tab, int n) {
+  const RingJob<T> j = tab[blockIdx.y];
+  ring_body(j.sc, j.psc, n, j.sring, j.gring, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Unnormalised 1-D DSTs of the four edges of a streamfunction ring, as they appear in
 // B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top s(i, n) on row
 // n-1, left s(0, j) on column 1, right s(n, j) on column n-1.  One workgroup.
 template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
-                                                      const c2<T>* __restrict__ tw, T* lift) {
+__device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
+                                                   const c2<T>* __restrict__ tw, T* lift) {
   __shared__ c2<T> buf[4 * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
   const int tid = threadIdx.x;
@@ -588,6 +665,19 @@ __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ srin
   }
 }
 
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
+                                                      const c2<T>* __restrict__ tw, T* lift) {
+  ring_edge_dst_body<T, N, NT>(sring, tw, lift);
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_edge_dst_multi(const RingJob<T>* __restrict__ tab,
+                                                            const c2<T>* __restrict__ tw) {
+  const RingJob<T> j = tab[blockIdx.y];
+  ring_edge_dst_body<T, N, NT>(j.sring, tw, j.lift);
+}
+
 // ------------------------------------------------ launches of one kernel configuration
 
 template <typename T, int N, int ROWS, int NT, int DST, int MAXR>
@@ -614,6 +704,35 @@ hipError_t launch_idst_cfg(const RowArgs<T>& a, int batch, const c2<T>* t, const
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_row_idst<T, N, ROWS, NT, DUAL, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT),
                      0, st, a, t, ring, ring_rows, nb);
+  return hipGetLastError();
+}
+
+// Many instances of grid size N per launch (tables in device memory, `count` entries);
+// maxrows: the largest row count [r0, r1] over the instances (row kernels).
+template <typename T, int N, int ROWS, int NT, int DST, int MAXR>
+hipError_t launch_rhs_multi_cfg(const RhsArgs<T>* tab, int count, const c2<T>* t, hipStream_t st) {
+  const int nb = (N - 1 + ROWS - 1) / ROWS;
+  hipLaunchKernelGGL((k_rhs_rowdst_multi<T, N, ROWS, NT, DST, MAXR>), dim3(xcd_grid(nb), count),
+                     dim3(NT), 0, st, tab, t);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int CW, int NT, int MAXR>
+hipError_t launch_col_multi_cfg(const ColArgs<T>* tab, int count, const c2<T>* t, const T* l,
+                                hipStream_t st) {
+  const int nb = (N - 1 + CW - 1) / CW;
+  hipLaunchKernelGGL((k_col_solve_multi<T, N, CW, NT, MAXR>), dim3(xcd_grid(nb), count), dim3(NT),
+                     0, st, tab, t, l);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR>
+hipError_t launch_idst_multi_cfg(const IdstJob<T>* tab, int count, int maxrows, const c2<T>* t,
+                                 hipStream_t st) {
+  const int nb = (maxrows + ROWS - 1) / ROWS;
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_row_idst_multi<T, N, ROWS, NT, DUAL, MAXR>), dim3(xcd_grid(nb), count),
+                     dim3(NT), 0, st, tab, t);
   return hipGetLastError();
 }
 

@@ -59,6 +59,24 @@ struct ColArgs {
   const int* gate;   // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
 };
 
+// Per-instance entries of the flow launches that take many instances of one grid size
+// (ib_batch_*): the inverse row transform with its ring, and a new ring from the next coarser
+// level with the edge transforms of its streamfunction part.
+template <typename T>
+struct IdstJob {
+  RowArgs<T> a;
+  const T* ring;
+  int ring_rows;
+};
+template <typename T>
+struct RingJob {
+  const T* sc;  // coarser level's streamfunction, pitch psc
+  int psc;
+  T* sring;
+  T* gring;
+  T* lift;
+};
+
 // Kernel configurations of the row and column sine-transform kernels, selected per grid
 // size by measurement (single precision, n >= FLOW_TUNE_MIN_N; otherwise entry 0).
 // Rows: rows per workgroup, threads, largest radix; columns: columns per workgroup,
@@ -125,5 +143,31 @@ template <typename T>
 hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStream_t st);
 template <typename T>
 hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, hipStream_t st);
+
+// The same launches for `count` instances of grid size n at once, their arguments in device
+// tables (entry b for blockIdx.y = b); var as above, the same for all instances.  maxrows:
+// the largest r1 - r0 + 1 over the entries.  launch_ring_multi makes the new rings and
+// then their edge transforms.
+template <typename T>
+hipError_t launch_rhs_rowdst_multi(const RhsArgs<T>* tab, int count, int n, int var,
+                                   const void* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_col_solve_multi(const ColArgs<T>* tab, int count, int n, int var, const void* tw,
+                                  const void* lam, hipStream_t st);
+template <typename T>
+hipError_t launch_row_idst_multi(const IdstJob<T>* tab, int count, int n, int maxrows, int dual,
+                                 int var, const void* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_rowdst_multi(const RowArgs<T>* tab, int count, int n, int maxrows,
+                               const void* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_ring_multi(const RingJob<T>* tab, int count, int n, const void* tw,
+                             hipStream_t st);
+hipError_t launch_rhs_rowdst_multi_var(const RhsArgs<float>* tab, int count, int n, int var,
+                                       const void* tw, hipStream_t st);
+hipError_t launch_col_solve_multi_var(const ColArgs<float>* tab, int count, int n, int var,
+                                      const void* tw, const void* lam, hipStream_t st);
+hipError_t launch_row_idst_multi_var(const IdstJob<float>* tab, int count, int n, int maxrows,
+                                     int var, const void* tw, hipStream_t st);
 
 }  // namespace ib

@@ -60,6 +60,19 @@ def test_null_handles_are_rejected(lib):
     assert lib.ib_destroy(None) == -1
 
 
+def test_batch_entry_points_reject_bad_arguments(lib):
+    import ctypes
+    out = ctypes.c_void_p()
+    assert lib.ib_batch_create(None, 1, None, ctypes.byref(out)) == -1
+    members = (ctypes.c_void_p * 2)(None, None)
+    assert lib.ib_batch_create(members, 2, None, ctypes.byref(out)) == -1
+    assert lib.ib_batch_create(members, 0, None, ctypes.byref(out)) == -1
+    assert not out.value
+    assert lib.ib_batch_step(None, 1) == -1
+    assert lib.ib_batch_destroy(None) == -1
+    assert lib.ib_batch_last_error(None) == b"null batch"
+
+
 def _config(binding, n, levels):
     return binding.IbConfig(n=n, levels=levels, h=2.0 / n, re=200.0, dt=0.4 / n, cx=0.0, cy=0.0,
                             precision=binding.IB_FP32_FLOW, newton_tol=1e-7, newton_max_iter=20,

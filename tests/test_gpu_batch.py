@@ -1,0 +1,158 @@
+"""Batches (ib_batch_*): many solvers stepped with one launch per kernel for all members.
+
+Every member's results must equal those of the same solver stepped alone, bit for bit: the
+batched launches run the same kernels on the same per-member arguments.  The alone runs
+are themselves held to the FP64 oracle by the parity tests; one batched member is also
+checked against the oracle directly here.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.step import Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _flow_only(n, levels, seed):
+    rng = np.random.default_rng(seed)
+    flow = W.Flow(n=n, levels=levels, h=3.2 / n, dt=0.2 * 3.2 / n, re=150.0, cx=0.1, cy=-0.05,
+                  u_inf=(1.0, 0.3))
+    w0 = [rng.normal(0.0, 1e-2, size=(n - 1, n - 1)) for _ in range(levels)]
+    return W.Problem("flow", flow, [], None, w0, 0)
+
+
+def _members():
+    """Uneven sizes, level counts and body kinds: stationary circles, torsional plates,
+    a deformable flag, a driven (moving) plate, a body-less flow and config-4 style
+    instances with several bodies."""
+    probs = [
+        W.cylinder_problem(n=32, steps=0),
+        W.plate_problem(n=48, levels=2, steps=0),
+        W.flag_problem(n=64, levels=2, steps=0),
+        W.driven_plate_problem(n=64, levels=2, steps=0),
+        _flow_only(32, 3, 7),
+        W.cylinder_problem(n=32, seed=9, steps=0),
+    ]
+    probs += W.batch_problems(count=4, seed=11, steps=0, sizes=(32, 48, 64))
+    return probs
+
+
+def _prec(prec):
+    from paper_2103_06415_amd import binding
+    return binding.IB_FP64 if prec == "fp64" else binding.IB_FP32_FLOW
+
+
+def _results(s, p):
+    out = {}
+    for g in range(p.flow.levels):
+        out[f"w{g}"] = s.vorticity(g)
+    for b in range(len(p.bodies)):
+        out[f"f{b}"] = s.stresses(b)
+        out[f"d{b}"] = s.deflection(b)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_members_equal_their_runs_alone(torch_cuda, gpu_lib, prec):
+    from paper_2103_06415_amd import binding
+    steps = 7
+    probs = _members()
+    alone = []
+    for k, p in enumerate(probs):
+        print(f"alone {prec} member {k} {p.name} n={p.flow.n} levels={p.flow.levels}", flush=True)
+        s = binding.Solver(p, precision=_prec(prec))
+        s.prepare()
+        s.step(steps)
+        s.sync()
+        alone.append(_results(s, p))
+        s.close()
+    print(f"batch {prec} of {len(probs)} members, {steps} steps", flush=True)
+    sols = []
+    for p in probs:
+        s = binding.Solver(p, precision=_prec(prec))
+        s.prepare()
+        sols.append(s)
+    batch = binding.Batch(sols)
+    batch.step(3)
+    batch.step(steps - 3)
+    torch_cuda.cuda.synchronize()
+    st = batch.stats()
+    print(f"  stats {st}", flush=True)
+    assert st["steps"] == steps
+    # each member's first step runs alone, the later ones batched
+    assert st["member_steps_alone"] == len(probs)
+    assert st["member_steps_batched"] == len(probs) * (steps - 1)
+    # a handful of launches per batched step, whatever the member count
+    assert st["launches"] / (steps - 1) < 80
+    for k, (s, p) in enumerate(zip(sols, probs)):
+        got = _results(s, p)
+        for key, ref in alone[k].items():
+            assert np.array_equal(got[key], ref), (k, p.name, key,
+                                                  float(np.max(np.abs(got[key] - ref))))
+        stats = s.stats()
+        assert stats["step"] == steps
+    batch.close()
+    for s in sols:
+        s.close()
+
+
+def test_batched_member_matches_oracle(torch_cuda, gpu_lib):
+    """A torsional-plate member of a mixed batch against the FP64 oracle (FP64 form, a fixed
+    iteration count so that both sides stop identically; the bars of the plate parity test)."""
+    from paper_2103_06415_amd import binding
+    from test_gpu_parity import fp64_tol, rel
+    steps, iters = 3, 3
+    p = W.plate_problem(n=32, levels=2, steps=steps)
+    others = [W.cylinder_problem(n=48, steps=0), _flow_only(64, 2, 3),
+              W.plate_problem(n=48, levels=1, steps=0)]
+    sols = []
+    for q in [p] + others:
+        s = binding.Solver(q, precision=binding.IB_FP64, fixed_iters=iters)
+        s.prepare()
+        sols.append(s)
+    batch = binding.Batch(sols)
+    batch.step(steps)
+    torch_cuda.cuda.synchronize()
+    ora = Oracle(p, fixed_iters=iters)
+    for _ in range(steps):
+        ora.step()
+    errs = [rel(sols[0].vorticity(g), ora.vorticity(g)) for g in range(2)]
+    ef = rel(sols[0].stresses(0), ora.f)
+    th = sols[0].deflection(0)
+    b = ora.bodies[0][1]
+    print(f"  vorticity {errs}; stresses {ef:.3e}; theta {th[0]:.6e} vs {b.theta:.6e}", flush=True)
+    assert max(errs) < fp64_tol(32, steps)
+    assert ef < 1e-9
+    assert abs(th[0] - b.theta) < 1e-10 * max(1.0, abs(b.theta)) + 1e-14
+    batch.close()
+    for s in sols:
+        s.close()
+
+
+def test_batch_rejects_bad_members(torch_cuda, gpu_lib):
+    from paper_2103_06415_amd import binding
+    a = binding.Solver(W.cylinder_problem(n=32, steps=0), precision=binding.IB_FP32_FLOW)
+    b = binding.Solver(W.cylinder_problem(n=32, steps=0), precision=binding.IB_FP64)
+    c = binding.Solver(W.cylinder_problem(n=32, steps=0), precision=binding.IB_FP32_FLOW)
+    a.prepare()
+    b.prepare()
+    with pytest.raises(binding.IbError) as e:
+        binding.Batch([a, a])
+    assert e.value.code == binding.IB_ERR_ARG
+    with pytest.raises(binding.IbError) as e:
+        binding.Batch([a, b])
+    assert e.value.code == binding.IB_ERR_ARG
+    with pytest.raises(binding.IbError) as e:
+        binding.Batch([a, c])  # c is not prepared
+    assert e.value.code == binding.IB_ERR_STATE
+    for s in (a, b, c):
+        s.close()
