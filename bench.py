@@ -320,6 +320,8 @@ def main():
                          "and through the scheduler")
     ap.add_argument("--batch-copies", type=int, default=4,
                     help="also step this many copies of the workload as one ib_batch (0: skip)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batch legs (--batch-copies, --batch); for profiling them")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware counter calibration)")
@@ -341,6 +343,15 @@ def main():
     n, levels = args.n, args.levels
     prob = W.flag_problem(n=n, levels=levels)
     cells = n * n * levels
+    if args.batch_only:
+        out = {"metric": METRIC, "unit": "grid-cell steps/s", "n_gpus": 1, "steps": args.steps,
+               "data": "synthetic", "legs": "batch only"}
+        if args.batch_copies > 0:
+            out["batch_copies"] = batch_run([prob] * args.batch_copies, args.steps, 3)
+        if args.batch:
+            out["batch64"] = batch_run(W.batch_problems(), args.steps, 3)
+        print(json.dumps(out))
+        return
     wall32, prep32, kt, st32 = run(prob, binding.IB_FP32_FLOW, args.steps, args.warmup)
     value = cells * args.steps / wall32
     value64 = None

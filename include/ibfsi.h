@@ -215,9 +215,13 @@ ib_status ib_destroy(ib_solver* s);
  *   replay it for later steps (a non-null stream is needed).  Measured on the flag workload,
  *   replay neither shortens a step nor raises the throughput of concurrent solvers, hence
  *   the default.
- * IB_OPT_REFRESH_EVERY_ITER (default 1): refresh the approximate Schur inverse (one
- *   Newton-Schulz step) at every FSI iteration instead of once per step (0); the refined
- *   stress solve then needs fewer sweeps.  The solution is the same to round-off either way.
+ * IB_OPT_REFRESH_EVERY_ITER (default 2): when the approximate Schur inverse X is refreshed
+ *   by one Newton-Schulz step X <- X (2I - M X) before a stress solve.  1: at every FSI
+ *   iteration (the refined solve then needs fewer sweeps); 0: at the first iteration of
+ *   every step; 2: at every iteration for up to 256 stress unknowns, above that only at the
+ *   first iteration of a step whose previous solve needed more than 6 sweeps (the two
+ *   n^3 products then cost more than the sweeps they save).  The solution is the same to
+ *   round-off in every mode.
  * Errors: IB_ERR_ARG for an unknown option or value. */
 #define IB_OPT_FSI_AHEAD 1
 #define IB_OPT_GRAPHS 2

@@ -38,6 +38,12 @@ namespace {
 // refinement sweeps launched per Schur solve; one that has not converged by then makes
 // the solver rebuild its approximate inverse
 constexpr int REFINE_MAXIT = 16;
+// Refresh policy of the approximate Schur inverse in the automatic mode: one Newton-Schulz
+// step at every FSI iteration up to this many stress unknowns (the two n^3 products cost
+// less than the refinement sweeps they save); above it, only at the first iteration of a
+// step whose previous stress solve needed more than REFRESH_SWEEPS sweeps.
+constexpr int REFRESH_ALL_NF = 256;
+constexpr int REFRESH_SWEEPS = 6;
 
 // ---- offline operator cache
 // The offline stage's product depends only on the grid, dt, Re and the sub-domain (plus
@@ -171,6 +177,7 @@ struct HipShared {
 struct StepGraph {
   hipGraphExec_t exec = nullptr;
   int K = 0;
+  bool refresh0 = false;
 };
 
 struct ib_solver {
@@ -246,7 +253,7 @@ struct ib_solver {
   int nmov = 0;             // rigid bodies in prescribed motion
   double* hpose = nullptr;  // pinned staging of their poses, two sets (alternate steps)
   bool graphs = false;      // replay recorded steps as HIP graphs
-  bool refresh_every_iter = true;   // Newton-Schulz refresh of X at every FSI iteration
+  int refresh_mode = 2;     // Newton-Schulz refresh of X: IB_OPT_REFRESH_EVERY_ITER's value
   static constexpr int GRAPH_SLOTS = 4;
   StepGraph step_graphs[2][GRAPH_SLOTS];  // by ring-buffer alternation, then by K
   int graph_next[2] = {0, 0};             // slot to reuse next (round robin)
@@ -1107,6 +1114,14 @@ ib_status do_prepare(ib_solver* s) {
 // it is solved with (fresh LU, or one Newton-Schulz refresh at the first iteration of a
 // step), the refined stress solve and the structure update.  With a.gate set every kernel
 // skips itself once the step's iterations have converged or stopped on the device.
+// Whether FSI iteration `it` refreshes the approximate inverse before its stress solve.
+bool refresh_at(const ib_solver* s, int it) {
+  if (s->refresh_mode == 1) return true;
+  if (s->refresh_mode == 0) return it == 0;
+  if (s->nf <= REFRESH_ALL_NF) return true;
+  return it == 0 && s->hrinfo != nullptr && s->hrinfo[1] > REFRESH_SWEEPS;
+}
+
 template <typename T>
 ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   FsiArgs a = a0;
@@ -1140,7 +1155,7 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   }
   const double* X = s->Minv;
   double* xcopy = nullptr;
-  if (!fresh && (it == 0 || s->refresh_every_iter)) {
+  if (!fresh && refresh_at(s, it)) {
     // one Newton-Schulz step towards the new matrix, X <- X (2I - M X), into Xn; the
     // refinement solves with it and copies it back to Minv as it loads it
     HIPCHK(launch_gemm64(a.M, s->Minv, s->W, nf, a.pm, 1, s->stream, a.gate));
@@ -1498,6 +1513,7 @@ void destroy_graphs(ib_solver* s) {
 struct StepPlan {
   bool ahead = false, use_graph = false;
   int K = 0, parity = 0;
+  bool refresh0 = false;  // the first FSI iteration refreshes the approximate inverse
 };
 
 StepPlan plan_step(const ib_solver* s) {
@@ -1510,12 +1526,13 @@ StepPlan plan_step(const ib_solver* s) {
   p.use_graph = s->graphs && s->fsi_ahead && sync_free && !s->first && !s->timing &&
                 s->stream != nullptr;
   p.parity = s->lv.size() > 1 ? s->lv[0].gcur : 0;
+  p.refresh0 = refresh_at(s, 0);
   return p;
 }
 
 const StepGraph* find_graph(const ib_solver* s, const StepPlan& p) {
   for (const StepGraph& g : s->step_graphs[p.parity])
-    if (g.exec && g.K == p.K) return &g;
+    if (g.exec && g.K == p.K && g.refresh0 == p.refresh0) return &g;
   return nullptr;
 }
 
@@ -1550,6 +1567,7 @@ ib_status record_step(ib_solver* s, const StepPlan& p) {
   if (graph) (void)hipGraphDestroy(graph);
   if (e == hipSuccess) {
     sg.K = p.K;
+    sg.refresh0 = p.refresh0;
     s->graph_captures++;
   } else {
     (void)hipGetLastError();
@@ -2030,7 +2048,7 @@ ib_status batch_step(ib_batch* b) {
       for (ib_solver* s : iter) {
         const FsiArgs& a = s->fa;
         const int nf = s->nf;
-        const bool refresh = it == 0 || s->refresh_every_iter;
+        const bool refresh = refresh_at(s, it);
         const double* X = s->Minv;
         double* xcopy = nullptr;
         if (refresh) {
@@ -2759,7 +2777,8 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
 
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
   HipShared hip_lock;
-  if (check(s) || (value != 0 && value != 1)) return IB_ERR_ARG;
+  if (check(s) || value < 0 || value > (option == IB_OPT_REFRESH_EVERY_ITER ? 2 : 1))
+    return IB_ERR_ARG;
   if (option == IB_OPT_FSI_AHEAD) {
     s->fsi_ahead = value != 0;
     destroy_graphs(s);
@@ -2771,7 +2790,7 @@ ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
     return IB_OK;
   }
   if (option == IB_OPT_REFRESH_EVERY_ITER) {
-    s->refresh_every_iter = value != 0;
+    s->refresh_mode = (int)value;
     destroy_graphs(s);
     return IB_OK;
   }

@@ -310,3 +310,33 @@ def test_driven_plate_matches_oracle(torch_cuda, gpu_lib, mode, prec):
     assert ef < (1e-9 if prec == "fp64" else 1e-3)
     assert epos < 1e-14
     assert st["newton_iters_max"] == 1  # no structural unknowns: one FSI iteration per step
+
+
+def test_refresh_modes_agree(torch_cuda, gpu_lib):
+    """The three refresh policies of the approximate Schur inverse (every iteration, first
+    iteration only, automatic) solve the same systems to round-off, on an instance whose
+    Schur system (a plate and two circles, 636 unknowns) takes the automatic mode's
+    large-system branch."""
+    from paper_2103_06415_amd import binding
+    p = W.batch_problems(count=64, seed=4)[48]
+    steps = 8
+    out = {}
+    for mode in (1, 0, 2):
+        print(f"refresh mode {mode}: {p.name} n={p.flow.n} levels={p.flow.levels}", flush=True)
+        s = binding.Solver(p, precision=binding.IB_FP64)
+        s.set_option(binding.IB_OPT_REFRESH_EVERY_ITER, mode)
+        s.prepare()
+        s.step(steps)
+        s.sync()
+        st = s.stats()
+        out[mode] = (s.vorticity(0), s.stresses(0), s.deflection(0), st)
+        print(f"  sweeps last {st['refine_iters']}, rebuilds {st['inverse_rebuilds']}", flush=True)
+        s.close()
+    ref = out[1]
+    for mode in (0, 2):
+        w, f, d, st = out[mode]
+        ew, ef = rel(w, ref[0]), rel(f, ref[1])
+        print(f"  mode {mode} vs 1: vorticity {ew:.2e} stresses {ef:.2e}", flush=True)
+        assert ew < 1e-10 and ef < 1e-8
+        assert abs(d[0] - ref[2][0]) <= 1e-10 * max(1.0, abs(ref[2][0]))
+        assert st["inverse_rebuilds"] == 1  # only the first step's LU
