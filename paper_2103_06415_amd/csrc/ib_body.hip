@@ -1297,11 +1297,19 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 // [1] sweeps, [2] barrier arrivals, [3] exits (32-bit counters), then two buffers of nb rows
 // of n + 1 values (the share, then the maximum); alternate sweeps use alternate buffers, so a
 // row is never overwritten while another workgroup may still read it.  The last workgroup to
-// leave zeroes the counters for the next launch.
+// leave zeroes the counters for the next launch.  Large systems (TWO) take more workgroups, so
+// that their rows of M and columns of X still fit in LDS; then summing all shares in every
+// workgroup would cost nb n loads each, so workgroup w sums only its slice of the columns (in
+// workgroup order) into a reduced vector (two more buffers of n + 1 after the shares), and
+// after a second barrier every workgroup reads that vector.
 constexpr int REF_HDR = 4;
-constexpr int REF_NB_MAX = 32;
+constexpr int REF_NB_ONE = 32;   // workgroups up to which every workgroup sums all shares
+constexpr int REF_NB_MAX = 128;
 constexpr size_t REF_LDS_CACHE = 48 * 1024;
-size_t refine_ws_doubles(int n, int) { return (size_t)REF_HDR + (size_t)2 * REF_NB_MAX * (n + 1); }
+constexpr size_t REF_LDS_BIG = 96 * 1024;
+size_t refine_ws_doubles(int n, int) {
+  return (size_t)REF_HDR + (size_t)2 * REF_NB_MAX * (n + 1) + (size_t)2 * (n + 1);
+}
 
 __device__ inline unsigned long long dbits(double v) {
   return (unsigned long long)__double_as_longlong(v);
@@ -1349,7 +1357,7 @@ __device__ inline double ld_agent(const double* p) {
 
 __device__ inline double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
 
-template <bool CACHE>
+template <bool CACHE, bool TWO>
 __device__ __forceinline__ void refine_body(const double* __restrict__ M,
                                             const double* __restrict__ X, int pm,
                                             const double* __restrict__ b, double* f, int n,
@@ -1365,6 +1373,7 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
   double* sred = sb + rw;     // 4 partial maxima
   double* sm = sred + 4;      // rows R_w of M (rw x n) when CACHE
   double* sx = sm + (size_t)rw * n;  // columns R_w of X (n x rw) when CACHE
+  double* sp = sx + (CACHE ? (size_t)rw * n : 0);  // TWO: this slice of every share (nb x cs)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = gx, w = bx, ns = n + 1;
   const int r0 = w * rw, r1 = min(n, r0 + rw), nr = max(0, r1 - r0);
@@ -1457,6 +1466,30 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
     // all maxima and shares, loads in flight together; shares summed in workgroup order
     const double* all = shares + (size_t)(it & 1) * REF_NB_MAX * ns;
     double nrm = 0.0;
+    if constexpr (TWO) {
+      const int cs = (n + nb - 1) / nb, c0 = w * cs, c1 = min(n, c0 + cs), nc = max(0, c1 - c0);
+      double* red = shares + (size_t)2 * REF_NB_MAX * ns + (size_t)(it & 1) * ns;
+      for (int e = tid; e < nc * nb; e += 256)
+        sp[e] = ld_agent(&all[(size_t)(e / nc) * ns + c0 + e % nc]);
+      for (int q = tid; q < nb; q += 256) nrm = nanmax(nrm, ld_agent(&all[(size_t)q * ns + n]));
+      __syncthreads();
+      if (tid < nc) {
+        double acc = 0.0;
+        for (int q = 0; q < nb; ++q) acc += sp[q * nc + tid];
+        st_agent(&red[c0 + tid], acc);
+      }
+      target += (unsigned)nb;
+      if (!grid_barrier(cnt, target, flags)) {
+        ok = false;
+        break;
+      }
+      for (int j = tid; j < n; j += 256) sd[j] = ld_agent(&red[j]);
+      // every thread needs the maximum over all workgroups
+      for (int off = 32; off > 0; off >>= 1) nrm = nanmax(nrm, __shfl_xor(nrm, off));
+      if (lane == 0) sred[wv] = nrm;
+      __syncthreads();
+      nrm = nanmax(nanmax(sred[0], sred[1]), nanmax(sred[2], sred[3]));
+    } else {
     for (int j0 = 0; j0 < n; j0 += 256) {
       const int j = j0 + tid, jc = min(j, n - 1);
       double acc = 0.0;
@@ -1474,6 +1507,7 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
         for (int q = 0; q < 16; ++q) acc += q0 + q < nb ? v[q] : 0.0;
       }
       if (j < n) sd[j] = acc;
+    }
     }
     rel = nbv > 0.0 ? nrm / nbv : 0.0;
     if (!(rel > 1e-16 * n) || !(nrm < 0.5 * prev)) {
@@ -1504,25 +1538,25 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
   }
 }
 
-template <bool CACHE>
+template <bool CACHE, bool TWO>
 __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
                                                 const double* __restrict__ X, int pm,
                                                 const double* __restrict__ b, double* f, int n,
                                                 int rw, int tpr, int maxit, int guess, double* ws,
                                                 double* out, int* flags, const int* gate,
                                                 double* xcopy) {
-  refine_body<CACHE>(M, X, pm, b, f, n, rw, tpr, maxit, guess, ws, out, flags, gate, xcopy,
-                     blockIdx.x, gridDim.x);
+  refine_body<CACHE, TWO>(M, X, pm, b, f, n, rw, tpr, maxit, guess, ws, out, flags, gate, xcopy,
+                          blockIdx.x, gridDim.x);
 }
 
 // Many instances per launch: instance blockIdx.y's nb workgroups are its own barrier group
 // (counters in its own workspace); the workgroups of one instance are consecutive in the
 // dispatch order.
-template <bool CACHE>
+template <bool CACHE, bool TWO>
 __global__ __launch_bounds__(256) void k_refine_multi(const RefineJob* __restrict__ tab) {
   const RefineJob j = tab[blockIdx.y];
   if ((int)blockIdx.x >= j.nb) return;
-  refine_body<CACHE>(j.M, j.X, j.pm, j.b, j.f, j.n, j.rw, j.tpr, j.maxit, j.guess, j.ws, j.out,
+  refine_body<CACHE, TWO>(j.M, j.X, j.pm, j.b, j.f, j.n, j.rw, j.tpr, j.maxit, j.guess, j.ws, j.out,
                      j.flags, j.gate, j.xcopy, blockIdx.x, j.nb);
 }
 
@@ -1648,17 +1682,27 @@ bool refine_shape(int n, RefineShape* out) {
   int nb = std::min(16, (n + 7) / 8);
   int rw = (n + nb - 1) / nb;
   if ((size_t)2 * rw * n * 8 > REF_LDS_CACHE) {
-    nb = std::min(REF_NB_MAX, (n + 7) / 8);
+    nb = std::min(REF_NB_ONE, (n + 7) / 8);
     rw = (n + nb - 1) / nb;
   }
+  bool cache = (size_t)2 * rw * n * 8 <= REF_LDS_CACHE;
+  if (!cache) {
+    // the fewest workgroups whose rows of M and columns of X fit REF_LDS_BIG
+    const int rwmax = (int)(REF_LDS_BIG / ((size_t)16 * n));
+    if (rwmax >= 1 && (n + rwmax - 1) / rwmax <= REF_NB_MAX) {
+      rw = rwmax;
+      cache = true;
+    }
+  }
   nb = (n + rw - 1) / rw;  // no workgroup without rows
+  const bool two = nb > REF_NB_ONE;
   int tpr = 64;            // threads per row of r = b - M f: a power of two, tpr * rw <= 256
   while (tpr > 1 && tpr * rw > 256) tpr >>= 1;
   if (tpr * rw > 256) return false;
-  const bool cache = (size_t)2 * rw * n * 8 <= REF_LDS_CACHE;
-  const size_t lds = ((size_t)2 * n + 2 * rw + 4 + (cache ? (size_t)2 * rw * n : 0)) * 8;
-  if (lds > 64 * 1024) return false;
-  *out = RefineShape{nb, rw, tpr, cache, lds};
+  const size_t lds = ((size_t)2 * n + 2 * rw + 4 + (cache ? (size_t)2 * rw * n : 0) +
+                      (two ? (size_t)n + nb : 0)) * 8;
+  if (lds > 150 * 1024) return false;
+  *out = RefineShape{nb, rw, tpr, cache, lds, two};
   return true;
 }
 
@@ -1667,12 +1711,15 @@ hipError_t launch_refine(const double* M, int pm, const double* X, const double*
                          const int* gate, double* xcopy, hipStream_t st) {
   RefineShape r;
   if (maxit < 1 || !refine_shape(n, &r)) return hipErrorInvalidValue;
-  if (r.cache)
-    hipLaunchKernelGGL(k_refine<true>, dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n, r.rw,
-                       r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
+  if (r.two)
+    hipLaunchKernelGGL((k_refine<true, true>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n,
+                       r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
+  else if (r.cache)
+    hipLaunchKernelGGL((k_refine<true, false>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f,
+                       n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
   else
-    hipLaunchKernelGGL(k_refine<false>, dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n, r.rw,
-                       r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
+    hipLaunchKernelGGL((k_refine<false, false>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f,
+                       n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
@@ -1901,11 +1948,13 @@ hipError_t launch_gemm64_multi(const GemmJob* tab, int count, int max_n, int kc5
 hipError_t launch_refine_multi(const RefineJob* tab, int count, int max_nb, size_t lds, int cache,
                                hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  if (lds > 64 * 1024 || max_nb < 1 || max_nb > REF_NB_MAX) return hipErrorInvalidValue;
-  if (cache)
-    hipLaunchKernelGGL(k_refine_multi<true>, dim3(max_nb, count), dim3(256), lds, st, tab);
+  if (lds > 150 * 1024 || max_nb < 1 || max_nb > REF_NB_MAX) return hipErrorInvalidValue;
+  if (cache == 2)
+    hipLaunchKernelGGL((k_refine_multi<true, true>), dim3(max_nb, count), dim3(256), lds, st, tab);
+  else if (cache == 1)
+    hipLaunchKernelGGL((k_refine_multi<true, false>), dim3(max_nb, count), dim3(256), lds, st, tab);
   else
-    hipLaunchKernelGGL(k_refine_multi<false>, dim3(max_nb, count), dim3(256), lds, st, tab);
+    hipLaunchKernelGGL((k_refine_multi<false, false>), dim3(max_nb, count), dim3(256), lds, st, tab);
   return hipGetLastError();
 }
 hipError_t launch_step_reset_multi(int* const* ctls, int count, hipStream_t st) {

@@ -151,6 +151,7 @@ struct RefineShape {
   int nb, rw, tpr;
   bool cache;
   size_t lds;
+  bool two;  // more than 32 workgroups: the shares are summed in slices (two barriers a sweep)
 };
 bool refine_shape(int n, RefineShape* out);
 // Workgroups of k_update for nf stress unknowns.
@@ -177,6 +178,7 @@ hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipSt
 // kc52: every entry has n <= 208 (the whole k range in one chunk); otherwise none has
 hipError_t launch_gemm64_multi(const GemmJob* tab, int count, int max_n, int kc52,
                                hipStream_t st);
+// cache: 0 uncached rows, 1 LDS-cached rows, 2 cached rows summed in slices (RefineShape::two)
 hipError_t launch_refine_multi(const RefineJob* tab, int count, int max_nb, size_t lds, int cache,
                                hipStream_t st);
 hipError_t launch_step_reset_multi(int* const* ctls, int count, hipStream_t st);

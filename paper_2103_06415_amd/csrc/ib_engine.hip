@@ -2042,9 +2042,9 @@ ib_status batch_step(ib_batch* b) {
       // Newton-Schulz refresh of the inverse into Xn, then the refinement (split by the
       // GEMM's k chunk and the refinement's LDS mode)
       std::vector<GemmJob> g1[2], g2[2];
-      std::vector<RefineJob> rj[2];
-      int gmax_n[2] = {0, 0}, rnb[2] = {0, 0};
-      size_t rlds[2] = {0, 0};
+      std::vector<RefineJob> rj[3];
+      int gmax_n[2] = {0, 0}, rnb[3] = {0, 0, 0};
+      size_t rlds[3] = {0, 0, 0};
       for (ib_solver* s : iter) {
         const FsiArgs& a = s->fa;
         const int nf = s->nf;
@@ -2064,7 +2064,7 @@ ib_status batch_step(ib_batch* b) {
           b->last_error = "Schur system too large for the refinement";
           return IB_ERR_ARG;
         }
-        const int c = sh.cache ? 1 : 0;
+        const int c = sh.two ? 2 : sh.cache ? 1 : 0;
         rj[c].push_back(RefineJob{a.M, X, a.pm, s->rhs, s->f, nf, sh.rw, sh.tpr, REFINE_MAXIT,
                                   it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags,
                                   s->gate, xcopy, sh.nb});
@@ -2079,7 +2079,7 @@ ib_status batch_step(ib_batch* b) {
         const int mn = gmax_n[k];
         pl.add(g2[k], [=](const GemmJob* d, int c) { return launch_gemm64_multi(d, c, mn, k, st); });
       }
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < 3; ++c) {
         const int mb = rnb[c];
         const size_t l = rlds[c];
         pl.add(rj[c], [=](const RefineJob* d, int cnt) {
