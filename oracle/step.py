@@ -23,7 +23,11 @@ eq. (A.17)'s second row, and the reading here is S_t = Q R.
 Rigid bodies in prescribed motion (Sec. 2.1, eq. (5); the driven plate of Sec. 5.1): their
 points sit at the pose of the new time level t_{n+1}, (x, y) + R(angle) xy_ref, and carry
 the prescribed velocity (vx, vy) + omega e_z x (R xy_ref) into b; in sub-domain mode they are
-interpolated through P like the other moving points (not appended to B').
+interpolated through P like the other moving points (not appended to B').  A torsional body
+mounted on such a driver (Sec. 5.1's passive plate; structure.MountedState) takes its hinge
+and reference angle from the driver at t_{n+1}, its points carry the driver's velocity at
+their positions into b on top of the deflection rate, and its g is the pseudo-moment of the
+hinge's acceleration at the current iterate.
 
 FSI iteration (Algorithm 2): start from the old structure state, stop when
 max |delta theta|, |delta chi| <= tol (both tests of Sec. 5 and Algorithm 2), at most
@@ -36,6 +40,9 @@ import numpy as np
 import workloads as W
 
 from . import delta, dst, grid, multidomain as md, structure, subdomain
+
+
+TORS = ("torsional", "mounted")
 
 
 class NotConverged(RuntimeError):
@@ -86,6 +93,11 @@ class Oracle:
                 self.bodies.append(("moving", b))
             elif isinstance(b, W.Torsional):
                 self.bodies.append(("torsional", structure.TorsionalState(b, flow.dt)))
+            elif isinstance(b, W.MountedTorsional):
+                driver = problem.bodies[b.driver]
+                if not isinstance(driver, W.MovingRigid):
+                    raise TypeError("a mounted torsional body needs a MovingRigid driver")
+                self.bodies.append(("mounted", structure.MountedState(b, driver, flow.dt)))
             elif isinstance(b, W.Deformable):
                 self.bodies.append(("deformable", structure.BeamState(b, flow.dt)))
             else:
@@ -165,7 +177,7 @@ class Oracle:
             return b.xy
         if kind == "moving":
             return moving_positions(b, self.t_new())
-        if kind == "torsional":
+        if kind in TORS:
             return b.positions(b.theta_k)
         return b.positions(b.chi_k)
 
@@ -257,7 +269,9 @@ class Oracle:
         ds = self.ds_vector()
         counts = self.npts_per_body()
         for kind, b in self.bodies:
-            if kind == "torsional":
+            if kind == "mounted":
+                b.set_time(self.t_new())
+            if kind in TORS:
                 b.theta_k = b.theta
             elif kind == "deformable":
                 b.chi_k = b.chi.copy()
@@ -284,11 +298,14 @@ class Oracle:
                 elif kind == "moving":
                     ub = moving_velocities(b, self.t_new())
                     rhs[blk] -= np.concatenate([ub[:, 0], ub[:, 1]])
-                elif kind == "torsional":
+                elif kind in TORS:
                     jt = b.jac()
                     srow = b.s_row(b.theta_k)
                     mat[blk, blk] += (2.0 * b.ds / dt) * np.outer(srow, srow) / jt
                     rhs[blk] -= srow * ((2.0 / dt) * b.r_phi() / jt - b.r_theta())
+                    if kind == "mounted":
+                        uv = b.mount_velocity(b.theta_k)
+                        rhs[blk] -= np.concatenate([uv[:, 0], uv[:, 1]])
                     updates.append((kind, b, blk, jt, srow))
                 else:
                     jd, res = b.jacobian(b.chi_k)
@@ -303,7 +320,7 @@ class Oracle:
             f = np.linalg.solve(mat, rhs)
             delta_max = 0.0
             for kind, b, blk, jmat, extra in updates:
-                if kind == "torsional":
+                if kind in TORS:
                     th_new = (b.r_phi() + b.ds * extra @ f[blk]) / jmat
                     delta_max = max(delta_max, abs(th_new - b.theta_k))
                     b.theta_new = th_new
@@ -322,7 +339,7 @@ class Oracle:
                 self.last_delta = delta_max
                 self.eh_used = eh
                 for kind, b, blk, jmat, extra in updates:
-                    if kind == "torsional":
+                    if kind in TORS:
                         b.theta_used = b.theta_k
                         b.finish(b.theta_new)
                         b.theta_k = b.theta
@@ -333,7 +350,7 @@ class Oracle:
                     raise NotConverged(f"FSI iteration did not converge ({delta_max:g})")
                 return f, eh
             for kind, b, blk, jmat, extra in updates:
-                if kind == "torsional":
+                if kind in TORS:
                     b.theta_k = b.theta_new
                 else:
                     b.chi_k = b.chi_new
@@ -374,6 +391,12 @@ class Oracle:
                 j = np.arange(m) * b.ds
                 ub[off:off + m] = -j * np.sin(ang) * b.phi
                 ub[off + m:off + 2 * m] = j * np.cos(ang) * b.phi
+            elif kind == "mounted":
+                ang = b.ang0 + b.theta_used
+                j = np.arange(m) * b.ds
+                uv = b.mount_velocity(b.theta_used)
+                ub[off:off + m] = uv[:, 0] - j * np.sin(ang) * b.phi
+                ub[off + m:off + 2 * m] = uv[:, 1] + j * np.cos(ang) * b.phi
             elif kind == "deformable":
                 ub[off:off + m] = b.zeta[0::3]
                 ub[off + m:off + 2 * m] = b.zeta[1::3]

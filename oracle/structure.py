@@ -77,6 +77,93 @@ class TorsionalState:
         self.theta, self.phi, self.phidot = theta_new, phi_new, phidot_new
 
 
+class MountedState(TorsionalState):
+    """Torsional body whose hinge rides on a rigid body in prescribed motion (Sec. 5.1's
+    passive plate).  Reading (the paper gives the equation for its two-plate case only, with
+    a garbled inertia symbol): with the hinge H(t) fixed in the driver's frame, the
+    driver's angle alpha(t), and the plate's absolute angle phi = alpha + theta_rel + theta,
+    the angular momentum balance about the moving hinge is
+
+        I_H (alpha_dd + theta_dd) + m r_G x a_H = M_fluid - k theta - c theta_dot,
+
+    r_G = cg (cos phi, sin phi), so the torsional equation of Sec. 2.1 holds for the
+    relative deflection theta with g = -I_H alpha_dd - m cg (cos phi a_Hy - sin phi a_Hx).
+    For the two-plate case (angles measured from the driver's -y direction) this is term
+    by term the paper's equation.  g is evaluated at the current iterate and at t_{n+1}
+    (Newmark average acceleration, as for the other torsional terms); the points carry the
+    hinge's velocity plus the driver's rotation on top of the deflection rate."""
+
+    def __init__(self, body, driver, dt):
+        self.mount = body
+        self.driver = driver
+        self.frame_t = None
+        base = _Plain(n=body.n, length=body.length, inertia=body.inertia,
+                      stiffness=body.stiffness, damping=body.damping, theta=body.theta,
+                      phi=body.phi)
+        self.b = base
+        self.dt = dt
+        self.theta = float(body.theta)
+        self.phi = float(body.phi)
+        self.set_time(0.0)
+        self.g = self.pseudo_moment(self.theta)
+        self.phidot = (self.g - body.damping * self.phi - body.stiffness * self.theta) / body.inertia
+        self.theta_k = self.theta
+
+    def set_time(self, t):
+        """Hinge, reference angle, and the driver's rates and accelerations at time t."""
+        x, y, ang, vx, vy, om = self.driver.pose(t)
+        ax, ay, al = self.driver.accelerations(t)
+        hb = self.mount.hinge_body
+        c, sn = math.cos(ang), math.sin(ang)
+        rx, ry = c * hb[0] - sn * hb[1], sn * hb[0] + c * hb[1]
+        self.hinge = (x + rx, y + ry)
+        self.vh = (vx - om * ry, vy + om * rx)
+        self.ah = (ax - al * ry - om * om * rx, ay + al * rx - om * om * ry)
+        self.omega = om
+        self.alpha_dd = al
+        self.ang0 = ang + self.mount.theta_rel
+        self.frame_t = t
+
+    def pseudo_moment(self, theta):
+        mb = self.mount
+        ph = self.ang0 + theta
+        return (-mb.inertia * self.alpha_dd
+                - mb.mass * mb.cg * (math.cos(ph) * self.ah[1] - math.sin(ph) * self.ah[0]))
+
+    def r_phi(self):
+        b, dt = self.b, self.dt
+        return (b.inertia * (4.0 * self.theta / dt ** 2 + 4.0 * self.phi / dt + self.phidot)
+                + b.damping * (2.0 * self.theta / dt + self.phi) + self.pseudo_moment(self.theta_k))
+
+    def positions(self, theta):
+        ang = self.ang0 + theta
+        j = np.arange(self.b.n) * self.b.ds
+        return np.stack([self.hinge[0] + j * math.cos(ang), self.hinge[1] + j * math.sin(ang)], axis=1)
+
+    def s_row(self, theta):
+        ang = self.ang0 + theta
+        j = np.arange(self.b.n) * self.b.ds
+        return np.concatenate([-j * math.sin(ang), j * math.cos(ang)])
+
+    def mount_velocity(self, theta):
+        """Velocity of the points from the driver alone: v_H + omega e_z x (p - H)."""
+        p = self.positions(theta) - np.array(self.hinge)
+        return np.stack([self.vh[0] - self.omega * p[:, 1], self.vh[1] + self.omega * p[:, 0]], axis=1)
+
+
+class _Plain:
+    """The torsional constants a MountedState shares with a fixed-hinge body."""
+
+    def __init__(self, n, length, inertia, stiffness, damping, theta, phi):
+        self.n, self.length = n, length
+        self.inertia, self.stiffness, self.damping = inertia, stiffness, damping
+        self.theta, self.phi = theta, phi
+
+    @property
+    def ds(self):
+        return self.length / (self.n - 1)
+
+
 def _wrap(a):
     return (a + math.pi) % (2.0 * math.pi) - math.pi
 

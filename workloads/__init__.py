@@ -44,13 +44,20 @@ class Rigid:
 class MovingRigid:
     """Rigid body with prescribed motion: points xy_ref in the body frame, and
     motion(t) -> (x, y, angle, vx, vy, omega), the pose of the body frame at time t and
-    its rates (an input of the problem)."""
+    its rates (an input of the problem).  accel(t) -> (ax, ay, alpha_dd), the frame's
+    accelerations, is needed only when a MountedTorsional body rides on it."""
     xy_ref: np.ndarray                  # (n, 2) body-frame point coordinates
     ds: float
     motion: Callable[[float], tuple]
+    accel: Optional[Callable[[float], tuple]] = None
 
     def pose(self, t):
         return tuple(float(v) for v in self.motion(t))
+
+    def accelerations(self, t):
+        if self.accel is None:
+            raise ValueError("this driver has no accelerations")
+        return tuple(float(v) for v in self.accel(t))
 
 
 @dataclasses.dataclass
@@ -64,6 +71,32 @@ class Torsional:
     damping: float
     theta: float = 0.0    # initial deflection from theta0
     phi: float = 0.0      # initial angular velocity
+
+    @property
+    def ds(self) -> float:
+        return self.length / (self.n - 1)
+
+
+@dataclasses.dataclass
+class MountedTorsional:
+    """A torsional body whose hinge rides on a rigid body in prescribed motion (Sec. 5.1: the
+    passive plate hinged to the driven plate).  The hinge sits at `hinge_body` in the
+    driver's body frame; at zero deflection the plate points at the driver's angle plus
+    `theta_rel`.  inertia is about the hinge; mass and cg (hinge to centre of mass, along the
+    plate) give the pseudo-moments of the hinge's acceleration.  driver: index of the
+    MovingRigid in the problem's body list."""
+    driver: int
+    n: int
+    hinge_body: tuple
+    theta_rel: float
+    length: float
+    inertia: float
+    stiffness: float
+    damping: float
+    mass: float
+    cg: float
+    theta: float = 0.0
+    phi: float = 0.0
 
     @property
     def ds(self) -> float:
@@ -134,6 +167,26 @@ def flapping_motion(a0=1.4, beta=math.pi / 4, sigma_t=0.628, sigma_r=0.628, freq
         om = -beta * dgr / gr_max
         return (center[0] + x, center[1], ang, vx, 0.0, om)
 
+    def accel(t):
+        ft = freq * t
+        w = 2 * math.pi * freq
+        tc = math.tanh(8.0 * ft - 2.0)
+        cnd = (tc + th2) / (1.0 + th2)
+        dcnd = 8.0 * freq * (1.0 - tc * tc) / (1.0 + th2)
+        ddcnd = -2.0 * tc * 8.0 * freq * dcnd
+        gt = g_t(ft) if ft >= 0 else -g_t(-ft)
+        tt = math.tanh(sigma_t * math.cos(w * t))
+        dgt = freq * tt
+        ddgt = freq * (1.0 - tt * tt) * sigma_t * (-w * math.sin(w * t))
+        ax = 0.5 * a0 / gt_max * (ddgt * cnd + 2.0 * dgt * dcnd + gt * ddcnd)
+        gr = math.tanh(sigma_r * math.cos(w * t))
+        u = sigma_r * (-w * math.sin(w * t))           # d/dt of the argument
+        du = sigma_r * (-w * w * math.cos(w * t))
+        dgr = (1.0 - gr * gr) * u
+        ddgr = -2.0 * gr * dgr * u + (1.0 - gr * gr) * du
+        return (ax, 0.0, -beta * ddgr / gr_max)
+
+    motion.accel = accel
     return motion
 
 
@@ -155,6 +208,38 @@ def driven_plate_problem(n=256, levels=2, steps=50, case=2, subdomain=True):
                        motion=flapping_motion(sigma_t=sigma, sigma_r=sigma))
     sd = (-1.95, 1.95, -0.85, 0.85) if subdomain else None
     return Problem("driven_plate", flow, [body], sd, None, steps)
+
+
+def two_plate_problem(n=256, levels=2, steps=50, case=2, subdomain=True):
+    """Sec. 5.1's flapping of two torsionally connected plates: a driven plate (chord 1.05,
+    centre of mass 0.55 above the hinge) in the Table kineparams motion, and a passive plate
+    of chord 1.05 hinged at its lower end.  At zero angles both hang along -y (the driver's
+    body frame points along -y; the paper's angles are measured from that direction, which
+    its coefficient cos(alpha_1 + theta) of the hinge acceleration implies).  Spring
+    K = 456, damper C = 3.95, inertia about the hinge 0.2886 (f = c = rho_f = 1); the
+    passive plate's mass pi/4 and its centre-of-mass distance 0.55 are those of the 5:1
+    ellipse of density ratio 5 that the paper's inertia stands for (m ((c/2)^2 + (c/10)^2)/4
+    + m 0.55^2 = 0.2886).  Finest level 6.3 x 6.3 centred at (0, -1.5); sub-domain
+    [-1.89, 1.89] x [-1.66, 0.65]; ds = 2h."""
+    sigma = 3.770 if case == 1 else 0.628
+    beta = math.pi / 4
+    re = 100.0 * math.tanh(sigma) / (2 * math.pi * beta * sigma)
+    width = 6.3
+    h = width / n
+    flow = Flow(n=n, levels=levels, h=h, dt=0.05 * h, re=re, cx=0.0, cy=-1.5, u_inf=(0.0, 0.0))
+    chord = 1.05
+    npts = int(round(chord / (2.0 * h))) + 1
+    # the hinge point belongs to the passive plate (its point 0), so the driver stops one
+    # spacing above it (coincident points would make the Schur matrix singular)
+    ys = np.linspace(0.5, -0.55, npts)[:-1]
+    driver = MovingRigid(xy_ref=np.stack([np.zeros(npts - 1), ys], axis=1), ds=chord / (npts - 1),
+                         motion=flapping_motion(sigma_t=sigma, sigma_r=sigma))
+    driver.accel = driver.motion.accel
+    passive = MountedTorsional(driver=0, n=npts, hinge_body=(0.0, -0.55), theta_rel=-math.pi / 2,
+                               length=chord, inertia=0.2886, stiffness=456.0, damping=3.95,
+                               mass=math.pi / 4, cg=0.55)
+    sd = (-1.89, 1.89, -1.66, 0.65) if subdomain else None
+    return Problem("two_plates", flow, [driver, passive], sd, None, steps)
 
 
 def cylinder(center, diameter, h, spacing=1.0):
