@@ -126,7 +126,9 @@ ib_status ib_add_rigid(ib_solver* s, int32_t m, const double* xy, double ds,
                        const double* u_b, int32_t* body_id);
 
 /* Pose of a rigid body's frame at time t and its rates: pose[0..5] = x, y, angle, vx, vy,
- * omega.  Called on the thread that calls ib_prepare / ib_step. */
+ * omega; optionally its accelerations pose[6..8] = ax, ay, alpha_dd (they arrive set to NaN
+ * and are needed only when a mounted torsional body rides on the body).  Called on the
+ * thread that calls ib_prepare / ib_step. */
 typedef void (*ib_motion_fn)(double t, double* pose, void* ctx);
 
 /* Rigid body in prescribed motion (Sec. 2.1, eq. (5): a rigid body moves with a prescribed
@@ -147,6 +149,26 @@ ib_status ib_add_moving_rigid(ib_solver* s, int32_t m, const double* xy_ref, dou
 ib_status ib_add_torsional(ib_solver* s, int32_t m, double hinge_x, double hinge_y,
                            double length, double theta0, double inertia, double stiffness,
                            double damping, double theta, double phi, int32_t* body_id);
+
+/* Torsional plate whose hinge rides on a rigid body in prescribed motion (Sec. 5.1: the
+ * passive plate hinged to the driven plate).  driver: the body id of an ib_add_moving_rigid
+ * body added earlier, whose callback must give accelerations.  The hinge sits at
+ * (hinge_bx, hinge_by) in the driver's frame; the m points are at hinge + j ds (cos, sin)
+ * (driver angle + theta_rel + theta), ds = length / (m - 1).  inertia, stiffness and
+ * damping are about the hinge; mass and cg (hinge to centre of mass, along the plate) give
+ * the pseudo-moment of the hinge's motion, g = -I_H alpha_dd - m r_G x a_H (r_G = cg along
+ * the plate, a_H the hinge acceleration, alpha_dd the driver's angular acceleration), which
+ * for Sec. 5.1's two plates is its equation of motion's right-hand side beyond the fluid
+ * moment.  theta: deflection relative to the driver, with rate phi, at t = 0.  The points
+ * carry the driver's velocity at their positions plus the deflection rate.
+ * ib_read_deflection returns theta, phi, phi_dot as for ib_add_torsional.  Errors:
+ * IB_ERR_ARG (m < 2, length or inertia <= 0, mass < 0, driver not a moving rigid body);
+ * IB_ERR_NONFINITE at ib_prepare / ib_step when the driver gives no accelerations. */
+ib_status ib_add_mounted_torsional(ib_solver* s, int32_t m, int32_t driver, double hinge_bx,
+                                   double hinge_by, double theta_rel, double length,
+                                   double inertia, double stiffness, double damping,
+                                   double mass, double cg, double theta, double phi,
+                                   int32_t* body_id);
 
 /* Deformable beam clamped at its first node: stress-free straight reference xy_ref[2m],
  * mass per unit length, bending (ei) and stretching (ea) stiffness, initial node

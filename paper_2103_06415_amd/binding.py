@@ -98,6 +98,8 @@ _SIGS = {
     "ib_add_torsional": (c_int32, [c_void_p, c_int32] + [c_double] * 9 + [POINTER(c_int32)]),
     "ib_add_moving_rigid": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, MOTION_FN,
                                       c_void_p, POINTER(c_int32)]),
+    "ib_add_mounted_torsional": (c_int32, [c_void_p, c_int32, c_int32] + [c_double] * 11 +
+                                 [POINTER(c_int32)]),
     "ib_add_deformable": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_double, c_double,
                                     c_double, POINTER(c_double), POINTER(c_double),
                                     POINTER(c_int32)]),
@@ -256,6 +258,10 @@ class Solver:
                     q = body.pose(t)
                     for k in range(6):
                         pose[k] = q[k]
+                    if body.accel is not None:
+                        acc = body.accelerations(t)
+                        for k in range(3):
+                            pose[6 + k] = acc[k]
 
                 cb = MOTION_FN(_cb)
                 self._motion_cbs.append(cb)
@@ -269,6 +275,12 @@ class Solver:
                                              None if ub is None else _dptr(ub), byref(bid)),
                        "ib_add_rigid")
                 self.npts.append(xy.shape[0])
+            elif isinstance(b, W.MountedTorsional):
+                _check(self.lib.ib_add_mounted_torsional(
+                    self.handle, b.n, b.driver, b.hinge_body[0], b.hinge_body[1], b.theta_rel,
+                    b.length, b.inertia, b.stiffness, b.damping, b.mass, b.cg, b.theta, b.phi,
+                    byref(bid)), "ib_add_mounted_torsional")
+                self.npts.append(b.n)
             elif isinstance(b, W.Torsional):
                 _check(self.lib.ib_add_torsional(self.handle, b.n, b.hinge[0], b.hinge[1], b.length,
                                                  b.theta0, b.inertia, b.stiffness, b.damping,
@@ -305,7 +317,7 @@ class Solver:
     def deflection(self, body):
         import workloads as W
         b = self.problem.bodies[body]
-        size = 3 if isinstance(b, W.Torsional) else (3 if isinstance(b, W.Deformable) else 2) * self.npts[body]
+        size = 3 if isinstance(b, (W.Torsional, W.MountedTorsional)) else (3 if isinstance(b, W.Deformable) else 2) * self.npts[body]
         out = np.zeros(size)
         _check(self.lib.ib_read_deflection(self.handle, body, _dptr(out), out.size), "ib_read_deflection")
         return out

@@ -100,6 +100,35 @@ __device__ __forceinline__ double face_flux(const T* s, int ps, int comp, int i,
   return -((double)s[(size_t)j * ps + i + 1] - (double)s[(size_t)j * ps + i]) + uy;
 }
 
+// Hinge and reference angle of a torsional body at t_{n+1}: its own, or those of its mount
+// (Sec. 5.1's passive plate rides on the driven plate).
+__device__ __forceinline__ void tors_frame(const FsiArgs& a, const BodyDev& b, double* hx,
+                                           double* hy, double* ang0) {
+  if (b.moff < 0) {
+    *hx = b.hx;
+    *hy = b.hy;
+    *ang0 = b.theta0;
+    return;
+  }
+  const double* q = a.poses + b.moff;
+  *hx = q[MF_HX];
+  *hy = q[MF_HY];
+  *ang0 = q[MF_ANG];
+}
+
+// g of the torsional equation (Sec. 2.1 eq. (4); Appendix A r_phi) at deflection th: the
+// body's constant, or for a mounted body the pseudo-moment of its moving hinge,
+// -I_H alpha_dd - m r_G x a_H with r_G = cg (cos, sin)(angle), evaluated at t_{n+1} and the
+// current iterate (for Sec. 5.1's two plates this is the right-hand side of its equation
+// of motion beyond the fluid moment).
+__device__ __forceinline__ double tors_g(const FsiArgs& a, const BodyDev& b, const double* ts,
+                                         double th) {
+  if (b.moff < 0) return ts[TS_G];
+  const double* q = a.poses + b.moff;
+  const double ph = q[MF_ANG] + th;
+  return -b.inertia * q[MF_AL] - b.mass * b.cg * (cos(ph) * q[MF_AY] - sin(ph) * q[MF_AX]);
+}
+
 __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, double* px,
                                double* py) {
   if (b.kind == BODY_RIGID) {
@@ -114,10 +143,12 @@ __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, do
   } else if (b.kind == BODY_TORSIONAL) {
     const double* ts = a.tors + b.tors * TS_COUNT;
     const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
-    const double ang = b.theta0 + th;
+    double hx, hy, ang0;
+    tors_frame(a, b, &hx, &hy, &ang0);
+    const double ang = ang0 + th;
     const double r = local * b.ds;
-    *px = b.hx + r * cos(ang);
-    *py = b.hy + r * sin(ang);
+    *px = hx + r * cos(ang);
+    *py = hy + r * sin(ang);
   } else {
     const double* c = a.iter == 0 ? a.chi : a.chi_new;
     *px = c[b.dof0 + 3 * local];
@@ -128,7 +159,8 @@ __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, do
 // The structural part subtracted from row (comp, local) of the Schur right-hand side:
 //   rigid       the prescribed velocity u_b (if any)
 //   moving      (vx, vy) + omega e_z x (R(angle) xy_ref) at t_{n+1}
-//   torsional   S ((2/dt) r_phi / J - r_theta)
+//   torsional   S ((2/dt) r_phi / J - r_theta), plus on a mount the driver's velocity at the
+//               point, v_H + omega e_z x (p - H)
 //   deformable  0 here; k_beam subtracts T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
 __device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, int comp) {
   const int m = b.npts;
@@ -144,16 +176,24 @@ __device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, i
     const double dt = a.dt;
     const double* ts = a.tors + b.tors * TS_COUNT;
     const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
-    const double ang = b.theta0 + th;
+    double hx, hy, ang0;
+    tors_frame(a, b, &hx, &hy, &ang0);
+    const double ang = ang0 + th;
     const double sn = sin(ang), cs = cos(ang);
     const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
     const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
-                        b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
+                        b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + tors_g(a, b, ts, th);
     const double rth = ts[TS_PHI] + 2.0 * ts[TS_THETA] / dt;
     const double rc = (2.0 / dt) * rphi / jt - rth;
-    const double su = (comp == 0 ? -sn : cs) * local * b.ds;
+    const double r = local * b.ds;
+    const double su = (comp == 0 ? -sn : cs) * r;
     (void)m;
-    return su * rc;
+    double v = su * rc;
+    if (b.moff >= 0) {
+      const double* q = a.poses + b.moff;
+      v += comp == 0 ? q[MF_VX] - q[MF_OM] * r * sn : q[MF_VY] + q[MF_OM] * r * cs;
+    }
+    return v;
   }
   return 0.0;
 }
@@ -446,7 +486,7 @@ __device__ __forceinline__ void schur_sd_body(const FsiArgs& a, int all4, int bx
       if (b.kind == BODY_TORSIONAL) {
         const double* ts = a.tors + b.tors * TS_COUNT;
         const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
-        const double ang = b.theta0 + th;
+        const double ang = (b.moff < 0 ? b.theta0 : a.poses[b.moff + MF_ANG]) + th;
         const double sn = sin(ang), cs = cos(ang);
         const double dt = a.dt;
         const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
@@ -909,11 +949,11 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
         double* ts = a.tors + b.tors * TS_COUNT;
         const double dt = a.dt;
         const double th = a.iter == 0 ? ts[TS_THETA] : ts[TS_NEW];
-        const double ang = b.theta0 + th;
+        const double ang = (b.moff < 0 ? b.theta0 : a.poses[b.moff + MF_ANG]) + th;
         const double sn = sin(ang), cs = cos(ang);
         const double jt = 4.0 * b.inertia / (dt * dt) + 2.0 * b.damping / dt + b.stiffness;
         const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
-                            b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + ts[TS_G];
+                            b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + tors_g(a, b, ts, th);
         double sf = 0.0;
         for (int u = lane; u < 2 * m; u += 64) sf += (u < m ? -sn : cs) * (u % m) * b.ds * a.f[r0 + u];
         for (int off = 32; off > 0; off >>= 1) sf += __shfl_xor(sf, off);

@@ -17,10 +17,19 @@ struct BodyDev {
   int dof0;   // deformable: offset of node 0's DOFs in the DOF arrays (3 per node)
   int has_ub; // rigid: prescribed velocity present
   int64_t yoff; // deformable: offset of its J_d^{-1} T^T workspace
+  int moff;     // torsional on a driver: offset of its frame in FsiArgs::poses, else -1
   double ds;
-  double hx, hy, theta0, inertia, stiffness, damping;  // torsional
-  double mass, ei, ea;                                 // deformable
+  double hx, hy, theta0, inertia, stiffness, damping;  // torsional (inertia about the hinge)
+  double mass, ei, ea;                                 // deformable; mass also of a mounted body
+  double cg;                                           // mounted: hinge to centre of mass
 };
+
+// Frame of a torsional body mounted on a rigid body in prescribed motion, at t_{n+1}
+// (MOUNT_W doubles in FsiArgs::poses after the 6 per moving body): hinge (x, y), reference
+// angle (driver angle + relative angle), hinge velocity (x, y), driver angular velocity,
+// hinge acceleration (x, y), driver angular acceleration, unused.
+constexpr int MOUNT_W = 10;
+enum { MF_HX = 0, MF_HY, MF_ANG, MF_VX, MF_VY, MF_OM, MF_AX, MF_AY, MF_AL };
 
 // Torsional state slots.
 enum { TS_THETA = 0, TS_PHI, TS_PHIDOT, TS_NEW, TS_G, TS_COUNT };
@@ -63,7 +72,8 @@ struct FsiArgs {
   // rigid geometry and prescribed velocities (2 per point, per body at pt0)
   const double* rigid_xy;   // BODY_MOVING: body-frame coordinates
   const double* rigid_ub;
-  const double* poses;      // BODY_MOVING: x, y, angle, vx, vy, omega at t_{n+1}, 6 per body
+  const double* poses;      // BODY_MOVING: x, y, angle, vx, vy, omega at t_{n+1}, 6 per body;
+                            // then the frames of mounted torsional bodies (MOUNT_W each)
   // per-row operator: window base (i0, j0) and 4 x 4 weights; P (4 entries)
   int* st_base;
   double* st_w;

@@ -125,8 +125,33 @@ struct HostBody {
   double mass = 0, ei = 0, ea = 0;
   ib_motion_fn motion = nullptr;                    // moving rigid: pose callback
   void* motion_ctx = nullptr;
-  double pose[6] = {0, 0, 0, 0, 0, 0};              // its pose at the last step's time
+  double pose[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};     // its pose, rates, accelerations (last step)
+  int driver = -1;                                  // torsional on a driver: its body index
+  double hbx = 0, hby = 0, theta_rel = 0, cg = 0;   //   hinge in the driver's frame, angles
 };
+
+// Frame of a mounted torsional body (MOUNT_W doubles, layout in ib_body.hpp) from its
+// driver's pose, rates and accelerations q[9] at the same time.
+void mount_frame(const HostBody& mb, const double* q, double* out) {
+  const double c = std::cos(q[2]), sn = std::sin(q[2]);
+  const double rx = c * mb.hbx - sn * mb.hby, ry = sn * mb.hbx + c * mb.hby;
+  out[MF_HX] = q[0] + rx;
+  out[MF_HY] = q[1] + ry;
+  out[MF_ANG] = q[2] + mb.theta_rel;
+  out[MF_VX] = q[3] - q[5] * ry;
+  out[MF_VY] = q[4] + q[5] * rx;
+  out[MF_OM] = q[5];
+  out[MF_AX] = q[6] - q[8] * ry - q[5] * q[5] * rx;
+  out[MF_AY] = q[7] + q[8] * rx - q[5] * q[5] * ry;
+  out[MF_AL] = q[8];
+  out[MOUNT_W - 1] = 0.0;
+}
+
+// Its pseudo-moment at deflection th (the device's tors_g, for the initial state).
+double mount_g(const HostBody& mb, const double* fr, double th) {
+  const double ph = fr[MF_ANG] + th;
+  return -mb.inertia * fr[MF_AL] - mb.mass * mb.cg * (std::cos(ph) * fr[MF_AY] - std::sin(ph) * fr[MF_AX]);
+}
 
 struct LevelState {
   double h = 0, alpha = 0;
@@ -251,6 +276,7 @@ struct ib_solver {
   int* gate = nullptr;      // device gates of the FSI iterations launched ahead (in ctl)
   bool fsi_ahead = true;    // launch a step's FSI iterations ahead of their tests
   int nmov = 0;             // rigid bodies in prescribed motion
+  int nmount = 0;           // torsional bodies mounted on them
   double* hpose = nullptr;  // pinned staging of their poses, two sets (alternate steps)
   bool graphs = false;      // replay recorded steps as HIP graphs
   int refresh_mode = 2;     // Newton-Schulz refresh of X: IB_OPT_REFRESH_EVERY_ITER's value
@@ -643,29 +669,51 @@ ib_status acquire_op(ib_solver* s, const std::vector<double>& key, F build) {
 }
 
 // Poses of the rigid bodies in prescribed motion at time t (x, y, angle, vx, vy, omega from
-// their callbacks) into the device array the FSI kernels read; the staging alternates
-// between two pinned sets, so a copy still pending from the previous step is not
-// overwritten.
+// their callbacks, and the accelerations ax, ay, alpha_dd where given), and the frames of
+// the torsional bodies mounted on them, into the device array the FSI kernels read; the
+// staging alternates between two pinned sets, so a copy still pending from the previous
+// step is not overwritten.
+size_t pose_doubles(const ib_solver* s) { return (size_t)6 * s->nmov + (size_t)MOUNT_W * s->nmount; }
+
+ib_status driver_pose(ib_solver* s, HostBody& hb, double t, double* q) {
+  for (int e = 0; e < 9; ++e) q[e] = e < 6 ? 0.0 : std::nan("");
+  hb.motion(t, q, hb.motion_ctx);
+  for (int e = 0; e < 6; ++e)
+    if (!std::isfinite(q[e])) {
+      s->last_error = "non-finite pose from a motion callback";
+      return IB_ERR_NONFINITE;
+    }
+  return IB_OK;
+}
+
 ib_status update_poses(ib_solver* s, double t) {
   if (!s->nmov) return IB_OK;
-  double* hp = s->hpose + (size_t)6 * s->nmov * (s->step & 1);
+  const size_t w = pose_doubles(s);
+  double* hp = s->hpose + w * (s->step & 1);
   int k = 0;
   for (auto& hb : s->bodies) {
     if (hb.kind != BODY_MOVING) continue;
-    double q[6] = {0, 0, 0, 0, 0, 0};
-    hb.motion(t, q, hb.motion_ctx);
-    for (int e = 0; e < 6; ++e) {
-      if (!std::isfinite(q[e])) {
-        s->last_error = "non-finite pose from a motion callback";
-        return IB_ERR_NONFINITE;
-      }
-      hp[6 * k + e] = q[e];
-      hb.pose[e] = q[e];
-    }
+    double q[9];
+    ib_status st = driver_pose(s, hb, t, q);
+    if (st) return st;
+    for (int e = 0; e < 6; ++e) hp[6 * k + e] = q[e];
+    for (int e = 0; e < 9; ++e) hb.pose[e] = q[e];
     ++k;
   }
-  HIPCHK(hipMemcpyAsync(const_cast<double*>(s->fa.poses), hp, (size_t)6 * s->nmov * 8,
-                        hipMemcpyHostToDevice, s->stream));
+  int j = 0;
+  for (auto& hb : s->bodies) {
+    if (hb.kind != BODY_TORSIONAL || hb.driver < 0) continue;
+    const HostBody& d = s->bodies[hb.driver];
+    for (int e = 6; e < 9; ++e)
+      if (!std::isfinite(d.pose[e])) {
+        s->last_error = "the driver of a mounted torsional body gives no accelerations";
+        return IB_ERR_NONFINITE;
+      }
+    mount_frame(hb, d.pose, hp + 6 * s->nmov + (size_t)MOUNT_W * j);
+    ++j;
+  }
+  HIPCHK(hipMemcpyAsync(const_cast<double*>(s->fa.poses), hp, w * 8, hipMemcpyHostToDevice,
+                        s->stream));
   return IB_OK;
 }
 
@@ -682,8 +730,10 @@ ib_status prepare_bodies(ib_solver* s) {
   int64_t yoff = 0;
   bool any_moving = false;
   s->ds_rows.clear();
+  int nmount = 0;
   for (auto& hb : s->bodies) {
     BodyDev b{};
+    b.moff = -1;
     b.kind = hb.kind;
     b.npts = hb.m;
     b.pt0 = pt;
@@ -714,9 +764,24 @@ ib_status prepare_bodies(ib_solver* s) {
       b.inertia = hb.inertia;
       b.stiffness = hb.stiffness;
       b.damping = hb.damping;
-      const double g = 0.0;
-      const double phidot = (g - hb.damping * hb.phi - hb.stiffness * hb.theta) / hb.inertia;
-      const double st[TS_COUNT] = {hb.theta, hb.phi, phidot, hb.theta, g};
+      double g0 = 0.0;  // g at t = 0 (for the initial angular acceleration)
+      if (hb.driver >= 0) {
+        // mounted: frame offset fixed below, once the moving bodies are counted
+        b.moff = nmount++;
+        b.mass = hb.mass;
+        b.cg = hb.cg;
+        double q[9], fr[MOUNT_W];
+        ib_status pst = driver_pose(s, s->bodies[hb.driver], 0.0, q);
+        if (pst) return pst;
+        if (!std::isfinite(q[6]) || !std::isfinite(q[7]) || !std::isfinite(q[8])) {
+          s->last_error = "the driver of a mounted torsional body gives no accelerations";
+          return IB_ERR_NONFINITE;
+        }
+        mount_frame(hb, q, fr);
+        g0 = mount_g(hb, fr, hb.theta);
+      }
+      const double phidot = (g0 - hb.damping * hb.phi - hb.stiffness * hb.theta) / hb.inertia;
+      const double st[TS_COUNT] = {hb.theta, hb.phi, phidot, hb.theta, 0.0};
       tors.insert(tors.end(), st, st + TS_COUNT);
     } else {
       any_moving = true;
@@ -754,6 +819,8 @@ ib_status prepare_bodies(ib_solver* s) {
     bd.push_back(b);
     pt += hb.m;
   }
+  for (auto& b : bd)
+    if (b.moff >= 0) b.moff = 6 * nmov + MOUNT_W * b.moff;  // frames follow the poses
   s->npts = pt;
   s->nf = 2 * pt;
   s->ntors = ntors;
@@ -848,11 +915,12 @@ ib_status prepare_bodies(ib_solver* s) {
   a.rigid_xy = up(rigid_xy);
   a.rigid_ub = up(rigid_ub);
   s->nmov = nmov;
+  s->nmount = nmount;
   a.poses = nullptr;
   if (nmov) {
-    a.poses = static_cast<double*>(dalloc(s, (size_t)6 * nmov * 8));
+    a.poses = static_cast<double*>(dalloc(s, pose_doubles(s) * 8));
     if (!a.poses) return IB_ERR_OOM;
-    if (!s->hpose) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->hpose), (size_t)12 * nmov * 8,
+    if (!s->hpose) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->hpose), 2 * pose_doubles(s) * 8,
                                         hipHostMallocDefault));
     ib_status pst = update_poses(s, (s->step + 1) * s->cfg.dt);
     if (pst) return pst;
@@ -2475,6 +2543,37 @@ ib_status ib_add_torsional(ib_solver* s, int32_t m, double hinge_x, double hinge
   b.damping = damping;
   b.theta = theta;
   b.phi = phi;
+  s->bodies.push_back(b);
+  if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
+  return IB_OK;
+}
+
+ib_status ib_add_mounted_torsional(ib_solver* s, int32_t m, int32_t driver, double hinge_bx,
+                                  double hinge_by, double theta_rel, double length,
+                                  double inertia, double stiffness, double damping, double mass,
+                                  double cg, double theta, double phi, int32_t* body_id) {
+  if (check(s) || m < 2 || !(length > 0) || !(inertia > 0) || !(mass >= 0) || driver < 0 ||
+      driver >= (int32_t)s->bodies.size() || s->bodies[driver].kind != BODY_MOVING ||
+      !std::isfinite(hinge_bx) || !std::isfinite(hinge_by) || !std::isfinite(theta_rel) ||
+      !std::isfinite(cg))
+    return IB_ERR_ARG;
+  if (s->prepared) return IB_ERR_STATE;
+  HostBody b;
+  b.kind = BODY_TORSIONAL;
+  b.m = m;
+  b.ds = length / (m - 1);
+  b.length = length;
+  b.inertia = inertia;
+  b.stiffness = stiffness;
+  b.damping = damping;
+  b.mass = mass;
+  b.cg = cg;
+  b.theta = theta;
+  b.phi = phi;
+  b.driver = driver;
+  b.hbx = hinge_bx;
+  b.hby = hinge_by;
+  b.theta_rel = theta_rel;
   s->bodies.push_back(b);
   if (body_id) *body_id = (int32_t)s->bodies.size() - 1;
   return IB_OK;

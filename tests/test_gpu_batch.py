@@ -32,13 +32,14 @@ def _flow_only(n, levels, seed):
 
 def _members():
     """Uneven sizes, level counts and body kinds: stationary circles, torsional plates,
-    a deformable flag, a driven (moving) plate, a body-less flow and config-4 style
-    instances with several bodies."""
+    a deformable flag, a driven (moving) plate, the driven plate with a passive plate on its
+    hinge, a body-less flow and config-4 style instances with several bodies."""
     probs = [
         W.cylinder_problem(n=32, steps=0),
         W.plate_problem(n=48, levels=2, steps=0),
         W.flag_problem(n=64, levels=2, steps=0),
         W.driven_plate_problem(n=64, levels=2, steps=0),
+        W.two_plate_problem(n=64, levels=2, steps=0, case=1),
         _flow_only(32, 3, 7),
         W.cylinder_problem(n=32, seed=9, steps=0),
     ]

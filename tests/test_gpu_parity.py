@@ -340,3 +340,40 @@ def test_refresh_modes_agree(torch_cuda, gpu_lib):
         assert ew < 1e-10 and ef < 1e-8
         assert abs(d[0] - ref[2][0]) <= 1e-10 * max(1.0, abs(ref[2][0]))
         assert st["inverse_rebuilds"] == 1  # only the first step's LU
+
+
+@pytest.mark.parametrize("mode", ["subdomain", "exact"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_plates_match_oracle(torch_cuda, gpu_lib, mode, prec):
+    """Sec. 5.1's two torsionally connected plates: the driven plate in the flapping motion
+    and the passive plate on its hinge, with the pseudo-moment of the hinge's motion, in
+    sub-domain and exact mode; a fixed iteration count so both sides stop identically."""
+    import torch
+    from paper_2103_06415_amd import binding
+    print(f"two plates n=64 {mode} {prec}", flush=True)
+    steps, iters = 5, 3
+    p = W.two_plate_problem(n=64, levels=2, steps=steps, case=1, subdomain=(mode == "subdomain"))
+    s = binding.Solver(p, precision=_prec(prec), fixed_iters=iters, stream=torch.cuda.Stream())
+    s.prepare()
+    s.step(steps)
+    s.sync()
+    ora = Oracle(p, fixed_iters=iters)
+    for _ in range(steps):
+        ora.step()
+    errs = [rel(s.vorticity(g), ora.vorticity(g)) for g in range(2)]
+    m0 = p.bodies[0].xy_ref.shape[0]
+    f = np.concatenate([s.stresses(0), s.stresses(1)])
+    fo = np.concatenate([ora.f[:2 * m0], ora.f[2 * m0:]])
+    ef = rel(f, fo)
+    th = s.deflection(1)
+    b = ora.bodies[1][1]
+    print(f"  vorticity {errs}; stresses {ef:.3e}; theta {th[0]:.9e} vs {b.theta:.9e}; "
+          f"phi {th[1]:.6e} vs {b.phi:.6e}", flush=True)
+    s.close()
+    tol = fp64_tol(64, steps) if prec == "fp64" else 1e-5
+    assert max(errs) < tol
+    assert ef < (1e-9 if prec == "fp64" else 1e-3)
+    dtol = 1e-10 if prec == "fp64" else 1e-4
+    assert abs(th[0] - b.theta) < dtol * max(1.0, abs(b.theta)) + 1e-14
+    assert abs(th[1] - b.phi) < dtol * max(1.0, abs(b.phi)) + 1e-12
+    assert abs(b.theta) > 1e-6  # the passive plate does deflect
