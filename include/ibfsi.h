@@ -73,8 +73,9 @@ typedef int32_t ib_status;
 typedef struct ib_solver ib_solver;
 
 typedef struct {
-  int32_t n;          /* cells per side of every level; one of 16, 32, 48, 64, 96, 128,
-                         192, 256, 384, 512, 768, 1024 */
+  int32_t n;          /* cells per side of every level; one of 16, 20, 32, 40, 48, 64, 80,
+                         96, 128, 160, 192, 256, 320, 384, 512, 640, 768, 1024, 1280
+                         (2^a 3^b 5^c: the sine transforms' FFT lengths) */
   int32_t levels;     /* nested levels (>= 1); level 0 is the finest */
   double h;           /* finest grid spacing */
   double cx, cy;      /* common centre of all levels */

@@ -12,7 +12,7 @@
 //
 // The FFT is a Stockham autosort transform working in place on LDS with stages of the
 // largest radix MAXR (16, 8 or 4) first, then one smaller power-of-two stage for the rest
-// of the power of two, then radix-3 stages: every stage loads its inputs into registers,
+// of the power of two, then radix-3 and radix-5 stages: every stage loads its inputs into registers,
 // synchronises the workgroup, and writes the butterflies' outputs back.  Large radices
 // mean fewer barriers and less LDS traffic; small ones more butterflies per stage (more
 // waves in flight to hide latency) and fewer registers per thread.  The choice is made per
@@ -25,22 +25,23 @@
 namespace ib {
 
 constexpr int ilog2c(int m) { return m <= 1 ? 0 : 1 + ilog2c(m / 2); }
-constexpr int pow3c(int l) { return (l % 3) ? 0 : 1 + pow3c(l / 3); }
-constexpr int ipow3(int p) { return p == 0 ? 1 : 3 * ipow3(p - 1); }
+constexpr int powc(int l, int f) { return (l % f) ? 0 : 1 + powc(l / f, f); }
+constexpr int ipowc(int f, int p) { return p == 0 ? 1 : f * ipowc(f, p - 1); }
 
 template <int L, int MAXR = 16>
 struct FftPlan {
   static_assert(MAXR == 16 || MAXR == 8 || MAXR == 4, "largest radix 16, 8 or 4");
   static constexpr int lr = ilog2c(MAXR);
-  static constexpr int p3 = pow3c(L);
-  static constexpr int p2 = ilog2c(L / ipow3(p3));
+  static constexpr int p5 = powc(L, 5);
+  static constexpr int p3 = powc(L / ipowc(5, p5), 3);
+  static constexpr int p2 = ilog2c(L / (ipowc(3, p3) * ipowc(5, p5)));
   static constexpr int nbig = p2 / lr;
   static constexpr int rem = p2 % lr;  // one more stage of radix 2^rem
   static constexpr int nmid = rem ? 1 : 0;
-  static constexpr int nst = nbig + nmid + p3;
-  static_assert(ipow3(p3) * (1 << p2) == L, "FFT length must be 2^a 3^b");
+  static constexpr int nst = nbig + nmid + p3 + p5;
+  static_assert(ipowc(5, p5) * ipowc(3, p3) * (1 << p2) == L, "FFT length must be 2^a 3^b 5^c");
   static constexpr int radix(int s) {
-    return s < nbig ? MAXR : (s < nbig + nmid ? (1 << rem) : 3);
+    return s < nbig ? MAXR : (s < nbig + nmid ? (1 << rem) : (s < nbig + nmid + p3 ? 3 : 5));
   }
 };
 
@@ -110,6 +111,26 @@ __device__ __forceinline__ void dft_small(c2<T>* v) {
       for (int q = 0; q < 4; ++q) u[k + 4 * q] = v[4 * k + q];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = u[e];
+  } else if constexpr (R == 5) {
+    // X_k = v_0 + sum_{m=1}^{4} v_m w^{mk}, w = e^{-2 pi i / 5}: pair m with 5 - m, whose
+    // twiddles are conjugate (cos(2 pi m k / 5) shared, sin(...) opposite)
+    const T c1 = T(0.30901699437494742410229341718282);   // cos(2 pi / 5)
+    const T c2v = T(-0.80901699437494742410229341718282); // cos(4 pi / 5)
+    const T s1 = T(0.95105651629515357211643933337938);   // sin(2 pi / 5)
+    const T s2 = T(0.58778525229247312916870595463907);   // sin(4 pi / 5)
+    const c2<T> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const c2<T> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const c2<T> x0 = v[0];
+    // real parts from the sums, -i times the sine parts from the differences
+    const c2<T> r1 = c2<T>{x0.x + c1 * a1.x + c2v * a2.x, x0.y + c1 * a1.y + c2v * a2.y};
+    const c2<T> r2 = c2<T>{x0.x + c2v * a1.x + c1 * a2.x, x0.y + c2v * a1.y + c1 * a2.y};
+    const c2<T> i1 = c2<T>{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};   // k = 1
+    const c2<T> i2 = c2<T>{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};   // k = 2
+    v[0] = c2<T>{x0.x + a1.x + a2.x, x0.y + a1.y + a2.y};
+    v[1] = cadd(r1, cmul_mi(i1));
+    v[4] = csub(r1, cmul_mi(i1));
+    v[2] = cadd(r2, cmul_mi(i2));
+    v[3] = csub(r2, cmul_mi(i2));
   } else {
     // e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
     const T h3 = T(0.86602540378443864676372317075294);

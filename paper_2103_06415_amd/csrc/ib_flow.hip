@@ -18,32 +18,41 @@ struct Cfg {
 #define IB_DISPATCH_N(n, MACRO)                                \
   switch (n) {                                                 \
     case 16: MACRO(16); break;                                 \
+    case 20: MACRO(20); break;                                 \
     case 32: MACRO(32); break;                                 \
+    case 40: MACRO(40); break;                                 \
     case 48: MACRO(48); break;                                 \
     case 64: MACRO(64); break;                                 \
+    case 80: MACRO(80); break;                                 \
     case 96: MACRO(96); break;                                 \
     case 128: MACRO(128); break;                               \
+    case 160: MACRO(160); break;                               \
     case 192: MACRO(192); break;                               \
     case 256: MACRO(256); break;                               \
+    case 320: MACRO(320); break;                               \
     case 384: MACRO(384); break;                               \
     case 512: MACRO(512); break;                               \
+    case 640: MACRO(640); break;                               \
     case 768: MACRO(768); break;                               \
     case 1024: MACRO(1024); break;                             \
+    case 1280: MACRO(1280); break;                             \
     default: return hipErrorInvalidValue;                      \
   }
 
 bool supported_n(int n) {
   switch (n) {
-    case 16: case 32: case 48: case 64: case 96: case 128: case 192: case 256:
-    case 384: case 512: case 768: case 1024:
+    case 16: case 20: case 32: case 40: case 48: case 64: case 80: case 96: case 128:
+    case 160: case 192: case 256: case 320: case 384: case 512: case 640: case 768:
+    case 1024: case 1280:
       return true;
     default:
       return false;
   }
 }
 
+// sizes with measured alternative configurations (ib_flow_tuned.hip, ib_flow_multi_tuned.hip)
 bool flow_variant_available(int n, int fp64) {
-  return !fp64 && supported_n(n) && n >= FLOW_TUNE_MIN_N;
+  return !fp64 && (n == 256 || n == 384 || n == 512 || n == 768 || n == 1024);
 }
 
 template <typename T>

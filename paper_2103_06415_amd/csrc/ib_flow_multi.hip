@@ -8,17 +8,24 @@ namespace ib {
 #define IB_MULTI_N(n, MACRO)                                   \
   switch (n) {                                                 \
     case 16: MACRO(16); break;                                 \
+    case 20: MACRO(20); break;                                 \
     case 32: MACRO(32); break;                                 \
+    case 40: MACRO(40); break;                                 \
     case 48: MACRO(48); break;                                 \
     case 64: MACRO(64); break;                                 \
+    case 80: MACRO(80); break;                                 \
     case 96: MACRO(96); break;                                 \
     case 128: MACRO(128); break;                               \
+    case 160: MACRO(160); break;                               \
     case 192: MACRO(192); break;                               \
     case 256: MACRO(256); break;                               \
+    case 320: MACRO(320); break;                               \
     case 384: MACRO(384); break;                               \
     case 512: MACRO(512); break;                               \
+    case 640: MACRO(640); break;                               \
     case 768: MACRO(768); break;                               \
     case 1024: MACRO(1024); break;                             \
+    case 1280: MACRO(1280); break;                             \
     default: return hipErrorInvalidValue;                      \
   }
 

@@ -43,7 +43,7 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("n", [16, 32, 48, 96, 128, 384, 1024])
+@pytest.mark.parametrize("n", [16, 20, 32, 40, 48, 80, 96, 128, 160, 320, 384, 640, 1024, 1280])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_op_solve(torch_cuda, gpu_lib, n, prec):
     torch = torch_cuda
@@ -102,7 +102,7 @@ def _run(problem, steps, prec, **kw):
     return s
 
 
-@pytest.mark.parametrize("n,levels", [(32, 1), (32, 3), (64, 2), (96, 2)])
+@pytest.mark.parametrize("n,levels", [(32, 1), (32, 3), (64, 2), (96, 2), (40, 3), (80, 2), (160, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16dst"])
 def test_flow_steps_match_oracle(torch_cuda, gpu_lib, n, levels, prec):
     print(f"flow n={n} levels={levels} {prec}", flush=True)

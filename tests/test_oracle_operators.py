@@ -51,14 +51,14 @@ def test_curl_transpose_is_adjoint(n):
     assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
 
 
-@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("n", [8, 16, 20])
 def test_laplacian_eigenvalues_closed_form(n):
     ev = np.sort(np.linalg.eigvalsh(dense_l5(n)))
     closed = np.sort(dst.eigenvalues(n).ravel())
     np.testing.assert_allclose(ev, closed, atol=1e-13)
 
 
-@pytest.mark.parametrize("n", [8, 16, 24])
+@pytest.mark.parametrize("n", [8, 16, 20, 24])
 def test_sine_matrix_orthonormal_and_involutory(n):
     s = dst.sine_matrix(n)
     np.testing.assert_allclose(s @ s, np.eye(n - 1), atol=1e-14)
@@ -73,7 +73,7 @@ def test_sine_transform_diagonalises_laplacian(n):
     np.testing.assert_allclose(d, np.diag(dst.eigenvalues(n).ravel()), atol=1e-12)
 
 
-@pytest.mark.parametrize("n,alpha", [(8, 0.05), (16, 0.3)])
+@pytest.mark.parametrize("n,alpha", [(8, 0.05), (16, 0.3), (20, 0.1)])
 def test_cac_solve_matches_dense_solve(n, alpha):
     """(C^T A C) from the dense curl and A = I/dt + C C^T/(2 Re h^2) (Sec. 2.2),
     solved by LU; the oracle uses the sine diagonalisation (Sec. 3.2.1)."""
