@@ -66,7 +66,7 @@ class IbStats(ctypes.Structure):
 
 
 FLOW_VARIANTS = 8
-IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS, IB_OPT_REFRESH_EVERY_ITER = 1, 2, 3
+IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS, IB_OPT_REFRESH_EVERY_ITER, IB_OPT_TOP_AHEAD = 1, 2, 3, 4
 
 
 class IbFlowTuning(ctypes.Structure):

@@ -226,6 +226,11 @@ struct ib_solver {
   void* work = nullptr;   // spectral rows of s (then s-transform rows)
   void* workg = nullptr;  // the same for the circulation
   void* work2 = nullptr;
+  void* work_pre = nullptr;   // spectral scratch of the coarsest level launched ahead
+  void* workg_pre = nullptr;
+  bool top_ahead = false;     // the next step's coarsest level is already on the stream
+  bool top_ahead_ok = true;   // IB_OPT_TOP_AHEAD
+  hipEvent_t ctl_ready = nullptr;  // this step's control block is on the host
   void* lift = nullptr;   // edge transforms of a new streamfunction ring, [4][n-1]
   void* sstar = nullptr;
   void* tw = nullptr;
@@ -1463,11 +1468,16 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
 // transform are launched ahead under the device gates and nothing here waits for the GPU,
 // so the launches can be recorded as a graph; otherwise the host tests every FSI iteration.
 // Host state that changes per step (ring buffer alternation, step count) is left alone.
+// One level of the predictor: its new ring from the next coarser level, the right-hand side
+// and the transforms into the spectral scratch (work, workg), then its inverse row transform
+// into the state; on level 0 with bodies the s* rows and the FSI part come first.  first:
+// the step has no history yet.
 template <typename T>
-ib_status enqueue_step(ib_solver* s, bool ahead, int K) {
+ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void* work,
+                        void* workg) {
   const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
   const bool bodies = !s->bodies.empty();
-  for (int g = G - 1; g >= 0; --g) {
+  {
     LevelState& L = s->lv[g];
     const bool has_ring = g < G - 1;
     const int nxt = 1 - L.gcur;
@@ -1484,9 +1494,9 @@ ib_status enqueue_step(ib_solver* s, bool ahead, int K) {
     a.gf = g > 0 ? static_cast<T*>(s->lv[g - 1].g) : nullptr;
     a.gring = static_cast<T*>(L.gring[L.gcur]);
     a.gring_new = has_ring ? static_cast<T*>(L.gring[nxt]) : nullptr;
-    a.hist_in = s->first ? nullptr : static_cast<T*>(L.hist);
+    a.hist_in = first ? nullptr : static_cast<T*>(L.hist);
     a.hist_out = static_cast<T*>(L.hist);
-    a.out = static_cast<T*>(s->work);
+    a.out = static_cast<T*>(work);
     a.n = n;
     a.ps = a.pg = a.pgf = a.ph = a.po = P;
     a.alpha = (T)L.alpha;
@@ -1505,12 +1515,12 @@ ib_status enqueue_step(ib_solver* s, bool ahead, int K) {
         HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
       }
       TimeScope ts(s, IB_K_COL_SOLVE);
-      st = solve_into<T>(s, s->work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
-                         s->workg, has_ring ? s->lift : nullptr, s->tune.col);
+      st = solve_into<T>(s, work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
+                         workg, has_ring ? s->lift : nullptr, s->tune.col);
     }
     if (st) return st;
     RowArgs<T> r{};
-    r.in = static_cast<T*>(s->work);
+    r.in = static_cast<T*>(work);
     r.pi = r.po = P;
     const T* ring = has_ring ? static_cast<T*>(L.sring) : nullptr;
     const int* gate = nullptr;
@@ -1535,7 +1545,7 @@ ib_status enqueue_step(ib_solver* s, bool ahead, int K) {
     r.out = static_cast<T*>(L.s);
     r.r0 = 1;
     r.r1 = n - 1;
-    r.in2 = static_cast<T*>(s->workg);
+    r.in2 = static_cast<T*>(workg);
     r.out2 = static_cast<T*>(L.g);
     r.var = s->tune.idst;
     r.gate = gate;
@@ -1543,6 +1553,17 @@ ib_status enqueue_step(ib_solver* s, bool ahead, int K) {
       TimeScope ts(s, IB_K_ROW_IDST);
       HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 1, s->stream));
     }
+  }
+  return IB_OK;
+}
+
+// A step's levels from gtop (the coarsest, G - 1, unless it was launched ahead) to 0.
+template <typename T>
+ib_status enqueue_step(ib_solver* s, bool ahead, int K, int gtop = -1) {
+  const int G = (int)s->lv.size();
+  for (int g = gtop < 0 ? G - 1 : gtop; g >= 0; --g) {
+    ib_status st = enqueue_level<T>(s, g, ahead, K, s->first, s->work, s->workg);
+    if (st) return st;
   }
   return IB_OK;
 }
@@ -1645,8 +1666,21 @@ ib_status record_step(ib_solver* s, const StepPlan& p) {
   return IB_OK;
 }
 
+// Whether the next step's coarsest level can be launched while the host waits for this
+// step's convergence tests: it reads only its own level and the next finer level's
+// circulation (coarsification on read), both final before this step's FSI part when there
+// are three or more levels (with two, the finer level is level 0, whose final transform
+// waits for convergence and may still be redone on the host), and it has spectral scratch
+// of its own, so nothing the host may still add to this step touches it.
+bool can_launch_top_ahead(const ib_solver* s) {
+  return s->lv.size() >= 3 && s->work_pre != nullptr && !s->gemm && !s->timing && !s->graphs &&
+         s->top_ahead_ok;
+}
+
+// pre_next: the caller takes another step right after this one (its coarsest level may be
+// launched ahead).
 template <typename T>
-ib_status do_step(ib_solver* s, const StepPlan& p) {
+ib_status do_step(ib_solver* s, const StepPlan& p, bool pre_next = false) {
   const int G = (int)s->lv.size();
   if (s->nmov) {
     ib_status pst = update_poses(s, (s->step + 1) * s->cfg.dt);  // constraint at t_{n+1}
@@ -1658,12 +1692,22 @@ ib_status do_step(ib_solver* s, const StepPlan& p) {
     HIPCHK(hipGraphLaunch(sg->exec, s->stream));
     s->graph_launches++;
   } else {
-    st = enqueue_step<T>(s, p.ahead, p.K);
+    st = enqueue_step<T>(s, p.ahead, p.K, s->top_ahead ? G - 2 : -1);
     if (st) return st;
   }
+  s->top_ahead = false;
   if (p.ahead) {
     HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    if (pre_next && can_launch_top_ahead(s) && !sg) {
+      if (!s->ctl_ready) HIPCHK(hipEventCreateWithFlags(&s->ctl_ready, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(s->ctl_ready, s->stream));
+      st = enqueue_level<T>(s, G - 1, false, 0, false, s->work_pre, s->workg_pre);
+      if (st) return st;
+      s->top_ahead = true;
+      HIPCHK(hipEventSynchronize(s->ctl_ready));
+    } else {
+      HIPCHK(hipStreamSynchronize(s->stream));
+    }
     int resume = -1;
     st = fsi_after_ahead(s, &resume);
     if (st) return st;
@@ -1741,6 +1785,13 @@ ib_status alloc_state(ib_solver* s) {
   s->work = dalloc(s, inner);
   s->workg = dalloc(s, inner);
   s->work2 = dalloc(s, inner);
+  s->work_pre = s->workg_pre = nullptr;
+  s->top_ahead = false;
+  if (s->lv.size() >= 3 && !s->gemm) {
+    s->work_pre = dalloc(s, inner);
+    s->workg_pre = dalloc(s, inner);
+    if (!s->work_pre || !s->workg_pre) return IB_ERR_OOM;
+  }
   s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
   s->sstar = dalloc(s, full);
   if (!s->work || !s->workg || !s->work2 || !s->sstar || !s->lift) return IB_ERR_OOM;
@@ -2651,7 +2702,8 @@ ib_status ib_step(ib_solver* s, int32_t nsteps) {
     }
     if (!st) {
       HipShared lk;
-      st = s->fp64 ? do_step<double>(s, p) : do_step<float>(s, p);
+      const bool more = k + 1 < nsteps;
+      st = s->fp64 ? do_step<double>(s, p, more) : do_step<float>(s, p, more);
     }
     if (st) {
       s->failed = true;
@@ -2893,6 +2945,10 @@ ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
     destroy_graphs(s);
     return IB_OK;
   }
+  if (option == IB_OPT_TOP_AHEAD) {
+    s->top_ahead_ok = value != 0;
+    return IB_OK;
+  }
   return IB_ERR_ARG;
 }
 
@@ -3128,6 +3184,7 @@ ib_status ib_destroy(ib_solver* s) {
   while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->hpose) (void)hipHostFree(s->hpose);
+  if (s->ctl_ready) (void)hipEventDestroy(s->ctl_ready);
   delete s;
   return IB_OK;
 }

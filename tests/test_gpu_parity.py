@@ -247,29 +247,32 @@ def test_exact_operator_for_moving_bodies(torch_cuda, gpu_lib, which):
 
 @pytest.mark.parametrize("which", ["flag", "plate"])
 def test_fsi_ahead_and_graphs_give_the_same_results(torch_cuda, gpu_lib, which):
-    """FSI iterations launched ahead with device-side convergence tests, and steps replayed
-    from recorded HIP graphs, reproduce the host-tested iteration bit for bit (same kernels,
-    same order); the steps that needed more iterations than were launched ahead continue
-    on the host."""
+    """FSI iterations launched ahead with device-side convergence tests (with and without
+    the next step's coarsest level launched while the host waits), and steps replayed from
+    recorded HIP graphs, reproduce the host-tested iteration bit for bit (same kernels, same
+    arithmetic); the steps that needed more iterations than were launched ahead continue on
+    the host."""
     from paper_2103_06415_amd import binding
     import torch
-    prob = (W.flag_problem(n=32, levels=2, steps=9) if which == "flag"
-            else W.plate_problem(n=32, levels=2, steps=9))
+    prob = (W.flag_problem(n=32, levels=3, steps=9) if which == "flag"
+            else W.plate_problem(n=32, levels=3, steps=9))
     runs = {}
-    for mode, (ahead, graphs) in {"host": (0, 0), "ahead": (1, 0), "graph": (1, 1)}.items():
+    modes = {"host": (0, 0, 1), "ahead": (1, 0, 1), "ahead_no_top": (1, 0, 0), "graph": (1, 1, 1)}
+    for mode, (ahead, graphs, top) in modes.items():
         print(f"{which} {mode}", flush=True)
         s = binding.Solver(prob, precision=binding.IB_FP64, stream=torch.cuda.Stream())
         s.set_option(binding.IB_OPT_FSI_AHEAD, ahead)
         s.set_option(binding.IB_OPT_GRAPHS, graphs)
+        s.set_option(binding.IB_OPT_TOP_AHEAD, top)
         s.prepare()
         s.step(9)
         s.sync()
         st = s.stats()
-        runs[mode] = (s.vorticity(0), s.vorticity(1), s.stresses(0), s.deflection(0), st)
+        runs[mode] = (s.vorticity(0), s.vorticity(2), s.stresses(0), s.deflection(0), st)
         print(f"  iters max {st['newton_iters_max']} graphs {st['graph_launches']} "
               f"captures {st['graph_captures']} resumes {st['fsi_resumes']}", flush=True)
         s.close()
-    for mode in ("ahead", "graph"):
+    for mode in ("ahead", "ahead_no_top", "graph"):
         for k in range(4):
             assert np.array_equal(runs[mode][k], runs["host"][k]), (mode, k)
     assert runs["host"][4]["graph_launches"] == 0
