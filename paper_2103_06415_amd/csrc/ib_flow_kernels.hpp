@@ -317,7 +317,11 @@ template <typename T, int N, int CW, int NT, int MAXR>
 __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>* __restrict__ tw,
                                                const T* __restrict__ lam, int nblocks, int bx,
                                                int by) {
-  __shared__ c2<T> buf[CW * fft_pad_len<N>()];
+  // With room for 2 CW transforms, the two inverse column transforms (s and gamma) run as one
+  // pass over 2 CW sequences: half the dependent stages, twice the butterflies per stage.
+  constexpr size_t REST = sizeof(c2<T>) * TwLayout<N, MAXR>::total + sizeof(T) * (3 * N + 2 * CW);
+  constexpr bool MERGE = REST + sizeof(c2<T>) * 2 * CW * fft_pad_len<N>() <= 160 * 1024;
+  __shared__ c2<T> buf[(MERGE ? 2 : 1) * CW * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
   __shared__ T slam[N];
   __shared__ T slift[2 * N];    // edge transforms of the left and right ring columns
@@ -423,6 +427,62 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
     }
   }
   const int nout = a.out2 != nullptr ? 2 : 1;
+  if constexpr (MERGE) {
+    if (nout == 2) {
+      T* dsts[2] = {a.out + (size_t)by * a.bso, a.out2 + (size_t)by * a.bso};
+      // previous values of the accumulated outputs, fetched while the transform runs
+      T pa[2][PER], pb[2][PER];
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int b = 0; b < PER; ++b) {
+          const int e = tid + b * NT;
+          const int c = e % CW, j = 1 + e / CW, col = k0 + c, j2 = N - j;
+          const bool ok = a.accumulate && e < NP && col < N - 1;
+          pa[o][b] = (ok && j >= a.w0 && j <= a.w1) ? dsts[o][(size_t)(j - 1) * a.po + col] : T(0);
+          pb[o][b] = (ok && j != N / 2 && j2 >= a.w0 && j2 <= a.w1)
+                         ? dsts[o][(size_t)(j2 - 1) * a.po + col]
+                         : T(0);
+        }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < PER; ++b) {
+        const int e = tid + b * NT;
+        if (e < NP) {
+          const int c = e % CW, l = 1 + e / CW;
+          const T ga = xa[b] / ea[b], gb = xb[b] / eb[b];
+          c2<T>* w0 = buf + c * fft_pad_len<N>();
+          c2<T>* w1 = buf + (CW + c) * fft_pad_len<N>();
+          dst_pack<T, N>(w0, l, (ga + fa[b]) * (a.scale / la[b]));
+          dst_pack<T, N>(w1, l, ga * a.scale);
+          if (l != N / 2) {
+            dst_pack<T, N>(w0, N - l, (gb + fb[b]) * (a.scale / lb[b]));
+            dst_pack<T, N>(w1, N - l, gb * a.scale);
+          }
+        }
+      }
+      for (int c = tid; c < 2 * CW; c += NT) dst_pack_zeros<T, N>(buf + c * fft_pad_len<N>());
+      __syncthreads();
+      fft_lds<T, N, 2 * CW, NT, MAXR>(buf, stw, tid);
+#pragma unroll
+      for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int b = 0; b < PER; ++b) {
+          const int e = tid + b * NT;
+          if (e >= NP) continue;
+          const int c = e % CW, j = 1 + e / CW;
+          const int col = k0 + c;
+          if (col >= N - 1) continue;
+          T yk, ynk;
+          dst_unpack<T, N>(buf + (o * CW + c) * fft_pad_len<N>(), stw, j, yk, ynk);
+          if (j >= a.w0 && j <= a.w1) dsts[o][(size_t)(j - 1) * a.po + col] = pa[o][b] + yk;
+          const int j2 = N - j;
+          if (j != N / 2 && j2 >= a.w0 && j2 <= a.w1)
+            dsts[o][(size_t)(j2 - 1) * a.po + col] = pb[o][b] + ynk;
+        }
+      return;
+    }
+  }
   for (int o = 0; o < nout; ++o) {
     T* dst = (o == 0 ? a.out : a.out2) + (size_t)by * a.bso;
     // previous values of the accumulated outputs, fetched while the transform runs
