@@ -1347,6 +1347,7 @@ constexpr int REF_NB_ONE = 32;   // workgroups up to which every workgroup sums 
 constexpr int REF_NB_MAX = 128;
 constexpr size_t REF_LDS_CACHE = 48 * 1024;
 constexpr size_t REF_LDS_BIG = 96 * 1024;
+constexpr int REF_LOADS = 8;      // loads of a thread in flight while the matrices fill LDS
 size_t refine_ws_doubles(int n, int) {
   return (size_t)REF_HDR + (size_t)2 * REF_NB_MAX * (n + 1) + (size_t)2 * (n + 1);
 }
@@ -1430,15 +1431,35 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
   if (lane == 0) sred[wv] = mb;
   for (int k = tid; k < nr; k += 256) sb[k] = b[r0 + k];
   if (CACHE) {
-    for (int e = tid; e < nr * n; e += 256) {
-      const int k = e / n, j = e % n;
-      sm[e] = M[(size_t)(r0 + k) * pm + j];
+    // rows R_w of M and columns R_w of X into LDS, REF_LOADS loads of a thread in flight at
+    // once (the matrices were just written elsewhere on the chip, so each round trip is long)
+    const int tot = nr * n;
+    for (int e0 = tid; e0 < tot; e0 += 256 * REF_LOADS) {
+      double v[REF_LOADS];
+#pragma unroll
+      for (int u = 0; u < REF_LOADS; ++u) {
+        const int e = min(e0 + u * 256, tot - 1);
+        v[u] = M[(size_t)(r0 + e / n) * pm + e % n];
+      }
+#pragma unroll
+      for (int u = 0; u < REF_LOADS; ++u)
+        if (e0 + u * 256 < tot) sm[e0 + u * 256] = v[u];
     }
-    for (int e = tid; e < nr * n; e += 256) {
-      const int j = e / nr, k = e % nr;
-      const double x = X[(size_t)j * pm + r0 + k];
-      sx[(size_t)j * rw + k] = x;
-      if (xcopy) xcopy[(size_t)j * pm + r0 + k] = x;
+    for (int e0 = tid; e0 < tot; e0 += 256 * REF_LOADS) {
+      double v[REF_LOADS];
+#pragma unroll
+      for (int u = 0; u < REF_LOADS; ++u) {
+        const int e = min(e0 + u * 256, tot - 1);
+        v[u] = X[(size_t)(e / nr) * pm + r0 + e % nr];
+      }
+#pragma unroll
+      for (int u = 0; u < REF_LOADS; ++u) {
+        const int e = e0 + u * 256;
+        if (e >= tot) continue;
+        const int j = e / nr, k = e % nr;
+        sx[(size_t)j * rw + k] = v[u];
+        if (xcopy) xcopy[(size_t)j * pm + r0 + k] = v[u];
+      }
     }
   } else if (xcopy) {
     for (int e = tid; e < nr * n; e += 256) {
