@@ -28,15 +28,15 @@ PEAK_HBM = 8.0e12
 # copy; profiles/flow_1024x4_fp32_hbm_traffic.md), by kernel class and the configuration
 # (variant) measured; a configuration without a measurement reports no traffic
 TRAFFIC_PER_LAUNCH = {
-    ("rhs_rowdst", 0): 21.80e6, ("rhs_rowdst", 1): 21.79e6, ("rhs_rowdst", 2): 21.69e6,
-    ("rhs_rowdst", 3): 21.68e6, ("rhs_rowdst", 4): 21.67e6, ("rhs_rowdst", 5): 21.76e6,
-    ("rhs_rowdst", 6): 21.69e6, ("rhs_rowdst", 7): 21.72e6,
-    ("col_solve", 0): 12.23e6, ("col_solve", 1): 13.23e6, ("col_solve", 2): 13.04e6,
-    ("col_solve", 3): 13.04e6, ("col_solve", 4): 13.02e6, ("col_solve", 5): 13.66e6,
-    ("col_solve", 6): 13.16e6, ("col_solve", 7): 37.95e6,
-    ("row_idst", 0): 17.11e6, ("row_idst", 1): 17.14e6, ("row_idst", 2): 17.06e6,
-    ("row_idst", 3): 17.05e6, ("row_idst", 4): 17.05e6, ("row_idst", 5): 17.10e6,
-    ("row_idst", 6): 17.05e6, ("row_idst", 7): 17.07e6,
+    ("rhs_rowdst", 0): 21.79e6, ("rhs_rowdst", 1): 21.79e6, ("rhs_rowdst", 2): 21.69e6,
+    ("rhs_rowdst", 3): 21.67e6, ("rhs_rowdst", 4): 21.67e6, ("rhs_rowdst", 5): 21.75e6,
+    ("rhs_rowdst", 6): 21.68e6, ("rhs_rowdst", 7): 21.74e6,
+    ("col_solve", 0): 12.35e6, ("col_solve", 1): 13.41e6, ("col_solve", 2): 13.12e6,
+    ("col_solve", 3): 13.10e6, ("col_solve", 4): 13.09e6, ("col_solve", 5): 13.70e6,
+    ("col_solve", 6): 42.97e6, ("col_solve", 7): 49.18e6,
+    ("row_idst", 0): 17.11e6, ("row_idst", 1): 17.13e6, ("row_idst", 2): 17.05e6,
+    ("row_idst", 3): 17.04e6, ("row_idst", 4): 17.05e6, ("row_idst", 5): 17.11e6,
+    ("row_idst", 6): 17.04e6, ("row_idst", 7): 17.07e6,
 }
 
 
