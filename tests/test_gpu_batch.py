@@ -157,3 +157,65 @@ def test_batch_rejects_bad_members(torch_cuda, gpu_lib):
     assert e.value.code == binding.IB_ERR_STATE
     for s in (a, b, c):
         s.close()
+
+
+def test_members_step_on_alone_after_the_batch(torch_cuda, gpu_lib):
+    """A batch can be destroyed and its members stepped further on their own (and a batch
+    step of zero steps does nothing); the results equal a solver stepped alone throughout."""
+    from paper_2103_06415_amd import binding
+    probs = [W.plate_problem(n=48, levels=2, steps=0), W.cylinder_problem(n=32, steps=0)]
+    ref = []
+    for p in probs:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        s.step(6)
+        s.sync()
+        ref.append((s.vorticity(0), s.stresses(0)))
+        s.close()
+    sols = []
+    for p in probs:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        sols.append(s)
+    batch = binding.Batch(sols)
+    batch.step(0)
+    assert batch.stats()["steps"] == 0
+    batch.step(4)
+    batch.close()
+    for s in sols:
+        s.step(2)
+        s.sync()
+    for (w, f), s in zip(ref, sols):
+        assert np.array_equal(s.vorticity(0), w)
+        assert np.array_equal(s.stresses(0), f)
+        assert s.stats()["step"] == 6
+        s.close()
+
+
+def test_a_failing_member_stops_the_batch(torch_cuda, gpu_lib):
+    """A member whose body leaves its sub-domain: the batch step reports that member's error,
+    says what happened, and refuses further steps (the member is marked failed)."""
+    from paper_2103_06415_amd import binding
+    fast = W.driven_plate_problem(n=64, levels=2, steps=0, subdomain=True)
+    body = fast.bodies[0]
+    # the same plate, starting near the sub-domain's right edge (x = 1.95; the plate's tip
+    # at 1.825) and translating at speed 2: its tip leaves after about 13 steps of 0.005
+    fast.bodies[0] = W.MovingRigid(xy_ref=body.xy_ref, ds=body.ds,
+                                   motion=lambda t: (1.3 + 2.0 * t, 0.0, 0.0, 2.0, 0.0, 0.0))
+    sols = []
+    for p in (W.cylinder_problem(n=32, steps=0), fast):
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        sols.append(s)
+    batch = binding.Batch(sols)
+    with pytest.raises(binding.IbError) as e:
+        batch.step(40)
+    print(f"  batch error: {e.value}", flush=True)
+    assert e.value.code == binding.IB_ERR_OUT_OF_SUBDOMAIN
+    assert batch.last_error() != ""
+    with pytest.raises(binding.IbError) as e2:
+        batch.step(1)
+    assert e2.value.code == binding.IB_ERR_STATE
+    batch.close()
+    for s in sols:
+        s.close()
