@@ -1622,30 +1622,36 @@ __global__ __launch_bounds__(256) void k_refine_multi(const RefineJob* __restric
 }
 
 // C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B, on the FP64 matrix
-// cores: each wave owns a 16 x 16 tile of C (v_mfma_f64_16x16x4f64; A fragment: lane l
-// holds A[i0 + l % 16][k + l / 16], B fragment B[k + l / 16][j0 + l % 16], result item v
-// of lane l is C[i0 + l / 16 + 4 v][j0 + l % 16]); 2 x 2 waves per 32 x 32 workgroup
-// tile; the k loop loads 16 fragments ahead.
+// cores (v_mfma_f64_16x16x4f64; A fragment: lane l holds A[i0 + l % 16][k + l / 16], B
+// fragment B[k + l / 16][j0 + l % 16], result item v of lane l is C[i0 + l / 16 + 4 v]
+// [j0 + l % 16]).  One 16 x 16 tile of C per workgroup of GEMM_KS waves: wave w takes the
+// w-th of GEMM_KS equal k ranges (multiples of 4), so the dependent MFMA chain of a wave is
+// 1/GEMM_KS of the k extent (at n = 202: 7 products of 64 cycles each at this chip's FP64
+// matrix rate, instead of 52 for a wave that owns its tile's whole k range).
 typedef double v4d __attribute__((ext_vector_type(4)));
-// KC k steps (of 4) per chunk, loaded before any is used; for n <= 4 KC the whole k range
-// is one chunk, so each wave waits for memory once.  Two accumulators alternate over k
-// (halving the dependent MFMA chain) and are added at the end.
+// KC k steps (of 4) per chunk, loaded before any is used; when a wave's k range fits one
+// chunk (n <= GEMM_ONE_N with KC = GEMM_KC) each wave waits for memory once.  Two
+// accumulators alternate over k; the partial tiles are added in wave order through LDS
+// (deterministic).
 template <int KC>
 __device__ __forceinline__ void gemm64_body(const double* A, const double* B, double* C, int n,
                                             int p, int two_minus, const int* gate, int bx, int by) {
+  __shared__ v4d part[GEMM_KS - 1][64];
   if (iter_gated(gate)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = by * 32 + (w >> 1) * 16, j0 = bx * 32 + (w & 1) * 16;
+  const int i0 = by * 16, j0 = bx * 16;
   const int li = lane & 15, lk = lane >> 4;
   const int ai = i0 + li, bj = j0 + li;
+  const int per = ((n + 3) / 4 + GEMM_KS - 1) / GEMM_KS;  // k steps of 4 per wave
+  const int kbeg = 4 * per * w, kend = min(n, 4 * per * (w + 1));
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < n; k0 += 4 * KC) {
+  for (int k0 = kbeg; k0 < kend; k0 += 4 * KC) {
     double av[KC], bv[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
       const int k = k0 + 4 * c + lk;
-      av[c] = (ai < n && k < n) ? A[(size_t)ai * p + k] : 0.0;
-      bv[c] = (bj < n && k < n) ? B[(size_t)k * p + bj] : 0.0;
+      av[c] = (ai < n && k < kend) ? A[(size_t)ai * p + k] : 0.0;
+      bv[c] = (bj < n && k < kend) ? B[(size_t)k * p + bj] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < KC; c += 2) {
@@ -1653,11 +1659,17 @@ __device__ __forceinline__ void gemm64_body(const double* A, const double* B, do
       if (c + 1 < KC) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[c + 1], bv[c + 1], acc1, 0, 0, 0);
     }
   }
+  acc0 += acc1;
+  if (w > 0) part[w - 1][lane] = acc0;
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
+  for (int q = 0; q < GEMM_KS - 1; ++q) acc0 += part[q][lane];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = i0 + lk + 4 * v, j = j0 + li;
     if (i < n && j < n) {
-      double val = acc0[v] + acc1[v];
+      double val = acc0[v];
       if (two_minus) val = (i == j ? 2.0 : 0.0) - val;
       C[(size_t)i * p + j] = val;
     }
@@ -1665,15 +1677,15 @@ __device__ __forceinline__ void gemm64_body(const double* A, const double* B, do
 }
 
 template <int KC>
-__global__ __launch_bounds__(256) void k_gemm64(const double* A, const double* B, double* C, int n,
+__global__ __launch_bounds__(64 * GEMM_KS) void k_gemm64(const double* A, const double* B, double* C, int n,
                                                 int p, int two_minus, const int* gate) {
   gemm64_body<KC>(A, B, C, n, p, two_minus, gate, blockIdx.x, blockIdx.y);
 }
 
 template <int KC>
-__global__ __launch_bounds__(256) void k_gemm64_multi(const GemmJob* __restrict__ tab) {
+__global__ __launch_bounds__(64 * GEMM_KS) void k_gemm64_multi(const GemmJob* __restrict__ tab) {
   const GemmJob j = tab[blockIdx.z];
-  const int nb = (j.n + 31) / 32;
+  const int nb = (j.n + 15) / 16;
   if ((int)blockIdx.x >= nb || (int)blockIdx.y >= nb) return;
   gemm64_body<KC>(j.A, j.B, j.C, j.n, j.p, j.two_minus, j.gate, blockIdx.x, blockIdx.y);
 }
@@ -1785,11 +1797,13 @@ hipError_t launch_refine(const double* M, int pm, const double* X, const double*
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
                          hipStream_t st, const int* gate) {
-  const int nb = (n + 31) / 32;
-  if (n <= 4 * 52)
-    hipLaunchKernelGGL(k_gemm64<52>, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus, gate);
+  const int nb = (n + 15) / 16;
+  if (n <= GEMM_ONE_N)
+    hipLaunchKernelGGL(k_gemm64<GEMM_KC>, dim3(nb, nb), dim3(64 * GEMM_KS), 0, st, A, B, C, n, p,
+                       two_minus, gate);
   else
-    hipLaunchKernelGGL(k_gemm64<16>, dim3(nb, nb), dim3(256), 0, st, A, B, C, n, p, two_minus, gate);
+    hipLaunchKernelGGL(k_gemm64<16>, dim3(nb, nb), dim3(64 * GEMM_KS), 0, st, A, B, C, n, p,
+                       two_minus, gate);
   return hipGetLastError();
 }
 
@@ -1999,11 +2013,11 @@ hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipSt
 hipError_t launch_gemm64_multi(const GemmJob* tab, int count, int max_n, int kc52,
                                hipStream_t st) {
   if (count <= 0 || max_n <= 0) return hipSuccess;
-  const int nb = (max_n + 31) / 32;
+  const int nb = (max_n + 15) / 16;
   if (kc52)
-    hipLaunchKernelGGL(k_gemm64_multi<52>, dim3(nb, nb, count), dim3(256), 0, st, tab);
+    hipLaunchKernelGGL(k_gemm64_multi<GEMM_KC>, dim3(nb, nb, count), dim3(64 * GEMM_KS), 0, st, tab);
   else
-    hipLaunchKernelGGL(k_gemm64_multi<16>, dim3(nb, nb, count), dim3(256), 0, st, tab);
+    hipLaunchKernelGGL(k_gemm64_multi<16>, dim3(nb, nb, count), dim3(64 * GEMM_KS), 0, st, tab);
   return hipGetLastError();
 }
 hipError_t launch_refine_multi(const RefineJob* tab, int count, int max_nb, size_t lds, int cache,

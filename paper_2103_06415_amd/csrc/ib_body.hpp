@@ -185,7 +185,12 @@ template <typename T>
 hipError_t launch_spread_multi(const SpreadJob<T>* tab, int count, int max_gx, int max_gy,
                                hipStream_t st);
 hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipStream_t st);
-// kc52: every entry has n <= 208 (the whole k range in one chunk); otherwise none has
+// Waves per workgroup of the FP64 product, each taking an equal share of the k range.
+constexpr int GEMM_KS = 8;
+// k steps (of 4) per chunk of a wave such that n <= GEMM_ONE_N takes one chunk per wave.
+constexpr int GEMM_KC = (52 + GEMM_KS - 1) / GEMM_KS;
+constexpr int GEMM_ONE_N = 4 * GEMM_KC * GEMM_KS;
+// kc52: every entry has n <= GEMM_ONE_N (the k range of each wave in one chunk); otherwise none has
 hipError_t launch_gemm64_multi(const GemmJob* tab, int count, int max_n, int kc52,
                                hipStream_t st);
 // cache: 0 uncached rows, 1 LDS-cached rows, 2 cached rows summed in slices (RefineShape::two)

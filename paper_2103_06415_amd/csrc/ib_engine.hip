@@ -2171,7 +2171,7 @@ ib_status batch_step(ib_batch* b) {
         const double* X = s->Minv;
         double* xcopy = nullptr;
         if (refresh) {
-          const int k = nf <= 4 * 52 ? 1 : 0;
+          const int k = nf <= GEMM_ONE_N ? 1 : 0;
           g1[k].push_back(GemmJob{a.M, s->Minv, s->W, nf, a.pm, 1, s->gate});
           g2[k].push_back(GemmJob{s->Minv, s->W, s->Xn, nf, a.pm, 0, s->gate});
           gmax_n[k] = std::max(gmax_n[k], nf);
