@@ -161,7 +161,7 @@ __device__ void point_position(const FsiArgs& a, const BodyDev& b, int local, do
 //   moving      (vx, vy) + omega e_z x (R(angle) xy_ref) at t_{n+1}
 //   torsional   S ((2/dt) r_phi / J - r_theta), plus on a mount the driver's velocity at the
 //               point, v_H + omega e_z x (p - H)
-//   deformable  0 here; k_beam subtracts T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
+//   deformable  0 here; k_schur_sd subtracts T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
 __device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, int comp) {
   const int m = b.npts;
   if (b.kind == BODY_RIGID) {
@@ -503,6 +503,22 @@ __device__ __forceinline__ void schur_sd_body(const FsiArgs& a, int all4, int bx
     }
     a.M[(size_t)r * a.pm + c] = mv;
   }
+  // a deformable body's row: the right-hand side loses T ((2/dt)(chi^k + J_d^{-1} res) -
+  // r_chi) (eqs. (17) and (37)), with the solve J_d^{-1} res that k_beam left in column 2m
+  // of ywork
+  if (tid == 0) {
+    const BodyDev& b = a.bodies[row_body(a, r)];
+    if (b.kind == BODY_DEFORMABLE) {
+      const int m = b.npts, u = r - 2 * b.pt0, node = u % m, cmp = u / m;
+      if (node > 0) {
+        const int g = 3 * node + cmp, ncol = 2 * m + 1;
+        const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
+        const double pred = ck[g] + a.ywork[b.yoff + (size_t)(g - 3) * ncol + 2 * m];
+        const double rchi = a.zeta[b.dof0 + g] + 2.0 * a.chi[b.dof0 + g] / a.dt;
+        a.rhs[r] -= (2.0 / a.dt) * pred - rchi;
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a, int all4) {
@@ -751,23 +767,6 @@ __device__ __forceinline__ void beam_body(const FsiArgs& a, int bi, int bx) {
     const int u = t / NC, col = c0 + t % NC;
     if (col < ncol) y[(size_t)u * ncol + col] = rhs[t];
   }
-  // the workgroup that solved J_d^{-1} res (column 2m) adds the deformable part of the
-  // Schur right-hand side: rhs -= T ((2/dt)(chi^k + J_d^{-1} res) - r_chi)
-  if (c0 <= 2 * m && 2 * m < c0 + NC) {
-    const int cl = 2 * m - c0, r0 = 2 * b.pt0;
-    const double dt = a.dt;
-    const double* ck = (a.iter == 0 ? a.chi : a.chi_new) + b.dof0;
-    const double* xn = a.chi + b.dof0;
-    const double* zn = a.zeta + b.dof0;
-    for (int u = tid; u < 2 * m; u += BEAM_NT) {
-      const int node = u % m, cmp = u / m;
-      if (node == 0) continue;
-      const int g = 3 * node + cmp;
-      const double pred = ck[g] + rhs[(g - 3) * NC + cl];
-      const double rchi = zn[g] + 2.0 * xn[g] / dt;
-      a.rhs[r0 + u] -= (2.0 / dt) * pred - rchi;
-    }
-  }
 }
 
 __global__ __launch_bounds__(BEAM_NT) void k_beam(FsiArgs a, int bi) {
@@ -781,6 +780,15 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam_multi(const BeamJob* __restric
   const int bi = j.bi, ncol = 2 * j.m + 1;
   if ((int)blockIdx.x >= (ncol + BEAM_NC - 1) / BEAM_NC) return;
   beam_body(a, bi, blockIdx.x);
+}
+
+// k_body_ops and k_beam of one deformable body in one launch: workgroups below nbeam solve
+// the beam's right-hand sides, the others take BEAM_NT body points each (the two share no
+// data: the beam's part of the Schur right-hand side is applied by k_schur_sd).
+template <typename T>
+__global__ __launch_bounds__(BEAM_NT) void k_ops_beam(FsiArgs a, int bi, int nbeam) {
+  if ((int)blockIdx.x < nbeam) beam_body(a, bi, blockIdx.x);
+  else body_ops_body<T>(a, blockIdx.x - nbeam);
 }
 
 // LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K); the
@@ -1862,6 +1870,18 @@ hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
   hipLaunchKernelGGL(k_beam, dim3((ncol + BEAM_NC - 1) / BEAM_NC), dim3(BEAM_NT), lds, st, a, bi);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_ops_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
+  const size_t lds = beam_lds_bytes(m);
+  if (m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
+  const int nbeam = (2 * m + 1 + BEAM_NC - 1) / BEAM_NC;
+  const int nops = (a.npts + BEAM_NT - 1) / BEAM_NT;
+  hipLaunchKernelGGL((k_ops_beam<T>), dim3(nbeam + nops), dim3(BEAM_NT), lds, st, a, bi, nbeam);
+  return hipGetLastError();
+}
+template hipError_t launch_ops_beam<float>(const FsiArgs&, int, int, hipStream_t);
+template hipError_t launch_ops_beam<double>(const FsiArgs&, int, int, hipStream_t);
+
 int update_blocks(int nf) {
   // enough waves for one group of 4 rows of the largest beam (3m - 3 <= 1.5 nf rows)
   const int groups = (3 * nf / 2 + 3) / 4;

@@ -228,6 +228,9 @@ hipError_t launch_matvec(const double* A, int pa, const double* x, double* y, in
 // iteration `it` of K launched ahead (tolerance tol, or a fixed count).
 hipError_t launch_update(const FsiArgs& a, int it, int K, double tol, int fixed, hipStream_t st);
 hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st);
+// k_body_ops and k_beam (deformable body bi, m points) in one launch.
+template <typename T>
+hipError_t launch_ops_beam(const FsiArgs& a, int bi, int m, hipStream_t st);
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st);
 template <typename T>
 hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,

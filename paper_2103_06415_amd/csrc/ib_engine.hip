@@ -1201,10 +1201,18 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   a.iter = it;
   const int n = s->n, nf = s->nf;
   TimeScope ts(s, IB_K_FSI);
-  HIPCHK(launch_body_ops<T>(a, s->stream));
+  // the body operators and the first deformable body's beam solves share one launch
+  int fused = -1;
   for (size_t bi = 0; bi < s->bodies.size(); ++bi)
-    if (s->bodies[bi].kind == BODY_DEFORMABLE)
-      HIPCHK(launch_beam(a, (int)bi, s->bodies[bi].m, s->stream));
+    if (s->bodies[bi].kind == BODY_DEFORMABLE) {
+      if (fused < 0) {
+        fused = (int)bi;
+        HIPCHK(launch_ops_beam<T>(a, fused, s->bodies[bi].m, s->stream));
+      } else {
+        HIPCHK(launch_beam(a, (int)bi, s->bodies[bi].m, s->stream));
+      }
+    }
+  if (fused < 0) HIPCHK(launch_body_ops<T>(a, s->stream));
   if (s->exact_moving) {
     // the exact flow block at this iterate: one point-source solve per body row
     for (int c0 = 0; c0 < nf; c0 += s->xo.nslots) {
