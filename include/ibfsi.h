@@ -245,12 +245,14 @@ ib_status ib_destroy(ib_solver* s);
  *   first iteration of a step whose previous solve needed more than 6 sweeps (the two
  *   n^3 products then cost more than the sweeps they save).  The solution is the same to
  *   round-off in every mode.
- * IB_OPT_TOP_AHEAD (default 1): within one ib_step call, launch the next step's coarsest
- *   level (three or more levels) while the host waits for this step's convergence tests,
- *   with its own spectral scratch; it needs only states this step has finished before its
- *   FSI part, so the results are the same bit for bit, and the GPU does not idle while the
- *   host prepares the next step.  Not used with IB_OPT_GRAPHS, IB_FP32_FLOW_BF16_DST or
- *   kernel timing.
+ * IB_OPT_TOP_AHEAD (default 2): within one ib_step call, with three or more levels, start
+ *   the next step's coarse levels early, with spectral scratch of their own.  1: the
+ *   coarsest level, on the solver's stream while the host waits for this step's
+ *   convergence tests.  2: every level >= 2, on a second stream (default priority) of the
+ *   solver as soon as this step's level 1 is done, concurrently with this step's level 0,
+ *   FSI part and corrector.  0: off.  Those levels need only states that are final once
+ *   this step's level 1 is (level 1 is never corrected), so the results are the same bit
+ *   for bit.  Not used with IB_OPT_GRAPHS, IB_FP32_FLOW_BF16_DST or kernel timing.
  * Errors: IB_ERR_ARG for an unknown option or value. */
 #define IB_OPT_FSI_AHEAD 1
 #define IB_OPT_GRAPHS 2

@@ -1104,20 +1104,28 @@ __global__ __launch_bounds__(STRUCT_NT) void k_finish_multi(const FsiArgs* __res
 // outside columns [ilo, ihi] are zero.  lambda_a = (ds_a / h) f_a.  Each workgroup
 // covers a 64 x 4 tile of vertices.  It first lists (in row order, by wave ballots) the
 // operator rows whose window reaches the tile, stages their windows and coefficients
-// in LDS, and then every vertex sums those rows in that fixed order, so the result is
-// deterministic.
+// in LDS (SPREAD_STAGE rows at a time), and then every vertex sums those rows in that
+// fixed order, so the result is deterministic.  Dynamic LDS (spread_lds_bytes): the list
+// (nf ints), then the staged rows; small enough that every workgroup of a launch is
+// resident at once.
 constexpr int SPREAD_TX = SPREAD_TILE_X, SPREAD_TY = SPREAD_TILE_Y, SPREAD_NT = SPREAD_TX * SPREAD_TY;
 constexpr int SPREAD_MAXROWS = SPREAD_ROWS_MAX;
+constexpr int SPREAD_STAGE = 64;
+
+size_t spread_lds_bytes(int nf) {
+  return (size_t)SPREAD_STAGE * (16 * 8 + 8 + 3 * 4) + (size_t)(nf + 1) / 2 * 8;
+}
 
 template <typename T>
 __device__ __forceinline__ void spread_body(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi,
                                             T* out, int po, int bx, int by) {
   constexpr int NW = SPREAD_NT / 64;
-  __shared__ int list[SPREAD_MAXROWS];
+  extern __shared__ double spl[];
+  double (*sw)[16] = reinterpret_cast<double (*)[16]>(spl);  // [SPREAD_STAGE][16]
+  double* sc = spl + SPREAD_STAGE * 16;                        // [SPREAD_STAGE]
+  int (*sb)[3] = reinterpret_cast<int (*)[3]>(sc + SPREAD_STAGE);  // [SPREAD_STAGE][3]
+  int* list = &sb[SPREAD_STAGE][0];                            // [nf]
   __shared__ int wcount[NW];
-  __shared__ int sb[SPREAD_NT][3];
-  __shared__ double sw[SPREAD_NT][16];
-  __shared__ double sc[SPREAD_NT];
   if (post_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tx = tid % SPREAD_TX, ty = tid / SPREAD_TX;
@@ -1146,8 +1154,8 @@ __device__ __forceinline__ void spread_body(const FsiArgs& a, int jlo, int jhi, 
     }
   }
   double src = 0.0;
-  for (int q0 = 0; q0 < cnt; q0 += SPREAD_NT) {
-    const int nq = min(SPREAD_NT, cnt - q0);
+  for (int q0 = 0; q0 < cnt; q0 += SPREAD_STAGE) {
+    const int nq = min(SPREAD_STAGE, cnt - q0);
     if (tid < nq) {
       const int r = list[q0 + tid];
       int bb[3];
@@ -1902,7 +1910,8 @@ hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T
                          hipStream_t st) {
   if (a.nf > SPREAD_MAXROWS) return hipErrorInvalidValue;
   dim3 g((a.n - 1 + SPREAD_TX - 1) / SPREAD_TX, (jhi - jlo + 1 + SPREAD_TY - 1) / SPREAD_TY);
-  hipLaunchKernelGGL((k_spread<T>), g, dim3(SPREAD_NT), 0, st, a, jlo, jhi, ilo, ihi, out, po);
+  hipLaunchKernelGGL((k_spread<T>), g, dim3(SPREAD_NT), spread_lds_bytes(a.nf), st, a, jlo, jhi,
+                     ilo, ihi, out, po);
   return hipGetLastError();
 }
 hipError_t launch_point_source_rowdst(const OffRows& o, int col0, int ncols, int nslots,
@@ -2020,9 +2029,11 @@ hipError_t launch_finish_multi(const FsiArgs* tab, int count, hipStream_t st) {
 }
 template <typename T>
 hipError_t launch_spread_multi(const SpreadJob<T>* tab, int count, int max_gx, int max_gy,
-                               hipStream_t st) {
+                               int max_nf, hipStream_t st) {
   if (count <= 0 || max_gx <= 0 || max_gy <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_spread_multi<T>), dim3(max_gx, max_gy, count), dim3(SPREAD_NT), 0, st, tab);
+  if (max_nf > SPREAD_MAXROWS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_spread_multi<T>), dim3(max_gx, max_gy, count), dim3(SPREAD_NT),
+                     spread_lds_bytes(max_nf), st, tab);
   return hipGetLastError();
 }
 hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipStream_t st) {
@@ -2065,9 +2076,10 @@ hipError_t launch_gather_ctl(int* const* ctls, int count, int* out, hipStream_t 
 
 template hipError_t launch_body_ops_multi<float>(const FsiArgs*, int, int, int, hipStream_t);
 template hipError_t launch_body_ops_multi<double>(const FsiArgs*, int, int, int, hipStream_t);
-template hipError_t launch_spread_multi<float>(const SpreadJob<float>*, int, int, int, hipStream_t);
-template hipError_t launch_spread_multi<double>(const SpreadJob<double>*, int, int, int,
-                                                hipStream_t);
+template hipError_t launch_spread_multi<float>(const SpreadJob<float>*, int, int, int, int,
+                                                 hipStream_t);
+template hipError_t launch_spread_multi<double>(const SpreadJob<double>*, int, int, int, int,
+                                                 hipStream_t);
 template hipError_t launch_body_ops<float>(const FsiArgs&, hipStream_t);
 template hipError_t launch_body_ops<double>(const FsiArgs&, hipStream_t);
 template hipError_t launch_spread<float>(const FsiArgs&, int, int, int, int, float*, int, hipStream_t);

@@ -183,7 +183,7 @@ hipError_t launch_update_multi(const UpdateJob* tab, int count, int max_nb, int 
 hipError_t launch_finish_multi(const FsiArgs* tab, int count, hipStream_t st);
 template <typename T>
 hipError_t launch_spread_multi(const SpreadJob<T>* tab, int count, int max_gx, int max_gy,
-                               hipStream_t st);
+                               int max_nf, hipStream_t st);
 hipError_t launch_matvec_multi(const MatvecJob* tab, int count, int max_n, hipStream_t st);
 // Waves per workgroup of the FP64 product, each taking an equal share of the k range.
 constexpr int GEMM_KS = 8;

@@ -226,11 +226,16 @@ struct ib_solver {
   void* work = nullptr;   // spectral rows of s (then s-transform rows)
   void* workg = nullptr;  // the same for the circulation
   void* work2 = nullptr;
-  void* work_pre = nullptr;   // spectral scratch of the coarsest level launched ahead
+  void* work_pre = nullptr;   // spectral scratch of the levels launched ahead
   void* workg_pre = nullptr;
+  void* lift_pre = nullptr;   // edge transforms of the rings of the levels launched ahead
   bool top_ahead = false;     // the next step's coarsest level is already on the stream
-  bool top_ahead_ok = true;   // IB_OPT_TOP_AHEAD
+  int ahead_mode = 2;         // IB_OPT_TOP_AHEAD: 0 off, 1 coarsest level, 2 side stream
   hipEvent_t ctl_ready = nullptr;  // this step's control block is on the host
+  hipStream_t side = nullptr;      // the next step's levels >= 2 (ahead_mode 2)
+  hipEvent_t l1_done = nullptr;    // level 1's state of this step is final (on `stream`)
+  hipEvent_t side_done = nullptr;  // the levels launched on `side` are done
+  bool side_ahead = false;         // this step's levels >= 2 were launched on `side`
   void* lift = nullptr;   // edge transforms of a new streamfunction ring, [4][n-1]
   void* sstar = nullptr;
   void* tw = nullptr;
@@ -1565,14 +1570,65 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
   return IB_OK;
 }
 
-// A step's levels from gtop (the coarsest, G - 1, unless it was launched ahead) to 0.
+// The next step's levels G-1 .. 2 on the side stream, after this step's level 1 (l1_done,
+// recorded on the solver's stream).  With three or more levels they read only their own states,
+// the next finer level's circulation (coarsification on read) and rings made from the
+// next coarser level, all final once this step's level 1 is: level 1 is never corrected, and
+// nothing of this step after level 1 reads a level >= 2.  So they run concurrently with
+// this step's level 0, FSI part and corrector, with spectral scratch and ring transforms of
+// their own, and give the same results bit for bit.  Their ring parity is the next step's
+// (the end of a step flips it).
 template <typename T>
-ib_status enqueue_step(ib_solver* s, bool ahead, int K, int gtop = -1) {
+ib_status launch_side_levels(ib_solver* s) {
   const int G = (int)s->lv.size();
-  for (int g = gtop < 0 ? G - 1 : gtop; g >= 0; --g) {
+  HIPCHK(hipStreamWaitEvent(s->side, s->l1_done, 0));
+  struct Swap {
+    ib_solver* s;
+    hipStream_t stream;
+    void* lift;
+    Swap(ib_solver* s_) : s(s_), stream(s_->stream), lift(s_->lift) {
+      s->stream = s->side;
+      s->lift = s->lift_pre;
+      for (int g = 2; g < (int)s->lv.size() - 1; ++g) s->lv[g].gcur ^= 1;
+    }
+    ~Swap() {
+      s->stream = stream;
+      s->lift = lift;
+      for (int g = 2; g < (int)s->lv.size() - 1; ++g) s->lv[g].gcur ^= 1;
+    }
+  };
+  {
+    Swap sw(s);
+    for (int g = G - 1; g >= 2; --g) {
+      ib_status st = enqueue_level<T>(s, g, false, 0, false, s->work_pre, s->workg_pre);
+      if (st) return st;
+    }
+  }
+  HIPCHK(hipEventRecord(s->side_done, s->side));
+  s->side_ahead = true;
+  return IB_OK;
+}
+
+// A step's levels from gtop (the coarsest, G - 1, unless it was launched ahead) to 0; with
+// side_next, the next step's levels >= 2 go to the side stream, waiting there for this
+// step's level 1.  They are enqueued after level 0 and the FSI part, so that the host has
+// queued this step's long dependent chain first and the side stream's kernels run beside it.
+template <typename T>
+ib_status enqueue_step(ib_solver* s, bool ahead, int K, int gtop = -1, bool side_next = false) {
+  const int G = (int)s->lv.size();
+  int g0 = gtop < 0 ? G - 1 : gtop;
+  if (s->side_ahead) {
+    // levels G-1 .. 2 of this step ran on the side stream
+    HIPCHK(hipStreamWaitEvent(s->stream, s->side_done, 0));
+    s->side_ahead = false;
+    g0 = 1;
+  }
+  for (int g = g0; g >= 0; --g) {
     ib_status st = enqueue_level<T>(s, g, ahead, K, s->first, s->work, s->workg);
     if (st) return st;
+    if (g == 1 && side_next) HIPCHK(hipEventRecord(s->l1_done, s->stream));
   }
+  if (side_next) return launch_side_levels<T>(s);
   return IB_OK;
 }
 
@@ -1682,7 +1738,13 @@ ib_status record_step(ib_solver* s, const StepPlan& p) {
 // of its own, so nothing the host may still add to this step touches it.
 bool can_launch_top_ahead(const ib_solver* s) {
   return s->lv.size() >= 3 && s->work_pre != nullptr && !s->gemm && !s->timing && !s->graphs &&
-         s->top_ahead_ok;
+         s->ahead_mode == 1;
+}
+
+// Whether the next step's levels >= 2 can run on the side stream (launch_side_levels).
+bool can_launch_side(const ib_solver* s) {
+  return s->lv.size() >= 3 && s->work_pre != nullptr && s->lift_pre != nullptr &&
+         s->side != nullptr && !s->gemm && !s->timing && !s->graphs && s->ahead_mode == 2;
 }
 
 // pre_next: the caller takes another step right after this one (its coarsest level may be
@@ -1700,7 +1762,8 @@ ib_status do_step(ib_solver* s, const StepPlan& p, bool pre_next = false) {
     HIPCHK(hipGraphLaunch(sg->exec, s->stream));
     s->graph_launches++;
   } else {
-    st = enqueue_step<T>(s, p.ahead, p.K, s->top_ahead ? G - 2 : -1);
+    st = enqueue_step<T>(s, p.ahead, p.K, s->top_ahead ? G - 2 : -1,
+                         pre_next && can_launch_side(s));
     if (st) return st;
   }
   s->top_ahead = false;
@@ -1793,12 +1856,18 @@ ib_status alloc_state(ib_solver* s) {
   s->work = dalloc(s, inner);
   s->workg = dalloc(s, inner);
   s->work2 = dalloc(s, inner);
-  s->work_pre = s->workg_pre = nullptr;
-  s->top_ahead = false;
+  s->work_pre = s->workg_pre = s->lift_pre = nullptr;
+  s->top_ahead = s->side_ahead = false;
   if (s->lv.size() >= 3 && !s->gemm) {
     s->work_pre = dalloc(s, inner);
     s->workg_pre = dalloc(s, inner);
-    if (!s->work_pre || !s->workg_pre) return IB_ERR_OOM;
+    s->lift_pre = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
+    if (!s->work_pre || !s->workg_pre || !s->lift_pre) return IB_ERR_OOM;
+    if (!s->side) {
+      HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&s->l1_done, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&s->side_done, hipEventDisableTiming));
+    }
   }
   s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
   s->sstar = dalloc(s, full);
@@ -2225,8 +2294,9 @@ ib_status batch_step(ib_batch* b) {
   {
     // corrector source on level 0 (eqs. (20), (40)) for every member with bodies
     std::vector<SpreadJob<T>> sp;
-    int gx = 0, gy = 0;
+    int gx = 0, gy = 0, mnf = 0;
     for (ib_solver* s : bodied) {
+      mnf = std::max(mnf, s->nf);
       if (s->nf > SPREAD_ROWS_MAX) {
         b->last_error = "too many body rows for the spread";
         return IB_ERR_ARG;
@@ -2238,7 +2308,7 @@ ib_status batch_step(ib_batch* b) {
       gx = std::max(gx, (s->n - 1 + SPREAD_TILE_X - 1) / SPREAD_TILE_X);
       gy = std::max(gy, (s->bhi - s->blo + 1 + SPREAD_TILE_Y - 1) / SPREAD_TILE_Y);
     }
-    pl.add(sp, [=](const SpreadJob<T>* d, int c) { return launch_spread_multi<T>(d, c, gx, gy, st); });
+    pl.add(sp, [=](const SpreadJob<T>* d, int c) { return launch_spread_multi<T>(d, c, gx, gy, mnf, st); });
   }
   for (auto& q : groups) {
     std::vector<RowArgs<T>> rows;
@@ -2715,6 +2785,11 @@ ib_status ib_step(ib_solver* s, int32_t nsteps) {
     }
     if (st) {
       s->failed = true;
+      if (s->side_ahead) {
+        // levels launched for a step that will not run: let them finish
+        (void)hipStreamSynchronize(s->side);
+        s->side_ahead = false;
+      }
       return st;
     }
   }
@@ -2936,8 +3011,8 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
 
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
   HipShared hip_lock;
-  if (check(s) || value < 0 || value > (option == IB_OPT_REFRESH_EVERY_ITER ? 2 : 1))
-    return IB_ERR_ARG;
+  const int vmax = option == IB_OPT_REFRESH_EVERY_ITER || option == IB_OPT_TOP_AHEAD ? 2 : 1;
+  if (check(s) || value < 0 || value > vmax) return IB_ERR_ARG;
   if (option == IB_OPT_FSI_AHEAD) {
     s->fsi_ahead = value != 0;
     destroy_graphs(s);
@@ -2954,7 +3029,7 @@ ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
     return IB_OK;
   }
   if (option == IB_OPT_TOP_AHEAD) {
-    s->top_ahead_ok = value != 0;
+    s->ahead_mode = (int)value;
     return IB_OK;
   }
   return IB_ERR_ARG;
@@ -3042,6 +3117,7 @@ ib_status ib_release(ib_solver* s) {
   if (s->released) return IB_OK;
   if (s->allocated) {
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->side) HIPCHK(hipStreamSynchronize(s->side));
     destroy_graphs(s);
     if (s->prepared && s->f) {
       s->h_f.resize(s->nf);
@@ -3073,6 +3149,8 @@ ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak
   const size_t full = (size_t)(n + 1) * P * es, inner = (size_t)(n - 1) * P * es;
   size_t r = (size_t)G * (full + 2 * inner + 3 * 4 * (n + 1) * es);
   r += 3 * inner + full + 4 * (size_t)(n - 1) * es + 2 * (size_t)2 * n * (8 + es);
+  // scratch of the levels launched ahead (three or more levels)
+  if (G >= 3 && !s->gemm) r += 2 * inner + 4 * (size_t)(n - 1) * es;
   if (s->gemm) {
     // split sine matrix (two BF16 copies of kpad^2) and two FP32 product buffers
     const size_t kp = (size_t)(n - 1 + 63) / 64 * 64;
@@ -3185,6 +3263,7 @@ ib_status ib_destroy(ib_solver* s) {
   HipShared hip_lock;
   if (!s) return IB_ERR_ARG;
   if (s->allocated) (void)hipStreamSynchronize(s->stream);
+  if (s->side) (void)hipStreamSynchronize(s->side);
   destroy_graphs(s);
   harvest_events(s);
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
@@ -3193,6 +3272,9 @@ ib_status ib_destroy(ib_solver* s) {
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->hpose) (void)hipHostFree(s->hpose);
   if (s->ctl_ready) (void)hipEventDestroy(s->ctl_ready);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  if (s->l1_done) (void)hipEventDestroy(s->l1_done);
+  if (s->side_done) (void)hipEventDestroy(s->side_done);
   delete s;
   return IB_OK;
 }

@@ -245,19 +245,21 @@ def test_exact_operator_for_moving_bodies(torch_cuda, gpu_lib, which):
     assert ed < 1e-10
 
 
-@pytest.mark.parametrize("which", ["flag", "plate"])
-def test_fsi_ahead_and_graphs_give_the_same_results(torch_cuda, gpu_lib, which):
-    """FSI iterations launched ahead with device-side convergence tests (with and without
-    the next step's coarsest level launched while the host waits), and steps replayed from
+@pytest.mark.parametrize("which,levels", [("flag", 3), ("flag", 4), ("plate", 3), ("plate", 5)])
+def test_fsi_ahead_and_graphs_give_the_same_results(torch_cuda, gpu_lib, which, levels):
+    """FSI iterations launched ahead with device-side convergence tests, the next step's
+    levels launched early (the coarsest while the host waits, or every level >= 2 on a side
+    stream concurrently with this step's level 0 and FSI part), and steps replayed from
     recorded HIP graphs, reproduce the host-tested iteration bit for bit (same kernels, same
     arithmetic); the steps that needed more iterations than were launched ahead continue on
     the host."""
     from paper_2103_06415_amd import binding
     import torch
-    prob = (W.flag_problem(n=32, levels=3, steps=9) if which == "flag"
-            else W.plate_problem(n=32, levels=3, steps=9))
+    prob = (W.flag_problem(n=32, levels=levels, steps=9) if which == "flag"
+            else W.plate_problem(n=32, levels=levels, steps=9))
     runs = {}
-    modes = {"host": (0, 0, 1), "ahead": (1, 0, 1), "ahead_no_top": (1, 0, 0), "graph": (1, 1, 1)}
+    modes = {"host": (0, 0, 0), "host_side": (0, 0, 2), "ahead": (1, 0, 2),
+             "ahead_top": (1, 0, 1), "ahead_plain": (1, 0, 0), "graph": (1, 1, 2)}
     for mode, (ahead, graphs, top) in modes.items():
         print(f"{which} {mode}", flush=True)
         s = binding.Solver(prob, precision=binding.IB_FP64, stream=torch.cuda.Stream())
@@ -272,7 +274,7 @@ def test_fsi_ahead_and_graphs_give_the_same_results(torch_cuda, gpu_lib, which):
         print(f"  iters max {st['newton_iters_max']} graphs {st['graph_launches']} "
               f"captures {st['graph_captures']} resumes {st['fsi_resumes']}", flush=True)
         s.close()
-    for mode in ("ahead", "ahead_no_top", "graph"):
+    for mode in ("host_side", "ahead", "ahead_top", "ahead_plain", "graph"):
         for k in range(4):
             assert np.array_equal(runs[mode][k], runs["host"][k]), (mode, k)
     assert runs["host"][4]["graph_launches"] == 0
