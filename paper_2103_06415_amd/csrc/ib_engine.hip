@@ -1496,10 +1496,9 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
     const int nxt = 1 - L.gcur;
     if (has_ring) {
       TimeScope ts(s, IB_K_RING);
-      HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
-                            static_cast<T*>(L.gring[nxt]), s->stream));
-      HIPCHK(launch_ring_edge_dst<T>(static_cast<T*>(L.sring), n, s->tw, static_cast<T*>(s->lift),
-                                     s->stream));
+      HIPCHK(launch_ring_dst<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
+                                static_cast<T*>(L.gring[nxt]), s->tw, static_cast<T*>(s->lift),
+                                s->stream));
     }
     RhsArgs<T> a{};
     a.s = static_cast<T*>(L.s);

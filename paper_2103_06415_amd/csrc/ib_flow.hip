@@ -145,6 +145,16 @@ hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_ring_dst(const T* sc, int psc, int n, T* sring, T* gring, const void* tw, T* lift,
+                           hipStream_t st) {
+  const c2<T>* t = static_cast<const c2<T>*>(tw);
+#define L_(NN) hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(4), dim3(256), 0, st, sc, psc, sring, gring, t, lift)
+  IB_DISPATCH_N(n, L_)
+#undef L_
+  return hipGetLastError();
+}
+
 #define IB_INST(T)                                                                              \
   template hipError_t launch_rhs_rowdst<T>(const RhsArgs<T>&, const void*, hipStream_t, int); \
   template hipError_t launch_rowdst<T>(const RowArgs<T>&, int, int, const void*, hipStream_t); \
@@ -153,7 +163,8 @@ hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, 
   template hipError_t launch_row_idst<T>(const RowArgs<T>&, int, int, const void*, const T*, int, \
                                          hipStream_t);                                         \
   template hipError_t launch_ring<T>(const T*, int, int, T*, T*, hipStream_t);         \
-  template hipError_t launch_ring_edge_dst<T>(const T*, int, const void*, T*, hipStream_t);
+  template hipError_t launch_ring_edge_dst<T>(const T*, int, const void*, T*, hipStream_t);    \
+  template hipError_t launch_ring_dst<T>(const T*, int, int, T*, T*, const void*, T*, hipStream_t);
 IB_INST(float)
 IB_INST(double)
 #undef IB_INST

@@ -651,13 +651,11 @@ __device__ __forceinline__ T coarse_val(const T* sc, int p, int edge, int line, 
 }
 
 template <typename T>
-__device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc, int n, T* sring,
-                                          T* gring, int e) {
-  if (e >= 4 * (n + 1)) return;
+__device__ __forceinline__ void ring_values(const T* __restrict__ sc, int psc, int n, int e, T& sv,
+                                            T& gv) {
   const int edge = e / (n + 1), idx = e % (n + 1);
   const int q = n / 2;
   const int line = (edge == RING_B || edge == RING_L) ? n / 4 : (3 * n) / 4;
-  T sv, gv;
   if (((idx + q) & 1) == 0) {
     const int I = (idx + q) / 2;
     sv = coarse_val(sc, psc, edge, line, I, false);
@@ -673,8 +671,17 @@ __device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc, int
           T(9) * coarse_val(sc, psc, edge, line, c + 1, true) -
           coarse_val(sc, psc, edge, line, c + 2, true)) / T(16);
   }
+  gv = T(0.25) * gv;
+}
+
+template <typename T>
+__device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc, int n, T* sring,
+                                          T* gring, int e) {
+  if (e >= 4 * (n + 1)) return;
+  T sv, gv;
+  ring_values(sc, psc, n, e, sv, gv);
   sring[e] = sv;
-  gring[e] = T(0.25) * gv;
+  gring[e] = gv;
 }
 
 template <typename T>
@@ -736,6 +743,35 @@ __global__ __launch_bounds__(NT) void k_ring_edge_dst_multi(const RingJob<T>* __
                                                             const c2<T>* __restrict__ tw) {
   const RingJob<T> j = tab[blockIdx.y];
   ring_edge_dst_body<T, N, NT>(j.sring, tw, j.lift);
+}
+
+// k_ring and k_ring_edge_dst in one launch: workgroup `edge` makes that edge's ring values
+// (the same arithmetic as k_ring) and transforms its streamfunction part (the same
+// arithmetic as k_ring_edge_dst, one sequence per workgroup).
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int psc, T* sring,
+                                                 T* gring, const c2<T>* __restrict__ tw, T* lift) {
+  __shared__ c2<T> buf[fft_pad_len<N>()];
+  __shared__ c2<T> stw[TwLayout<N>::total];
+  const int tid = threadIdx.x, edge = blockIdx.x;
+  load_table<T, N, NT>(stw, tw, tid);
+  for (int idx = tid; idx <= N; idx += NT) {
+    const int e = edge * (N + 1) + idx;
+    T sv, gv;
+    ring_values(sc, psc, N, e, sv, gv);
+    sring[e] = sv;
+    gring[e] = gv;
+    if (idx >= 1 && idx <= N - 1) dst_pack<T, N>(buf, idx, sv);
+  }
+  if (tid == 0) dst_pack_zeros<T, N>(buf);
+  __syncthreads();
+  fft_lds<T, N, 1, NT>(buf, stw, tid);
+  for (int k = 1 + tid; k <= N / 2; k += NT) {
+    T xk, xnk;
+    dst_unpack<T, N>(buf, stw, k, xk, xnk);
+    lift[edge * (N - 1) + k - 1] = xk;
+    if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
+  }
 }
 
 // ------------------------------------------------ launches of one kernel configuration
