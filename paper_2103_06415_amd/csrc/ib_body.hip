@@ -1113,7 +1113,7 @@ constexpr int SPREAD_MAXROWS = SPREAD_ROWS_MAX;
 constexpr int SPREAD_STAGE = 64;
 
 size_t spread_lds_bytes(int nf) {
-  return (size_t)SPREAD_STAGE * (16 * 8 + 8 + 3 * 4) + (size_t)(nf + 1) / 2 * 8;
+  return (size_t)SPREAD_STAGE * (16 * 8 + 8 + 4 * 4) + (size_t)(nf + 1) / 2 * 8;
 }
 
 template <typename T>
@@ -1123,8 +1123,8 @@ __device__ __forceinline__ void spread_body(const FsiArgs& a, int jlo, int jhi, 
   extern __shared__ double spl[];
   double (*sw)[16] = reinterpret_cast<double (*)[16]>(spl);  // [SPREAD_STAGE][16]
   double* sc = spl + SPREAD_STAGE * 16;                        // [SPREAD_STAGE]
-  int (*sb)[3] = reinterpret_cast<int (*)[3]>(sc + SPREAD_STAGE);  // [SPREAD_STAGE][3]
-  int* list = &sb[SPREAD_STAGE][0];                            // [nf]
+  int4* sb = reinterpret_cast<int4*>(sc + SPREAD_STAGE);       // [SPREAD_STAGE]: base, comp
+  int* list = reinterpret_cast<int*>(sb + SPREAD_STAGE);       // [nf]
   __shared__ int wcount[NW];
   if (post_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1163,18 +1163,30 @@ __device__ __forceinline__ void spread_body(const FsiArgs& a, int jlo, int jhi, 
       for (int k = 0; k < 3; ++k) bb[k] = a.st_base[3 * r + k];
       for (int k = 0; k < 16; ++k) ww[k] = a.st_w[16 * r + k];
       const double coef = (row_ds(a, r) / a.h) * a.f[r];
-      for (int k = 0; k < 3; ++k) sb[tid][k] = bb[k];
+      sb[tid] = make_int4(bb[0], bb[1], bb[2], 0);
       for (int k = 0; k < 16; ++k) sw[tid][k] = ww[k];
       sc[tid] = coef;
     }
     __syncthreads();
     if (i >= ilo && i <= ihi && i <= a.n - 1 && j <= jhi) {
+      // first the staged rows whose window reaches this vertex, as a bit mask (no branch per
+      // row, so the LDS reads of many rows are in flight together), then those rows in
+      // staging order
+      unsigned long long hit = 0;
+#pragma unroll 16
       for (int q = 0; q < nq; ++q) {
-        const int di = i - sb[q][0], dj = j - sb[q][1];
-        if (di < 0 || di > 4 || dj < 0 || dj > 4) continue;
+        const int4 bq = sb[q];
+        const unsigned di = (unsigned)(i - bq.x), dj = (unsigned)(j - bq.y);
+        hit |= (unsigned long long)(di <= 4u && dj <= 4u) << q;
+      }
+      while (hit != 0) {
+        const int q = __builtin_ctzll(hit);
+        hit &= hit - 1;
+        const int4 bq = sb[q];
+        const int di = i - bq.x, dj = j - bq.y;
         const double* w = sw[q];
         double c = 0.0;
-        if (sb[q][2] == 0) {
+        if (bq.z == 0) {
           // x-faces [j][i] (-) and [j-1][i] (+)
           if (di < 4 && dj < 4) c -= w[dj * 4 + di];
           if (di < 4 && dj >= 1) c += w[(dj - 1) * 4 + di];
