@@ -236,6 +236,7 @@ struct ib_solver {
   hipEvent_t l1_done = nullptr;    // level 1's state of this step is final (on `stream`)
   hipEvent_t side_done = nullptr;  // the levels launched on `side` are done
   bool side_ahead = false;         // this step's levels >= 2 were launched on `side`
+  bool ctl_early = false;          // copy the control block right after the FSI iterations
   void* lift = nullptr;   // edge transforms of a new streamfunction ring, [4][n-1]
   void* sstar = nullptr;
   void* tw = nullptr;
@@ -1549,6 +1550,12 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
       if (ahead) {
         st = fsi_launch_ahead<T>(s, K);
         gate = s->gate;
+        if (!st && s->ctl_early) {
+          // the control block is final after the iterations: the host can read it and
+          // queue the next step while the (gated) corrector still runs
+          HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
+          HIPCHK(hipEventRecord(s->ctl_ready, s->stream));
+        }
       } else {
         st = fsi_host<T>(s, 0);
       }
@@ -1761,22 +1768,33 @@ ib_status do_step(ib_solver* s, const StepPlan& p, bool pre_next = false) {
     HIPCHK(hipGraphLaunch(sg->exec, s->stream));
     s->graph_launches++;
   } else {
+    // without the coarsest level launched during the host wait (IB_OPT_TOP_AHEAD = 1), the
+    // control block is copied as soon as the FSI iterations are queued
+    s->ctl_early = p.ahead && s->ahead_mode != 1;
+    if (s->ctl_early && !s->ctl_ready)
+      HIPCHK(hipEventCreateWithFlags(&s->ctl_ready, hipEventDisableTiming));
     st = enqueue_step<T>(s, p.ahead, p.K, s->top_ahead ? G - 2 : -1,
                          pre_next && can_launch_side(s));
+    s->ctl_early = false;
     if (st) return st;
   }
   s->top_ahead = false;
   if (p.ahead) {
-    HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
-    if (pre_next && can_launch_top_ahead(s) && !sg) {
-      if (!s->ctl_ready) HIPCHK(hipEventCreateWithFlags(&s->ctl_ready, hipEventDisableTiming));
-      HIPCHK(hipEventRecord(s->ctl_ready, s->stream));
-      st = enqueue_level<T>(s, G - 1, false, 0, false, s->work_pre, s->workg_pre);
-      if (st) return st;
-      s->top_ahead = true;
+    if (!sg && s->ahead_mode != 1) {
+      // copied right after the iterations (enqueue_level); the corrector may still run
       HIPCHK(hipEventSynchronize(s->ctl_ready));
     } else {
-      HIPCHK(hipStreamSynchronize(s->stream));
+      HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
+      if (pre_next && can_launch_top_ahead(s) && !sg) {
+        if (!s->ctl_ready) HIPCHK(hipEventCreateWithFlags(&s->ctl_ready, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(s->ctl_ready, s->stream));
+        st = enqueue_level<T>(s, G - 1, false, 0, false, s->work_pre, s->workg_pre);
+        if (st) return st;
+        s->top_ahead = true;
+        HIPCHK(hipEventSynchronize(s->ctl_ready));
+      } else {
+        HIPCHK(hipStreamSynchronize(s->stream));
+      }
     }
     int resume = -1;
     st = fsi_after_ahead(s, &resume);

@@ -282,6 +282,33 @@ def test_fsi_ahead_and_graphs_give_the_same_results(torch_cuda, gpu_lib, which, 
     assert runs["graph"][4]["graph_launches"] >= 5
 
 
+def test_steps_that_resume_on_the_host_give_the_same_results(torch_cuda, gpu_lib):
+    """Steps whose launched-ahead iterations do not suffice (they continue on the host) with
+    the control block read while the gated corrector is still queued, and with the next
+    step's coarse levels on the side stream: bit for bit the host-tested stepping."""
+    from paper_2103_06415_amd import binding
+    import torch
+    prob = W.flag_problem(n=64, levels=3, steps=12)
+    runs = {}
+    for mode, (ahead, top) in {"host": (0, 0), "ahead_side": (1, 2), "ahead_top": (1, 1),
+                               "ahead_plain": (1, 0)}.items():
+        s = binding.Solver(prob, precision=binding.IB_FP32_FLOW, stream=torch.cuda.Stream())
+        s.set_option(binding.IB_OPT_FSI_AHEAD, ahead)
+        s.set_option(binding.IB_OPT_TOP_AHEAD, top)
+        s.prepare()
+        s.step(12)
+        s.sync()
+        st = s.stats()
+        print(f"  {mode}: resumes {st['fsi_resumes']} iters max {st['newton_iters_max']}", flush=True)
+        runs[mode] = (s.vorticity(0), s.vorticity(1), s.vorticity(2), s.stresses(0),
+                      s.deflection(0), st["fsi_resumes"])
+        s.close()
+    for mode in ("ahead_side", "ahead_top", "ahead_plain"):
+        assert runs[mode][5] >= 1, mode  # the case this test is for
+        for k in range(5):
+            assert np.array_equal(runs[mode][k], runs["host"][k]), (mode, k)
+
+
 @pytest.mark.parametrize("mode", ["subdomain", "exact"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_driven_plate_matches_oracle(torch_cuda, gpu_lib, mode, prec):
