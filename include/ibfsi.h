@@ -252,7 +252,9 @@ ib_status ib_destroy(ib_solver* s);
  *   solver as soon as this step's level 1 is done, concurrently with this step's level 0,
  *   FSI part and corrector.  0: off.  Those levels need only states that are final once
  *   this step's level 1 is (level 1 is never corrected), so the results are the same bit
- *   for bit.  Not used with IB_OPT_GRAPHS, IB_FP32_FLOW_BF16_DST or kernel timing.
+ *   for bit.  Used only while no other solver of the process is inside ib_step (several
+ *   solvers stepping at once fill the GPU without it), and not with IB_OPT_GRAPHS,
+ *   IB_FP32_FLOW_BF16_DST or kernel timing.
  * Errors: IB_ERR_ARG for an unknown option or value. */
 #define IB_OPT_FSI_AHEAD 1
 #define IB_OPT_GRAPHS 2

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -197,6 +198,12 @@ std::shared_lock<std::shared_mutex> ib::hip_shared_lock() {
 struct HipShared {
   std::shared_lock<std::shared_mutex> l{g_hip_mu};
 };
+
+// Solvers of the process inside ib_step right now.  The next step's levels are launched
+// early (side stream or during the host wait) only while a solver steps alone: several
+// solvers stepping at once already fill the GPU, and the extra stream's event waits then
+// hold up the other solvers' work on the runtime's few hardware queues.
+static std::atomic<int> g_stepping{0};
 
 // A recorded step: its executable graph and the number of FSI iterations it launches ahead.
 struct StepGraph {
@@ -1632,7 +1639,16 @@ ib_status enqueue_step(ib_solver* s, bool ahead, int K, int gtop = -1, bool side
   for (int g = g0; g >= 0; --g) {
     ib_status st = enqueue_level<T>(s, g, ahead, K, s->first, s->work, s->workg);
     if (st) return st;
-    if (g == 1 && side_next) HIPCHK(hipEventRecord(s->l1_done, s->stream));
+    if (g == 1 && side_next) {
+      if (!s->side) {
+        // created at first use: solvers that never step alone add no stream (the runtime
+        // maps every stream of the process onto a few hardware queues)
+        HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&s->l1_done, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&s->side_done, hipEventDisableTiming));
+      }
+      HIPCHK(hipEventRecord(s->l1_done, s->stream));
+    }
   }
   if (side_next) return launch_side_levels<T>(s);
   return IB_OK;
@@ -1744,13 +1760,14 @@ ib_status record_step(ib_solver* s, const StepPlan& p) {
 // of its own, so nothing the host may still add to this step touches it.
 bool can_launch_top_ahead(const ib_solver* s) {
   return s->lv.size() >= 3 && s->work_pre != nullptr && !s->gemm && !s->timing && !s->graphs &&
-         s->ahead_mode == 1;
+         s->ahead_mode == 1 && g_stepping.load(std::memory_order_relaxed) == 1;
 }
 
 // Whether the next step's levels >= 2 can run on the side stream (launch_side_levels).
 bool can_launch_side(const ib_solver* s) {
-  return s->lv.size() >= 3 && s->work_pre != nullptr && s->lift_pre != nullptr &&
-         s->side != nullptr && !s->gemm && !s->timing && !s->graphs && s->ahead_mode == 2;
+  return s->lv.size() >= 3 && s->work_pre != nullptr && s->lift_pre != nullptr && !s->gemm &&
+         !s->timing && !s->graphs && s->ahead_mode == 2 &&
+         g_stepping.load(std::memory_order_relaxed) == 1;
 }
 
 // pre_next: the caller takes another step right after this one (its coarsest level may be
@@ -1880,11 +1897,6 @@ ib_status alloc_state(ib_solver* s) {
     s->workg_pre = dalloc(s, inner);
     s->lift_pre = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
     if (!s->work_pre || !s->workg_pre || !s->lift_pre) return IB_ERR_OOM;
-    if (!s->side) {
-      HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&s->l1_done, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&s->side_done, hipEventDisableTiming));
-    }
   }
   s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
   s->sstar = dalloc(s, full);
@@ -2786,6 +2798,10 @@ ib_status ib_prepare(ib_solver* s) {
 ib_status ib_step(ib_solver* s, int32_t nsteps) {
   if (check(s) || nsteps < 0) return IB_ERR_ARG;
   if (!s->prepared || s->failed || s->released) return IB_ERR_STATE;
+  struct Stepping {
+    Stepping() { g_stepping.fetch_add(1, std::memory_order_relaxed); }
+    ~Stepping() { g_stepping.fetch_sub(1, std::memory_order_relaxed); }
+  } stepping;
   for (int k = 0; k < nsteps; ++k) {
     const StepPlan p = plan_step(s);
     ib_status st = IB_OK;
