@@ -791,6 +791,26 @@ __global__ __launch_bounds__(BEAM_NT) void k_ops_beam(FsiArgs a, int bi, int nbe
   else body_ops_body<T>(a, blockIdx.x - nbeam);
 }
 
+// Many instances (ib_batch_*): rows y < nbeam of the grid solve beam job y's right-hand
+// sides, the others take BEAM_NT body points each of instance y - nbeam (k_ops_beam's split).
+template <typename T>
+__global__ __launch_bounds__(BEAM_NT) void k_ops_beam_multi(const FsiArgs* __restrict__ fa, int ni,
+                                                            const BeamJob* __restrict__ beams,
+                                                            int nbeam, int it) {
+  (void)ni;
+  if ((int)blockIdx.y < nbeam) {
+    const BeamJob& j = beams[blockIdx.y];
+    if ((int)blockIdx.x >= (2 * j.m + 1 + BEAM_NC - 1) / BEAM_NC) return;
+    FsiArgs a = j.a;
+    a.iter = it;
+    beam_body(a, j.bi, blockIdx.x);
+  } else {
+    FsiArgs a = fa[blockIdx.y - nbeam];
+    a.iter = it;
+    body_ops_body<T>(a, blockIdx.x);
+  }
+}
+
 // LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K); the
 // element scratch (42 (m-1)) overlays A^{-1} .. rhs, which is large enough for NC >= 5
 size_t beam_lds_bytes(int m) {
@@ -2028,6 +2048,20 @@ hipError_t launch_beam_multi(const BeamJob* tab, int count, int max_m, size_t ld
                      st, tab, it);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_ops_beam_multi(const FsiArgs* fa, int ni, int max_npts, const BeamJob* beams,
+                                 int nbeam, int max_m, size_t lds, int it, hipStream_t st) {
+  if (ni <= 0) return hipSuccess;
+  if (max_m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
+  const int gx = std::max((2 * max_m + 1 + BEAM_NC - 1) / BEAM_NC, (max_npts + BEAM_NT - 1) / BEAM_NT);
+  hipLaunchKernelGGL((k_ops_beam_multi<T>), dim3(gx, nbeam + ni), dim3(BEAM_NT), lds, st, fa, ni,
+                     beams, nbeam, it);
+  return hipGetLastError();
+}
+template hipError_t launch_ops_beam_multi<float>(const FsiArgs*, int, int, const BeamJob*, int, int,
+                                                 size_t, int, hipStream_t);
+template hipError_t launch_ops_beam_multi<double>(const FsiArgs*, int, int, const BeamJob*, int, int,
+                                                  size_t, int, hipStream_t);
 hipError_t launch_update_multi(const UpdateJob* tab, int count, int max_nb, int it, int K,
                                hipStream_t st) {
   if (count <= 0) return hipSuccess;

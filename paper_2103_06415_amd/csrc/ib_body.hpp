@@ -176,6 +176,10 @@ hipError_t launch_body_ops_multi(const FsiArgs* tab, int count, int max_npts, in
                                  hipStream_t st);
 hipError_t launch_schur_sd_multi(const FsiArgs* tab, int count, int max_nf, size_t lds, int it,
                                  hipStream_t st);
+// launch_body_ops_multi and launch_beam_multi (nbeam >= 1 jobs) in one launch.
+template <typename T>
+hipError_t launch_ops_beam_multi(const FsiArgs* fa, int ni, int max_npts, const BeamJob* beams,
+                                 int nbeam, int max_m, size_t lds, int it, hipStream_t st);
 hipError_t launch_beam_multi(const BeamJob* tab, int count, int max_m, size_t lds, int it,
                              hipStream_t st);
 hipError_t launch_update_multi(const UpdateJob* tab, int count, int max_nb, int it, int K,

@@ -2251,14 +2251,16 @@ ib_status batch_step(ib_batch* b) {
     const size_t upd_off = pl.put(upd);
     const int ni = (int)iter.size(), nbeam = (int)beams.size();
     for (int it = 0; it < K; ++it) {
-      pl.launches.push_back([=](const char* d) {
-        return launch_body_ops_multi<T>(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, max_pts,
-                                        it, st);
-      });
       if (nbeam)
         pl.launches.push_back([=](const char* d) {
-          return launch_beam_multi(reinterpret_cast<const BeamJob*>(d + beam_off), nbeam, max_m,
-                                   beam_lds_max, it, st);
+          return launch_ops_beam_multi<T>(reinterpret_cast<const FsiArgs*>(d + fa_off), ni,
+                                          max_pts, reinterpret_cast<const BeamJob*>(d + beam_off),
+                                          nbeam, max_m, beam_lds_max, it, st);
+        });
+      else
+        pl.launches.push_back([=](const char* d) {
+          return launch_body_ops_multi<T>(reinterpret_cast<const FsiArgs*>(d + fa_off), ni,
+                                          max_pts, it, st);
         });
       pl.launches.push_back([=](const char* d) {
         return launch_schur_sd_multi(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, max_nf,

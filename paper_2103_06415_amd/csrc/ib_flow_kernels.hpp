@@ -749,11 +749,11 @@ __global__ __launch_bounds__(NT) void k_ring_edge_dst_multi(const RingJob<T>* __
 // (the same arithmetic as k_ring) and transforms its streamfunction part (the same
 // arithmetic as k_ring_edge_dst, one sequence per workgroup).
 template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int psc, T* sring,
-                                                 T* gring, const c2<T>* __restrict__ tw, T* lift) {
+__device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc, T* sring, T* gring,
+                                              const c2<T>* __restrict__ tw, T* lift, int edge) {
   __shared__ c2<T> buf[fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
-  const int tid = threadIdx.x, edge = blockIdx.x;
+  const int tid = threadIdx.x;
   load_table<T, N, NT>(stw, tw, tid);
   for (int idx = tid; idx <= N; idx += NT) {
     const int e = edge * (N + 1) + idx;
@@ -772,6 +772,20 @@ __global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int p
     lift[edge * (N - 1) + k - 1] = xk;
     if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
   }
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int psc, T* sring,
+                                                 T* gring, const c2<T>* __restrict__ tw, T* lift) {
+  ring_dst_body<T, N, NT>(sc, psc, sring, gring, tw, lift, blockIdx.x);
+}
+
+// Many instances of one grid size: workgroup (edge, instance blockIdx.y).
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_ring_dst_multi(const RingJob<T>* __restrict__ tab,
+                                                       const c2<T>* __restrict__ tw) {
+  const RingJob<T> j = tab[blockIdx.y];
+  ring_dst_body<T, N, NT>(j.sc, j.psc, j.sring, j.gring, tw, j.lift, blockIdx.x);
 }
 
 // ------------------------------------------------ launches of one kernel configuration

@@ -108,13 +108,9 @@ template <typename T>
 hipError_t launch_ring_multi(const RingJob<T>* tab, int count, int n, const void* tw,
                              hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  const int tot = 4 * (n + 1);
-  hipLaunchKernelGGL((k_ring_multi<T>), dim3((tot + 255) / 256, count), dim3(256), 0, st, tab, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
 #define L_(NN) \
-  hipLaunchKernelGGL((k_ring_edge_dst_multi<T, NN, 256>), dim3(1, count), dim3(256), 0, st, tab, t)
+  hipLaunchKernelGGL((k_ring_dst_multi<T, NN, 256>), dim3(4, count), dim3(256), 0, st, tab, t)
   IB_MULTI_N(n, L_)
 #undef L_
   return hipGetLastError();
