@@ -689,11 +689,6 @@ __global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gr
   ring_body(sc, psc, n, sring, gring, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-template <typename T>
-__global__ void k_ring_multi(const RingJob<T>* __restrict__ tab, int n) {
-  const RingJob<T> j = tab[blockIdx.y];
-  ring_body(j.sc, j.psc, n, j.sring, j.gring, blockIdx.x * blockDim.x + threadIdx.x);
-}
 
 // Unnormalised 1-D DSTs of the four edges of a streamfunction ring, as they appear in
 // B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top s(i, n) on row
@@ -736,13 +731,6 @@ template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
                                                       const c2<T>* __restrict__ tw, T* lift) {
   ring_edge_dst_body<T, N, NT>(sring, tw, lift);
-}
-
-template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_ring_edge_dst_multi(const RingJob<T>* __restrict__ tab,
-                                                            const c2<T>* __restrict__ tw) {
-  const RingJob<T> j = tab[blockIdx.y];
-  ring_edge_dst_body<T, N, NT>(j.sring, tw, j.lift);
 }
 
 // k_ring and k_ring_edge_dst in one launch: workgroup `edge` makes that edge's ring values
