@@ -211,7 +211,9 @@ ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64
 ib_status ib_get_stats(ib_solver* s, ib_stats* out);
 
 /* Kernel timing for measurement: while enabled, every launch of the classes below is
- * bracketed by HIP events on the solver's stream (adds a few microseconds per launch).
+ * bracketed by HIP events on the solver's stream (adds a few microseconds per launch);
+ * column-solve launches (IB_K_COL_SOLVE) record their events at the kernel's own start and
+ * end (hipExtLaunchKernelGGL), so that class's time excludes the dispatch.
  * ib_get_kernel_timing synchronises and returns the launches and the summed kernel
  * time (milliseconds) of one class since timing was last enabled. */
 #define IB_K_RHS_ROWDST 0   /* explicit right-hand side + row sine transform */

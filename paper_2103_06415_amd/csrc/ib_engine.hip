@@ -386,8 +386,11 @@ ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
 template <typename T>
 ib_status solve_into(ib_solver* s, void* work, double alpha, double scale, int r0, int r1,
                      const void* tw, const void* lam, void* workg = nullptr,
-                     const void* lift = nullptr, int var = 0) {
+                     const void* lift = nullptr, int var = 0, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr) {
   ColArgs<T> c{};
+  c.ev0 = ev0;
+  c.ev1 = ev1;
   c.var = var;
   c.in = static_cast<T*>(work);
   c.out = static_cast<T*>(work);
@@ -535,15 +538,16 @@ struct TimeScope {
     (void)hipEventCreate(&v);
     return v;
   }
-  TimeScope(ib_solver* s_, int c) : s(s_), cls(c) {
+  bool ext = false;  // the scope's one launch records b and e itself (hipExtLaunchKernelGGL)
+  TimeScope(ib_solver* s_, int c, bool ext_ = false) : s(s_), cls(c), ext(ext_) {
     if (!s->timing) return;
     b = take();
     e = take();
-    (void)hipEventRecord(b, s->stream);
+    if (!ext) (void)hipEventRecord(b, s->stream);
   }
   ~TimeScope() {
     if (!s->timing || !b) return;
-    (void)hipEventRecord(e, s->stream);
+    if (!ext) (void)hipEventRecord(e, s->stream);
     s->events.push_back({b, e, cls});
   }
 };
@@ -1299,7 +1303,9 @@ ib_status corrector(ib_solver* s, const int* gate) {
   c.w1 = n - 1;
   c.var = s->tune.col;
   c.gate = gate;
-  TimeScope ts(s, IB_K_COL_SOLVE);
+  TimeScope ts(s, IB_K_COL_SOLVE, true);
+  c.ev0 = ts.b;
+  c.ev1 = ts.e;
   HIPCHK(launch_col_solve<T>(c, n, 1, s->tw, s->lam, s->stream));
   return IB_OK;
 }
@@ -1534,9 +1540,9 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
         TimeScope ts(s, IB_K_RHS_ROWDST);
         HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
       }
-      TimeScope ts(s, IB_K_COL_SOLVE);
+      TimeScope ts(s, IB_K_COL_SOLVE, true);
       st = solve_into<T>(s, work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
-                         workg, has_ring ? s->lift : nullptr, s->tune.col);
+                         workg, has_ring ? s->lift : nullptr, s->tune.col, ts.b, ts.e);
     }
     if (st) return st;
     RowArgs<T> r{};

@@ -101,7 +101,13 @@ hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* t
   const int nb = (n - 1 + CW - 1) / CW;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
   const T* l = static_cast<const T*>(lam);
-#define L_(NN) hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, l, nb)
+#define L_(NN)                                                                                     \
+  if (a.ev0)                                                                                       \
+    hipExtLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, \
+                          a.ev0, a.ev1, 0, a, t, l, nb);                                           \
+  else                                                                                             \
+    hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, \
+                       t, l, nb)
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();

@@ -15,6 +15,8 @@
 // so the circulation state never passes through the large streamfunction values
 // (differencing s would lose about log10((n/pi)^2) digits in single precision), and
 // B(s_ring)^ is a sum of four outer products of 1-D edge transforms.
+#include <hip/hip_ext.h>
+
 #include "ib_internal.hpp"
 #include "ib_fft.hpp"
 
@@ -790,8 +792,12 @@ template <typename T, int N, int CW, int NT, int MAXR>
 hipError_t launch_col_cfg(const ColArgs<T>& a, int n, int batch, const c2<T>* t, const T* l,
                           hipStream_t st) {
   const int nb = (n - 1 + CW - 1) / CW;
-  hipLaunchKernelGGL((k_col_solve<T, N, CW, NT, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st,
-                     a, t, l, nb);
+  if (a.ev0)
+    hipExtLaunchKernelGGL((k_col_solve<T, N, CW, NT, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT), 0,
+                          st, a.ev0, a.ev1, 0, a, t, l, nb);
+  else
+    hipLaunchKernelGGL((k_col_solve<T, N, CW, NT, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st,
+                       a, t, l, nb);
   return hipGetLastError();
 }
 

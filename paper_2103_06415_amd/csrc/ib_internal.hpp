@@ -57,6 +57,8 @@ struct ColArgs {
   int w0, w1;        // output rows written (1-based); others untouched
   int var;           // kernel configuration (COL_VARIANTS; 0 = default)
   const int* gate;   // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
+  hipEvent_t ev0, ev1;  // host side, if set (kernel timing): recorded at the kernel's start and
+                        //   end by the launch itself (hipExtLaunchKernelGGL), without its dispatch
 };
 
 // Per-instance entries of the flow launches that take many instances of one grid size
