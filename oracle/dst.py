@@ -6,31 +6,53 @@ solve used by the predictor (eq. (16)) and the corrector (eq. (20)) is
 
     (C^T A C)^{-1} r = dt * S2 diag(1 / (lam (1 + alpha lam))) S2 r,
 
-S2 = S (x) S the 2-D transform.  The oracle applies S as a dense orthonormal
-matrix (naive O(n^3) products, no FFT).
+S2 = S (x) S the 2-D transform.  In double precision the oracle applies S as a dense
+orthonormal matrix (naive O(n^3) products, no FFT).
+
+Extended precision (arrays of ``numpy.longdouble``, the x87 80-bit format with a 64-bit
+significand): every function here follows the dtype of its input.  The products with S are
+then done by a library primitive, the orthonormal type-I DST of ``scipy.fft`` (pocketfft,
+which computes in the input's precision), because a dense long-double product of size
+1023 takes about 12 s; it is pinned against the dense long-double S.
 """
 import numpy as np
+import scipy.fft
 
 
-def sine_matrix(n):
-    """Orthonormal DST-I of size n-1: S[j-1, k-1] = sqrt(2/n) sin(pi j k / n)."""
+PI_TEXT = "3.14159265358979323846264338327950288419716939937510"
+
+
+def _pi(dtype):
+    return np.pi if dtype == np.float64 else np.asarray(PI_TEXT, dtype=np.longdouble).astype(dtype)[()]
+
+
+def sine_matrix(n, dtype=np.float64):
+    """Orthonormal DST-I of size n-1: S[j-1, k-1] = sqrt(2/n) sin(pi j k / n).
+
+    The integer j k is first reduced modulo 2n (sin has period 2 pi), so that the rounding
+    of pi is not multiplied by j k / n, up to n, in the angle."""
     j = np.arange(1, n)
-    return np.sqrt(2.0 / n) * np.sin(np.pi * np.outer(j, j) / n)
+    two = np.asarray(2, dtype=dtype)
+    m = np.outer(j, j) % (2 * n)
+    return np.sqrt(two / n) * np.sin(_pi(dtype) * m.astype(dtype) / n)
 
 
-def eigenvalues_1d(n):
-    k = np.arange(1, n)
-    return 4.0 * np.sin(np.pi * k / (2.0 * n)) ** 2
+def eigenvalues_1d(n, dtype=np.float64):
+    k = np.arange(1, n).astype(dtype)
+    return 4 * np.sin(_pi(dtype) * k / (2 * n)) ** 2
 
 
-def eigenvalues(n):
+def eigenvalues(n, dtype=np.float64):
     """lam[l-1, k-1] = 4 sin^2(pi k / 2n) + 4 sin^2(pi l / 2n): eigenvalues of C^T C."""
-    lam = eigenvalues_1d(n)
+    lam = eigenvalues_1d(n, dtype)
     return lam[:, None] + lam[None, :]
 
 
 def dst2(x):
     """2-D orthonormal DST-I of an (n-1, n-1) array (self-inverse)."""
+    if x.dtype != np.float64:
+        return scipy.fft.dst(scipy.fft.dst(x, type=1, norm="ortho", axis=0), type=1, norm="ortho",
+                             axis=1)
     s = sine_matrix(x.shape[0] + 1)
     return s @ x @ s
 
@@ -41,13 +63,17 @@ def solve_cac(rhs, alpha):
     Multiply by dt for (C^T A C)^{-1}.
     """
     n = rhs.shape[0] + 1
+    lam = eigenvalues(n, rhs.dtype)
+    if rhs.dtype != np.float64:
+        return dst2(dst2(rhs) / (lam * (1 + alpha * lam)))
     s = sine_matrix(n)
-    lam = eigenvalues(n)
     return s @ ((s @ rhs @ s) / (lam * (1.0 + alpha * lam))) @ s
 
 
 def solve_poisson(rhs):
     """(C^T C)^{-1} rhs with homogeneous Dirichlet values."""
     n = rhs.shape[0] + 1
+    if rhs.dtype != np.float64:
+        return dst2(dst2(rhs) / eigenvalues(n, rhs.dtype))
     s = sine_matrix(n)
     return s @ ((s @ rhs @ s) / eigenvalues(n)) @ s

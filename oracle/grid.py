@@ -35,7 +35,7 @@ def pad(interior, ring=None):
     """(n+1, n+1) array from interior values and (optionally) a full array whose
     outer ring supplies the boundary values."""
     n = interior.shape[0] + 1
-    out = np.zeros((n + 1, n + 1)) if ring is None else ring.copy()
+    out = np.zeros((n + 1, n + 1), dtype=interior.dtype) if ring is None else ring.copy()
     out[1:-1, 1:-1] = interior
     return out
 

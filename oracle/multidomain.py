@@ -31,7 +31,7 @@ def ring_from_coarse(vc, n):
 
     Returns an (n+1, n+1) array holding only the fine ring.
     """
-    out = np.zeros((n + 1, n + 1))
+    out = np.zeros((n + 1, n + 1), dtype=vc.dtype)
     q = n // 2
 
     def along(line, i):

@@ -34,6 +34,12 @@ max |delta theta|, |delta chi| <= tol (both tests of Sec. 5 and Algorithm 2), at
 ``newton_max`` iterations, or run exactly ``fixed_iters`` iterations (parity mode).
 The corrector uses the interpolation operator of the last solve; the structure takes
 the last update.  AB2 starts with N_{-1} := N_0.
+
+Precision: float64 by default.  ``dtype=numpy.longdouble`` runs the flow part (problems
+without bodies) in extended precision, as a reference finer than double rounding: the
+double-precision oracle re-differences its streamfunction (C^T C s) for the circulation it
+hands between levels, which amplifies the rounding of s by up to (n/pi)^2 / 2, so at
+n >= 96 with nested levels its own s and vorticity carry errors of 1e-12 .. 1e-10.
 """
 import numpy as np
 
@@ -66,17 +72,20 @@ def moving_velocities(b, t):
 
 class Oracle:
     def __init__(self, problem, newton_tol=1e-7, newton_max=20, fixed_iters=0,
-                 drop_tol=0.007, subdomain_mode=None):
+                 drop_tol=0.007, subdomain_mode=None, dtype=np.float64):
         self.p = problem
         flow = problem.flow
         assert flow.n % 4 == 0
+        self.dtype = np.dtype(dtype)
+        if self.dtype != np.float64 and problem.bodies:
+            raise ValueError("extended precision covers the flow of problems without bodies")
         self.levels = [grid.Level(flow, g) for g in range(flow.levels)]
         n = flow.n
         self.n = n
         self.dt = flow.dt
-        self.s = [np.zeros((n + 1, n + 1)) for _ in self.levels]
+        self.s = [self._zeros((n + 1, n + 1)) for _ in self.levels]
         self.hist = [None for _ in self.levels]
-        self.gring = [np.zeros((n + 1, n + 1)) for _ in self.levels]
+        self.gring = [self._zeros((n + 1, n + 1)) for _ in self.levels]
         self.newton_tol = newton_tol
         self.newton_max = newton_max
         self.fixed_iters = fixed_iters
@@ -107,6 +116,9 @@ class Oracle:
             self.set_vorticity(problem.vorticity0)
         self.prepared = False
 
+    def _zeros(self, shape):
+        return np.zeros(shape, dtype=self.dtype)
+
     # ------------------------------------------------------------------ setup
     def set_vorticity(self, omegas):
         """Streamfunction on every level from interior vorticity, coarse to fine."""
@@ -114,13 +126,13 @@ class Oracle:
         for g in reversed(range(nl)):
             lv = self.levels[g]
             if g == nl - 1:
-                ring_s = np.zeros((self.n + 1, self.n + 1))
-                ring_g = np.zeros((self.n + 1, self.n + 1))
+                ring_s = self._zeros((self.n + 1, self.n + 1))
+                ring_g = self._zeros((self.n + 1, self.n + 1))
             else:
                 ring_s = md.ring_from_coarse(self.s[g + 1], self.n)
                 ring_g = 0.25 * md.ring_from_coarse(md.coarse_circulation(self.s[g + 1]), self.n)
-            om = omegas[g] if g < len(omegas) and omegas[g] is not None else np.zeros((self.n - 1,) * 2)
-            gam = lv.h * lv.h * om
+            om = omegas[g] if g < len(omegas) and omegas[g] is not None else self._zeros((self.n - 1,) * 2)
+            gam = lv.h * lv.h * np.asarray(om, dtype=self.dtype)
             bs = -grid.l5(grid.ring_only(ring_s))
             self.s[g] = grid.pad(dst.solve_poisson(gam + bs), ring_s)
             self.gring[g] = ring_g
@@ -233,8 +245,8 @@ class Oracle:
         for g in reversed(range(nl)):
             lv = self.levels[g]
             if g == nl - 1:
-                ring_s = np.zeros((n + 1, n + 1))
-                ring_g = np.zeros((n + 1, n + 1))
+                ring_s = self._zeros((n + 1, n + 1))
+                ring_g = self._zeros((n + 1, n + 1))
             else:
                 ring_s = md.ring_from_coarse(new_s[g + 1], n)
                 ring_g = 0.25 * md.ring_from_coarse(md.coarse_circulation(new_s[g + 1]), n)

@@ -415,8 +415,9 @@ ib_status init_streamfunction(ib_solver* s) {
   for (int g = G - 1; g >= 0; --g) {
     LevelState& L = s->lv[g];
     if (g < G - 1) {
-      HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
-                            static_cast<T*>(L.gring[L.gcur]), s->stream));
+      HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, static_cast<T*>(s->lv[g + 1].g), P,
+                            n, static_cast<T*>(L.sring), static_cast<T*>(L.gring[L.gcur]),
+                            s->stream));
     }
     std::fill(host.begin(), host.end(), T(0));
     if (g < (int)s->omega0.size() && !s->omega0[g].empty()) {
@@ -1510,7 +1511,8 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
     const int nxt = 1 - L.gcur;
     if (has_ring) {
       TimeScope ts(s, IB_K_RING);
-      HIPCHK(launch_ring_dst<T>(static_cast<T*>(s->lv[g + 1].s), P, n, static_cast<T*>(L.sring),
+      HIPCHK(launch_ring_dst<T>(static_cast<T*>(s->lv[g + 1].s), P,
+                                static_cast<T*>(s->lv[g + 1].g), P, n, static_cast<T*>(L.sring),
                                 static_cast<T*>(L.gring[nxt]), s->tw, static_cast<T*>(s->lift),
                                 s->stream));
     }
@@ -2128,6 +2130,7 @@ ib_status batch_step(ib_batch* b) {
         const int nxt = 1 - L.gcur;
         if (has_ring)
           rings.push_back(RingJob<T>{static_cast<const T*>(s->lv[g + 1].s), P,
+                                     static_cast<const T*>(s->lv[g + 1].g), P,
                                      static_cast<T*>(L.sring), static_cast<T*>(L.gring[nxt]),
                                      static_cast<T*>(s->lift)});
         RhsArgs<T> a{};

@@ -136,9 +136,11 @@ hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw
 }
 
 template <typename T>
-hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStream_t st) {
+hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
+                       hipStream_t st) {
   const int tot = 4 * (n + 1);
-  hipLaunchKernelGGL((k_ring<T>), dim3((tot + 255) / 256), dim3(256), 0, st, sc, psc, n, sring, gring);
+  hipLaunchKernelGGL((k_ring<T>), dim3((tot + 255) / 256), dim3(256), 0, st, sc, psc, gc, pgc, n,
+                     sring, gring);
   return hipGetLastError();
 }
 
@@ -152,10 +154,10 @@ hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, 
 }
 
 template <typename T>
-hipError_t launch_ring_dst(const T* sc, int psc, int n, T* sring, T* gring, const void* tw, T* lift,
-                           hipStream_t st) {
+hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
+                           const void* tw, T* lift, hipStream_t st) {
   const c2<T>* t = static_cast<const c2<T>*>(tw);
-#define L_(NN) hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(4), dim3(256), 0, st, sc, psc, sring, gring, t, lift)
+#define L_(NN) hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(4), dim3(256), 0, st, sc, psc, gc, pgc, sring, gring, t, lift)
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();
@@ -168,9 +170,10 @@ hipError_t launch_ring_dst(const T* sc, int psc, int n, T* sring, T* gring, cons
                                           hipStream_t);                                        \
   template hipError_t launch_row_idst<T>(const RowArgs<T>&, int, int, const void*, const T*, int, \
                                          hipStream_t);                                         \
-  template hipError_t launch_ring<T>(const T*, int, int, T*, T*, hipStream_t);         \
+  template hipError_t launch_ring<T>(const T*, int, const T*, int, int, T*, T*, hipStream_t);   \
   template hipError_t launch_ring_edge_dst<T>(const T*, int, const void*, T*, hipStream_t);    \
-  template hipError_t launch_ring_dst<T>(const T*, int, int, T*, T*, const void*, T*, hipStream_t);
+  template hipError_t launch_ring_dst<T>(const T*, int, const T*, int, int, T*, T*, const void*, T*, \
+                                         hipStream_t);
 IB_INST(float)
 IB_INST(double)
 #undef IB_INST

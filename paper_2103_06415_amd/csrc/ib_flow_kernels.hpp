@@ -639,56 +639,66 @@ __global__ __launch_bounds__(NT) void k_row_idst_multi(const IdstJob<T>* __restr
   row_idst_body<T, N, ROWS, NT, DUAL, MAXR>(j.a, tw, j.ring, j.ring_rows, nb, blockIdx.x, 0);
 }
 
-// New boundary rings of a fine level from the next coarser level's streamfunction:
-// coincident vertices are copied, midpoints use the cubic (-1, 9, 9, -1)/16 along the
-// edge; the circulation ring is the same interpolation of the coarse C^T C s, scaled
-// by 1/4 (gamma = h^2 omega and h halves).
+// New boundary rings of a fine level from the next coarser level's new state: coincident
+// vertices are copied, midpoints use the cubic (-1, 9, 9, -1)/16 along the edge.  The
+// streamfunction ring interpolates the coarse s; the circulation ring interpolates the
+// coarse level's circulation C^T C s, read from its carried state gc (interior vertex
+// (i, j) at gc[(j - 1) pgc + i - 1]; the ring only reads coarse vertices n/4 - 1 .. 3n/4 + 1,
+// all interior), scaled by 1/4 (gamma = h^2 omega and h halves).  Reading the carried
+// circulation instead of differencing s keeps the ring at the circulation's own relative
+// rounding (differencing amplifies the rounding of s by up to (n/pi)^2 / 2).
 template <typename T>
-__device__ __forceinline__ T coarse_val(const T* sc, int p, int edge, int line, int I, bool gam) {
+__device__ __forceinline__ T coarse_s(const T* sc, int p, int edge, int line, int I) {
   const int j = (edge < 2) ? line : I;
   const int i = (edge < 2) ? I : line;
-  if (!gam) return sc[(size_t)j * p + i];
-  return T(4) * sc[(size_t)j * p + i] - sc[(size_t)j * p + i + 1] - sc[(size_t)j * p + i - 1] -
-         sc[(size_t)(j + 1) * p + i] - sc[(size_t)(j - 1) * p + i];
+  return sc[(size_t)j * p + i];
 }
 
 template <typename T>
-__device__ __forceinline__ void ring_values(const T* __restrict__ sc, int psc, int n, int e, T& sv,
+__device__ __forceinline__ T coarse_g(const T* gc, int p, int edge, int line, int I) {
+  const int j = (edge < 2) ? line : I;
+  const int i = (edge < 2) ? I : line;
+  return gc[(size_t)(j - 1) * p + (i - 1)];
+}
+
+template <typename T>
+__device__ __forceinline__ void ring_values(const T* __restrict__ sc, int psc,
+                                            const T* __restrict__ gc, int pgc, int n, int e, T& sv,
                                             T& gv) {
   const int edge = e / (n + 1), idx = e % (n + 1);
   const int q = n / 2;
   const int line = (edge == RING_B || edge == RING_L) ? n / 4 : (3 * n) / 4;
   if (((idx + q) & 1) == 0) {
     const int I = (idx + q) / 2;
-    sv = coarse_val(sc, psc, edge, line, I, false);
-    gv = coarse_val(sc, psc, edge, line, I, true);
+    sv = coarse_s(sc, psc, edge, line, I);
+    gv = coarse_g(gc, pgc, edge, line, I);
   } else {
     const int c = (idx + q - 1) / 2;
-    sv = (-coarse_val(sc, psc, edge, line, c - 1, false) +
-          T(9) * coarse_val(sc, psc, edge, line, c, false) +
-          T(9) * coarse_val(sc, psc, edge, line, c + 1, false) -
-          coarse_val(sc, psc, edge, line, c + 2, false)) / T(16);
-    gv = (-coarse_val(sc, psc, edge, line, c - 1, true) +
-          T(9) * coarse_val(sc, psc, edge, line, c, true) +
-          T(9) * coarse_val(sc, psc, edge, line, c + 1, true) -
-          coarse_val(sc, psc, edge, line, c + 2, true)) / T(16);
+    sv = (-coarse_s(sc, psc, edge, line, c - 1) + T(9) * coarse_s(sc, psc, edge, line, c) +
+          T(9) * coarse_s(sc, psc, edge, line, c + 1) - coarse_s(sc, psc, edge, line, c + 2)) /
+         T(16);
+    gv = (-coarse_g(gc, pgc, edge, line, c - 1) + T(9) * coarse_g(gc, pgc, edge, line, c) +
+          T(9) * coarse_g(gc, pgc, edge, line, c + 1) - coarse_g(gc, pgc, edge, line, c + 2)) /
+         T(16);
   }
   gv = T(0.25) * gv;
 }
 
 template <typename T>
-__device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc, int n, T* sring,
+__device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc,
+                                          const T* __restrict__ gc, int pgc, int n, T* sring,
                                           T* gring, int e) {
   if (e >= 4 * (n + 1)) return;
   T sv, gv;
-  ring_values(sc, psc, n, e, sv, gv);
+  ring_values(sc, psc, gc, pgc, n, e, sv, gv);
   sring[e] = sv;
   gring[e] = gv;
 }
 
 template <typename T>
-__global__ void k_ring(const T* __restrict__ sc, int psc, int n, T* sring, T* gring) {
-  ring_body(sc, psc, n, sring, gring, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void k_ring(const T* __restrict__ sc, int psc, const T* __restrict__ gc, int pgc, int n,
+                       T* sring, T* gring) {
+  ring_body(sc, psc, gc, pgc, n, sring, gring, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 
@@ -739,7 +749,8 @@ __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ srin
 // (the same arithmetic as k_ring) and transforms its streamfunction part (the same
 // arithmetic as k_ring_edge_dst, one sequence per workgroup).
 template <typename T, int N, int NT>
-__device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc, T* sring, T* gring,
+__device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc,
+                                              const T* __restrict__ gc, int pgc, T* sring, T* gring,
                                               const c2<T>* __restrict__ tw, T* lift, int edge) {
   __shared__ c2<T> buf[fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
@@ -748,7 +759,7 @@ __device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc,
   for (int idx = tid; idx <= N; idx += NT) {
     const int e = edge * (N + 1) + idx;
     T sv, gv;
-    ring_values(sc, psc, N, e, sv, gv);
+    ring_values(sc, psc, gc, pgc, N, e, sv, gv);
     sring[e] = sv;
     gring[e] = gv;
     if (idx >= 1 && idx <= N - 1) dst_pack<T, N>(buf, idx, sv);
@@ -765,9 +776,10 @@ __device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc,
 }
 
 template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int psc, T* sring,
+__global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int psc,
+                                                 const T* __restrict__ gc, int pgc, T* sring,
                                                  T* gring, const c2<T>* __restrict__ tw, T* lift) {
-  ring_dst_body<T, N, NT>(sc, psc, sring, gring, tw, lift, blockIdx.x);
+  ring_dst_body<T, N, NT>(sc, psc, gc, pgc, sring, gring, tw, lift, blockIdx.x);
 }
 
 // Many instances of one grid size: workgroup (edge, instance blockIdx.y).
@@ -775,7 +787,7 @@ template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_dst_multi(const RingJob<T>* __restrict__ tab,
                                                        const c2<T>* __restrict__ tw) {
   const RingJob<T> j = tab[blockIdx.y];
-  ring_dst_body<T, N, NT>(j.sc, j.psc, j.sring, j.gring, tw, j.lift, blockIdx.x);
+  ring_dst_body<T, N, NT>(j.sc, j.psc, j.gc, j.pgc, j.sring, j.gring, tw, j.lift, blockIdx.x);
 }
 
 // ------------------------------------------------ launches of one kernel configuration

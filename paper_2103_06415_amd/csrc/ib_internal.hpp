@@ -74,6 +74,8 @@ template <typename T>
 struct RingJob {
   const T* sc;  // coarser level's streamfunction, pitch psc
   int psc;
+  const T* gc;  // coarser level's circulation (interior vertices), pitch pgc
+  int pgc;
   T* sring;
   T* gring;
   T* lift;
@@ -142,13 +144,14 @@ template <typename T>
 hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw, const T* ring,
                            int ring_rows, hipStream_t st);
 template <typename T>
-hipError_t launch_ring(const T* sc, int psc, int n, T* sring, T* gring, hipStream_t st);
+hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, hipStream_t st);
 // launch_ring and launch_ring_edge_dst in one launch (the same results).
 template <typename T>
-hipError_t launch_ring_dst(const T* sc, int psc, int n, T* sring, T* gring, const void* tw, T* lift,
-                           hipStream_t st);
+hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
+                           const void* tw, T* lift, hipStream_t st);
 
 // The same launches for `count` instances of grid size n at once, their arguments in device
 // tables (entry b for blockIdx.y = b); var as above, the same for all instances.  maxrows:

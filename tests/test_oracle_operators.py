@@ -238,3 +238,90 @@ def test_ring_interpolation_exact_for_cubics():
         mask = np.ones_like(ring, dtype=bool)
         mask[1:-1, 1:-1] = False
         np.testing.assert_allclose(ring[mask], ref[mask], atol=1e-10)
+
+
+# ---- extended precision (numpy.longdouble, 64-bit significand: eps = 2^-63 ~ 1.1e-19) ----
+
+LD = np.longdouble
+EPS_LD = float(np.finfo(LD).eps)
+
+
+def test_longdouble_is_wider_than_double():
+    assert EPS_LD < 1e-18
+
+
+@pytest.mark.parametrize("n", [16, 64, 96])
+def test_extended_sine_transform_equals_dense_extended_matrix(n):
+    """The library DST-I used in extended precision equals the dense orthonormal sine matrix
+    S[j-1, k-1] = sqrt(2/n) sin(pi j k / n) built and multiplied in long double, and S S = I
+    there (Sec. 3.2.1).  A transform done in double anywhere would miss by ~1e-16."""
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=(n - 1, n - 1)).astype(LD)
+    s = dst.sine_matrix(n, LD)
+    assert s.dtype == LD
+    dense = s @ x @ s
+    fast = dst.dst2(x)
+    assert fast.dtype == LD
+    assert float(np.max(np.abs(fast - dense))) < 100 * EPS_LD * float(np.max(np.abs(dense)))
+    eye = s @ s
+    assert float(np.max(np.abs(eye - np.eye(n - 1, dtype=LD)))) < 50 * EPS_LD
+
+
+@pytest.mark.parametrize("n", [32, 96])
+def test_extended_eigenvalues_closed_form(n):
+    """In long double, the 5-point stencil applied to a sine mode returns the mode times
+    4 sin^2(pi k/2n) + 4 sin^2(pi l/2n) (the diagonalisation of C^T C, Sec. 3.2.1)."""
+    k, l = 3, n // 3
+    s = dst.sine_matrix(n, LD)
+    mode = np.outer(s[:, l - 1], s[:, k - 1])
+    lam = dst.eigenvalues(n, LD)[l - 1, k - 1]
+    res = grid.l5(grid.pad(mode)) - lam * mode
+    assert float(np.max(np.abs(res))) < 50 * EPS_LD * float(np.max(np.abs(mode)))
+
+
+def test_extended_solve_residual():
+    """The extended-precision solve of L (I + alpha L) s = r leaves a long-double residual
+    when the operator is applied back by its stencils."""
+    n, alpha = 48, 0.31
+    rng = np.random.default_rng(3)
+    r = rng.normal(size=(n - 1, n - 1)).astype(LD)
+    x = dst.solve_cac(r, alpha)
+    lx = grid.l5(grid.pad(x))
+    back = lx + alpha * grid.l5(grid.pad(lx))
+    assert float(np.max(np.abs(back - r))) < 1e3 * EPS_LD * float(np.max(np.abs(r)))
+
+
+def _smooth_flow(n, levels):
+    flow = W.Flow(n=n, levels=levels, h=3.2 / n, dt=0.2 * 3.2 / n, re=150.0, cx=0.1, cy=-0.05,
+                  u_inf=(1.0, 0.3))
+    x = flow.cx - 0.5 * n * flow.h + flow.h * np.arange(1, n)
+    y = flow.cy - 0.5 * n * flow.h + flow.h * np.arange(1, n)
+    yy, xx = np.meshgrid(y, x, indexing="ij")
+    rng = np.random.default_rng(7)
+    w = 4.0 * np.exp(-((xx + 0.2) ** 2 + (yy - 0.1) ** 2) / 0.08) + 0.05 * rng.normal(size=xx.shape)
+    return W.Problem("flow", flow, [], vorticity0=[w] + [None] * (levels - 1))
+
+
+def test_extended_oracle_agrees_with_double_where_double_is_accurate():
+    """One level (no circulation handed between levels): the double oracle holds s to a few
+    ulps, so the extended run agrees with it to 1e-14 in s; its vorticity, C^T C s, to the
+    (n/pi)^2 / 2 amplified double rounding.  Every array of the extended run stays long
+    double."""
+    from oracle.step import Oracle
+    p = _smooth_flow(64, 1)
+    a, b = Oracle(p), Oracle(p, dtype=LD)
+    for _ in range(3):
+        a.step()
+        b.step()
+    assert b.s[0].dtype == LD and b.vorticity(0).dtype == LD
+    es = float(np.linalg.norm((a.s[0] - b.s[0]).astype(np.float64)) / np.linalg.norm(a.s[0]))
+    ew = float(np.linalg.norm((a.vorticity(0) - b.vorticity(0)).astype(np.float64))
+               / np.linalg.norm(a.vorticity(0)))
+    assert es < 1e-14, es
+    assert ew < 40 * 2.0 ** -52 * 0.5 * (64 / math.pi) ** 2, ew
+
+
+def test_extended_oracle_rejects_bodies():
+    from oracle.step import Oracle
+    with pytest.raises(ValueError):
+        Oracle(W.cylinder_problem(n=32, steps=1), dtype=LD)
