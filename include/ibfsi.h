@@ -54,6 +54,8 @@ typedef int32_t ib_status;
 #define IB_ERR_NEAR_BOUNDARY (-7)     /* delta support reaches the finest level's edge */
 #define IB_ERR_NONFINITE (-8)         /* NaN or Inf in the state */
 #define IB_ERR_CAPACITY (-9)          /* caller's output buffer is too small */
+#define IB_ERR_SCRATCH (-11)          /* the call needs more than the fixed device scratch of an
+                                         allocation-free entry point */
 
 /* precision */
 #define IB_FP64 0        /* everything in double precision */
@@ -416,6 +418,20 @@ const char* ib_last_error(const ib_solver* s);
  * elements; in == out is allowed. */
 ib_status ib_op_solve(int32_t n, int32_t precision, double alpha, const void* in, void* out,
                       int32_t pitch, void* hip_stream);
+
+/* ib_op_solve for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same operation, arguments,
+ * kernels and results, with no hipMalloc, hipFree or other allocating call.  The transform
+ * tables that ib_op_solve allocates per call (twiddles exp(-i pi m/n), m < 2n, and the
+ * eigenvalues 4 sin^2(pi k/2n)) are written into a fixed 64 KiB device array that the library
+ * holds on each GPU it runs on until the process ends; the tables of every supported n fit
+ * (at most 51,200 bytes, n = 1280 in double).  Every call overwrites the tables it uses, so
+ * nothing needs clearing, but all calls on one GPU share the array: calls that overlap on one
+ * GPU (other host threads, other streams) race.  Returns once the solve is complete, like
+ * ib_op_solve.  Errors: IB_ERR_ARG as for ib_op_solve; IB_ERR_SCRATCH if the tables would not
+ * fit; IB_ERR_HIP if the array's device address cannot be obtained or a launch fails. */
+ib_status ib_op_solve_noalloc(int32_t n, int32_t precision, double alpha, const void* in,
+                              void* out, int32_t pitch, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -116,6 +116,8 @@ _SIGS = {
     "ib_destroy": (c_int32, [c_void_p]),
     "ib_status_str": (ctypes.c_char_p, [c_int32]),
     "ib_op_solve": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_void_p, c_int32, c_void_p]),
+    "ib_op_solve_noalloc": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_void_p, c_int32,
+                                      c_void_p]),
     "ib_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
     "ib_get_kernel_timing": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "ib_set_stream": (c_int32, [c_void_p, c_void_p]),
@@ -222,6 +224,13 @@ def op_solve(n, precision, alpha, in_ptr, out_ptr, pitch, stream=0):
     lib = load()
     _check(lib.ib_op_solve(n, precision, alpha, c_void_p(in_ptr), c_void_p(out_ptr), pitch,
                            c_void_p(stream)), "ib_op_solve")
+
+
+def op_solve_noalloc(n, precision, alpha, in_ptr, out_ptr, pitch, stream=0):
+    """ib_op_solve without device allocation (see ib_op_solve_noalloc)."""
+    lib = load()
+    _check(lib.ib_op_solve_noalloc(n, precision, alpha, c_void_p(in_ptr), c_void_p(out_ptr), pitch,
+                                   c_void_p(stream)), "ib_op_solve_noalloc")
 
 
 class Solver:

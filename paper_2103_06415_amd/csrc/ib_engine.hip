@@ -324,6 +324,12 @@ struct ib_solver {
   double t_ms[IB_K_CLASSES] = {0};
 };
 
+// Fixed device scratch of the allocation-free entry point (ib_op_solve_noalloc): one copy
+// per GPU, reached from host code only through its address from hipGetSymbolAddress.
+constexpr size_t kNoallocScratchBytes = 64 * 1024;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 namespace {
 
 ib_status hip_fail(ib_solver* s, hipError_t e, const char* what) {
@@ -335,6 +341,12 @@ ib_status hip_fail(ib_solver* s, hipError_t e, const char* what) {
   do {                                                 \
     hipError_t e_ = (expr);                            \
     if (e_ != hipSuccess) return hip_fail(s, e_, #expr); \
+  } while (0)
+
+// The same check for code that has no solver handle.
+#define HIPRET(expr)                                 \
+  do {                                               \
+    if ((expr) != hipSuccess) return IB_ERR_HIP;     \
   } while (0)
 
 void* dalloc(ib_solver* s, size_t bytes) {
@@ -361,9 +373,10 @@ void dfree(ib_solver* s, void* p) {
 }
 
 // Twiddles exp(-i pi m / n), m < 2n, and 1-D eigenvalues 4 sin^2(pi k / 2n), k < n.
+// Transform tables of grid size n: twiddles exp(-i pi m / n), m < 2n, as (re, im) pairs in
+// t[0 .. 4n), and the 1-D eigenvalues 4 sin^2(pi k / 2n), k = 1 .. n-1, in l[0 .. n-1).
 template <typename T>
-ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
-  std::vector<T> t(4 * n), l(n);
+void table_values(int n, T* t, T* l) {
   for (int m = 0; m < 2 * n; ++m) {
     const long double a = 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
     t[2 * m] = (T)std::cos((double)a);
@@ -373,12 +386,111 @@ ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
     const double v = std::sin(M_PI * k / (2.0 * n));
     l[k - 1] = (T)(4.0 * v * v);
   }
+}
+
+template <typename T>
+ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
+  std::vector<T> t(4 * n), l(n);
+  table_values<T>(n, t.data(), l.data());
   *tw = dalloc(s, t.size() * sizeof(T));
   *lam = dalloc(s, l.size() * sizeof(T));
   if (!*tw || !*lam) return IB_ERR_OOM;
   HIPCHK(hipMemcpy(*tw, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(*lam, l.data(), l.size() * sizeof(T), hipMemcpyHostToDevice));
   return IB_OK;
+}
+
+// The operator solve of ib_op_solve on its tables: row transform of `in` into `out`, column
+// transform, spectral divide and inverse, inverse row transform, all in `out`.
+template <typename T>
+ib_status op_solve_run(int n, int pitch, hipStream_t st, double alpha, const void* in, void* out,
+                       const void* tw, const void* lam) {
+  RowArgs<T> r{};
+  r.in = static_cast<const T*>(in);
+  r.out = static_cast<T*>(out);
+  r.pi = r.po = pitch;
+  r.r0 = 1;
+  r.r1 = n - 1;
+  HIPRET(launch_rowdst<T>(r, n, 1, tw, st));
+  ColArgs<T> c{};
+  c.in = static_cast<T*>(out);
+  c.out = static_cast<T*>(out);
+  c.pi = c.po = pitch;
+  c.r0 = 1;
+  c.r1 = n - 1;
+  c.alpha = (T)alpha;
+  c.scale = (T)(4.0 / ((double)n * n));
+  c.w0 = 1;
+  c.w1 = n - 1;
+  HIPRET(launch_col_solve<T>(c, n, 1, tw, lam, st));
+  r.in = static_cast<const T*>(out);
+  r.interior_out = 1;
+  HIPRET(launch_row_idst<T>(r, n, 1, tw, nullptr, 0, st));
+  return IB_OK;
+}
+
+// ---- fixed device scratch of the allocation-free entry point ----
+// ib_op_solve_noalloc keeps the transform tables that ib_op_solve allocates per call in this
+// file-scope device array instead.  Each GPU the library runs on holds its own copy, at its
+// own address, until the process ends.  In host code the array's name is only a stand-in:
+// its device address comes from hipGetSymbolAddress, once per device, and only that address
+// is handed to kernels and copies.
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up at the first call there).
+static ib_status scratch_address(void** out) {
+  int dev = 0;
+  HIPRET(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return IB_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return IB_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return IB_OK;
+}
+
+// Bytes of scratch the tables of size n take: twiddles (4n values) from offset 0, eigenvalues
+// (n - 1 values) from the next 256-byte boundary.
+template <typename T>
+size_t noalloc_lam_offset(int n) {
+  return ((size_t)4 * n * sizeof(T) + 255) / 256 * 256;
+}
+template <typename T>
+size_t noalloc_bytes(int n) {
+  return noalloc_lam_offset<T>(n) + (size_t)n * sizeof(T);
+}
+
+template <typename T>
+ib_status op_solve_noalloc_run(int n, int pitch, hipStream_t st, double alpha, const void* in,
+                               void* out) {
+  if (noalloc_bytes<T>(n) > kNoallocScratchBytes) return IB_ERR_SCRATCH;
+  void* base = nullptr;
+  ib_status rc = scratch_address(&base);
+  if (rc) return rc;
+  // host tables in a fixed buffer (no heap): 4n + n values, n <= 1280 for every supported n
+  constexpr int kMaxN = 1280;
+  if (n > kMaxN) return IB_ERR_SCRATCH;
+  T host[5 * kMaxN];
+  T* ht = host;
+  T* hl = host + 4 * n;
+  table_values<T>(n, ht, hl);
+  unsigned char* b = static_cast<unsigned char*>(base);
+  void* tw = b;
+  void* lam = b + noalloc_lam_offset<T>(n);
+  if (hipMemcpyAsync(tw, ht, (size_t)4 * n * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(lam, hl, (size_t)(n - 1) * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+    rc = IB_ERR_HIP;
+  if (!rc) rc = op_solve_run<T>(n, pitch, st, alpha, in, out, tw, lam);
+  // on every path the host tables outlive their copies; the solve is complete on return, as
+  // for ib_op_solve
+  const hipError_t e = hipStreamSynchronize(st);
+  if (rc) return rc;
+  return e == hipSuccess ? IB_OK : IB_ERR_HIP;
 }
 
 // ------------------------------------------------------------- flow helpers
@@ -2624,6 +2736,7 @@ const char* ib_status_str(ib_status st) {
     case IB_ERR_NEAR_BOUNDARY: return "delta support reaches the finest level's boundary";
     case IB_ERR_NONFINITE: return "non-finite value";
     case IB_ERR_CAPACITY: return "output buffer too small";
+    case IB_ERR_SCRATCH: return "larger than the fixed device scratch of an allocation-free call";
     default: return "unknown status";
   }
 }
@@ -3335,43 +3448,27 @@ ib_status ib_op_solve(int32_t n, int32_t precision, double alpha, const void* in
   s->n = n;
   s->pitch = pitch;
   ib_status st = IB_OK;
-  const double scale = 4.0 / ((double)n * n);
   if (precision == IB_FP64) {
     st = make_tables<double>(s, n, &s->tw, &s->lam);
-    if (!st) {
-      RowArgs<double> r{};
-      r.in = static_cast<const double*>(in);
-      r.out = static_cast<double*>(out);
-      r.pi = r.po = pitch;
-      r.r0 = 1;
-      r.r1 = n - 1;
-      if (launch_rowdst<double>(r, n, 1, s->tw, s->stream) != hipSuccess) st = IB_ERR_HIP;
-      if (!st) st = solve_into<double>(s, out, alpha, scale, 1, n - 1, s->tw, s->lam);
-      r.in = static_cast<const double*>(out);
-      r.interior_out = 1;
-      if (!st && launch_row_idst<double>(r, n, 1, s->tw, nullptr, 0, s->stream) != hipSuccess)
-        st = IB_ERR_HIP;
-    }
+    if (!st) st = op_solve_run<double>(n, pitch, s->stream, alpha, in, out, s->tw, s->lam);
   } else {
     st = make_tables<float>(s, n, &s->tw, &s->lam);
-    if (!st) {
-      RowArgs<float> r{};
-      r.in = static_cast<const float*>(in);
-      r.out = static_cast<float*>(out);
-      r.pi = r.po = pitch;
-      r.r0 = 1;
-      r.r1 = n - 1;
-      if (launch_rowdst<float>(r, n, 1, s->tw, s->stream) != hipSuccess) st = IB_ERR_HIP;
-      if (!st) st = solve_into<float>(s, out, alpha, scale, 1, n - 1, s->tw, s->lam);
-      r.in = static_cast<const float*>(out);
-      r.interior_out = 1;
-      if (!st && launch_row_idst<float>(r, n, 1, s->tw, nullptr, 0, s->stream) != hipSuccess)
-        st = IB_ERR_HIP;
-    }
+    if (!st) st = op_solve_run<float>(n, pitch, s->stream, alpha, in, out, s->tw, s->lam);
   }
   (void)hipStreamSynchronize(s->stream);
   while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
   return st;
+}
+
+ib_status ib_op_solve_noalloc(int32_t n, int32_t precision, double alpha, const void* in,
+                              void* out, int32_t pitch, void* hip_stream) {
+  HipShared hip_lock;
+  if (!supported_n(n) || !in || !out || pitch < n - 1 ||
+      (precision != IB_FP64 && precision != IB_FP32_FLOW))
+    return IB_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (precision == IB_FP64) return op_solve_noalloc_run<double>(n, pitch, st, alpha, in, out);
+  return op_solve_noalloc_run<float>(n, pitch, st, alpha, in, out);
 }
 
 }  // extern "C"
