@@ -54,6 +54,8 @@ typedef int32_t ib_status;
 #define IB_ERR_NEAR_BOUNDARY (-7)     /* delta support reaches the finest level's edge */
 #define IB_ERR_NONFINITE (-8)         /* NaN or Inf in the state */
 #define IB_ERR_CAPACITY (-9)          /* caller's output buffer is too small */
+#define IB_ERR_BUDGET (-10)           /* the request's device-memory estimate exceeds the budget
+                                         it is admitted against */
 #define IB_ERR_SCRATCH (-11)          /* the call needs more than the fixed device scratch of an
                                          allocation-free entry point */
 
@@ -65,6 +67,14 @@ typedef int32_t ib_status;
                             dense products with the sine matrix on the BF16 matrix cores, each
                             operand split in two BF16 parts (three products, FP32
                             accumulation; about 16 significant bits per transform) */
+
+/* discrete delta kernel of the interpolation E and regularisation E^T (Sec. 3.1, eq. (24):
+ * the paper does not name its kernel) */
+#define IB_DELTA_ROMA3 0    /* 3-point kernel of Roma, Peskin & Berger (1999), support 1.5 h */
+#define IB_DELTA_PESKIN4 1  /* Peskin's 4-point kernel (2002), support 2 h; with the exact
+                               operator only: in sub-domain mode the hat-combined E0 rows of
+                               this kernel do not fit the 4 x 4 face window of a stress row
+                               (ib_prepare returns IB_ERR_ARG) */
 
 /* Schur operator */
 #define IB_SCHUR_AUTO 0       /* sub-domain if a sub-domain is set, else exact */
@@ -90,6 +100,7 @@ typedef struct {
   int32_t newton_max_iter;   /* give up after this many FSI iterations (e.g. 20) */
   int32_t newton_fixed_iter; /* > 0: run exactly this many FSI iterations, no test */
   double drop_tol;    /* B' drop tolerance epsilon (0.007, Sec. 3.2.2) */
+  int32_t delta;      /* IB_DELTA_ROMA3 (0, the default) or IB_DELTA_PESKIN4 */
 } ib_config;
 
 typedef struct {
@@ -115,6 +126,21 @@ typedef struct {
   int64_t graph_captures;    /* graphs recorded */
   int64_t fsi_resumes;       /* steps whose FSI iterations launched ahead did not suffice
                                 and were continued on the host (IB_OPT_FSI_AHEAD) */
+  int32_t converged;         /* 1 when the last step's final max |delta| <= newton_tol (also
+                                without bodies or steps); 0 after a fixed iteration count that
+                                stopped above it */
+  double noslip_resid;       /* no-slip residual of the last step (Sec. 2.3, the constraint at
+                                t_{n+1}): max over stress rows of |(1/h) W (C s_{n+1} + q_inf)
+                                - U_b|, W the row's interpolation of the last FSI iterate (E,
+                                or P E0 in sub-domain mode), U_b the body velocity at t_{n+1};
+                                round-off with the exact operator, the sub-domain operator's
+                                approximation error otherwise */
+  double force[2];           /* total force of the fluid on all bodies, sum of f ds (x, y); per
+                                body: ib_read_force */
+  int64_t solve_fallbacks;   /* steps whose stress solves were redone by LU because the
+                                refinement's device-wide barrier timed out */
+  int32_t solve_by_lu;       /* 1 when every stress solve is an LU factorisation: the
+                                refinement's workgroups cannot all be resident on this device */
 } ib_stats;
 
 /* Create a solver.  `alloc` may be NULL (hipMalloc); `hip_stream` is a hipStream_t
@@ -199,6 +225,13 @@ ib_status ib_sync(ib_solver* s);
 /* Stresses of a body after the last step: 2m doubles (x block then y block). */
 ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap);
 
+/* Force of the fluid on a body after the last step (Sec. 5: forces and lift coefficients),
+ * out[0..1] = (F_x, F_y) = ds * sum of the body's stresses, summed on the device.  With unit
+ * free stream and chord, c_d = 2 F_x and c_l = 2 F_y.  (0, 0) before the first step; still
+ * readable after ib_release.  Errors: IB_ERR_ARG, IB_ERR_STATE (not prepared),
+ * IB_ERR_CAPACITY (cap < 2). */
+ib_status ib_read_force(ib_solver* s, int32_t body_id, double* out, int64_t cap);
+
 /* Structure state: torsional -> (theta, phi, phidot); deformable -> 3m doubles
  * (x, y, rotation per node); rigid -> its 2m point coordinates. */
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap);
@@ -264,6 +297,16 @@ ib_status ib_destroy(ib_solver* s);
 #define IB_OPT_GRAPHS 2
 #define IB_OPT_REFRESH_EVERY_ITER 3
 #define IB_OPT_TOP_AHEAD 4
+/* IB_OPT_BARRIER_SPIN (default 0 = the built-in bound, 2^22): the bound on the spins of the
+ * stress refinement's device-wide barrier, up to 2^40.  The refinement keeps rows of the Schur
+ * matrix and of its approximate inverse in the LDS of co-resident workgroups and meets at one
+ * barrier per sweep; when a wait reaches the bound (the workgroups were not all resident,
+ * e.g. beside other solvers' kernels) every workgroup leaves, and the host redoes that step's
+ * FSI iterations with LU solves of the Schur matrix (ib_stats.solve_fallbacks).
+ * IB_OPT_BARRIER_FORCE_TIMEOUT (default 0; 1 for tests of that path): every barrier waits for
+ * one arrival more than the launch has workgroups, so every wait ends at the spin bound. */
+#define IB_OPT_BARRIER_SPIN 5
+#define IB_OPT_BARRIER_FORCE_TIMEOUT 6
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value);
 
 /* ---- measured kernel configurations of the sine transforms ----
@@ -353,7 +396,8 @@ typedef struct {
 
 ib_status ib_server_create(int32_t max_active, int64_t hbm_budget_bytes, int32_t chunk_steps,
                            ib_server** out);
-/* Errors: IB_ERR_CAPACITY when the request's estimate exceeds the whole budget. */
+/* Errors: IB_ERR_BUDGET when the request's peak estimate exceeds the whole budget (it could
+ * never be admitted). */
 ib_status ib_server_submit(ib_server* sv, ib_solver* s, int32_t nsteps, double arrival,
                            int64_t* ticket);
 /* Run until every submitted request has finished or failed (blocking). */

@@ -8,6 +8,12 @@ kernel d; the reading adopted here is the 3-point kernel of Roma, Peskin & Berge
     d(r) = (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6       1/2 <= |r| <= 3/2
     d(r) = 0                                              otherwise
 
+Peskin's 4-point kernel (Peskin 2002) is the alternative, selected per problem:
+
+    d(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4 r^2)) / 8        |r| <= 1
+    d(r) = (5 - 2|r| - sqrt(-7 + 12|r| - 4 r^2)) / 8       1 <= |r| <= 2
+    d(r) = 0                                              otherwise
+
 The scaling the paper leaves open ("to within a scaling factor") is fixed by the
 physics: interpolated velocity = E q / h on the flux q = u h, and the body force
 enters the circulation equation as C^T E^T (ds / h) f, which keeps the spread the
@@ -32,9 +38,23 @@ def roma3(r):
     return out
 
 
-def interpolation_matrix(level, points):
+def peskin4(r):
+    a = np.abs(np.asarray(r, dtype=np.float64))
+    out = np.zeros_like(a)
+    m1 = a <= 1.0
+    m2 = (a > 1.0) & (a <= 2.0)
+    out[m1] = (3.0 - 2.0 * a[m1] + np.sqrt(1.0 + 4.0 * a[m1] - 4.0 * a[m1] ** 2)) / 8.0
+    out[m2] = (5.0 - 2.0 * a[m2] - np.sqrt(np.maximum(0.0, -7.0 + 12.0 * a[m2] - 4.0 * a[m2] ** 2))) / 8.0
+    return out
+
+
+KERNELS = {"roma3": roma3, "peskin4": peskin4}
+
+
+def interpolation_matrix(level, points, kernel="roma3"):
     """Sparse E (2 m x n_faces) for m points (x rows then y rows), by the definition:
     the tensor product of the kernel over every face of the level."""
+    phi = KERNELS[kernel]
     (xfx, xfy), (yfx, yfy) = level.face_coords()
     h = level.h
     n = level.n
@@ -43,15 +63,15 @@ def interpolation_matrix(level, points):
     rows, cols, vals = [], [], []
     for a in range(m):
         px, py = points[a]
-        wx = roma3((xfx - px) / h)
-        wy = roma3((xfy - py) / h)
+        wx = phi((xfx - px) / h)
+        wy = phi((xfy - py) / h)
         w = np.outer(wy, wx)                     # x-faces [j, i]
         jj, ii = np.nonzero(w)
         rows.append(np.full(jj.size, a))
         cols.append(jj * (n + 1) + ii)
         vals.append(w[jj, ii])
-        wx = roma3((yfx - px) / h)
-        wy = roma3((yfy - py) / h)
+        wx = phi((yfx - px) / h)
+        wy = phi((yfy - py) / h)
         w = np.outer(wy, wx)                     # y-faces [j, i]
         jj, ii = np.nonzero(w)
         rows.append(np.full(jj.size, m + a))

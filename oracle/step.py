@@ -80,6 +80,7 @@ class Oracle:
         if self.dtype != np.float64 and problem.bodies:
             raise ValueError("extended precision covers the flow of problems without bodies")
         self.levels = [grid.Level(flow, g) for g in range(flow.levels)]
+        self.kernel = getattr(flow, "delta", "roma3")
         n = flow.n
         self.n = n
         self.dt = flow.dt
@@ -172,7 +173,7 @@ class Oracle:
             self.sd_ngrid = (i1 - i0 + 1) * (j1 - j0 + 1)
             self.sd_pts = subdomain.point_set(lv, self.sd_box, app)
             self.sd_total = self.sd_pts.shape[0]
-            self.e0 = subdomain.sub_e0(lv, self.sd_pts)
+            self.e0 = subdomain.sub_e0(lv, self.sd_pts, self.kernel)
             delta.check_support(lv, self.e0)
             self.b_full = subdomain.build_b(lv, self.e0)
             self.b_filtered = subdomain.filter_b(self.b_full, self.drop_tol)
@@ -200,7 +201,7 @@ class Oracle:
         blocks = []
         if not self.use_subdomain:
             for kind, b in self.bodies:
-                e = delta.interpolation_matrix(lv, self.positions(kind, b))
+                e = delta.interpolation_matrix(lv, self.positions(kind, b), self.kernel)
                 delta.check_support(lv, e)
                 blocks.append(e.toarray())
             return np.vstack(blocks)

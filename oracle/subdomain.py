@@ -110,9 +110,9 @@ def hat_rows(level, box, npts_grid, n_sd_total, positions, comp_offset, appended
     return rows
 
 
-def sub_e0(level, pts):
+def sub_e0(level, pts, kernel="roma3"):
     """E0 (2 n_sd x n_faces): x rows of all points, then y rows."""
-    return delta.interpolation_matrix(level, pts)
+    return delta.interpolation_matrix(level, pts, kernel)
 
 
 def as_sparse(b):

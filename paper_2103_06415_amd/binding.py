@@ -20,14 +20,17 @@ IB_FP32_FLOW_BF16_DST = 2
 IB_SCHUR_AUTO = 0
 IB_SCHUR_EXACT = 1
 IB_SCHUR_SUBDOMAIN = 2
+IB_DELTA_ROMA3 = 0
+IB_DELTA_PESKIN4 = 1
 
 (IB_OK, IB_ERR_ARG, IB_ERR_STATE, IB_ERR_OOM, IB_ERR_HIP, IB_ERR_NOT_CONVERGED,
- IB_ERR_OUT_OF_SUBDOMAIN, IB_ERR_NEAR_BOUNDARY, IB_ERR_NONFINITE, IB_ERR_CAPACITY) = range(0, -10, -1)
+ IB_ERR_OUT_OF_SUBDOMAIN, IB_ERR_NEAR_BOUNDARY, IB_ERR_NONFINITE, IB_ERR_CAPACITY, IB_ERR_BUDGET,
+ IB_ERR_SCRATCH) = range(0, -12, -1)
 
 STATUS = {
     0: "IB_OK", -1: "IB_ERR_ARG", -2: "IB_ERR_STATE", -3: "IB_ERR_OOM", -4: "IB_ERR_HIP",
     -5: "IB_ERR_NOT_CONVERGED", -6: "IB_ERR_OUT_OF_SUBDOMAIN", -7: "IB_ERR_NEAR_BOUNDARY",
-    -8: "IB_ERR_NONFINITE", -9: "IB_ERR_CAPACITY",
+    -8: "IB_ERR_NONFINITE", -9: "IB_ERR_CAPACITY", -10: "IB_ERR_BUDGET", -11: "IB_ERR_SCRATCH",
 }
 
 
@@ -42,7 +45,7 @@ class IbConfig(ctypes.Structure):
         ("n", c_int32), ("levels", c_int32), ("h", c_double), ("cx", c_double), ("cy", c_double),
         ("re", c_double), ("dt", c_double), ("u_inf", c_double * 2), ("precision", c_int32),
         ("schur_mode", c_int32), ("newton_tol", c_double), ("newton_max_iter", c_int32),
-        ("newton_fixed_iter", c_int32), ("drop_tol", c_double),
+        ("newton_fixed_iter", c_int32), ("drop_tol", c_double), ("delta", c_int32),
     ]
 
 
@@ -62,11 +65,14 @@ class IbStats(ctypes.Structure):
         ("prepare_seconds", c_double), ("refine_iters", c_int32), ("inverse_rebuilds", c_int32),
         ("refine_residual", c_double), ("operator_source", c_int32),
         ("graph_launches", c_int64), ("graph_captures", c_int64), ("fsi_resumes", c_int64),
+        ("converged", c_int32), ("noslip_resid", c_double), ("force", c_double * 2),
+        ("solve_fallbacks", c_int64), ("solve_by_lu", c_int32),
     ]
 
 
 FLOW_VARIANTS = 8
 IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS, IB_OPT_REFRESH_EVERY_ITER, IB_OPT_TOP_AHEAD = 1, 2, 3, 4
+IB_OPT_BARRIER_SPIN, IB_OPT_BARRIER_FORCE_TIMEOUT = 5, 6
 
 
 class IbFlowTuning(ctypes.Structure):
@@ -111,6 +117,7 @@ _SIGS = {
     "ib_read_stresses": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
     "ib_read_deflection": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
     "ib_read_vorticity": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
+    "ib_read_force": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
     "ib_read_streamfunction": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int64]),
     "ib_get_stats": (c_int32, [c_void_p, POINTER(IbStats)]),
     "ib_destroy": (c_int32, [c_void_p]),
@@ -250,6 +257,7 @@ class Solver:
         cfg.precision, cfg.schur_mode = precision, schur
         cfg.newton_tol, cfg.newton_max_iter = newton_tol, newton_max
         cfg.newton_fixed_iter, cfg.drop_tol = fixed_iters, drop_tol
+        cfg.delta = {"roma3": IB_DELTA_ROMA3, "peskin4": IB_DELTA_PESKIN4}[getattr(fl, "delta", "roma3")]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._alloc = TorchAllocator(torch.cuda.current_device(), self.stream) if torch_alloc else None
         self.handle = c_void_p()
@@ -347,7 +355,14 @@ class Solver:
     def stats(self):
         st = IbStats()
         _check(self.lib.ib_get_stats(self.handle, byref(st)), "ib_get_stats")
-        return {k: getattr(st, k) for k, _ in IbStats._fields_}
+        out = {k: getattr(st, k) for k, _ in IbStats._fields_}
+        out["force"] = (st.force[0], st.force[1])
+        return out
+
+    def force(self, body):
+        out = np.zeros(2)
+        _check(self.lib.ib_read_force(self.handle, body, _dptr(out), out.size), "ib_read_force")
+        return out
 
     def set_kernel_timing(self, on=True):
         _check(self.lib.ib_set_kernel_timing(self.handle, 1 if on else 0), "ib_set_kernel_timing")

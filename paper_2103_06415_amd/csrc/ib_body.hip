@@ -35,10 +35,36 @@ __device__ __forceinline__ double roma3(double r) {
   return 0.0;
 }
 
-// True-E window of a point for one component (0: x-faces, 1: y-faces).
+__device__ __forceinline__ double peskin4(double r) {
+  const double a = fabs(r);
+  if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+  if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(fmax(0.0, -7.0 + 12.0 * a - 4.0 * a * a))) / 8.0;
+  return 0.0;
+}
+
+// True-E window of a point for one component (0: x-faces, 1: y-faces).  kind 0: the 3-point
+// kernel, 3 x 3 faces about the nearest face; kind 1: the 4-point kernel, the 4 x 4 faces
+// within two cells (from floor(r) - 1 along each axis, r the point in face units).
 __device__ void exact_window(double px, double py, int comp, double x0, double y0, double h,
-                             int* base, double* w) {
+                             int* base, double* w, int kind) {
   for (int e = 0; e < 16; ++e) w[e] = 0.0;
+  if (kind == 1) {
+    const double rx = comp == 0 ? (px - x0) / h : (px - x0) / h - 0.5;
+    const double ry = comp == 0 ? (py - y0) / h - 0.5 : (py - y0) / h;
+    base[0] = (int)floor(rx) - 1;
+    base[1] = (int)floor(ry) - 1;
+    for (int dj = 0; dj < 4; ++dj) {
+      const int j = base[1] + dj;
+      const double fy = comp == 0 ? y0 + h * (j + 0.5) : y0 + h * j;
+      const double wy = peskin4((fy - py) / h);
+      for (int di = 0; di < 4; ++di) {
+        const int i = base[0] + di;
+        const double fx = comp == 0 ? x0 + h * i : x0 + h * (i + 0.5);
+        w[dj * 4 + di] = wy * peskin4((fx - px) / h);
+      }
+    }
+    return;
+  }
   int ic, jc;
   if (comp == 0) {
     ic = (int)rint((px - x0) / h);
@@ -222,10 +248,10 @@ __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
     int* pidx = a.p_idx + 4 * row;
     double* pw = a.p_w + 4 * row;
     if (!a.use_sd) {
-      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w);
+      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w, a.delta_kind);
     } else if (b.kind == BODY_RIGID) {
       const int app = a.sd_ngrid + b.app0 + local;
-      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w);
+      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w, a.delta_kind);
       for (int e = 0; e < 4; ++e) {
         pidx[e] = comp * a.sd_total + app;
         pw[e] = e == 0 ? 1.0 : 0.0;
@@ -1261,7 +1287,8 @@ __device__ void off_window(const OffRows& o, int row, int* base, int* comp, doub
     add_e0_vertex(p, q, *comp, 1.0, o.x0, o.y0, o.h, base, w);
   } else {
     const int ap = pt - o.sd_ngrid;
-    exact_window(o.app_xy[2 * ap], o.app_xy[2 * ap + 1], *comp, o.x0, o.y0, o.h, base, w);
+    // appended exact points exist in sub-domain mode only, which uses the 3-point kernel
+    exact_window(o.app_xy[2 * ap], o.app_xy[2 * ap + 1], *comp, o.x0, o.y0, o.h, base, w, 0);
   }
 }
 
@@ -1411,9 +1438,14 @@ __device__ inline double bitsd(unsigned long long v) { return __longlong_as_doub
 // L2 caches, so readers need no cache invalidation; every thread's agent-scope release fence
 // before the workgroup barrier makes its stores complete before the arrival.  The wait is bounded:
 // on time-out it records FLAG_BARRIER in flags[0] and returns false, and every other
-// waiting workgroup then leaves its wait at once.
+// waiting workgroup then leaves its wait at once.  `limit` > 0 replaces the default bound
+// on the spins; `limit` < 0 is a test hook of the host: the wait then needs one arrival more
+// than the launch has workgroups, which never comes, so every wait ends at the bound -limit
+// and the kernel's time-out path runs (every workgroup still leaves normally).
 constexpr long BARRIER_SPIN_LIMIT = 1L << 22;
-__device__ bool grid_barrier(unsigned* cnt, unsigned target, int* flags) {
+__device__ bool grid_barrier(unsigned* cnt, unsigned target, int* flags, long limit) {
+  const long lim = limit > 0 ? limit : (limit < 0 ? -limit : BARRIER_SPIN_LIMIT);
+  const unsigned want = limit < 0 ? target + 1u : target;
   __shared__ int ok_s;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
@@ -1421,10 +1453,10 @@ __device__ bool grid_barrier(unsigned* cnt, unsigned target, int* flags) {
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     long spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
       __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 255) == 0 &&
-          (spins > BARRIER_SPIN_LIMIT ||
+      if (++spins > lim ||
+          ((spins & 255) == 0 &&
            __hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == FLAG_BARRIER)) {
         atomicMax(&flags[0], FLAG_BARRIER);
         ok = 0;
@@ -1452,7 +1484,7 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
                                             const double* __restrict__ b, double* f, int n,
                                             int rw, int tpr, int maxit, int guess, double* ws,
                                             double* out, int* flags, const int* gate,
-                                            double* xcopy, int bx, int gx) {
+                                            double* xcopy, long spin, int bx, int gx) {
   if (iter_gated(gate)) return;  // the same for every workgroup: none enters a barrier
   extern __shared__ double lds[];
   double* sf = lds;           // f (n)
@@ -1568,7 +1600,7 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
       st_agent(&sh[j], acc);
     }
     target += (unsigned)nb;
-    if (!grid_barrier(cnt, target, flags)) {
+    if (!grid_barrier(cnt, target, flags, spin)) {
       ok = false;
       break;
     }
@@ -1588,7 +1620,7 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
         st_agent(&red[c0 + tid], acc);
       }
       target += (unsigned)nb;
-      if (!grid_barrier(cnt, target, flags)) {
+      if (!grid_barrier(cnt, target, flags, spin)) {
         ok = false;
         break;
       }
@@ -1653,9 +1685,9 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
                                                 const double* __restrict__ b, double* f, int n,
                                                 int rw, int tpr, int maxit, int guess, double* ws,
                                                 double* out, int* flags, const int* gate,
-                                                double* xcopy) {
+                                                double* xcopy, long spin) {
   refine_body<CACHE, TWO>(M, X, pm, b, f, n, rw, tpr, maxit, guess, ws, out, flags, gate, xcopy,
-                          blockIdx.x, gridDim.x);
+                          spin, blockIdx.x, gridDim.x);
 }
 
 // Many instances per launch: instance blockIdx.y's nb workgroups are its own barrier group
@@ -1666,7 +1698,7 @@ __global__ __launch_bounds__(256) void k_refine_multi(const RefineJob* __restric
   const RefineJob j = tab[blockIdx.y];
   if ((int)blockIdx.x >= j.nb) return;
   refine_body<CACHE, TWO>(j.M, j.X, j.pm, j.b, j.f, j.n, j.rw, j.tpr, j.maxit, j.guess, j.ws, j.out,
-                     j.flags, j.gate, j.xcopy, blockIdx.x, j.nb);
+                     j.flags, j.gate, j.xcopy, j.spin, blockIdx.x, j.nb);
 }
 
 // C = A B for n x n FP64 matrices (pitch p), optionally C = 2 I - A B, on the FP64 matrix
@@ -1829,19 +1861,43 @@ bool refine_shape(int n, RefineShape* out) {
 
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, double* xcopy, hipStream_t st) {
+                         const int* gate, double* xcopy, long spin, hipStream_t st) {
   RefineShape r;
   if (maxit < 1 || !refine_shape(n, &r)) return hipErrorInvalidValue;
   if (r.two)
     hipLaunchKernelGGL((k_refine<true, true>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n,
-                       r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
+                       r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin);
   else if (r.cache)
     hipLaunchKernelGGL((k_refine<true, false>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f,
-                       n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
+                       n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin);
   else
     hipLaunchKernelGGL((k_refine<false, false>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f,
-                       n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy);
+                       n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin);
   return hipGetLastError();
+}
+
+// Whether the nb workgroups of one refinement of n unknowns can all be resident at once on
+// this device (the device-wide barrier needs that): the kernel's occupancy per compute unit,
+// for its threads and LDS, times the compute units.
+bool refine_coresident(int n, int* have, int* need) {
+  RefineShape r;
+  *have = *need = 0;
+  if (!refine_shape(n, &r)) return false;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return false;
+  hipError_t e;
+  if (r.two)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine<true, true>, 256, r.lds);
+  else if (r.cache)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine<true, false>, 256, r.lds);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_refine<false, false>, 256, r.lds);
+  if (e != hipSuccess) return false;
+  *have = per * cus;
+  *need = r.nb;
+  return *have >= *need;
 }
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int p, int two_minus,
                          hipStream_t st, const int* gate) {
@@ -2126,6 +2182,86 @@ template hipError_t launch_spread_multi<float>(const SpreadJob<float>*, int, int
                                                  hipStream_t);
 template hipError_t launch_spread_multi<double>(const SpreadJob<double>*, int, int, int, int,
                                                  hipStream_t);
+// Outputs of the last step (Sec. 5: forces and lift; Sec. 2.3: the no-slip constraint at
+// t_{n+1}), one workgroup:
+//   out[0]           max over stress rows of |(1/h) W (C s_{n+1} + q_inf) - U_b|, with W the
+//                    row's operator of the last FSI iterate (E, or P E0 in sub-domain mode)
+//                    and U_b the body velocity at t_{n+1}: the prescribed one (rigid,
+//                    moving), phi_{n+1} e_z x (p - hinge) at the last iterate's points
+//                    (torsional; plus the driver's velocity on a mount), zeta_{n+1} at the
+//                    node (deformable);
+//   out[1 + 2b + c]  force of body b in direction c, ds * sum of its stresses (tree sum in a
+//                    fixed order).
+constexpr int OUT_NT = 256;
+template <typename T>
+__global__ __launch_bounds__(OUT_NT) void k_outputs(FsiArgs a, const T* __restrict__ s0, int ps,
+                                                    double* out) {
+  __shared__ double red[OUT_NT];
+  const int tid = threadIdx.x;
+  double mx = 0.0;
+  for (int row = tid; row < a.nf; row += OUT_NT) {
+    const BodyDev& b = a.bodies[row_body(a, row)];
+    const int rel = row - 2 * b.pt0;
+    const int comp = a.st_base[3 * row + 2];
+    const int local = rel - comp * b.npts;
+    const int p = b.pt0 + local;
+    const int bx = a.st_base[3 * row], by = a.st_base[3 * row + 1];
+    double acc = 0.0;
+    for (int e = 0; e < 16; ++e) {
+      const double w = a.st_w[16 * row + e];
+      if (w != 0.0) acc += w * face_flux(s0, ps, comp, bx + (e & 3), by + (e >> 2), a.ux, a.uy);
+    }
+    double tgt = 0.0;
+    if (b.kind == BODY_RIGID || b.kind == BODY_MOVING) {
+      tgt = rhs_body_term(a, b, local, comp);
+    } else if (b.kind == BODY_TORSIONAL) {
+      const double* ts = a.tors + b.tors * TS_COUNT;
+      double hx, hy, ang0;
+      tors_frame(a, b, &hx, &hy, &ang0);
+      const double dx = a.pos[2 * p] - hx, dy = a.pos[2 * p + 1] - hy;
+      tgt = comp == 0 ? -ts[TS_PHI] * dy : ts[TS_PHI] * dx;
+      if (b.moff >= 0) {
+        const double* q = a.poses + b.moff;
+        tgt += comp == 0 ? q[MF_VX] - q[MF_OM] * dy : q[MF_VY] + q[MF_OM] * dx;
+      }
+    } else {
+      tgt = a.zeta[b.dof0 + 3 * local + comp];
+    }
+    mx = fmax(mx, fabs(acc / a.h - tgt));
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = OUT_NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = red[0];
+  __syncthreads();
+  for (int bi = 0; bi < a.nbodies; ++bi) {
+    const BodyDev& b = a.bodies[bi];
+    for (int c = 0; c < 2; ++c) {
+      double sum = 0.0;
+      for (int k = tid; k < b.npts; k += OUT_NT) sum += a.f[2 * b.pt0 + c * b.npts + k];
+      red[tid] = sum;
+      __syncthreads();
+      for (int w = OUT_NT / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+      }
+      if (tid == 0) out[1 + 2 * bi + c] = red[0] * b.ds;
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_outputs(const FsiArgs& a, const T* s0, int ps, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_outputs<T>), dim3(1), dim3(OUT_NT), 0, st, a, s0, ps, out);
+  return hipGetLastError();
+}
+template hipError_t launch_outputs<float>(const FsiArgs&, const float*, int, double*, hipStream_t);
+template hipError_t launch_outputs<double>(const FsiArgs&, const double*, int, double*, hipStream_t);
+
 template hipError_t launch_body_ops<float>(const FsiArgs&, hipStream_t);
 template hipError_t launch_body_ops<double>(const FsiArgs&, hipStream_t);
 template hipError_t launch_spread<float>(const FsiArgs&, int, int, int, int, float*, int, hipStream_t);

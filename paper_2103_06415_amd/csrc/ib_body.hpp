@@ -61,6 +61,8 @@ struct FsiArgs {
   // level 0 geometry
   int n, ps;
   double h, x0, y0, ux, uy, dt;
+  int delta_kind;      // 0: 3-point kernel (Roma et al.), 1: 4-point kernel (Peskin); the
+                       // latter with the true E only
   const void* sstar;   // predictor streamfunction, float or double per fp64
   int fp64;
   // sub-domain
@@ -155,6 +157,7 @@ struct RefineJob {
   const int* gate;
   double* xcopy;
   int nb;
+  long spin;  // bound on the barrier's spins (0: the default)
 };
 // Launch shape of one refinement (as launch_refine chooses it); false if n is too large.
 struct RefineShape {
@@ -217,6 +220,10 @@ struct OffRows {
 
 template <typename T>
 hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st);
+// No-slip residual of the last step and the force of every body (see k_outputs): out holds
+// 1 + 2 nbodies doubles; s0 is level 0's streamfunction (ring included, pitch ps).
+template <typename T>
+hipError_t launch_outputs(const FsiArgs& a, const T* s0, int ps, double* out, hipStream_t st);
 // LDS of the sub-domain Schur assembly per body row (acc, pw, cid, pidx) and its cap
 constexpr size_t SCHUR_LDS_PER_ROW = 4 * (8 + 8 + 4 + 4);
 constexpr size_t SCHUR_LDS_PER_ROW_ALL4 = 4 * (4 * 8 + 8 + 4 + 4);  // four hat points at once
@@ -257,7 +264,10 @@ hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
 // otherwise flags[1] is raised when the residual stays above 1e-9
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, double* xcopy, hipStream_t st);
+                         const int* gate, double* xcopy, long spin, hipStream_t st);
+// Whether a refinement of n unknowns fits on the device at once (all its workgroups resident,
+// which its device-wide barrier needs); have / need: resident capacity and workgroups.
+bool refine_coresident(int n, int* have, int* need);
 size_t refine_ws_doubles(int n, int maxit);
 hipError_t launch_identity(double* X, int p, int n, hipStream_t st);
 // *out (zeroed by the caller) folds in max |W - I| over the n x n matrix (+Inf if not finite)

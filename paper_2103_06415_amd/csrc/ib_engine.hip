@@ -258,6 +258,22 @@ struct ib_solver {
   bool allocated = false;  // level state lives on the device (from ib_prepare on)
   bool released = false;   // device memory given back; results kept on the host
   std::vector<double> h_f, h_tors, h_chi, h_vort0;
+  // Schur solves without the device-wide barrier: LU of a copy of M (lu_always when the
+  // refinement's workgroups cannot all be resident; lu_step for the rest of a step whose
+  // refinement barrier timed out); barrier_spin: the barrier's spin bound (0: default)
+  bool lu_always = false, lu_step = false;
+  int64_t solve_fallbacks = 0;
+  long barrier_spin = 0;       // as set by IB_OPT_BARRIER_SPIN
+  bool barrier_force = false;  // IB_OPT_BARRIER_FORCE_TIMEOUT
+  // the refinement kernels' barrier argument: the bound, negated when every wait must time out
+  long barrier_arg() const {
+    const long b = barrier_spin > 0 ? barrier_spin : (1L << 22);
+    return barrier_force ? -b : barrier_spin;
+  }
+  // no-slip residual and body forces of the last step (k_outputs), for step out_step
+  double* dout = nullptr;
+  std::vector<double> h_out;
+  int64_t out_step = -1;
   int64_t step = 0;
   int iters_last = 0, iters_max = 0;
   double delta_last = 0;
@@ -968,8 +984,17 @@ ib_status prepare_bodies(ib_solver* s) {
     s->last_error = "sub-domain mode needs ib_set_subdomain";
     return IB_ERR_STATE;
   }
+  if (s->use_sd && s->cfg.delta != IB_DELTA_ROMA3) {
+    s->last_error = "the 4-point delta kernel is available with the exact operator only";
+    return IB_ERR_ARG;
+  }
   s->stationary = !s->use_sd && !any_moving;
   s->exact_moving = !s->use_sd && any_moving;
+  if (!s->stationary && s->nf > 0) {
+    // the refinement's device-wide barrier needs all its workgroups resident at once
+    int have = 0, need = 0;
+    s->lu_always = !refine_coresident(s->nf, &have, &need);
+  }
   for (auto& hb : s->bodies)
     if (hb.kind == BODY_DEFORMABLE && 3 * hb.m - 3 > 600) {
       s->last_error = "deformable body with more than 201 nodes";
@@ -1037,6 +1062,7 @@ ib_status prepare_bodies(ib_solver* s) {
   a.ux = s->cfg.u_inf[0] * h;
   a.uy = s->cfg.u_inf[1] * h;
   a.dt = s->cfg.dt;
+  a.delta_kind = s->cfg.delta;
   a.sstar = s->sstar;
   a.fp64 = s->fp64;
   a.use_sd = s->use_sd;
@@ -1162,6 +1188,7 @@ ib_status prepare_bodies(ib_solver* s) {
                                (double)a.pm};
     key.insert(key.end(), rigid_xy.begin(), rigid_xy.end());
     key.insert(key.end(), s->ds_rows.begin(), s->ds_rows.end());
+    key.push_back((double)s->cfg.delta);  // the delta kernel shapes E
     s->Minv = static_cast<double*>(dalloc(s, (size_t)nf * a.pm * 8 + 8));
     if (!s->Minv) return IB_ERR_OOM;
     st = acquire_op(s, key, [&](OpData& d) -> ib_status {
@@ -1354,6 +1381,14 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   }
   HIPCHK(launch_schur_sd(a, s->stream));
   const size_t mb = (size_t)nf * a.pm * 8;
+  if (s->lu_always || s->lu_step) {
+    // the stress solve without a device-wide barrier: LU with partial pivoting of a copy
+    HIPCHK(hipMemcpyAsync(s->Mtmp, a.M, mb, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->f, s->rhs, (size_t)nf * 8, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(launch_lu_solve(s->Mtmp, a.pm, s->f, 1, nf, 1, s->flags, s->stream));
+    HIPCHK(launch_update(a, it, K, s->cfg.newton_tol, s->cfg.newton_fixed_iter, s->stream));
+    return IB_OK;
+  }
   const bool fresh = !s->x_valid;
   if (fresh) {
     // fresh inverse of the current Schur matrix by LU on a copy
@@ -1376,7 +1411,7 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   }
   HIPCHK(launch_refine(a.M, a.pm, X, s->rhs, s->f, nf, REFINE_MAXIT,
                        it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, a.gate, xcopy,
-                       s->stream));
+                       s->barrier_arg(), s->stream));
   HIPCHK(launch_update(a, it, K, s->cfg.newton_tol, s->cfg.newton_fixed_iter, s->stream));
   return IB_OK;
 }
@@ -1427,7 +1462,7 @@ ib_status corrector(ib_solver* s, const int* gate) {
 // (device-side control, one host synchronisation per step).  The first use of the Schur
 // inverse (LU) and the exact operator (host-driven column solves) stay on the host path.
 bool fsi_ahead(const ib_solver* s) {
-  return !s->stationary && !s->exact_moving && s->x_valid && s->fsi_ahead;
+  return !s->stationary && !s->exact_moving && s->x_valid && s->fsi_ahead && !s->lu_always;
 }
 
 int fsi_ahead_count(const ib_solver* s) {
@@ -1451,6 +1486,19 @@ ib_status fsi_launch_ahead(ib_solver* s, int K) {
   return corrector<T>(s, s->gate);
 }
 
+// A refinement's device-wide barrier timed out (its workgroups were not all resident, e.g.
+// next to other solvers' kernels): the step's FSI iterations are redone from the old
+// structure state (the finish and corrector never ran) with LU solves, and the approximate
+// inverse, which that refinement may have left half refreshed, is rebuilt at its next use.
+ib_status begin_solve_fallback(ib_solver* s) {
+  HIPCHK(launch_step_reset(s->flags, s->stream));
+  s->lu_step = true;
+  s->x_valid = false;
+  s->x_valid_retry = false;
+  s->solve_fallbacks++;
+  return IB_OK;
+}
+
 // After the iterations launched ahead (and a synchronisation that brought the control block
 // to the host): converged, or go on on the host from where the device stopped.  *resume
 // receives the iteration to continue with, or -1 when the step's FSI part is complete.
@@ -1462,6 +1510,12 @@ ib_status fsi_after_ahead(ib_solver* s, int* resume) {
     s->iters_last = next;
     s->delta_last = s->hdelta[0];
     s->iters_max = std::max(s->iters_max, s->iters_last);
+    return IB_OK;
+  }
+  if (s->hflags[0] == FLAG_BARRIER) {
+    ib_status e = begin_solve_fallback(s);
+    if (e) return e;
+    *resume = 0;
     return IB_OK;
   }
   ib_status st = map_flags(s, s->hflags[0]);
@@ -1503,6 +1557,12 @@ ib_status fsi_host(ib_solver* s, int it0) {
     if (e) return e;
     HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->hflags[0] == FLAG_BARRIER && !s->lu_step) {
+      e = begin_solve_fallback(s);
+      if (e) return e;
+      it = 0;
+      continue;
+    }
     ib_status st = map_flags(s, s->hflags[0]);
     if (st) return st;
     if (s->hflags[1]) {
@@ -1537,6 +1597,7 @@ ib_status fsi_host(ib_solver* s, int it0) {
     ++it;
   }
   s->iters_max = std::max(s->iters_max, s->iters_last);
+  s->lu_step = false;
   return corrector<T>(s, nullptr);
 }
 
@@ -2415,7 +2476,7 @@ ib_status batch_step(ib_batch* b) {
         const int c = sh.two ? 2 : sh.cache ? 1 : 0;
         rj[c].push_back(RefineJob{a.M, X, a.pm, s->rhs, s->f, nf, sh.rw, sh.tpr, REFINE_MAXIT,
                                   it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags,
-                                  s->gate, xcopy, sh.nb});
+                                  s->gate, xcopy, sh.nb, s->barrier_arg()});
         rnb[c] = std::max(rnb[c], sh.nb);
         rlds[c] = std::max(rlds[c], sh.lds);
       }
@@ -2722,6 +2783,32 @@ ib_status tune_flow(ib_solver* s) {
   return IB_OK;
 }
 
+// No-slip residual of the last step and the force of every body, computed on the device
+// (k_outputs) once per step and kept on the host, so that they stay readable after
+// ib_release.  Nothing to do before the first step, without bodies, or once released.
+template <typename T>
+ib_status compute_outputs_t(ib_solver* s) {
+  const size_t cnt = 1 + 2 * (size_t)s->fa.nbodies;
+  if (!s->dout) {
+    s->dout = static_cast<double*>(dalloc(s, cnt * 8));
+    if (!s->dout) return IB_ERR_OOM;
+  }
+  HIPCHK(launch_outputs<T>(s->fa, static_cast<const T*>(s->lv[0].s), s->pitch, s->dout,
+                           s->stream));
+  s->h_out.assign(cnt, 0.0);
+  HIPCHK(hipMemcpyAsync(s->h_out.data(), s->dout, cnt * 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->out_step = s->step;
+  return IB_OK;
+}
+
+ib_status compute_outputs(ib_solver* s) {
+  if (!s->prepared || s->released || !s->allocated || s->bodies.empty() || s->step == 0 ||
+      s->failed || s->out_step == s->step)
+    return IB_OK;
+  return s->fp64 ? compute_outputs_t<double>(s) : compute_outputs_t<float>(s);
+}
+
 extern "C" {
 
 const char* ib_status_str(ib_status st) {
@@ -2736,6 +2823,7 @@ const char* ib_status_str(ib_status st) {
     case IB_ERR_NEAR_BOUNDARY: return "delta support reaches the finest level's boundary";
     case IB_ERR_NONFINITE: return "non-finite value";
     case IB_ERR_CAPACITY: return "output buffer too small";
+    case IB_ERR_BUDGET: return "over the device-memory budget";
     case IB_ERR_SCRATCH: return "larger than the fixed device scratch of an allocation-free call";
     default: return "unknown status";
   }
@@ -2749,7 +2837,7 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
       !(cfg->h > 0) || !(cfg->dt > 0) || !(cfg->re > 0) ||
       (cfg->precision != IB_FP64 && cfg->precision != IB_FP32_FLOW &&
        cfg->precision != IB_FP32_FLOW_BF16_DST) || cfg->schur_mode < 0 ||
-      cfg->schur_mode > 2)
+      cfg->schur_mode > 2 || (cfg->delta != IB_DELTA_ROMA3 && cfg->delta != IB_DELTA_PESKIN4))
     return IB_ERR_ARG;
   ib_solver* s = new ib_solver();
   s->cfg = *cfg;
@@ -2977,6 +3065,22 @@ ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap
   return IB_OK;
 }
 
+ib_status ib_read_force(ib_solver* s, int32_t body_id, double* out, int64_t cap) {
+  HipShared hip_lock;
+  if (check(s) || !out || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
+  if (!s->prepared) return IB_ERR_STATE;
+  if (cap < 2) return IB_ERR_CAPACITY;
+  const ib_status st = compute_outputs(s);
+  if (st) return st;
+  if (s->out_step < 0 || s->h_out.size() < 3 + 2 * (size_t)body_id) {
+    out[0] = out[1] = 0.0;  // no step taken yet
+    return IB_OK;
+  }
+  out[0] = s->h_out[1 + 2 * body_id];
+  out[1] = s->h_out[2 + 2 * body_id];
+  return IB_OK;
+}
+
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap) {
   HipShared hip_lock;
   if (check(s) || !out || body_id < 0 || body_id >= (int)s->bodies.size()) return IB_ERR_ARG;
@@ -3148,7 +3252,21 @@ const char* ib_last_error(const ib_solver* s) {
 
 ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   if (check(s) || !out) return IB_ERR_ARG;
+  {
+    HipShared hip_lock;
+    const ib_status st = compute_outputs(s);
+    if (st) return st;
+  }
   std::memset(out, 0, sizeof(*out));
+  out->converged = s->bodies.empty() || s->step == 0 || s->delta_last <= s->cfg.newton_tol;
+  if (s->out_step >= 0 && !s->h_out.empty()) {
+    out->noslip_resid = s->h_out[0];
+    const size_t nb = (s->h_out.size() - 1) / 2;
+    for (size_t b = 0; b < nb; ++b) {
+      out->force[0] += s->h_out[1 + 2 * b];
+      out->force[1] += s->h_out[2 + 2 * b];
+    }
+  }
   out->step = s->step;
   out->newton_iters = s->iters_last;
   out->newton_iters_max = s->iters_max;
@@ -3163,11 +3281,25 @@ ib_status ib_get_stats(ib_solver* s, ib_stats* out) {
   out->graph_launches = s->graph_launches;
   out->graph_captures = s->graph_captures;
   out->fsi_resumes = s->fsi_resumes;
+  out->solve_fallbacks = s->solve_fallbacks;
+  out->solve_by_lu = s->lu_always ? 1 : 0;
   return IB_OK;
 }
 
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value) {
   HipShared hip_lock;
+  if (option == IB_OPT_BARRIER_SPIN) {
+    if (check(s) || value < 0 || value > (int64_t(1) << 40)) return IB_ERR_ARG;
+    s->barrier_spin = (long)value;
+    destroy_graphs(s);
+    return IB_OK;
+  }
+  if (option == IB_OPT_BARRIER_FORCE_TIMEOUT) {
+    if (check(s) || value < 0 || value > 1) return IB_ERR_ARG;
+    s->barrier_force = value != 0;
+    destroy_graphs(s);
+    return IB_OK;
+  }
   const int vmax = option == IB_OPT_REFRESH_EVERY_ITER || option == IB_OPT_TOP_AHEAD ? 2 : 1;
   if (check(s) || value < 0 || value > vmax) return IB_ERR_ARG;
   if (option == IB_OPT_FSI_AHEAD) {
@@ -3276,6 +3408,10 @@ ib_status ib_release(ib_solver* s) {
     HIPCHK(hipStreamSynchronize(s->stream));
     if (s->side) HIPCHK(hipStreamSynchronize(s->side));
     destroy_graphs(s);
+    {
+      const ib_status st = compute_outputs(s);
+      if (st) return st;
+    }
     if (s->prepared && s->f) {
       s->h_f.resize(s->nf);
       HIPCHK(hipMemcpy(s->h_f.data(), s->f, (size_t)s->nf * 8, hipMemcpyDeviceToHost));
@@ -3294,6 +3430,7 @@ ib_status ib_release(ib_solver* s) {
   harvest_events(s);
   while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
   s->f = nullptr;
+  s->dout = nullptr;
   s->allocated = false;
   s->released = true;
   return IB_OK;

@@ -87,7 +87,7 @@ ib_status ib_server_submit(ib_server* sv, ib_solver* s, int32_t nsteps, double a
   ib_status st = ib_estimate_bytes(s, &resident, &peak);
   if (st) return st;
   r.bytes = peak;
-  if (r.bytes > sv->budget) return IB_ERR_CAPACITY;
+  if (r.bytes > sv->budget) return IB_ERR_BUDGET;
   r.info.ticket = (int64_t)sv->req.size();
   r.info.status = 1;  // waiting
   r.info.arrival = arrival;

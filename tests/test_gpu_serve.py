@@ -98,6 +98,12 @@ def test_admission_respects_the_memory_budget(torch_cuda, gpu_lib):
         assert b["admitted"] >= a["finished"] - 1e-6, (a, b)
     for i in infos:
         assert i["status"] == 0
+    # a request whose estimate exceeds the whole budget can never be admitted
+    tiny = binding.Server(max_active=1, hbm_budget_bytes=min(sizes) - 1, chunk_steps=3)
+    with pytest.raises(binding.IbError) as e:
+        tiny.submit(solvers[0], 1)
+    assert e.value.code == binding.IB_ERR_BUDGET
+    tiny.close()
     for s in solvers:
         s.close()
     server.close()

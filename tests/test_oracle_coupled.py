@@ -122,8 +122,10 @@ def test_block_lu_equals_dense_coupled_solve(with_beam):
                                atol=1e-11 * np.abs(x[:m]).max())
 
 
-def test_noslip_residual_exact_mode():
+@pytest.mark.parametrize("kernel", ["roma3", "peskin4"])
+def test_noslip_residual_exact_mode(kernel):
     p = W.cylinder_problem(n=32, steps=2)
+    p.flow.delta = kernel
     o = Oracle(p)
     for _ in range(2):
         o.step()
@@ -137,8 +139,10 @@ def test_noslip_residual_moving_exact_mode():
         assert o.noslip_residual() < 1e-11
 
 
-def test_stationary_schur_block_is_spd():
+@pytest.mark.parametrize("kernel", ["roma3", "peskin4"])
+def test_stationary_schur_block_is_spd(kernel):
     p = W.cylinder_problem(n=32, steps=1)
+    p.flow.delta = kernel
     o = Oracle(p)
     o.prepare()
     g = o.g_static

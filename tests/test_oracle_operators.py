@@ -199,11 +199,28 @@ def test_roma_kernel_moments():
         assert abs((w * w).sum() - 0.5) < 1e-14
 
 
-def test_interpolation_reproduces_linear_fields_and_conserves_force():
+def test_peskin_kernel_moments():
+    """Peskin's 4-point kernel: for any shift the weights sum to 1, have zero first moment,
+    split evenly between even and odd offsets (1/2 each), and their squares sum to 3/8."""
+    rng = np.random.default_rng(4)
+    for shift in rng.uniform(-0.5, 0.5, size=20):
+        j = np.arange(-4, 5)
+        r = j - shift
+        w = delta.peskin4(r)
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs((r * w).sum()) < 1e-14
+        assert abs(w[j % 2 == 0].sum() - 0.5) < 1e-14
+        assert abs((w * w).sum() - 0.375) < 1e-14
+    assert delta.peskin4(np.array([2.0, -2.0, 2.5]))[:].max() == 0.0
+    np.testing.assert_allclose(delta.peskin4(np.array([0.0, 1.0])), [0.5, 0.25], atol=1e-15)
+
+
+@pytest.mark.parametrize("kernel", ["roma3", "peskin4"])
+def test_interpolation_reproduces_linear_fields_and_conserves_force(kernel):
     lv = grid.Level(W.Flow(n=32, levels=1, h=0.1, dt=0.01, re=1.0), 0)
     rng = np.random.default_rng(3)
     pts = rng.uniform(-0.8, 0.8, size=(7, 2))
-    e = delta.interpolation_matrix(lv, pts)
+    e = delta.interpolation_matrix(lv, pts, kernel)
     (xfx, xfy), (yfx, yfy) = lv.face_coords()
     ux = 0.3 + 1.1 * xfx[None, :] - 0.7 * xfy[:, None]
     uy = -0.2 + 0.4 * yfx[None, :] + 0.9 * yfy[:, None]
@@ -221,6 +238,12 @@ def test_support_check_rejects_points_near_the_edge():
     e = delta.interpolation_matrix(lv, np.array([[0.0, 0.0]]))
     delta.check_support(lv, e)
     e = delta.interpolation_matrix(lv, np.array([[0.75, 0.0]]))
+    with pytest.raises(ValueError):
+        delta.check_support(lv, e)
+    # the 4-point kernel reaches half a cell further: accepted with the 3-point one only
+    e = delta.interpolation_matrix(lv, np.array([[0.6, 0.0]]))
+    delta.check_support(lv, e)
+    e = delta.interpolation_matrix(lv, np.array([[0.6, 0.0]]), "peskin4")
     with pytest.raises(ValueError):
         delta.check_support(lv, e)
 

@@ -31,6 +31,7 @@ class Flow:
     cx: float = 0.0      # common centre of all levels
     cy: float = 0.0
     u_inf: tuple = (1.0, 0.0)
+    delta: str = "roma3"  # discrete delta kernel: "roma3" (3-point) or "peskin4" (4-point)
 
 
 @dataclasses.dataclass
