@@ -40,8 +40,28 @@ TRAFFIC_PER_LAUNCH = {
 }
 
 
+def survey_bytes_per_launch(cls, n, es):
+    """Algorithmic bytes of one launch in the fused three-pass Poisson model: words per
+    interior vertex for the pass times the (n-1)^2 vertices a launch covers.  Pass 1
+    (right-hand side + row transform) reads s and the AB2 history and writes the history and
+    the rows, 4 words; pass 2 (column transform, spectral divide, inverse column transform)
+    reads and writes the array once, 2 words; pass 3 (inverse row transform) 2 words."""
+    words = {"rhs_rowdst": 4, "col_solve": 2, "row_idst": 2}[cls]
+    return words * (n - 1) ** 2 * es
+
+
+def step_bytes(n, levels, es):
+    """Algorithmic bytes of one step: w n^2 (8 G + 4 + 6 (G - 1)) -- 8 words per level for the
+    predictor, 4 for the corrector on level 0 (its source is sparse), 6 per coarse level for
+    the re-solve after coarsification (counted although the reading used here coarsifies on
+    read and spends no extra solve)."""
+    return es * n * n * (8 * levels + 4 + 6 * (levels - 1))
+
+
 def algorithmic_bytes(cls, n, levels, steps, es, body_rows):
-    """Bytes a launch class must move per timed region (roofline)."""
+    """Bytes a launch class of this design moves per timed region: it carries the
+    circulation as state beside s, so a level's passes move 12 words per vertex (5 + 3 + 4)
+    where the three-pass model counts 8."""
     m = (n - 1) ** 2
     full = (n + 1) ** 2
     if cls == "col_solve":
@@ -259,31 +279,127 @@ def exact_compare(make, tors_body, force_bodies, steps, workload):
     return out
 
 
-def cpu_baseline(n, levels, seconds=20.0):
-    """The FP64 oracle on the host: flow steps of the same grid (no body coupling)."""
+# ---- CPU leg: the FP64 oracle on the host cores (run as a child process of this script,
+# with the BLAS thread variables set in its environment before numpy is imported; the child
+# touches no GPU) ----
+
+def _host_info():
+    import platform
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
+    try:
+        import threadpoolctl
+        blas = [{"library": d.get("internal_api"), "threads": d.get("num_threads")}
+                for d in threadpoolctl.threadpool_info() if d.get("user_api") == "blas"]
+    except Exception:
+        blas = []
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "blas": blas}
+
+
+def _oracle_coupled(n, levels, seconds, max_steps=400):
+    """The full step of the flag workload (predictor on every level, FSI iterations on the
+    sub-domain Schur system with the beam's Newton update, corrector); B' built first and
+    reported apart, as the paper excludes the offline stage."""
+    import workloads as W
+    from oracle.step import Oracle
+    o = Oracle(W.flag_problem(n=n, levels=levels))
+    t0 = time.perf_counter()
+    o.prepare()
+    prep = time.perf_counter() - t0
+    o.step()  # warm-up (the first step has no history)
+    k = 0
+    t0 = time.perf_counter()
+    while k < max_steps:
+        o.step()
+        k += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": n * n * levels * k / wall, "steps": k, "wall_s": wall,
+            "ms_per_step": 1e3 * wall / k, "offline_s": prep,
+            "subdomain_rows": int(o.b_filtered.shape[0]), "newton_iters_last": o.last_iters}
+
+
+def _oracle_flow(n, levels, seconds, max_steps=50):
+    """Flow steps of the headline grid without body coupling (B' at 1024^2 is out of the
+    oracle's reach: about 100,000 dense point-source solves)."""
     import numpy as np
 
     import workloads as W
     from oracle.step import Oracle
     p = W.flag_problem(n=n, levels=levels)
-    flow = W.Problem("flow", p.flow, [], vorticity0=None)
-    o = Oracle(flow)
+    o = Oracle(W.Problem("flow", p.flow, [], vorticity0=None))
     rng = np.random.default_rng(0)
     o.s[0][1:-1, 1:-1] = 1e-3 * rng.normal(size=(n - 1, n - 1))
+    o.step()
     k = 0
     t0 = time.perf_counter()
-    while True:
+    while k < max_steps:
         o.step()
         k += 1
-        if time.perf_counter() - t0 > seconds or k >= 50:
+        if time.perf_counter() - t0 > seconds:
             break
     wall = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": n * n * levels * k / wall, "unit": "grid-cell steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{k} oracle flow steps of the {n}^2 x {levels}-level grid (dense FP64 "
-                      f"sine-matrix solves on every level, nonlinear term, rings; no body "
-                      f"coupling), {wall:.1f} s"}
+    return {"value": n * n * levels * k / wall, "steps": k, "wall_s": wall,
+            "ms_per_step": 1e3 * wall / k}
+
+
+def cpu_leg(args):
+    out = {"coupled": _oracle_coupled(args.cpu_n, args.levels, args.cpu_seconds)}
+    if args.cpu_flow_n > 0:
+        out["flow"] = _oracle_flow(args.cpu_flow_n, args.levels, args.cpu_seconds)
+    out["host"] = _host_info()  # after numpy has loaded its BLAS
+    print(json.dumps(out))
+
+
+def cpu_baseline(n_coupled, n_flow, levels, gpu_coupled, seconds=10.0):
+    """The oracle in two child processes, one BLAS thread and the default count; the
+    coupled-step figure at n_coupled x levels is the baseline (the GPU's throughput on the
+    same workload beside it), the flow-only figure on the headline grid comes second."""
+    import subprocess
+    runs = {}
+    for label, threads in (("one_thread", "1"), ("all_threads", None)):
+        env = dict(os.environ)
+        if threads is not None:
+            for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+                env[var] = threads
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--cpu-n", str(n_coupled),
+               "--cpu-flow-n", str(n_flow if threads is None else 0), "--levels", str(levels),
+               "--cpu-seconds", str(seconds)]
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode != 0:
+            runs[label] = {"error": r.stderr[-400:]}
+            continue
+        runs[label] = json.loads(r.stdout.strip().splitlines()[-1])
+    allc = runs.get("all_threads", {})
+    one = runs.get("one_thread", {})
+    host = allc.get("host", {})
+    threads = max([b.get("threads") or 0 for b in host.get("blas", [])] or [0]) or host.get("nproc")
+    coupled = allc.get("coupled", {})
+    out = {"value": coupled.get("value"), "unit": "grid-cell steps/s", "cores": threads,
+           "kind": "oracle",
+           "sample": (f"{coupled.get('steps')} full coupled oracle steps of the flag workload at "
+                      f"{n_coupled}^2 x {levels} levels (dense FP64 sine-matrix solves on every "
+                      f"level, sub-domain Schur system and beam Newton update by numpy.linalg, "
+                      f"corrector), {coupled.get('wall_s', 0):.1f} s after B' was built in "
+                      f"{coupled.get('offline_s', 0):.1f} s"),
+           "one_thread_value": one.get("coupled", {}).get("value"),
+           "host": host,
+           "gpu_same_workload": gpu_coupled,
+           "flow_1024x4": allc.get("flow")}
+    if out["value"] and gpu_coupled and gpu_coupled.get("value_fp32"):
+        out["gpu_fp32_over_oracle"] = gpu_coupled["value_fp32"] / out["value"]
+    return out
 
 
 def tuning_summary(t):
@@ -317,16 +433,27 @@ def main():
     ap.add_argument("--concurrent", type=int, default=4,
                     help="also run this many copies of the workload concurrently (0: skip)")
     ap.add_argument("--batch", action="store_true",
-                    help="also run the 64-instance batch (sizes 128^2..768^2) as one ib_batch "
-                         "and through the scheduler")
+                    help="also run the 64 instances through the scheduler")
+    ap.add_argument("--no-batch64", action="store_true",
+                    help="skip the 64-instance batch (sizes 128^2..768^2) as one ib_batch")
+    ap.add_argument("--no-plate", action="store_true",
+                    help="skip the plate workload (512^2 x 3, FP32 and FP64)")
     ap.add_argument("--batch-copies", type=int, default=4,
                     help="also step this many copies of the workload as one ib_batch (0: skip)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch legs (--batch-copies, --batch); for profiling them")
+    ap.add_argument("--cpu-leg", action="store_true",
+                    help="(internal) the oracle's CPU timing, run as a child process")
+    ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--cpu-flow-n", type=int, default=1024)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware counter calibration)")
     args = ap.parse_args()
+    if args.cpu_leg:
+        cpu_leg(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: each MI355X box here has one, and the "
               "single-instance step does not shard across GPUs (see DESIGN.md).", file=sys.stderr)
@@ -349,7 +476,7 @@ def main():
                "data": "synthetic", "legs": "batch only"}
         if args.batch_copies > 0:
             out["batch_copies"] = batch_run([prob] * args.batch_copies, args.steps, 3)
-        if args.batch:
+        if not args.no_batch64:
             out["batch64"] = batch_run(W.batch_problems(), args.steps, 3)
         print(json.dumps(out))
         return
@@ -378,7 +505,10 @@ def main():
     dom_variant = st32["flow_tuning"][{"rhs_rowdst": "rhs", "col_solve": "col",
                                        "row_idst": "idst"}[dom] + "_variant"]
     tot_bytes = algorithmic_bytes(dom, n, levels, args.steps, 4, body_rows)
-    achieved = tot_bytes / (ms * 1e-3) if ms > 0 else 0.0
+    avg_launch_s = ms * 1e-3 / max(launches, 1)
+    alg_launch = survey_bytes_per_launch(dom, n, 4)
+    achieved = alg_launch / avg_launch_s if ms > 0 else 0.0
+    sbytes = step_bytes(n, levels, 4)
     times_ms = {k: round(v[1] / args.steps, 5) for k, v in kt.items()}
     out = {
         "metric": METRIC,
@@ -415,8 +545,13 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM,
                      "traffic": (TRAFFIC_PER_LAUNCH.get((dom, dom_variant)) if n == 1024 else None),
                      "variant": dom_variant,
-                     "bytes_per_launch": tot_bytes / max(launches, 1),
-                     "avg_launch_us": 1e3 * ms / max(launches, 1)},
+                     "algorithmic_bytes_per_launch": alg_launch,
+                     "design_bytes_per_launch": tot_bytes / max(launches, 1),
+                     "design_over_algorithmic": (tot_bytes / max(launches, 1)) / alg_launch,
+                     "avg_launch_us": 1e6 * avg_launch_s,
+                     "step_bytes": sbytes,
+                     "step_achieved": sbytes / (wall32 / args.steps) / 1e9,
+                     "step_frac": sbytes / (wall32 / args.steps) / PEAK_HBM},
     }
     if args.concurrent > 1:
         out["concurrent"] = concurrent(prob, args.concurrent, args.steps)
@@ -445,14 +580,36 @@ def main():
         out["batch_copies"]["workload"] = (f"{args.batch_copies} copies of the flag workload as "
                                            "one batch (one launch per kernel for all), FP32 flow")
     if args.batch:
-        out["batch64"] = batch_run(W.batch_problems(), 20, 3, alone_steps=5)
-        out["batch64"]["workload"] = ("64 instances, 128^2..768^2 x 1-3 levels, 1-3 rigid or "
-                                      "torsional bodies, one batch, FP32 flow")
         out["batched"] = serve([(0.0, p) for p in W.batch_problems()], max_active=16)
         out["batched"]["workload"] = ("the same 64 instances (200 steps) through the scheduler, "
                                       "16 slots")
+    # the plate workload: 512^2 x 3 levels, FP32 flow next to the plain FP64 form
+    if not args.no_plate:
+        pl = W.plate_problem(n=512, levels=3)
+        pc = 512 * 512 * 3
+        w32, p32, _, s32 = run(pl, binding.IB_FP32_FLOW, args.steps, args.warmup, timing=False)
+        w64p, _, _, _ = run(pl, binding.IB_FP64, args.steps, args.warmup, timing=False)
+        out["plate_512x3"] = {"value_fp32": pc * args.steps / w32, "value_fp64": pc * args.steps / w64p,
+                              "ms_per_step_fp32": 1e3 * w32 / args.steps,
+                              "ms_per_step_fp64": 1e3 * w64p / args.steps, "prepare_s": p32,
+                              "newton_iters_max": s32["newton_iters_max"],
+                              "workload": "torsional plate (51 points, I 5, k 1, c 0.1, 20 deg), "
+                                          "512^2 x 3 levels, Re 200, sub-domain B', FSI tol 1e-7"}
+    if not args.no_batch64:
+        out["batch64"] = batch_run(W.batch_problems(), 20, 3, alone_steps=5)
+        out["batch64"]["workload"] = ("64 instances, 128^2..768^2 x 1-3 levels, 1-3 rigid or "
+                                      "torsional bodies, one batch, FP32 flow")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, levels)
+        # the GPU on the oracle's coupled sample (the flag at 128^2 x 4)
+        small = W.flag_problem(n=args.cpu_n, levels=levels)
+        sc = args.cpu_n ** 2 * levels
+        k = max(args.steps, 200)
+        w32s, _, _, _ = run(small, binding.IB_FP32_FLOW, k, args.warmup, timing=False)
+        w64s, _, _, _ = run(small, binding.IB_FP64, k, args.warmup, timing=False)
+        gpu_small = {"value_fp32": sc * k / w32s, "value_fp64": sc * k / w64s,
+                     "ms_per_step_fp32": 1e3 * w32s / k, "ms_per_step_fp64": 1e3 * w64s / k,
+                     "steps": k}
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, n, levels, gpu_small, args.cpu_seconds)
     print(json.dumps(out))
 
 
