@@ -310,27 +310,32 @@ ib_status ib_destroy(ib_solver* s);
 ib_status ib_set_option(ib_solver* s, int32_t option, int64_t value);
 
 /* ---- measured kernel configurations of the sine transforms ----
- * For single-precision flow and n >= 256, ib_prepare times IB_FLOW_VARIANTS configurations
- * of each of three kernels (right-hand side + row transform, column solve, inverse row
- * transform) on scratch buffers of one level's shape and keeps the fastest; the choice is
- * remembered per n for the process.  A configuration fixes the rows (or columns) per
- * workgroup, the threads per workgroup and the largest FFT radix (16, 8 or 4) of the
- * Stockham stages (Sec. 3.2.1 transforms).  All configurations compute the same
- * transforms; they differ in rounding order only. */
-#define IB_FLOW_VARIANTS 8
+ * For single-precision flow and n in {256, 384, 512, 768, 1024}, ib_prepare times the
+ * configurations of each of three kernels (right-hand side + row transform, column solve,
+ * inverse row transform) on scratch buffers of one level's shape and keeps the fastest; the
+ * choice is remembered per n for the process.  Row kernels have 8 configurations (0 .. 7)
+ * and the column solve 9 (0 .. 8).  Configurations 0 .. 7 fix the rows (or columns) per
+ * workgroup, the threads per workgroup and the largest FFT radix (16, 8 or 4) of the LDS
+ * Stockham stages (Sec. 3.2.1 transforms).  Column configuration 8 exists for n = 1024: each
+ * column's transform of length 1024 = 32 x 32 runs in registers on 32 lanes of one wave,
+ * with one LDS transpose per transform and no workgroup barrier between its stages
+ * (ib_flow_variant_info reports it as 4 columns, 128 threads, radix 32).  All
+ * configurations compute the same transforms; they differ in rounding order only. */
+#define IB_FLOW_VARIANTS 9
 typedef struct {
   int32_t n;             /* grid size the choice was made for (0: none, defaults used) */
   int32_t rhs_variant;   /* chosen configurations, 0 .. IB_FLOW_VARIANTS-1 */
   int32_t col_variant;
   int32_t idst_variant;
   double rhs_us[IB_FLOW_VARIANTS];  /* measured average launch time (microseconds; */
-  double col_us[IB_FLOW_VARIANTS];  /*   0 where not measured) */
+  double col_us[IB_FLOW_VARIANTS];  /*   0 where not measured or not available for n) */
   double idst_us[IB_FLOW_VARIANTS];
 } ib_flow_tuning;
 ib_status ib_get_flow_tuning(ib_solver* s, ib_flow_tuning* out);
 
 /* Fix the configurations instead of measuring (before or after ib_prepare).  Nonzero
- * variants need single precision and n >= 256 (IB_ERR_ARG otherwise); -1 keeps one as is. */
+ * variants need single precision and one of the measured sizes, column configuration 8
+ * n = 1024 (IB_ERR_ARG otherwise); -1 keeps one as is. */
 ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t idst);
 
 /* Configuration `variant` of kind 0 (row kernels: rows per workgroup) or 1 (column solve:

@@ -70,7 +70,7 @@ class IbStats(ctypes.Structure):
     ]
 
 
-FLOW_VARIANTS = 8
+FLOW_VARIANTS = 9
 IB_OPT_FSI_AHEAD, IB_OPT_GRAPHS, IB_OPT_REFRESH_EVERY_ITER, IB_OPT_TOP_AHEAD = 1, 2, 3, 4
 IB_OPT_BARRIER_SPIN, IB_OPT_BARRIER_FORCE_TIMEOUT = 5, 6
 

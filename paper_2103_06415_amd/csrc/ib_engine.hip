@@ -2769,10 +2769,12 @@ ib_status tune_flow(ib_solver* s) {
   int* pick[3] = {&t.rhs, &t.col, &t.idst};
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     if (k == 0 && s->gemm) continue;  // the matrix-core path has its own right-hand side pass
-    for (int v = 0; v < ib::FLOW_VARIANTS && e == hipSuccess; ++v) e = measure(k, v, &tabs[k][v]);
+    const int kind = k == 1 ? 1 : 0;
+    for (int v = 0; v < ib::FLOW_VARIANTS && e == hipSuccess; ++v)
+      if (ib::flow_kind_variant_available(kind, v, n, 0)) e = measure(k, v, &tabs[k][v]);
     int b = 0;
     for (int v = 1; v < ib::FLOW_VARIANTS; ++v)
-      if (tabs[k][v] < tabs[k][b]) b = v;
+      if (tabs[k][v] > 0.0 && tabs[k][v] < tabs[k][b]) b = v;
     *pick[k] = b;
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -3346,7 +3348,8 @@ ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t i
   const int32_t v[3] = {rhs, col, idst};
   for (int k = 0; k < 3; ++k) {
     if (v[k] < -1 || v[k] >= IB_FLOW_VARIANTS) return IB_ERR_ARG;
-    if (v[k] > 0 && !ib::flow_variant_available(s->n, s->fp64 ? 1 : 0)) return IB_ERR_ARG;
+    if (v[k] > 0 && !ib::flow_kind_variant_available(k == 1 ? 1 : 0, v[k], s->n, s->fp64 ? 1 : 0))
+      return IB_ERR_ARG;
   }
   if (rhs > 0 && s->gemm) return IB_ERR_ARG;
   if (rhs >= 0) s->tune.rhs = rhs;
@@ -3359,7 +3362,8 @@ ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t i
 
 ib_status ib_flow_variant_info(int32_t kind, int32_t variant, int32_t* width, int32_t* threads,
                                int32_t* max_radix) {
-  if ((kind != 0 && kind != 1) || variant < 0 || variant >= IB_FLOW_VARIANTS || !width ||
+  if ((kind != 0 && kind != 1) || variant < 0 ||
+      variant >= (kind == 0 ? ib::ROW_VARIANT_COUNT : ib::COL_VARIANT_COUNT) || !width ||
       !threads || !max_radix)
     return IB_ERR_ARG;
   const ib::FlowVariant& f = kind == 0 ? ib::ROW_VARIANTS[variant] : ib::COL_VARIANTS[variant];

@@ -55,11 +55,19 @@ bool flow_variant_available(int n, int fp64) {
   return !fp64 && (n == 256 || n == 384 || n == 512 || n == 768 || n == 1024);
 }
 
+bool flow_kind_variant_available(int kind, int v, int n, int fp64) {
+  if (v == 0) return true;
+  if (v < 0 || !flow_variant_available(n, fp64)) return false;
+  if (kind == 0) return v < ROW_VARIANT_COUNT;
+  if (v == COL_REG_VARIANT) return n == 1024;
+  return v < COL_VARIANT_COUNT;
+}
+
 template <typename T>
 hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st, int transform) {
   if constexpr (sizeof(T) == 4) {
     if (a.var != 0) {
-      if (!transform || a.var < 0 || a.var >= FLOW_VARIANTS || !flow_variant_available(a.n, 0))
+      if (!transform || !flow_kind_variant_available(0, a.var, a.n, 0))
         return hipErrorInvalidValue;
       return launch_rhs_rowdst_var(a, tw, st);
     }
@@ -92,8 +100,7 @@ hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* t
                             hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
     if (a.var != 0) {
-      if (a.var < 0 || a.var >= FLOW_VARIANTS || !flow_variant_available(n, 0))
-        return hipErrorInvalidValue;
+      if (!flow_kind_variant_available(1, a.var, n, 0)) return hipErrorInvalidValue;
       return launch_col_solve_var(a, n, batch, tw, lam, st);
     }
   }
@@ -118,8 +125,7 @@ hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw
                            int ring_rows, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
     if (a.var != 0 && a.in2 != nullptr) {
-      if (a.var < 0 || a.var >= FLOW_VARIANTS || !flow_variant_available(n, 0))
-        return hipErrorInvalidValue;
+      if (!flow_kind_variant_available(0, a.var, n, 0)) return hipErrorInvalidValue;
       return launch_row_idst_var(a, n, batch, tw, ring, ring_rows, st);
     }
   }

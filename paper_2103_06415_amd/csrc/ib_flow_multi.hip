@@ -35,8 +35,7 @@ hipError_t launch_rhs_rowdst_multi(const RhsArgs<T>* tab, int count, int n, int 
   if (count <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
     if (var != 0) {
-      if (var < 0 || var >= FLOW_VARIANTS || !flow_variant_available(n, 0))
-        return hipErrorInvalidValue;
+      if (!flow_kind_variant_available(0, var, n, 0)) return hipErrorInvalidValue;
       return launch_rhs_rowdst_multi_var(tab, count, n, var, tw, st);
     }
   }
@@ -54,8 +53,7 @@ hipError_t launch_col_solve_multi(const ColArgs<T>* tab, int count, int n, int v
   if (count <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
     if (var != 0) {
-      if (var < 0 || var >= FLOW_VARIANTS || !flow_variant_available(n, 0))
-        return hipErrorInvalidValue;
+      if (!flow_kind_variant_available(1, var, n, 0)) return hipErrorInvalidValue;
       return launch_col_solve_multi_var(tab, count, n, var, tw, lam, st);
     }
   }
@@ -74,8 +72,7 @@ hipError_t launch_row_idst_multi(const IdstJob<T>* tab, int count, int n, int ma
   if (count <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
     if (var != 0 && dual) {
-      if (var < 0 || var >= FLOW_VARIANTS || !flow_variant_available(n, 0))
-        return hipErrorInvalidValue;
+      if (!flow_kind_variant_available(0, var, n, 0)) return hipErrorInvalidValue;
       return launch_row_idst_multi_var(tab, count, n, maxrows, var, tw, st);
     }
   }

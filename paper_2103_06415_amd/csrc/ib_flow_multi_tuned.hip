@@ -1,6 +1,7 @@
 // The measured alternative configurations (ROW_VARIANTS, COL_VARIANTS) of the single-precision
 // flow kernels for many instances of one grid size per launch.
 #include "ib_flow_kernels.hpp"
+#include "ib_flow_reg.hpp"
 
 namespace ib {
 
@@ -14,7 +15,7 @@ constexpr FlowVariant CV = COL_VARIANTS[V];
 template <int N, int V>
 hipError_t rhs_mv(const RhsArgs<float>* tab, int count, int var, const c2<float>* t,
                   hipStream_t st) {
-  if constexpr (V >= FLOW_VARIANTS) {
+  if constexpr (V >= ROW_VARIANT_COUNT) {
     return hipErrorInvalidValue;
   } else {
     if (var != V) return rhs_mv<N, V + 1>(tab, count, var, t, st);
@@ -25,18 +26,23 @@ hipError_t rhs_mv(const RhsArgs<float>* tab, int count, int var, const c2<float>
 template <int N, int V>
 hipError_t col_mv(const ColArgs<float>* tab, int count, int var, const c2<float>* t,
                   const float* l, hipStream_t st) {
-  if constexpr (V >= FLOW_VARIANTS) {
+  if constexpr (V >= COL_VARIANT_COUNT) {
     return hipErrorInvalidValue;
   } else {
     if (var != V) return col_mv<N, V + 1>(tab, count, var, t, l, st);
-    return launch_col_multi_cfg<float, N, CV<V>.width, CV<V>.nt, CV<V>.maxr>(tab, count, t, l, st);
+    if constexpr (V == COL_REG_VARIANT) {
+      if constexpr (N == 1024) return launch_col_reg_multi<float, 32, CV<V>.nt / 64>(tab, count, t, l, st);
+      else return hipErrorInvalidValue;
+    } else {
+      return launch_col_multi_cfg<float, N, CV<V>.width, CV<V>.nt, CV<V>.maxr>(tab, count, t, l, st);
+    }
   }
 }
 
 template <int N, int V>
 hipError_t idst_mv(const IdstJob<float>* tab, int count, int maxrows, int var,
                    const c2<float>* t, hipStream_t st) {
-  if constexpr (V >= FLOW_VARIANTS) {
+  if constexpr (V >= ROW_VARIANT_COUNT) {
     return hipErrorInvalidValue;
   } else {
     if (var != V) return idst_mv<N, V + 1>(tab, count, maxrows, var, t, st);

@@ -2,6 +2,7 @@
 // (ROW_VARIANTS, COL_VARIANTS): rows or columns per workgroup, threads per workgroup and the
 // largest FFT radix.  The engine measures them per grid size and launches the fastest.
 #include "ib_flow_kernels.hpp"
+#include "ib_flow_reg.hpp"
 
 namespace ib {
 
@@ -14,7 +15,7 @@ constexpr FlowVariant CV = COL_VARIANTS[V];
 
 template <int N, int V>
 hipError_t rhs_v(const RhsArgs<float>& a, const c2<float>* t, hipStream_t st) {
-  if constexpr (V >= FLOW_VARIANTS) {
+  if constexpr (V >= ROW_VARIANT_COUNT) {
     return hipErrorInvalidValue;
   } else {
     if (a.var != V) return rhs_v<N, V + 1>(a, t, st);
@@ -25,18 +26,23 @@ hipError_t rhs_v(const RhsArgs<float>& a, const c2<float>* t, hipStream_t st) {
 template <int N, int V>
 hipError_t col_v(const ColArgs<float>& a, int n, int batch, const c2<float>* t, const float* l,
                  hipStream_t st) {
-  if constexpr (V >= FLOW_VARIANTS) {
+  if constexpr (V >= COL_VARIANT_COUNT) {
     return hipErrorInvalidValue;
   } else {
     if (a.var != V) return col_v<N, V + 1>(a, n, batch, t, l, st);
-    return launch_col_cfg<float, N, CV<V>.width, CV<V>.nt, CV<V>.maxr>(a, n, batch, t, l, st);
+    if constexpr (V == COL_REG_VARIANT) {
+      if constexpr (N == 1024) return launch_col_reg<float, 32, CV<V>.nt / 64>(a, batch, t, l, st);
+      else return hipErrorInvalidValue;
+    } else {
+      return launch_col_cfg<float, N, CV<V>.width, CV<V>.nt, CV<V>.maxr>(a, n, batch, t, l, st);
+    }
   }
 }
 
 template <int N, int V>
 hipError_t idst_v(const RowArgs<float>& a, int batch, const c2<float>* t, const float* ring,
                   int ring_rows, hipStream_t st) {
-  if constexpr (V >= FLOW_VARIANTS) {
+  if constexpr (V >= ROW_VARIANT_COUNT) {
     return hipErrorInvalidValue;
   } else {
     if (a.var != V) return idst_v<N, V + 1>(a, batch, t, ring, ring_rows, st);

@@ -88,15 +88,24 @@ struct RingJob {
 struct FlowVariant {
   int width, nt, maxr;
 };
-constexpr int FLOW_VARIANTS = 8;
+// Row kernels have ROW_VARIANT_COUNT configurations, the column solve COL_VARIANT_COUNT;
+// FLOW_VARIANTS is the larger (the size of the measurement tables).  Column configuration
+// COL_REG_VARIANT is the register-resident form (ib_flow_reg.hpp: columns per workgroup,
+// threads, FFT split P = 32), available where n = P^2 (n = 1024).
+constexpr int ROW_VARIANT_COUNT = 8;
+constexpr int COL_VARIANT_COUNT = 9;
+constexpr int FLOW_VARIANTS = 9;
+constexpr int COL_REG_VARIANT = 8;
 constexpr int FLOW_TUNE_MIN_N = 256;
-constexpr FlowVariant ROW_VARIANTS[FLOW_VARIANTS] = {
+constexpr FlowVariant ROW_VARIANTS[ROW_VARIANT_COUNT] = {
     {2, 256, 16}, {2, 256, 8}, {2, 512, 16}, {2, 512, 8},
     {2, 512, 4},  {4, 512, 8}, {4, 1024, 8}, {4, 1024, 16}};
-constexpr FlowVariant COL_VARIANTS[FLOW_VARIANTS] = {
+constexpr FlowVariant COL_VARIANTS[COL_VARIANT_COUNT] = {
     {4, 256, 16}, {4, 256, 8}, {2, 256, 4},  {4, 512, 16},
-    {4, 512, 8},  {4, 1024, 16}, {8, 512, 16}, {8, 1024, 16}};
+    {4, 512, 8},  {4, 1024, 16}, {8, 512, 16}, {8, 1024, 16}, {4, 128, 32}};
 bool flow_variant_available(int n, int fp64);
+// Whether configuration v of kind 0 (row kernels) or 1 (column solve) exists for n.
+bool flow_kind_variant_available(int kind, int v, int n, int fp64);
 // Shared side of the lock between graph recording and the library's other HIP calls.
 std::shared_lock<std::shared_mutex> hip_shared_lock();
 // Single-precision launches of configuration var (1 .. FLOW_VARIANTS-1), n >= FLOW_TUNE_MIN_N.

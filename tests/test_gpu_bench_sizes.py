@@ -74,10 +74,12 @@ def _oracle(n, levels, dtype=np.float64):
 
 SIZES = [(512, 3), (1024, 4)]
 CONFIGS = ["measured", (7, 5, 7)] + [(v, v, v) for v in range(8)]
+# the register-resident column solve (configuration 8) exists at n = 1024 only
+CASES = [(n, lv, c) for n, lv in SIZES for c in CONFIGS] + [(1024, 4, (7, 8, 7)), (1024, 4, (0, 8, 0))]
 
 
-@pytest.mark.parametrize("config", CONFIGS, ids=lambda c: c if isinstance(c, str) else "-".join(map(str, c)))
-@pytest.mark.parametrize("n,levels", SIZES)
+@pytest.mark.parametrize("n,levels,config", CASES,
+                         ids=lambda c: c if isinstance(c, str) else ("-".join(map(str, c)) if isinstance(c, tuple) else str(c)))
 def test_fp32_transform_configurations_at_bench_sizes(torch_cuda, gpu_lib, n, levels, config):
     from paper_2103_06415_amd import binding
     w_ref, s_ref = _oracle(n, levels)
