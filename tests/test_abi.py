@@ -142,19 +142,24 @@ def test_operator_import_validates_its_input(lib):
 
 def test_flow_variant_table_and_forcing(lib):
     """The transform-kernel configurations are listed, and forcing one is validated: only
-    single precision at n >= 256 has alternatives to configuration 0."""
+    single precision at the measured sizes has alternatives to configuration 0; the row
+    kernels have 8 configurations, the column solve 9, the last of them (register-resident
+    transforms, FFT split 32) at n = 1024 only."""
     from paper_2103_06415_amd import binding
+    counts = {0: 8, 1: 9}
     for kind in (0, 1):
         seen = set()
-        for v in range(binding.FLOW_VARIANTS):
+        for v in range(counts[kind]):
             w, t, r = binding.flow_variant_info(kind, v)
-            assert w >= 1 and t in (64, 128, 256, 512, 1024) and r in (4, 8, 16)
+            assert w >= 1 and t in (64, 128, 256, 512, 1024) and r in (4, 8, 16, 32)
             assert t % 64 == 0 and t >= 2 * w
             seen.add((w, t, r))
-        assert len(seen) == binding.FLOW_VARIANTS  # all distinct
+        assert len(seen) == counts[kind]  # all distinct
+    assert binding.flow_variant_info(1, 8) == (4, 128, 32)
     w, t, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert lib.ib_flow_variant_info(2, 0, ctypes.byref(w), ctypes.byref(t), ctypes.byref(r)) == -1
     assert lib.ib_flow_variant_info(0, 8, ctypes.byref(w), ctypes.byref(t), ctypes.byref(r)) == -1
+    assert lib.ib_flow_variant_info(1, 9, ctypes.byref(w), ctypes.byref(t), ctypes.byref(r)) == -1
     for n, prec, ok in ((256, binding.IB_FP32_FLOW, True), (128, binding.IB_FP32_FLOW, False),
                         (256, binding.IB_FP64, False)):
         cfg = _config(binding, n, 1)
@@ -163,7 +168,9 @@ def test_flow_variant_table_and_forcing(lib):
         assert lib.ib_create(ctypes.byref(cfg), None, None, ctypes.byref(h)) == 0
         assert lib.ib_set_flow_variants(h, 0, 0, 0) == 0  # defaults are always allowed
         assert lib.ib_set_flow_variants(h, 1, 2, 3) == (0 if ok else -1)
-        assert lib.ib_set_flow_variants(h, 0, 8, 0) == -1
+        assert lib.ib_set_flow_variants(h, 0, 9, 0) == -1
+        assert lib.ib_set_flow_variants(h, 8, 0, 0) == -1     # rows: 8 configurations
+        assert lib.ib_set_flow_variants(h, 0, 8, 0) == -1     # column 8: n = 1024 only
         tun = binding.IbFlowTuning()
         assert lib.ib_get_flow_tuning(h, ctypes.byref(tun)) == 0
         if ok:
