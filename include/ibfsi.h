@@ -207,7 +207,13 @@ ib_status ib_add_deformable(ib_solver* s, int32_t m, const double* xy_ref, doubl
                             double ei, double ea, const double* xy0, const double* rot0,
                             int32_t* body_id);
 
-/* Sub-domain rectangle (Sec. 3.1.1); it is snapped outwards to finest-level vertices. */
+/* Sub-domain rectangle (Sec. 3.1.1); it is snapped outwards to finest-level vertices.  Each
+ * call adds one rectangle (at most 8), for bodies that lie far apart: the sub-domain points
+ * are the rectangles' vertex grids one after another (B' couples them all), and each
+ * torsional or deformable body is interpolated on the first rectangle that holds all its
+ * points at the start (rigid bodies in prescribed motion and plates mounted on them: on the
+ * first rectangle).  Errors: IB_ERR_ARG (empty rectangle, a ninth one); at ib_prepare
+ * IB_ERR_OUT_OF_SUBDOMAIN when a body lies in no rectangle. */
 ib_status ib_set_subdomain(ib_solver* s, double x0, double x1, double y0, double y1);
 
 /* Initial vorticity of one level: omega[(n-1)^2] at interior vertices (host). */

@@ -168,10 +168,16 @@ class Oracle:
         if self.use_subdomain:
             appended = [b.xy for kind, b in self.bodies if kind == "rigid"]
             app = np.concatenate(appended) if appended else None
-            self.sd_box = self.p.subdomain
-            i0, i1, j0, j1 = subdomain.grid_points(lv, self.sd_box)
-            self.sd_ngrid = (i1 - i0 + 1) * (j1 - j0 + 1)
-            self.sd_pts = subdomain.point_set(lv, self.sd_box, app)
+            self.sd_boxes = subdomain.boxes_of(self.p.subdomain)
+            self.sd_offsets, self.sd_ngrid = subdomain.box_offsets(lv, self.sd_boxes)
+            # each moving body's rectangle: the first that holds all its points at the start
+            # (torsional and deformable bodies); rigid bodies in prescribed motion and plates
+            # mounted on them use the first rectangle
+            self.sd_body_box = [None if kind == "rigid" else
+                                (0 if kind in ("moving", "mounted") else
+                                 subdomain.box_containing(lv, self.sd_boxes, self.positions(kind, b)))
+                                for kind, b in self.bodies]
+            self.sd_pts = subdomain.point_set(lv, self.sd_boxes, app)
             self.sd_total = self.sd_pts.shape[0]
             self.e0 = subdomain.sub_e0(lv, self.sd_pts, self.kernel)
             delta.check_support(lv, self.e0)
@@ -211,16 +217,20 @@ class Oracle:
         lv = self.levels[0]
         rows = []
         app_start = 0
-        for kind, b in self.bodies:
+        for (kind, b), bx in zip(self.bodies, self.sd_body_box):
             pos = self.positions(kind, b)
             m = pos.shape[0]
             app_idx = None
+            box, off = self.sd_boxes[0], 0
             if kind == "rigid":
                 app_idx = np.arange(app_start, app_start + m)
                 app_start += m
-            rows.append(subdomain.hat_rows(lv, self.sd_box, self.sd_ngrid, self.sd_total, pos, 0, app_idx))
-            rows.append(subdomain.hat_rows(lv, self.sd_box, self.sd_ngrid, self.sd_total, pos,
-                                           self.sd_total, app_idx))
+            else:
+                box, off = self.sd_boxes[bx], self.sd_offsets[bx]
+            rows.append(subdomain.hat_rows(lv, box, self.sd_ngrid, self.sd_total, pos, 0, app_idx,
+                                           off))
+            rows.append(subdomain.hat_rows(lv, box, self.sd_ngrid, self.sd_total, pos,
+                                           self.sd_total, app_idx, off))
         return np.vstack(rows)
 
     def flow_block(self, eh):

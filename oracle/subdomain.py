@@ -3,7 +3,10 @@
 Sec. 3.1 (eqs. (22)-(29)): E ~= P E0 with E0 the IB interpolation at a fixed set of
 sub-domain points and P a sparse interpolation onto the moving body points.
 Sec. 3.1.1: sub-domain points are the vertices (vorticity points) of the finest
-level inside a user rectangle.  Sec. 3.1.2: P uses the two-point hat
+level inside a user rectangle.  Reading for several bodies far apart: the sub-domain may be
+a union of rectangles (one per body, say); its points are the rectangles' vertex grids one
+after another (row-major each, the rectangles in the order given), and each moving body is
+interpolated through P on the first rectangle that contains it at the start.  Sec. 3.1.2: P uses the two-point hat
 d_p(r) = 1 - |r|/dr with the 4 tensor neighbours (eq. (29)).  Sec. 5.2: exact body
 points of stationary bodies may be appended to the sub-domain point set; reading:
 each appended point is one more row/column of B and its body point takes P weight 1.
@@ -40,15 +43,51 @@ def grid_points(level, box):
     return i0, i1, j0, j1
 
 
+def boxes_of(sub):
+    """The rectangles of a sub-domain given as one (x0, x1, y0, y1) or a list of them."""
+    if sub is None:
+        return []
+    if len(sub) == 4 and all(np.isscalar(v) for v in sub):
+        return [tuple(float(v) for v in sub)]
+    return [tuple(float(v) for v in b) for b in sub]
+
+
+def box_offsets(level, boxes):
+    """First sub-domain point of each rectangle and the total count of grid points."""
+    offs, tot = [], 0
+    for box in boxes:
+        i0, i1, j0, j1 = grid_points(level, box)
+        offs.append(tot)
+        tot += (i1 - i0 + 1) * (j1 - j0 + 1)
+    return offs, tot
+
+
 def point_set(level, box, appended=None):
-    """Coordinates of the sub-domain points: grid vertices row-major (y outer),
-    followed by the appended exact points."""
-    i0, i1, j0, j1 = grid_points(level, box)
-    ii, jj = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1))
-    pts = np.stack([level.x0 + ii.ravel() * level.h, level.y0 + jj.ravel() * level.h], axis=1)
+    """Coordinates of the sub-domain points: each rectangle's grid vertices row-major (y
+    outer), rectangle after rectangle, followed by the appended exact points."""
+    parts = []
+    for b in boxes_of(box):
+        i0, i1, j0, j1 = grid_points(level, b)
+        ii, jj = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1))
+        parts.append(np.stack([level.x0 + ii.ravel() * level.h, level.y0 + jj.ravel() * level.h],
+                              axis=1))
+    pts = np.concatenate(parts, axis=0)
     if appended is not None and len(appended):
         pts = np.concatenate([pts, np.asarray(appended, dtype=np.float64)], axis=0)
     return pts
+
+
+def box_containing(level, boxes, positions):
+    """Index of the first rectangle whose vertex grid contains every point (the body's
+    rectangle); ValueError when none does."""
+    for k, box in enumerate(boxes):
+        i0, i1, j0, j1 = grid_points(level, box)
+        rx = (positions[:, 0] - (level.x0 + i0 * level.h)) / level.h
+        ry = (positions[:, 1] - (level.y0 + j0 * level.h)) / level.h
+        if (np.all(rx >= -TOL) and np.all(ry >= -TOL) and np.all(rx <= i1 - i0 + TOL)
+                and np.all(ry <= j1 - j0 + TOL)):
+            return k
+    raise ValueError("body outside every sub-domain rectangle")
 
 
 def apply_b_column(level, e0, col):
@@ -80,11 +119,13 @@ def filter_b(b, eps):
     return out
 
 
-def hat_rows(level, box, npts_grid, n_sd_total, positions, comp_offset, appended_index=None):
+def hat_rows(level, box, npts_grid, n_sd_total, positions, comp_offset, appended_index=None,
+             box_offset=0):
     """Rows of P for one component of a body's points.
 
-    ``positions`` (m, 2); ``comp_offset`` is 0 (x) or n_sd_total (y).  With
-    ``appended_index`` (m,) the rows are unit rows on appended points instead.
+    ``positions`` (m, 2); ``comp_offset`` is 0 (x) or n_sd_total (y); ``box`` the body's
+    rectangle, whose first grid point is ``box_offset``.  With ``appended_index`` (m,) the
+    rows are unit rows on appended points instead.
     """
     m = positions.shape[0]
     rows = np.zeros((m, 2 * n_sd_total))
@@ -106,7 +147,7 @@ def hat_rows(level, box, npts_grid, n_sd_total, positions, comp_offset, appended
         fx, fy = rx - ix, ry - iy
         for dxi, wx in ((0, 1.0 - fx), (1, fx)):
             for dyi, wy in ((0, 1.0 - fy), (1, fy)):
-                rows[a, comp_offset + (iy + dyi) * npx + (ix + dxi)] += wx * wy
+                rows[a, comp_offset + box_offset + (iy + dyi) * npx + (ix + dxi)] += wx * wy
     return rows
 
 

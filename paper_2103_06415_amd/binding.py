@@ -310,7 +310,10 @@ class Solver:
                        "ib_add_deformable")
                 self.npts.append(xr.shape[0])
         if problem.subdomain is not None:
-            _check(self.lib.ib_set_subdomain(self.handle, *problem.subdomain), "ib_set_subdomain")
+            sd = problem.subdomain
+            rects = [sd] if len(sd) == 4 and all(np.isscalar(v) for v in sd) else list(sd)
+            for r in rects:
+                _check(self.lib.ib_set_subdomain(self.handle, *r), "ib_set_subdomain")
         if problem.vorticity0 is not None:
             for g, w in enumerate(problem.vorticity0):
                 if w is not None:

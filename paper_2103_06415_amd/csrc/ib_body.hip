@@ -258,10 +258,13 @@ __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
       }
       a.act[pidx[0]] = 4 * row;
     } else {
-      const double xs0 = a.x0 + a.sd_i0 * a.h, ys0 = a.y0 + a.sd_j0 * a.h;
+      // the body's rectangle of the sub-domain
+      const int bx = b.sdbox;
+      const int bi0 = a.sdb.i0[bx], bj0 = a.sdb.j0[bx], npx = a.sdb.npx[bx], npy = a.sdb.npy[bx];
+      const double xs0 = a.x0 + bi0 * a.h, ys0 = a.y0 + bj0 * a.h;
       const double rx = (px - xs0) / a.h, ry = (py - ys0) / a.h;
       const double tol = 1e-9;
-      if (!(rx >= -tol && ry >= -tol && rx <= a.sd_npx - 1 + tol && ry <= a.sd_npy - 1 + tol)) {
+      if (!(rx >= -tol && ry >= -tol && rx <= npx - 1 + tol && ry <= npy - 1 + tol)) {
         atomicMax(&a.flags[0], 1);  // out of sub-domain (or non-finite position)
         for (int e = 0; e < 16; ++e) w[e] = 0.0;
         base[0] = base[1] = 2;
@@ -271,10 +274,10 @@ __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
         }
       } else {
         int ix = (int)floor(rx), iy = (int)floor(ry);
-        ix = ix < 0 ? 0 : (ix > a.sd_npx - 2 ? a.sd_npx - 2 : ix);
-        iy = iy < 0 ? 0 : (iy > a.sd_npy - 2 ? a.sd_npy - 2 : iy);
+        ix = ix < 0 ? 0 : (ix > npx - 2 ? npx - 2 : ix);
+        iy = iy < 0 ? 0 : (iy > npy - 2 ? npy - 2 : iy);
         const double fx = rx - ix, fy = ry - iy;
-        const int gp = a.sd_i0 + ix, gq = a.sd_j0 + iy;
+        const int gp = bi0 + ix, gq = bj0 + iy;
         base[0] = gp - 1;
         base[1] = gq - 1;
         for (int e = 0; e < 16; ++e) w[e] = 0.0;
@@ -285,7 +288,7 @@ __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
         const double k0 = roma3(0.0), k1 = roma3(1.0), kh = roma3(0.5);
         const double across[3] = {k1, k0, k1};
         for (int e = 0; e < 4; ++e) {
-          pidx[e] = comp * a.sd_total + (iy + dy[e]) * a.sd_npx + (ix + dx[e]);
+          pidx[e] = comp * a.sd_total + a.sdb.off[bx] + (iy + dy[e]) * npx + (ix + dx[e]);
           pw[e] = hw[e];
           if (hw[e] != 0.0) a.act[pidx[e]] = 4 * row + e;  // any writer of a shared row wins
           for (int u = 0; u < 3; ++u)
@@ -1280,7 +1283,10 @@ __device__ void off_window(const OffRows& o, int row, int* base, int* comp, doub
   *comp = row >= o.sd_total ? 1 : 0;
   const int pt = row - (*comp) * o.sd_total;
   if (pt < o.sd_ngrid) {
-    const int p = o.sd_i0 + pt % o.sd_npx, q = o.sd_j0 + pt / o.sd_npx;
+    int k = 0;  // the rectangle holding sub-domain point pt
+    while (k + 1 < o.sdb.n && o.sdb.off[k + 1] <= pt) ++k;
+    const int loc = pt - o.sdb.off[k];
+    const int p = o.sdb.i0[k] + loc % o.sdb.npx[k], q = o.sdb.j0[k] + loc / o.sdb.npx[k];
     base[0] = p - 1;
     base[1] = q - 1;
     for (int e = 0; e < 16; ++e) w[e] = 0.0;

@@ -8,6 +8,16 @@ namespace ib {
 enum { BODY_RIGID = 0, BODY_TORSIONAL = 1, BODY_DEFORMABLE = 2, BODY_MOVING = 3 };
 
 // Per-body data in device memory (double precision throughout).
+// Rectangles of the sub-domain (Sec. 3.1.1; several when bodies lie far apart): vertex origin
+// (i0, j0) and extent (npx x npy) of each, and its first sub-domain point `off` (the
+// rectangles' vertex grids follow one another, row-major each).
+constexpr int SD_MAX_BOXES = 8;
+struct SdBoxes {
+  int n;
+  int i0[SD_MAX_BOXES], j0[SD_MAX_BOXES], npx[SD_MAX_BOXES], npy[SD_MAX_BOXES],
+      off[SD_MAX_BOXES];
+};
+
 struct BodyDev {
   int kind;
   int npts;   // m
@@ -18,6 +28,7 @@ struct BodyDev {
   int has_ub; // rigid: prescribed velocity present
   int64_t yoff; // deformable: offset of its J_d^{-1} T^T workspace
   int moff;     // torsional on a driver: offset of its frame in FsiArgs::poses, else -1
+  int sdbox;    // sub-domain mode, moving bodies: the rectangle its points are interpolated on
   double ds;
   double hx, hy, theta0, inertia, stiffness, damping;  // torsional (inertia about the hinge)
   double mass, ei, ea;                                 // deformable; mass also of a mounted body
@@ -66,7 +77,8 @@ struct FsiArgs {
   const void* sstar;   // predictor streamfunction, float or double per fp64
   int fp64;
   // sub-domain
-  int use_sd, sd_i0, sd_j0, sd_npx, sd_npy, sd_ngrid, sd_total;
+  int use_sd, sd_ngrid, sd_total;
+  SdBoxes sdb;
   const double* app_xy;     // appended exact points (2 per point)
   const int64_t* bp_ptr;    // B' CSR (rows = 2 sd_total)
   const int32_t* bp_col;
@@ -212,7 +224,8 @@ struct OffRows {
   int kind;  // 0: body rows from st arrays, 1: sub-domain points
   const int* st_base;
   const double* st_w;
-  int sd_i0, sd_j0, sd_npx, sd_ngrid, sd_total;
+  int sd_ngrid, sd_total;
+  SdBoxes sdb;
   const double* app_xy;
   int n;
   double h, x0, y0;

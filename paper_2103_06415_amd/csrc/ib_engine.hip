@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -253,7 +254,7 @@ struct ib_solver {
   std::vector<std::vector<double>> omega0;
   std::vector<HostBody> bodies;
   bool has_sd = false;
-  double sd[4] = {0, 0, 0, 0};
+  std::vector<std::array<double, 4>> sd_rects;  // sub-domain rectangles (x0, x1, y0, y1)
   bool prepared = false, failed = false, first = true;
   bool allocated = false;  // level state lives on the device (from ib_prepare on)
   bool released = false;   // device memory given back; results kept on the host
@@ -284,8 +285,9 @@ struct ib_solver {
   // ---- bodies on the device
   int npts = 0, nf = 0, ntors = 0, ndef = 0, ndof = 0, nel_total = 0;
   bool use_sd = false, stationary = false;
-  int sd_i0 = 0, sd_i1 = 0, sd_j0 = 0, sd_j1 = 0, sd_npx = 0, sd_npy = 0, sd_ngrid = 0,
-      sd_total = 0;
+  ib::SdBoxes sdb{};          // the rectangles snapped to level-0 vertices
+  int sd_ilo = 0, sd_ihi = 0, sd_jlo = 0, sd_jhi = 0;  // vertex bounds of their union
+  int sd_ngrid = 0, sd_total = 0;
   int64_t bp_nnz = 0;
   // exact operator for moving bodies: G = E C (C^T A C)^{-1} C^T E^T rebuilt at every FSI
   // iterate from point-source columns (no sub-domain)
@@ -1000,21 +1002,71 @@ ib_status prepare_bodies(ib_solver* s) {
       s->last_error = "deformable body with more than 201 nodes";
       return IB_ERR_ARG;
     }
-  // ---- sub-domain geometry (snapped outwards to vertices)
+  // ---- sub-domain geometry: each rectangle snapped outwards to vertices, their vertex
+  // grids one after another; each moving body interpolates on one rectangle
   if (s->use_sd) {
     const double tol = 1e-9;
-    s->sd_i0 = (int)std::floor((s->sd[0] - x0) / h + tol);
-    s->sd_i1 = (int)std::ceil((s->sd[1] - x0) / h - tol);
-    s->sd_j0 = (int)std::floor((s->sd[2] - y0) / h + tol);
-    s->sd_j1 = (int)std::ceil((s->sd[3] - y0) / h - tol);
-    if (s->sd_i0 < 2 || s->sd_j0 < 2 || s->sd_i1 > n - 2 || s->sd_j1 > n - 2) {
-      s->last_error = "sub-domain reaches the level-0 boundary";
-      return IB_ERR_NEAR_BOUNDARY;
+    ib::SdBoxes& q = s->sdb;
+    q = ib::SdBoxes{};
+    q.n = (int)s->sd_rects.size();
+    int tot = 0;
+    s->sd_ilo = s->sd_jlo = n;
+    s->sd_ihi = s->sd_jhi = 0;
+    std::vector<std::array<int, 4>> ext(q.n);
+    for (int k = 0; k < q.n; ++k) {
+      const auto& r = s->sd_rects[k];
+      const int i0 = (int)std::floor((r[0] - x0) / h + tol), i1 = (int)std::ceil((r[1] - x0) / h - tol);
+      const int j0 = (int)std::floor((r[2] - y0) / h + tol), j1 = (int)std::ceil((r[3] - y0) / h - tol);
+      if (i0 < 2 || j0 < 2 || i1 > n - 2 || j1 > n - 2) {
+        s->last_error = "sub-domain reaches the level-0 boundary";
+        return IB_ERR_NEAR_BOUNDARY;
+      }
+      q.i0[k] = i0;
+      q.j0[k] = j0;
+      q.npx[k] = i1 - i0 + 1;
+      q.npy[k] = j1 - j0 + 1;
+      q.off[k] = tot;
+      tot += q.npx[k] * q.npy[k];
+      ext[k] = {i0, i1, j0, j1};
+      s->sd_ilo = std::min(s->sd_ilo, i0);
+      s->sd_ihi = std::max(s->sd_ihi, i1);
+      s->sd_jlo = std::min(s->sd_jlo, j0);
+      s->sd_jhi = std::max(s->sd_jhi, j1);
     }
-    s->sd_npx = s->sd_i1 - s->sd_i0 + 1;
-    s->sd_npy = s->sd_j1 - s->sd_j0 + 1;
-    s->sd_ngrid = s->sd_npx * s->sd_npy;
+    s->sd_ngrid = tot;
     s->sd_total = s->sd_ngrid + app;
+    // a torsional or deformable body uses the first rectangle that holds all its points at
+    // the start; bodies in prescribed motion and plates mounted on them use the first
+    auto holds = [&](int k, double px, double py) {
+      const double rx = (px - (x0 + q.i0[k] * h)) / h, ry = (py - (y0 + q.j0[k] * h)) / h;
+      return rx >= -tol && ry >= -tol && rx <= q.npx[k] - 1 + tol && ry <= q.npy[k] - 1 + tol;
+    };
+    for (size_t bi = 0; bi < s->bodies.size(); ++bi) {
+      const HostBody& hb = s->bodies[bi];
+      int box = 0;
+      std::vector<double> pts;
+      if (hb.kind == BODY_TORSIONAL && hb.driver < 0) {
+        for (int j = 0; j < hb.m; ++j) {
+          pts.push_back(hb.hx + j * hb.ds * std::cos(hb.theta0 + hb.theta));
+          pts.push_back(hb.hy + j * hb.ds * std::sin(hb.theta0 + hb.theta));
+        }
+      } else if (hb.kind == BODY_DEFORMABLE) {
+        pts = hb.xy0;
+      }
+      if (!pts.empty()) {
+        box = -1;
+        for (int k = 0; k < q.n && box < 0; ++k) {
+          bool all = true;
+          for (size_t e = 0; e + 1 < pts.size() && all; e += 2) all = holds(k, pts[e], pts[e + 1]);
+          if (all) box = k;
+        }
+        if (box < 0) {
+          s->last_error = "a body lies outside every sub-domain rectangle";
+          return IB_ERR_OUT_OF_SUBDOMAIN;
+        }
+      }
+      bd[bi].sdbox = box;
+    }
   }
   // rows and columns the body operators and the spread can touch
   {
@@ -1025,8 +1077,8 @@ ib_status prepare_bodies(ib_solver* s) {
     };
     for (auto& hb : s->bodies) if (hb.kind == BODY_RIGID) for (int k = 0; k < hb.m; ++k) acc(hb.xy[2 * k], hb.xy[2 * k + 1]);
     if (s->use_sd) {
-      acc(x0 + s->sd_i0 * h, y0 + s->sd_j0 * h);
-      acc(x0 + s->sd_i1 * h, y0 + s->sd_j1 * h);
+      acc(x0 + s->sd_ilo * h, y0 + s->sd_jlo * h);
+      acc(x0 + s->sd_ihi * h, y0 + s->sd_jhi * h);
     }
     if (xmin > xmax) { xmin = xmax = s->cfg.cx; ymin = ymax = s->cfg.cy; }
     s->bilo = std::max(1, (int)std::floor((xmin - x0) / h) - 4);
@@ -1066,10 +1118,7 @@ ib_status prepare_bodies(ib_solver* s) {
   a.sstar = s->sstar;
   a.fp64 = s->fp64;
   a.use_sd = s->use_sd;
-  a.sd_i0 = s->sd_i0;
-  a.sd_j0 = s->sd_j0;
-  a.sd_npx = s->sd_npx;
-  a.sd_npy = s->sd_npy;
+  a.sdb = s->sdb;
   a.sd_ngrid = s->sd_ngrid;
   a.sd_total = s->sd_total;
   a.app_xy = up(appxy);
@@ -1240,15 +1289,13 @@ ib_status prepare_bodies(ib_solver* s) {
   } else if (s->use_sd) {
     OffRows rows = geo;
     rows.kind = 1;
-    rows.sd_i0 = s->sd_i0;
-    rows.sd_j0 = s->sd_j0;
-    rows.sd_npx = s->sd_npx;
+    rows.sdb = s->sdb;
     rows.sd_ngrid = s->sd_ngrid;
     rows.sd_total = s->sd_total;
     rows.app_xy = a.app_xy;
     const int nsd = 2 * s->sd_total;
     // target rows: the sub-domain vertices' windows and the appended points' windows
-    int tlo = s->sd_j0 - 2, thi = s->sd_j1 + 3;
+    int tlo = s->sd_jlo - 2, thi = s->sd_jhi + 3;
     for (size_t k = 0; k < appxy.size() / 2; ++k) {
       const int jj = (int)std::floor((appxy[2 * k + 1] - y0) / h);
       tlo = std::min(tlo, jj - 3);
@@ -1257,8 +1304,12 @@ ib_status prepare_bodies(ib_solver* s) {
     tlo = std::max(1, tlo);
     thi = std::min(n - 1, thi);
     std::vector<double> key = {1.0, (double)n, h, x0, y0, s->cfg.dt, s->cfg.re, s->cfg.drop_tol,
-                               (double)s->sd_i0, (double)s->sd_i1, (double)s->sd_j0,
-                               (double)s->sd_j1, (double)appxy.size()};
+                               (double)s->sdb.n};
+    for (int k = 0; k < s->sdb.n; ++k)
+      for (double v : {(double)s->sdb.i0[k], (double)s->sdb.j0[k], (double)s->sdb.npx[k],
+                       (double)s->sdb.npy[k]})
+        key.push_back(v);
+    key.push_back((double)appxy.size());
     key.insert(key.end(), appxy.begin(), appxy.end());
     st = acquire_op(s, key, [&](OpData& d) -> ib_status {
       Offline w;
@@ -2978,11 +3029,12 @@ ib_status ib_add_deformable(ib_solver* s, int32_t m, const double* xy_ref, doubl
 ib_status ib_set_subdomain(ib_solver* s, double x0, double x1, double y0, double y1) {
   if (check(s) || !(x1 > x0) || !(y1 > y0)) return IB_ERR_ARG;
   if (s->prepared) return IB_ERR_STATE;
+  if ((int)s->sd_rects.size() >= ib::SD_MAX_BOXES) {
+    s->last_error = "more than 8 sub-domain rectangles";
+    return IB_ERR_ARG;
+  }
   s->has_sd = true;
-  s->sd[0] = x0;
-  s->sd[1] = x1;
-  s->sd[2] = y0;
-  s->sd[3] = y1;
+  s->sd_rects.push_back({x0, x1, y0, y1});
   return IB_OK;
 }
 
@@ -3468,9 +3520,10 @@ ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak
       // B' rows and an allowance of 800 stored entries per row (about 750 measured at
       // the drop tolerance 0.007), plus the offline batch buffers
       const double h = s->cfg.h;
-      const size_t npx = (size_t)((s->sd[1] - s->sd[0]) / h) + 3;
-      const size_t npy = (size_t)((s->sd[3] - s->sd[2]) / h) + 3;
-      const size_t rows = 2 * (npx * npy + app);
+      size_t grid = 0;
+      for (const auto& r : s->sd_rects)
+        grid += ((size_t)((r[1] - r[0]) / h) + 3) * ((size_t)((r[3] - r[2]) / h) + 3);
+      const size_t rows = 2 * (grid + app);
       const double scale = s->cfg.drop_tol > 0 ? std::min(4.0, 0.007 / s->cfg.drop_tol) : 4.0;
       r += rows * (size_t)(800 * scale) * 12 + rows * 12;
       peak_extra = (size_t)1 << 30;

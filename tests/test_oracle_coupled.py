@@ -211,6 +211,32 @@ def test_subdomain_without_filter_on_vertices_equals_exact():
     np.testing.assert_allclose(a.s[0], b.s[0], atol=1e-12)
 
 
+def test_two_subdomain_rectangles_without_filter_on_vertices_equal_exact():
+    """Several bodies far apart, each in a rectangle of its own (the sub-domain is the union
+    of the rectangles): with eps = 0 and body points on vertices, P E0 = E and
+    P B P^T = E C K C^T E^T still hold row by row, so a step equals the exact operator's to
+    round-off.  Mutations that fail it: the second rectangle's offset left out of P (its
+    plate would interpolate on the first rectangle's points), or the rectangles' grids
+    concatenated in the other order."""
+    flow = W.Flow(n=32, levels=1, h=0.1, dt=0.02, re=100.0, u_inf=(1.0, 0.0))
+    rng = np.random.default_rng(8)
+    w0 = [0.3 * rng.normal(size=(31, 31))]
+    a = W.Torsional(n=4, hinge=(-0.2, 0.0), length=0.6, theta0=0.0, inertia=1.0, stiffness=1.0,
+                    damping=0.0)
+    b = W.Torsional(n=3, hinge=(0.0, -0.5), length=0.4, theta0=0.0, inertia=0.5, stiffness=2.0,
+                    damping=0.1, theta=0.0, phi=0.2)
+    boxes = [(-0.4, 0.6, -0.3, 0.3), (-0.25, 0.55, -0.75, -0.35)]
+    p = W.Problem("two", flow, [a, b], boxes, w0, 1)
+    sd = Oracle(p, fixed_iters=1, drop_tol=0.0, subdomain_mode=True)
+    ex = Oracle(p, fixed_iters=1, subdomain_mode=False)
+    sd.step()
+    ex.step()
+    assert sd.sd_body_box == [0, 1]
+    assert sd.sd_offsets[1] == 11 * 7  # the first rectangle's 11 x 7 vertices come first
+    np.testing.assert_allclose(sd.f, ex.f, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(sd.s[0], ex.s[0], atol=1e-12)
+
+
 def test_multidomain_matches_single_large_grid():
     """A compact vortex advected for a few steps: the level-0 vorticity of a 3-level
     32^2 hierarchy matches one 128^2 grid spanning the coarsest extent at level-0

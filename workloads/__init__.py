@@ -124,7 +124,8 @@ class Problem:
     name: str
     flow: Flow
     bodies: list
-    subdomain: Optional[tuple] = None          # (x0, x1, y0, y1) or None = exact operators
+    subdomain: Optional[object] = None         # (x0, x1, y0, y1), a list of such rectangles,
+                                               # or None = exact operators
     vorticity0: Optional[List[np.ndarray]] = None  # per level, (n-1, n-1) interior omega
     steps: int = 1
 
@@ -361,10 +362,11 @@ def batch_problems(count=64, seed=4, steps=200, sizes=(128, 256, 384, 512, 768))
     """Independent instances: seeded grid size, level count, Re and 1-3 bodies each.
 
     Bodies are rigid circles (D ~ U[0.3, 0.8]) or torsional plates (L ~ U[0.3, 0.8],
-    theta0 ~ U[-30, 30] degrees, inertia 5, stiffness 1, damping 0.1) placed without
-    overlap in [-1.2, 1.2]^2 on a finest level of side 4 (h = 4/n, dt = 0.2 h), Re ~
-    U[50, 400]; body points 2h apart (Sec. 5).  At most one plate per instance, and its sub-domain is the box of the
-    sector it can sweep; instances with only circles use the exact stationary operator.
+    theta0 ~ U[-30, 30] degrees, inertia 5, stiffness 1, damping 0.1), each kind with
+    probability 1/2, placed without overlap in [-1.2, 1.2]^2 on a finest level of side 4
+    (h = 4/n, dt = 0.2 h), Re ~ U[50, 400]; body points 2h apart (Sec. 5).  Every plate
+    has a sub-domain rectangle of its own, the box of the sector it can sweep; instances with
+    only circles use the exact stationary operator.
     """
     out = []
     for i in range(count):
@@ -375,10 +377,10 @@ def batch_problems(count=64, seed=4, steps=200, sizes=(128, 256, 384, 512, 768))
         h = 4.0 / n
         flow = Flow(n=n, levels=levels, h=h, dt=0.2 * h, re=re)
         nb = int(rng.integers(1, 4))
-        kinds = ["plate" if (k == 0 and rng.uniform() < 0.5) else "circle" for k in range(nb)]
+        kinds = ["plate" if rng.uniform() < 0.5 else "circle" for k in range(nb)]
         sizes_ = [float(rng.uniform(0.3, 0.8)) for _ in range(nb)]
         centres = _place(rng, sizes_, h)
-        bodies, sd = [], None
+        bodies, boxes = [], []
         for kind, size, c in zip(kinds, sizes_, centres):
             if kind == "circle":
                 bodies.append(cylinder(c, size, h, spacing=2.0))
@@ -388,8 +390,8 @@ def batch_problems(count=64, seed=4, steps=200, sizes=(128, 256, 384, 512, 768))
                 hinge = (c[0] - 0.5 * size * math.cos(th0), c[1] - 0.5 * size * math.sin(th0))
                 bodies.append(Torsional(n=npts, hinge=hinge, length=size, theta0=th0,
                                         inertia=5.0, stiffness=1.0, damping=0.1))
-                sd = plate_box(hinge, size, th0)
-        out.append(Problem(f"batch{i}", flow, bodies, sd, None, steps))
+                boxes.append(plate_box(hinge, size, th0))
+        out.append(Problem(f"batch{i}", flow, bodies, boxes or None, None, steps))
     return out
 
 
