@@ -195,7 +195,8 @@ def batch_run(problems, steps, warmup, alone_steps=None):
     return out
 
 
-def serve(problems, max_active=8, budget=200 << 30, precision=None):
+def serve(problems, max_active=8, budget=200 << 30, precision=None, per_request=False,
+          progress=False):
     """Run (arrival, Problem) requests through the continuous-batching server."""
     from paper_2103_06415_amd import binding
     prec = binding.IB_FP32_FLOW if precision is None else precision
@@ -207,10 +208,39 @@ def serve(problems, max_active=8, budget=200 << 30, precision=None):
         tickets.append(server.submit(s, p.steps, arrival=arrival))
         cells += p.flow.n * p.flow.n * p.flow.levels * p.steps
     t0 = time.perf_counter()
-    server.run()
+    if progress:
+        # the server runs in a thread of its own; a line for every few requests that finish
+        import threading
+        err = []
+
+        def go():
+            try:
+                server.run()
+            except Exception as e:  # noqa: BLE001 (re-raised below)
+                err.append(e)
+        th = threading.Thread(target=go)
+        th.start()
+        shown = 0
+        while th.is_alive():
+            th.join(0.5)
+            done = sum(1 for t in tickets if server.info(t)["status"] <= 0)
+            if done - shown >= max(1, len(tickets) // 20) or (done == len(tickets) > shown):
+                shown = done
+                print(f"  served {shown}/{len(tickets)} requests, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+        if err:
+            raise err[0]
+    else:
+        server.run()
     wall = time.perf_counter() - t0
     infos = [server.info(t) for t in tickets]
-    sources = [s.stats()["operator_source"] for s in solvers]
+    stats = [s.stats() for s in solvers]
+    sources = [st["operator_source"] for st in stats]
+    prep = [st["prepare_seconds"] for st in stats]
+    failures = [{"request": k, "status": i["status"], "steps_done": i["steps_done"],
+                 "n": p.flow.n, "levels": p.flow.levels,
+                 "bodies": [type(b).__name__ for b in p.bodies], "error": s.last_error()}
+                for k, ((_, p), i, s) in enumerate(zip(problems, infos, solvers)) if i["status"] != 0]
     for s in solvers:
         s.close()
     server.close()
@@ -222,13 +252,44 @@ def serve(problems, max_active=8, budget=200 << 30, precision=None):
 
     def pct(q):
         return lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)] if lat else None
-    return {"requests": len(infos), "failed": len(infos) - len(ok),
+    return {"requests": len(infos), "failed": len(infos) - len(ok), "failures": failures,
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99),
             "makespan_s": makespan, "wall_s": wall,
             "throughput": done_cells / makespan if makespan > 0 else None,
             "throughput_unit": "grid-cell steps/s", "requests_per_s": len(ok) / makespan if makespan else None,
             "max_active": max_active,
-            "operators_built": sources.count(0), "operators_from_cache": sources.count(1)}
+            "operators_built": sources.count(0), "operators_from_cache": sources.count(1),
+            "cache_hit_share": sources.count(1) / max(1, sources.count(0) + sources.count(1)),
+            "offline_seconds_total": sum(prep), "offline_seconds_max": max(prep) if prep else None,
+            "per_request": [{"n": p.flow.n, "levels": p.flow.levels, "bodies": len(p.bodies),
+                             "steps": p.steps, "offline_s": round(pr, 4), "source": src,
+                             "latency_s": (round(i["finished"] - i["arrival"], 4)
+                                           if i["status"] == 0 else None)}
+                            for (_, p), pr, src, i in zip(problems, prep, sources, infos)]
+            if per_request else None}
+
+
+def serve_legs(args, W):
+    """The serving traces: continuous batching of seeded Poisson arrivals (latency = finish -
+    arrival).  The family trace repeats six geometries, so most requests reuse an offline
+    operator; the drawn trace draws every request's grid, levels, Re and bodies, so nearly every
+    request builds its own."""
+    out = {"served": serve(W.serve_trace())}
+    out["served"]["workload"] = ("48 requests, Poisson arrivals 40/s, 6 families of "
+                                 "256^2x1 .. 1024^2x4 grids with 1-3 rigid/torsional/"
+                                 "deformable bodies, 200-2000 steps, FP32 flow")
+    if args.serve_drawn > 0:
+        r = serve(W.drawn_trace(count=args.serve_drawn), per_request=True, progress=True)
+        per = r.pop("per_request")
+        big = [q for q in per if q["n"] == 1024 and q["source"] == 0]
+        r["offline_s_median_1024"] = (sorted(q["offline_s"] for q in big)[len(big) // 2]
+                                      if big else None)
+        r["workload"] = (f"{args.serve_drawn} requests, Poisson arrivals 40/s, each drawing N in "
+                         "{256,384,512,768,1024}, 1-4 levels, Re in [50, 400], 1-3 circles, "
+                         "plates or flags (a sub-domain rectangle per plate or flag), 200-2000 "
+                         "steps, FP32 flow")
+        out["served_drawn"] = r
+    return out
 
 
 def exact_compare(make, tors_body, force_bodies, steps, workload):
@@ -447,6 +508,12 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-flow-n", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-drawn", type=int, default=48,
+                    help="requests in the drawn serving trace (grid, levels, Re and 1-3 bodies "
+                         "drawn per request, Poisson arrivals 40/s); 0: skip")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the two serving traces (--serve-drawn sets the drawn one's "
+                         "length)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware counter calibration)")
@@ -471,6 +538,12 @@ def main():
     n, levels = args.n, args.levels
     prob = W.flag_problem(n=n, levels=levels)
     cells = n * n * levels
+    if args.serve_only:
+        out = {"metric": METRIC, "unit": "grid-cell steps/s", "n_gpus": 1, "data": "synthetic",
+               "legs": "serving only"}
+        out.update(serve_legs(args, W))
+        print(json.dumps(out))
+        return
     if args.batch_only:
         out = {"metric": METRIC, "unit": "grid-cell steps/s", "n_gpus": 1, "steps": args.steps,
                "data": "synthetic", "legs": "batch only"}
@@ -558,11 +631,7 @@ def main():
         out["concurrent"]["workload"] = (f"{args.concurrent} copies of the flag workload, one stream "
                                          "and host thread each, FP32 flow")
     if not args.no_serve:
-        # continuous batching of a seeded Poisson trace; latency = finish - arrival
-        out["served"] = serve(W.serve_trace())
-        out["served"]["workload"] = ("48 requests, Poisson arrivals 40/s, 6 families of "
-                                     "256^2x1 .. 1024^2x4 grids with 1-3 rigid/torsional/"
-                                     "deformable bodies, 200-2000 steps, FP32 flow")
+        out.update(serve_legs(args, W))
     if not args.no_exact:
         out["subdomain_vs_exact"] = exact_compare(
             lambda sd: W.plate_problem(n=512, levels=3, steps=200, subdomain=sd), 0, [0], 200,

@@ -451,3 +451,55 @@ def serve_trace(count=48, rate=40.0, seed=5, steps=(200, 2000), families=SERVE_F
         st = int(rng.integers(steps[0], steps[1] + 1))
         out.append((t, serve_request(fam, rng, st)))
     return out
+
+
+def drawn_request(rng, steps=(200, 2000), sizes=(256, 384, 512, 768, 1024), noise=1e-3):
+    """One request with everything drawn: N ~ U{sizes}, G ~ U{1..4}, Re ~ U[50, 400] and 1-3
+    bodies, each a rigid circle, a torsional plate or a deformable flag with equal probability,
+    steps ~ U{steps[0] .. steps[1]}.  Sizes and placement as in batch_problems (circles
+    D ~ U[0.3, 0.8]; plates L ~ U[0.3, 0.8], theta0 ~ U[-30, 30] degrees, inertia 5,
+    stiffness 1, damping 0.1; flags L ~ U[0.3, 0.8] clamped along +x, mass ratio 0.2, bending
+    stiffness 1e-3, stretching stiffness 1e3, initial deflection a ~ U[0.05, 0.1] L), finest
+    level of side 4 (h = 4/N, dt = 0.2 h), body points 2h apart.  Every plate and flag has a
+    sub-domain rectangle of its own: the box of the sector a plate can sweep, or the strip
+    [x_c - 0.02, x_c + L + 0.02] x [y_c - 0.6 L, y_c + 0.6 L] of a flag clamped at (x_c, y_c)."""
+    n = int(rng.choice(sizes))
+    levels = int(rng.integers(1, 5))
+    re = float(rng.uniform(50.0, 400.0))
+    h = 4.0 / n
+    flow = Flow(n=n, levels=levels, h=h, dt=0.2 * h, re=re)
+    nb = int(rng.integers(1, 4))
+    kinds = [("circle", "plate", "flag")[int(rng.integers(0, 3))] for _ in range(nb)]
+    sizes_ = [float(rng.uniform(0.3, 0.8)) for _ in range(nb)]
+    centres = _place(rng, sizes_, h)
+    bodies, boxes = [], []
+    for kind, size, c in zip(kinds, sizes_, centres):
+        if kind == "circle":
+            bodies.append(cylinder(c, size, h, spacing=2.0))
+        elif kind == "plate":
+            npts = int(round(size / (2.0 * h))) + 1
+            th0 = math.radians(float(rng.uniform(-30.0, 30.0)))
+            hinge = (c[0] - 0.5 * size * math.cos(th0), c[1] - 0.5 * size * math.sin(th0))
+            bodies.append(Torsional(n=npts, hinge=hinge, length=size, theta0=th0,
+                                    inertia=5.0, stiffness=1.0, damping=0.1))
+            boxes.append(plate_box(hinge, size, th0))
+        else:
+            clamp = (c[0] - 0.5 * size, c[1])
+            a = float(rng.uniform(0.05, 0.1)) * size
+            bodies.append(flag_body(clamp, size, h, a=a))
+            boxes.append((clamp[0] - 0.02, clamp[0] + size + 0.02, clamp[1] - 0.6 * size,
+                          clamp[1] + 0.6 * size))
+    w0 = [rng.normal(0.0, noise, size=(n - 1, n - 1))] + [None] * (levels - 1)
+    st = int(rng.integers(steps[0], steps[1] + 1))
+    return Problem("drawn", flow, bodies, boxes or None, w0, st)
+
+
+def drawn_trace(count=500, rate=40.0, seed=6, steps=(200, 2000)):
+    """Poisson arrivals (mean rate per second) of requests drawn one by one (drawn_request):
+    a list of (arrival seconds, Problem)."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        out.append((t, drawn_request(rng, steps)))
+    return out
