@@ -269,6 +269,103 @@ def serve(problems, max_active=8, budget=200 << 30, precision=None, per_request=
             if per_request else None}
 
 
+def trace_gaps(path, step_kernel="k_spread_multi", pattern="_multi", split_us=1000.0):
+    """Busy and idle time of the batched step from a rocprofv3 kernel trace (CSV): the region
+    runs from the first to the last dispatch whose name contains `pattern`; busy is the union
+    of the dispatches' [start, end] intervals in it, idle the rest (launch gaps and host
+    waits); steps are counted by the dispatches of `step_kernel` (one per batched step).  Idle
+    stretches longer than split_us are the caller's own pauses between calls (warm-up, timing)
+    and are left out of the span; the per-step host round trip is the largest gap of each step."""
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"],
+                         int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0),
+                         int(r.get("Workgroup_Size") or r.get("Workgroup_Size_X") or 1)))
+    rows.sort()
+    sel = [r for r in rows if pattern in r[2]]
+    if not sel:
+        return {"error": f"no dispatch named *{pattern}* in {path}"}
+    t0, t1 = sel[0][0], max(r[1] for r in sel)
+    inside = [r for r in rows if r[0] >= t0 and r[1] <= t1]
+    steps = sum(1 for r in inside if step_kernel in r[2])
+    busy, cs, ce = 0, None, None
+    gaps = []
+    for s0, e0, *_ in inside:
+        if ce is None:
+            cs, ce = s0, e0
+        elif s0 > ce:
+            busy += ce - cs
+            gaps.append(s0 - ce)
+            cs, ce = s0, e0
+        else:
+            ce = max(ce, e0)
+    busy += ce - cs
+    pauses = [g for g in gaps if g > split_us * 1e3]
+    gaps = [g for g in gaps if g <= split_us * 1e3]
+    span = t1 - t0 - sum(pauses)
+    # the largest gap between consecutive step-kernel dispatches: the host's per-step wait
+    marks = [r[1] for r in inside if step_kernel in r[2]]
+    step_max = []
+    for a, b in zip(marks, marks[1:]):
+        seg = [r for r in inside if a <= r[0] < b]
+        m, ce2 = 0, a
+        for s0, e0, *_ in seg:
+            if s0 - ce2 <= split_us * 1e3:
+                m = max(m, s0 - ce2)
+            ce2 = max(ce2, e0)
+        step_max.append(m)
+    by = {}
+    for s0, e0, name, grid, wg in inside:
+        key = name.split("(")[0]
+        d = by.setdefault(key, [0, 0.0, 0])
+        d[0] += 1
+        d[1] += (e0 - s0) * 1e-3
+        d[2] = max(d[2], grid // max(wg, 1))
+    top = sorted(by.items(), key=lambda kv: -kv[1][1])[:12]
+    per = max(steps, 1)
+    return {"trace": os.path.basename(path), "steps": steps, "dispatches": len(inside),
+            "dispatches_per_step": len(inside) / per, "span_ms_per_step": span * 1e-6 / per,
+            "busy_ms_per_step": busy * 1e-6 / per, "idle_ms_per_step": (span - busy) * 1e-6 / per,
+            "idle_share": (span - busy) / span, "gaps_per_step": len(gaps) / per,
+            "mean_gap_us": (sum(gaps) / len(gaps) * 1e-3) if gaps else 0.0,
+            "pauses_left_out_ms": [round(g * 1e-6, 3) for g in pauses],
+            "largest_gap_per_step_us_mean": (sum(step_max) / len(step_max) * 1e-3) if step_max else 0.0,
+            "other_idle_ms_per_step": ((span - busy) - sum(step_max)) * 1e-6 / per,
+            "top_kernels_us_per_step": [(k, round(v[1] / per, 1), v[0] // per, v[2]) for k, v in top]}
+
+
+def library_gemm():
+    """Matrix-core library products (torch's matmul, hipBLASLt on this platform) at the shapes of
+    one sine transform as a dense product: BF16 inputs with FP32 accumulation, the split form's
+    k = 3 (n - 1) padded and unpadded, and a large square product for the library's own best
+    rate.  Times are averages over 200 back-to-back products between two events."""
+    import torch
+    out = {}
+    for m, k, n, dt in ((1024, 1024, 1024, torch.bfloat16), (1024, 3072, 1024, torch.bfloat16),
+                        (1023, 3069, 1023, torch.bfloat16), (4096, 4096, 4096, torch.bfloat16),
+                        (1024, 1024, 1024, torch.float32)):
+        a = torch.randn(m, k, device="cuda", dtype=dt)
+        b = torch.randn(k, n, device="cuda", dtype=dt)
+        for _ in range(5):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(200):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 200
+        tf = 2.0 * m * n * k / (us * 1e-6) / 1e12
+        peak = 2500.0 if dt == torch.bfloat16 else 157.3
+        out[f"{m}x{k}x{n}_{str(dt).split('.')[-1]}"] = {"us": round(us, 2), "tflops": round(tf, 1),
+                                                         "frac_of_dense_peak": round(tf / peak, 3)}
+        del a, b, c
+    return out
+
+
 def serve_legs(args, W):
     """The serving traces: continuous batching of seeded Poisson arrivals (latency = finish -
     arrival).  The family trace repeats six geometries, so most requests reuse an offline
@@ -514,10 +611,18 @@ def main():
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the two serving traces (--serve-drawn sets the drawn one's "
                          "length)")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="only time the matrix-core library's products at the sine-transform shapes")
+    ap.add_argument("--trace-gaps", default=None, metavar="CSV",
+                    help="only analyse a rocprofv3 kernel trace (kernel_trace.csv) of a "
+                         "--batch-only run: busy and idle time of the batched step")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference "
                          "dispatch of known traffic for hardware counter calibration)")
     args = ap.parse_args()
+    if args.trace_gaps:
+        print(json.dumps(trace_gaps(args.trace_gaps), indent=1))
+        return
     if args.cpu_leg:
         cpu_leg(args)
         return
@@ -538,6 +643,9 @@ def main():
     n, levels = args.n, args.levels
     prob = W.flag_problem(n=n, levels=levels)
     cells = n * n * levels
+    if args.library_gemm:
+        print(json.dumps({"library_gemm": library_gemm()}))
+        return
     if args.serve_only:
         out = {"metric": METRIC, "unit": "grid-cell steps/s", "n_gpus": 1, "data": "synthetic",
                "legs": "serving only"}
