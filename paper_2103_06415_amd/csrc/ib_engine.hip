@@ -224,6 +224,7 @@ struct ib_solver {
   FlowTuning tune;    // kernel configurations of the row and column transforms
   bool tune_forced = false;
   int kpad = 0;       // size of the padded sine matrix
+  int gemm_tn = 0;    // measured stage depth in k of the sine-transform products (64 or 128)
   void* shi = nullptr;
   void* slo = nullptr;
   float* sinv = nullptr;
@@ -1675,6 +1676,7 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
       g.px = P;
       g.c = static_cast<float*>(s->work);
       g.pc = P;
+      g.tn = s->gemm_tn;
       HIPCHK(launch_dst_gemm(g, 1, s->stream));
     }
     TimeScope ts(s, IB_K_COL_SOLVE);
@@ -1695,6 +1697,7 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
     g.scale = (float)(4.0 / ((double)n * n));
     g.lift = has_ring ? static_cast<const float*>(s->lift) : nullptr;
     g.sinv = s->sinv;
+    g.tn = s->gemm_tn;
     HIPCHK(launch_dst_gemm(g, 0, s->stream));
     GemmArgs h{};
     h.shi = g.shi;
@@ -1703,6 +1706,7 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
     h.nv = g.nv;
     h.kpad = g.kpad;
     h.px = h.pc = P;
+    h.tn = s->gemm_tn;
     h.x = s->ys;
     h.c = static_cast<float*>(s->work);
     HIPCHK(launch_dst_gemm(h, 0, s->stream));
@@ -2104,6 +2108,46 @@ ib_status make_gemm_tables(ib_solver* s) {
   return IB_OK;
 }
 
+// Measured stage depth of the sine-transform products (64 or 128 values of k per stage): the
+// column product (the plain form of the three S . products of a level) timed with each on the
+// spectral scratch arrays (their contents do not matter for the time), the faster kept.
+ib_status tune_gemm(ib_solver* s) {
+  s->gemm_tn = 64;
+  if (s->kpad % 128 != 0) return IB_OK;
+  GemmArgs g{};
+  g.shi = static_cast<const __bf16*>(s->shi);
+  g.slo = static_cast<const __bf16*>(s->slo);
+  g.ps = s->kpad;
+  g.nv = s->n - 1;
+  g.kpad = s->kpad;
+  g.x = static_cast<const float*>(s->work);
+  g.px = g.pc = s->pitch;
+  g.c = static_cast<float*>(s->workg);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = 0.0f;
+  for (int bk : {64, 128}) {
+    if (e != hipSuccess) break;
+    g.tn = bk;
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_dst_gemm(g, 0, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+    for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_dst_gemm(g, 0, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (bk == 64 || ms < best)) {
+      best = ms;
+      s->gemm_tn = bk;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(s, e, "sine-transform product timing");
+  return IB_OK;
+}
+
 // Device state of the levels (allocated by ib_prepare, so that creating a solver costs
 // no device memory and a scheduler can admit it later).
 ib_status alloc_state(ib_solver* s) {
@@ -2137,6 +2181,7 @@ ib_status alloc_state(ib_solver* s) {
                          : make_tables<float>(s, s->n, &s->tw, &s->lam);
   if (st == IB_OK) st = make_tables<double>(s, s->n, &s->tw64, &s->lam64);
   if (st == IB_OK && s->gemm) st = make_gemm_tables(s);
+  if (st == IB_OK && s->gemm) st = tune_gemm(s);
   if (st) return st;
   for (auto& L : s->lv) {
     HIPCHK(hipMemsetAsync(L.s, 0, full, s->stream));

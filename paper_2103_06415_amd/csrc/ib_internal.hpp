@@ -136,6 +136,7 @@ struct GemmArgs {
   float alpha, scale;
   const float* lift;
   const float* sinv;
+  int tn;  // stage depth in k of the products (64 or 128); 0: chosen by size
 };
 hipError_t launch_dst_gemm(const GemmArgs& g, int mode, hipStream_t st);
 
