@@ -6,7 +6,8 @@ solve used by the predictor (eq. (16)) and the corrector (eq. (20)) is
 
     (C^T A C)^{-1} r = dt * S2 diag(1 / (lam (1 + alpha lam))) S2 r,
 
-S2 = S (x) S the 2-D transform.  In double precision the oracle applies S as a dense
+S2 = S_y (x) S_x the 2-D transform (one sine matrix per axis; the same one on square
+levels), lam = lam_x + lam_y.  In double precision the oracle applies S as a dense
 orthonormal matrix (naive O(n^3) products, no FFT).
 
 Extended precision (arrays of ``numpy.longdouble``, the x87 80-bit format with a 64-bit
@@ -42,19 +43,19 @@ def eigenvalues_1d(n, dtype=np.float64):
     return 4 * np.sin(_pi(dtype) * k / (2 * n)) ** 2
 
 
-def eigenvalues(n, dtype=np.float64):
-    """lam[l-1, k-1] = 4 sin^2(pi k / 2n) + 4 sin^2(pi l / 2n): eigenvalues of C^T C."""
-    lam = eigenvalues_1d(n, dtype)
-    return lam[:, None] + lam[None, :]
+def eigenvalues(n, dtype=np.float64, ny=None):
+    """lam[l-1, k-1] = 4 sin^2(pi k / 2n) + 4 sin^2(pi l / 2 ny): eigenvalues of C^T C on a
+    level of n cells along x and ny (default n) along y; rows are the y modes."""
+    ny = n if ny is None else ny
+    return eigenvalues_1d(ny, dtype)[:, None] + eigenvalues_1d(n, dtype)[None, :]
 
 
 def dst2(x):
-    """2-D orthonormal DST-I of an (n-1, n-1) array (self-inverse)."""
+    """2-D orthonormal DST-I of an (ny-1, nx-1) array (self-inverse): S_y x S_x."""
     if x.dtype != np.float64:
         return scipy.fft.dst(scipy.fft.dst(x, type=1, norm="ortho", axis=0), type=1, norm="ortho",
                              axis=1)
-    s = sine_matrix(x.shape[0] + 1)
-    return s @ x @ s
+    return sine_matrix(x.shape[0] + 1) @ x @ sine_matrix(x.shape[1] + 1)
 
 
 def solve_cac(rhs, alpha):
@@ -62,18 +63,18 @@ def solve_cac(rhs, alpha):
 
     Multiply by dt for (C^T A C)^{-1}.
     """
-    n = rhs.shape[0] + 1
-    lam = eigenvalues(n, rhs.dtype)
+    ny, nx = rhs.shape[0] + 1, rhs.shape[1] + 1
+    lam = eigenvalues(nx, rhs.dtype, ny)
     if rhs.dtype != np.float64:
         return dst2(dst2(rhs) / (lam * (1 + alpha * lam)))
-    s = sine_matrix(n)
-    return s @ ((s @ rhs @ s) / (lam * (1.0 + alpha * lam))) @ s
+    sy, sx = sine_matrix(ny), sine_matrix(nx)
+    return sy @ ((sy @ rhs @ sx) / (lam * (1.0 + alpha * lam))) @ sx
 
 
 def solve_poisson(rhs):
     """(C^T C)^{-1} rhs with homogeneous Dirichlet values."""
-    n = rhs.shape[0] + 1
+    ny, nx = rhs.shape[0] + 1, rhs.shape[1] + 1
     if rhs.dtype != np.float64:
-        return dst2(dst2(rhs) / eigenvalues(n, rhs.dtype))
-    s = sine_matrix(n)
-    return s @ ((s @ rhs @ s) / eigenvalues(n)) @ s
+        return dst2(dst2(rhs) / eigenvalues(nx, rhs.dtype, ny))
+    sy, sx = sine_matrix(ny), sine_matrix(nx)
+    return sy @ ((sy @ rhs @ sx) / eigenvalues(nx, np.float64, ny)) @ sx

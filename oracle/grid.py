@@ -2,10 +2,11 @@
 
 Layout (a reading: the paper defers the grid to Taira & Colonius / Colonius & Taira):
 
-* A level has ``n`` cells per side and spacing ``h``.  Vertex (i, j), i, j = 0..n, sits
-  at (x0 + i h, y0 + j h) and carries the streamfunction s and the circulation
-  gamma = h^2 * vorticity.  Arrays are indexed ``[j, i]`` (row = y).  The unknowns are
-  the (n-1)^2 interior vertices; the outer ring holds boundary values.
+* A level has ``nx`` cells along x, ``ny`` along y (``n`` when square) and spacing ``h``.
+  Vertex (i, j), i = 0..nx, j = 0..ny, sits at (x0 + i h, y0 + j h) and carries the
+  streamfunction s and the circulation gamma = h^2 * vorticity.  Arrays are indexed
+  ``[j, i]`` (row = y).  The unknowns are the (ny-1)(nx-1) interior vertices; the outer
+  ring holds boundary values.  The operators below work on either shape.
 * x-faces (vertical cell edges) carry the flux qx = u h at (x_i, y_{j+1/2}):
   ``qx[j, i] = s[j+1, i] - s[j, i]``, shape (n, n+1).
 * y-faces carry qy = v h at (x_{i+1/2}, y_j): ``qy[j, i] = -(s[j, i+1] - s[j, i])``,
@@ -32,10 +33,10 @@ def l5(v):
 
 
 def pad(interior, ring=None):
-    """(n+1, n+1) array from interior values and (optionally) a full array whose
-    outer ring supplies the boundary values."""
-    n = interior.shape[0] + 1
-    out = np.zeros((n + 1, n + 1), dtype=interior.dtype) if ring is None else ring.copy()
+    """(ny+1, nx+1) array from (ny-1, nx-1) interior values and (optionally) a full
+    array whose outer ring supplies the boundary values."""
+    my, mx = interior.shape
+    out = np.zeros((my + 2, mx + 2), dtype=interior.dtype) if ring is None else ring.copy()
     out[1:-1, 1:-1] = interior
     return out
 
@@ -111,13 +112,14 @@ class Level:
 
     def __init__(self, flow, g):
         self.g = g
-        self.n = flow.n
+        self.nx, self.ny = flow.n, (getattr(flow, "ny", 0) or flow.n)
+        self.n = self.nx  # the body operators use square levels
         self.h = flow.h * (2 ** g)
         self.dt = flow.dt
         self.re = flow.re
         self.alpha = flow.dt / (2.0 * flow.re * self.h * self.h)
-        self.x0 = flow.cx - 0.5 * flow.n * self.h
-        self.y0 = flow.cy - 0.5 * flow.n * self.h
+        self.x0 = flow.cx - 0.5 * self.nx * self.h
+        self.y0 = flow.cy - 0.5 * self.ny * self.h
         self.u_inf = tuple(flow.u_inf)
 
     def face_coords(self):

@@ -75,18 +75,22 @@ class Oracle:
                  drop_tol=0.007, subdomain_mode=None, dtype=np.float64):
         self.p = problem
         flow = problem.flow
-        assert flow.n % 4 == 0
+        nx, ny = flow.nx_ny
+        assert nx % 4 == 0 and ny % 4 == 0
         self.dtype = np.dtype(dtype)
         if self.dtype != np.float64 and problem.bodies:
             raise ValueError("extended precision covers the flow of problems without bodies")
+        if nx != ny and problem.bodies:
+            raise ValueError("bodies need square levels")
         self.levels = [grid.Level(flow, g) for g in range(flow.levels)]
         self.kernel = getattr(flow, "delta", "roma3")
         n = flow.n
         self.n = n
+        self.nx, self.ny = nx, ny
         self.dt = flow.dt
-        self.s = [self._zeros((n + 1, n + 1)) for _ in self.levels]
+        self.s = [self._zeros((ny + 1, nx + 1)) for _ in self.levels]
         self.hist = [None for _ in self.levels]
-        self.gring = [self._zeros((n + 1, n + 1)) for _ in self.levels]
+        self.gring = [self._zeros((ny + 1, nx + 1)) for _ in self.levels]
         self.newton_tol = newton_tol
         self.newton_max = newton_max
         self.fixed_iters = fixed_iters
@@ -126,13 +130,15 @@ class Oracle:
         nl = len(self.levels)
         for g in reversed(range(nl)):
             lv = self.levels[g]
+            nx, ny = self.nx, self.ny
             if g == nl - 1:
-                ring_s = self._zeros((self.n + 1, self.n + 1))
-                ring_g = self._zeros((self.n + 1, self.n + 1))
+                ring_s = self._zeros((ny + 1, nx + 1))
+                ring_g = self._zeros((ny + 1, nx + 1))
             else:
-                ring_s = md.ring_from_coarse(self.s[g + 1], self.n)
-                ring_g = 0.25 * md.ring_from_coarse(md.coarse_circulation(self.s[g + 1]), self.n)
-            om = omegas[g] if g < len(omegas) and omegas[g] is not None else self._zeros((self.n - 1,) * 2)
+                ring_s = md.ring_from_coarse(self.s[g + 1], nx, ny)
+                ring_g = 0.25 * md.ring_from_coarse(md.coarse_circulation(self.s[g + 1]), nx, ny)
+            om = (omegas[g] if g < len(omegas) and omegas[g] is not None
+                  else self._zeros((ny - 1, nx - 1)))
             gam = lv.h * lv.h * np.asarray(om, dtype=self.dtype)
             bs = -grid.l5(grid.ring_only(ring_s))
             self.s[g] = grid.pad(dst.solve_poisson(gam + bs), ring_s)
@@ -249,18 +255,18 @@ class Oracle:
         if not self.prepared:
             self.prepare()
         nl = len(self.levels)
-        n = self.n
+        n, nx, ny = self.n, self.nx, self.ny
         new_s = [None] * nl
         new_h = [None] * nl
         new_ring = [None] * nl
         for g in reversed(range(nl)):
             lv = self.levels[g]
             if g == nl - 1:
-                ring_s = self._zeros((n + 1, n + 1))
-                ring_g = self._zeros((n + 1, n + 1))
+                ring_s = self._zeros((ny + 1, nx + 1))
+                ring_g = self._zeros((ny + 1, nx + 1))
             else:
-                ring_s = md.ring_from_coarse(new_s[g + 1], n)
-                ring_g = 0.25 * md.ring_from_coarse(md.coarse_circulation(new_s[g + 1]), n)
+                ring_s = md.ring_from_coarse(new_s[g + 1], nx, ny)
+                ring_g = 0.25 * md.ring_from_coarse(md.coarse_circulation(new_s[g + 1]), nx, ny)
             gam = md.circulation_for_rhs(self.s[g], self.gring[g], self.s[g - 1] if g > 0 else None)
             qx, qy = lv.flux(self.s[g])
             ctn = grid.curl_t_nonlinear(*grid.nonlinear(qx, qy, gam, lv.h))

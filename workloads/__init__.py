@@ -23,7 +23,7 @@ import numpy as np
 
 @dataclasses.dataclass
 class Flow:
-    n: int               # cells per side of every level
+    n: int               # cells along x of every level (and along y unless ny is set)
     levels: int          # number of nested levels (level 0 is the finest)
     h: float             # finest grid spacing
     dt: float
@@ -32,6 +32,11 @@ class Flow:
     cy: float = 0.0
     u_inf: tuple = (1.0, 0.0)
     delta: str = "roma3"  # discrete delta kernel: "roma3" (3-point) or "peskin4" (4-point)
+    ny: int = 0          # cells along y of every level; 0: ny = n (square levels)
+
+    @property
+    def nx_ny(self):
+        return self.n, (self.ny if self.ny else self.n)
 
 
 @dataclasses.dataclass
@@ -126,7 +131,7 @@ class Problem:
     bodies: list
     subdomain: Optional[object] = None         # (x0, x1, y0, y1), a list of such rectangles,
                                                # or None = exact operators
-    vorticity0: Optional[List[np.ndarray]] = None  # per level, (n-1, n-1) interior omega
+    vorticity0: Optional[List[np.ndarray]] = None  # per level, (ny-1, nx-1) interior omega
     steps: int = 1
 
 
