@@ -24,8 +24,9 @@
  *     ib_step returns once the work is enqueued unless a host decision is needed
  *     (FSI convergence test), ib_sync waits for it.
  *   - A solver handle is not thread-safe; distinct handles are independent.
- *   - Grid arrays are row-major with the y index outer: value (i, j) of an
- *     (n-1) x (n-1) interior array is at [(j-1) * (n-1) + (i-1)].
+ *   - Grid arrays are row-major with the y index outer: value (i, j) of an interior
+ *     array of ny-1 rows of nx-1 values (nx = n; ny = n unless set) is at
+ *     [(j-1) * (nx-1) + (i-1)].
  *   - Stresses of a body of m points are 2m values: the m x-components, then the m
  *     y-components (Sec. 4.2).  f is the stress the fluid exerts on the body (force
  *     per unit length), so the body's force is sum(f) * ds.
@@ -85,9 +86,10 @@ typedef int32_t ib_status;
 typedef struct ib_solver ib_solver;
 
 typedef struct {
-  int32_t n;          /* cells per side of every level; one of 16, 20, 32, 40, 48, 64, 80,
-                         96, 128, 160, 192, 256, 320, 384, 512, 640, 768, 1024, 1280
-                         (2^a 3^b 5^c: the sine transforms' FFT lengths) */
+  int32_t n;          /* cells along x of every level (and along y unless ny is set); one of
+                         16, 20, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512,
+                         640, 768, 1024, 1280 (2^a 3^b 5^c: the sine transforms' FFT
+                         lengths), a multiple of 4 */
   int32_t levels;     /* nested levels (>= 1); level 0 is the finest */
   double h;           /* finest grid spacing */
   double cx, cy;      /* common centre of all levels */
@@ -101,6 +103,14 @@ typedef struct {
   int32_t newton_fixed_iter; /* > 0: run exactly this many FSI iterations, no test */
   double drop_tol;    /* B' drop tolerance epsilon (0.007, Sec. 3.2.2) */
   int32_t delta;      /* IB_DELTA_ROMA3 (0, the default) or IB_DELTA_PESKIN4 */
+  int32_t ny;         /* cells along y of every level (Sec. 5.3 runs on 2:1 levels); 0: ny = n.
+                         From the same list as n, a multiple of 4.  Rectangular levels
+                         (ny != n) carry flows without bodies (ib_prepare returns IB_ERR_ARG
+                         when bodies were added), in IB_FP64 or IB_FP32_FLOW (not
+                         IB_FP32_FLOW_BF16_DST) with the default transform configurations
+                         (ib_set_flow_variants refuses others), and are not batch members.
+                         Vorticity arrays are then (ny-1) rows of nx-1, streamfunction arrays
+                         (ny+1) rows of nx+1. */
 } ib_config;
 
 typedef struct {
@@ -216,7 +226,7 @@ ib_status ib_add_deformable(ib_solver* s, int32_t m, const double* xy_ref, doubl
  * IB_ERR_OUT_OF_SUBDOMAIN when a body lies in no rectangle. */
 ib_status ib_set_subdomain(ib_solver* s, double x0, double x1, double y0, double y1);
 
-/* Initial vorticity of one level: omega[(n-1)^2] at interior vertices (host). */
+/* Initial vorticity of one level: omega[(ny-1) (nx-1)] at interior vertices (host). */
 ib_status ib_set_vorticity(ib_solver* s, int32_t level, const double* omega);
 
 /* Offline stage: initial streamfunction from the vorticity, then the stationary
@@ -242,11 +252,11 @@ ib_status ib_read_force(ib_solver* s, int32_t body_id, double* out, int64_t cap)
  * (x, y, rotation per node); rigid -> its 2m point coordinates. */
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap);
 
-/* Vorticity of a level at interior vertices, (n-1)^2 doubles: the level's circulation
+/* Vorticity of a level at interior vertices, (ny-1) (nx-1) doubles: the level's circulation
  * state gamma (= C^T C s, carried alongside s) divided by h^2. */
 ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap);
 
-/* Streamfunction of a level including its ring, (n+1)^2 doubles. */
+/* Streamfunction of a level including its ring, (ny+1) (nx+1) doubles. */
 ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap);
 
 ib_status ib_get_stats(ib_solver* s, ib_stats* out);

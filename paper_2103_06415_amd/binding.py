@@ -46,6 +46,7 @@ class IbConfig(ctypes.Structure):
         ("re", c_double), ("dt", c_double), ("u_inf", c_double * 2), ("precision", c_int32),
         ("schur_mode", c_int32), ("newton_tol", c_double), ("newton_max_iter", c_int32),
         ("newton_fixed_iter", c_int32), ("drop_tol", c_double), ("delta", c_int32),
+        ("ny", c_int32),
     ]
 
 
@@ -258,6 +259,7 @@ class Solver:
         cfg.newton_tol, cfg.newton_max_iter = newton_tol, newton_max
         cfg.newton_fixed_iter, cfg.drop_tol = fixed_iters, drop_tol
         cfg.delta = {"roma3": IB_DELTA_ROMA3, "peskin4": IB_DELTA_PESKIN4}[getattr(fl, "delta", "roma3")]
+        cfg.ny = getattr(fl, "ny", 0) or 0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._alloc = TorchAllocator(torch.cuda.current_device(), self.stream) if torch_alloc else None
         self.handle = c_void_p()
@@ -343,17 +345,17 @@ class Solver:
         return out
 
     def vorticity(self, level=0):
-        n = self.problem.flow.n
-        out = np.zeros((n - 1) * (n - 1))
+        nx, ny = self.problem.flow.nx_ny
+        out = np.zeros((nx - 1) * (ny - 1))
         _check(self.lib.ib_read_vorticity(self.handle, level, _dptr(out), out.size), "ib_read_vorticity")
-        return out.reshape(n - 1, n - 1)
+        return out.reshape(ny - 1, nx - 1)
 
     def streamfunction(self, level=0):
-        n = self.problem.flow.n
-        out = np.zeros((n + 1) * (n + 1))
+        nx, ny = self.problem.flow.nx_ny
+        out = np.zeros((nx + 1) * (ny + 1))
         _check(self.lib.ib_read_streamfunction(self.handle, level, _dptr(out), out.size),
                "ib_read_streamfunction")
-        return out.reshape(n + 1, n + 1)
+        return out.reshape(ny + 1, nx + 1)
 
     def stats(self):
         st = IbStats()

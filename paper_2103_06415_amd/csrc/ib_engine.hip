@@ -219,6 +219,10 @@ struct ib_solver {
   bool has_alloc = false;
   hipStream_t stream = nullptr;
   int n = 0, pitch = 0;
+  int ny = 0;          // cells along y (n on a square level)
+  void* twy = nullptr;   // rectangular levels: transform tables of length ny, in the flow
+  void* lamy = nullptr;  //   precision, and sin(pi k / n), k <= n (the x axis)
+  void* sinx = nullptr;
   bool fp64 = true;
   bool gemm = false;  // predictor transforms as BF16-split products on the matrix cores
   FlowTuning tune;    // kernel configurations of the row and column transforms
@@ -419,6 +423,20 @@ ib_status make_tables(ib_solver* s, int n, void** tw, void** lam) {
   return IB_OK;
 }
 
+// Rectangular levels: the y axis's transform tables (length ny) and sin(pi k / nx), k <= nx,
+// which the column solve needs for the x transforms of the ring's bottom and top edges.
+template <typename T>
+ib_status make_rect_tables(ib_solver* s) {
+  ib_status st = make_tables<T>(s, s->ny, &s->twy, &s->lamy);
+  if (st) return st;
+  std::vector<T> sx(s->n + 1);
+  for (int k = 0; k <= s->n; ++k) sx[k] = (T)std::sin(M_PI * k / s->n);
+  s->sinx = dalloc(s, sx.size() * sizeof(T));
+  if (!s->sinx) return IB_ERR_OOM;
+  HIPCHK(hipMemcpy(s->sinx, sx.data(), sx.size() * sizeof(T), hipMemcpyHostToDevice));
+  return IB_OK;
+}
+
 // The operator solve of ib_op_solve on its tables: row transform of `in` into `out`, column
 // transform, spectral divide and inverse, inverse row transform, all in `out`.
 template <typename T>
@@ -533,27 +551,39 @@ ib_status solve_into(ib_solver* s, void* work, double alpha, double scale, int r
   c.alpha = (T)alpha;
   c.scale = (T)scale;
   c.w0 = 1;
-  c.w1 = s->n - 1;
+  c.w1 = s->ny - 1;
+  if (s->ny != s->n) {
+    // rectangular level: the column transform runs along y with the y tables; the x
+    // eigenvalues and sines come with the columns
+    c.ncols = s->n - 1;
+    c.lamx = static_cast<const T*>(lam);
+    c.sinx = static_cast<const T*>(s->sinx);
+    HIPCHK(launch_col_solve<T>(c, s->ny, 1, s->twy, s->lamy, s->stream));
+    return IB_OK;
+  }
   HIPCHK(launch_col_solve<T>(c, s->n, 1, tw, lam, s->stream));
   return IB_OK;
 }
 
+// Transform tables of the y axis (the x axis's on a square level).
+inline const void* twy_of(const ib_solver* s) { return s->ny != s->n ? s->twy : s->tw; }
+
 // Initial streamfunction of every level from its vorticity, coarse to fine.
 template <typename T>
 ib_status init_streamfunction(ib_solver* s) {
-  const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
-  std::vector<T> host((size_t)(n - 1) * P, T(0));
+  const int n = s->n, ny = s->ny, G = (int)s->lv.size(), P = s->pitch;
+  std::vector<T> host((size_t)(ny - 1) * P, T(0));
   for (int g = G - 1; g >= 0; --g) {
     LevelState& L = s->lv[g];
     if (g < G - 1) {
       HIPCHK(launch_ring<T>(static_cast<T*>(s->lv[g + 1].s), P, static_cast<T*>(s->lv[g + 1].g), P,
-                            n, static_cast<T*>(L.sring), static_cast<T*>(L.gring[L.gcur]),
+                            n, ny, static_cast<T*>(L.sring), static_cast<T*>(L.gring[L.gcur]),
                             s->stream));
     }
     std::fill(host.begin(), host.end(), T(0));
     if (g < (int)s->omega0.size() && !s->omega0[g].empty()) {
       const double h2 = L.h * L.h;
-      for (int j = 0; j < n - 1; ++j)
+      for (int j = 0; j < ny - 1; ++j)
         for (int i = 0; i < n - 1; ++i)
           host[(size_t)j * P + i] = (T)(h2 * s->omega0[g][(size_t)j * (n - 1) + i]);
     }
@@ -562,16 +592,17 @@ ib_status init_streamfunction(ib_solver* s) {
     HIPCHK(hipMemcpyAsync(L.g, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice,
                           s->stream));
     if (g < G - 1)
-      HIPCHK(launch_ring_edge_dst<T>(static_cast<T*>(L.sring), n, s->tw, static_cast<T*>(s->lift),
-                                     s->stream));
+      HIPCHK(launch_ring_edge_dst<T>(static_cast<T*>(L.sring), n, ny, s->tw, twy_of(s),
+                                     static_cast<T*>(s->lift), s->stream));
     RowArgs<T> r{};
     r.in = static_cast<T*>(s->work);
     r.out = static_cast<T*>(s->work);
     r.pi = r.po = P;
     r.r0 = 1;
-    r.r1 = n - 1;
+    r.r1 = ny - 1;
+    r.ny = ny;
     HIPCHK(launch_rowdst<T>(r, n, 1, s->tw, s->stream));
-    ib_status st = solve_into<T>(s, s->work, 0.0, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
+    ib_status st = solve_into<T>(s, s->work, 0.0, 4.0 / ((double)n * ny), 1, ny - 1, s->tw, s->lam,
                                  nullptr, g < G - 1 ? s->lift : nullptr);
     if (st) return st;
     RowArgs<T> q = r;
@@ -1731,7 +1762,7 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
 template <typename T>
 ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void* work,
                         void* workg) {
-  const int n = s->n, G = (int)s->lv.size(), P = s->pitch;
+  const int n = s->n, ny = s->ny, G = (int)s->lv.size(), P = s->pitch;
   const bool bodies = !s->bodies.empty();
   {
     LevelState& L = s->lv[g];
@@ -1740,9 +1771,9 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
     if (has_ring) {
       TimeScope ts(s, IB_K_RING);
       HIPCHK(launch_ring_dst<T>(static_cast<T*>(s->lv[g + 1].s), P,
-                                static_cast<T*>(s->lv[g + 1].g), P, n, static_cast<T*>(L.sring),
-                                static_cast<T*>(L.gring[nxt]), s->tw, static_cast<T*>(s->lift),
-                                s->stream));
+                                static_cast<T*>(s->lv[g + 1].g), P, n, ny,
+                                static_cast<T*>(L.sring), static_cast<T*>(L.gring[nxt]), s->tw,
+                                twy_of(s), static_cast<T*>(s->lift), s->stream));
     }
     RhsArgs<T> a{};
     a.s = static_cast<T*>(L.s);
@@ -1754,6 +1785,7 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
     a.hist_out = static_cast<T*>(L.hist);
     a.out = static_cast<T*>(work);
     a.n = n;
+    a.ny = ny;
     a.ps = a.pg = a.pgf = a.ph = a.po = P;
     a.alpha = (T)L.alpha;
     a.dt = (T)s->cfg.dt;
@@ -1771,7 +1803,7 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
         HIPCHK(launch_rhs_rowdst<T>(a, s->tw, s->stream));
       }
       TimeScope ts(s, IB_K_COL_SOLVE, true);
-      st = solve_into<T>(s, work, L.alpha, 4.0 / ((double)n * n), 1, n - 1, s->tw, s->lam,
+      st = solve_into<T>(s, work, L.alpha, 4.0 / ((double)n * ny), 1, ny - 1, s->tw, s->lam,
                          workg, has_ring ? s->lift : nullptr, s->tune.col, ts.b, ts.e);
     }
     if (st) return st;
@@ -1806,7 +1838,8 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
     }
     r.out = static_cast<T*>(L.s);
     r.r0 = 1;
-    r.r1 = n - 1;
+    r.r1 = ny - 1;
+    r.ny = ny;
     r.in2 = static_cast<T*>(workg);
     r.out2 = static_cast<T*>(L.g);
     r.var = s->tune.idst;
@@ -1901,7 +1934,8 @@ ib_status final_transform_level0(ib_solver* s) {
   r.pi = r.po = P;
   r.out = static_cast<T*>(L.s);
   r.r0 = 1;
-  r.r1 = n - 1;
+  r.r1 = s->ny - 1;
+  r.ny = s->ny;
   r.in2 = static_cast<T*>(s->workg);
   r.out2 = static_cast<T*>(L.g);
   r.var = s->tune.idst;
@@ -2151,9 +2185,10 @@ ib_status tune_gemm(ib_solver* s) {
 // Device state of the levels (allocated by ib_prepare, so that creating a solver costs
 // no device memory and a scheduler can admit it later).
 ib_status alloc_state(ib_solver* s) {
-  const size_t full = (size_t)(s->n + 1) * s->pitch * s->es;
-  const size_t inner = (size_t)(s->n - 1) * s->pitch * s->es;
-  const size_t ring = (size_t)4 * (s->n + 1) * s->es;
+  const size_t full = (size_t)(s->ny + 1) * s->pitch * s->es;
+  const size_t inner = (size_t)(s->ny - 1) * s->pitch * s->es;
+  const size_t ring = (size_t)ring_len(s->n, s->ny) * s->es;
+  const size_t lift = (size_t)(2 * (s->n - 1) + 2 * (s->ny - 1)) * s->es;
   for (auto& L : s->lv) {
     L.s = dalloc(s, full);
     L.g = dalloc(s, inner);
@@ -2171,15 +2206,16 @@ ib_status alloc_state(ib_solver* s) {
   if (s->lv.size() >= 3 && !s->gemm) {
     s->work_pre = dalloc(s, inner);
     s->workg_pre = dalloc(s, inner);
-    s->lift_pre = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
+    s->lift_pre = dalloc(s, lift);
     if (!s->work_pre || !s->workg_pre || !s->lift_pre) return IB_ERR_OOM;
   }
-  s->lift = dalloc(s, (size_t)4 * (s->n - 1) * s->es);
+  s->lift = dalloc(s, lift);
   s->sstar = dalloc(s, full);
   if (!s->work || !s->workg || !s->work2 || !s->sstar || !s->lift) return IB_ERR_OOM;
   ib_status st = s->fp64 ? make_tables<double>(s, s->n, &s->tw, &s->lam)
                          : make_tables<float>(s, s->n, &s->tw, &s->lam);
   if (st == IB_OK) st = make_tables<double>(s, s->n, &s->tw64, &s->lam64);
+  if (st == IB_OK && s->ny != s->n) st = s->fp64 ? make_rect_tables<double>(s) : make_rect_tables<float>(s);
   if (st == IB_OK && s->gemm) st = make_gemm_tables(s);
   if (st == IB_OK && s->gemm) st = tune_gemm(s);
   if (st) return st;
@@ -2755,7 +2791,7 @@ ib_status tune_flow(ib_solver* s) {
   const int n = s->n, P = s->pitch;
   if (s->tune_forced) return IB_OK;
   s->tune = FlowTuning{};
-  if (s->fp64 || !ib::flow_variant_available(n, 0)) return IB_OK;
+  if (s->fp64 || s->ny != n || !ib::flow_variant_available(n, 0)) return IB_OK;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(n);
   if (it != g_tune.end()) {
@@ -2931,6 +2967,10 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
                     ib_solver** out) {
   if (!cfg || !out) return IB_ERR_ARG;
   *out = nullptr;
+  const int cny = cfg->ny > 0 ? cfg->ny : cfg->n;
+  if (cfg->ny < 0 || !supported_n(cny) || cny % 4 != 0 ||
+      (cny != cfg->n && cfg->precision == IB_FP32_FLOW_BF16_DST))
+    return IB_ERR_ARG;
   if (!supported_n(cfg->n) || cfg->n % 4 != 0 || cfg->levels < 1 || cfg->levels > 12 ||
       !(cfg->h > 0) || !(cfg->dt > 0) || !(cfg->re > 0) ||
       (cfg->precision != IB_FP64 && cfg->precision != IB_FP32_FLOW &&
@@ -2948,6 +2988,7 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   }
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->n = cfg->n;
+  s->ny = cny;
   s->fp64 = cfg->precision == IB_FP64;
   s->gemm = cfg->precision == IB_FP32_FLOW_BF16_DST;
   s->es = s->fp64 ? 8 : 4;
@@ -3087,7 +3128,7 @@ ib_status ib_set_vorticity(ib_solver* s, int32_t level, const double* omega) {
   if (check(s) || level < 0 || level >= (int)s->lv.size() || !omega) return IB_ERR_ARG;
   if (s->prepared) return IB_ERR_STATE;
   if ((int)s->omega0.size() <= level) s->omega0.resize(level + 1);
-  s->omega0[level].assign(omega, omega + (size_t)(s->n - 1) * (s->n - 1));
+  s->omega0[level].assign(omega, omega + (size_t)(s->n - 1) * (s->ny - 1));
   return IB_OK;
 }
 
@@ -3095,6 +3136,10 @@ ib_status ib_prepare(ib_solver* s) {
   HipShared hip_lock;
   if (check(s)) return IB_ERR_ARG;
   if (s->prepared || s->released) return IB_ERR_STATE;
+  if (s->ny != s->n && !s->bodies.empty()) {
+    s->last_error = "bodies need square levels (ny = n)";
+    return IB_ERR_ARG;
+  }
   ib_status st = s->allocated ? IB_OK : alloc_state(s);
   if (st == IB_OK) st = tune_flow(s);
   if (st == IB_OK) st = s->fp64 ? do_prepare<double>(s) : do_prepare<float>(s);
@@ -3219,12 +3264,12 @@ ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64
   HipShared hip_lock;
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
   if (!s->allocated) return IB_ERR_STATE;
-  const int n = s->n;
-  if (cap < (int64_t)(n + 1) * (n + 1)) return IB_ERR_CAPACITY;
+  const int n = s->n, ny = s->ny;
+  if (cap < (int64_t)(n + 1) * (ny + 1)) return IB_ERR_CAPACITY;
   HIPCHK(hipStreamSynchronize(s->stream));
-  std::vector<char> buf((size_t)(n + 1) * s->pitch * s->es);
+  std::vector<char> buf((size_t)(ny + 1) * s->pitch * s->es);
   HIPCHK(hipMemcpy(buf.data(), s->lv[level].s, buf.size(), hipMemcpyDeviceToHost));
-  for (int j = 0; j <= n; ++j)
+  for (int j = 0; j <= ny; ++j)
     for (int i = 0; i <= n; ++i) {
       const size_t k = (size_t)j * s->pitch + i;
       out[(size_t)j * (n + 1) + i] =
@@ -3235,8 +3280,8 @@ ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64
 
 ib_status read_vorticity_impl(ib_solver* s, int32_t level, double* out, int64_t cap) {
   if (check(s) || !out || level < 0 || level >= (int)s->lv.size()) return IB_ERR_ARG;
-  const int n = s->n;
-  if (cap < (int64_t)(n - 1) * (n - 1)) return IB_ERR_CAPACITY;
+  const int n = s->n, ny = s->ny;
+  if (cap < (int64_t)(n - 1) * (ny - 1)) return IB_ERR_CAPACITY;
   if (s->released) {
     if (level != 0) return IB_ERR_STATE;
     std::memcpy(out, s->h_vort0.data(), s->h_vort0.size() * 8);
@@ -3244,11 +3289,11 @@ ib_status read_vorticity_impl(ib_solver* s, int32_t level, double* out, int64_t 
   }
   if (!s->allocated) return IB_ERR_STATE;
   HIPCHK(hipStreamSynchronize(s->stream));
-  std::vector<char> buf((size_t)(n - 1) * s->pitch * s->es);
+  std::vector<char> buf((size_t)(ny - 1) * s->pitch * s->es);
   HIPCHK(hipMemcpy(buf.data(), s->lv[level].g, buf.size(), hipMemcpyDeviceToHost));
   const double h = s->lv[level].h;
   const double inv = 1.0 / (h * h);
-  for (int j = 0; j < n - 1; ++j)
+  for (int j = 0; j < ny - 1; ++j)
     for (int i = 0; i < n - 1; ++i) {
       const size_t k = (size_t)j * s->pitch + i;
       const double g = s->fp64 ? reinterpret_cast<double*>(buf.data())[k]
@@ -3273,7 +3318,7 @@ ib_status ib_batch_create(ib_solver* const* members, int32_t count, void* hip_st
     if (!s) return IB_ERR_ARG;
     for (int j = 0; j < i; ++j)
       if (members[j] == s) return IB_ERR_ARG;
-    if (s->fp64 != members[0]->fp64) return IB_ERR_ARG;
+    if (s->fp64 != members[0]->fp64 || s->ny != s->n) return IB_ERR_ARG;  // square levels only
     if (!s->prepared || s->failed || s->released) return IB_ERR_STATE;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -3445,7 +3490,8 @@ ib_status ib_set_flow_variants(ib_solver* s, int32_t rhs, int32_t col, int32_t i
   const int32_t v[3] = {rhs, col, idst};
   for (int k = 0; k < 3; ++k) {
     if (v[k] < -1 || v[k] >= IB_FLOW_VARIANTS) return IB_ERR_ARG;
-    if (v[k] > 0 && !ib::flow_kind_variant_available(k == 1 ? 1 : 0, v[k], s->n, s->fp64 ? 1 : 0))
+    if (v[k] > 0 && (s->ny != s->n ||
+                     !ib::flow_kind_variant_available(k == 1 ? 1 : 0, v[k], s->n, s->fp64 ? 1 : 0)))
       return IB_ERR_ARG;
   }
   if (rhs > 0 && s->gemm) return IB_ERR_ARG;
@@ -3523,7 +3569,7 @@ ib_status ib_release(ib_solver* s) {
       if (s->ndof)
         HIPCHK(hipMemcpy(s->h_chi.data(), s->fa.chi, s->h_chi.size() * 8, hipMemcpyDeviceToHost));
     }
-    std::vector<double> v((size_t)(s->n - 1) * (s->n - 1));
+    std::vector<double> v((size_t)(s->n - 1) * (s->ny - 1));
     ib_status st = read_vorticity_impl(s, 0, v.data(), (int64_t)v.size());
     if (st) return st;
     s->h_vort0.swap(v);
@@ -3539,13 +3585,15 @@ ib_status ib_release(ib_solver* s) {
 
 ib_status ib_estimate_bytes(const ib_solver* s, int64_t* resident, int64_t* peak) {
   if (!s || !resident || !peak) return IB_ERR_ARG;
-  const int n = s->n, G = (int)s->lv.size();
+  const int n = s->n, ny = s->ny, G = (int)s->lv.size();
   const size_t es = s->es, P = s->pitch;
-  const size_t full = (size_t)(n + 1) * P * es, inner = (size_t)(n - 1) * P * es;
-  size_t r = (size_t)G * (full + 2 * inner + 3 * 4 * (n + 1) * es);
-  r += 3 * inner + full + 4 * (size_t)(n - 1) * es + 2 * (size_t)2 * n * (8 + es);
+  const size_t full = (size_t)(ny + 1) * P * es, inner = (size_t)(ny - 1) * P * es;
+  const size_t ring = (size_t)ring_len(n, ny) * es, lift = (size_t)(2 * (n - 1) + 2 * (ny - 1)) * es;
+  size_t r = (size_t)G * (full + 2 * inner + 3 * ring);
+  r += 3 * inner + full + lift + 2 * (size_t)2 * n * (8 + es);
+  if (ny != n) r += (size_t)2 * ny * (8 + es) + (size_t)(n + 1) * es;  // the y tables
   // scratch of the levels launched ahead (three or more levels)
-  if (G >= 3 && !s->gemm) r += 2 * inner + 4 * (size_t)(n - 1) * es;
+  if (G >= 3 && !s->gemm) r += 2 * inner + lift;
   if (s->gemm) {
     // split sine matrix (two BF16 copies of kpad^2) and two FP32 product buffers
     const size_t kp = (size_t)(n - 1 + 63) / 64 * 64;

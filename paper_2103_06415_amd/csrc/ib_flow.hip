@@ -73,7 +73,7 @@ hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st
     }
   }
   constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
-  const int nb = (a.n - 1 + R - 1) / R;
+  const int nb = ((a.ny > 0 ? a.ny : a.n) - 1 + R - 1) / R;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
 #define L_(NN)                                                                                   \
   if (transform) hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 1>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb); \
@@ -105,7 +105,7 @@ hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* t
     }
   }
   constexpr int CW = Cfg<T>::CW, NT = Cfg<T>::NTC;
-  const int nb = (n - 1 + CW - 1) / CW;
+  const int nb = ((a.ncols > 0 ? a.ncols : n - 1) + CW - 1) / CW;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
   const T* l = static_cast<const T*>(lam);
 #define L_(NN)                                                                                     \
@@ -142,30 +142,42 @@ hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw
 }
 
 template <typename T>
-hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
-                       hipStream_t st) {
-  const int tot = 4 * (n + 1);
-  hipLaunchKernelGGL((k_ring<T>), dim3((tot + 255) / 256), dim3(256), 0, st, sc, psc, gc, pgc, n,
-                     sring, gring);
+hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int nx, int ny, T* sring,
+                       T* gring, hipStream_t st) {
+  const int tot = ring_len(nx, ny);
+  hipLaunchKernelGGL((k_ring<T>), dim3((tot + 255) / 256), dim3(256), 0, st, sc, psc, gc, pgc, nx,
+                     ny, sring, gring);
   return hipGetLastError();
 }
 
+// Edge transforms of a ring: all four edges in one workgroup on a square level; on a
+// rectangular one the bottom and top edges (length nx, tables twx) and the left and right
+// edges (length ny, tables twy) in one workgroup each.
 template <typename T>
-hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, hipStream_t st) {
-  const c2<T>* t = static_cast<const c2<T>*>(tw);
-#define L_(NN) hipLaunchKernelGGL((k_ring_edge_dst<T, NN, 256>), dim3(1), dim3(256), 0, st, sring, t, lift)
-  IB_DISPATCH_N(n, L_)
+hipError_t launch_ring_edge_dst(const T* sring, int nx, int ny, const void* twx, const void* twy,
+                                T* lift, hipStream_t st) {
+  for (int pass = 0; pass < (nx == ny ? 1 : 2); ++pass) {
+    const int n = pass == 0 ? nx : ny, e0 = pass == 0 ? 0 : 2, ne = nx == ny ? 4 : 2;
+    const c2<T>* t = static_cast<const c2<T>*>(pass == 0 ? twx : twy);
+#define L_(NN) hipLaunchKernelGGL((k_ring_edge_dst<T, NN, 256>), dim3(1), dim3(256), 0, st, sring, t, lift, e0, ne, nx, ny)
+    IB_DISPATCH_N(n, L_)
 #undef L_
+  }
   return hipGetLastError();
 }
 
+// New rings and their edge transforms, one workgroup per edge (two launches on a rectangular
+// level: the bottom and top edges with the x tables, the left and right with the y tables).
 template <typename T>
-hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
-                           const void* tw, T* lift, hipStream_t st) {
-  const c2<T>* t = static_cast<const c2<T>*>(tw);
-#define L_(NN) hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(4), dim3(256), 0, st, sc, psc, gc, pgc, sring, gring, t, lift)
-  IB_DISPATCH_N(n, L_)
+hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int nx, int ny, T* sring,
+                           T* gring, const void* twx, const void* twy, T* lift, hipStream_t st) {
+  for (int pass = 0; pass < (nx == ny ? 1 : 2); ++pass) {
+    const int n = pass == 0 ? nx : ny, e0 = pass == 0 ? 0 : 2, ne = nx == ny ? 4 : 2;
+    const c2<T>* t = static_cast<const c2<T>*>(pass == 0 ? twx : twy);
+#define L_(NN) hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(ne), dim3(256), 0, st, sc, psc, gc, pgc, sring, gring, t, lift, e0, nx, ny)
+    IB_DISPATCH_N(n, L_)
 #undef L_
+  }
   return hipGetLastError();
 }
 
@@ -176,10 +188,11 @@ hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int n, T*
                                           hipStream_t);                                        \
   template hipError_t launch_row_idst<T>(const RowArgs<T>&, int, int, const void*, const T*, int, \
                                          hipStream_t);                                         \
-  template hipError_t launch_ring<T>(const T*, int, const T*, int, int, T*, T*, hipStream_t);   \
-  template hipError_t launch_ring_edge_dst<T>(const T*, int, const void*, T*, hipStream_t);    \
-  template hipError_t launch_ring_dst<T>(const T*, int, const T*, int, int, T*, T*, const void*, T*, \
-                                         hipStream_t);
+  template hipError_t launch_ring<T>(const T*, int, const T*, int, int, int, T*, T*, hipStream_t); \
+  template hipError_t launch_ring_edge_dst<T>(const T*, int, int, const void*, const void*, T*,  \
+                                              hipStream_t);                                     \
+  template hipError_t launch_ring_dst<T>(const T*, int, const T*, int, int, int, T*, T*,         \
+                                         const void*, const void*, T*, hipStream_t);
 IB_INST(float)
 IB_INST(double)
 #undef IB_INST

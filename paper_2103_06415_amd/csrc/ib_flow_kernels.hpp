@@ -40,19 +40,19 @@ __device__ __forceinline__ T ld(const T* p, int pitch, int j, int i) {
 // of its loads before it uses any of them.
 template <typename T>
 __device__ __forceinline__ const T* gamma_src(const RhsArgs<T>& a, int i, int j, int& idx, T& sc) {
-  const int n = a.n;
+  const int nx = a.n, ny = a.ny > 0 ? a.ny : a.n;
   const T* p = a.g;
   idx = (j - 1) * a.pg + (i - 1);
   sc = T(1);
-  if (a.gf != nullptr && i > n / 4 && i < 3 * n / 4 && j > n / 4 && j < 3 * n / 4) {
+  if (a.gf != nullptr && i > nx / 4 && i < 3 * nx / 4 && j > ny / 4 && j < 3 * ny / 4) {
     p = a.gf;
-    idx = (2 * j - n / 2 - 1) * a.pgf + (2 * i - n / 2 - 1);
+    idx = (2 * j - ny / 2 - 1) * a.pgf + (2 * i - nx / 2 - 1);
     sc = T(4);
   }
-  if (i == n) { p = a.gring; idx = RING_R * (n + 1) + j; sc = T(1); }
-  if (i == 0) { p = a.gring; idx = RING_L * (n + 1) + j; sc = T(1); }
-  if (j == n) { p = a.gring; idx = RING_T * (n + 1) + i; sc = T(1); }
-  if (j == 0) { p = a.gring; idx = RING_B * (n + 1) + i; sc = T(1); }
+  if (i == nx) { p = a.gring; idx = ring_off(RING_R, nx, ny) + j; sc = T(1); }
+  if (i == 0) { p = a.gring; idx = ring_off(RING_L, nx, ny) + j; sc = T(1); }
+  if (j == ny) { p = a.gring; idx = ring_off(RING_T, nx, ny) + i; sc = T(1); }
+  if (j == 0) { p = a.gring; idx = ring_off(RING_B, nx, ny) + i; sc = T(1); }
   return p;
 }
 
@@ -127,11 +127,13 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
   constexpr int UNI = (STG > BUFT ? STG : BUFT) / 2 + 1;
   __shared__ c2<T> uni[UNI];
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
-  __shared__ T sring[4][W];          // new circulation ring: bottom, top, left, right
-  static_assert(sizeof(uni) + sizeof(stw) + sizeof(sring) <= 160 * 1024, "LDS");
+  __shared__ T sbt[2][W];            // new circulation ring: bottom and top rows
+  __shared__ T slr[2][ROWS];         //   left and right entries at this block's rows
+  static_assert(sizeof(uni) + sizeof(stw) + sizeof(sbt) + sizeof(slr) <= 160 * 1024, "LDS");
   const int blk = xcd_block(bx, nblocks);
   if (blk < 0) return;
   const int tid = threadIdx.x;
+  const int ny = a.ny > 0 ? a.ny : N;  // rows of the level (the row length is N)
   const int j0 = 1 + blk * ROWS;
   T* ss = reinterpret_cast<T*>(uni);
   T* sg = ss + SR * W;
@@ -148,7 +150,7 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
       const int r = e / W, i = e % W;
-      const int j = min(j0 - 1 + r, N);
+      const int j = min(j0 - 1 + r, ny);
       int gi;
       const T* gp = gamma_src(a, i, j, gi, gsc[b]);
       vs[b] = a.s[j * a.ps + i];  // indices fit in 32 bits (n <= 1024)
@@ -157,21 +159,30 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
 #pragma unroll
     for (int b = 0; b < PP; ++b) {
       const int e = tid + b * NT;
-      const int t = e / (N - 1), i = 1 + e % (N - 1), j = min(j0 + t, N - 1);
+      const int t = e / (N - 1), i = 1 + e % (N - 1), j = min(j0 + t, ny - 1);
       hp[b] = a.hist_in != nullptr ? a.hist_in[(j - 1) * a.ph + (i - 1)] : T(0);
     }
-    constexpr int PR = (4 * W + NT - 1) / NT;
+    // the ring entries this block uses: the bottom and top rows, the left and right entries
+    // of rows j0 .. j0 + ROWS - 1 (clamped to the ring)
+    constexpr int RC = 2 * W + 2 * ROWS;
+    constexpr int PR = (RC + NT - 1) / NT;
     T rv0[PR];
     if (a.gring_new != nullptr) {
 #pragma unroll
-      for (int b = 0; b < PR; ++b) rv0[b] = a.gring_new[min(tid + b * NT, 4 * W - 1)];
+      for (int b = 0; b < PR; ++b) {
+        const int e = min(tid + b * NT, RC - 1);
+        const int idx = e < 2 * W ? ring_off(e / W, N, ny) + e % W
+                                  : ring_off(RING_L + (e - 2 * W) / ROWS, N, ny) +
+                                        min(j0 + (e - 2 * W) % ROWS, ny);
+        rv0[b] = a.gring_new[idx];
+      }
     }
     load_table<T, N, NT, MAXR>(stw, tw, tid);
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
       if (e < CNT) {
-        const bool ok = j0 - 1 + e / W <= N;
+        const bool ok = j0 - 1 + e / W <= ny;
         ss[e] = ok ? vs[b] : T(0);
         sg[e] = ok ? gsc[b] * vg[b] : T(0);
       }
@@ -180,7 +191,8 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
 #pragma unroll
       for (int b = 0; b < PR; ++b) {
         const int e = tid + b * NT;
-        if (e < 4 * W) (&sring[0][0])[e] = rv0[b];
+        if (e < 2 * W) (&sbt[0][0])[e] = rv0[b];
+        else if (e < RC) (&slr[0][0])[e - 2 * W] = rv0[b];
       }
     }
   }
@@ -191,13 +203,13 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
     const int e = tid + b * NT;
     const int t = e / (N - 1), i = 1 + e % (N - 1), j = j0 + t;
     rv[b] = T(0);
-    if (e < NPT && j <= N - 1) {
+    if (e < NPT && j <= ny - 1) {
       T ring = T(0);
       if (a.gring_new != nullptr) {
-        if (i == 1) ring += sring[RING_L][j];
-        if (i == N - 1) ring += sring[RING_R][j];
-        if (j == 1) ring += sring[RING_B][i];
-        if (j == N - 1) ring += sring[RING_T][i];
+        if (i == 1) ring += slr[0][t];
+        if (i == N - 1) ring += slr[1][t];
+        if (j == 1) ring += sbt[RING_B][i];
+        if (j == ny - 1) ring += sbt[RING_T][i];
       }
       rv[b] = rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr, ring);
     }
@@ -208,7 +220,7 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
     for (int b = 0; b < PP; ++b) {
       const int e = tid + b * NT;
       const int j = j0 + e / (N - 1);
-      if (e < NPT && j <= N - 1) a.out[(size_t)(j - 1) * a.po + e % (N - 1)] = rv[b];
+      if (e < NPT && j <= ny - 1) a.out[(size_t)(j - 1) * a.po + e % (N - 1)] = rv[b];
     }
     return;
   }
@@ -225,7 +237,7 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
   for (int e = tid; e < ROWS * (N / 2); e += NT) {
     const int t = e / (N / 2), k = 1 + e % (N / 2);
     const int j = j0 + t;
-    if (j > N - 1) continue;
+    if (j > ny - 1) continue;
     T xk, xnk;
     dst_unpack<T, N>(buf + t * fft_pad_len<N>(), stw, k, xk, xnk);
     T* o = a.out + (size_t)(j - 1) * a.po;
@@ -246,7 +258,7 @@ template <typename T, int N, int ROWS, int NT, int DST, int MAXR = 16>
 __global__ __launch_bounds__(NT) void k_rhs_rowdst_multi(const RhsArgs<T>* __restrict__ tab,
                                                          const c2<T>* __restrict__ tw) {
   const RhsArgs<T> a = tab[blockIdx.y];
-  const int nb = (a.n - 1 + ROWS - 1) / ROWS;
+  const int nb = ((a.ny > 0 ? a.ny : a.n) - 1 + ROWS - 1) / ROWS;
   if ((int)blockIdx.x >= xcd_grid(nb)) return;
   rhs_rowdst_body<T, N, ROWS, NT, DST, MAXR>(a, tw, nb, blockIdx.x);
 }
@@ -334,6 +346,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
   if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;
   const int k0 = blk * CW;
+  const int nc = a.ncols > 0 ? a.ncols : N - 1;  // columns (x); the transform runs along y (N)
   const T* in = a.in + (size_t)by * a.bsi;
   {
     constexpr int CNT = (N - 1) * CW;
@@ -344,7 +357,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
       const int r = e / CW, col = k0 + e % CW;
-      bool ok = e < CNT && col < N - 1;
+      bool ok = e < CNT && col < nc;
       long idx;
       if (a.rfirst != nullptr) {
         const int q = r + 1 - rf;
@@ -368,11 +381,11 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
 #pragma unroll
       for (int b = 0; b < PF; ++b) {
         const int e = tid + b * NT;
-        fv[b] = e < 2 * (N - 1) ? a.lift[2 * (N - 1) + e] : T(0);
+        fv[b] = e < 2 * (N - 1) ? a.lift[2 * nc + e] : T(0);
       }
       if (tid < 2 * CW) {
         const int col = k0 + tid % CW;
-        f01 = col < N - 1 ? a.lift[(tid / CW) * (N - 1) + col] : T(0);
+        f01 = col < nc ? a.lift[(tid / CW) * nc + col] : T(0);
       }
     }
 #pragma unroll
@@ -406,7 +419,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
       const int c = e % CW, l = 1 + e / CW;
       const int col = k0 + c;
       dst_unpack<T, N>(buf + c * fft_pad_len<N>(), stw, l, xa[b], xb[b]);
-      const T lk = (col < N - 1) ? slam[col] : T(1);
+      const T lk = (col < nc) ? (a.lamx != nullptr ? a.lamx[col] : slam[col]) : T(1);
       const T l1 = lk + slam[l - 1];
       const T l2 = lk + slam[N - l - 1];
       la[b] = l1;
@@ -415,10 +428,11 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
       eb[b] = T(1) + a.alpha * l2;
       fa[b] = T(0);
       fb[b] = T(0);
-      if (a.lift != nullptr && col < N - 1) {
-        // sum_{i,j} B(s_ring)_{ij} sin(pi i k / n) sin(pi j l / n) over the four edges
+      if (a.lift != nullptr && col < nc) {
+        // sum_{i,j} B(s_ring)_{ij} sin(pi i k / nx) sin(pi j l / ny) over the four edges
         const int k = col + 1;
-        const T sk = tw_sin<T, N>(stw, k), sl = tw_sin<T, N>(stw, l);  // sin(pi k/n), sin(pi l/n)
+        const T sk = a.sinx != nullptr ? a.sinx[k] : tw_sin<T, N>(stw, k);  // sin(pi k / nx)
+        const T sl = tw_sin<T, N>(stw, l);                                  // sin(pi l / ny)
         const T pk = (k & 1) ? T(1) : T(-1);     // (-1)^(k+1)
         const T pl = (l & 1) ? T(1) : T(-1);     // (-1)^(l+1) = (-1)^(n-l+1)
         const T eb_k = slift01[c], et_k = slift01[CW + c];
@@ -440,7 +454,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
         for (int b = 0; b < PER; ++b) {
           const int e = tid + b * NT;
           const int c = e % CW, j = 1 + e / CW, col = k0 + c, j2 = N - j;
-          const bool ok = a.accumulate && e < NP && col < N - 1;
+          const bool ok = a.accumulate && e < NP && col < nc;
           pa[o][b] = (ok && j >= a.w0 && j <= a.w1) ? dsts[o][(size_t)(j - 1) * a.po + col] : T(0);
           pb[o][b] = (ok && j != N / 2 && j2 >= a.w0 && j2 <= a.w1)
                          ? dsts[o][(size_t)(j2 - 1) * a.po + col]
@@ -474,7 +488,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
           if (e >= NP) continue;
           const int c = e % CW, j = 1 + e / CW;
           const int col = k0 + c;
-          if (col >= N - 1) continue;
+          if (col >= nc) continue;
           T yk, ynk;
           dst_unpack<T, N>(buf + (o * CW + c) * fft_pad_len<N>(), stw, j, yk, ynk);
           if (j >= a.w0 && j <= a.w1) dsts[o][(size_t)(j - 1) * a.po + col] = pa[o][b] + yk;
@@ -493,7 +507,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
     for (int b = 0; b < PER; ++b) {
       const int e = tid + b * NT;
       const int c = e % CW, j = 1 + e / CW, col = k0 + c, j2 = N - j;
-      const bool ok = a.accumulate && e < NP && col < N - 1;
+      const bool ok = a.accumulate && e < NP && col < nc;
       pa[b] = (ok && j >= a.w0 && j <= a.w1) ? dst[(size_t)(j - 1) * a.po + col] : T(0);
       pb[b] = (ok && j != N / 2 && j2 >= a.w0 && j2 <= a.w1) ? dst[(size_t)(j2 - 1) * a.po + col]
                                                               : T(0);
@@ -520,7 +534,7 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
       if (e >= NP) continue;
       const int c = e % CW, j = 1 + e / CW;
       const int col = k0 + c;
-      if (col >= N - 1) continue;
+      if (col >= nc) continue;
       T yk, ynk;
       dst_unpack<T, N>(buf + c * fft_pad_len<N>(), stw, j, yk, ynk);
       if (j >= a.w0 && j <= a.w1) dst[(size_t)(j - 1) * a.po + col] = pa[b] + yk;
@@ -546,9 +560,9 @@ __global__ __launch_bounds__(NT) void k_col_solve_multi(const ColArgs<T>* __rest
   col_solve_body<T, N, CW, NT, MAXR>(a, tw, lam, nb, blockIdx.x, 0);
 }
 
-// Inverse row DST of rows [r0, r1] into the interior of a full (n+1)-row array; the
-// ring columns (and, when ring rows are requested, rows 0 and n) come from `ring`
-// (zero when null).  With interior_out the output is an (n-1)-row interior array.
+// Inverse row DST of rows [r0, r1] into the interior of a full (ny+1)-row array (rows of N+1
+// entries, ny = a.ny or N); the ring columns (and, when ring rows are requested, rows 0 and
+// ny) come from `ring` (zero when null).  With interior_out the output is an (n-1)-row interior array.
 // With in2/out2 set the same rows of a second array are transformed in the same
 // workgroup into the interior array out2 (the level's circulation).
 template <typename T, int N, int ROWS, int NT, int DUAL, int MAXR>
@@ -607,17 +621,18 @@ __device__ __forceinline__ void row_idst_body(const RowArgs<T>& a, const c2<T>* 
     }
   }
   if (a.interior_out) return;
+  const int ny = a.ny > 0 ? a.ny : N;
   for (int t = tid; t < ROWS; t += NT) {
     const int j = j0 + t;
     if (j > a.r1) continue;
     T* o = out + (size_t)j * a.po;
-    o[0] = ring ? ring[RING_L * (N + 1) + j] : T(0);
-    o[N] = ring ? ring[RING_R * (N + 1) + j] : T(0);
+    o[0] = ring ? ring[ring_off(RING_L, N, ny) + j] : T(0);
+    o[N] = ring ? ring[ring_off(RING_R, N, ny) + j] : T(0);
   }
   if (ring_rows && blk == 0) {
     for (int i = tid; i <= N; i += NT) {
-      out[i] = ring ? ring[RING_B * (N + 1) + i] : T(0);
-      out[(size_t)N * a.po + i] = ring ? ring[RING_T * (N + 1) + i] : T(0);
+      out[i] = ring ? ring[ring_off(RING_B, N, ny) + i] : T(0);
+      out[(size_t)ny * a.po + i] = ring ? ring[ring_off(RING_T, N, ny) + i] : T(0);
     }
   }
 }
@@ -661,13 +676,16 @@ __device__ __forceinline__ T coarse_g(const T* gc, int p, int edge, int line, in
   return gc[(size_t)(j - 1) * p + (i - 1)];
 }
 
+// Entry idx of ring edge `edge` of an nx x ny level: along the bottom and top edges the fine i
+// sits at coarse (i + nx/2) / 2 on the coarse rows ny/4 and 3 ny/4; along the left and right
+// edges the fine j sits at (j + ny/2) / 2 on the coarse columns nx/4 and 3 nx/4.
 template <typename T>
 __device__ __forceinline__ void ring_values(const T* __restrict__ sc, int psc,
-                                            const T* __restrict__ gc, int pgc, int n, int e, T& sv,
-                                            T& gv) {
-  const int edge = e / (n + 1), idx = e % (n + 1);
-  const int q = n / 2;
-  const int line = (edge == RING_B || edge == RING_L) ? n / 4 : (3 * n) / 4;
+                                            const T* __restrict__ gc, int pgc, int nx, int ny,
+                                            int edge, int idx, T& sv, T& gv) {
+  const int q = edge < 2 ? nx / 2 : ny / 2;
+  const int line = edge == RING_B ? ny / 4 : edge == RING_T ? (3 * ny) / 4
+                 : edge == RING_L ? nx / 4 : (3 * nx) / 4;
   if (((idx + q) & 1) == 0) {
     const int I = (idx + q) / 2;
     sv = coarse_s(sc, psc, edge, line, I);
@@ -686,28 +704,33 @@ __device__ __forceinline__ void ring_values(const T* __restrict__ sc, int psc,
 
 template <typename T>
 __device__ __forceinline__ void ring_body(const T* __restrict__ sc, int psc,
-                                          const T* __restrict__ gc, int pgc, int n, T* sring,
-                                          T* gring, int e) {
-  if (e >= 4 * (n + 1)) return;
+                                          const T* __restrict__ gc, int pgc, int nx, int ny,
+                                          T* sring, T* gring, int e) {
+  if (e >= ring_len(nx, ny)) return;
+  const int edge = e < 2 * (nx + 1) ? e / (nx + 1) : 2 + (e - 2 * (nx + 1)) / (ny + 1);
+  const int idx = e - ring_off(edge, nx, ny);
   T sv, gv;
-  ring_values(sc, psc, gc, pgc, n, e, sv, gv);
+  ring_values(sc, psc, gc, pgc, nx, ny, edge, idx, sv, gv);
   sring[e] = sv;
   gring[e] = gv;
 }
 
 template <typename T>
-__global__ void k_ring(const T* __restrict__ sc, int psc, const T* __restrict__ gc, int pgc, int n,
-                       T* sring, T* gring) {
-  ring_body(sc, psc, gc, pgc, n, sring, gring, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void k_ring(const T* __restrict__ sc, int psc, const T* __restrict__ gc, int pgc, int nx,
+                       int ny, T* sring, T* gring) {
+  ring_body(sc, psc, gc, pgc, nx, ny, sring, gring, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 
-// Unnormalised 1-D DSTs of the four edges of a streamfunction ring, as they appear in
-// B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top s(i, n) on row
-// n-1, left s(0, j) on column 1, right s(n, j) on column n-1.  One workgroup.
+// Unnormalised 1-D DSTs of edges edge0 .. edge0 + nedge - 1 (nedge <= 4) of a streamfunction
+// ring, as they appear in B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top
+// s(i, ny) on row ny-1, left s(0, j) on column 1, right s(nx, j) on column nx-1.  N is the
+// length of those edges' transforms (nx for bottom and top, ny for left and right).  One
+// workgroup.
 template <typename T, int N, int NT>
 __device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
-                                                   const c2<T>* __restrict__ tw, T* lift) {
+                                                   const c2<T>* __restrict__ tw, T* lift,
+                                                   int edge0, int nedge, int nx, int ny) {
   __shared__ c2<T> buf[4 * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
   const int tid = threadIdx.x;
@@ -717,8 +740,8 @@ __device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
     T v[PER];
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
-      const int e = tid + b * NT;
-      v[b] = e < CNT ? sring[(e / (N - 1)) * (N + 1) + 1 + e % (N - 1)] : T(0);
+      const int e = tid + b * NT, q = e / (N - 1);
+      v[b] = (e < CNT && q < nedge) ? sring[ring_off(edge0 + q, nx, ny) + 1 + e % (N - 1)] : T(0);
     }
     load_table<T, N, NT>(stw, tw, tid);
 #pragma unroll
@@ -727,74 +750,81 @@ __device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
       if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
     }
   }
-  for (int edge = tid; edge < 4; edge += NT) dst_pack_zeros<T, N>(buf + edge * fft_pad_len<N>());
+  for (int q = tid; q < 4; q += NT) dst_pack_zeros<T, N>(buf + q * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, 4, NT>(buf, stw, tid);
-  for (int e = tid; e < 4 * (N / 2); e += NT) {
-    const int edge = e / (N / 2), k = 1 + e % (N / 2);
+  for (int e = tid; e < nedge * (N / 2); e += NT) {
+    const int q = e / (N / 2), k = 1 + e % (N / 2);
     T xk, xnk;
-    dst_unpack<T, N>(buf + edge * fft_pad_len<N>(), stw, k, xk, xnk);
-    lift[edge * (N - 1) + k - 1] = xk;
-    if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
+    dst_unpack<T, N>(buf + q * fft_pad_len<N>(), stw, k, xk, xnk);
+    T* lo = lift + lift_off(edge0 + q, nx, ny);
+    lo[k - 1] = xk;
+    if (k != N / 2) lo[N - k - 1] = xnk;
   }
 }
 
 template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
-                                                      const c2<T>* __restrict__ tw, T* lift) {
-  ring_edge_dst_body<T, N, NT>(sring, tw, lift);
+                                                      const c2<T>* __restrict__ tw, T* lift,
+                                                      int edge0, int nedge, int nx, int ny) {
+  ring_edge_dst_body<T, N, NT>(sring, tw, lift, edge0, nedge, nx, ny);
 }
 
 // k_ring and k_ring_edge_dst in one launch: workgroup `edge` makes that edge's ring values
 // (the same arithmetic as k_ring) and transforms its streamfunction part (the same
-// arithmetic as k_ring_edge_dst, one sequence per workgroup).
+// arithmetic as k_ring_edge_dst, one sequence per workgroup).  N is the edge's transform
+// length: nx for the bottom and top edges, ny for the left and right.
 template <typename T, int N, int NT>
 __device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc,
                                               const T* __restrict__ gc, int pgc, T* sring, T* gring,
-                                              const c2<T>* __restrict__ tw, T* lift, int edge) {
+                                              const c2<T>* __restrict__ tw, T* lift, int edge,
+                                              int nx, int ny) {
   __shared__ c2<T> buf[fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
   const int tid = threadIdx.x;
   load_table<T, N, NT>(stw, tw, tid);
+  const int off = ring_off(edge, nx, ny);
   for (int idx = tid; idx <= N; idx += NT) {
-    const int e = edge * (N + 1) + idx;
     T sv, gv;
-    ring_values(sc, psc, gc, pgc, N, e, sv, gv);
-    sring[e] = sv;
-    gring[e] = gv;
+    ring_values(sc, psc, gc, pgc, nx, ny, edge, idx, sv, gv);
+    sring[off + idx] = sv;
+    gring[off + idx] = gv;
     if (idx >= 1 && idx <= N - 1) dst_pack<T, N>(buf, idx, sv);
   }
   if (tid == 0) dst_pack_zeros<T, N>(buf);
   __syncthreads();
   fft_lds<T, N, 1, NT>(buf, stw, tid);
+  T* lo = lift + lift_off(edge, nx, ny);
   for (int k = 1 + tid; k <= N / 2; k += NT) {
     T xk, xnk;
     dst_unpack<T, N>(buf, stw, k, xk, xnk);
-    lift[edge * (N - 1) + k - 1] = xk;
-    if (k != N / 2) lift[edge * (N - 1) + N - k - 1] = xnk;
+    lo[k - 1] = xk;
+    if (k != N / 2) lo[N - k - 1] = xnk;
   }
 }
 
 template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_dst(const T* __restrict__ sc, int psc,
                                                  const T* __restrict__ gc, int pgc, T* sring,
-                                                 T* gring, const c2<T>* __restrict__ tw, T* lift) {
-  ring_dst_body<T, N, NT>(sc, psc, gc, pgc, sring, gring, tw, lift, blockIdx.x);
+                                                 T* gring, const c2<T>* __restrict__ tw, T* lift,
+                                                 int edge0, int nx, int ny) {
+  ring_dst_body<T, N, NT>(sc, psc, gc, pgc, sring, gring, tw, lift, edge0 + (int)blockIdx.x, nx,
+                          ny);
 }
 
-// Many instances of one grid size: workgroup (edge, instance blockIdx.y).
+// Many instances of one (square) grid size: workgroup (edge, instance blockIdx.y).
 template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_ring_dst_multi(const RingJob<T>* __restrict__ tab,
                                                        const c2<T>* __restrict__ tw) {
   const RingJob<T> j = tab[blockIdx.y];
-  ring_dst_body<T, N, NT>(j.sc, j.psc, j.gc, j.pgc, j.sring, j.gring, tw, j.lift, blockIdx.x);
+  ring_dst_body<T, N, NT>(j.sc, j.psc, j.gc, j.pgc, j.sring, j.gring, tw, j.lift, blockIdx.x, N, N);
 }
 
 // ------------------------------------------------ launches of one kernel configuration
 
 template <typename T, int N, int ROWS, int NT, int DST, int MAXR>
 hipError_t launch_rhs_cfg(const RhsArgs<T>& a, const c2<T>* t, hipStream_t st) {
-  const int nb = (a.n - 1 + ROWS - 1) / ROWS;
+  const int nb = ((a.ny > 0 ? a.ny : a.n) - 1 + ROWS - 1) / ROWS;
   hipLaunchKernelGGL((k_rhs_rowdst<T, N, ROWS, NT, DST, MAXR>), dim3(xcd_grid(nb)), dim3(NT), 0, st,
                      a, t, nb);
   return hipGetLastError();
@@ -803,7 +833,7 @@ hipError_t launch_rhs_cfg(const RhsArgs<T>& a, const c2<T>* t, hipStream_t st) {
 template <typename T, int N, int CW, int NT, int MAXR>
 hipError_t launch_col_cfg(const ColArgs<T>& a, int n, int batch, const c2<T>* t, const T* l,
                           hipStream_t st) {
-  const int nb = (n - 1 + CW - 1) / CW;
+  const int nb = ((a.ncols > 0 ? a.ncols : n - 1) + CW - 1) / CW;
   if (a.ev0)
     hipExtLaunchKernelGGL((k_col_solve<T, N, CW, NT, MAXR>), dim3(xcd_grid(nb), batch), dim3(NT), 0,
                           st, a.ev0, a.ev1, 0, a, t, l, nb);

@@ -18,9 +18,10 @@ struct RhsArgs {
   const T* hist_in;    // C^T N_{n-1}, (n-1) rows x ph, or null on the first step
   T* hist_out;         // C^T N_n (may alias hist_in)
   T* out;              // row-transformed right-hand side, (n-1) rows x po
-  int n, ps, pg, pgf, ph, po;
+  int n, ps, pg, pgf, ph, po;  // n: cells along x (the row transform's length)
   T alpha, dt, ux, uy, cn;  // cn = -1 / (2 h^2); ux, uy = free-stream flux u_inf h
   int var;             // kernel configuration (ROW_VARIANTS; 0 = default)
+  int ny;              // cells along y; 0: ny = n (square level)
 };
 
 // Row-wise transform of rows [r0, r1] (1-based interior rows).
@@ -37,6 +38,7 @@ struct RowArgs {
   T* out2;          //   into the interior array out2 (pitch po); batch 1 only
   int var;          // inverse transform with in2: kernel configuration (ROW_VARIANTS)
   const int* gate;  // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
+  int ny;           // inverse transform with its ring: cells along y; 0: the row length
 };
 
 // Column transform + spectral scale + inverse column transform.
@@ -59,6 +61,11 @@ struct ColArgs {
   const int* gate;   // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
   hipEvent_t ev0, ev1;  // host side, if set (kernel timing): recorded at the kernel's start and
                         //   end by the launch itself (hipExtLaunchKernelGGL), without its dispatch
+  // rectangular levels (the column transform runs along y, of length ny): the nx - 1 columns,
+  // the x eigenvalues lam_x[k - 1] and sin(pi k / nx), k <= nx; 0 / null: square level
+  int ncols;
+  const T* lamx;
+  const T* sinx;
 };
 
 // Per-instance entries of the flow launches that take many instances of one grid size
@@ -79,6 +86,7 @@ struct RingJob {
   T* sring;
   T* gring;
   T* lift;
+  int nx, ny;   // cells of the fine level
 };
 
 // Kernel configurations of the row and column sine-transform kernels, selected per grid
@@ -153,15 +161,18 @@ hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* t
 template <typename T>
 hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw, const T* ring,
                            int ring_rows, hipStream_t st);
+// Rings of an nx x ny level (ring_off layout) from the next coarser level; twx / twy are the
+// transform tables of lengths nx and ny (the same on a square level).
 template <typename T>
-hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
-                       hipStream_t st);
+hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int nx, int ny, T* sring,
+                       T* gring, hipStream_t st);
 template <typename T>
-hipError_t launch_ring_edge_dst(const T* sring, int n, const void* tw, T* lift, hipStream_t st);
-// launch_ring and launch_ring_edge_dst in one launch (the same results).
+hipError_t launch_ring_edge_dst(const T* sring, int nx, int ny, const void* twx, const void* twy,
+                                T* lift, hipStream_t st);
+// launch_ring and launch_ring_edge_dst in one launch per edge length (the same results).
 template <typename T>
-hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int n, T* sring, T* gring,
-                           const void* tw, T* lift, hipStream_t st);
+hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int nx, int ny, T* sring,
+                           T* gring, const void* twx, const void* twy, T* lift, hipStream_t st);
 
 // The same launches for `count` instances of grid size n at once, their arguments in device
 // tables (entry b for blockIdx.y = b); var as above, the same for all instances.  maxrows:

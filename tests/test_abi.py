@@ -179,3 +179,26 @@ def test_flow_variant_table_and_forcing(lib):
             assert lib.ib_get_flow_tuning(h, ctypes.byref(tun)) == 0
             assert (tun.rhs_variant, tun.col_variant, tun.idst_variant) == (1, 5, 3)
         assert lib.ib_destroy(h) == 0
+
+
+def test_rectangular_levels_are_validated_and_estimated(lib):
+    """ny (cells along y) takes the same sizes as n; the matrix-core transform form stays square;
+    the memory estimate follows nx x ny."""
+    from paper_2103_06415_amd import binding
+    est = {}
+    for n, ny, prec, ok in ((64, 32, binding.IB_FP32_FLOW, True), (64, 30, binding.IB_FP32_FLOW, False),
+                            (64, 0, binding.IB_FP32_FLOW, True), (64, 128, binding.IB_FP64, True),
+                            (64, 32, binding.IB_FP32_FLOW_BF16_DST, False), (64, -4, binding.IB_FP64, False),
+                            (64, 2000, binding.IB_FP64, False)):
+        cfg = _config(binding, n, 2)
+        cfg.ny = ny
+        cfg.precision = prec
+        h = ctypes.c_void_p()
+        rc = lib.ib_create(ctypes.byref(cfg), None, None, ctypes.byref(h))
+        assert rc == (0 if ok else -1), (n, ny, prec, rc)
+        if ok:
+            res, peak = ctypes.c_int64(), ctypes.c_int64()
+            assert lib.ib_estimate_bytes(h, ctypes.byref(res), ctypes.byref(peak)) == 0
+            est[(ny, prec)] = res.value
+            assert lib.ib_destroy(h) == 0
+    assert est[(32, binding.IB_FP32_FLOW)] < est[(0, binding.IB_FP32_FLOW)]
