@@ -336,6 +336,31 @@ def trace_gaps(path, step_kernel="k_spread_multi", pattern="_multi", split_us=10
             "top_kernels_us_per_step": [(k, round(v[1] / per, 1), v[0] // per, v[2]) for k, v in top]}
 
 
+def paper_grid(steps, warmup):
+    """Flow steps on levels of the size of the paper's largest run (Sec. 5.3: 4000 x 2000 cells,
+    5 levels), without bodies: a seeded vortex pair with noise on level 0, h = 0.002, Re 500,
+    free stream (1, 0), FP32 flow."""
+    import numpy as np
+    import workloads as W
+    from paper_2103_06415_amd import binding
+    nx, ny, levels, h = 4000, 2000, 5, 0.002
+    flow = W.Flow(n=nx, ny=ny, levels=levels, h=h, dt=0.2 * h, re=500.0)
+    rng = np.random.default_rng(9)
+    x = -0.5 * nx * h + h * np.arange(1, nx)
+    y = -0.5 * ny * h + h * np.arange(1, ny)
+    yy, xx = np.meshgrid(y, x, indexing="ij")
+    w = (5.0 * np.exp(-((xx + 1.0) ** 2 + (yy - 0.3) ** 2) / 0.05)
+         - 5.0 * np.exp(-((xx + 1.0) ** 2 + (yy + 0.3) ** 2) / 0.05)
+         + 1e-3 * rng.normal(size=xx.shape))
+    p = W.Problem("paper_grid", flow, [], vorticity0=[w] + [None] * (levels - 1))
+    wall, prep, _, st = run(p, binding.IB_FP32_FLOW, steps, warmup, timing=False)
+    cells = nx * ny * levels
+    return {"value": cells * steps / wall, "unit": "grid-cell steps/s",
+            "ms_per_step": 1e3 * wall / steps, "prepare_s": prep, "steps": steps,
+            "workload": "flow without bodies on 5 levels of 4000 x 2000 cells (Sec. 5.3's grid), "
+                        "FP32 flow, default transform configurations"}
+
+
 def library_gemm():
     """Matrix-core library products (torch's matmul, hipBLASLt on this platform) at the shapes of
     one sine transform as a dense product: BF16 inputs with FP32 accumulation, the split form's
@@ -594,6 +619,8 @@ def main():
                     help="also run the 64 instances through the scheduler")
     ap.add_argument("--no-batch64", action="store_true",
                     help="skip the 64-instance batch (sizes 128^2..768^2) as one ib_batch")
+    ap.add_argument("--no-paper-grid", action="store_true",
+                    help="skip the flow on levels of 4000 x 2000 cells (5 levels, FP32)")
     ap.add_argument("--no-plate", action="store_true",
                     help="skip the plate workload (512^2 x 3, FP32 and FP64)")
     ap.add_argument("--batch-copies", type=int, default=4,
@@ -772,6 +799,8 @@ def main():
                               "newton_iters_max": s32["newton_iters_max"],
                               "workload": "torsional plate (51 points, I 5, k 1, c 0.1, 20 deg), "
                                           "512^2 x 3 levels, Re 200, sub-domain B', FSI tol 1e-7"}
+    if not args.no_paper_grid:
+        out["paper_grid_4000x2000x5"] = paper_grid(args.steps, args.warmup)
     if not args.no_batch64:
         out["batch64"] = batch_run(W.batch_problems(), 20, 3, alone_steps=5)
         out["batch64"]["workload"] = ("64 instances, 128^2..768^2 x 1-3 levels, 1-3 rigid or "

@@ -509,7 +509,7 @@ ib_status op_solve_noalloc_run(int n, int pitch, hipStream_t st, double alpha, c
   void* base = nullptr;
   ib_status rc = scratch_address(&base);
   if (rc) return rc;
-  // host tables in a fixed buffer (no heap): 4n + n values, n <= 1280 for every supported n
+  // host tables in a fixed buffer (no heap): 4n + n values; larger sizes are refused
   constexpr int kMaxN = 1280;
   if (n > kMaxN) return IB_ERR_SCRATCH;
   T host[5 * kMaxN];
@@ -2971,6 +2971,10 @@ ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_s
   if (cfg->ny < 0 || !supported_n(cny) || cny % 4 != 0 ||
       (cny != cfg->n && cfg->precision == IB_FP32_FLOW_BF16_DST))
     return IB_ERR_ARG;
+  // double precision up to 2000 cells per axis; the matrix-core transforms up to 1280
+  if (cfg->precision == IB_FP64 && (!supported_n_fp64(cfg->n) || !supported_n_fp64(cny)))
+    return IB_ERR_ARG;
+  if (cfg->precision == IB_FP32_FLOW_BF16_DST && cfg->n > 1280) return IB_ERR_ARG;
   if (!supported_n(cfg->n) || cfg->n % 4 != 0 || cfg->levels < 1 || cfg->levels > 12 ||
       !(cfg->h > 0) || !(cfg->dt > 0) || !(cfg->re > 0) ||
       (cfg->precision != IB_FP64 && cfg->precision != IB_FP32_FLOW &&
@@ -3138,6 +3142,11 @@ ib_status ib_prepare(ib_solver* s) {
   if (s->prepared || s->released) return IB_ERR_STATE;
   if (s->ny != s->n && !s->bodies.empty()) {
     s->last_error = "bodies need square levels (ny = n)";
+    return IB_ERR_ARG;
+  }
+  if (s->n > 1280 && !s->bodies.empty()) {
+    // the offline operators are built in double precision with the square kernels of n
+    s->last_error = "bodies need at most 1280 cells per side";
     return IB_ERR_ARG;
   }
   ib_status st = s->allocated ? IB_OK : alloc_state(s);
@@ -3318,7 +3327,8 @@ ib_status ib_batch_create(ib_solver* const* members, int32_t count, void* hip_st
     if (!s) return IB_ERR_ARG;
     for (int j = 0; j < i; ++j)
       if (members[j] == s) return IB_ERR_ARG;
-    if (s->fp64 != members[0]->fp64 || s->ny != s->n) return IB_ERR_ARG;  // square levels only
+    // square levels of the batched kernels' sizes only
+    if (s->fp64 != members[0]->fp64 || s->ny != s->n || s->n > 1280) return IB_ERR_ARG;
     if (!s->prepared || s->failed || s->released) return IB_ERR_STATE;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -3727,7 +3737,8 @@ ib_status ib_op_solve(int32_t n, int32_t precision, double alpha, const void* in
                       int32_t pitch, void* hip_stream) {
   HipShared hip_lock;
   if (!supported_n(n) || !in || !out || pitch < n - 1 ||
-      (precision != IB_FP64 && precision != IB_FP32_FLOW))
+      (precision != IB_FP64 && precision != IB_FP32_FLOW) ||
+      (precision == IB_FP64 && !supported_n_fp64(n)))
     return IB_ERR_ARG;
   ib_solver tmp;
   ib_solver* s = &tmp;
@@ -3751,7 +3762,8 @@ ib_status ib_op_solve_noalloc(int32_t n, int32_t precision, double alpha, const 
                               void* out, int32_t pitch, void* hip_stream) {
   HipShared hip_lock;
   if (!supported_n(n) || !in || !out || pitch < n - 1 ||
-      (precision != IB_FP64 && precision != IB_FP32_FLOW))
+      (precision != IB_FP64 && precision != IB_FP32_FLOW) ||
+      (precision == IB_FP64 && !supported_n_fp64(n)))
     return IB_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (precision == IB_FP64) return op_solve_noalloc_run<double>(n, pitch, st, alpha, in, out);

@@ -7,13 +7,23 @@ namespace ib {
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T>
+// Default configuration of transform length N: rows (or columns) per workgroup and threads.
+// From N = 2000 on, one row per workgroup and two columns (one in double precision or at 4000)
+// keep the staged rows, the transform buffers and the twiddle table inside the 160 KB of LDS.
+template <typename T, int N>
 struct Cfg {
-  static constexpr int ROWS = 2;
+  static constexpr bool BIG = N >= 2000;
+  static constexpr int ROWS = BIG ? 1 : 2;
   static constexpr int NTR = 256;
-  static constexpr int CW = 4;
+  static constexpr int CW = BIG ? ((sizeof(T) == 8 || N >= 4000) ? 1 : 2) : 4;
   static constexpr int NTC = 256;
 };
+// Transform lengths whose kernels fit the LDS in this precision: 4000 in single precision only
+// (its double-precision row staging alone would take 192 KB).
+template <typename T, int N>
+constexpr bool fits_lds() {
+  return !(sizeof(T) == 8 && N >= 4000);
+}
 
 #define IB_DISPATCH_N(n, MACRO)                                \
   switch (n) {                                                 \
@@ -36,6 +46,8 @@ struct Cfg {
     case 768: MACRO(768); break;                               \
     case 1024: MACRO(1024); break;                             \
     case 1280: MACRO(1280); break;                             \
+    case 2000: MACRO(2000); break;                             \
+    case 4000: MACRO(4000); break;                             \
     default: return hipErrorInvalidValue;                      \
   }
 
@@ -43,12 +55,14 @@ bool supported_n(int n) {
   switch (n) {
     case 16: case 20: case 32: case 40: case 48: case 64: case 80: case 96: case 128:
     case 160: case 192: case 256: case 320: case 384: case 512: case 640: case 768:
-    case 1024: case 1280:
+    case 1024: case 1280: case 2000: case 4000:
       return true;
     default:
       return false;
   }
 }
+
+bool supported_n_fp64(int n) { return supported_n(n) && n < 4000; }
 
 // sizes with measured alternative configurations (ib_flow_tuned.hip, ib_flow_multi_tuned.hip)
 bool flow_variant_available(int n, int fp64) {
@@ -72,12 +86,19 @@ hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st
       return launch_rhs_rowdst_var(a, tw, st);
     }
   }
-  constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
-  const int nb = ((a.ny > 0 ? a.ny : a.n) - 1 + R - 1) / R;
+  const int rows = (a.ny > 0 ? a.ny : a.n) - 1;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
 #define L_(NN)                                                                                   \
-  if (transform) hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 1>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb); \
-  else hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 0>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb)
+  {                                                                                              \
+    if constexpr (fits_lds<T, NN>()) {                                                           \
+      constexpr int R = Cfg<T, NN>::ROWS, NT = Cfg<T, NN>::NTR;                                  \
+      const int nb = (rows + R - 1) / R;                                                         \
+      if (transform) hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 1>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb); \
+      else hipLaunchKernelGGL((k_rhs_rowdst<T, NN, R, NT, 0>), dim3(xcd_grid(nb)), dim3(NT), 0, st, a, t, nb); \
+    } else {                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+    }                                                                                            \
+  }
   IB_DISPATCH_N(a.n, L_)
 #undef L_
   return hipGetLastError();
@@ -85,11 +106,18 @@ hipError_t launch_rhs_rowdst(const RhsArgs<T>& a, const void* tw, hipStream_t st
 
 template <typename T>
 hipError_t launch_rowdst(const RowArgs<T>& a, int n, int batch, const void* tw, hipStream_t st) {
-  constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
-  const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;
-  if (nb <= 0) return hipSuccess;
+  if (a.r1 < a.r0) return hipSuccess;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
-#define L_(NN) hipLaunchKernelGGL((k_rowdst<T, NN, R, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, nb)
+#define L_(NN)                                                                                   \
+  {                                                                                              \
+    if constexpr (fits_lds<T, NN>()) {                                                           \
+      constexpr int R = Cfg<T, NN>::ROWS, NT = Cfg<T, NN>::NTR;                                  \
+      const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;                                              \
+      hipLaunchKernelGGL((k_rowdst<T, NN, R, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, nb); \
+    } else {                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+    }                                                                                            \
+  }
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();
@@ -104,17 +132,24 @@ hipError_t launch_col_solve(const ColArgs<T>& a, int n, int batch, const void* t
       return launch_col_solve_var(a, n, batch, tw, lam, st);
     }
   }
-  constexpr int CW = Cfg<T>::CW, NT = Cfg<T>::NTC;
-  const int nb = ((a.ncols > 0 ? a.ncols : n - 1) + CW - 1) / CW;
+  const int cols = a.ncols > 0 ? a.ncols : n - 1;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
   const T* l = static_cast<const T*>(lam);
 #define L_(NN)                                                                                     \
-  if (a.ev0)                                                                                       \
-    hipExtLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, \
-                          a.ev0, a.ev1, 0, a, t, l, nb);                                           \
-  else                                                                                             \
-    hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, \
-                       t, l, nb)
+  {                                                                                                \
+    if constexpr (fits_lds<T, NN>()) {                                                             \
+      constexpr int CW = Cfg<T, NN>::CW, NT = Cfg<T, NN>::NTC;                                     \
+      const int nb = (cols + CW - 1) / CW;                                                         \
+      if (a.ev0)                                                                                   \
+        hipExtLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, \
+                              a.ev0, a.ev1, 0, a, t, l, nb);                                       \
+      else                                                                                         \
+        hipLaunchKernelGGL((k_col_solve<T, NN, CW, NT>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, \
+                           t, l, nb);                                                              \
+    } else {                                                                                       \
+      return hipErrorInvalidValue;                                                                 \
+    }                                                                                              \
+  }
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();
@@ -129,13 +164,19 @@ hipError_t launch_row_idst(const RowArgs<T>& a, int n, int batch, const void* tw
       return launch_row_idst_var(a, n, batch, tw, ring, ring_rows, st);
     }
   }
-  constexpr int R = Cfg<T>::ROWS, NT = Cfg<T>::NTR;
-  const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;
-  if (nb <= 0) return hipSuccess;
+  if (a.r1 < a.r0) return hipSuccess;
   const c2<T>* t = static_cast<const c2<T>*>(tw);
 #define L_(NN)                                                                                   \
-  if (a.in2) hipLaunchKernelGGL((k_row_idst<T, NN, R, NT, 1>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb); \
-  else hipLaunchKernelGGL((k_row_idst<T, NN, R, NT, 0>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb)
+  {                                                                                              \
+    if constexpr (fits_lds<T, NN>()) {                                                           \
+      constexpr int R = Cfg<T, NN>::ROWS, NT = Cfg<T, NN>::NTR;                                  \
+      const int nb = (a.r1 - a.r0 + 1 + R - 1) / R;                                              \
+      if (a.in2) hipLaunchKernelGGL((k_row_idst<T, NN, R, NT, 1>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb); \
+      else hipLaunchKernelGGL((k_row_idst<T, NN, R, NT, 0>), dim3(xcd_grid(nb), batch), dim3(NT), 0, st, a, t, ring, ring_rows, nb); \
+    } else {                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+    }                                                                                            \
+  }
   IB_DISPATCH_N(n, L_)
 #undef L_
   return hipGetLastError();
@@ -152,14 +193,24 @@ hipError_t launch_ring(const T* sc, int psc, const T* gc, int pgc, int nx, int n
 
 // Edge transforms of a ring: all four edges in one workgroup on a square level; on a
 // rectangular one the bottom and top edges (length nx, tables twx) and the left and right
-// edges (length ny, tables twy) in one workgroup each.
+// edges (length ny, tables twy) in one workgroup each.  From length 2000 on, one workgroup
+// per edge (the LDS holds one sequence of that length).
 template <typename T>
 hipError_t launch_ring_edge_dst(const T* sring, int nx, int ny, const void* twx, const void* twy,
                                 T* lift, hipStream_t st) {
   for (int pass = 0; pass < (nx == ny ? 1 : 2); ++pass) {
     const int n = pass == 0 ? nx : ny, e0 = pass == 0 ? 0 : 2, ne = nx == ny ? 4 : 2;
     const c2<T>* t = static_cast<const c2<T>*>(pass == 0 ? twx : twy);
-#define L_(NN) hipLaunchKernelGGL((k_ring_edge_dst<T, NN, 256>), dim3(1), dim3(256), 0, st, sring, t, lift, e0, ne, nx, ny)
+#define L_(NN)                                                                                   \
+  {                                                                                              \
+    if constexpr (!fits_lds<T, NN>()) {                                                          \
+      return hipErrorInvalidValue;                                                               \
+    } else if constexpr (NN >= 2000) {                                                           \
+      hipLaunchKernelGGL((k_ring_edge_dst<T, NN, 256, 1>), dim3(ne), dim3(256), 0, st, sring, t, lift, e0, ne, nx, ny); \
+    } else {                                                                                     \
+      hipLaunchKernelGGL((k_ring_edge_dst<T, NN, 256, 4>), dim3(1), dim3(256), 0, st, sring, t, lift, e0, ne, nx, ny); \
+    }                                                                                            \
+  }
     IB_DISPATCH_N(n, L_)
 #undef L_
   }
@@ -174,7 +225,14 @@ hipError_t launch_ring_dst(const T* sc, int psc, const T* gc, int pgc, int nx, i
   for (int pass = 0; pass < (nx == ny ? 1 : 2); ++pass) {
     const int n = pass == 0 ? nx : ny, e0 = pass == 0 ? 0 : 2, ne = nx == ny ? 4 : 2;
     const c2<T>* t = static_cast<const c2<T>*>(pass == 0 ? twx : twy);
-#define L_(NN) hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(ne), dim3(256), 0, st, sc, psc, gc, pgc, sring, gring, t, lift, e0, nx, ny)
+#define L_(NN)                                                                                   \
+  {                                                                                              \
+    if constexpr (fits_lds<T, NN>()) {                                                           \
+      hipLaunchKernelGGL((k_ring_dst<T, NN, 256>), dim3(ne), dim3(256), 0, st, sc, psc, gc, pgc, sring, gring, t, lift, e0, nx, ny); \
+    } else {                                                                                     \
+      return hipErrorInvalidValue;                                                               \
+    }                                                                                            \
+  }
     IB_DISPATCH_N(n, L_)
 #undef L_
   }

@@ -127,8 +127,12 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
   constexpr int UNI = (STG > BUFT ? STG : BUFT) / 2 + 1;
   __shared__ c2<T> uni[UNI];
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
-  __shared__ T sbt[2][W];            // new circulation ring: bottom and top rows
-  __shared__ T slr[2][ROWS];         //   left and right entries at this block's rows
+  // new circulation ring: the bottom and top rows (staged below length 2000; above, the first
+  // and last row blocks read them from memory) and the left and right entries at this block's
+  // rows
+  constexpr bool STAGE_BT = N < 2000;
+  __shared__ T sbt[2][STAGE_BT ? W : 1];
+  __shared__ T slr[2][ROWS];
   static_assert(sizeof(uni) + sizeof(stw) + sizeof(sbt) + sizeof(slr) <= 160 * 1024, "LDS");
   const int blk = xcd_block(bx, nblocks);
   if (blk < 0) return;
@@ -164,16 +168,17 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
     }
     // the ring entries this block uses: the bottom and top rows, the left and right entries
     // of rows j0 .. j0 + ROWS - 1 (clamped to the ring)
-    constexpr int RC = 2 * W + 2 * ROWS;
+    constexpr int BW = STAGE_BT ? 2 * W : 0;
+    constexpr int RC = BW + 2 * ROWS;
     constexpr int PR = (RC + NT - 1) / NT;
     T rv0[PR];
     if (a.gring_new != nullptr) {
 #pragma unroll
       for (int b = 0; b < PR; ++b) {
         const int e = min(tid + b * NT, RC - 1);
-        const int idx = e < 2 * W ? ring_off(e / W, N, ny) + e % W
-                                  : ring_off(RING_L + (e - 2 * W) / ROWS, N, ny) +
-                                        min(j0 + (e - 2 * W) % ROWS, ny);
+        const int idx = e < BW ? ring_off(e / W, N, ny) + e % W
+                               : ring_off(RING_L + (e - BW) / ROWS, N, ny) +
+                                     min(j0 + (e - BW) % ROWS, ny);
         rv0[b] = a.gring_new[idx];
       }
     }
@@ -191,8 +196,8 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
 #pragma unroll
       for (int b = 0; b < PR; ++b) {
         const int e = tid + b * NT;
-        if (e < 2 * W) (&sbt[0][0])[e] = rv0[b];
-        else if (e < RC) (&slr[0][0])[e - 2 * W] = rv0[b];
+        if (e < BW) (&sbt[0][0])[e] = rv0[b];
+        else if (e < RC) (&slr[0][0])[e - BW] = rv0[b];
       }
     }
   }
@@ -208,8 +213,13 @@ __device__ __forceinline__ void rhs_rowdst_body(const RhsArgs<T>& a, const c2<T>
       if (a.gring_new != nullptr) {
         if (i == 1) ring += slr[0][t];
         if (i == N - 1) ring += slr[1][t];
-        if (j == 1) ring += sbt[RING_B][i];
-        if (j == ny - 1) ring += sbt[RING_T][i];
+        if constexpr (STAGE_BT) {
+          if (j == 1) ring += sbt[RING_B][i];
+          if (j == ny - 1) ring += sbt[RING_T][i];
+        } else {
+          if (j == 1) ring += a.gring_new[ring_off(RING_B, N, ny) + i];
+          if (j == ny - 1) ring += a.gring_new[ring_off(RING_T, N, ny) + i];
+        }
       }
       rv[b] = rhs_staged<T, W>(a, ss + t * W, sg + t * W, i, j, hp[b], a.hist_in != nullptr, ring);
     }
@@ -725,17 +735,19 @@ __global__ void k_ring(const T* __restrict__ sc, int psc, const T* __restrict__ 
 // Unnormalised 1-D DSTs of edges edge0 .. edge0 + nedge - 1 (nedge <= 4) of a streamfunction
 // ring, as they appear in B(s_ring): bottom edge values s(i, 0) sit on interior row 1, top
 // s(i, ny) on row ny-1, left s(0, j) on column 1, right s(nx, j) on column nx-1.  N is the
-// length of those edges' transforms (nx for bottom and top, ny for left and right).  One
-// workgroup.
-template <typename T, int N, int NT>
+// length of those edges' transforms (nx for bottom and top, ny for left and right).  Each
+// workgroup transforms NEB of the edges (workgroup b the edges edge0 + NEB b onwards).
+template <typename T, int N, int NT, int NEB>
 __device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
                                                    const c2<T>* __restrict__ tw, T* lift,
-                                                   int edge0, int nedge, int nx, int ny) {
-  __shared__ c2<T> buf[4 * fft_pad_len<N>()];
+                                                   int edge0, int nedge, int nx, int ny, int bx) {
+  __shared__ c2<T> buf[NEB * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N>::total];
   const int tid = threadIdx.x;
+  edge0 += NEB * bx;
+  nedge = min(NEB, nedge - NEB * bx);
   {
-    constexpr int CNT = 4 * (N - 1);
+    constexpr int CNT = NEB * (N - 1);
     constexpr int PER = (CNT + NT - 1) / NT;
     T v[PER];
 #pragma unroll
@@ -750,9 +762,9 @@ __device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
       if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
     }
   }
-  for (int q = tid; q < 4; q += NT) dst_pack_zeros<T, N>(buf + q * fft_pad_len<N>());
+  for (int q = tid; q < NEB; q += NT) dst_pack_zeros<T, N>(buf + q * fft_pad_len<N>());
   __syncthreads();
-  fft_lds<T, N, 4, NT>(buf, stw, tid);
+  fft_lds<T, N, NEB, NT>(buf, stw, tid);
   for (int e = tid; e < nedge * (N / 2); e += NT) {
     const int q = e / (N / 2), k = 1 + e % (N / 2);
     T xk, xnk;
@@ -763,11 +775,11 @@ __device__ __forceinline__ void ring_edge_dst_body(const T* __restrict__ sring,
   }
 }
 
-template <typename T, int N, int NT>
+template <typename T, int N, int NT, int NEB>
 __global__ __launch_bounds__(NT) void k_ring_edge_dst(const T* __restrict__ sring,
                                                       const c2<T>* __restrict__ tw, T* lift,
                                                       int edge0, int nedge, int nx, int ny) {
-  ring_edge_dst_body<T, N, NT>(sring, tw, lift, edge0, nedge, nx, ny);
+  ring_edge_dst_body<T, N, NT, NEB>(sring, tw, lift, edge0, nedge, nx, ny, blockIdx.x);
 }
 
 // k_ring and k_ring_edge_dst in one launch: workgroup `edge` makes that edge's ring values

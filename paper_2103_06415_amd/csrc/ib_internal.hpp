@@ -149,6 +149,8 @@ struct GemmArgs {
 hipError_t launch_dst_gemm(const GemmArgs& g, int mode, hipStream_t st);
 
 bool supported_n(int n);
+// Transform lengths that run in double precision (every supported one below 4000).
+bool supported_n_fp64(int n);
 
 // transform = 0: only the explicit right-hand side, written to a.out row by row
 template <typename T>

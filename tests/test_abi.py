@@ -182,15 +182,19 @@ def test_flow_variant_table_and_forcing(lib):
 
 
 def test_rectangular_levels_are_validated_and_estimated(lib):
-    """ny (cells along y) takes the same sizes as n; the matrix-core transform form stays square;
-    the memory estimate follows nx x ny."""
+    """ny (cells along y) takes the same sizes as n (2000 and 4000 included, 4000 in single
+    precision only); the matrix-core transform form stays square; the memory estimate follows
+    nx x ny."""
     from paper_2103_06415_amd import binding
     est = {}
     for n, ny, prec, ok in ((64, 32, binding.IB_FP32_FLOW, True), (64, 30, binding.IB_FP32_FLOW, False),
                             (64, 0, binding.IB_FP32_FLOW, True), (64, 128, binding.IB_FP64, True),
                             (64, 32, binding.IB_FP32_FLOW_BF16_DST, False), (64, -4, binding.IB_FP64, False),
-                            (64, 2000, binding.IB_FP64, False)):
+                            (64, 2000, binding.IB_FP64, True), (64, 4000, binding.IB_FP32_FLOW, True),
+                            (64, 4000, binding.IB_FP64, False), (64, 3000, binding.IB_FP32_FLOW, False),
+                            (4000, 2000, binding.IB_FP32_FLOW, True)):
         cfg = _config(binding, n, 2)
+        cfg.h = 4.0 / n
         cfg.ny = ny
         cfg.precision = prec
         h = ctypes.c_void_p()

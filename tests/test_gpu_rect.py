@@ -42,11 +42,20 @@ def rect_flow(nx, ny, levels, seed=7):
 
 CASES = [(64, 32, 3), (32, 64, 3), (160, 80, 3), (80, 160, 2), (128, 64, 1), (256, 128, 3),
          (40, 20, 2)]
+# the long transforms of the paper-scale levels (4000 x 2000) on thin levels the oracle can step:
+# rows of 4000 or 2000 (one row per workgroup, ring edges read from memory), columns of 4000 or
+# 2000 (one or two columns per workgroup); 4000 in single precision only
+BIG = [(4000, 32, 2, "fp32"), (32, 4000, 2, "fp32"), (2000, 64, 2, "fp64"), (2000, 64, 2, "fp32"),
+       (64, 2000, 2, "fp64"), (64, 2000, 2, "fp32")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("nx,ny,levels", CASES)
 def test_rectangular_flow_matches_oracle(torch_cuda, gpu_lib, nx, ny, levels, prec):
+    _check_rect(nx, ny, levels, prec)
+
+
+def _check_rect(nx, ny, levels, prec):
     import torch
     from paper_2103_06415_amd import binding
     print(f"rectangular flow {nx} x {ny}, {levels} levels, {prec}", flush=True)
@@ -87,3 +96,8 @@ def test_rectangular_levels_refuse_bodies_and_batches(torch_cuda, gpu_lib):
     assert q.lib.ib_batch_create(members, 1, None, ctypes.byref(h)) == binding.IB_ERR_ARG
     assert q.lib.ib_set_flow_variants(q.handle, 1, 0, 0) == binding.IB_ERR_ARG
     q.close()
+
+
+@pytest.mark.parametrize("nx,ny,levels,prec", BIG)
+def test_long_transforms_match_oracle(torch_cuda, gpu_lib, nx, ny, levels, prec):
+    _check_rect(nx, ny, levels, prec)
