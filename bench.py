@@ -458,7 +458,39 @@ def exact_compare(make, tors_body, force_bodies, steps, workload):
                                       max(abs(fy_ex[k0:].mean()), 1e-30))
     out["lift_rel_diff_incl_start"] = float(np.max(np.abs(fy_sd - fy_ex)) /
                                             max(np.max(np.abs(fy_ex)), 1e-30))
+    # the paper's error measure (Sec. 5): ||eta - eta_ref||_2 / ||eta_ref||_2 over the run
+    out["theta_l2_err"] = float(np.linalg.norm(th_sd - th_ex) / max(np.linalg.norm(th_ex), 1e-30))
+    out["lift_l2_err"] = float(np.linalg.norm(fy_sd - fy_ex) / max(np.linalg.norm(fy_ex), 1e-30))
     out["workload"] = workload
+    return out
+
+
+def refinement_study():
+    """Sub-domain against exact operator on successively finer grids, the physical time of
+    each run fixed: the torsional plate (3 levels, 200 steps at 512^2 scaled with n) and Sec.
+    5.1's two plates (case 2, 3 levels, one flapping period: 2000 steps at 256^2 scaled with
+    n).  The sub-domain method's hat interpolation P is second order in h, so the differences
+    should shrink about fourfold per halving of h once the flow is resolved."""
+    import workloads as W
+    out = {"plate": {}, "two_plates": {}}
+    for n in (256, 512, 1024):
+        steps = 200 * n // 512
+        print(f"  refinement: plate n={n}, {steps} steps", file=sys.stderr, flush=True)
+        r = exact_compare(lambda sd, n=n, steps=steps: W.plate_problem(n=n, levels=3, steps=steps,
+                                                                       subdomain=sd),
+                          0, [0], steps, f"torsional plate {n}^2 x 3, {steps} steps")
+        out["plate"][n] = {k: r[k] for k in ("theta_l2_err", "lift_l2_err", "theta_rel_diff",
+                                             "lift_rel_diff", "mean_lift_rel_diff",
+                                             "ms_per_step_subdomain", "ms_per_step_exact")}
+    for n in (128, 256, 512):
+        steps = 2000 * n // 256
+        print(f"  refinement: two plates n={n}, {steps} steps", file=sys.stderr, flush=True)
+        r = exact_compare(lambda sd, n=n, steps=steps: W.two_plate_problem(n=n, levels=3, steps=steps,
+                                                                           case=2, subdomain=sd),
+                          1, [0, 1], steps, f"two plates {n}^2 x 3, {steps} steps")
+        out["two_plates"][n] = {k: r[k] for k in ("theta_l2_err", "lift_l2_err", "theta_rel_diff",
+                                                  "lift_rel_diff", "mean_lift_rel_diff",
+                                                  "ms_per_step_subdomain", "ms_per_step_exact")}
     return out
 
 
@@ -638,6 +670,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the two serving traces (--serve-drawn sets the drawn one's "
                          "length)")
+    ap.add_argument("--refinement", action="store_true",
+                    help="only run the sub-domain vs exact comparison on three grid sizes")
     ap.add_argument("--library-gemm", action="store_true",
                     help="only time the matrix-core library's products at the sine-transform shapes")
     ap.add_argument("--trace-gaps", default=None, metavar="CSV",
@@ -672,6 +706,9 @@ def main():
     cells = n * n * levels
     if args.library_gemm:
         print(json.dumps({"library_gemm": library_gemm()}))
+        return
+    if args.refinement:
+        print(json.dumps({"refinement": refinement_study()}))
         return
     if args.serve_only:
         out = {"metric": METRIC, "unit": "grid-cell steps/s", "n_gpus": 1, "data": "synthetic",

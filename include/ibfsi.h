@@ -153,9 +153,12 @@ typedef struct {
                                 refinement's workgroups cannot all be resident on this device */
 } ib_stats;
 
-/* Create a solver.  `alloc` may be NULL (hipMalloc); `hip_stream` is a hipStream_t
- * or NULL.  Errors: IB_ERR_ARG for unsupported sizes (n not in the list, n % 4 != 0,
- * levels < 1, non-positive h/dt/re). */
+/* Create a solver for the problem set-up of Algorithm 1 (grid hierarchy of Sec. 5, time step,
+ * Reynolds number, free stream; the bodies and the sub-domain are added next).  `alloc` may be
+ * NULL (hipMalloc); `hip_stream` is a hipStream_t or NULL.  The configuration is copied; the
+ * handle owns nothing on the device until ib_prepare.  Errors: IB_ERR_ARG for unsupported
+ * sizes (n or ny not in the list, not a multiple of 4, 4000 in IB_FP64, levels outside
+ * 1..12) or non-positive h / dt / re. */
 ib_status ib_create(const ib_config* cfg, const ib_allocator* alloc, void* hip_stream,
                     ib_solver** out);
 
@@ -236,9 +239,13 @@ ib_status ib_prepare(ib_solver* s);
 /* Online stage: advance nsteps time steps (Algorithm 2). */
 ib_status ib_step(ib_solver* s, int32_t nsteps);
 
+/* Wait until the work ib_step enqueued on the solver's stream is done (the state of
+ * Algorithm 2's last step is then readable).  Errors: IB_ERR_ARG, IB_ERR_HIP. */
 ib_status ib_sync(ib_solver* s);
 
-/* Stresses of a body after the last step: 2m doubles (x block then y block). */
+/* Stresses f_{n+1} of a body after the last step (eq. (17) / (37)): 2m doubles, x block then
+ * y block (Sec. 4.2), into the caller's host buffer of cap doubles.  Errors: IB_ERR_ARG (bad
+ * id), IB_ERR_STATE (not prepared), IB_ERR_CAPACITY (cap < 2m). */
 ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap);
 
 /* Force of the fluid on a body after the last step (Sec. 5: forces and lift coefficients),
@@ -248,17 +255,25 @@ ib_status ib_read_stresses(ib_solver* s, int32_t body_id, double* f, int64_t cap
  * IB_ERR_CAPACITY (cap < 2). */
 ib_status ib_read_force(ib_solver* s, int32_t body_id, double* out, int64_t cap);
 
-/* Structure state: torsional -> (theta, phi, phidot); deformable -> 3m doubles
- * (x, y, rotation per node); rigid -> its 2m point coordinates. */
+/* Structure state of a body after the last step (eqs. (18)-(19), Appendix A): torsional ->
+ * (theta, phi, phidot); deformable -> 3m doubles (x, y, rotation per node); rigid -> its 2m
+ * point coordinates.  Host buffer of cap doubles.  Errors: IB_ERR_ARG, IB_ERR_STATE,
+ * IB_ERR_CAPACITY. */
 ib_status ib_read_deflection(ib_solver* s, int32_t body_id, double* out, int64_t cap);
 
-/* Vorticity of a level at interior vertices, (ny-1) (nx-1) doubles: the level's circulation
- * state gamma (= C^T C s, carried alongside s) divided by h^2. */
+/* Vorticity of a level at interior vertices (Sec. 2.2: omega = C^T C s / h^2), (ny-1) (nx-1)
+ * doubles: the level's circulation state gamma (= C^T C s, carried alongside s) divided by h^2.
+ * Host buffer of cap doubles; level 0 stays readable after ib_release.  Errors: IB_ERR_ARG,
+ * IB_ERR_STATE (nothing on the device), IB_ERR_CAPACITY. */
 ib_status ib_read_vorticity(ib_solver* s, int32_t level, double* out, int64_t cap);
 
-/* Streamfunction of a level including its ring, (ny+1) (nx+1) doubles. */
+/* Streamfunction s of a level including its boundary ring (Sec. 2.2), (ny+1) (nx+1) doubles
+ * into a host buffer of cap doubles.  Errors: IB_ERR_ARG, IB_ERR_STATE, IB_ERR_CAPACITY. */
 ib_status ib_read_streamfunction(ib_solver* s, int32_t level, double* out, int64_t cap);
 
+/* Statistics of the solver (ib_stats: Newton iterations and last update of Algorithm 2's
+ * loop, sub-domain size and B' entries of Algorithm 1, outputs of the last step); still
+ * readable after ib_release.  Errors: IB_ERR_ARG. */
 ib_status ib_get_stats(ib_solver* s, ib_stats* out);
 
 /* Kernel timing for measurement: while enabled, every launch of the classes below is
@@ -278,6 +293,8 @@ ib_status ib_set_kernel_timing(ib_solver* s, int32_t enable);
 ib_status ib_get_kernel_timing(ib_solver* s, int32_t kernel_class, int64_t* launches,
                                double* total_ms);
 
+/* Free the solver and everything it holds (device memory first, as ib_release).  The handle is
+ * invalid afterwards.  Errors: IB_ERR_ARG (null). */
 ib_status ib_destroy(ib_solver* s);
 
 /* ---- execution options ----
