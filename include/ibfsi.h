@@ -129,7 +129,8 @@ typedef struct {
   double prepare_seconds;    /* wall time of the offline stage */
   int32_t refine_iters;      /* Schur refinement sweeps in the last FSI iteration */
   int32_t inverse_rebuilds;  /* fresh Schur inverses (LU) made so far */
-  double refine_residual;    /* relative residual of the last Schur solve */
+  double refine_residual;    /* relative residual of the last Schur solve (max norms; when the
+                                refinement stopped on a predicted residual, that prediction) */
   int32_t operator_source;   /* offline operator: 0 built, 1 from the cache, 2 imported,
                                 -1 none (no bodies) */
   int64_t graph_launches;    /* steps replayed from a recorded graph (IB_OPT_GRAPHS) */

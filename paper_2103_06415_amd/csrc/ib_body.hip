@@ -1413,8 +1413,11 @@ __global__ __launch_bounds__(CMP_NT) void k_filter_compact(const double* vals, i
 // one grid barrier every workgroup reads all shares and maxima and adds the shares in
 // workgroup order, so all hold the same f and take the same decision.  Sweeps stop when the
 // relative residual |r|/|b| (max norms) is at most 1e-16 n or no longer halves, after at most
-// maxit sweeps; f then keeps the value whose residual was tested.  With no guess, f starts at
-// 0, so the first sweep gives f = X b.  Workspace `ws` (doubles): [0] relative residual,
+// maxit sweeps; f then keeps the value whose residual was tested.  They also stop right after
+// an update when the residual it leaves, predicted from the last contraction (|r_k|^2 /
+// |r_{k-1}|), is below 1/100 of that target: the sweep that would only confirm it is not run,
+// and the reported residual is that prediction.  With no guess, f starts at 0, so the first
+// sweep gives f = X b.  Workspace `ws` (doubles): [0] relative residual,
 // [1] sweeps, [2] barrier arrivals, [3] exits (32-bit counters), then two buffers of nb rows
 // of n + 1 values (the share, then the maximum); alternate sweeps use alternate buffers, so a
 // row is never overwritten while another workgroup may still read it.  The last workgroup to
@@ -1429,6 +1432,7 @@ constexpr int REF_NB_MAX = 128;
 constexpr size_t REF_LDS_CACHE = 48 * 1024;
 constexpr size_t REF_LDS_BIG = 96 * 1024;
 constexpr int REF_LOADS = 8;      // loads of a thread in flight while the matrices fill LDS
+constexpr double REF_PREDICT = 0.01;  // margin of the predicted stop (see refine_body)
 size_t refine_ws_doubles(int n, int) {
   return (size_t)REF_HDR + (size_t)2 * REF_NB_MAX * (n + 1) + (size_t)2 * (n + 1);
 }
@@ -1483,6 +1487,29 @@ __device__ inline double ld_agent(const double* p) {
 }
 
 __device__ inline double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
+
+// A double moved between lanes by a DPP control (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over aligned groups of g lanes (g a power of two <= 64), the same value in every lane
+// of a group: within quads by quad permutations, then half rows and rows by mirrors (each
+// step adds two partial sums, the same two in both lanes of a pair, so every lane ends with
+// the same bits), then across rows by shuffles.  Every lane of the wave must be active.
+__device__ __forceinline__ double lane_group_sum(double v, int g) {
+  if (g >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  if (g >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  if (g >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+  if (g >= 16) v += dpp_move<0x140>(v); // row_mirror
+  if (g >= 32) v += __shfl_xor(v, 16);
+  if (g >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
 
 template <bool CACHE, bool TWO>
 __device__ __forceinline__ void refine_body(const double* __restrict__ M,
@@ -1560,6 +1587,69 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
   bool ok = true;
   unsigned target = 0;
   const int rk = tid / tpr, rp = tid % tpr;  // row and part of this thread in r = b - M f
+  if constexpr (CACHE && !TWO) {
+    // Rows and columns in LDS.  r on the own rows with tpr lanes per row summed across the
+    // lanes (DPP); then thread e forms element e of the share X[:, R_w] r_{R_w}, and the thread
+    // of element n the maximum |r| on R_w.
+    for (int it = 0; it < maxit; ++it) {
+      double acc = 0.0;
+      if (rk < nr) {
+        const double* mr = sm + (size_t)rk * n;
+#pragma unroll 4
+        for (int j = rp; j < n; j += tpr) acc = fma(mr[j], sf[j], acc);
+      }
+      acc = lane_group_sum(acc, tpr);
+      if (rk < nr && rp == 0) sr[rk] = sb[rk] - acc;
+      __syncthreads();
+      double* sh = shares + (size_t)(it & 1) * REF_NB_MAX * ns + (size_t)w * ns;
+      for (int e = tid; e <= n; e += 256) {
+        double v = 0.0;
+        if (e < n) {
+          const double* xr = sx + (size_t)e * rw;
+          for (int k = 0; k < nr; ++k) v = fma(xr[k], sr[k], v);
+        } else {
+          for (int k = 0; k < nr; ++k) v = nanmax(v, fabs(sr[k]));
+        }
+        st_agent(&sh[e], v);
+      }
+      target += (unsigned)nb;
+      if (!grid_barrier(cnt, target, flags, spin)) {
+        ok = false;
+        break;
+      }
+      // all shares and maxima, loads in flight together; shares added in workgroup order
+      const double* all = shares + (size_t)(it & 1) * REF_NB_MAX * ns;
+      for (int e = tid; e <= n; e += 256) {
+        double a = 0.0;
+        for (int q0 = 0; q0 < nb; q0 += 16) {
+          double v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) v[u] = ld_agent(&all[(size_t)min(q0 + u, nb - 1) * ns + e]);
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (q0 + u < nb) a = e < n ? a + v[u] : nanmax(a, v[u]);
+        }
+        if (e < n) sd[e] = a;
+        else sred[0] = a;
+      }
+      __syncthreads();
+      const double nrm = sred[0];
+      rel = nbv > 0.0 ? nrm / nbv : 0.0;
+      if (!(rel > 1e-16 * n) || !(nrm < 0.5 * prev)) {
+        sweeps = it;
+        break;
+      }
+      const double pred = it > 0 ? nrm * (nrm / prev) : INFINITY;
+      prev = nrm;
+      for (int j = tid; j < n; j += 256) sf[j] += sd[j];
+      __syncthreads();
+      if (pred <= REF_PREDICT * 1e-16 * n * nbv) {
+        sweeps = it + 1;
+        rel = pred / nbv;
+        break;
+      }
+    }
+  } else {
   for (int it = 0; it < maxit; ++it) {
     // r = b - M f on the own rows: tpr threads per row
     {
@@ -1661,9 +1751,18 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
       sweeps = it;
       break;
     }
+    // the residual after this update if it contracts as the last one did
+    const double pred = it > 0 ? nrm * (nrm / prev) : INFINITY;
     prev = nrm;
     for (int j = tid; j < n; j += 256) sf[j] += sd[j];
     __syncthreads();
+    if (pred <= REF_PREDICT * 1e-16 * n * nbv) {
+      // below the target with a wide margin: the sweep that would only confirm it is skipped
+      sweeps = it + 1;
+      rel = pred / nbv;
+      break;
+    }
+  }
   }
   if (ok) {
     for (int i = r0 + tid; i < r1; i += 256) f[i] = sf[i];

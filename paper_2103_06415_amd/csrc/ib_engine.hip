@@ -1435,6 +1435,13 @@ bool refresh_at(const ib_solver* s, int it) {
   return it == 0 && s->hrinfo != nullptr && s->hrinfo[1] > REFRESH_SWEEPS;
 }
 
+// Whether the refinement of FSI iteration `it` starts from the stresses in s->f: the previous
+// iterate's, or at a step's first iteration the previous step's (every completed step leaves
+// a converged solve there); not after a refinement that stopped contracting.
+bool refine_guess(const ib_solver* s, int it) {
+  return (it > 0 || s->step > 0) && !s->x_valid_retry;
+}
+
 template <typename T>
 ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
   FsiArgs a = a0;
@@ -1492,8 +1499,8 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
     X = s->Xn;
     xcopy = s->Minv;
   }
-  HIPCHK(launch_refine(a.M, a.pm, X, s->rhs, s->f, nf, REFINE_MAXIT,
-                       it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags, a.gate, xcopy,
+  HIPCHK(launch_refine(a.M, a.pm, X, s->rhs, s->f, nf, REFINE_MAXIT, refine_guess(s, it),
+                       s->rinfo, s->rout, s->flags, a.gate, xcopy,
                        s->barrier_arg(), s->stream));
   HIPCHK(launch_update(a, it, K, s->cfg.newton_tol, s->cfg.newton_fixed_iter, s->stream));
   return IB_OK;
@@ -2607,7 +2614,7 @@ ib_status batch_step(ib_batch* b) {
         }
         const int c = sh.two ? 2 : sh.cache ? 1 : 0;
         rj[c].push_back(RefineJob{a.M, X, a.pm, s->rhs, s->f, nf, sh.rw, sh.tpr, REFINE_MAXIT,
-                                  it > 0 && !s->x_valid_retry, s->rinfo, s->rout, s->flags,
+                                  refine_guess(s, it), s->rinfo, s->rout, s->flags,
                                   s->gate, xcopy, sh.nb, s->barrier_arg()});
         rnb[c] = std::max(rnb[c], sh.nb);
         rlds[c] = std::max(rlds[c], sh.lds);
