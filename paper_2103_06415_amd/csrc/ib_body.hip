@@ -655,11 +655,31 @@ __device__ __forceinline__ void beam_body(const FsiArgs& a, int bi, int bx) {
   const double* zn = a.zeta + b.dof0;
   const double* an = a.zetadot + b.dof0;
   const double* ms = a.dmass + b.dof0;
+  double* sms = sres + nd;   // masses of the free DOFs
+  // the free DOFs' masses and states are read first, so that their latency overlaps the
+  // element phase (their loads would otherwise follow its barrier)
+  constexpr int UPT = (MAX_BEAM_DOF + BEAM_NT - 1) / BEAM_NT;
+  double pmass[UPT], px[UPT], pz[UPT], pa[UPT], pc[UPT];
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) {
+    const int u = tid + q * BEAM_NT, g = u + 3;
+    pmass[q] = px[q] = pz[q] = pa[q] = pc[q] = 0.0;
+    if (u < nd) {
+      pmass[q] = ms[g];
+      px[q] = xn[g];
+      pz[q] = zn[g];
+      pa[q] = an[g];
+      pc[q] = ck[g];
+    }
+  }
 
   // element internal forces and tangents, one element per thread
   for (int el = tid; el < m - 1; el += BEAM_NT)
     beam_element(ck + 3 * el, a.l0[b.dof0 / 3 + el], a.beta0[b.dof0 / 3 + el], b.ea, b.ei,
                  ek + 42 * el, ek + 42 * el + 6);
+#pragma unroll
+  for (int q = 0; q < UPT; ++q)
+    if (tid + q * BEAM_NT < nd) sms[tid + q * BEAM_NT] = pmass[q];
   __syncthreads();
   // blocks of node k+1: A_k from elements k (second node) and k+1 (first node),
   // U_k = J(k, k+1) from element k+1, L_k = J(k, k-1) from element k (node 0 is clamped)
@@ -670,7 +690,7 @@ __device__ __forceinline__ void beam_body(const FsiArgs& a, int bi, int bx) {
     if (which == 0) {
       v = ek[42 * k + 6 + (r + 3) * 6 + c + 3];
       if (k + 1 <= m - 2) v += ek[42 * (k + 1) + 6 + r * 6 + c];
-      if (r == c) v += 4.0 * ms[3 * (k + 1) + c] / (dt * dt);
+      if (r == c) v += 4.0 * sms[3 * k + c] / (dt * dt);  // ms[3 (k + 1) + c]
     } else if (which == 1) {
       if (k >= 1) v = ek[42 * k + 6 + (r + 3) * 6 + c];
     } else {
@@ -678,12 +698,15 @@ __device__ __forceinline__ void beam_body(const FsiArgs& a, int bi, int bx) {
     }
     bsm[e] = v;
   }
-  for (int u = tid; u < nd; u += BEAM_NT) {
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) {
+    const int u = tid + q * BEAM_NT;
+    if (u >= nd) continue;
     const int g = u + 3, node = g / 3, c = g % 3;
     double rint = ek[42 * (node - 1) + 3 + c];
     if (node <= m - 2) rint += ek[42 * node + c];
-    const double rz = ms[g] * (4.0 * xn[g] / (dt * dt) + 4.0 * zn[g] / dt + an[g]);
-    sres[u] = rz - 4.0 * ms[g] * ck[g] / (dt * dt) - rint;
+    const double rz = pmass[q] * (4.0 * px[q] / (dt * dt) + 4.0 * pz[q] / dt + pa[q]);
+    sres[u] = rz - 4.0 * pmass[q] * pc[q] / (dt * dt) - rint;
   }
   __syncthreads();
 
@@ -840,11 +863,12 @@ __global__ __launch_bounds__(BEAM_NT) void k_ops_beam_multi(const FsiArgs* __res
   }
 }
 
-// LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K); the
-// element scratch (42 (m-1)) overlays A^{-1} .. rhs, which is large enough for NC >= 5
+// LDS of k_beam: A, L, U, A^{-1} (9K each), P (18K), rhs (3K NC), residual (3K), masses
+// (3K); the element scratch (42 (m-1)) overlays A^{-1} .. rhs, which is large enough for
+// NC >= 5
 size_t beam_lds_bytes(int m) {
   const size_t K = m - 1;
-  return (size_t)(54 * K + 3 * K * BEAM_NC + 3 * K) * 8;
+  return (size_t)(54 * K + 3 * K * BEAM_NC + 6 * K) * 8;
 }
 
 constexpr int LU_NT = 1024;
