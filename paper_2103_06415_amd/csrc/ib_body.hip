@@ -1455,7 +1455,7 @@ constexpr int REF_NB_ONE = 32;   // workgroups up to which every workgroup sums 
 constexpr int REF_NB_MAX = 128;
 constexpr size_t REF_LDS_CACHE = 48 * 1024;
 constexpr size_t REF_LDS_BIG = 96 * 1024;
-constexpr int REF_LOADS = 8;      // loads of a thread in flight while the matrices fill LDS
+constexpr int REF_LOADS = 12;     // loads of a thread per matrix in flight while LDS fills
 constexpr double REF_PREDICT = 0.01;  // margin of the predicted stop (see refine_body)
 size_t refine_ws_doubles(int n, int) {
   return (size_t)REF_HDR + (size_t)2 * REF_NB_MAX * (n + 1) + (size_t)2 * (n + 1);
@@ -1558,44 +1558,66 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
   unsigned* cnt = reinterpret_cast<unsigned*>(ws + 2);
   unsigned* ext = reinterpret_cast<unsigned*>(ws + 3);
   double* shares = ws + REF_HDR;
+  // Every global value of the set-up is requested before any is used, so that one round trip
+  // covers b, f, and (CACHE) the first REF_LOADS elements per thread of rows R_w of M and of
+  // columns R_w of X (both just written elsewhere on the chip, so each round trip is long).
+  constexpr int BF = 2;  // elements of b and f per thread held in registers; more are looped
+  double bv[BF], fv[BF];
+#pragma unroll
+  for (int q = 0; q < BF; ++q) {
+    const int i = tid + 256 * q;
+    bv[q] = i < n ? b[i] : 0.0;
+    fv[q] = (guess && i < n) ? f[i] : 0.0;
+  }
+  const double bown = tid < nr ? b[r0 + tid] : 0.0;
+  const int tot = nr * n;
+  double vm[REF_LOADS], vx[REF_LOADS];
+  if (CACHE) {
+#pragma unroll
+    for (int u = 0; u < REF_LOADS; ++u) {
+      const int e = min(tid + u * 256, tot - 1);
+      vm[u] = M[(size_t)(r0 + e / n) * pm + e % n];
+      vx[u] = X[(size_t)(e / nr) * pm + r0 + e % nr];
+    }
+  }
   // |b| and the starting f (the same in every workgroup)
   double mb = 0.0;
-  for (int i = tid; i < n; i += 256) {
+#pragma unroll
+  for (int q = 0; q < BF; ++q) {
+    const int i = tid + 256 * q;
+    if (i < n) {
+      mb = nanmax(mb, fabs(bv[q]));
+      sf[i] = fv[q];
+    }
+  }
+  for (int i = tid + 256 * BF; i < n; i += 256) {
     mb = nanmax(mb, fabs(b[i]));
     sf[i] = guess ? f[i] : 0.0;
   }
   for (int off = 32; off > 0; off >>= 1) mb = nanmax(mb, __shfl_xor(mb, off));
   if (lane == 0) sred[wv] = mb;
-  for (int k = tid; k < nr; k += 256) sb[k] = b[r0 + k];
+  if (tid < nr) sb[tid] = bown;
+  for (int k = tid + 256; k < nr; k += 256) sb[k] = b[r0 + k];
   if (CACHE) {
-    // rows R_w of M and columns R_w of X into LDS, REF_LOADS loads of a thread in flight at
-    // once (the matrices were just written elsewhere on the chip, so each round trip is long)
-    const int tot = nr * n;
+    // rows R_w of M and columns R_w of X into LDS: the first round is in flight already, the
+    // rest follow REF_LOADS loads of a thread at a time
     for (int e0 = tid; e0 < tot; e0 += 256 * REF_LOADS) {
-      double v[REF_LOADS];
+      if (e0 != tid) {
 #pragma unroll
-      for (int u = 0; u < REF_LOADS; ++u) {
-        const int e = min(e0 + u * 256, tot - 1);
-        v[u] = M[(size_t)(r0 + e / n) * pm + e % n];
-      }
-#pragma unroll
-      for (int u = 0; u < REF_LOADS; ++u)
-        if (e0 + u * 256 < tot) sm[e0 + u * 256] = v[u];
-    }
-    for (int e0 = tid; e0 < tot; e0 += 256 * REF_LOADS) {
-      double v[REF_LOADS];
-#pragma unroll
-      for (int u = 0; u < REF_LOADS; ++u) {
-        const int e = min(e0 + u * 256, tot - 1);
-        v[u] = X[(size_t)(e / nr) * pm + r0 + e % nr];
+        for (int u = 0; u < REF_LOADS; ++u) {
+          const int e = min(e0 + u * 256, tot - 1);
+          vm[u] = M[(size_t)(r0 + e / n) * pm + e % n];
+          vx[u] = X[(size_t)(e / nr) * pm + r0 + e % nr];
+        }
       }
 #pragma unroll
       for (int u = 0; u < REF_LOADS; ++u) {
         const int e = e0 + u * 256;
         if (e >= tot) continue;
+        sm[e] = vm[u];
         const int j = e / nr, k = e % nr;
-        sx[(size_t)j * rw + k] = v[u];
-        if (xcopy) xcopy[(size_t)j * pm + r0 + k] = v[u];
+        sx[(size_t)j * rw + k] = vx[u];
+        if (xcopy) xcopy[(size_t)j * pm + r0 + k] = vx[u];
       }
     }
   } else if (xcopy) {
