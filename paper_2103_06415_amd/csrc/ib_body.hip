@@ -1011,7 +1011,7 @@ __device__ void convergence_test(int* ctl, double d, int it, int K, double tol, 
 // non-negative maxima; a non-finite update reports +Inf.  Many workgroups: one wave per
 // group of 4 beam rows.
 __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, double tol, int fixed,
-                                            int bx, int gx) {
+                                            int bx, int gx, const double* fs) {
   if (iter_gated(a.gate)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = STRUCT_NT / 64;
@@ -1036,7 +1036,7 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
         const double rphi = b.inertia * (4.0 * ts[TS_THETA] / (dt * dt) + 4.0 * ts[TS_PHI] / dt + ts[TS_PHIDOT]) +
                             b.damping * (2.0 * ts[TS_THETA] / dt + ts[TS_PHI]) + tors_g(a, b, ts, th);
         double sf = 0.0;
-        for (int u = lane; u < 2 * m; u += 64) sf += (u < m ? -sn : cs) * (u % m) * b.ds * a.f[r0 + u];
+        for (int u = lane; u < 2 * m; u += 64) sf += (u < m ? -sn : cs) * (u % m) * b.ds * fs[r0 + u];
         for (int off = 32; off > 0; off >>= 1) sf += __shfl_xor(sf, off);
         if (lane == 0) {
           const double thn = (rphi + b.ds * sf) / jt;
@@ -1057,7 +1057,7 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
 #pragma unroll
         for (int k = 0; k < CQ; ++k) {
           const int c = lane + 64 * k;
-          fc[k] = c < 2 * m ? a.f[r0 + c] : 0.0;
+          fc[k] = c < 2 * m ? fs[r0 + c] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1114,7 +1114,7 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
 
 __global__ __launch_bounds__(STRUCT_NT) void k_update(FsiArgs a, int it, int K, double tol,
                                                      int fixed) {
-  update_body(a, it, K, tol, fixed, blockIdx.x, gridDim.x);
+  update_body(a, it, K, tol, fixed, blockIdx.x, gridDim.x, a.f);
 }
 
 __global__ __launch_bounds__(STRUCT_NT) void k_update_multi(const UpdateJob* __restrict__ tab,
@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__(STRUCT_NT) void k_update_multi(const UpdateJob* __r
   a.iter = it;
   const int nb = j.nb;
   if ((int)blockIdx.x >= nb) return;
-  update_body(a, it, K, j.tol, j.fixed, blockIdx.x, nb);
+  update_body(a, it, K, j.tol, j.fixed, blockIdx.x, nb, a.f);
 }
 
 // Newmark completion of the step with the accepted iterate.
@@ -1535,14 +1535,16 @@ __device__ __forceinline__ double lane_group_sum(double v, int g) {
   return v;
 }
 
+// Returns whether the solve completed (its f is then in the first n doubles of the dynamic
+// LDS, the same in every workgroup).
 template <bool CACHE, bool TWO>
-__device__ __forceinline__ void refine_body(const double* __restrict__ M,
+__device__ __forceinline__ bool refine_body(const double* __restrict__ M,
                                             const double* __restrict__ X, int pm,
                                             const double* __restrict__ b, double* f, int n,
                                             int rw, int tpr, int maxit, int guess, double* ws,
                                             double* out, int* flags, const int* gate,
                                             double* xcopy, long spin, int bx, int gx) {
-  if (iter_gated(gate)) return;  // the same for every workgroup: none enters a barrier
+  if (iter_gated(gate)) return false;  // the same for every workgroup: none enters a barrier
   extern __shared__ double lds[];
   double* sf = lds;           // f (n)
   double* sd = sf + n;        // the update of this sweep (n)
@@ -1828,6 +1830,7 @@ __device__ __forceinline__ void refine_body(const double* __restrict__ M,
       __hip_atomic_store(ext, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  return ok;
 }
 
 template <bool CACHE, bool TWO>
@@ -1839,6 +1842,25 @@ __global__ __launch_bounds__(256) void k_refine(const double* __restrict__ M,
                                                 double* xcopy, long spin) {
   refine_body<CACHE, TWO>(M, X, pm, b, f, n, rw, tpr, maxit, guess, ws, out, flags, gate, xcopy,
                           spin, blockIdx.x, gridDim.x);
+}
+
+// The refinement followed by the structure update of the same FSI iteration (k_update's
+// work) on the same workgroups, which all hold the new f in LDS: one launch fewer per
+// iteration.  When the refinement gave up, the update reads f from memory, as k_update would.
+template <bool CACHE, bool TWO>
+__global__ __launch_bounds__(256) void k_refine_update(const double* __restrict__ M,
+                                                       const double* __restrict__ X, int pm,
+                                                       const double* __restrict__ b, double* f,
+                                                       int n, int rw, int tpr, int maxit,
+                                                       int guess, double* ws, double* out,
+                                                       int* flags, const int* gate, double* xcopy,
+                                                       long spin, FsiArgs ua, int uit, int uK,
+                                                       double utol, int ufixed) {
+  const bool ok = refine_body<CACHE, TWO>(M, X, pm, b, f, n, rw, tpr, maxit, guess, ws, out,
+                                          flags, gate, xcopy, spin, blockIdx.x, gridDim.x);
+  extern __shared__ double lds[];
+  __syncthreads();
+  update_body(ua, uit, uK, utol, ufixed, blockIdx.x, gridDim.x, ok ? lds : ua.f);
 }
 
 // Many instances per launch: instance blockIdx.y's nb workgroups are its own barrier group
@@ -2012,9 +2034,25 @@ bool refine_shape(int n, RefineShape* out) {
 
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, double* xcopy, long spin, hipStream_t st) {
+                         const int* gate, double* xcopy, long spin, hipStream_t st,
+                         const FsiArgs* ua, int uit, int uK, double utol, int ufixed) {
   RefineShape r;
   if (maxit < 1 || !refine_shape(n, &r)) return hipErrorInvalidValue;
+  if (ua != nullptr) {
+    if (r.two)
+      hipLaunchKernelGGL((k_refine_update<true, true>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm,
+                         b, f, n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin,
+                         *ua, uit, uK, utol, ufixed);
+    else if (r.cache)
+      hipLaunchKernelGGL((k_refine_update<true, false>), dim3(r.nb), dim3(256), r.lds, st, M, X,
+                         pm, b, f, n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin,
+                         *ua, uit, uK, utol, ufixed);
+    else
+      hipLaunchKernelGGL((k_refine_update<false, false>), dim3(r.nb), dim3(256), r.lds, st, M, X,
+                         pm, b, f, n, r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin,
+                         *ua, uit, uK, utol, ufixed);
+    return hipGetLastError();
+  }
   if (r.two)
     hipLaunchKernelGGL((k_refine<true, true>), dim3(r.nb), dim3(256), r.lds, st, M, X, pm, b, f, n,
                        r.rw, r.tpr, maxit, guess, ws, out, flags, gate, xcopy, spin);

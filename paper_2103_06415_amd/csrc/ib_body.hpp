@@ -275,9 +275,13 @@ hipError_t launch_beam_init(const FsiArgs& a, hipStream_t st);
 // out[0] = final relative residual, out[1] = sweeps, out[2] = 1 when `partial` is set and
 // the maxit sweeps ran out before convergence (the caller continues with guess = 1);
 // otherwise flags[1] is raised when the residual stays above 1e-9
+// With ua set, the same launch then runs the structure update of FSI iteration uit of uK
+// (launch_update's work, tolerance utol, fixed iteration count ufixed) with the new f.
 hipError_t launch_refine(const double* M, int pm, const double* X, const double* b, double* f,
                          int n, int maxit, int guess, double* ws, double* out, int* flags,
-                         const int* gate, double* xcopy, long spin, hipStream_t st);
+                         const int* gate, double* xcopy, long spin, hipStream_t st,
+                         const FsiArgs* ua = nullptr, int uit = 0, int uK = 0, double utol = 0.0,
+                         int ufixed = 0);
 // Whether a refinement of n unknowns fits on the device at once (all its workgroups resident,
 // which its device-wide barrier needs); have / need: resident capacity and workgroups.
 bool refine_coresident(int n, int* have, int* need);

@@ -1499,10 +1499,10 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
     X = s->Xn;
     xcopy = s->Minv;
   }
+  // the refinement and then, in the same launch, the structure update with the new stresses
   HIPCHK(launch_refine(a.M, a.pm, X, s->rhs, s->f, nf, REFINE_MAXIT, refine_guess(s, it),
-                       s->rinfo, s->rout, s->flags, a.gate, xcopy,
-                       s->barrier_arg(), s->stream));
-  HIPCHK(launch_update(a, it, K, s->cfg.newton_tol, s->cfg.newton_fixed_iter, s->stream));
+                       s->rinfo, s->rout, s->flags, a.gate, xcopy, s->barrier_arg(), s->stream,
+                       &a, it, K, s->cfg.newton_tol, s->cfg.newton_fixed_iter));
   return IB_OK;
 }
 
