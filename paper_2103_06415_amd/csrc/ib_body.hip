@@ -224,24 +224,28 @@ __device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, i
   return 0.0;
 }
 
-// Body operator rows, u* and the Schur right-hand side for every point (one thread per
-// point); point 0 also clears the convergence maximum that k_update folds into.
+// Body operator rows, u* and the Schur right-hand side for every point and velocity
+// component (one thread each, the two of a point adjacent); point 0 also clears the
+// convergence maximum that k_update folds into.  Launches take 2 npts threads.
 template <typename T>
 __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
   if (iter_gated(a.gate)) return;
-  const int p = bx * blockDim.x + threadIdx.x;
+  const int t = bx * blockDim.x + threadIdx.x;
+  const int p = t >> 1, comp = t & 1;
   if (p >= a.npts) return;
   int bi = 0;
   while (bi + 1 < a.nbodies && a.bodies[bi + 1].pt0 <= p) ++bi;
   const BodyDev& b = a.bodies[bi];
   const int local = p - b.pt0;
-  if (p == 0) a.delta[0] = 0.0;
+  if (p == 0 && comp == 0) a.delta[0] = 0.0;
   double px, py;
   point_position(a, b, local, &px, &py);
-  a.pos[2 * p] = px;
-  a.pos[2 * p + 1] = py;
+  if (comp == 0) {
+    a.pos[2 * p] = px;
+    a.pos[2 * p + 1] = py;
+  }
   const T* s = static_cast<const T*>(a.sstar);
-  for (int comp = 0; comp < 2; ++comp) {
+  {
     const int row = 2 * b.pt0 + comp * b.npts + local;
     int base[2];
     double w[16];
@@ -835,7 +839,7 @@ __global__ __launch_bounds__(BEAM_NT) void k_beam_multi(const BeamJob* __restric
 }
 
 // k_body_ops and k_beam of one deformable body in one launch: workgroups below nbeam solve
-// the beam's right-hand sides, the others take BEAM_NT body points each (the two share no
+// the beam's right-hand sides, the others take BEAM_NT / 2 body points each (the two share no
 // data: the beam's part of the Schur right-hand side is applied by k_schur_sd).
 template <typename T>
 __global__ __launch_bounds__(BEAM_NT) void k_ops_beam(FsiArgs a, int bi, int nbeam) {
@@ -844,7 +848,7 @@ __global__ __launch_bounds__(BEAM_NT) void k_ops_beam(FsiArgs a, int bi, int nbe
 }
 
 // Many instances (ib_batch_*): rows y < nbeam of the grid solve beam job y's right-hand
-// sides, the others take BEAM_NT body points each of instance y - nbeam (k_ops_beam's split).
+// sides, the others take BEAM_NT / 2 body points each of instance y - nbeam (k_ops_beam's split).
 template <typename T>
 __global__ __launch_bounds__(BEAM_NT) void k_ops_beam_multi(const FsiArgs* __restrict__ fa, int ni,
                                                             const BeamJob* __restrict__ beams,
@@ -2103,7 +2107,7 @@ hipError_t launch_gemm64(const double* A, const double* B, double* C, int n, int
 
 template <typename T>
 hipError_t launch_body_ops(const FsiArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_body_ops<T>), dim3((a.npts + 63) / 64), dim3(64), 0, st, a);
+  hipLaunchKernelGGL((k_body_ops<T>), dim3((2 * a.npts + 63) / 64), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 __global__ void k_cols_to_matrix(const double* vals, int nf, int ns, int c0, double* G, int pm) {
@@ -2160,7 +2164,7 @@ hipError_t launch_ops_beam(const FsiArgs& a, int bi, int m, hipStream_t st) {
   const size_t lds = beam_lds_bytes(m);
   if (m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
   const int nbeam = (2 * m + 1 + BEAM_NC - 1) / BEAM_NC;
-  const int nops = (a.npts + BEAM_NT - 1) / BEAM_NT;
+  const int nops = (2 * a.npts + BEAM_NT - 1) / BEAM_NT;
   hipLaunchKernelGGL((k_ops_beam<T>), dim3(nbeam + nops), dim3(BEAM_NT), lds, st, a, bi, nbeam);
   return hipGetLastError();
 }
@@ -2273,7 +2277,7 @@ template <typename T>
 hipError_t launch_body_ops_multi(const FsiArgs* tab, int count, int max_npts, int it,
                                  hipStream_t st) {
   if (count <= 0 || max_npts <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_body_ops_multi<T>), dim3((max_npts + 63) / 64, count), dim3(64), 0, st,
+  hipLaunchKernelGGL((k_body_ops_multi<T>), dim3((2 * max_npts + 63) / 64, count), dim3(64), 0, st,
                      tab, it);
   return hipGetLastError();
 }
@@ -2298,7 +2302,8 @@ hipError_t launch_ops_beam_multi(const FsiArgs* fa, int ni, int max_npts, const 
                                  int nbeam, int max_m, size_t lds, int it, hipStream_t st) {
   if (ni <= 0) return hipSuccess;
   if (max_m < 2 || lds > 150 * 1024) return hipErrorInvalidValue;
-  const int gx = std::max((2 * max_m + 1 + BEAM_NC - 1) / BEAM_NC, (max_npts + BEAM_NT - 1) / BEAM_NT);
+  const int gx =
+      std::max((2 * max_m + 1 + BEAM_NC - 1) / BEAM_NC, (2 * max_npts + BEAM_NT - 1) / BEAM_NT);
   hipLaunchKernelGGL((k_ops_beam_multi<T>), dim3(gx, nbeam + ni), dim3(BEAM_NT), lds, st, fa, ni,
                      beams, nbeam, it);
   return hipGetLastError();
