@@ -28,6 +28,26 @@ __device__ __forceinline__ bool post_gated(const int* gate) {
 }
 
 
+// Rectangle k of a sub-domain (origin, points per side, first point), read with constant
+// indices only: the boxes sit in kernel arguments, and an index known only at run time would
+// make every field a memory load of its own.
+struct SdBox {
+  int i0, j0, npx, npy, off;
+};
+__device__ __forceinline__ SdBox sd_box(const SdBoxes& s, int k) {
+  int i0 = s.i0[0], j0 = s.j0[0], npx = s.npx[0], npy = s.npy[0], off = s.off[0];
+#pragma unroll
+  for (int q = 1; q < SD_MAX_BOXES; ++q) {
+    const bool m = k == q;
+    i0 = m ? s.i0[q] : i0;
+    j0 = m ? s.j0[q] : j0;
+    npx = m ? s.npx[q] : npx;
+    npy = m ? s.npy[q] : npy;
+    off = m ? s.off[q] : off;
+  }
+  return SdBox{i0, j0, npx, npy, off};
+}
+
 __device__ __forceinline__ double roma3(double r) {
   const double a = fabs(r);
   if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
@@ -226,7 +246,9 @@ __device__ double rhs_body_term(const FsiArgs& a, const BodyDev& b, int local, i
 
 // Body operator rows, u* and the Schur right-hand side for every point and velocity
 // component (one thread each, the two of a point adjacent); point 0 also clears the
-// convergence maximum that k_update folds into.  Launches take 2 npts threads.
+// convergence maximum that k_update folds into.  Launches take 2 npts threads.  Every global
+// load comes before the first global store: the memory counter a wait uses also counts
+// stores, so a load after a store would wait for that store's acknowledgement as well.
 template <typename T>
 __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
   if (iter_gated(a.gate)) return;
@@ -235,104 +257,115 @@ __device__ __forceinline__ void body_ops_body(const FsiArgs& a, int bx) {
   if (p >= a.npts) return;
   int bi = 0;
   while (bi + 1 < a.nbodies && a.bodies[bi + 1].pt0 <= p) ++bi;
-  const BodyDev& b = a.bodies[bi];
+  const BodyDev b = a.bodies[bi];
   const int local = p - b.pt0;
-  if (p == 0 && comp == 0) a.delta[0] = 0.0;
   double px, py;
   point_position(a, b, local, &px, &py);
+  const T* s = static_cast<const T*>(a.sstar);
+  const int row = 2 * b.pt0 + comp * b.npts + local;
+  int base[2];
+  double w[16];
+  // the P row of a sub-domain point (slots and hat weights) and the slots it names (act)
+  int pidx[4] = {0, 0, 0, 0};
+  double pw[4] = {0.0, 0.0, 0.0, 0.0};
+  int nact = 0;  // act entries to set: pidx[e] for e < nact with pw[e] != 0 (rigid: e = 0)
+  int flag = 0;  // error code for flags[0]
+  if (!a.use_sd) {
+    exact_window(px, py, comp, a.x0, a.y0, a.h, base, w, a.delta_kind);
+  } else if (b.kind == BODY_RIGID) {
+    const int app = a.sd_ngrid + b.app0 + local;
+    exact_window(px, py, comp, a.x0, a.y0, a.h, base, w, a.delta_kind);
+    for (int e = 0; e < 4; ++e) {
+      pidx[e] = comp * a.sd_total + app;
+      pw[e] = e == 0 ? 1.0 : 0.0;
+    }
+    nact = 1;
+  } else {
+    // the body's rectangle of the sub-domain
+    const SdBox bb = sd_box(a.sdb, b.sdbox);
+    const int bi0 = bb.i0, bj0 = bb.j0, npx = bb.npx, npy = bb.npy;
+    const double xs0 = a.x0 + bi0 * a.h, ys0 = a.y0 + bj0 * a.h;
+    const double rx = (px - xs0) / a.h, ry = (py - ys0) / a.h;
+    const double tol = 1e-9;
+    if (!(rx >= -tol && ry >= -tol && rx <= npx - 1 + tol && ry <= npy - 1 + tol)) {
+      flag = 1;  // out of sub-domain (or non-finite position)
+      for (int e = 0; e < 16; ++e) w[e] = 0.0;
+      base[0] = base[1] = 2;
+    } else {
+      int ix = (int)floor(rx), iy = (int)floor(ry);
+      ix = ix < 0 ? 0 : (ix > npx - 2 ? npx - 2 : ix);
+      iy = iy < 0 ? 0 : (iy > npy - 2 ? npy - 2 : iy);
+      const double fx = rx - ix, fy = ry - iy;
+      const int gp = bi0 + ix, gq = bj0 + iy;
+      base[0] = gp - 1;
+      base[1] = gq - 1;
+      for (int e = 0; e < 16; ++e) w[e] = 0.0;
+      const double hw[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};
+      const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
+      // E0 row of a vertex: the kernel at offsets (-1, 0, 1) across the component's
+      // faces and (-1/2, 1/2) along them (the same pattern at every vertex)
+      const double k0 = roma3(0.0), k1 = roma3(1.0), kh = roma3(0.5);
+      const double across[3] = {k1, k0, k1};
+      for (int e = 0; e < 4; ++e) {
+        pidx[e] = comp * a.sd_total + bb.off + (iy + dy[e]) * npx + (ix + dx[e]);
+        pw[e] = hw[e];
+        for (int u = 0; u < 3; ++u)
+          for (int v = 0; v < 2; ++v) {
+            const double c = hw[e] * (across[u] * kh);
+            if (comp == 0) w[(dy[e] + v) * 4 + dx[e] + u] += c;
+            else w[(dy[e] + u) * 4 + dx[e] + v] += c;
+          }
+      }
+      nact = 4;
+    }
+  }
+  if (!window_ok(base, w, comp, a.n)) {
+    flag = 2;  // near the boundary: keep every later access in bounds
+    for (int e = 0; e < 16; ++e) w[e] = 0.0;
+    base[0] = base[1] = 2;
+  }
+  // all 16 face fluxes of the window are loaded at once, then summed in window order;
+  // indices are clamped to [0, n-1] (every access stays inside the (n+1)-row array):
+  // that changes none of the nonzero-weight faces (window_ok), and the others carry
+  // weight 0 on a finite value
+  double fl[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int fi = min(max(base[0] + (e & 3), 0), a.n - 1);
+    const int fj = min(max(base[1] + (e >> 2), 0), a.n - 1);
+    fl[e] = face_flux(s, a.ps, comp, fi, fj, a.ux, a.uy);
+  }
+  const double term = rhs_body_term(a, b, local, comp);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc += w[e] * fl[e];
+  const double us = acc / a.h;
+  // the stores
+  if (p == 0 && comp == 0) a.delta[0] = 0.0;
   if (comp == 0) {
     a.pos[2 * p] = px;
     a.pos[2 * p + 1] = py;
   }
-  const T* s = static_cast<const T*>(a.sstar);
-  {
-    const int row = 2 * b.pt0 + comp * b.npts + local;
-    int base[2];
-    double w[16];
-    int* pidx = a.p_idx + 4 * row;
-    double* pw = a.p_w + 4 * row;
-    if (!a.use_sd) {
-      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w, a.delta_kind);
-    } else if (b.kind == BODY_RIGID) {
-      const int app = a.sd_ngrid + b.app0 + local;
-      exact_window(px, py, comp, a.x0, a.y0, a.h, base, w, a.delta_kind);
-      for (int e = 0; e < 4; ++e) {
-        pidx[e] = comp * a.sd_total + app;
-        pw[e] = e == 0 ? 1.0 : 0.0;
-      }
-      a.act[pidx[0]] = 4 * row;
-    } else {
-      // the body's rectangle of the sub-domain
-      const int bx = b.sdbox;
-      const int bi0 = a.sdb.i0[bx], bj0 = a.sdb.j0[bx], npx = a.sdb.npx[bx], npy = a.sdb.npy[bx];
-      const double xs0 = a.x0 + bi0 * a.h, ys0 = a.y0 + bj0 * a.h;
-      const double rx = (px - xs0) / a.h, ry = (py - ys0) / a.h;
-      const double tol = 1e-9;
-      if (!(rx >= -tol && ry >= -tol && rx <= npx - 1 + tol && ry <= npy - 1 + tol)) {
-        atomicMax(&a.flags[0], 1);  // out of sub-domain (or non-finite position)
-        for (int e = 0; e < 16; ++e) w[e] = 0.0;
-        base[0] = base[1] = 2;
-        for (int e = 0; e < 4; ++e) {
-          pidx[e] = 0;
-          pw[e] = 0.0;
-        }
-      } else {
-        int ix = (int)floor(rx), iy = (int)floor(ry);
-        ix = ix < 0 ? 0 : (ix > npx - 2 ? npx - 2 : ix);
-        iy = iy < 0 ? 0 : (iy > npy - 2 ? npy - 2 : iy);
-        const double fx = rx - ix, fy = ry - iy;
-        const int gp = bi0 + ix, gq = bj0 + iy;
-        base[0] = gp - 1;
-        base[1] = gq - 1;
-        for (int e = 0; e < 16; ++e) w[e] = 0.0;
-        const double hw[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};
-        const int dx[4] = {0, 1, 0, 1}, dy[4] = {0, 0, 1, 1};
-        // E0 row of a vertex: the kernel at offsets (-1, 0, 1) across the component's
-        // faces and (-1/2, 1/2) along them (the same pattern at every vertex)
-        const double k0 = roma3(0.0), k1 = roma3(1.0), kh = roma3(0.5);
-        const double across[3] = {k1, k0, k1};
-        for (int e = 0; e < 4; ++e) {
-          pidx[e] = comp * a.sd_total + a.sdb.off[bx] + (iy + dy[e]) * npx + (ix + dx[e]);
-          pw[e] = hw[e];
-          if (hw[e] != 0.0) a.act[pidx[e]] = 4 * row + e;  // any writer of a shared row wins
-          for (int u = 0; u < 3; ++u)
-            for (int v = 0; v < 2; ++v) {
-              const double c = hw[e] * (across[u] * kh);
-              if (comp == 0) w[(dy[e] + v) * 4 + dx[e] + u] += c;
-              else w[(dy[e] + u) * 4 + dx[e] + v] += c;
-            }
-        }
-      }
-    }
-    if (!window_ok(base, w, comp, a.n)) {
-      atomicMax(&a.flags[0], 2);  // near the boundary: keep every later access in bounds
-      for (int e = 0; e < 16; ++e) w[e] = 0.0;
-      base[0] = base[1] = 2;
-    }
-    a.st_base[3 * row] = base[0];
-    a.st_base[3 * row + 1] = base[1];
-    a.st_base[3 * row + 2] = comp;
-    // all 16 face fluxes of the window are loaded at once, then summed in window order;
-    // indices are clamped to [0, n-1] (every access stays inside the (n+1)-row array):
-    // that changes none of the nonzero-weight faces (window_ok), and the others carry
-    // weight 0 on a finite value
-    double fl[16];
+  if (flag == 1) atomicMax(&a.flags[0], 1);
+  if (flag == 2) atomicMax(&a.flags[0], 2);
+  if (a.use_sd) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int fi = min(max(base[0] + (e & 3), 0), a.n - 1);
-      const int fj = min(max(base[1] + (e >> 2), 0), a.n - 1);
-      fl[e] = face_flux(s, a.ps, comp, fi, fj, a.ux, a.uy);
+    for (int e = 0; e < 4; ++e) {
+      a.p_idx[4 * row + e] = pidx[e];
+      a.p_w[4 * row + e] = pw[e];
     }
-    double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      a.st_w[16 * row + e] = w[e];
-      acc += w[e] * fl[e];
-    }
-    const double us = acc / a.h;
-    a.ustar[row] = us;
-    a.rhs[row] = us - rhs_body_term(a, b, local, comp);
+    for (int e = 0; e < 4; ++e)
+      if (e < nact && (nact == 1 || pw[e] != 0.0))
+        a.act[pidx[e]] = 4 * row + e;  // any writer of a shared row wins
   }
+  a.st_base[3 * row] = base[0];
+  a.st_base[3 * row + 1] = base[1];
+  a.st_base[3 * row + 2] = comp;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) a.st_w[16 * row + e] = w[e];
+  a.ustar[row] = us;
+  a.rhs[row] = us - term;
 }
 
 template <typename T>
@@ -510,7 +543,7 @@ __device__ __forceinline__ void schur_sd_body(const FsiArgs& a, int all4, int bx
     const int c = tid + k * SCHUR_NT;
     if (c >= nf) continue;
     const int bc = row_body(a, c);
-    const BodyDev& b = a.bodies[bc];
+    const BodyDev b = a.bodies[bc];
     double mv = (a.dt / (a.h * a.h)) * m[k] * b.ds;
     const int r0 = 2 * b.pt0, mpts = b.npts;
     if (r >= r0 && r < r0 + 2 * mpts && (b.kind == BODY_TORSIONAL || b.kind == BODY_DEFORMABLE)) {
@@ -540,7 +573,7 @@ __device__ __forceinline__ void schur_sd_body(const FsiArgs& a, int all4, int bx
   // r_chi) (eqs. (17) and (37)), with the solve J_d^{-1} res that k_beam left in column 2m
   // of ywork
   if (tid == 0) {
-    const BodyDev& b = a.bodies[row_body(a, r)];
+    const BodyDev b = a.bodies[row_body(a, r)];
     if (b.kind == BODY_DEFORMABLE) {
       const int m = b.npts, u = r - 2 * b.pt0, node = u % m, cmp = u / m;
       if (node > 0) {
@@ -642,7 +675,7 @@ __device__ __forceinline__ void beam_body(const FsiArgs& a, int bi, int bx) {
   if (iter_gated(a.gate)) return;
   constexpr int NC = BEAM_NC;
   extern __shared__ double bsm[];
-  const BodyDev& b = a.bodies[bi];
+  const BodyDev b = a.bodies[bi];
   const int m = b.npts, K = m - 1, nd = 3 * K, ncol = 2 * m + 1;
   const int tid = threadIdx.x;
   const double dt = a.dt;
@@ -1027,7 +1060,7 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
     else my = fmax(my, d);
   };
   for (int bi = 0; bi < a.nbodies; ++bi) {
-    const BodyDev& b = a.bodies[bi];
+    const BodyDev b = a.bodies[bi];
     const int m = b.npts, r0 = 2 * b.pt0;
     if (b.kind == BODY_TORSIONAL) {
       if (gw == 0) {
@@ -1057,7 +1090,8 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
       double* cn = a.chi_new + b.dof0;
       constexpr int CQ = 7;  // 2m <= 448 columns
       for (int u0 = 4 * gw; u0 < nd; u0 += 4 * nwaves) {
-        double v[4][CQ], yr[4], fc[CQ];
+        // every load of the group (rows of Y, the residual column, chi^k) before its stores
+        double v[4][CQ], yr[4], fc[CQ], cv[4];
 #pragma unroll
         for (int k = 0; k < CQ; ++k) {
           const int c = lane + 64 * k;
@@ -1067,23 +1101,28 @@ __device__ __forceinline__ void update_body(const FsiArgs& a, int it, int K, dou
         for (int q = 0; q < 4; ++q) {
           const int u = u0 + q;
           yr[q] = u < nd ? y[(size_t)u * ncol + 2 * m] : 0.0;
+          cv[q] = (lane == 0 && u < nd) ? ck[u + 3] : 0.0;
 #pragma unroll
           for (int k = 0; k < CQ; ++k) {
             const int c = lane + 64 * k;
             v[q][k] = (u < nd && c < 2 * m) ? y[(size_t)u * ncol + c] : 0.0;
           }
         }
+        double dxq[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double acc = 0.0;
 #pragma unroll
           for (int k = 0; k < CQ; ++k) acc += v[q][k] * fc[k];
           for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+          dxq[q] = yr[q] + b.ds * acc;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
           const int u = u0 + q;
           if (lane == 0 && u < nd) {
-            const double dx = yr[q] + b.ds * acc;
-            fold(fabs(dx));
-            cn[u + 3] = ck[u + 3] + dx;  // ck may alias cn: this lane reads, then writes
+            fold(fabs(dxq[q]));
+            cn[u + 3] = cv[q] + dxq[q];  // ck may alias cn: this lane read it above
           }
         }
       }
@@ -1137,7 +1176,7 @@ __device__ __forceinline__ void finish_body(const FsiArgs& a) {
   const int tid = threadIdx.x;
   const double dt = a.dt;
   for (int bi = 0; bi < a.nbodies; ++bi) {
-    const BodyDev& b = a.bodies[bi];
+    const BodyDev b = a.bodies[bi];
     if (b.kind == BODY_TORSIONAL) {
       if (tid == 0) {
         double* ts = a.tors + b.tors * TS_COUNT;
@@ -1312,9 +1351,12 @@ __device__ void off_window(const OffRows& o, int row, int* base, int* comp, doub
   const int pt = row - (*comp) * o.sd_total;
   if (pt < o.sd_ngrid) {
     int k = 0;  // the rectangle holding sub-domain point pt
-    while (k + 1 < o.sdb.n && o.sdb.off[k + 1] <= pt) ++k;
-    const int loc = pt - o.sdb.off[k];
-    const int p = o.sdb.i0[k] + loc % o.sdb.npx[k], q = o.sdb.j0[k] + loc / o.sdb.npx[k];
+#pragma unroll
+    for (int q = 1; q < SD_MAX_BOXES; ++q)
+      if (q < o.sdb.n && o.sdb.off[q] <= pt) k = q;
+    const SdBox bb = sd_box(o.sdb, k);
+    const int loc = pt - bb.off;
+    const int p = bb.i0 + loc % bb.npx, q = bb.j0 + loc / bb.npx;
     base[0] = p - 1;
     base[1] = q - 1;
     for (int e = 0; e < 16; ++e) w[e] = 0.0;
@@ -2235,7 +2277,7 @@ __global__ void k_gather_batch(const int* cols, const double* vals, int ntarget,
 __global__ __launch_bounds__(STRUCT_NT) void k_beam_init(FsiArgs a) {
   const int tid = threadIdx.x;
   for (int bi = 0; bi < a.nbodies; ++bi) {
-    const BodyDev& b = a.bodies[bi];
+    const BodyDev b = a.bodies[bi];
     if (b.kind != BODY_DEFORMABLE) continue;
     const int m = b.npts;
     __shared__ double rint[MAX_BEAM_DOF + 3];
@@ -2394,7 +2436,7 @@ __global__ __launch_bounds__(OUT_NT) void k_outputs(FsiArgs a, const T* __restri
   const int tid = threadIdx.x;
   double mx = 0.0;
   for (int row = tid; row < a.nf; row += OUT_NT) {
-    const BodyDev& b = a.bodies[row_body(a, row)];
+    const BodyDev b = a.bodies[row_body(a, row)];
     const int rel = row - 2 * b.pt0;
     const int comp = a.st_base[3 * row + 2];
     const int local = rel - comp * b.npts;
@@ -2432,7 +2474,7 @@ __global__ __launch_bounds__(OUT_NT) void k_outputs(FsiArgs a, const T* __restri
   if (tid == 0) out[0] = red[0];
   __syncthreads();
   for (int bi = 0; bi < a.nbodies; ++bi) {
-    const BodyDev& b = a.bodies[bi];
+    const BodyDev b = a.bodies[bi];
     for (int c = 0; c < 2; ++c) {
       double sum = 0.0;
       for (int k = tid; k < b.npts; k += OUT_NT) sum += a.f[2 * b.pt0 + c * b.npts + k];

@@ -607,6 +607,26 @@ __device__ __forceinline__ void row_idst_body(const RowArgs<T>& a, const c2<T>* 
       if (e < CNT) dst_pack<T, N>(buf + (e / (N - 1)) * fft_pad_len<N>(), 1 + e % (N - 1), v[b]);
     }
   }
+  static_assert(ROWS <= NT, "one thread per ring row");
+  // the ring values this workgroup writes last are read now: a load issued after the output
+  // stores would wait for their acknowledgement too
+  const int ny = a.ny > 0 ? a.ny : N;
+  constexpr int RB = (N + 1 + NT - 1) / NT;
+  T rlv = T(0), rrv = T(0), rbv[RB], rtv[RB];
+  if (!a.interior_out && ring != nullptr) {
+    if (tid < ROWS && j0 + tid <= a.r1) {
+      rlv = ring[ring_off(RING_L, N, ny) + j0 + tid];
+      rrv = ring[ring_off(RING_R, N, ny) + j0 + tid];
+    }
+    if (ring_rows && blk == 0) {
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int i = tid + q * NT;
+        rbv[q] = i <= N ? ring[ring_off(RING_B, N, ny) + i] : T(0);
+        rtv[q] = i <= N ? ring[ring_off(RING_T, N, ny) + i] : T(0);
+      }
+    }
+  }
   for (int t = tid; t < NS; t += NT) dst_pack_zeros<T, N>(buf + t * fft_pad_len<N>());
   __syncthreads();
   fft_lds<T, N, NS, NT, MAXR>(buf, stw, tid);
@@ -631,18 +651,18 @@ __device__ __forceinline__ void row_idst_body(const RowArgs<T>& a, const c2<T>* 
     }
   }
   if (a.interior_out) return;
-  const int ny = a.ny > 0 ? a.ny : N;
-  for (int t = tid; t < ROWS; t += NT) {
-    const int j = j0 + t;
-    if (j > a.r1) continue;
-    T* o = out + (size_t)j * a.po;
-    o[0] = ring ? ring[ring_off(RING_L, N, ny) + j] : T(0);
-    o[N] = ring ? ring[ring_off(RING_R, N, ny) + j] : T(0);
+  if (tid < ROWS && j0 + tid <= a.r1) {
+    T* o = out + (size_t)(j0 + tid) * a.po;
+    o[0] = rlv;
+    o[N] = rrv;
   }
   if (ring_rows && blk == 0) {
-    for (int i = tid; i <= N; i += NT) {
-      out[i] = ring ? ring[ring_off(RING_B, N, ny) + i] : T(0);
-      out[(size_t)ny * a.po + i] = ring ? ring[ring_off(RING_T, N, ny) + i] : T(0);
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int i = tid + q * NT;
+      if (i > N) continue;
+      out[i] = ring != nullptr ? rbv[q] : T(0);
+      out[(size_t)ny * a.po + i] = ring != nullptr ? rtv[q] : T(0);
     }
   }
 }
@@ -796,12 +816,23 @@ __device__ __forceinline__ void ring_dst_body(const T* __restrict__ sc, int psc,
   const int tid = threadIdx.x;
   load_table<T, N, NT>(stw, tw, tid);
   const int off = ring_off(edge, nx, ny);
-  for (int idx = tid; idx <= N; idx += NT) {
-    T sv, gv;
-    ring_values(sc, psc, gc, pgc, nx, ny, edge, idx, sv, gv);
-    sring[off + idx] = sv;
-    gring[off + idx] = gv;
-    if (idx >= 1 && idx <= N - 1) dst_pack<T, N>(buf, idx, sv);
+  // every value is read before the first store (a load issued after a store waits for that
+  // store's acknowledgement too)
+  constexpr int PR = (N + 1 + NT - 1) / NT;
+  T sv[PR], gv[PR];
+#pragma unroll
+  for (int q = 0; q < PR; ++q) {
+    const int idx = tid + q * NT;
+    sv[q] = gv[q] = T(0);
+    if (idx <= N) ring_values(sc, psc, gc, pgc, nx, ny, edge, idx, sv[q], gv[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < PR; ++q) {
+    const int idx = tid + q * NT;
+    if (idx > N) continue;
+    sring[off + idx] = sv[q];
+    gring[off + idx] = gv[q];
+    if (idx >= 1 && idx <= N - 1) dst_pack<T, N>(buf, idx, sv[q]);
   }
   if (tid == 0) dst_pack_zeros<T, N>(buf);
   __syncthreads();
