@@ -337,6 +337,10 @@ __global__ __launch_bounds__(NT) void k_rowdst_multi(const RowArgs<T>* __restric
 // Reads input rows [r0, r1] (others are zero) and writes
 //   out = (accumulate ? out : 0) + result
 // for every row; input and output may alias when accumulate == 0.
+// 1 / x: the hardware reciprocal in single precision (within 1 ulp), a division in double.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename T, int N, int CW, int NT, int MAXR>
 __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>* __restrict__ tw,
                                                const T* __restrict__ lam, int nblocks, int bx,
@@ -476,14 +480,16 @@ __device__ __forceinline__ void col_solve_body(const ColArgs<T>& a, const c2<T>*
         const int e = tid + b * NT;
         if (e < NP) {
           const int c = e % CW, l = 1 + e / CW;
-          const T ga = xa[b] / ea[b], gb = xb[b] / eb[b];
+          // s = (g + f) scale / L and gamma = g scale with g = x / (1 + alpha L), from one
+          // reciprocal of L (1 + alpha L) per mode (single precision: the hardware reciprocal)
+          const T sa = a.scale * recip(ea[b] * la[b]), sb = a.scale * recip(eb[b] * lb[b]);
           c2<T>* w0 = buf + c * fft_pad_len<N>();
           c2<T>* w1 = buf + (CW + c) * fft_pad_len<N>();
-          dst_pack<T, N>(w0, l, (ga + fa[b]) * (a.scale / la[b]));
-          dst_pack<T, N>(w1, l, ga * a.scale);
+          dst_pack<T, N>(w0, l, (xa[b] + fa[b] * ea[b]) * sa);
+          dst_pack<T, N>(w1, l, xa[b] * la[b] * sa);
           if (l != N / 2) {
-            dst_pack<T, N>(w0, N - l, (gb + fb[b]) * (a.scale / lb[b]));
-            dst_pack<T, N>(w1, N - l, gb * a.scale);
+            dst_pack<T, N>(w0, N - l, (xb[b] + fb[b] * eb[b]) * sb);
+            dst_pack<T, N>(w1, N - l, xb[b] * lb[b] * sb);
           }
         }
       }
