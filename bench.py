@@ -21,22 +21,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-cell steps/s (1024², 4 levels) fp32 vs fp64; served p50/p99 latency"
 PEAK_HBM = 8.0e12
-# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes recorded in
-# profiles/flow_1024x4_fp32_hbm_traffic.md (scaled by a 256 MiB reference copy); valid for
-# the kernels as measured there, at n = 1024 in FP32
-# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes (scaled by a reference
-# copy; profiles/flow_1024x4_fp32_hbm_traffic.md), by kernel class and the configuration
-# (variant) measured; a configuration without a measurement reports no traffic
+# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes (each scaled by what the
+# counter reads for a 256 MiB reference copy; profiles/flow_1024x4_fp32_hbm_traffic.md), by kernel
+# class and configuration (variant), at n = 1024 in FP32, for the kernels as measured there; a
+# configuration without a measurement reports no traffic
 TRAFFIC_PER_LAUNCH = {
-    ("rhs_rowdst", 0): 21.79e6, ("rhs_rowdst", 1): 21.79e6, ("rhs_rowdst", 2): 21.69e6,
-    ("rhs_rowdst", 3): 21.67e6, ("rhs_rowdst", 4): 21.67e6, ("rhs_rowdst", 5): 21.75e6,
-    ("rhs_rowdst", 6): 21.68e6, ("rhs_rowdst", 7): 21.74e6,
-    ("col_solve", 0): 12.35e6, ("col_solve", 1): 13.41e6, ("col_solve", 2): 13.12e6,
-    ("col_solve", 3): 13.10e6, ("col_solve", 4): 13.09e6, ("col_solve", 5): 13.70e6,
-    ("col_solve", 6): 42.97e6, ("col_solve", 7): 49.18e6,
-    ("row_idst", 0): 17.11e6, ("row_idst", 1): 17.13e6, ("row_idst", 2): 17.05e6,
-    ("row_idst", 3): 17.04e6, ("row_idst", 4): 17.05e6, ("row_idst", 5): 17.11e6,
-    ("row_idst", 6): 17.04e6, ("row_idst", 7): 17.07e6,
+    ("col_solve", 0): 12.35e6, ("col_solve", 1): 13.41e6, ("col_solve", 2): 13.13e6,
+    ("col_solve", 3): 13.78e6, ("col_solve", 4): 13.08e6, ("col_solve", 5): 13.02e6,
+    ("col_solve", 6): 41.88e6, ("col_solve", 7): 49.80e6, ("rhs_rowdst", 0): 21.75e6,
+    ("rhs_rowdst", 1): 21.75e6, ("rhs_rowdst", 2): 21.64e6, ("rhs_rowdst", 3): 21.63e6,
+    ("rhs_rowdst", 4): 21.61e6, ("rhs_rowdst", 5): 21.71e6, ("rhs_rowdst", 6): 21.68e6,
+    ("rhs_rowdst", 7): 21.65e6, ("row_idst", 0): 17.12e6, ("row_idst", 1): 17.15e6,
+    ("row_idst", 2): 17.05e6, ("row_idst", 3): 17.04e6, ("row_idst", 4): 17.05e6,
+    ("row_idst", 5): 17.11e6, ("row_idst", 6): 17.05e6, ("row_idst", 7): 17.07e6,
 }
 
 
