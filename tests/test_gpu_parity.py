@@ -425,3 +425,47 @@ def test_two_plates_match_oracle(torch_cuda, gpu_lib, mode, prec):
     assert abs(th[0] - b.theta) < dtol * max(1.0, abs(b.theta)) + 1e-14
     assert abs(th[1] - b.phi) < dtol * max(1.0, abs(b.phi)) + 1e-12
     assert abs(b.theta) > 1e-6  # the passive plate does deflect
+
+
+@pytest.mark.parametrize("which", ["flag", "plate"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_long_converged_runs_match_oracle(torch_cuda, gpu_lib, which, prec):
+    """100 steps with the tolerance-driven FSI loop (tol 1e-9): every refinement starts from
+    the last stresses (the previous step's at a step's first iteration) and may stop on its
+    predicted residual, over many steps (the oracle takes 4 or 5 iterations per step on the
+    flag, 3 or 4 on the plate).  In FP64 both sides take the same Newton iteration counts and
+    the state stays at the 3-step bars; the FP32 bars are the 3-step ones widened by
+    sqrt(100 / 4) = 5 for the random walk of the rounding."""
+    print(f"{which} 32^2 x 2, 100 converged steps, {prec}", flush=True)
+    make = W.flag_problem if which == "flag" else W.plate_problem
+    p = make(n=32, levels=2, steps=100)
+    steps = 100
+    gpu = _run(p, steps, prec, newton_tol=1e-9)
+    ora = Oracle(p, newton_tol=1e-9)
+    iters = []
+    for _ in range(steps):
+        ora.step()
+        iters.append(ora.last_iters)
+    st = gpu.stats()
+    ev = rel(gpu.vorticity(0), ora.vorticity(0))
+    es = rel(gpu.streamfunction(0), ora.s[0])
+    ef = rel(gpu.stresses(0), ora.f)
+    if which == "flag":
+        ed = float(np.max(np.abs(gpu.deflection(0) - ora.bodies[0][1].chi)))
+    else:
+        th = gpu.deflection(0)
+        ed = abs(th[0] - ora.bodies[0][1].theta)
+    print(f"  iterations last {st['newton_iters']} / max {st['newton_iters_max']} vs oracle "
+          f"{iters[-1]} / {max(iters)}; vorticity {ev:.2e}, streamfunction {es:.2e}, "
+          f"stresses {ef:.2e}, structure {ed:.2e}; sweeps last {st['refine_iters']}, "
+          f"inverse rebuilds {st['inverse_rebuilds']}", flush=True)
+    gpu.close()
+    if prec == "fp64":
+        assert st["newton_iters"] == iters[-1] and st["newton_iters_max"] == max(iters)
+        assert ev < fp64_tol(32, steps) and es < 1e-11
+        assert ef < 1e-9 and ed < 1e-10
+    else:
+        # single-precision flow: an increment that lands near the tolerance may take one
+        # iteration more or less than on the double oracle
+        assert abs(st["newton_iters_max"] - max(iters)) <= 1
+        assert ev < 5e-5 and ed < 5e-5 and ef < 5e-3
