@@ -242,6 +242,7 @@ struct ib_solver {
   void* work_pre = nullptr;   // spectral scratch of the levels launched ahead
   void* workg_pre = nullptr;
   void* lift_pre = nullptr;   // edge transforms of the rings of the levels launched ahead
+  void* lift_l1 = nullptr;    // edge transforms of level 1's next ring, made on `side`
   bool top_ahead = false;     // the next step's coarsest level is already on the stream
   int ahead_mode = 2;         // IB_OPT_TOP_AHEAD: 0 off, 1 coarsest level, 2 side stream
   hipEvent_t ctl_ready = nullptr;  // this step's control block is on the host
@@ -1768,14 +1769,17 @@ ib_status gemm_solve(ib_solver* s, RhsArgs<T>& a, double alpha, bool has_ring) {
 // the step has no history yet.
 template <typename T>
 ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void* work,
-                        void* workg) {
+                        void* workg, bool ring_made = false) {
   const int n = s->n, ny = s->ny, G = (int)s->lv.size(), P = s->pitch;
   const bool bodies = !s->bodies.empty();
   {
     LevelState& L = s->lv[g];
     const bool has_ring = g < G - 1;
     const int nxt = 1 - L.gcur;
-    if (has_ring) {
+    // ring_made: the side stream already made this level's ring (level 1 after the levels
+    // launched ahead), with its edge transforms in lift_l1
+    void* lift = ring_made ? s->lift_l1 : s->lift;
+    if (has_ring && !ring_made) {
       TimeScope ts(s, IB_K_RING);
       HIPCHK(launch_ring_dst<T>(static_cast<T*>(s->lv[g + 1].s), P,
                                 static_cast<T*>(s->lv[g + 1].g), P, n, ny,
@@ -1811,7 +1815,7 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
       }
       TimeScope ts(s, IB_K_COL_SOLVE, true);
       st = solve_into<T>(s, work, L.alpha, 4.0 / ((double)n * ny), 1, ny - 1, s->tw, s->lam,
-                         workg, has_ring ? s->lift : nullptr, s->tune.col, ts.b, ts.e);
+                         workg, has_ring ? lift : nullptr, s->tune.col, ts.b, ts.e);
     }
     if (st) return st;
     RowArgs<T> r{};
@@ -1893,6 +1897,16 @@ ib_status launch_side_levels(ib_solver* s) {
       if (st) return st;
     }
   }
+  // Level 1's ring for the next step, from level 2's new state: nothing of this step reads
+  // level 1's ring after l1_done, and its new circulation ring goes to the buffer that this
+  // step's level 1 read as the old one (the parity flips at the end of the step).
+  {
+    LevelState& L1 = s->lv[1];
+    HIPCHK(launch_ring_dst<T>(static_cast<T*>(s->lv[2].s), s->pitch,
+                              static_cast<T*>(s->lv[2].g), s->pitch, s->n, s->ny,
+                              static_cast<T*>(L1.sring), static_cast<T*>(L1.gring[L1.gcur]),
+                              s->tw, twy_of(s), static_cast<T*>(s->lift_l1), s->side));
+  }
   HIPCHK(hipEventRecord(s->side_done, s->side));
   s->side_ahead = true;
   return IB_OK;
@@ -1906,14 +1920,17 @@ template <typename T>
 ib_status enqueue_step(ib_solver* s, bool ahead, int K, int gtop = -1, bool side_next = false) {
   const int G = (int)s->lv.size();
   int g0 = gtop < 0 ? G - 1 : gtop;
+  bool side_ran = false;
   if (s->side_ahead) {
-    // levels G-1 .. 2 of this step ran on the side stream
+    // levels G-1 .. 2 of this step, and level 1's ring, ran on the side stream
     HIPCHK(hipStreamWaitEvent(s->stream, s->side_done, 0));
     s->side_ahead = false;
+    side_ran = true;
     g0 = 1;
   }
   for (int g = g0; g >= 0; --g) {
-    ib_status st = enqueue_level<T>(s, g, ahead, K, s->first, s->work, s->workg);
+    ib_status st = enqueue_level<T>(s, g, ahead, K, s->first, s->work, s->workg,
+                                    side_ran && g == 1);
     if (st) return st;
     if (g == 1 && side_next) {
       if (!s->side) {
@@ -2208,13 +2225,14 @@ ib_status alloc_state(ib_solver* s) {
   s->work = dalloc(s, inner);
   s->workg = dalloc(s, inner);
   s->work2 = dalloc(s, inner);
-  s->work_pre = s->workg_pre = s->lift_pre = nullptr;
+  s->work_pre = s->workg_pre = s->lift_pre = s->lift_l1 = nullptr;
   s->top_ahead = s->side_ahead = false;
   if (s->lv.size() >= 3 && !s->gemm) {
     s->work_pre = dalloc(s, inner);
     s->workg_pre = dalloc(s, inner);
     s->lift_pre = dalloc(s, lift);
-    if (!s->work_pre || !s->workg_pre || !s->lift_pre) return IB_ERR_OOM;
+    s->lift_l1 = dalloc(s, lift);
+    if (!s->work_pre || !s->workg_pre || !s->lift_pre || !s->lift_l1) return IB_ERR_OOM;
   }
   s->lift = dalloc(s, lift);
   s->sstar = dalloc(s, full);
