@@ -1322,7 +1322,13 @@ __device__ __forceinline__ void spread_body(const FsiArgs& a, int jlo, int jhi, 
 
 template <typename T>
 __global__ __launch_bounds__(SPREAD_NT) void k_spread(FsiArgs a, int jlo, int jhi, int ilo, int ihi,
-                                                      T* out, int po) {
+                                                      T* out, int po, int fin_bx) {
+  // the workgroups of the column fin_bx (launched only with the structure finish): block
+  // (fin_bx, 0) runs it, the others have nothing to do
+  if ((int)blockIdx.x == fin_bx) {
+    if (blockIdx.y == 0) finish_body(a);
+    return;
+  }
   spread_body<T>(a, jlo, jhi, ilo, ihi, out, po, blockIdx.x, blockIdx.y);
 }
 
@@ -2230,11 +2236,13 @@ hipError_t launch_finish(const FsiArgs& a, hipStream_t st) {
 }
 template <typename T>
 hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,
-                         hipStream_t st) {
+                         hipStream_t st, bool finish) {
   if (a.nf > SPREAD_MAXROWS) return hipErrorInvalidValue;
-  dim3 g((a.n - 1 + SPREAD_TX - 1) / SPREAD_TX, (jhi - jlo + 1 + SPREAD_TY - 1) / SPREAD_TY);
+  static_assert(SPREAD_NT == STRUCT_NT, "the structure finish runs in a spread workgroup");
+  const int gx = (a.n - 1 + SPREAD_TX - 1) / SPREAD_TX;
+  dim3 g(gx + (finish ? 1 : 0), (jhi - jlo + 1 + SPREAD_TY - 1) / SPREAD_TY);
   hipLaunchKernelGGL((k_spread<T>), g, dim3(SPREAD_NT), spread_lds_bytes(a.nf), st, a, jlo, jhi,
-                     ilo, ihi, out, po);
+                     ilo, ihi, out, po, finish ? gx : -1);
   return hipGetLastError();
 }
 hipError_t launch_point_source_rowdst(const OffRows& o, int col0, int ncols, int nslots,
@@ -2500,7 +2508,9 @@ template hipError_t launch_outputs<double>(const FsiArgs&, const double*, int, d
 
 template hipError_t launch_body_ops<float>(const FsiArgs&, hipStream_t);
 template hipError_t launch_body_ops<double>(const FsiArgs&, hipStream_t);
-template hipError_t launch_spread<float>(const FsiArgs&, int, int, int, int, float*, int, hipStream_t);
-template hipError_t launch_spread<double>(const FsiArgs&, int, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_spread<float>(const FsiArgs&, int, int, int, int, float*, int, hipStream_t,
+                                         bool);
+template hipError_t launch_spread<double>(const FsiArgs&, int, int, int, int, double*, int,
+                                          hipStream_t, bool);
 
 }  // namespace ib

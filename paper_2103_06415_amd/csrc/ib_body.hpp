@@ -256,9 +256,11 @@ hipError_t launch_beam(const FsiArgs& a, int bi, int m, hipStream_t st);
 template <typename T>
 hipError_t launch_ops_beam(const FsiArgs& a, int bi, int m, hipStream_t st);
 hipError_t launch_finish(const FsiArgs& a, hipStream_t st);
+// finish: one more workgroup runs k_finish's structure update (the spread reads none of the
+// structure state that it writes, and both run only after converged iterations)
 template <typename T>
 hipError_t launch_spread(const FsiArgs& a, int jlo, int jhi, int ilo, int ihi, T* out, int po,
-                         hipStream_t st);
+                         hipStream_t st, bool finish = false);
 hipError_t launch_point_source_rowdst(const OffRows& o, int col0, int ncols, int nslots,
                                       const void* tw, double* out, int po, size_t bso,
                                       int* rows_first, hipStream_t st);

@@ -1508,9 +1508,10 @@ ib_status fsi_iteration(ib_solver* s, const FsiArgs& a0, int it, int K = 0) {
 }
 
 // Corrector s_{n+1} = s* - dt K C^T E^T (ds/h) f on level 0 (eqs. (20), (40)); with `gate`
-// set it runs only if the step's iterations converged on the device.
+// set it runs only if the step's iterations converged on the device.  finish: the spread's
+// launch also runs the structure finish (k_finish's work) in a workgroup of its own.
 template <typename T>
-ib_status corrector(ib_solver* s, const int* gate) {
+ib_status corrector(ib_solver* s, const int* gate, bool finish = false) {
   const int n = s->n, P = s->pitch;
   LevelState& L0 = s->lv[0];
   FsiArgs a = s->fa;
@@ -1518,7 +1519,7 @@ ib_status corrector(ib_solver* s, const int* gate) {
   {
     TimeScope ts(s, IB_K_CORRECT);
     HIPCHK(launch_spread<T>(a, s->blo, s->bhi, s->bilo, s->bihi, static_cast<T*>(s->work2), P,
-                            s->stream));
+                            s->stream, finish));
     RowArgs<T> r{};
     r.in = static_cast<T*>(s->work2);
     r.out = static_cast<T*>(s->work2);
@@ -1573,8 +1574,7 @@ ib_status fsi_launch_ahead(ib_solver* s, int K) {
     ib_status e = fsi_iteration<T>(s, g, it, K);  // k_update runs the convergence test
     if (e) return e;
   }
-  HIPCHK(launch_finish(g, s->stream));
-  return corrector<T>(s, s->gate);
+  return corrector<T>(s, s->gate, true);  // with the structure finish
 }
 
 // A refinement's device-wide barrier timed out (its workgroups were not all resident, e.g.
@@ -1838,7 +1838,9 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
         gate = s->gate;
         if (!st && s->ctl_early) {
           // the control block is final after the iterations: the host can read it and
-          // queue the next step while the (gated) corrector still runs
+          // queue the next step while the (gated) corrector's inverse row transform still
+          // runs (copied earlier, before the corrector, the host's next launches slowed
+          // the step: 0.380 against 0.375 ms)
           HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
           HIPCHK(hipEventRecord(s->ctl_ready, s->stream));
         }
@@ -2092,7 +2094,7 @@ ib_status do_step(ib_solver* s, const StepPlan& p, bool pre_next = false) {
   s->top_ahead = false;
   if (p.ahead) {
     if (!sg && s->ahead_mode != 1) {
-      // copied right after the iterations (enqueue_level); the corrector may still run
+      // copied after the corrector's column solve (enqueue_level); its last transform may still run
       HIPCHK(hipEventSynchronize(s->ctl_ready));
     } else {
       HIPCHK(hipMemcpyAsync(s->hctl, s->ctl, FsiCtl::BYTES, hipMemcpyDeviceToHost, s->stream));
