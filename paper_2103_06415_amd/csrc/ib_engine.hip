@@ -1828,11 +1828,14 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
       r.out = static_cast<T*>(s->sstar);
       r.r0 = std::max(1, s->blo - 3);
       r.r1 = std::min(n - 1, s->bhi + 3);
+      // the same launch clears the step's control block (flags, gates, counters)
+      r.reset = s->flags;
+      r.nreset = FsiCtl::INTS;
       {
         TimeScope ts(s, IB_K_ROW_IDST);
         HIPCHK(launch_row_idst<T>(r, n, 1, s->tw, ring, 0, s->stream));
       }
-      HIPCHK(launch_step_reset(s->flags, s->stream));
+      r.reset = nullptr;
       if (ahead) {
         st = fsi_launch_ahead<T>(s, K);
         gate = s->gate;

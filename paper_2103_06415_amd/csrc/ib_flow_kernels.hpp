@@ -589,6 +589,8 @@ __device__ __forceinline__ void row_idst_body(const RowArgs<T>& a, const c2<T>* 
   __shared__ c2<T> buf[NS * fft_pad_len<N>()];
   __shared__ c2<T> stw[TwLayout<N, MAXR>::total];
   static_assert(sizeof(buf) + sizeof(stw) <= 160 * 1024, "LDS");
+  if (a.reset != nullptr && bx == 0 && by == 0 && (int)threadIdx.x < a.nreset)
+    a.reset[threadIdx.x] = 0;
   const int blk = xcd_block(bx, nblocks);
   if (blk < 0 || flow_gated(a.gate)) return;
   const int tid = threadIdx.x;

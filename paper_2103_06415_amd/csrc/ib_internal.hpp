@@ -39,6 +39,8 @@ struct RowArgs {
   int var;          // inverse transform with in2: kernel configuration (ROW_VARIANTS)
   const int* gate;  // if set: run only when gate[0] = 1 and gate[1] = 0 (FsiArgs::gate)
   int ny;           // inverse transform with its ring: cells along y; 0: the row length
+  int* reset;       // inverse transform: if set, its first workgroup also clears `nreset`
+  int nreset;       //   ints there (a control block that only later launches read)
 };
 
 // Column transform + spectral scale + inverse column transform.
