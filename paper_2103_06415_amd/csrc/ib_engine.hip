@@ -2565,20 +2565,31 @@ ib_status batch_step(ib_batch* b) {
     std::vector<FsiArgs> fa;
     std::vector<BeamJob> beams;
     std::vector<UpdateJob> upd;
-    int max_pts = 0, max_nf = 0, max_m = 0, max_ub = 0;
-    size_t schur_lds = 0, beam_lds_max = 0;
+    int max_pts = 0, max_m = 0, max_ub = 0;
+    size_t beam_lds_max = 0;
+    // The Schur assembly in classes of LDS size, one launch each: a launch's dynamic LDS is
+    // its largest member's, and a workgroup sized for the largest system would hold a CU
+    // alone for every member's rows
+    constexpr int NSC = 4;
+    const size_t sc_lim[NSC] = {20 * 1024, 40 * 1024, 80 * 1024, SCHUR_LDS_MAX};
+    std::vector<FsiArgs> sc_fa[NSC];
+    int sc_nf[NSC] = {0, 0, 0, 0};
+    size_t sc_lds[NSC] = {0, 0, 0, 0};
     for (ib_solver* s : iter) {
       FsiArgs a = s->fa;
       a.gate = s->gate;
       fa.push_back(a);
       max_pts = std::max(max_pts, a.npts);
-      max_nf = std::max(max_nf, s->nf);
       const size_t l = schur_lds_bytes(a);
       if (l == 0) {
         b->last_error = "Schur assembly does not fit a workgroup";
         return IB_ERR_ARG;
       }
-      schur_lds = std::max(schur_lds, l);
+      int k = 0;
+      while (l > sc_lim[k]) ++k;
+      sc_fa[k].push_back(a);
+      sc_nf[k] = std::max(sc_nf[k], s->nf);
+      sc_lds[k] = std::max(sc_lds[k], l);
       for (size_t bi = 0; bi < s->bodies.size(); ++bi) {
         if (s->bodies[bi].kind != BODY_DEFORMABLE) continue;
         const int m = s->bodies[bi].m;
@@ -2591,6 +2602,8 @@ ib_status batch_step(ib_batch* b) {
       max_ub = std::max(max_ub, nb);
     }
     const size_t fa_off = pl.put(fa);
+    size_t sc_off[NSC];
+    for (int k = 0; k < NSC; ++k) sc_off[k] = sc_fa[k].empty() ? 0 : pl.put(sc_fa[k]);
     const size_t beam_off = beams.empty() ? 0 : pl.put(beams);
     const size_t upd_off = pl.put(upd);
     const int ni = (int)iter.size(), nbeam = (int)beams.size();
@@ -2606,10 +2619,15 @@ ib_status batch_step(ib_batch* b) {
           return launch_body_ops_multi<T>(reinterpret_cast<const FsiArgs*>(d + fa_off), ni,
                                           max_pts, it, st);
         });
-      pl.launches.push_back([=](const char* d) {
-        return launch_schur_sd_multi(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, max_nf,
-                                     schur_lds, it, st);
-      });
+      for (int k = 0; k < NSC; ++k) {
+        if (sc_fa[k].empty()) continue;
+        const size_t off = sc_off[k], lds = sc_lds[k];
+        const int cnt = (int)sc_fa[k].size(), mnf = sc_nf[k];
+        pl.launches.push_back([=](const char* d) {
+          return launch_schur_sd_multi(reinterpret_cast<const FsiArgs*>(d + off), cnt, mnf, lds,
+                                       it, st);
+        });
+      }
       // Newton-Schulz refresh of the inverse into Xn, then the refinement (split by the
       // GEMM's k chunk and the refinement's LDS mode)
       std::vector<GemmJob> g1[2], g2[2];
