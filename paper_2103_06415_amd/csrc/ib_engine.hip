@@ -2631,9 +2631,11 @@ ib_status batch_step(ib_batch* b) {
       // Newton-Schulz refresh of the inverse into Xn, then the refinement (split by the
       // GEMM's k chunk and the refinement's LDS mode)
       std::vector<GemmJob> g1[2], g2[2];
-      std::vector<RefineJob> rj[3];
-      int gmax_n[2] = {0, 0}, rnb[3] = {0, 0, 0};
-      size_t rlds[3] = {0, 0, 0};
+      // refinements by LDS mode, and within a mode by the same LDS size classes as the
+      // Schur assembly (a launch's LDS is its largest member's)
+      std::vector<RefineJob> rj[3][NSC];
+      int gmax_n[2] = {0, 0}, rnb[3][NSC] = {};
+      size_t rlds[3][NSC] = {};
       for (ib_solver* s : iter) {
         const FsiArgs& a = s->fa;
         const int nf = s->nf;
@@ -2654,11 +2656,13 @@ ib_status batch_step(ib_batch* b) {
           return IB_ERR_ARG;
         }
         const int c = sh.two ? 2 : sh.cache ? 1 : 0;
-        rj[c].push_back(RefineJob{a.M, X, a.pm, s->rhs, s->f, nf, sh.rw, sh.tpr, REFINE_MAXIT,
-                                  refine_guess(s, it), s->rinfo, s->rout, s->flags,
-                                  s->gate, xcopy, sh.nb, s->barrier_arg()});
-        rnb[c] = std::max(rnb[c], sh.nb);
-        rlds[c] = std::max(rlds[c], sh.lds);
+        int k = 0;
+        while (sh.lds > sc_lim[k]) ++k;
+        rj[c][k].push_back(RefineJob{a.M, X, a.pm, s->rhs, s->f, nf, sh.rw, sh.tpr, REFINE_MAXIT,
+                                     refine_guess(s, it), s->rinfo, s->rout, s->flags,
+                                     s->gate, xcopy, sh.nb, s->barrier_arg()});
+        rnb[c][k] = std::max(rnb[c][k], sh.nb);
+        rlds[c][k] = std::max(rlds[c][k], sh.lds);
       }
       for (int k = 0; k < 2; ++k) {
         const int mn = gmax_n[k];
@@ -2668,13 +2672,14 @@ ib_status batch_step(ib_batch* b) {
         const int mn = gmax_n[k];
         pl.add(g2[k], [=](const GemmJob* d, int c) { return launch_gemm64_multi(d, c, mn, k, st); });
       }
-      for (int c = 0; c < 3; ++c) {
-        const int mb = rnb[c];
-        const size_t l = rlds[c];
-        pl.add(rj[c], [=](const RefineJob* d, int cnt) {
-          return launch_refine_multi(d, cnt, mb, l, c, st);
-        });
-      }
+      for (int c = 0; c < 3; ++c)
+        for (int k = 0; k < NSC; ++k) {
+          const int mb = rnb[c][k];
+          const size_t l = rlds[c][k];
+          pl.add(rj[c][k], [=](const RefineJob* d, int cnt) {
+            return launch_refine_multi(d, cnt, mb, l, c, st);
+          });
+        }
       pl.launches.push_back([=](const char* d) {
         return launch_update_multi(reinterpret_cast<const UpdateJob*>(d + upd_off), ni, max_ub, it,
                                    K, st);
