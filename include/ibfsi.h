@@ -480,7 +480,9 @@ typedef struct {
 ib_status ib_batch_create(ib_solver* const* members, int32_t count, void* hip_stream,
                           ib_batch** out);
 /* nsteps steps of every member; returns after the last step's convergence tests (the
- * flow of the last step may still run on hip_stream when no member has moving bodies). */
+ * members' control blocks are read right after their FSI iterations, so the last step's
+ * corrector and final transforms, or with no moving bodies its flow, may still run on
+ * hip_stream; the members' read calls wait for them). */
 ib_status ib_batch_step(ib_batch* b, int32_t nsteps);
 ib_status ib_batch_get_stats(const ib_batch* b, ib_batch_stats* out);
 const char* ib_batch_last_error(const ib_batch* b);

@@ -2311,6 +2311,7 @@ struct ib_batch {
   char* hbuf[2] = {nullptr, nullptr};
   char* dbuf[2] = {nullptr, nullptr};
   hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t ctl_ready = nullptr;  // the members' control blocks of this step are on the host
   size_t cap = 0;
   int slot = 0;
   // gathered control blocks of the members iterating on the device, and their mirror
@@ -2689,6 +2690,24 @@ ib_status batch_step(ib_batch* b) {
       return launch_finish_multi(reinterpret_cast<const FsiArgs*>(d + fa_off), ni, st);
     });
   }
+  // The control blocks of the members iterating on the device are final after their FSI
+  // iterations: gathered and copied to the host right there, so that the host reads them and
+  // builds and queues the next step while the (gated) corrector and final transforms run.
+  if (!iter.empty()) {
+    std::vector<int*> ictl;
+    for (ib_solver* s : iter) ictl.push_back(s->flags);
+    ib_status rs0 = batch_reserve(b, 0, (int)ictl.size());
+    if (rs0) return rs0;
+    int* const dctl_target = b->dctl;
+    int* const hctl_target = b->hctl;
+    hipEvent_t const ready = b->ctl_ready;
+    const size_t cb = ictl.size() * FsiCtl::BYTES;
+    pl.add(ictl, [=](int* const* d, int c) { return launch_gather_ctl(d, c, dctl_target, st); });
+    pl.launches.push_back([=](const char*) {
+      const hipError_t e = hipMemcpyAsync(hctl_target, dctl_target, cb, hipMemcpyDeviceToHost, st);
+      return e != hipSuccess ? e : hipEventRecord(ready, st);
+    });
+  }
   {
     // corrector source on level 0 (eqs. (20), (40)) for every member with bodies
     std::vector<SpreadJob<T>> sp;
@@ -2768,13 +2787,7 @@ ib_status batch_step(ib_batch* b) {
       return launch_row_idst_multi<T>(d, c, n, n - 1, 1, vi, tw, st);
     });
   }
-  std::vector<int*> ictl;
-  for (ib_solver* s : iter) ictl.push_back(s->flags);
-  ib_status rs0 = batch_reserve(b, 0, (int)ictl.size());
-  if (rs0) return rs0;
-  int* const dctl_target = b->dctl;
-  pl.add(ictl, [=](int* const* d, int c) { return launch_gather_ctl(d, c, dctl_target, st); });
-  rs0 = batch_reserve(b, pl.tab.size(), (int)ictl.size());
+  ib_status rs0 = batch_reserve(b, pl.tab.size(), (int)iter.size());
   if (rs0) return rs0;
 
   // ---- tables to the device (one copy), then the launches
@@ -2789,9 +2802,8 @@ ib_status batch_step(ib_batch* b) {
 
   // ---- convergence of the members iterating on the device
   if (!iter.empty()) {
-    const size_t cb = (size_t)iter.size() * FsiCtl::BYTES;
-    BCHK(hipMemcpyAsync(b->hctl, b->dctl, cb, hipMemcpyDeviceToHost, st));
-    BCHK(hipStreamSynchronize(st));
+    // copied right after the FSI part (above); the corrector and final transforms may still run
+    BCHK(hipEventSynchronize(b->ctl_ready));
     for (size_t i = 0; i < iter.size(); ++i) {
       ib_solver* s = iter[i];
       std::memcpy(s->hctl, reinterpret_cast<const char*>(b->hctl) + i * FsiCtl::BYTES,
@@ -3404,6 +3416,11 @@ ib_status ib_batch_create(ib_solver* const* members, int32_t count, void* hip_st
       delete b;
       return IB_ERR_HIP;
     }
+  if (hipEventCreateWithFlags(&b->ctl_ready, hipEventDisableTiming) != hipSuccess) {
+    for (auto f : b->copied) (void)hipEventDestroy(f);
+    delete b;
+    return IB_ERR_HIP;
+  }
   *out = b;
   return IB_OK;
 }
@@ -3448,6 +3465,7 @@ ib_status ib_batch_destroy(ib_batch* b) {
   if (b->hctl) (void)hipHostFree(b->hctl);
   for (auto e : b->copied)
     if (e) (void)hipEventDestroy(e);
+  if (b->ctl_ready) (void)hipEventDestroy(b->ctl_ready);
   delete b;
   return IB_OK;
 }
