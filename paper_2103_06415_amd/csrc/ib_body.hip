@@ -1605,7 +1605,7 @@ __device__ __forceinline__ bool refine_body(const double* __restrict__ M,
   double* sred = sb + rw;     // 4 partial maxima
   double* sm = sred + 4;      // rows R_w of M (rw x n) when CACHE
   double* sx = sm + (size_t)rw * n;  // columns R_w of X (n x rw) when CACHE
-  double* sp = sx + (CACHE ? (size_t)rw * n : 0);  // TWO: this slice of every share (nb x cs)
+  double* sp = CACHE ? sx + (size_t)rw * n : sm;    // TWO: this slice of every share (nb x cs)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = gx, w = bx, ns = n + 1;
   const int r0 = w * rw, r1 = min(n, r0 + rw), nr = max(0, r1 - r0);
