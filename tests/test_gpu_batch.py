@@ -219,3 +219,50 @@ def test_a_failing_member_stops_the_batch(torch_cuda, gpu_lib):
     batch.close()
     for s in sols:
         s.close()
+
+
+def test_large_members_equal_their_runs_alone(torch_cuda, gpu_lib):
+    """Members of the 64-instance configuration whose Schur systems take the two-level
+    refinement (more than 32 workgroups, shares summed in slices) next to members with the
+    one-level form, in LDS size classes of their own: bit for bit their runs alone, with no
+    FSI iteration continued on the host."""
+    from paper_2103_06415_amd import binding
+    probs = W.batch_problems()
+    pick = [29, 9, 44, 7, 22]  # 756, 466, 438, 232 and 22 unknowns
+    members = [probs[i] for i in pick]
+
+    def nf(p):
+        return 2 * sum(b.n if isinstance(b, W.Torsional) else len(b.xy) for b in p.bodies)
+
+    sizes = [nf(p) for p in members]
+    print(f"large members {pick}: Schur unknowns {sizes}", flush=True)
+    assert max(sizes) > 700 and min(sizes) < 100
+    steps = 6
+    alone = []
+    for k, p in zip(pick, members):
+        print(f"  alone member {k} n={p.flow.n} levels={p.flow.levels}", flush=True)
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        s.step(steps)
+        s.sync()
+        alone.append(_results(s, p))
+        s.close()
+    sols = []
+    for p in members:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        sols.append(s)
+    batch = binding.Batch(sols)
+    batch.step(steps)
+    torch_cuda.cuda.synchronize()
+    st = batch.stats()
+    print(f"  stats {st}", flush=True)
+    assert st["fsi_resumes"] == 0
+    for k, (s, p) in enumerate(zip(sols, members)):
+        got = _results(s, p)
+        for key, ref in alone[k].items():
+            assert np.array_equal(got[key], ref), (pick[k], key,
+                                                  float(np.max(np.abs(got[key] - ref))))
+    batch.close()
+    for s in sols:
+        s.close()
