@@ -266,3 +266,38 @@ def test_large_members_equal_their_runs_alone(torch_cuda, gpu_lib):
     batch.close()
     for s in sols:
         s.close()
+
+
+def test_batched_members_that_resume_on_the_host(torch_cuda, gpu_lib):
+    """Batched steps whose launched-ahead FSI iterations do not suffice for a member (it then
+    continues on the host, after the control blocks were read while the batch's gated corrector
+    was still queued): bit for bit the same members stepped alone."""
+    from paper_2103_06415_amd import binding
+    probs = [W.flag_problem(n=64, levels=3, steps=0), W.plate_problem(n=48, levels=2, steps=0)]
+    steps = 12
+    alone = []
+    for p in probs:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        s.step(steps)
+        s.sync()
+        alone.append(_results(s, p))
+        s.close()
+    sols = []
+    for p in probs:
+        s = binding.Solver(p, precision=binding.IB_FP32_FLOW)
+        s.prepare()
+        sols.append(s)
+    batch = binding.Batch(sols)
+    batch.step(steps)
+    torch_cuda.cuda.synchronize()
+    st = batch.stats()
+    print(f"  stats {st}", flush=True)
+    assert st["fsi_resumes"] >= 1  # the case this test is for
+    for k, (s, p) in enumerate(zip(sols, probs)):
+        got = _results(s, p)
+        for key, ref in alone[k].items():
+            assert np.array_equal(got[key], ref), (k, key, float(np.max(np.abs(got[key] - ref))))
+    batch.close()
+    for s in sols:
+        s.close()
