@@ -1506,7 +1506,7 @@ constexpr int REF_HDR = 4;
 constexpr int REF_NB_ONE = 32;   // workgroups up to which every workgroup sums all shares
 constexpr int REF_NB_MAX = 128;
 constexpr size_t REF_LDS_CACHE = 48 * 1024;
-constexpr size_t REF_LDS_BIG = 96 * 1024;
+constexpr size_t REF_LDS_BIG = 120 * 1024;
 constexpr int REF_LOADS = 12;     // loads of a thread per matrix in flight while LDS fills
 constexpr double REF_PREDICT = 0.01;  // margin of the predicted stop (see refine_body)
 size_t refine_ws_doubles(int n, int) {
