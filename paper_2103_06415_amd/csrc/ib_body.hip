@@ -592,7 +592,7 @@ __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd(FsiArgs a, int all4) {
 }
 
 __device__ __forceinline__ int schur_all4(const FsiArgs& a) {
-  return a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
+  return a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_ALL4_MAX;
 }
 
 __global__ __launch_bounds__(SCHUR_NT) void k_schur_sd_multi(const FsiArgs* __restrict__ tab,
@@ -2177,7 +2177,7 @@ hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, dou
 size_t schur_lds_bytes(const FsiArgs& a) {
   size_t lds = a.gx != nullptr ? 8 : (size_t)a.nf * SCHUR_LDS_PER_ROW;
   if (lds > SCHUR_LDS_MAX || a.nf > SCHUR_CPT * SCHUR_NT) return 0;
-  const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
+  const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_ALL4_MAX;
   if (all4) lds = (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4;
   return lds;
 }
@@ -2185,7 +2185,7 @@ size_t schur_lds_bytes(const FsiArgs& a) {
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st) {
   const size_t lds = schur_lds_bytes(a);
   if (lds == 0) return hipErrorInvalidValue;
-  const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_MAX;
+  const int all4 = a.gx == nullptr && (size_t)a.nf * SCHUR_LDS_PER_ROW_ALL4 <= SCHUR_LDS_ALL4_MAX;
   hipLaunchKernelGGL(k_schur_sd, dim3(a.nf), dim3(SCHUR_NT), lds, st, a, all4);
   return hipGetLastError();
 }

@@ -241,6 +241,10 @@ hipError_t launch_outputs(const FsiArgs& a, const T* s0, int ps, double* out, hi
 constexpr size_t SCHUR_LDS_PER_ROW = 4 * (8 + 8 + 4 + 4);
 constexpr size_t SCHUR_LDS_PER_ROW_ALL4 = 4 * (4 * 8 + 8 + 4 + 4);  // four hat points at once
 constexpr size_t SCHUR_LDS_MAX = 150 * 1024;
+// The four B' rows of a Schur row are scanned at once up to this much LDS per workgroup (one
+// round of dependent loads instead of four); larger systems scan them one after another in a
+// quarter of the LDS, so that several workgroups share a CU (the rows of M are the same)
+constexpr size_t SCHUR_LDS_ALL4_MAX = 40 * 1024;
 hipError_t launch_schur_sd(const FsiArgs& a, hipStream_t st);
 // G[t][c0 + b] = vals[b][t] for the ns point-source columns of one offline batch
 hipError_t launch_cols_to_matrix(const double* vals, int nf, int ns, int c0, double* G, int pm,
