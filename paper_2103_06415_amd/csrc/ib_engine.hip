@@ -1875,7 +1875,7 @@ ib_status enqueue_level(ib_solver* s, int g, bool ahead, int K, bool first, void
 // nothing of this step after level 1 reads a level >= 2.  So they run concurrently with
 // this step's level 0, FSI part and corrector, with spectral scratch and ring transforms of
 // their own, and give the same results bit for bit.  Their ring parity is the next step's
-// (the end of a step flips it).
+// (the end of a step flips it).  Level 1's ring for the next step follows them there.
 template <typename T>
 ib_status launch_side_levels(ib_solver* s) {
   const int G = (int)s->lv.size();
